@@ -1,0 +1,331 @@
+"""Plain FP64 CPU oracle for the adjoint Lindblad master equation of damped
+Kerr-coupled bosonic modes.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the product library never does, and this
+package never imports the product library.
+
+The heavy loop (the element-wise right-hand side of the adjoint master
+equation, Eq. (3), and classical RK4) is the C file ``adjoint_me.c`` next to
+this one; this module builds it with gcc, loads it with ctypes and adds the
+plain numpy pieces: sector bookkeeping, states, the expectation value, and the
+coefficient maps of Eqs. (6) and (11) with the basis of Eqs. (7)-(8).
+
+Operators are dictionaries ``{d: box}``: ``d`` is the occupation difference
+l - k (a tuple of ints), ``box`` a complex128 array of shape ``cutoff`` whose
+entry at k is the number-basis element A[k, k + d] (zero where k + d leaves
+the truncated space).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import itertools
+import math
+import os
+import subprocess
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "adjoint_me.c")
+_LIB = os.path.join(_HERE, "_adjoint_me.so")
+_lib = None
+
+Sectors = Dict[Tuple[int, ...], np.ndarray]
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (OpenMP, IEEE arithmetic)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp",
+           _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    ip, dp, vp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
+    sysargs = [ctypes.c_int, ip, dp, dp, dp, dp, dp, dp]
+    lib.oracle_rhs.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_int]
+    lib.oracle_evolve.argtypes = sysargs + [ctypes.c_int, ip, vp, ctypes.c_long,
+                                            ctypes.c_double, ctypes.c_int]
+    lib.oracle_evolve_sens.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_long,
+                                                 ctypes.c_double, ctypes.c_int]
+    lib.oracle_num_params.argtypes = [ctypes.c_int]
+    lib.oracle_max_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _sysargs(system):
+    n = system.n_modes
+    keep = []
+
+    def arr(x, dt):
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt).reshape(-1))
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int if dt == np.int32 else ctypes.c_double))
+
+    args = [n, arr(system.cutoff, np.int32), arr(system.detuning, np.float64),
+            arr(system.kerr, np.float64), arr(system.cross_kerr, np.float64),
+            arr(system.gamma1, np.float64), arr(system.gamma_phi, np.float64),
+            arr(system.n_th, np.float64)]
+    return args, keep
+
+
+def _pack(system, ops: Sectors):
+    keys = sorted(ops.keys())
+    n = system.n_modes
+    d = np.ascontiguousarray(np.array(keys, dtype=np.int32).reshape(len(keys), n))
+    A = np.ascontiguousarray(np.stack([np.asarray(ops[k], dtype=np.complex128).reshape(system.cutoff)
+                                       for k in keys]))
+    return keys, d, A
+
+
+def num_params(n: int) -> int:
+    """K[N], chi[i<j], Delta[N], gamma1[N], gamma_phi[N]."""
+    return n + n * (n - 1) // 2 + 3 * n
+
+
+def rhs(system, ops: Sectors, nthreads: int = 0) -> Sectors:
+    """One evaluation of the right-hand side of Eq. (3) on every sector."""
+    lib = _load()
+    keys, d, A = _pack(system, ops)
+    out = np.zeros_like(A)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_rhs(*args, len(keys), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                        A.ctypes.data, out.ctypes.data, nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_rhs failed ({rc})")
+    return {k: out[i] for i, k in enumerate(keys)}
+
+
+def n_steps(t_total: float, dt: float) -> int:
+    m = int(round(t_total / dt))
+    if m < 0 or abs(m * dt - t_total) > 1e-9 * max(1.0, abs(t_total)):
+        raise ValueError("t_total must be a non-negative integer multiple of dt")
+    return m
+
+
+def evolve(system, ops: Sectors, t_total: float, dt: float, nthreads: int = 0) -> Sectors:
+    """A(T) from A(0) by classical RK4 with step dt (same scheme as the paper's
+    fourth-order Runge-Kutta integration)."""
+    lib = _load()
+    keys, d, A = _pack(system, ops)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve(*args, len(keys), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           A.ctypes.data, n_steps(t_total, dt), float(dt), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve failed ({rc})")
+    return {k: A[i] for i, k in enumerate(keys)}
+
+
+def evolve_steps(system, ops: Sectors, steps: int, dt: float, nthreads: int = 0) -> Sectors:
+    lib = _load()
+    keys, d, A = _pack(system, ops)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve(*args, len(keys), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           A.ctypes.data, int(steps), float(dt), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve failed ({rc})")
+    return {k: A[i] for i, k in enumerate(keys)}
+
+
+def evolve_sens(system, ops: Sectors, t_total: float, dt: float, nthreads: int = 0):
+    """A(T) and dA(T)/dtheta_p for every parameter (forward sensitivities of
+    the discrete RK4 map).  Returns (A_T, [S_p])."""
+    lib = _load()
+    keys, d, A = _pack(system, ops)
+    P = num_params(system.n_modes)
+    S = np.zeros((P,) + A.shape, dtype=np.complex128)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve_sens(*args, len(keys), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                A.ctypes.data, S.ctypes.data, n_steps(t_total, dt), float(dt),
+                                nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve_sens failed ({rc})")
+    a_t = {k: A[i] for i, k in enumerate(keys)}
+    sens = [{k: S[p, i] for i, k in enumerate(keys)} for p in range(P)]
+    return a_t, sens
+
+
+# ------------------------------------------------------------------ operators
+
+def product_sectors(factors: Sequence[np.ndarray]) -> Sectors:
+    """Sectors of the tensor product of per-mode matrices M_j:
+    A[k, l] = prod_j M_j[k_j, l_j]."""
+    cutoff = tuple(m.shape[0] for m in factors)
+    per_mode = []
+    for m in factors:
+        nc = m.shape[0]
+        ds = [dj for dj in range(-nc + 1, nc) if np.any(np.diagonal(m, offset=dj) != 0)]
+        per_mode.append(ds)
+    out: Sectors = {}
+    for d in itertools.product(*per_mode):
+        box = np.ones(cutoff, dtype=np.complex128)
+        for j, (m, dj) in enumerate(zip(factors, d)):
+            nc = m.shape[0]
+            col = np.zeros(nc, dtype=np.complex128)
+            for k in range(nc):
+                if 0 <= k + dj < nc:
+                    col[k] = m[k, k + dj]
+            shape = [1] * len(cutoff)
+            shape[j] = nc
+            box = box * col.reshape(shape)
+        out[tuple(int(x) for x in d)] = box
+    return out
+
+
+def sparse_sectors(cutoff: Sequence[int], ks, ls, vals) -> Sectors:
+    """Sectors of sum_t vals[t] |k_t><l_t| (repeated (k, l) pairs add up)."""
+    out: Sectors = {}
+    for k, l, v in zip(np.asarray(ks), np.asarray(ls), np.asarray(vals)):
+        d = tuple(int(b - a) for a, b in zip(k, l))
+        box = out.setdefault(d, np.zeros(tuple(cutoff), dtype=np.complex128))
+        box[tuple(int(a) for a in k)] += v
+    return out
+
+
+def dense_from_sectors(cutoff: Sequence[int], ops: Sectors) -> np.ndarray:
+    """Full number-basis matrix (small systems only), index order C-style."""
+    dim = int(np.prod(cutoff))
+    M = np.zeros((dim, dim), dtype=np.complex128)
+    for d, box in ops.items():
+        for k in itertools.product(*[range(c) for c in cutoff]):
+            l = tuple(a + b for a, b in zip(k, d))
+            if all(0 <= x < c for x, c in zip(l, cutoff)):
+                M[np.ravel_multi_index(k, cutoff), np.ravel_multi_index(l, cutoff)] = box[k]
+    return M
+
+
+def sectors_from_dense(cutoff: Sequence[int], M: np.ndarray, tol: float = 0.0) -> Sectors:
+    out: Sectors = {}
+    for ki in range(M.shape[0]):
+        k = np.unravel_index(ki, cutoff)
+        for li in range(M.shape[1]):
+            if abs(M[ki, li]) <= tol:
+                continue
+            l = np.unravel_index(li, cutoff)
+            d = tuple(int(b - a) for a, b in zip(k, l))
+            box = out.setdefault(d, np.zeros(tuple(cutoff), dtype=np.complex128))
+            box[tuple(int(a) for a in k)] = M[ki, li]
+    return out
+
+
+# ------------------------------------------------------------------ states
+
+def mode_amplitudes(nc: int, kind: str, value) -> np.ndarray:
+    """Number-basis amplitudes c_n of one mode's state.
+
+    fock: c = delta_{n, value}.
+    coherent: c_n = alpha^n / sqrt(n!), renormalised on the truncated space.
+    """
+    if kind == "fock":
+        c = np.zeros(nc, dtype=np.complex128)
+        c[int(value)] = 1.0
+        return c
+    if kind == "coherent":
+        alpha = complex(value)
+        c = np.array([alpha ** n / math.sqrt(math.factorial(n)) for n in range(nc)],
+                     dtype=np.complex128)
+        return c / np.linalg.norm(c)
+    raise ValueError(kind)
+
+
+def state_amplitudes(cutoff: Sequence[int], state) -> List[np.ndarray]:
+    kind, vals = state
+    if kind == "product":
+        return [np.asarray(v, dtype=np.complex128) for v in vals]
+    return [mode_amplitudes(nc, kind, v) for nc, v in zip(cutoff, vals)]
+
+
+def expectation(cutoff: Sequence[int], ops: Sectors, state) -> complex:
+    """<psi0| A |psi0> = sum_{k,l} conj(c_k) A[k,l] c_l for a product state."""
+    amps = state_amplitudes(cutoff, state)
+    total = 0.0 + 0.0j
+    for d, box in ops.items():
+        left = np.ones((1,) * len(cutoff), dtype=np.complex128)
+        right = np.ones((1,) * len(cutoff), dtype=np.complex128)
+        for j, (c, dj) in enumerate(zip(amps, d)):
+            nc = len(c)
+            shifted = np.zeros(nc, dtype=np.complex128)
+            for k in range(nc):
+                if 0 <= k + dj < nc:
+                    shifted[k] = c[k + dj]
+            shape = [1] * len(cutoff)
+            shape[j] = nc
+            left = left * np.conj(c).reshape(shape)
+            right = right * shifted.reshape(shape)
+        total += complex(np.sum(left * box * right))
+    return total
+
+
+# ------------------------------------------------------- coefficient maps
+
+def adag_matrix(nc: int) -> np.ndarray:
+    m = np.zeros((nc, nc), dtype=np.complex128)
+    for n in range(1, nc):
+        m[n, n - 1] = math.sqrt(n)
+    return m
+
+
+def number_from_normal(f: np.ndarray) -> np.ndarray:
+    """Single mode: the matrix of sum_{p,q} f[p,q] (a^+)^p a^q on the
+    truncated space (Eq. (2) with o1 = a^+, o2 = a), by matrix products."""
+    nc = f.shape[0]
+    ad = adag_matrix(nc)
+    a = ad.conj().T
+    out = np.zeros((nc, nc), dtype=np.complex128)
+    for p in range(nc):
+        for q in range(nc):
+            if f[p, q] != 0:
+                out += f[p, q] * np.linalg.matrix_power(ad, p) @ np.linalg.matrix_power(a, q)
+    return out
+
+
+def g_from_f(f: np.ndarray, r: complex = 1.0) -> np.ndarray:
+    """Eq. (6): g[k,l] = sum_{j=0}^{min(k,l)} r^{-j}/j! f[k-j, l-j]."""
+    nc0, nc1 = f.shape
+    g = np.zeros_like(f, dtype=np.complex128)
+    for k in range(nc0):
+        for l in range(nc1):
+            g[k, l] = sum(r ** (-j) / math.factorial(j) * f[k - j, l - j]
+                          for j in range(min(k, l) + 1))
+    return g
+
+
+def f_from_g(g: np.ndarray, r: complex = 1.0) -> np.ndarray:
+    """Inverse of Eq. (6), the inner sum of Eq. (11):
+    f[k,l] = sum_{j=0}^{min(k,l)} (-r)^{-j}/j! g[k-j, l-j]."""
+    nc0, nc1 = g.shape
+    f = np.zeros_like(g, dtype=np.complex128)
+    for k in range(nc0):
+        for l in range(nc1):
+            f[k, l] = sum((-r) ** (-j) / math.factorial(j) * g[k - j, l - j]
+                          for j in range(min(k, l) + 1))
+    return f
+
+
+def basis_T(k: int, l: int, nc: int, r: complex = 1.0) -> np.ndarray:
+    """Eq. (8) on the truncated space: T_{k,l} = sum_j (-r)^{-j}/j! (a^+)^{k+j} a^{l+j}."""
+    ad = adag_matrix(nc)
+    a = ad.conj().T
+    out = np.zeros((nc, nc), dtype=np.complex128)
+    for j in range(nc):
+        if k + j >= nc or l + j >= nc:
+            break
+        out += (-r) ** (-j) / math.factorial(j) * (np.linalg.matrix_power(ad, k + j)
+                                                   @ np.linalg.matrix_power(a, l + j))
+    return out

@@ -1,0 +1,318 @@
+/*
+ * Plain FP64 CPU oracle: the adjoint (Heisenberg-picture) Lindblad master
+ * equation of damped, Kerr-coupled bosonic modes, written directly in the
+ * truncated number basis and integrated with classical fourth-order
+ * Runge-Kutta.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no code with the HIP path.
+ *
+ * What it computes (paper: adjoint master equation, Eq. (3)):
+ *   dA/dt = i[H, A] + sum_n (kappa_n/2) (2 L_n^+ A L_n - {L_n^+ L_n, A})
+ * with
+ *   H = sum_j [Delta_j n_j + (K_j/2) a_j^+ a_j^+ a_j a_j] + sum_{i<j} chi_ij n_i n_j
+ * and, for every mode j, three channels
+ *   L = a_j    with kappa = gamma1_j (1 + nth_j)      (emission into the bath)
+ *   L = a_j^+  with kappa = gamma1_j nth_j            (absorption from the bath)
+ *   L = n_j    with kappa = 2 gamma_phi_j             (pure dephasing)
+ * The ladder operators are the truncated matrices on span{|0>,...,|Nc_j-1>}
+ * (a|0> = 0 and a^+|Nc-1> = 0).
+ *
+ * Storage.  An operator is held by "difference sectors": for a fixed integer
+ * vector d, the sector holds the elements A[k, l] with l = k + d, stored as a
+ * row-major array over the whole box k in prod_j [0, Nc_j) with the last mode
+ * varying fastest; entries whose l falls outside the box are kept at zero.
+ * The equation above maps each sector onto itself (every term moves k and l
+ * together), which is why a sector can be evolved on its own; the full
+ * operator is the set of all sectors.
+ *
+ * Parameter order for sensitivities: K[N], chi[i<j lexicographic], Delta[N],
+ * gamma1[N], gamma_phi[N].
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OMAXN 16
+
+typedef double complex cplx;
+
+typedef struct {
+  int n;
+  int nc[OMAXN];
+  double det[OMAXN], kerr[OMAXN], chi[OMAXN * OMAXN];
+  double g1[OMAXN], gphi[OMAXN], nth[OMAXN];
+} osys;
+
+static int load_sys(osys *s, int n, const int *nc, const double *det, const double *kerr,
+                    const double *chi, const double *g1, const double *gphi, const double *nth) {
+  if (n < 1 || n > OMAXN) return -1;
+  s->n = n;
+  for (int j = 0; j < n; ++j) {
+    if (nc[j] < 1) return -1;
+    s->nc[j] = nc[j];
+    s->det[j] = det[j];
+    s->kerr[j] = kerr[j];
+    s->g1[j] = g1[j];
+    s->gphi[j] = gphi[j];
+    s->nth[j] = nth[j];
+    for (int i = 0; i < n; ++i) s->chi[j * n + i] = chi[j * n + i];
+  }
+  return 0;
+}
+
+static long box_size(const osys *s) {
+  long t = 1;
+  for (int j = 0; j < s->n; ++j) t *= s->nc[j];
+  return t;
+}
+
+/* Energy of the number state |k> (eigenvalue of H above). */
+static double energy(const osys *s, const int *k) {
+  double e = 0.0;
+  for (int j = 0; j < s->n; ++j)
+    e += s->det[j] * k[j] + 0.5 * s->kerr[j] * k[j] * (k[j] - 1);
+  for (int i = 0; i < s->n; ++i)
+    for (int j = i + 1; j < s->n; ++j) e += s->chi[i * s->n + j] * k[i] * k[j];
+  return e;
+}
+
+/* Matrix elements of the truncated single-mode operators. */
+static double elem_a(int row, int col, int nc) { /* <row| a |col> */
+  return (col >= 1 && row == col - 1 && col < nc) ? sqrt((double)col) : 0.0;
+}
+static double elem_adag(int row, int col, int nc) { /* <row| a^+ |col> */
+  return (row >= 1 && col == row - 1 && row < nc) ? sqrt((double)row) : 0.0;
+}
+
+/*
+ * One right-hand-side evaluation on one sector.  For element (k, l):
+ *   i (E_k - E_l) A[k,l]
+ *   + sum over channels of (kappa/2) (2 (L^+ A L)[k,l] - (L^+L)[k,k] A[k,l] - A[k,l] (L^+L)[l,l])
+ * All three jump operators map a number state to (a multiple of) a single
+ * number state, so L^+ A L touches exactly one element of A and L^+ L is
+ * diagonal.
+ */
+static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out) {
+  const int n = s->n;
+  const long total = box_size(s);
+  long stride[OMAXN];
+  stride[n - 1] = 1;
+  for (int j = n - 2; j >= 0; --j) stride[j] = stride[j + 1] * s->nc[j + 1];
+
+#pragma omp parallel for schedule(static)
+  for (long f = 0; f < total; ++f) {
+    int k[OMAXN], l[OMAXN];
+    long rem = f;
+    int inside = 1;
+    for (int j = 0; j < n; ++j) {
+      k[j] = (int)(rem / stride[j]);
+      rem %= stride[j];
+      l[j] = k[j] + d[j];
+      if (l[j] < 0 || l[j] >= s->nc[j]) inside = 0;
+    }
+    if (!inside) {
+      out[f] = 0.0;
+      continue;
+    }
+    const cplx a = A[f];
+    cplx r = I * (energy(s, k) - energy(s, l)) * a;
+    for (int j = 0; j < n; ++j) {
+      const int nc = s->nc[j];
+      const int kj = k[j], lj = l[j];
+      /* channel L = a_j: L^+ A L = a^+ A a; (a^+ a)[m,m] = m */
+      {
+        const double kap = s->g1[j] * (1.0 + s->nth[j]);
+        cplx sandwich = 0.0;
+        if (kj >= 1 && lj >= 1) /* (a^+ A a)[k,l] = <k|a^+|k-1> A[k-1,l-1] <l-1|a|l> */
+          sandwich = elem_adag(kj, kj - 1, nc) * A[f - stride[j]] * elem_a(lj - 1, lj, nc);
+        r += 0.5 * kap * (2.0 * sandwich - (double)kj * a - (double)lj * a);
+      }
+      /* channel L = a_j^+: L^+ A L = a A a^+; (a a^+)[m,m] = m+1 below the top level, 0 at it */
+      {
+        const double kap = s->g1[j] * s->nth[j];
+        cplx sandwich = 0.0;
+        if (kj + 1 < nc && lj + 1 < nc)
+          sandwich = elem_a(kj, kj + 1, nc) * A[f + stride[j]] * elem_adag(lj + 1, lj, nc);
+        const double aadag_k = (kj + 1 < nc) ? (double)(kj + 1) : 0.0;
+        const double aadag_l = (lj + 1 < nc) ? (double)(lj + 1) : 0.0;
+        r += 0.5 * kap * (2.0 * sandwich - aadag_k * a - aadag_l * a);
+      }
+      /* channel L = n_j: L^+ A L = n A n; (n n)[m,m] = m^2 */
+      {
+        const double kap = 2.0 * s->gphi[j];
+        const cplx sandwich = (double)kj * a * (double)lj;
+        r += 0.5 * kap * (2.0 * sandwich - (double)(kj * kj) * a - (double)(lj * lj) * a);
+      }
+    }
+    out[f] = r;
+  }
+}
+
+static void rhs_all(const osys *s, int nsec, const int *d, const cplx *A, cplx *out) {
+  const long box = box_size(s);
+  for (int q = 0; q < nsec; ++q) rhs_sector(s, d + q * s->n, A + q * box, out + q * box);
+}
+
+/* y <- x + c * z, elementwise */
+static void axpy_into(long len, cplx *y, const cplx *x, double c, const cplx *z) {
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < len; ++i) y[i] = x[i] + c * z[i];
+}
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int oracle_rhs(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+               const double *g1, const double *gphi, const double *nth, int nsec, const int *d,
+               const cplx *A, cplx *out, int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  set_threads(nthreads);
+  rhs_all(&s, nsec, d, A, out);
+  return 0;
+}
+
+/*
+ * Classical RK4 with fixed step h:
+ *   k1 = f(A), k2 = f(A + h/2 k1), k3 = f(A + h/2 k2), k4 = f(A + h k3),
+ *   A <- A + h/6 (k1 + 2 k2 + 2 k3 + k4).
+ */
+int oracle_evolve(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+                  const double *g1, const double *gphi, const double *nth, int nsec, const int *d,
+                  cplx *A, long nsteps, double h, int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  set_threads(nthreads);
+  const long len = box_size(&s) * nsec;
+  cplx *kk = malloc(sizeof(cplx) * len);
+  cplx *Y = malloc(sizeof(cplx) * len);
+  cplx *acc = malloc(sizeof(cplx) * len);
+  if (!kk || !Y || !acc) {
+    free(kk); free(Y); free(acc);
+    return -2;
+  }
+  for (long step = 0; step < nsteps; ++step) {
+    rhs_all(&s, nsec, d, A, kk);            /* k1 */
+    axpy_into(len, acc, A, h / 6.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    rhs_all(&s, nsec, d, Y, kk);            /* k2 */
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    rhs_all(&s, nsec, d, Y, kk);            /* k3 */
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h, kk);
+    rhs_all(&s, nsec, d, Y, kk);            /* k4 */
+    axpy_into(len, A, acc, h / 6.0, kk);
+  }
+  free(kk); free(Y); free(acc);
+  return 0;
+}
+
+int oracle_num_params(int n) { return n + n * (n - 1) / 2 + 3 * n; }
+
+/*
+ * The right-hand side is linear in the parameter vector
+ * theta = (K, chi[i<j], Delta, gamma1, gamma_phi) for fixed nth, so its
+ * derivative along theta_p is the right-hand side of a system whose only
+ * non-zero parameter is theta_p = 1.
+ */
+static void unit_system(const osys *s, int p, osys *u) {
+  const int n = s->n;
+  *u = *s;
+  memset(u->det, 0, sizeof(u->det));
+  memset(u->kerr, 0, sizeof(u->kerr));
+  memset(u->chi, 0, sizeof(u->chi));
+  memset(u->g1, 0, sizeof(u->g1));
+  memset(u->gphi, 0, sizeof(u->gphi));
+  if (p < n) { u->kerr[p] = 1.0; return; }
+  p -= n;
+  const int npair = n * (n - 1) / 2;
+  if (p < npair) {
+    int q = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j, ++q)
+        if (q == p) { u->chi[i * n + j] = 1.0; u->chi[j * n + i] = 1.0; }
+    return;
+  }
+  p -= npair;
+  if (p < n) { u->det[p] = 1.0; return; }
+  p -= n;
+  if (p < n) { u->g1[p] = 1.0; return; }
+  p -= n;
+  u->gphi[p] = 1.0;
+}
+
+/*
+ * Forward sensitivities: the augmented state (A, S_1..S_P) with
+ *   dS_p/dt = f(S_p) + (df/dtheta_p)(A)
+ * integrated with the same RK4 steps.  S_p(T) is then the exact derivative
+ * of the discrete map A(0) -> A(T) with respect to theta_p.  S must hold
+ * P * nsec * box elements and is overwritten (S_p(0) = 0).
+ */
+int oracle_evolve_sens(int n, const int *nc, const double *det, const double *kerr,
+                       const double *chi, const double *g1, const double *gphi, const double *nth,
+                       int nsec, const int *d, cplx *A, cplx *S, long nsteps, double h,
+                       int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  set_threads(nthreads);
+  const int P = oracle_num_params(n);
+  const long len = box_size(&s) * nsec;
+  const long tot = len * (P + 1);
+  osys *units = malloc(sizeof(osys) * P);
+  cplx *X = malloc(sizeof(cplx) * tot);   /* [A | S_1 | ... | S_P] */
+  cplx *kk = malloc(sizeof(cplx) * tot);
+  cplx *Y = malloc(sizeof(cplx) * tot);
+  cplx *acc = malloc(sizeof(cplx) * tot);
+  cplx *tmp = malloc(sizeof(cplx) * len);
+  if (!units || !X || !kk || !Y || !acc || !tmp) {
+    free(units); free(X); free(kk); free(Y); free(acc); free(tmp);
+    return -2;
+  }
+  for (int p = 0; p < P; ++p) unit_system(&s, p, &units[p]);
+  memcpy(X, A, sizeof(cplx) * len);
+  memset(X + len, 0, sizeof(cplx) * len * P);
+
+  for (long step = 0; step < nsteps; ++step) {
+    for (int st = 0; st < 4; ++st) {
+      const cplx *src = (st == 0) ? X : Y;
+      /* kk = F(src): the augmented right-hand side */
+      rhs_all(&s, nsec, d, src, kk);
+      for (int p = 0; p < P; ++p) {
+        rhs_all(&s, nsec, d, src + len * (p + 1), kk + len * (p + 1));
+        rhs_all(&units[p], nsec, d, src, tmp);
+        axpy_into(len, kk + len * (p + 1), kk + len * (p + 1), 1.0, tmp);
+      }
+      static const double wacc[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+      static const double wnext[3] = {0.5, 0.5, 1.0};
+      if (st == 0) axpy_into(tot, acc, X, h * wacc[0], kk);
+      else if (st < 3) axpy_into(tot, acc, acc, h * wacc[st], kk);
+      if (st < 3) axpy_into(tot, Y, X, h * wnext[st], kk);
+      else axpy_into(tot, X, acc, h * wacc[3], kk);
+    }
+  }
+  memcpy(A, X, sizeof(cplx) * len);
+  memcpy(S, X + len, sizeof(cplx) * len * P);
+  free(units); free(X); free(kk); free(Y); free(acc); free(tmp);
+  return 0;
+}

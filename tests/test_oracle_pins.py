@@ -1,0 +1,283 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these compares the oracle with itself: each check uses a closed form,
+an invariant, an independent dense construction (Kronecker-product
+superoperator + scipy expm), or the exact polynomial of classical RK4.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import pinlib
+
+
+def small_system(seed=0, cutoff=(3, 4), **kw):
+    return synth.random_system(cutoff, seed, **kw)
+
+
+# --------------------------------------------------------------- invariants
+
+def test_identity_is_stationary(oracle_lib):
+    """Adjoint master equation, Eq. (3): L^dagger(I) = 0 (trace preservation)."""
+    s = small_system(1, (4, 3, 3))
+    ops = {(0, 0, 0): np.ones(s.cutoff, dtype=np.complex128)}
+    r = oracle.rhs(s, ops)
+    assert np.max(np.abs(r[(0, 0, 0)])) < 1e-12
+    out = oracle.evolve(s, ops, 0.2, 1e-3)
+    assert np.max(np.abs(out[(0, 0, 0)] - 1.0)) < 1e-12
+
+
+def test_hermiticity_preserved(oracle_lib):
+    """Eq. (3) maps Hermitian operators to Hermitian operators: sector -d is the
+    conjugate transpose of sector d at all times."""
+    s = small_system(2, (3, 4))
+    rng = np.random.default_rng(5)
+    dim = 12
+    M = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    M = M + M.conj().T
+    ops = oracle.sectors_from_dense(s.cutoff, M)
+    out = oracle.evolve(s, ops, 0.3, 1e-3)
+    Mt = oracle.dense_from_sectors(s.cutoff, out)
+    assert np.max(np.abs(Mt - Mt.conj().T)) < 1e-13 * np.max(np.abs(Mt))
+    assert pinlib.rel(Mt, M) > 1e-3  # it did evolve
+
+
+def test_sectors_do_not_leak(oracle_lib):
+    """Every term of the master equation shifts k and l together, so the full
+    operator evolved as one object equals its sectors evolved separately."""
+    s = small_system(3, (3, 3))
+    rng = np.random.default_rng(6)
+    M = rng.normal(size=(9, 9)) + 1j * rng.normal(size=(9, 9))
+    ops = oracle.sectors_from_dense(s.cutoff, M)
+    whole = oracle.dense_from_sectors(s.cutoff, oracle.evolve(s, ops, 0.1, 1e-3))
+    parts = np.zeros_like(whole)
+    for d, box in ops.items():
+        parts += oracle.dense_from_sectors(s.cutoff, oracle.evolve(s, {d: box}, 0.1, 1e-3))
+    assert pinlib.rel(parts, whole) < 1e-14
+
+
+# ------------------------------------------------------- dense expm pin
+
+@pytest.mark.parametrize("cutoff,seed", [((3, 3), 11), ((4,), 12), ((2, 3, 2), 13)])
+def test_against_dense_superoperator_expm(oracle_lib, cutoff, seed):
+    """The oracle's RK4 result equals exp(S T) applied to A(0), with S the
+    adjoint Liouvillian built from Kronecker products, within RK4's error."""
+    s = small_system(seed, cutoff, n_th=0.3)
+    rng = np.random.default_rng(seed)
+    dim = int(np.prod(cutoff))
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    ops = oracle.sectors_from_dense(cutoff, A0)
+    T, dt = 0.5, 1e-3
+    got = oracle.dense_from_sectors(cutoff, oracle.evolve(s, ops, T, dt))
+    ref = pinlib.expm_evolve(s, A0, T)
+    assert pinlib.rel(got, ref) < 1e-10
+
+
+def test_rk4_converges_at_fourth_order(oracle_lib):
+    """Halving dt cuts the error against the exact exponential ~16x
+    (the reference-method recipe of the paper uses half the time step)."""
+    s = small_system(21, (3, 3), scale=20.0, n_th=0.2)
+    rng = np.random.default_rng(21)
+    A0 = rng.normal(size=(9, 9)) + 1j * rng.normal(size=(9, 9))
+    ops = oracle.sectors_from_dense(s.cutoff, A0)
+    T = 0.2
+    ref = pinlib.expm_evolve(s, A0, T)
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        got = oracle.dense_from_sectors(s.cutoff, oracle.evolve(s, ops, T, dt))
+        errs.append(pinlib.rel(got, ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 12 < r1 < 20 and 12 < r2 < 20, errs
+
+
+# ------------------------------------------------------- closed forms
+
+def test_no_jumps_matches_rk4_polynomial(oracle_lib):
+    """With gamma1 = 0 only the diagonal rates remain: each element gets
+    R(lambda h)^M with R the RK4 stability polynomial and
+    lambda = i(E_k - E_l) - gamma_phi (k - l)^2, exactly (up to rounding)."""
+    s = small_system(31, (4, 3))
+    s.gamma1[:] = 0.0
+    rng = np.random.default_rng(31)
+    A0 = rng.normal(size=(12, 12)) + 1j * rng.normal(size=(12, 12))
+    ops = oracle.sectors_from_dense(s.cutoff, A0)
+    h, M = 2e-3, 150
+    got = oracle.dense_from_sectors(s.cutoff, oracle.evolve_steps(s, ops, M, h))
+    ref = np.zeros_like(A0)
+    for ki in range(12):
+        k = np.unravel_index(ki, s.cutoff)
+        for li in range(12):
+            l = np.unravel_index(li, s.cutoff)
+
+            def E(v):
+                e = sum(s.detuning[j] * v[j] + 0.5 * s.kerr[j] * v[j] * (v[j] - 1) for j in range(2))
+                return e + s.cross_kerr[0, 1] * v[0] * v[1]
+
+            lam = 1j * (E(k) - E(l)) - sum(s.gamma_phi[j] * (k[j] - l[j]) ** 2 for j in range(2))
+            ref[ki, li] = pinlib.rk4_polynomial(lam * h) ** M * A0[ki, li]
+    assert pinlib.rel(got, ref) < 1e-13
+
+
+def test_number_operator_closed_form(oracle_lib):
+    """<a^+a>(t) = e^{-gamma t} <a^+a>(0) + n_th (1 - e^{-gamma t}) for a damped
+    mode with thermal bath (the closed form the damped oscillator obeys)."""
+    nc = 24
+    g, nth = 0.7, 0.05
+    s = synth.System((nc,), np.array([0.3]), np.array([-4.0]), np.zeros((1, 1)),
+                     np.array([g]), np.array([0.4]), np.array([nth]))
+    ops = {(0,): np.arange(nc, dtype=np.complex128)}
+    T = 1.3
+    out = oracle.evolve(s, ops, T, 1e-3)
+    for alpha in (0.0, 0.8, 1.2 + 0.5j):
+        got = oracle.expectation(s.cutoff, out, ("coherent", [alpha])).real
+        ref = math.exp(-g * T) * abs(alpha) ** 2 + nth * (1 - math.exp(-g * T))
+        assert abs(got - ref) < 1e-11
+
+
+def test_single_mode_zero_temperature_projector(oracle_lib):
+    """n_th = 0: <n| P1(T) |n> = n e^{-gT} (1 - e^{-gT})^{n-1} (binomial
+    thinning of a Fock state) and, for a coherent state, s e^{-s} with
+    s = |alpha|^2 e^{-gT} (Poisson thinning).  Kerr and dephasing do not
+    change populations."""
+    nc = 30
+    g = 0.02
+    s = synth.System((nc,), np.array([0.0]), np.array([synth.TWO_PI * -200.0]), np.zeros((1, 1)),
+                     np.array([g]), np.array([0.01]), np.array([0.0]))
+    ops = oracle.product_sectors(synth.projector_factors((nc,), (1,)))
+    T = 10.0
+    out = oracle.evolve(s, ops, T, 1e-2)
+    e = math.exp(-g * T)
+    for n in range(0, 6):
+        got = oracle.expectation(s.cutoff, out, ("fock", [n])).real
+        ref = n * e * (1 - e) ** (n - 1) if n >= 1 else 0.0
+        assert abs(got - ref) < 1e-12
+    a = 1.1
+    got = oracle.expectation(s.cutoff, out, ("coherent", [a])).real
+    sv = a * a * e
+    assert abs(got - sv * math.exp(-sv)) < 1e-12
+
+
+def test_single_mode_thermal_projector(oracle_lib):
+    """n_th > 0, coherent state: the damped state is a displaced thermal state
+    with amplitude beta = alpha e^{-gT/2} and occupation nt = n_th (1 - e^{-gT});
+    its |1> population is e^{-|b|^2/(1+nt)} [nt/(1+nt)^2 + |b|^2/(1+nt)^3]."""
+    nc = 30
+    g, nth = 0.5, 0.2
+    s = synth.System((nc,), np.array([0.7]), np.array([-3.0]), np.zeros((1, 1)),
+                     np.array([g]), np.array([0.3]), np.array([nth]))
+    ops = oracle.product_sectors(synth.projector_factors((nc,), (1,)))
+    T = 1.5
+    out = oracle.evolve(s, ops, T, 1e-3)
+    for alpha in (0.6, 1.0 - 0.4j):
+        got = oracle.expectation(s.cutoff, out, ("coherent", [alpha])).real
+        b2 = abs(alpha) ** 2 * math.exp(-g * T)
+        nt = nth * (1 - math.exp(-g * T))
+        ref = math.exp(-b2 / (1 + nt)) * (nt / (1 + nt) ** 2 + b2 / (1 + nt) ** 3)
+        assert abs(got - ref) < 1e-11
+
+
+# ------------------------------------------------------- structure
+
+def test_product_observable_factorises(oracle_lib):
+    """On the diagonal sector the generator is a sum of commuting single-mode
+    generators, so a product observable in a product state gives the product
+    of single-mode expectation values (up to RK4's O(h^5) splitting term)."""
+    s = small_system(41, (5, 4, 6), n_th=0.1)
+    bits = (1, 0, 2)
+    alpha = (0.7, 1.1j, 0.5 - 0.2j)
+    ops = oracle.product_sectors(synth.projector_factors(s.cutoff, bits))
+    out = oracle.evolve(s, ops, 1.0, 1e-3)
+    J = oracle.expectation(s.cutoff, out, ("coherent", alpha))
+    prod = 1.0
+    for j in range(3):
+        sj = synth.System((s.cutoff[j],), s.detuning[j:j + 1], s.kerr[j:j + 1], np.zeros((1, 1)),
+                          s.gamma1[j:j + 1], s.gamma_phi[j:j + 1], s.n_th[j:j + 1])
+        oj = oracle.evolve(sj, oracle.product_sectors([synth.projector_factors(
+            (s.cutoff[j],), (bits[j],))[0]]), 1.0, 1e-3)
+        prod *= oracle.expectation(sj.cutoff, oj, ("coherent", [alpha[j]]))
+    assert abs(J - prod) < 1e-12 * abs(prod)
+
+
+def test_diagonal_sector_ignores_hamiltonian_and_dephasing(oracle_lib):
+    s = small_system(51, (4, 5), n_th=0.1)
+    ops = oracle.product_sectors(synth.projector_factors(s.cutoff, (1, 2)))
+    a = oracle.evolve(s, ops, 0.7, 1e-3)
+    s2 = s.copy()
+    s2.kerr[:] = 0
+    s2.detuning[:] = 0
+    s2.cross_kerr[:] = 0
+    s2.gamma_phi[:] = 0
+    b = oracle.evolve(s2, ops, 0.7, 1e-3)
+    assert pinlib.rel(a[(0, 0)], b[(0, 0)]) < 1e-14
+
+
+# ------------------------------------------------------- coefficient maps
+
+@pytest.mark.parametrize("nc", [1, 4, 7])
+def test_coefficient_maps(nc):
+    """Eq. (6) and the inner sum of Eq. (11) are inverse maps; the basis of
+    Eqs. (7)-(8) with r = 1 is T_{k,l} = sqrt(k! l!) |k><l| on the truncated
+    space, so g_{k,l} = <k|A|l> / sqrt(k! l!)."""
+    f = synth.random_normal_coeffs(nc, 7 + nc)
+    g = oracle.g_from_f(f)
+    assert np.max(np.abs(oracle.f_from_g(g) - f)) < 1e-12 * np.max(np.abs(f))
+    A = oracle.number_from_normal(f)
+    scale = np.array([[math.sqrt(math.factorial(k) * math.factorial(l)) for l in range(nc)]
+                      for k in range(nc)])
+    assert np.max(np.abs(g * scale - A)) < 1e-11 * np.max(np.abs(A))
+    for k in range(nc):
+        for l in range(nc):
+            T = oracle.basis_T(k, l, nc)
+            ref = np.zeros((nc, nc))
+            ref[k, l] = scale[k, l]
+            assert np.max(np.abs(T - ref)) < 1e-10 * scale[k, l]
+    # Eq. (7): A = sum g_kl T_kl
+    recon = sum(g[k, l] * oracle.basis_T(k, l, nc) for k in range(nc) for l in range(nc))
+    assert np.max(np.abs(recon - A)) < 1e-10 * max(1.0, np.max(np.abs(A)))
+
+
+# ------------------------------------------------------- sensitivities
+
+def test_sensitivities_match_finite_differences(oracle_lib):
+    """Forward sensitivities of the discrete RK4 map against central finite
+    differences of the oracle's own expectation value."""
+    s = small_system(61, (3, 4), n_th=0.2)
+    rng = np.random.default_rng(61)
+    A0 = rng.normal(size=(12, 12)) + 1j * rng.normal(size=(12, 12))
+    A0 = A0 + A0.conj().T
+    ops = oracle.sectors_from_dense(s.cutoff, A0)
+    state = ("coherent", (0.6 + 0.2j, 0.9))
+    T, dt = 0.2, 2e-3
+    _, sens = oracle.evolve_sens(s, ops, T, dt)
+    n = s.n_modes
+    names = []
+    for j in range(n):
+        names.append(("kerr", j))
+    for i in range(n):
+        for j in range(i + 1, n):
+            names.append(("chi", (i, j)))
+    for j in range(n):
+        names.append(("detuning", j))
+    for j in range(n):
+        names.append(("gamma1", j))
+    for j in range(n):
+        names.append(("gamma_phi", j))
+    assert len(names) == oracle.num_params(n) == len(sens)
+    for p, (field, idx) in enumerate(names):
+        def J(delta):
+            s2 = s.copy()
+            if field == "chi":
+                s2.cross_kerr[idx] += delta
+                s2.cross_kerr[idx[::-1]] += delta
+            else:
+                getattr(s2, field)[idx] += delta
+            return oracle.expectation(s2.cutoff, oracle.evolve(s2, ops, T, dt), state)
+
+        h = 1e-5
+        fd = (J(h) - J(-h)) / (2 * h)
+        an = oracle.expectation(s.cutoff, sens[p], state)
+        assert abs(an - fd) < 1e-7 * max(1.0, abs(fd)), (field, idx, an, fd)
