@@ -1,0 +1,230 @@
+/*
+ * hgf.h -- C ABI of the MI355X (gfx950) generating-function solver for the
+ * adjoint Lindblad master equation of damped, Kerr-coupled bosonic modes.
+ *
+ * Method (paper: "Efficient classical simulation of open bosonic quantum
+ * systems", arXiv:2203.05526):
+ *   (i)   an operator A(0) is mapped to the coefficients g_{k,l}(0) of its
+ *         transformed generating function G = e^{xy} F (Eqs. (2), (5)-(8));
+ *   (ii)  the G equations (Eqs. (9) and (17)-(19)) are integrated with
+ *         fourth-order Runge-Kutta, each independent function in parallel;
+ *   (iii) the result is read out as <psi0| A(T) |psi0> (Eq. (11) contracted
+ *         with a product state).
+ * With o1 = a^+, o2 = a (r = 1) the basis element T_{k,l} of Eq. (8) is
+ * sqrt(k! l!) |k><l| on the truncated space, so g_{k,l} = <k|A|l>/sqrt(k! l!)
+ * per mode.  The physics handled is
+ *   H = sum_j [Delta_j n_j + (K_j/2) a_j^+ a_j^+ a_j a_j] + sum_{i<j} chi_ij n_i n_j
+ * with, per mode, emission (a_j, rate gamma1_j (1 + n_th_j)), absorption
+ * (a_j^+, rate gamma1_j n_th_j) and dephasing (n_j, rate 2 gamma_phi_j) in the
+ * Lindblad form of Eq. (3).  Every term then moves k and l together, so the
+ * occupation difference d = l - k is conserved and the grid of one function is
+ * an N-dimensional box over m_j = min(k_j, l_j), extent Nc_j - |d_j|.
+ *
+ * Conventions for every entry point:
+ *  - Units: time in microseconds, angular frequency in rad/us, rates in 1/us.
+ *  - Complex numbers are interleaved (re, im) doubles.
+ *  - Arrays of a mode-indexed quantity are ordered by mode 0..N-1.  Grids are
+ *    row-major over m with the last mode varying fastest.
+ *  - Inputs are copied during the call; the caller keeps its arrays.
+ *  - Outputs go to caller-provided buffers.
+ *  - Every call returns an hgf_status; nothing is thrown across the ABI.
+ *    On error, hgf_last_error() returns a thread-local message and the handle
+ *    passed in is left as it was (except as noted for hgf_evolve).
+ *  - `hip_stream` is a hipStream_t (NULL means the null stream).  Work is
+ *    enqueued on it; calls that return host values synchronise it.
+ *  - Handles are not thread-safe; calls on different handles may run on
+ *    different threads.
+ */
+#ifndef HGF_H
+#define HGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HGF_OK = 0,
+  HGF_EINVAL = -1,       /* malformed or out-of-range argument */
+  HGF_ENOMEM = -2,       /* device or host allocation failed */
+  HGF_EDEVICE = -3,      /* a HIP runtime call failed */
+  HGF_EUNSTABLE = -4,    /* dt outside the RK4 stability bound of the generator */
+  HGF_ENONFINITE = -5,   /* a NaN or Inf appeared in an evolved function */
+  HGF_EUNSUPPORTED = -6, /* valid request this build does not implement */
+  HGF_ESTATE = -7        /* handle in a state that forbids the call */
+} hgf_status;
+
+/* precision of an operator's functions */
+enum {
+  HGF_FP64 = 0,  /* every grid in complex128, stencil in FP64 */
+  HGF_MIXED = 1  /* RK stage grids complex64 with FP32 stencil; state complex128 */
+};
+
+/* how an operator's coefficients are grouped into independently evolved functions */
+enum {
+  HGF_MERGED = 0, /* one grid per occupation-difference sector, initial value the
+                     sector's part of G(0) (Eq. (10) summed up front by linearity) */
+  HGF_SPLIT = 1   /* one function per non-negligible g_{p,q}(0): G = Gx Gy + R with
+                     Gx = c_x x^p, Gy = c_y y^q, R(0) = 0 (Eqs. (9)-(10), (19)) */
+};
+
+/* operator input forms */
+enum {
+  HGF_OP_PRODUCT = 0, /* A = tensor product of per-mode Nc_j x Nc_j matrices */
+  HGF_OP_SPARSE = 1   /* A = sum_t value_t M(k_t, l_t) */
+};
+enum {
+  HGF_BASIS_NUMBER = 0, /* entries are number-basis elements <k|A|l> */
+  HGF_BASIS_NORMAL = 1  /* entries are the normal-ordered coefficients f_{k,l} of Eq. (2) */
+};
+
+/* product states psi0 = tensor product over modes */
+enum {
+  HGF_PSI_FOCK = 0,     /* |n_0> x |n_1> x ... */
+  HGF_PSI_COHERENT = 1, /* coherent |alpha_j>, truncated to the cutoff and renormalised */
+  HGF_PSI_PRODUCT = 2   /* arbitrary per-mode amplitude vectors (used as given) */
+};
+
+typedef struct hgf_system_s* hgf_system;
+typedef struct hgf_operator_s* hgf_operator;
+
+typedef struct {
+  int32_t n_modes;          /* 1 .. HGF_MAX_MODES */
+  const int32_t* cutoff;    /* [N] Fock levels kept per mode, 1 .. HGF_MAX_CUTOFF */
+  const double* detuning;   /* [N] Delta_j, rad/us */
+  const double* kerr;       /* [N] K_j, rad/us */
+  const double* cross_kerr; /* [N*N] chi_ij, rad/us, symmetric; the diagonal is ignored */
+  const double* gamma1;     /* [N] 1/T1, 1/us, >= 0 */
+  const double* gamma_phi;  /* [N] 1/Tphi, 1/us, >= 0 */
+  const double* n_th;       /* [N] bath occupation, >= 0 */
+} hgf_system_desc;
+
+#define HGF_MAX_MODES 16
+#define HGF_MAX_CUTOFF 32
+
+/*
+ * Validate and copy a system description (the Hamiltonian of Eq. (1) and the
+ * dissipators of Eq. (3), restricted as above).  Errors: HGF_EINVAL for a
+ * NULL pointer, N or a cutoff out of range, a negative or non-finite rate,
+ * or a non-symmetric cross_kerr.  *out is owned by the caller and freed by
+ * hgf_destroy_system.
+ */
+hgf_status hgf_define_system(const hgf_system_desc* desc, hgf_system* out);
+void hgf_destroy_system(hgf_system sys);
+
+/* Number of real parameters that hgf_grad differentiates:
+ * K[N], chi[i<j lexicographic], Delta[N], gamma1[N], gamma_phi[N]. */
+int32_t hgf_num_params(hgf_system sys);
+
+typedef struct {
+  int32_t kind;           /* HGF_OP_PRODUCT or HGF_OP_SPARSE */
+  int32_t basis;          /* HGF_BASIS_NUMBER or HGF_BASIS_NORMAL */
+  const double* values;   /* PRODUCT: the N matrices one after another, each
+                             Nc_j x Nc_j row-major complex (2*sum Nc_j^2 doubles);
+                             SPARSE: n_terms complex values (2*n_terms doubles) */
+  const int32_t* indices; /* SPARSE only: n_terms rows of 2N ints (k_0..k_{N-1}, l_0..l_{N-1});
+                             NUMBER basis: M = |k><l|; NORMAL basis: M = prod_j (a_j^+)^{k_j} a_j^{l_j} */
+  int64_t n_terms;        /* SPARSE only */
+  int32_t precision;      /* HGF_FP64 or HGF_MIXED */
+  int32_t layout;         /* HGF_MERGED or HGF_SPLIT */
+  double drop_tol;        /* g_{p,q}(0) with |g| <= drop_tol are dropped (Eqs. (10)-(13)) */
+} hgf_operator_desc;
+
+/*
+ * Step (i): map A(0) to its set of functions and place them on the current
+ * device.  Coefficients follow g_{k,l} = <k|A|l>/sqrt(k! l!) per mode, or
+ * Eq. (6) from normal-ordered f.  Functions are grouped by sector d = l - k
+ * (merged) or one per coefficient (split).  Errors: HGF_EINVAL (bad kind,
+ * basis, layout, precision, index out of the cutoff box, NULL arrays),
+ * HGF_ENOMEM, HGF_EDEVICE.  The operator keeps its own copy of the system.
+ */
+hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_operator* out);
+void hgf_destroy_operator(hgf_operator op);
+
+/*
+ * Step (ii): advance every function of the operator by t_total_us with
+ * classical RK4 steps of dt_us (Heisenberg picture: A(0) -> A(t)).
+ * t_total_us / dt_us must be a non-negative integer (to 1e-9 relative).
+ * Errors: HGF_EINVAL; HGF_EUNSTABLE when dt times a bound on the generator's
+ * spectral radius leaves the RK4 stability region (nothing is run);
+ * HGF_ENONFINITE when a NaN/Inf appears (the functions are restored to the
+ * last state checked finite and the operator moves to an error state in which
+ * further evolves return HGF_ESTATE); HGF_EDEVICE.
+ */
+hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, void* hip_stream);
+
+/*
+ * Batched form of hgf_evolve: every member advances by its own t_total/dt
+ * (arrays of n), all members' RK stages issued as one grouped launch per
+ * stage and captured in a HIP graph.  Members must be distinct handles on the
+ * same device with the layout HGF_MERGED.  Errors as for hgf_evolve; on
+ * error no member has been advanced.
+ */
+hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_us,
+                            const double* dt_us, void* hip_stream);
+
+typedef struct {
+  int32_t kind;         /* HGF_PSI_FOCK, HGF_PSI_COHERENT or HGF_PSI_PRODUCT */
+  const int32_t* fock;  /* FOCK: [N] occupations, each below the cutoff */
+  const double* alpha;  /* COHERENT: [2N] complex alpha_j */
+  const double* amps;   /* PRODUCT: per-mode amplitude vectors, complex, 2*sum Nc_j doubles */
+} hgf_state_desc;
+
+/*
+ * Step (iii): out_re_im = <psi0| A(t) |psi0> for a product state, summed over
+ * every function with FP64 accumulation (Eq. (11) contracted with psi0; in
+ * split mode the separable part c_x c_y x^p y^q is added analytically).
+ * Errors: HGF_EINVAL, HGF_EDEVICE.  Synchronises hip_stream.
+ */
+hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2],
+                           void* hip_stream);
+
+/*
+ * Gradient of J = <psi0| A(T) |psi0> with respect to every parameter of
+ * hgf_num_params, by a discrete adjoint (reverse) sweep of the RK4 steps over
+ * checkpoints taken every `checkpoint_every` steps, in FP64 and merged layout
+ * (desc->precision and desc->layout are ignored).  value_out receives J,
+ * grad_out 2*hgf_num_params doubles (complex dJ/dtheta; real for Hermitian A).
+ * Errors: HGF_EINVAL, HGF_EUNSTABLE, HGF_ENOMEM, HGF_EDEVICE, HGF_ENONFINITE.
+ */
+hgf_status hgf_grad(hgf_system sys, const hgf_operator_desc* desc, const hgf_state_desc* psi,
+                    double t_total_us, double dt_us, int32_t checkpoint_every, double value_out[2],
+                    double* grad_out, void* hip_stream);
+
+typedef struct {
+  int32_t n_functions;
+  int32_t precision;
+  int32_t layout;
+  int32_t n_modes;
+  int64_t total_points;   /* sum of grid points over functions */
+  int64_t steps_done;     /* RK4 steps taken so far */
+  double time_us;         /* t reached so far */
+  int64_t fp32_underflow; /* MIXED: nonzero initial coefficients below FP32's normal range */
+  int32_t error_state;    /* nonzero after HGF_ENONFINITE */
+} hgf_operator_info;
+
+hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
+
+/*
+ * Copy function `idx` to the host for inspection: sector_d [N] gets d = q - p
+ * (merged: the sector), extents [N] the grid extents, grid the complex128
+ * values R(m) (merged: the whole function) row-major, capacity `n_points`
+ * points.  split_out (may be NULL) receives, in split mode, 4N+6 doubles:
+ * p[N], q[N] (as doubles), g_pq(0), c_x, c_y (complex) and then 2N zeros.
+ * Errors: HGF_EINVAL (idx out of range, buffer too small), HGF_EDEVICE.
+ */
+hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int32_t* extents,
+                            double* grid, int64_t n_points, double* split_out, void* hip_stream);
+
+/* Thread-local message describing the last error of this thread ("" if none). */
+const char* hgf_last_error(void);
+
+/* Library version string. */
+const char* hgf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGF_H */

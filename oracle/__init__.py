@@ -329,3 +329,26 @@ def basis_T(k: int, l: int, nc: int, r: complex = 1.0) -> np.ndarray:
         out += (-r) ** (-j) / math.factorial(j) * (np.linalg.matrix_power(ad, k + j)
                                                    @ np.linalg.matrix_power(a, l + j))
     return out
+
+
+def generating_coefficients(cutoff: Sequence[int], ops: Sectors) -> Sectors:
+    """g[k, l] = <k|A|l> / sqrt(prod_j k_j! l_j!): the coefficients of A in the
+    basis T_{k,l} of Eqs. (7)-(8) with o1 = a^+, o2 = a (r = 1)."""
+    out: Sectors = {}
+    for d, box in ops.items():
+        scale = np.ones(tuple(cutoff))
+        for j, (nc, dj) in enumerate(zip(cutoff, d)):
+            s = np.array([math.sqrt(math.factorial(k) * math.factorial(k + dj)) if 0 <= k + dj < nc else 1.0
+                          for k in range(nc)])
+            shape = [1] * len(cutoff)
+            shape[j] = nc
+            scale = scale * s.reshape(shape)
+        out[d] = box / scale
+    return out
+
+
+def sector_grid(cutoff: Sequence[int], d: Sequence[int], box: np.ndarray) -> np.ndarray:
+    """The part of a k-box where l = k + d stays inside the truncated space,
+    indexed by m = min(k, l) (extent Nc_j - |d_j| per mode)."""
+    sl = tuple(slice(max(0, -dj), max(0, -dj) + nc - abs(dj)) for nc, dj in zip(cutoff, d))
+    return box[sl]

@@ -1,0 +1,22 @@
+"""MI355X (gfx950) generating-function solver for the adjoint Lindblad master
+equation of damped Kerr-coupled bosonic modes (arXiv:2203.05526).
+
+The numerical work runs in the HIP library ``libhgf.so`` (C ABI in
+``include/hgf.h``); this package is its Python binding.
+"""
+
+from .hgf import (  # noqa: F401
+    HgfError,
+    Operator,
+    System,
+    define_system,
+    evolve,
+    evolve_batch,
+    expectation,
+    grad,
+    load_library,
+    map_operator,
+    param_names,
+    params_vector,
+    version,
+)

@@ -1,0 +1,1042 @@
+// C-ABI entry points and the host runtime around the HIP kernels: system
+// validation, the operator -> function map (step (i) of the method), the RK4
+// step loop with HIP-graph replay (step (ii)), the expectation value
+// (step (iii)) and the discrete-adjoint gradient.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hgf.h"
+#include "hgf_internal.h"
+#include "hgf_kernels.h"
+
+namespace hgf {
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+thread_local std::string g_last_error;
+
+struct Failure : std::exception {
+  hgf_status code;
+  std::string msg;
+  Failure(hgf_status c, std::string m) : code(c), msg(std::move(m)) {}
+};
+}  // namespace
+
+void set_error(hgf_status code, const std::string& msg) {
+  (void)code;
+  g_last_error = msg;
+}
+
+[[noreturn]] void fail(hgf_status code, const std::string& msg) { throw Failure(code, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) fail(HGF_ENOMEM, std::string(what) + ": out of device memory");
+    fail(HGF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+template <typename F>
+static hgf_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return HGF_OK;
+  } catch (const Failure& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HGF_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HGF_EDEVICE;
+  }
+}
+
+// ------------------------------------------------------------------ helpers
+
+static double sqrt_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return std::sqrt(f);
+}
+
+static double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+static void* dmalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  return p;
+}
+
+static void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// RAII device buffer for temporaries
+struct DBuf {
+  void* p = nullptr;
+  explicit DBuf(size_t bytes) { p = dmalloc(bytes); }
+  ~DBuf() { dfree(p); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+static int64_t check_steps(double t_total, double dt) {
+  if (!(std::isfinite(t_total) && std::isfinite(dt)) || t_total < 0 || dt <= 0)
+    fail(HGF_EINVAL, "t_total must be >= 0 and dt > 0, both finite");
+  const double r = t_total / dt;
+  const int64_t m = (int64_t)std::llround(r);
+  if (std::fabs(r - (double)m) > 1e-9 * std::max(1.0, r))
+    fail(HGF_EINVAL, "t_total must be an integer multiple of dt");
+  return m;
+}
+
+static void check_stability(const std::vector<Function>& fns, double dt) {
+  // RK4's stability region holds the left half-disc of radius ~2.6; the
+  // Gershgorin bound of the sector generator must fit in it.
+  for (const auto& f : fns) {
+    const double b = generator_bound(f.tab) * dt;
+    if (b > 2.5)
+      fail(HGF_EUNSTABLE, "dt * spectral bound = " + std::to_string(b) +
+                              " exceeds the RK4 stability limit 2.5; reduce dt");
+  }
+}
+
+// ------------------------------------------------------------------ functions
+
+static void fill_grid_args(Function& f, int precision) {
+  GridArgs& g = f.ga;
+  std::memset(&g, 0, sizeof(g));
+  const SectorTables& t = f.tab;
+  g.n = t.n;
+  g.nfast = 0;
+  int64_t s = 1;
+  for (int j = t.n - 1; j >= 0; --j) {
+    g.ext[j] = t.ext[j];
+    g.stride[j] = s;
+    s *= t.ext[j];
+  }
+  g.points = s;
+  g.tile_points = 1;
+  g.ntiles = s;
+  int off = 0;
+  for (int j = 0; j < t.n; ++j) {
+    g.off[j] = off;
+    off += t.ext[j];
+    g.alpha[j] = t.alpha[j];
+  }
+  g.lam0_re = t.lam0.real();
+  g.lam0_im = t.lam0.imag();
+  // device tables: lam (double2), beta (double), lam_f (float2), beta_f (float)
+  const int tot = off;
+  std::vector<double> lam(2 * tot), beta(tot);
+  std::vector<float> lamf(2 * tot), betaf(tot);
+  for (int j = 0; j < t.n; ++j)
+    for (int m = 0; m < t.ext[j]; ++m) {
+      const int o = g.off[j] + m;
+      lam[2 * o] = t.lam[j][m].real();
+      lam[2 * o + 1] = t.lam[j][m].imag();
+      beta[o] = t.beta[j][m];
+      lamf[2 * o] = (float)lam[2 * o];
+      lamf[2 * o + 1] = (float)lam[2 * o + 1];
+      betaf[o] = (float)beta[o];
+    }
+  const size_t b_lam = sizeof(double) * 2 * tot, b_beta = sizeof(double) * tot;
+  const size_t b_lamf = sizeof(float) * 2 * tot, b_betaf = sizeof(float) * tot;
+  const size_t total = b_lam + b_beta + b_lamf + b_betaf + 64;
+  f.dtab = dmalloc(total);
+  char* base = (char*)f.dtab;
+  hip_check(hipMemcpy(base, lam.data(), b_lam, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + b_lam, beta.data(), b_beta, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + b_lam + b_beta, lamf.data(), b_lamf, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + b_lam + b_beta + b_lamf, betaf.data(), b_betaf, hipMemcpyHostToDevice),
+            "upload tables");
+  g.lam = (const double2*)base;
+  g.beta = (const double*)(base + b_lam);
+  g.lam_f = (const float2*)(base + b_lam + b_beta);
+  g.beta_f = (const float*)(base + b_lam + b_beta + b_lamf);
+  (void)precision;
+}
+
+static void alloc_function_buffers(Function& f, int precision) {
+  const int64_t P = f.ga.points;
+  const size_t cs = precision == HGF_FP64 ? sizeof(double2) : sizeof(float2);
+  f.y = dmalloc(P * sizeof(double2));
+  f.s1 = dmalloc(P * cs);
+  f.s2 = dmalloc(P * cs);
+  f.s3 = dmalloc(P * cs);
+  if (f.split) f.s4 = dmalloc(P * sizeof(double2));
+}
+
+static void free_function(Function& f) {
+  dfree(f.y);
+  dfree(f.s1);
+  dfree(f.s2);
+  dfree(f.s3);
+  dfree(f.s4);
+  dfree(f.ybak);
+  dfree(f.dtab);
+}
+
+static int64_t flat_index(const SectorTables& t, const int* m) {
+  int64_t idx = 0;
+  for (int j = 0; j < t.n; ++j) idx = idx * t.ext[j] + m[j];
+  return idx;
+}
+
+// Per-mode g-matrix from the per-mode input matrix (Eqs. (6)-(8), r = 1).
+static std::vector<cd> mode_g(const double* vals, int nc, int basis) {
+  std::vector<cd> in(nc * nc), g(nc * nc);
+  for (int i = 0; i < nc * nc; ++i) in[i] = cd(vals[2 * i], vals[2 * i + 1]);
+  for (int k = 0; k < nc; ++k)
+    for (int l = 0; l < nc; ++l) {
+      if (basis == HGF_BASIS_NUMBER) {
+        g[k * nc + l] = in[k * nc + l] / (sqrt_factorial(k) * sqrt_factorial(l));
+      } else {  // Eq. (6): g_{k,l} = sum_j f_{k-j,l-j} / j!
+        cd s = 0.0;
+        for (int j = 0; j <= std::min(k, l); ++j) s += in[(k - j) * nc + (l - j)] / factorial(j);
+        g[k * nc + l] = s;
+      }
+    }
+  return g;
+}
+
+struct Coeff {
+  std::vector<int> k, l;
+  cd v;
+};
+
+// All nonzero g_{k,l}(0) of the operator, as (k, l, value).
+static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map<std::vector<int>, std::vector<cd>>& merged,
+                           std::vector<Coeff>& split, bool want_split) {
+  const int n = s.n;
+  if (d->kind == HGF_OP_PRODUCT) {
+    if (!d->values) fail(HGF_EINVAL, "operator values is NULL");
+    std::vector<std::vector<cd>> gm(n);
+    std::vector<std::vector<int>> diags(n);
+    size_t off = 0;
+    for (int j = 0; j < n; ++j) {
+      const int nc = s.nc[j];
+      for (int i = 0; i < 2 * nc * nc; ++i)
+        if (!std::isfinite(d->values[off + i])) fail(HGF_EINVAL, "non-finite operator entry");
+      gm[j] = mode_g(d->values + off, nc, d->basis);
+      off += 2 * (size_t)nc * nc;
+      for (int dj = -nc + 1; dj < nc; ++dj) {
+        bool nz = false;
+        for (int k = 0; k < nc; ++k) {
+          const int l = k + dj;
+          if (l >= 0 && l < nc && gm[j][k * nc + l] != 0.0) nz = true;
+        }
+        if (nz) diags[j].push_back(dj);
+      }
+      if (diags[j].empty()) return;  // zero operator
+    }
+    // enumerate sectors as the product of per-mode diagonals
+    std::vector<int> idx(n, 0);
+    while (true) {
+      std::vector<int> dv(n);
+      for (int j = 0; j < n; ++j) dv[j] = diags[j][idx[j]];
+      SectorTables t;
+      t.n = n;
+      int64_t pts = 1;
+      int u[kMaxModes], v[kMaxModes], e[kMaxModes];
+      for (int j = 0; j < n; ++j) {
+        u[j] = dv[j] < 0 ? -dv[j] : 0;
+        v[j] = dv[j] > 0 ? dv[j] : 0;
+        e[j] = s.nc[j] - std::abs(dv[j]);
+        pts *= e[j];
+      }
+      if (!want_split) {
+        std::vector<cd> grid(pts);
+        std::vector<int> m(n, 0);
+        for (int64_t f = 0; f < pts; ++f) {
+          cd val = 1.0;
+          for (int j = 0; j < n; ++j) val *= gm[j][(m[j] + u[j]) * s.nc[j] + (m[j] + v[j])];
+          grid[f] = val;
+          for (int j = n - 1; j >= 0; --j) {
+            if (++m[j] < e[j]) break;
+            m[j] = 0;
+          }
+        }
+        merged[dv] = std::move(grid);
+      } else {
+        std::vector<int> m(n, 0);
+        for (int64_t f = 0; f < pts; ++f) {
+          cd val = 1.0;
+          for (int j = 0; j < n; ++j) val *= gm[j][(m[j] + u[j]) * s.nc[j] + (m[j] + v[j])];
+          if (val != 0.0) {
+            Coeff c;
+            c.k.resize(n);
+            c.l.resize(n);
+            for (int j = 0; j < n; ++j) {
+              c.k[j] = m[j] + u[j];
+              c.l[j] = m[j] + v[j];
+            }
+            c.v = val;
+            split.push_back(std::move(c));
+          }
+          for (int j = n - 1; j >= 0; --j) {
+            if (++m[j] < e[j]) break;
+            m[j] = 0;
+          }
+        }
+      }
+      int j = n - 1;
+      while (j >= 0 && ++idx[j] == (int)diags[j].size()) idx[j--] = 0;
+      if (j < 0) break;
+    }
+    return;
+  }
+  if (d->kind != HGF_OP_SPARSE) fail(HGF_EINVAL, "unknown operator kind");
+  if (d->n_terms < 0 || (d->n_terms > 0 && (!d->values || !d->indices)))
+    fail(HGF_EINVAL, "sparse operator needs values and indices");
+  // accumulate g over (k, l)
+  std::map<std::pair<std::vector<int>, std::vector<int>>, cd> acc;
+  for (int64_t t = 0; t < d->n_terms; ++t) {
+    std::vector<int> k(n), l(n);
+    for (int j = 0; j < n; ++j) {
+      k[j] = d->indices[t * 2 * n + j];
+      l[j] = d->indices[t * 2 * n + n + j];
+      if (k[j] < 0 || k[j] >= s.nc[j] || l[j] < 0 || l[j] >= s.nc[j])
+        fail(HGF_EINVAL, "sparse operator index outside the cutoff box");
+    }
+    const cd val(d->values[2 * t], d->values[2 * t + 1]);
+    if (!std::isfinite(val.real()) || !std::isfinite(val.imag())) fail(HGF_EINVAL, "non-finite operator entry");
+    if (d->basis == HGF_BASIS_NUMBER) {
+      double sc = 1.0;
+      for (int j = 0; j < n; ++j) sc *= sqrt_factorial(k[j]) * sqrt_factorial(l[j]);
+      acc[{k, l}] += val / sc;
+    } else {
+      // Eq. (6) in several modes: f_{k,l} feeds g_{k+i, l+i} with weight prod_j 1/i_j!
+      std::vector<int> i(n, 0);
+      while (true) {
+        bool inside = true;
+        double w = 1.0;
+        std::vector<int> kk(n), ll(n);
+        for (int j = 0; j < n; ++j) {
+          kk[j] = k[j] + i[j];
+          ll[j] = l[j] + i[j];
+          if (kk[j] >= s.nc[j] || ll[j] >= s.nc[j]) inside = false;
+          w /= factorial(i[j]);
+        }
+        if (inside) acc[{kk, ll}] += val * w;
+        int j = n - 1;
+        while (j >= 0) {
+          if (k[j] + i[j] + 1 < s.nc[j] && l[j] + i[j] + 1 < s.nc[j]) {
+            ++i[j];
+            break;
+          }
+          i[j] = 0;
+          --j;
+        }
+        if (j < 0) break;
+      }
+    }
+  }
+  for (auto& kv : acc) {
+    const auto& k = kv.first.first;
+    const auto& l = kv.first.second;
+    if (kv.second == 0.0) continue;
+    if (want_split) {
+      split.push_back(Coeff{k, l, kv.second});
+    } else {
+      std::vector<int> dv(n);
+      int64_t pts = 1;
+      int e[kMaxModes], m[kMaxModes];
+      for (int j = 0; j < n; ++j) {
+        dv[j] = l[j] - k[j];
+        e[j] = s.nc[j] - std::abs(dv[j]);
+        m[j] = std::min(k[j], l[j]);
+        pts *= e[j];
+      }
+      auto it = merged.find(dv);
+      if (it == merged.end()) it = merged.emplace(dv, std::vector<cd>(pts, 0.0)).first;
+      int64_t f = 0;
+      for (int j = 0; j < n; ++j) f = f * e[j] + m[j];
+      it->second[f] += kv.second;
+    }
+  }
+}
+
+static void upload_state(Function& f, const std::vector<cd>& grid) {
+  static_assert(sizeof(cd) == sizeof(double2), "layout");
+  hip_check(hipMemcpy(f.y, grid.data(), grid.size() * sizeof(double2), hipMemcpyHostToDevice), "upload state");
+}
+
+// energy of the number state |k>
+static double energy(const System& s, const int* k) {
+  double e = 0.0;
+  for (int j = 0; j < s.n; ++j) e += s.det[j] * k[j] + 0.5 * s.kerr[j] * k[j] * (k[j] - 1);
+  for (int i = 0; i < s.n; ++i)
+    for (int j = i + 1; j < s.n; ++j) e += s.chi[i][j] * k[i] * k[j];
+  return e;
+}
+
+// Split layout (Eqs. (9), (19)-(20)): G^{(p,q)} = c_x x^p c_y y^q + R with
+//   dc_x/dt = (rho_x + C) c_x,  dc_y/dt = (rho_y - C) c_y,
+//   dR/dt   = L R + c_x c_y S,  S = L[x^p y^q] - (rho_x + rho_y) x^p y^q,
+// where rho_x + rho_y is the diagonal rate lambda at (p, q) minus the
+// dephasing cross term, rho_x collects the p-dependent and rho_y the
+// q-dependent part, and C = -(i/2)(E(p) + E(q)) minimises
+// |c_x'/c_x|^2 + |c_y'/c_y|^2 of the undamped system (Eq. (20)).
+static void setup_split(Function& f, const System& s, const Coeff& c) {
+  const int n = s.n;
+  const cd I(0.0, 1.0);
+  int p[kMaxModes], q[kMaxModes], m[kMaxModes];
+  for (int j = 0; j < n; ++j) {
+    p[j] = c.k[j];
+    q[j] = c.l[j];
+    f.p[j] = p[j];
+    f.q[j] = q[j];
+    m[j] = std::min(p[j], q[j]);
+  }
+  const double Ep = energy(s, p), Eq = energy(s, q);
+  cd rx = I * Ep, ry = -I * Eq;
+  for (int j = 0; j < n; ++j) {
+    const double down = s.g1[j] * (1 + s.nth[j]), up = s.g1[j] * s.nth[j];
+    const double pt = (p[j] + 1 < s.nc[j]) ? p[j] + 1 : 0, qt = (q[j] + 1 < s.nc[j]) ? q[j] + 1 : 0;
+    rx -= 0.5 * down * p[j] + 0.5 * up * pt + s.gphi[j] * double(p[j] * p[j]);
+    ry -= 0.5 * down * q[j] + 0.5 * up * qt + s.gphi[j] * double(q[j] * q[j]);
+  }
+  const cd C = -0.5 * I * (Ep + Eq);
+  f.ax = rx + C;
+  f.ay = ry - C;
+  f.cx = 1.0;
+  f.cy = 1.0;
+  f.g0 = c.v;
+  f.mono_index = flat_index(f.tab, m);
+  // S = L delta_{m*} - (rho_x + rho_y) delta_{m*}
+  const SectorTables& t = f.tab;
+  cd lam = t.lam0;
+  for (int j = 0; j < n; ++j) lam += t.lam[j][m[j]];
+  f.sources.clear();
+  f.sources.push_back({f.mono_index, lam - (rx + ry)});
+  for (int j = 0; j < n; ++j) {
+    int mm[kMaxModes];
+    std::memcpy(mm, m, sizeof(int) * n);
+    if (m[j] + 1 < t.ext[j]) {  // (L delta)(m*+e_j) = alpha_j
+      mm[j] = m[j] + 1;
+      f.sources.push_back({flat_index(t, mm), cd(t.alpha[j], 0.0)});
+    }
+    if (m[j] >= 1) {  // (L delta)(m*-e_j) = beta_j(m*_j - 1)
+      mm[j] = m[j] - 1;
+      const double b = t.beta[j][m[j] - 1];
+      if (b != 0.0) f.sources.push_back({flat_index(t, mm), cd(b, 0.0)});
+    }
+  }
+}
+
+static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
+  std::map<std::vector<int>, std::vector<cd>> merged;
+  std::vector<Coeff> coeffs;
+  const bool split = op->layout == HGF_SPLIT;
+  collect_coeffs(op->sys, d, merged, coeffs, split);
+  const int n = op->sys.n;
+  if (!split) {
+    for (auto& kv : merged) {
+      bool any = false;
+      for (auto& v : kv.second) {
+        if (std::abs(v) <= d->drop_tol) v = 0.0;
+        if (v != 0.0) any = true;
+        if (v != 0.0 && std::abs(v) < FLT_MIN) op->underflow++;
+      }
+      if (!any) continue;
+      op->fn.emplace_back();
+      Function& f = op->fn.back();
+      f.tab = sector_tables(op->sys, kv.first.data());
+      fill_grid_args(f, op->precision);
+      alloc_function_buffers(f, op->precision);
+      upload_state(f, kv.second);
+    }
+  } else {
+    for (const Coeff& c : coeffs) {
+      if (std::abs(c.v) <= d->drop_tol) continue;
+      if (std::abs(c.v) < FLT_MIN) op->underflow++;
+      int dv[kMaxModes];
+      for (int j = 0; j < n; ++j) dv[j] = c.l[j] - c.k[j];
+      op->fn.emplace_back();
+      Function& f = op->fn.back();
+      f.split = true;
+      f.tab = sector_tables(op->sys, dv);
+      fill_grid_args(f, op->precision);
+      alloc_function_buffers(f, op->precision);
+      std::vector<cd> zero(f.ga.points, 0.0);
+      upload_state(f, zero);
+      setup_split(f, op->sys, c);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ stepping
+
+static void reset_flag(hgf_operator_s* op, hipStream_t st) {
+  hip_check(hipMemsetAsync(op->dflag, 0, sizeof(int), st), "reset flag");
+}
+
+static void merged_step(hgf_operator_s* op, Function& f, double h, hipStream_t st) {
+  launch_horner(1, op->precision, f.ga, f.y, nullptr, f.y, f.s1, h, op->dflag, st);
+  launch_horner(2, op->precision, f.ga, f.s1, f.s1, f.y, f.s2, h, op->dflag, st);
+  launch_horner(3, op->precision, f.ga, f.s2, f.s1, f.y, f.s3, h, op->dflag, st);
+  launch_horner(4, op->precision, f.ga, f.s3, f.s1, f.y, nullptr, h, op->dflag, st);
+}
+
+static void drop_graph(hgf_operator_s* op) {
+  if (op->graph_exec) (void)hipGraphExecDestroy((hipGraphExec_t)op->graph_exec);
+  op->graph_exec = nullptr;
+  op->graph_steps = 0;
+}
+
+// One graph holds `chunk` merged steps of every function of the operator.
+static void ensure_graph(hgf_operator_s* op, double h, int chunk) {
+  if (op->graph_exec && op->graph_dt == h && op->graph_steps == chunk) return;
+  drop_graph(op);
+  if (!op->cap_stream) hip_check(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking), "stream");
+  hipGraph_t graph;
+  hip_check(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  for (int s = 0; s < chunk; ++s)
+    for (auto& f : op->fn) merged_step(op, f, h, op->cap_stream);
+  hip_check(hipStreamEndCapture(op->cap_stream, &graph), "end capture");
+  hipGraphExec_t exec;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  hip_check(e, "graph instantiate");
+  op->graph_exec = exec;
+  op->graph_steps = chunk;
+  op->graph_dt = h;
+}
+
+static void split_step(hgf_operator_s* op, Function& f, double h, hipStream_t st) {
+  // stage products c_x c_y of the scalar RK4 for (c_x, c_y), then the
+  // classical stages of R with point sources scaled by them
+  cd cx = f.cx, cy = f.cy;
+  cd kx[4], ky[4], X[4], Y[4];
+  X[0] = cx;
+  Y[0] = cy;
+  const double a[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int s = 0; s < 4; ++s) {
+    if (s > 0) {
+      X[s] = cx + a[s] * h * kx[s - 1];
+      Y[s] = cy + a[s] * h * ky[s - 1];
+    }
+    kx[s] = f.ax * X[s];
+    ky[s] = f.ay * Y[s];
+  }
+  PointSources ps{};
+  ps.count = (int)f.sources.size();
+  for (int i = 0; i < ps.count; ++i) {
+    ps.index[i] = f.sources[i].first;
+    ps.re[i] = f.sources[i].second.real();
+    ps.im[i] = f.sources[i].second.imag();
+  }
+  void* in[4] = {f.y, f.s1, f.s2, f.s1};
+  void* nx[4] = {f.s1, f.s2, f.s1, nullptr};
+  for (int s = 0; s < 4; ++s) {
+    const cd P = X[s] * Y[s];
+    ps.scale_re = P.real();
+    ps.scale_im = P.imag();
+    launch_classical(s + 1, op->precision, f.ga, in[s], f.y, f.s4, nx[s], h, ps, op->dflag, st);
+  }
+  f.cx = cx + h / 6.0 * (kx[0] + 2.0 * kx[1] + 2.0 * kx[2] + kx[3]);
+  f.cy = cy + h / 6.0 * (ky[0] + 2.0 * ky[1] + 2.0 * ky[2] + ky[3]);
+}
+
+static int read_flag(hgf_operator_s* op, hipStream_t st) {
+  int flag = 0;
+  hip_check(hipMemcpyAsync(&flag, op->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  return flag;
+}
+
+static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st) {
+  if (steps == 0) return;
+  if (op->fn.empty()) {  // the zero operator stays zero
+    op->steps_done += steps;
+    op->time_us += steps * h;
+    return;
+  }
+  check_stability(op->fn, h);
+  // keep a copy of the states for recovery after a non-finite result
+  for (auto& f : op->fn) {
+    const size_t bytes = f.ga.points * sizeof(double2);
+    if (!f.ybak) f.ybak = dmalloc(bytes);
+    hip_check(hipMemcpyAsync(f.ybak, f.y, bytes, hipMemcpyDeviceToDevice, st), "backup");
+  }
+  std::vector<cd> cx0, cy0;
+  for (auto& f : op->fn) {
+    cx0.push_back(f.cx);
+    cy0.push_back(f.cy);
+  }
+  reset_flag(op, st);
+  if (op->layout == HGF_MERGED) {
+    const int chunk = (int)std::min<int64_t>(steps, 64);
+    ensure_graph(op, h, chunk);
+    int64_t done = 0;
+    while (steps - done >= chunk) {
+      hip_check(hipGraphLaunch((hipGraphExec_t)op->graph_exec, st), "graph launch");
+      done += chunk;
+    }
+    for (; done < steps; ++done)
+      for (auto& f : op->fn) merged_step(op, f, h, st);
+  } else {
+    for (int64_t s = 0; s < steps; ++s)
+      for (auto& f : op->fn) split_step(op, f, h, st);
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+  if (read_flag(op, st)) {
+    for (size_t i = 0; i < op->fn.size(); ++i) {
+      const size_t bytes = op->fn[i].ga.points * sizeof(double2);
+      hip_check(hipMemcpyAsync(op->fn[i].y, op->fn[i].ybak, bytes, hipMemcpyDeviceToDevice, st), "restore");
+      op->fn[i].cx = cx0[i];
+      op->fn[i].cy = cy0[i];
+    }
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    op->error_state = 1;
+    fail(HGF_ENONFINITE, "non-finite value in an evolved function; state restored to the start of this call");
+  }
+  op->steps_done += steps;
+  op->time_us += steps * h;
+}
+
+// ------------------------------------------------------------------ expectation
+
+static std::vector<cd> mode_amps(const hgf_state_desc* psi, int j, int nc, size_t amp_off) {
+  std::vector<cd> c(nc, 0.0);
+  if (psi->kind == HGF_PSI_FOCK) {
+    c[psi->fock[j]] = 1.0;
+  } else if (psi->kind == HGF_PSI_COHERENT) {
+    const cd a(psi->alpha[2 * j], psi->alpha[2 * j + 1]);
+    double norm = 0.0;
+    cd p = 1.0;
+    for (int k = 0; k < nc; ++k) {
+      c[k] = p / sqrt_factorial(k);
+      norm += std::norm(c[k]);
+      p *= a;
+    }
+    norm = std::sqrt(norm);
+    for (auto& v : c) v /= norm;
+  } else {
+    for (int k = 0; k < nc; ++k) c[k] = cd(psi->amps[amp_off + 2 * k], psi->amps[amp_off + 2 * k + 1]);
+  }
+  return c;
+}
+
+static void validate_state(const System& s, const hgf_state_desc* psi) {
+  if (!psi) fail(HGF_EINVAL, "state is NULL");
+  if (psi->kind == HGF_PSI_FOCK) {
+    if (!psi->fock) fail(HGF_EINVAL, "fock occupations are NULL");
+    for (int j = 0; j < s.n; ++j)
+      if (psi->fock[j] < 0 || psi->fock[j] >= s.nc[j]) fail(HGF_EINVAL, "fock occupation outside the cutoff");
+  } else if (psi->kind == HGF_PSI_COHERENT) {
+    if (!psi->alpha) fail(HGF_EINVAL, "alpha is NULL");
+    for (int j = 0; j < 2 * s.n; ++j)
+      if (!std::isfinite(psi->alpha[j])) fail(HGF_EINVAL, "non-finite alpha");
+  } else if (psi->kind == HGF_PSI_PRODUCT) {
+    if (!psi->amps) fail(HGF_EINVAL, "amplitudes are NULL");
+  } else {
+    fail(HGF_EINVAL, "unknown state kind");
+  }
+}
+
+// per-axis weights w_j(m) = sqrt(k! l!) conj(c_k) c_l of one sector, concatenated
+static std::vector<cd> sector_weights(const System& s, const SectorTables& t, const std::vector<std::vector<cd>>& amps) {
+  std::vector<cd> w;
+  for (int j = 0; j < t.n; ++j)
+    for (int m = 0; m < t.ext[j]; ++m) {
+      const int k = m + t.u[j], l = m + t.v[j];
+      w.push_back(sqrt_factorial(k) * sqrt_factorial(l) * std::conj(amps[j][k]) * amps[j][l]);
+    }
+  (void)s;
+  return w;
+}
+
+static std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_desc* psi) {
+  std::vector<std::vector<cd>> amps(s.n);
+  size_t off = 0;
+  for (int j = 0; j < s.n; ++j) {
+    amps[j] = mode_amps(psi, j, s.nc[j], off);
+    off += 2 * (size_t)s.nc[j];
+  }
+  return amps;
+}
+
+static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStream_t st) {
+  validate_state(op->sys, psi);
+  const auto amps = all_amps(op->sys, psi);
+  const int nf = (int)op->fn.size();
+  if (nf == 0) return 0.0;
+  std::vector<int> start(nf + 1, 0);
+  std::vector<cd> coef(nf), wall;
+  std::vector<int> woff(nf);
+  cd analytic = 0.0;
+  for (int i = 0; i < nf; ++i) {
+    Function& f = op->fn[i];
+    const auto w = sector_weights(op->sys, f.tab, amps);
+    woff[i] = (int)wall.size();
+    wall.insert(wall.end(), w.begin(), w.end());
+    start[i + 1] = start[i] + expect_blocks(f.ga);
+    coef[i] = f.split ? f.g0 : cd(1.0);
+    if (f.split) {  // separable part c_x c_y x^p y^q contracted with psi0
+      cd wm = 1.0;
+      for (int j = 0; j < op->sys.n; ++j) wm *= w[f.ga.off[j] + std::min(f.p[j], f.q[j])];
+      analytic += f.g0 * f.cx * f.cy * wm;
+    }
+  }
+  DBuf dw(wall.size() * sizeof(double2)), dpart(start[nf] * sizeof(double2)), dstart((nf + 1) * sizeof(int)),
+      dcoef(nf * sizeof(double2)), dout(sizeof(double2));
+  hip_check(hipMemcpyAsync(dw.p, wall.data(), wall.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(dstart.p, start.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(dcoef.p, coef.data(), nf * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+  for (int i = 0; i < nf; ++i)
+    launch_expect_partial(op->fn[i].ga, op->fn[i].y, true, dw.as<double2>() + woff[i],
+                          dpart.as<double2>() + start[i], st);
+  launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), nf,
+                      make_double2(analytic.real(), analytic.imag()), dout.as<double2>(), st);
+  hip_check(hipGetLastError(), "kernel launch");
+  double2 r;
+  hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  return cd(r.x, r.y);
+}
+
+// ------------------------------------------------------------------ gradient
+
+static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
+                      double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
+  const int64_t M = check_steps(T, dt);
+  if (ce < 1) fail(HGF_EINVAL, "checkpoint_every must be >= 1");
+  validate_state(sys, psi);
+  hgf_operator_s op;
+  op.sys = sys;
+  op.precision = HGF_FP64;
+  op.layout = HGF_MERGED;
+  hip_check(hipGetDevice(&op.device), "hipGetDevice");
+  hgf_operator_desc d2 = *desc;
+  d2.layout = HGF_MERGED;
+  d2.precision = HGF_FP64;
+  struct OpGuard {
+    hgf_operator_s& o;
+    ~OpGuard() {
+      for (auto& f : o.fn) free_function(f);
+      if (o.dflag) (void)hipFree(o.dflag);
+    }
+  } guard{op};
+  op.dflag = (int*)dmalloc(sizeof(int));
+  build_functions(&op, &d2);
+  check_stability(op.fn, dt);
+  const auto amps = all_amps(sys, psi);
+  const int P = num_params(sys.n);
+  std::vector<cd> grad(P, 0.0);
+  cd value = 0.0;
+  reset_flag(&op, st);
+  for (auto& f : op.fn) {
+    const int64_t pts = f.ga.points;
+    const size_t gb = pts * sizeof(double2);
+    const int64_t nseg = (M + ce - 1) / ce;
+    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)std::min<int64_t>(ce, std::max<int64_t>(M, 1)) * gb),
+        mu(gb), vb2(gb), vb1(gb), xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
+    const auto w = sector_weights(sys, f.tab, amps);
+    DBuf dw(w.size() * sizeof(double2));
+    hip_check(hipMemcpyAsync(dw.p, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+    launch_fill_weights(f.ga, dw.as<double2>(), wt.as<double2>(), st);
+    // forward with checkpoints (f.y is the working state)
+    double2* ck = ckpt.as<double2>();
+    hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+    DBuf y0(gb);
+    hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
+    for (int64_t s = 0; s < M; ++s) {
+      merged_step(&op, f, dt, st);
+      if ((s + 1) % ce == 0) hip_check(hipMemcpyAsync(ck + ((s + 1) / ce) * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+    }
+    // value
+    {
+      std::vector<int> start = {0, expect_blocks(f.ga)};
+      cd one = 1.0;
+      DBuf dpart(start[1] * sizeof(double2)), dstart(2 * sizeof(int)), dcoef(sizeof(double2)), dout(sizeof(double2));
+      hip_check(hipMemcpyAsync(dstart.p, start.data(), 2 * sizeof(int), hipMemcpyHostToDevice, st), "upload");
+      hip_check(hipMemcpyAsync(dcoef.p, &one, sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+      launch_expect_partial(f.ga, f.y, true, dw.as<double2>(), dpart.as<double2>(), st);
+      launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), 1, make_double2(0, 0),
+                          dout.as<double2>(), st);
+      double2 r;
+      hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+      hip_check(hipStreamSynchronize(st), "synchronize");
+      value += cd(r.x, r.y);
+    }
+    // reverse sweep: mu_M = w
+    hip_check(hipMemcpyAsync(mu.p, wt.p, gb, hipMemcpyDeviceToDevice, st), "seed");
+    launch_fill_zero(Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
+    double2* seg = segbuf.as<double2>();
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
+      // recompute y_{s0} .. y_{s0+L-1} into the segment buffer
+      hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+      for (int64_t i = 0; i < L; ++i) {
+        hip_check(hipMemcpyAsync(seg + i * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "save");
+        if (i + 1 < L) merged_step(&op, f, dt, st);
+      }
+      for (int64_t i = L - 1; i >= 0; --i) {
+        double2* yn = seg + i * pts;
+        // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
+        launch_horner(1, HGF_FP64, f.ga, yn, nullptr, yn, f.s1, dt, op.dflag, st);
+        launch_horner(2, HGF_FP64, f.ga, f.s1, f.s1, yn, f.s2, dt, op.dflag, st);
+        launch_horner(3, HGF_FP64, f.ga, f.s2, f.s1, yn, f.s3, dt, op.dflag, st);
+        double2* Qp = Q.as<double2>();
+        launch_adjoint(1, f.ga, mu.as<double2>(), (const double2*)f.s3, nullptr, nullptr, vb2.as<double2>(), Qp, dt, st);
+        launch_adjoint(2, f.ga, vb2.as<double2>(), (const double2*)f.s2, nullptr, nullptr, vb1.as<double2>(), Qp, dt, st);
+        launch_adjoint(3, f.ga, vb1.as<double2>(), (const double2*)f.s1, mu.as<double2>(), vb2.as<double2>(),
+                       xb1.as<double2>(), Qp, dt, st);
+        launch_adjoint(4, f.ga, xb1.as<double2>(), yn, mu.as<double2>(), nullptr, mu.as<double2>(), Qp, dt, st);
+      }
+    }
+    // leave the function at its initial state
+    hip_check(hipMemcpyAsync(f.y, y0.p, gb, hipMemcpyDeviceToDevice, st), "restore");
+    // marginals of Q -> parameter derivatives
+    const int nb = marginal_bins(f.ga);
+    DBuf dbins(nb * sizeof(double2));
+    launch_marginals(f.ga, Q.as<double2>(), dbins.as<double2>(), st);
+    hip_check(hipGetLastError(), "kernel launch");
+    std::vector<cd> bins(nb);
+    hip_check(hipMemcpyAsync(bins.data(), dbins.p, nb * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    int tot_e = 0;
+    for (int j = 0; j < sys.n; ++j) tot_e += f.ga.ext[j];
+    cd S0 = 0.0;
+    for (int v = 0; v < f.ga.ext[0]; ++v) S0 += bins[v];
+    for (int p = 0; p < P; ++p) {
+      const System u = unit_system(sys, p);
+      const SectorTables tp = sector_tables(u, f.tab.d);
+      cd g = tp.lam0 * S0;
+      for (int j = 0; j < sys.n; ++j) {
+        g += tp.alpha[j] * bins[tot_e + j];
+        for (int v = 0; v < f.ga.ext[j]; ++v) {
+          g += tp.lam[j][v] * bins[f.ga.off[j] + v];
+          g += tp.beta[j][v] * bins[tot_e + sys.n + f.ga.off[j] + v];
+        }
+      }
+      grad[p] += g;
+    }
+  }
+  if (read_flag(&op, st)) fail(HGF_ENONFINITE, "non-finite value during the gradient sweep");
+  value_out[0] = value.real();
+  value_out[1] = value.imag();
+  for (int p = 0; p < P; ++p) {
+    grad_out[2 * p] = grad[p].real();
+    grad_out[2 * p + 1] = grad[p].imag();
+  }
+}
+
+static System system_from_desc(const hgf_system_desc* d) {
+  if (!d) fail(HGF_EINVAL, "system description is NULL");
+  const int n = d->n_modes;
+  if (n < 1 || n > kMaxModes) fail(HGF_EINVAL, "n_modes must be in 1..16");
+  if (!d->cutoff || !d->detuning || !d->kerr || !d->cross_kerr || !d->gamma1 || !d->gamma_phi || !d->n_th)
+    fail(HGF_EINVAL, "system description has a NULL array");
+  System s;
+  s.n = n;
+  for (int j = 0; j < n; ++j) {
+    if (d->cutoff[j] < 1 || d->cutoff[j] > kMaxCutoff) fail(HGF_EINVAL, "cutoff must be in 1..32");
+    s.nc[j] = d->cutoff[j];
+    s.det[j] = d->detuning[j];
+    s.kerr[j] = d->kerr[j];
+    s.g1[j] = d->gamma1[j];
+    s.gphi[j] = d->gamma_phi[j];
+    s.nth[j] = d->n_th[j];
+    for (double v : {s.det[j], s.kerr[j], s.g1[j], s.gphi[j], s.nth[j]})
+      if (!std::isfinite(v)) fail(HGF_EINVAL, "non-finite system parameter");
+    if (s.g1[j] < 0 || s.gphi[j] < 0 || s.nth[j] < 0) fail(HGF_EINVAL, "rates and n_th must be >= 0");
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double a = d->cross_kerr[i * n + j], b = d->cross_kerr[j * n + i];
+      if (!std::isfinite(a)) fail(HGF_EINVAL, "non-finite cross_kerr");
+      if (i != j && a != b) fail(HGF_EINVAL, "cross_kerr must be symmetric");
+      s.chi[i][j] = (i == j) ? 0.0 : a;
+    }
+  return s;
+}
+
+}  // namespace hgf
+
+using namespace hgf;
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* hgf_last_error(void) { return g_last_error.c_str(); }
+
+const char* hgf_version(void) { return "hgf 0.1 (gfx950)"; }
+
+hgf_status hgf_define_system(const hgf_system_desc* desc, hgf_system* out) {
+  return guarded([&] {
+    if (!out) fail(HGF_EINVAL, "out is NULL");
+    System s = system_from_desc(desc);
+    auto* h = new hgf_system_s;
+    h->sys = s;
+    *out = h;
+  });
+}
+
+void hgf_destroy_system(hgf_system sys) { delete sys; }
+
+int32_t hgf_num_params(hgf_system sys) { return sys ? num_params(sys->sys.n) : -1; }
+
+hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_operator* out) {
+  return guarded([&] {
+    if (!sys || !desc || !out) fail(HGF_EINVAL, "NULL argument");
+    if (desc->precision != HGF_FP64 && desc->precision != HGF_MIXED) fail(HGF_EINVAL, "unknown precision");
+    if (desc->layout != HGF_MERGED && desc->layout != HGF_SPLIT) fail(HGF_EINVAL, "unknown layout");
+    if (desc->basis != HGF_BASIS_NUMBER && desc->basis != HGF_BASIS_NORMAL) fail(HGF_EINVAL, "unknown basis");
+    if (!(desc->drop_tol >= 0)) fail(HGF_EINVAL, "drop_tol must be >= 0");
+    auto* op = new hgf_operator_s;
+    try {
+      op->sys = sys->sys;
+      op->precision = desc->precision;
+      op->layout = desc->layout;
+      hip_check(hipGetDevice(&op->device), "hipGetDevice");
+      op->dflag = (int*)dmalloc(sizeof(int));
+      build_functions(op, desc);
+      hip_check(hipDeviceSynchronize(), "synchronize");
+    } catch (...) {
+      hgf_destroy_operator(op);
+      throw;
+    }
+    *out = op;
+  });
+}
+
+void hgf_destroy_operator(hgf_operator op) {
+  if (!op) return;
+  (void)hipSetDevice(op->device);
+  drop_graph(op);
+  for (auto& f : op->fn) free_function(f);
+  if (op->dflag) (void)hipFree(op->dflag);
+  if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
+  delete op;
+}
+
+hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, void* hip_stream) {
+  return guarded([&] {
+    if (!op) fail(HGF_EINVAL, "operator is NULL");
+    if (op->error_state) fail(HGF_ESTATE, "operator is in an error state after a non-finite result");
+    const int64_t m = check_steps(t_total_us, dt_us);
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    evolve_impl(op, m, dt_us, (hipStream_t)hip_stream);
+  });
+}
+
+hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_us, const double* dt_us,
+                            void* hip_stream) {
+  return guarded([&] {
+    if (n < 0 || (n > 0 && (!ops || !t_total_us || !dt_us))) fail(HGF_EINVAL, "bad batch arguments");
+    std::vector<int64_t> steps(n);
+    for (int i = 0; i < n; ++i) {
+      if (!ops[i]) fail(HGF_EINVAL, "NULL operator in batch");
+      if (ops[i]->error_state) fail(HGF_ESTATE, "operator in batch is in an error state");
+      if (ops[i]->layout != HGF_MERGED) fail(HGF_EINVAL, "batched evolve needs the merged layout");
+      for (int k = 0; k < i; ++k)
+        if (ops[k] == ops[i]) fail(HGF_EINVAL, "batch members must be distinct");
+      steps[i] = check_steps(t_total_us[i], dt_us[i]);
+      check_stability(ops[i]->fn, dt_us[i]);
+    }
+    for (int i = 0; i < n; ++i) evolve_impl(ops[i], steps[i], dt_us[i], (hipStream_t)hip_stream);
+  });
+}
+
+hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2], void* hip_stream) {
+  return guarded([&] {
+    if (!op || !out_re_im) fail(HGF_EINVAL, "NULL argument");
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    const cd r = expectation_impl(op, psi, (hipStream_t)hip_stream);
+    out_re_im[0] = r.real();
+    out_re_im[1] = r.imag();
+  });
+}
+
+hgf_status hgf_grad(hgf_system sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double t_total_us,
+                    double dt_us, int32_t checkpoint_every, double value_out[2], double* grad_out,
+                    void* hip_stream) {
+  return guarded([&] {
+    if (!sys || !desc || !psi || !value_out || !grad_out) fail(HGF_EINVAL, "NULL argument");
+    if (desc->basis != HGF_BASIS_NUMBER && desc->basis != HGF_BASIS_NORMAL) fail(HGF_EINVAL, "unknown basis");
+    grad_impl(sys->sys, desc, psi, t_total_us, dt_us, checkpoint_every, value_out, grad_out,
+              (hipStream_t)hip_stream);
+  });
+}
+
+hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
+  return guarded([&] {
+    if (!op || !info) fail(HGF_EINVAL, "NULL argument");
+    info->n_functions = (int32_t)op->fn.size();
+    info->precision = op->precision;
+    info->layout = op->layout;
+    info->n_modes = op->sys.n;
+    int64_t pts = 0;
+    for (auto& f : op->fn) pts += f.ga.points;
+    info->total_points = pts;
+    info->steps_done = op->steps_done;
+    info->time_us = op->time_us;
+    info->fp32_underflow = op->underflow;
+    info->error_state = op->error_state;
+  });
+}
+
+hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int32_t* extents, double* grid,
+                            int64_t n_points, double* split_out, void* hip_stream) {
+  return guarded([&] {
+    if (!op) fail(HGF_EINVAL, "operator is NULL");
+    if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
+    Function& f = op->fn[idx];
+    const int n = op->sys.n;
+    if (sector_d)
+      for (int j = 0; j < n; ++j) sector_d[j] = f.tab.d[j];
+    if (extents)
+      for (int j = 0; j < n; ++j) extents[j] = f.tab.ext[j];
+    if (grid) {
+      if (n_points < f.ga.points) fail(HGF_EINVAL, "grid buffer too small");
+      hip_check(hipSetDevice(op->device), "hipSetDevice");
+      hip_check(hipMemcpyAsync(grid, f.y, f.ga.points * sizeof(double2), hipMemcpyDeviceToHost,
+                               (hipStream_t)hip_stream),
+                "download");
+      hip_check(hipStreamSynchronize((hipStream_t)hip_stream), "synchronize");
+    }
+    if (split_out) {
+      std::vector<double> o(4 * n + 6, 0.0);
+      for (int j = 0; j < n; ++j) {
+        o[j] = f.split ? f.p[j] : 0;
+        o[n + j] = f.split ? f.q[j] : 0;
+      }
+      const cd g0 = f.split ? f.g0 : cd(1.0), cx = f.split ? f.cx : cd(0.0), cy = f.split ? f.cy : cd(0.0);
+      o[2 * n] = g0.real();
+      o[2 * n + 1] = g0.imag();
+      o[2 * n + 2] = cx.real();
+      o[2 * n + 3] = cx.imag();
+      o[2 * n + 4] = cy.real();
+      o[2 * n + 5] = cy.imag();
+      std::memcpy(split_out, o.data(), o.size() * sizeof(double));
+    }
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Internal structures shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hgf.h"
+
+namespace hgf {
+
+constexpr int kMaxModes = HGF_MAX_MODES;
+constexpr int kMaxCutoff = HGF_MAX_CUTOFF;
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  hgf_status code;
+  std::string msg;
+};
+void set_error(hgf_status code, const std::string& msg);
+[[noreturn]] void fail(hgf_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+// ------------------------------------------------------------------ system
+struct System {
+  int n = 0;
+  int nc[kMaxModes] = {};
+  double det[kMaxModes] = {}, kerr[kMaxModes] = {}, g1[kMaxModes] = {}, gphi[kMaxModes] = {},
+         nth[kMaxModes] = {};
+  double chi[kMaxModes][kMaxModes] = {};
+};
+
+// Coefficients of the generator restricted to one occupation-difference
+// sector d (Eq. (17) with the dissipators of Eq. (3); derivation in the
+// sector form): for grid point m,
+//   (L g)(m) = [lam0 + sum_j lam_j(m_j)] g(m)
+//            + sum_j [ alpha_j g(m - e_j) [m_j >= 1] + beta_j(m_j) g(m + e_j) [m_j + 1 < ext_j] ]
+struct SectorTables {
+  int n = 0;
+  int d[kMaxModes] = {};
+  int ext[kMaxModes] = {};
+  int u[kMaxModes] = {}, v[kMaxModes] = {};  // k = m + u, l = m + v
+  cd lam0;
+  std::vector<cd> lam[kMaxModes];      // [ext_j]
+  std::vector<double> beta[kMaxModes]; // [ext_j]; zero at the top of the axis
+  double alpha[kMaxModes] = {};
+  int64_t points() const {
+    int64_t p = 1;
+    for (int j = 0; j < n; ++j) p *= ext[j];
+    return p;
+  }
+};
+SectorTables sector_tables(const System& s, const int* d);
+System unit_system(const System& s, int p);  // only parameter p set to 1 (n_th kept)
+int num_params(int n);
+
+// spectral-radius bound used for the RK4 stability check
+double generator_bound(const SectorTables& t);
+
+// ------------------------------------------------------------------ device layout
+// Device coefficient block of one grid, in FP64 and FP32 copies.
+struct DevTables {
+  // offsets into the concatenated per-axis arrays
+  int off[kMaxModes];
+};
+
+// Everything a stage kernel needs to know about one grid; passed by value.
+struct GridArgs {
+  int n;                    // number of axes
+  int nfast;                // trailing axes held inside one tile
+  int ext[kMaxModes];
+  int64_t stride[kMaxModes];
+  int64_t points;
+  int64_t tile_points;      // product of the fast extents
+  int64_t ntiles;
+  int off[kMaxModes];       // start of axis j in the concatenated tables
+  double lam0_re, lam0_im;
+  double alpha[kMaxModes];
+  const double2* lam;       // concatenated lam_j(m)
+  const double* beta;       // concatenated beta_j(m)
+  const float2* lam_f;
+  const float* beta_f;
+};
+
+// ------------------------------------------------------------------ functions
+struct Function {
+  SectorTables tab;
+  GridArgs ga{};
+  // device buffers (owned)
+  void* y = nullptr;   // complex128 state
+  void* ybak = nullptr;  // complex128 copy of y taken at the start of each evolve
+  void* s1 = nullptr;  // stage buffers: complex128 (FP64) or complex64 (MIXED)
+  void* s2 = nullptr;
+  void* s3 = nullptr;
+  void* s4 = nullptr;  // classical (split) form only: RK accumulator, complex128
+  void* dtab = nullptr;  // device tables
+  // split mode
+  bool split = false;
+  int p[kMaxModes] = {}, q[kMaxModes] = {};
+  int64_t mono_index = 0;  // flat index of (p, q) in the grid
+  cd g0 = 0.0, cx = 1.0, cy = 1.0;
+  cd ax = 0.0, ay = 0.0;   // dc_x/dt = ax c_x, dc_y/dt = ay c_y
+  std::vector<std::pair<int64_t, cd>> sources;  // R' = L R + c_x c_y S
+};
+
+}  // namespace hgf
+
+struct hgf_system_s {
+  hgf::System sys;
+};
+
+struct hgf_operator_s {
+  hgf::System sys;
+  int precision = HGF_FP64;
+  int layout = HGF_MERGED;
+  int device = 0;
+  std::vector<hgf::Function> fn;
+  int64_t steps_done = 0;
+  double time_us = 0.0;
+  int64_t underflow = 0;
+  int error_state = 0;
+  int* dflag = nullptr;  // device non-finite flag
+  // cached graph of merged-mode steps
+  void* graph_exec = nullptr;
+  int graph_steps = 0;
+  double graph_dt = 0.0;
+  hipStream_t cap_stream = nullptr;
+};

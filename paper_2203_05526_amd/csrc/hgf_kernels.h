@@ -1,0 +1,49 @@
+// Launch wrappers for the HIP kernels (host-callable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hgf_internal.h"
+
+namespace hgf {
+
+// Digits of a grid-stride loop's stride in the grid's mixed radix.
+struct StrideDigits {
+  int64_t total;
+  int digit[kMaxModes];
+};
+
+struct LaunchShape {
+  int blocks;
+  int threads;
+};
+
+// Point sources of the split layout: K(m) += scale * value at up to
+// kMaxSources grid points.
+constexpr int kMaxSources = 2 * kMaxModes + 1;
+struct PointSources {
+  int count;
+  int64_t index[kMaxSources];
+  double re[kMaxSources], im[kMaxSources];
+  double scale_re, scale_im;
+};
+
+LaunchShape shape_for(const GridArgs& g, int max_blocks);
+
+void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+                   void* out, double h, int* flag, hipStream_t st);
+void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
+                      double h, const PointSources& src, int* flag, hipStream_t st);
+int expect_blocks(const GridArgs& g);
+void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, const double2* wtab,
+                           double2* partial, hipStream_t st);
+void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
+                         double2 analytic, double2* out, hipStream_t st);
+void launch_adjoint(int stage, const GridArgs& g, const double2* in, const double2* fwd, const double2* mu,
+                    const double2* vb2, double2* out, double2* Q, double h, hipStream_t st);
+int marginal_bins(const GridArgs& g);
+void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st);
+void launch_fill_zero(double2* p, int64_t n, hipStream_t st);
+void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st);
+
+}  // namespace hgf

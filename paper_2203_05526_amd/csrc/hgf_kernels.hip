@@ -1,0 +1,573 @@
+// HIP kernels for gfx950: the sector stencil of the transformed
+// generating-function equations (Eqs. (17)-(19) with the dissipators of
+// Eq. (3)), fused with the RK4 stage updates, the expectation reduction, and
+// the discrete-adjoint sweep used for gradients.
+//
+// Grid convention: a function of one occupation-difference sector is a
+// row-major N-dimensional box over m (last axis fastest).  The generator is
+//   (L g)(m) = lam(m) g(m) + sum_j [alpha_j g(m-e_j) [m_j>=1] + beta_j(m_j) g(m+e_j) [m_j+1<ext_j]]
+// with lam(m) = lam0 + sum_j lam_j(m_j).
+#include <hip/hip_runtime.h>
+
+#include "hgf_internal.h"
+#include "hgf_kernels.h"
+
+namespace hgf {
+
+// ------------------------------------------------------------ small helpers
+
+template <typename R>
+struct C2;
+template <>
+struct C2<double> {
+  using T = double2;
+};
+template <>
+struct C2<float> {
+  using T = float2;
+};
+
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2(a.x, a.y); }
+template <typename T>
+__device__ __forceinline__ T from_d2(double2 a);
+template <>
+__device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <>
+__device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+  return make_float2((float)a.x, (float)a.y);
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ typename C2<R>::T load_as(const T* p, int64_t i) {
+  T v = p[i];
+  typename C2<R>::T o;
+  o.x = (R)v.x;
+  o.y = (R)v.y;
+  return o;
+}
+
+template <typename R>
+__device__ __forceinline__ const typename C2<R>::T* lam_table(const GridArgs& g);
+template <>
+__device__ __forceinline__ const double2* lam_table<double>(const GridArgs& g) { return g.lam; }
+template <>
+__device__ __forceinline__ const float2* lam_table<float>(const GridArgs& g) { return g.lam_f; }
+template <typename R>
+__device__ __forceinline__ const R* beta_table(const GridArgs& g);
+template <>
+__device__ __forceinline__ const double* beta_table<double>(const GridArgs& g) { return g.beta; }
+template <>
+__device__ __forceinline__ const float* beta_table<float>(const GridArgs& g) { return g.beta_f; }
+
+// Mixed-radix bookkeeping for a grid-stride loop: each thread keeps the
+// coordinates of its current point and adds the digits of the loop stride.
+struct Walker {
+  int c[kMaxModes];
+  int64_t i;
+};
+
+__device__ __forceinline__ void walker_init(Walker& w, const GridArgs& g, int64_t i0) {
+  w.i = i0;
+  int64_t rem = i0;
+#pragma unroll
+  for (int j = kMaxModes - 1; j >= 0; --j) {
+    if (j < g.n) {
+      const int e = g.ext[j];
+      w.c[j] = (int)(rem % e);
+      rem /= e;
+    } else {
+      w.c[j] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ void walker_step(Walker& w, const GridArgs& g, const StrideDigits& sd) {
+  w.i += sd.total;
+  int carry = 0;
+#pragma unroll
+  for (int j = kMaxModes - 1; j >= 0; --j) {
+    if (j < g.n) {
+      int c = w.c[j] + sd.digit[j] + carry;
+      carry = c >= g.ext[j];
+      w.c[j] = carry ? c - g.ext[j] : c;
+    }
+  }
+}
+
+// (L in)(m) in precision R
+template <typename R, typename TIN>
+__device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TIN* __restrict__ in,
+                                                     const Walker& w) {
+  using CT = typename C2<R>::T;
+  const CT* lam = lam_table<R>(g);
+  const R* beta = beta_table<R>(g);
+  R lr = (R)g.lam0_re, li = (R)g.lam0_im;
+  CT acc;
+  acc.x = 0;
+  acc.y = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxModes; ++j) {
+    if (j < g.n) {
+      const int m = w.c[j];
+      const CT lj = lam[g.off[j] + m];
+      lr += lj.x;
+      li += lj.y;
+      if (m >= 1) {
+        const CT nb = load_as<R>(in, w.i - g.stride[j]);
+        const R a = (R)g.alpha[j];
+        acc.x += a * nb.x;
+        acc.y += a * nb.y;
+      }
+      if (m + 1 < g.ext[j]) {
+        const CT nb = load_as<R>(in, w.i + g.stride[j]);
+        const R b = beta[g.off[j] + m];
+        acc.x += b * nb.x;
+        acc.y += b * nb.y;
+      }
+    }
+  }
+  const CT c = load_as<R>(in, w.i);
+  acc.x += lr * c.x - li * c.y;
+  acc.y += lr * c.y + li * c.x;
+  return acc;
+}
+
+// (L^T in)(m): down and up neighbours swap roles, no conjugation.
+template <typename TIN>
+__device__ __forceinline__ double2 apply_LT(const GridArgs& g, const TIN* __restrict__ in,
+                                            const Walker& w) {
+  double lr = g.lam0_re, li = g.lam0_im;
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < kMaxModes; ++j) {
+    if (j < g.n) {
+      const int m = w.c[j];
+      const double2 lj = g.lam[g.off[j] + m];
+      lr += lj.x;
+      li += lj.y;
+      if (m + 1 < g.ext[j]) {  // L[m+e, m] = alpha
+        const double2 nb = to_d2(in[w.i + g.stride[j]]);
+        acc.x += g.alpha[j] * nb.x;
+        acc.y += g.alpha[j] * nb.y;
+      }
+      if (m >= 1) {  // L[m-e, m] = beta(m-1)
+        const double2 nb = to_d2(in[w.i - g.stride[j]]);
+        const double b = g.beta[g.off[j] + m - 1];
+        acc.x += b * nb.x;
+        acc.y += b * nb.y;
+      }
+    }
+  }
+  const double2 c = to_d2(in[w.i]);
+  acc.x += lr * c.x - li * c.y;
+  acc.y += lr * c.y + li * c.x;
+  return acc;
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 cscale(double s, double2 a) {
+  return make_double2(s * a.x, s * a.y);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ------------------------------------------------------------ RK4, merged form
+//
+// For a linear, time-independent generator the classical RK4 step is
+// y' = R(hL) y with R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24.  It is evaluated
+// here as y' = y + P(hL) X1 with X1 = hLy and P(z) = 1 + z/2 + z^2/6 + z^3/24
+// in nested form:
+//   stage 1: X1 = h L y
+//   stage 2: V1 = X1 + (h/4) L X1
+//   stage 3: V2 = X1 + (h/3) L V1
+//   stage 4: y  = y + X1 + (h/2) L V2
+// The stage grids hold only increments (small next to y), so storing them in
+// complex64 keeps the state's FP64 accuracy to first order in hL.
+
+template <int STAGE, typename R, typename TIN, typename TS>
+__global__ __launch_bounds__(256) void k_horner(GridArgs g, StrideDigits sd, const TIN* __restrict__ in,
+                                                const TS* __restrict__ x1, double2* __restrict__ y,
+                                                TS* __restrict__ out, double h, int* __restrict__ flag) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  int bad = 0;
+  while (w.i < g.points) {
+    const auto lv = apply_L<R>(g, in, w);
+    if (STAGE == 1) {
+      out[w.i] = from_d2<TS>(make_double2(h * (double)lv.x, h * (double)lv.y));
+    } else if (STAGE == 2 || STAGE == 3) {
+      const double c = (STAGE == 2) ? 0.25 * h : h / 3.0;
+      const double2 base = to_d2(x1[w.i]);
+      out[w.i] = from_d2<TS>(make_double2(base.x + c * (double)lv.x, base.y + c * (double)lv.y));
+    } else {
+      const double c = 0.5 * h;
+      const double2 base = to_d2(x1[w.i]);
+      double2 yv = y[w.i];
+      yv.x += base.x + c * (double)lv.x;
+      yv.y += base.y + c * (double)lv.y;
+      bad |= !(isfinite(yv.x) && isfinite(yv.y));
+      y[w.i] = yv;
+    }
+    walker_step(w, g, sd);
+  }
+  if (STAGE == 4 && bad) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------ RK4, classical form
+// (split layout: the residual R gets point sources c_x c_y S at stage times)
+//   stage s input Y_s (Y_1 = y), K_s = L Y_s + P_s S
+//   s=1: acc = y + h/6 K, next = y + h/2 K
+//   s=2: acc += h/3 K,    next = y + h/2 K
+//   s=3: acc += h/3 K,    next = y + h K
+//   s=4: y = acc + h/6 K
+
+template <int STAGE, typename R, typename TIN, typename TS>
+__global__ __launch_bounds__(256) void k_classical(GridArgs g, StrideDigits sd, const TIN* __restrict__ in,
+                                                   double2* __restrict__ y, double2* __restrict__ acc,
+                                                   TS* __restrict__ next, double h, PointSources src,
+                                                   int* __restrict__ flag) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  int bad = 0;
+  while (w.i < g.points) {
+    const auto lv = apply_L<R>(g, in, w);
+    double2 k = make_double2((double)lv.x, (double)lv.y);
+    for (int s = 0; s < src.count; ++s) {
+      if (src.index[s] == w.i) {
+        const double2 sv = make_double2(src.re[s], src.im[s]);
+        k = cadd(k, cmul(make_double2(src.scale_re, src.scale_im), sv));
+      }
+    }
+    if (STAGE == 1) {
+      const double2 yv = y[w.i];
+      acc[w.i] = cadd(yv, cscale(h / 6.0, k));
+      next[w.i] = from_d2<TS>(cadd(yv, cscale(0.5 * h, k)));
+    } else if (STAGE == 2 || STAGE == 3) {
+      const double2 yv = y[w.i];
+      acc[w.i] = cadd(acc[w.i], cscale(h / 3.0, k));
+      next[w.i] = from_d2<TS>(cadd(yv, cscale(STAGE == 2 ? 0.5 * h : h, k)));
+    } else {
+      const double2 yv = cadd(acc[w.i], cscale(h / 6.0, k));
+      bad |= !(isfinite(yv.x) && isfinite(yv.y));
+      y[w.i] = yv;
+    }
+    walker_step(w, g, sd);
+  }
+  if (STAGE == 4 && bad) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------ expectation
+// partial[b] = sum over this block's points of w(m) g(m), w(m) = prod_j wtab_j(m_j)
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double2 block_sum(double2 v) {
+  __shared__ double sx[kRedThreads / 64], sy[kRedThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_down(v.x, off, 64);
+    v.y += __shfl_down(v.y, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sx[wid] = v.x;
+    sy[wid] = v.y;
+  }
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      r.x += sx[k];
+      r.y += sy[k];
+    }
+  }
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_expect_partial(GridArgs g, StrideDigits sd,
+                                                                const T* __restrict__ grid,
+                                                                const double2* __restrict__ wtab,
+                                                                double2* __restrict__ partial) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double2 s = make_double2(0.0, 0.0);
+  if (i0 < g.points) {
+    Walker w;
+    walker_init(w, g, i0);
+    while (w.i < g.points) {
+      double2 wt = make_double2(1.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < kMaxModes; ++j)
+        if (j < g.n) wt = cmul(wt, wtab[g.off[j] + w.c[j]]);
+      s = cadd(s, cmul(wt, to_d2(grid[w.i])));
+      walker_step(w, g, sd);
+    }
+  }
+  const double2 r = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// out = analytic + sum_f coef_f * sum_{b in f} partial[b], in a fixed order
+__global__ void k_expect_final(const double2* __restrict__ partial, const int* __restrict__ start,
+                               const double2* __restrict__ coef, int nfun, double2 analytic,
+                               double2* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2 tot = analytic;
+  for (int f = 0; f < nfun; ++f) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int b = start[f]; b < start[f + 1]; ++b) s = cadd(s, partial[b]);
+    tot = cadd(tot, cmul(coef[f], s));
+  }
+  *out = tot;
+}
+
+// ------------------------------------------------------------ adjoint sweep
+// One reverse RK4 step in the merged form (see k_horner):
+//   B1: Vb2 = (h/2) L^T mu                 Q += (h/2) mu  (x) V2
+//   B2: Vb1 = (h/3) L^T Vb2                Q += (h/3) Vb2 (x) V1
+//   B3: Xb1 = mu + Vb2 + Vb1 + (h/4) L^T Vb1   Q += (h/4) Vb1 (x) X1
+//   B4: mu  = mu + h L^T Xb1               Q += h Xb1 (x) y
+// where "Q += a (x) b" accumulates, per point m, the products that the
+// parameter derivative of the generator needs:
+//   Q0(m) += a(m) b(m),  Qd_j(m) += a(m) b(m-e_j),  Qu_j(m) += a(m) b(m+e_j).
+// Q is laid out as (1 + 2N) consecutive planes of `points` complex values.
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adjoint(GridArgs g, StrideDigits sd, const double2* __restrict__ in,
+                                                 const double2* __restrict__ fwd, const double2* mu,
+                                                 const double2* __restrict__ vb2, double2* out,
+                                                 double2* __restrict__ Q, double h) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  const double c = STAGE == 1 ? 0.5 * h : STAGE == 2 ? h / 3.0 : STAGE == 3 ? 0.25 * h : h;
+  Walker w;
+  walker_init(w, g, i0);
+  while (w.i < g.points) {
+    const double2 lt = apply_LT(g, in, w);
+    const double2 a = cscale(c, in[w.i]);
+    double2 o = cscale(c, lt);
+    if (STAGE == 3) o = cadd(o, cadd(mu[w.i], cadd(vb2[w.i], in[w.i])));
+    if (STAGE == 4) o = cadd(o, mu[w.i]);
+    // parameter products
+    const int64_t P = g.points;
+    Q[w.i] = cadd(Q[w.i], cmul(a, fwd[w.i]));
+#pragma unroll
+    for (int j = 0; j < kMaxModes; ++j) {
+      if (j < g.n) {
+        const int m = w.c[j];
+        if (m >= 1) {
+          double2& q = Q[(1 + j) * P + w.i];
+          q = cadd(q, cmul(a, fwd[w.i - g.stride[j]]));
+        }
+        if (m + 1 < g.ext[j]) {
+          double2& q = Q[(1 + g.n + j) * P + w.i];
+          q = cadd(q, cmul(a, fwd[w.i + g.stride[j]]));
+        }
+      }
+    }
+    out[w.i] = o;
+    walker_step(w, g, sd);
+  }
+}
+
+// Marginals of Q: bins[0 .. sum e) hold sum over m with m_j = v of Q0,
+// bins[sum e .. sum e + N) hold sum of Qd_j, bins[sum e + N ..) sum over
+// m_j = v of Qu_j.  One thread per bin walks its slice in a fixed order.
+__global__ void k_marginals(GridArgs g, const double2* __restrict__ Q, double2* __restrict__ bins) {
+  int tot_e = 0;
+  for (int j = 0; j < g.n; ++j) tot_e += g.ext[j];
+  const int nb = 2 * tot_e + g.n;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int kind, axis = 0, val = 0;
+  if (b < tot_e) {
+    kind = 0;
+    int r = b;
+    while (r >= g.ext[axis]) r -= g.ext[axis++];
+    val = r;
+  } else if (b < tot_e + g.n) {
+    kind = 1;
+    axis = b - tot_e;
+  } else {
+    kind = 2;
+    int r = b - tot_e - g.n;
+    while (r >= g.ext[axis]) r -= g.ext[axis++];
+    val = r;
+  }
+  const double2* plane =
+      Q + (kind == 0 ? 0 : kind == 1 ? (int64_t)(1 + axis) * g.points : (int64_t)(1 + g.n + axis) * g.points);
+  double2 s = make_double2(0.0, 0.0);
+  if (kind == 1) {
+    for (int64_t i = 0; i < g.points; ++i) s = cadd(s, plane[i]);
+  } else {
+    // iterate over all points whose coordinate `axis` equals val
+    const int64_t st = g.stride[axis];
+    const int64_t outer = g.points / (st * g.ext[axis]);
+    for (int64_t o = 0; o < outer; ++o)
+      for (int64_t inner = 0; inner < st; ++inner) s = cadd(s, plane[(o * g.ext[axis] + val) * st + inner]);
+  }
+  bins[b] = s;
+}
+
+// ------------------------------------------------------------ misc
+__global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_fill_weights(GridArgs g, StrideDigits sd, const double2* __restrict__ wtab,
+                               double2* __restrict__ out) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  while (w.i < g.points) {
+    double2 wt = make_double2(1.0, 0.0);
+    for (int j = 0; j < g.n; ++j) wt = cmul(wt, wtab[g.off[j] + w.c[j]]);
+    out[w.i] = wt;
+    walker_step(w, g, sd);
+  }
+}
+
+// ============================================================ launchers
+
+static StrideDigits digits_for(const GridArgs& g, int64_t total) {
+  StrideDigits sd{};
+  sd.total = total;
+  int64_t rem = total;
+  for (int j = g.n - 1; j >= 0; --j) {
+    sd.digit[j] = (int)(rem % g.ext[j]);
+    rem /= g.ext[j];
+  }
+  return sd;
+}
+
+LaunchShape shape_for(const GridArgs& g, int max_blocks) {
+  LaunchShape ls;
+  ls.threads = 256;
+  int64_t need = (g.points + ls.threads - 1) / ls.threads;
+  ls.blocks = (int)std::min<int64_t>(need, max_blocks);
+  if (ls.blocks < 1) ls.blocks = 1;
+  return ls;
+}
+
+static const int kStageBlocks = 4096;
+
+void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+                   void* out, double h, int* flag, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  dim3 gr(ls.blocks), bl(ls.threads);
+  double2* yd = (double2*)y;
+  if (precision == HGF_FP64) {
+    const double2* i2 = (const double2*)in;
+    const double2* x = (const double2*)x1;
+    double2* o = (double2*)out;
+    switch (stage) {
+      case 1: hipLaunchKernelGGL((k_horner<1, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
+      case 2: hipLaunchKernelGGL((k_horner<2, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
+      case 3: hipLaunchKernelGGL((k_horner<3, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
+      default: hipLaunchKernelGGL((k_horner<4, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
+    }
+  } else {
+    const float2* x = (const float2*)x1;
+    float2* o = (float2*)out;
+    switch (stage) {
+      case 1: hipLaunchKernelGGL((k_horner<1, double, double2, float2>), gr, bl, 0, st, g, sd, (const double2*)in, x, yd, o, h, flag); break;
+      case 2: hipLaunchKernelGGL((k_horner<2, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
+      case 3: hipLaunchKernelGGL((k_horner<3, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
+      default: hipLaunchKernelGGL((k_horner<4, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
+    }
+  }
+}
+
+void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
+                      double h, const PointSources& src, int* flag, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  dim3 gr(ls.blocks), bl(ls.threads);
+  double2* yd = (double2*)y;
+  double2* ad = (double2*)acc;
+  if (precision == HGF_FP64) {
+    const double2* i2 = (const double2*)in;
+    double2* nx = (double2*)next;
+    switch (stage) {
+      case 1: hipLaunchKernelGGL((k_classical<1, double, double2, double2>), gr, bl, 0, st, g, sd, i2, yd, ad, nx, h, src, flag); break;
+      case 2: hipLaunchKernelGGL((k_classical<2, double, double2, double2>), gr, bl, 0, st, g, sd, i2, yd, ad, nx, h, src, flag); break;
+      case 3: hipLaunchKernelGGL((k_classical<3, double, double2, double2>), gr, bl, 0, st, g, sd, i2, yd, ad, nx, h, src, flag); break;
+      default: hipLaunchKernelGGL((k_classical<4, double, double2, double2>), gr, bl, 0, st, g, sd, i2, yd, ad, nx, h, src, flag); break;
+    }
+  } else {
+    float2* nx = (float2*)next;
+    switch (stage) {
+      case 1: hipLaunchKernelGGL((k_classical<1, double, double2, float2>), gr, bl, 0, st, g, sd, (const double2*)in, yd, ad, nx, h, src, flag); break;
+      case 2: hipLaunchKernelGGL((k_classical<2, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, yd, ad, nx, h, src, flag); break;
+      case 3: hipLaunchKernelGGL((k_classical<3, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, yd, ad, nx, h, src, flag); break;
+      default: hipLaunchKernelGGL((k_classical<4, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, yd, ad, nx, h, src, flag); break;
+    }
+  }
+}
+
+int expect_blocks(const GridArgs& g) { return shape_for(g, 1024).blocks; }
+
+void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, const double2* wtab,
+                           double2* partial, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, 1024);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  if (grid_fp64)
+    hipLaunchKernelGGL((k_expect_partial<double2>), dim3(ls.blocks), dim3(kRedThreads), 0, st, g, sd,
+                       (const double2*)grid, wtab, partial);
+  else
+    hipLaunchKernelGGL((k_expect_partial<float2>), dim3(ls.blocks), dim3(kRedThreads), 0, st, g, sd,
+                       (const float2*)grid, wtab, partial);
+}
+
+void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
+                         double2 analytic, double2* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, st, partial, start, coef, nfun, analytic, out);
+}
+
+void launch_adjoint(int stage, const GridArgs& g, const double2* in, const double2* fwd, const double2* mu,
+                    const double2* vb2, double2* out, double2* Q, double h, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  dim3 gr(ls.blocks), bl(ls.threads);
+  switch (stage) {
+    case 1: hipLaunchKernelGGL((k_adjoint<1>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
+    case 2: hipLaunchKernelGGL((k_adjoint<2>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
+    case 3: hipLaunchKernelGGL((k_adjoint<3>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
+    default: hipLaunchKernelGGL((k_adjoint<4>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
+  }
+}
+
+int marginal_bins(const GridArgs& g) {
+  int tot = 0;
+  for (int j = 0; j < g.n; ++j) tot += g.ext[j];
+  return 2 * tot + g.n;
+}
+
+void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st) {
+  const int nb = marginal_bins(g);
+  hipLaunchKernelGGL(k_marginals, dim3((nb + 63) / 64), dim3(64), 0, st, g, Q, bins);
+}
+
+void launch_fill_zero(double2* p, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, p, n);
+}
+
+void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  hipLaunchKernelGGL(k_fill_weights, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, wtab, out);
+}
+
+}  // namespace hgf

@@ -1,0 +1,83 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function the
+header declares, and validates host-side arguments without touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hgf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hgf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def hgf():
+    import paper_2203_05526_amd as pkg
+    from paper_2203_05526_amd import hgf as mod
+    if not os.path.exists(mod.LIB_PATH):
+        from paper_2203_05526_amd import build
+        build.build()
+    pkg.load_library()
+    return pkg
+
+
+def test_exports_every_declared_symbol(hgf):
+    from paper_2203_05526_amd import hgf as mod
+    lib = ctypes.CDLL(mod.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(mod.EXPORTED) <= set(names)
+
+
+def test_version_and_params(hgf):
+    assert "gfx950" in hgf.version()
+    s = synth.random_system((3, 4, 2), 0)
+    S = hgf.define_system(s)
+    assert S.num_params() == 3 + 3 + 3 * 3
+    assert len(hgf.param_names(3)) == S.num_params()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("gamma1", -0.1), ("gamma_phi", -1.0), ("n_th", -0.5), ("kerr", np.nan), ("detuning", np.inf),
+])
+def test_define_system_rejects_bad_parameters(hgf, field, value):
+    s = synth.random_system((3, 2), 0)
+    getattr(s, field)[0] = value
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.define_system(s)
+    assert e.value.status == "HGF_EINVAL"
+
+
+def test_define_system_rejects_bad_shapes(hgf):
+    s = synth.random_system((3, 2), 0)
+    s.cross_kerr[0, 1] += 1.0  # not symmetric
+    with pytest.raises(hgf.HgfError):
+        hgf.define_system(s)
+    with pytest.raises(hgf.HgfError):
+        hgf.System((0,), [0.0], [0.0], [0.0], [0.1], [0.1], [0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System((40,), [0.0], [0.0], [0.0], [0.1], [0.1], [0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System(tuple([2] * 17), *[[0.0] * 17] * 2, [0.0] * 289, *[[0.1] * 17] * 3)
+
+
+def test_null_arguments_are_rejected(hgf):
+    from paper_2203_05526_amd import hgf as mod
+    lib = mod.load_library()
+    out = ctypes.c_void_p()
+    assert lib.hgf_define_system(None, ctypes.byref(out)) == -1
+    assert b"NULL" in lib.hgf_last_error()
+    assert lib.hgf_evolve(None, 1.0, 0.1, None) == -1
+    assert lib.hgf_num_params(None) == -1

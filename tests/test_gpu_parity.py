@@ -1,0 +1,326 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: relative 1e-10 for FP64, 1e-5 for the mixed form (complex64
+stage grids, FP64 state), measured as max |gpu - oracle| / max |oracle| over
+every grid point of every sector, or as relative error of an expectation
+value.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import announce, gpu_grids, library, max_rel_err, oracle_grids, rel
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def hgf():
+    return library()
+
+
+def _dense_random_operator(cutoff, seed, hermitian=False):
+    rng = np.random.default_rng(seed)
+    dim = int(np.prod(cutoff))
+    M = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    if hermitian:
+        M = M + M.conj().T
+    return M
+
+
+def _sparse_from_dense(cutoff, M):
+    ks, ls, vals = [], [], []
+    for ki in range(M.shape[0]):
+        for li in range(M.shape[1]):
+            if M[ki, li] != 0:
+                ks.append(np.unravel_index(ki, cutoff))
+                ls.append(np.unravel_index(li, cutoff))
+                vals.append(M[ki, li])
+    return np.array(ks), np.array(ls), np.array(vals)
+
+
+# ----------------------------------------------------------------- map only
+
+@pytest.mark.parametrize("basis", ["number", "normal"])
+def test_map_operator_coefficients(hgf, basis):
+    """Step (i): g = <k|A|l>/sqrt(k!l!) per mode (number input) or Eq. (6)
+    (normal-ordered input), grouped by sector."""
+    cutoff = (4, 3)
+    announce(f"map_operator basis={basis}")
+    s = synth.random_system(cutoff, 1)
+    S = hgf.define_system(s)
+    f0 = synth.random_normal_coeffs(4, 3)
+    f1 = synth.random_normal_coeffs(3, 4)
+    if basis == "number":
+        factors = [oracle.number_from_normal(f0), oracle.number_from_normal(f1)]
+    else:
+        factors = [f0, f1]
+    op = hgf.map_operator(S, factors=factors, basis=basis)
+    ref = oracle_grids(cutoff, oracle.product_sectors([oracle.number_from_normal(f0),
+                                                        oracle.number_from_normal(f1)]))
+    assert max_rel_err(gpu_grids(op), ref) < 1e-12
+
+
+# ----------------------------------------------------------------- single mode
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_single_mode_workload(hgf, precision, tol):
+    """One Kerr mode, cutoff 16, |1><1| evolved 1 us with dt = 0.1 ns."""
+    w = synth.single_mode_c0()
+    announce(f"single mode {precision}")
+    ref_ops = oracle.evolve(w.system, oracle.product_sectors(w.factors), w.t_total, w.dt)
+    S = hgf.define_system(w.system)
+    op = hgf.map_operator(S, factors=w.factors, precision=precision)
+    hgf.evolve(op, w.t_total, w.dt)
+    assert op.info()["steps_done"] == w.n_steps
+    for st in w.states + [synth.fock_state([2])]:
+        got = hgf.expectation(op, st)
+        ref = oracle.expectation(w.system.cutoff, ref_ops, st)
+        assert rel(got, ref) < tol, (st, got, ref)
+    assert max_rel_err(gpu_grids(op), oracle_grids(w.system.cutoff, ref_ops)) < tol
+
+
+# ----------------------------------------------------------------- all sectors
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+@pytest.mark.parametrize("cutoff,seed", [((4, 5), 3), ((3, 2, 4), 4), ((1, 7, 3, 2), 5)])
+def test_random_operator_all_sectors(hgf, cutoff, seed, precision, tol):
+    """A dense random operator populates every occupation-difference sector,
+    including those with Kerr and cross-Kerr phases."""
+    announce(f"all sectors cutoff={cutoff} {precision}")
+    s = synth.random_system(cutoff, seed, scale=2.0)
+    M = _dense_random_operator(cutoff, seed)
+    ops = oracle.sectors_from_dense(cutoff, M)
+    T, dt = 0.3, 1e-3
+    ref = oracle.evolve(s, ops, T, dt)
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, sparse=_sparse_from_dense(cutoff, M), precision=precision)
+    hgf.evolve(op, T / 2, dt)
+    hgf.evolve(op, T / 2, dt)  # two calls compose
+    assert max_rel_err(gpu_grids(op), oracle_grids(cutoff, ref)) < tol
+    state = synth.coherent_state([0.4 + 0.1j * j for j in range(len(cutoff))])
+    assert rel(hgf.expectation(op, state), oracle.expectation(cutoff, ref, state)) < (
+        10 * tol if precision == "mixed" else tol)
+
+
+def test_split_layout_matches_oracle(hgf):
+    """The paper's separated form G = Gx Gy + R (Eqs. (9)-(10), (19)-(20)),
+    one function per coefficient, against the oracle."""
+    cutoff = (3, 4)
+    announce("split layout")
+    s = synth.random_system(cutoff, 7, scale=2.0)
+    M = _dense_random_operator(cutoff, 7, hermitian=True)
+    ops = oracle.sectors_from_dense(cutoff, M)
+    T, dt = 0.2, 5e-4
+    ref = oracle.evolve(s, ops, T, dt)
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, sparse=_sparse_from_dense(cutoff, M), layout="split")
+    assert op.info()["n_functions"] == np.count_nonzero(M)
+    hgf.evolve(op, T, dt)
+    for st in (synth.coherent_state([0.7, 0.3 - 0.5j]), synth.fock_state([1, 2])):
+        assert rel(hgf.expectation(op, st), oracle.expectation(cutoff, ref, st)) < 1e-9
+
+
+def test_split_equals_merged_and_separation_constant_cancels(hgf):
+    """Split and merged layouts agree (to RK4's O(h^5) per step); the split
+    functions' separable parts c_x c_y carry the whole initial value."""
+    cutoff = (5,)
+    announce("split vs merged")
+    s = synth.random_system(cutoff, 8)
+    S = hgf.define_system(s)
+    fac = [synth.projector_factors(cutoff, (2,))[0] + 0.5 * synth.quadrature_factors(cutoff)[0]]
+    a = hgf.map_operator(S, factors=fac, layout="split")
+    b = hgf.map_operator(S, factors=fac, layout="merged")
+    for op in (a, b):
+        hgf.evolve(op, 0.5, 1e-3)
+    st = synth.coherent_state([0.9 - 0.2j])
+    assert rel(hgf.expectation(a, st), hgf.expectation(b, st)) < 1e-11
+
+
+# ----------------------------------------------------------------- larger grids
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_five_mode_ragged_grid(hgf, precision, tol):
+    """15120-point grid (extents 7, 9, 6, 8, 5): many blocks and a ragged tail."""
+    cutoff = (7, 9, 6, 8, 5)
+    announce(f"five modes {precision}")
+    s, bits, alpha = synth.seeded_system(cutoff, 11, n_th=0.3)
+    s.gamma1 *= 50.0
+    fac = synth.projector_factors(cutoff, bits)
+    T, dt = 0.05, 1e-4
+    ref = oracle.evolve(s, oracle.product_sectors(fac), T, dt)
+    op = hgf.map_operator(hgf.define_system(s), factors=fac, precision=precision)
+    hgf.evolve(op, T, dt)
+    assert max_rel_err(gpu_grids(op), oracle_grids(cutoff, ref)) < tol
+    st = synth.coherent_state(alpha)
+    assert rel(hgf.expectation(op, st), oracle.expectation(cutoff, ref, st)) < tol
+
+
+def test_three_mode_workload_full_horizon(hgf):
+    """3 Kerr modes, cutoff 12, bitstring projector, T = 10 us, dt = 0.1 ns
+    (1e5 steps): FP64 and mixed against the oracle's stored full-horizon
+    values (written by tests/golden/make_golden.py)."""
+    with open(os.path.join(GOLDEN, "three_mode.json")) as fh:
+        gold = json.load(fh)
+    w = synth.three_mode_c1()
+    S = hgf.define_system(w.system)
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        announce(f"three modes full horizon {precision}")
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        hgf.evolve(op, w.t_total, w.dt)
+        for st, ref in zip(w.states, gold["values"]):
+            got = hgf.expectation(op, st)
+            assert rel(got, complex(*ref)) < tol, (precision, st, got, ref)
+
+
+def test_large_grid_factorises(hgf):
+    """10 modes at cutoff 6 (6^10 = 60,466,176 points, mixed precision, the
+    benchmark's launch configuration): sampled grid points and the
+    expectation equal products of single-mode oracle solutions, exact on the
+    diagonal sector where the generator is a sum of commuting single-mode
+    generators (up to RK4's O(h^5) splitting term)."""
+    w = synth.large_c4()
+    steps = 200
+    announce("10-mode grid, 200 steps, mixed")
+    op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed")
+    hgf.evolve(op, steps * w.dt, w.dt)
+    d, e, grid, _ = op.function(0)
+    assert d == (0,) * 10 and e == (6,) * 10
+    singles = []
+    for j in range(10):
+        sj = synth.System((6,), w.system.detuning[j:j + 1], w.system.kerr[j:j + 1], np.zeros((1, 1)),
+                          w.system.gamma1[j:j + 1], w.system.gamma_phi[j:j + 1], w.system.n_th[j:j + 1])
+        oj = oracle.evolve_steps(sj, oracle.product_sectors([w.factors[j]]), steps, w.dt)
+        singles.append(oracle_grids((6,), oj)[(0,)])
+    rng = np.random.default_rng(0)
+    idx = rng.integers(0, 6, size=(20000, 10))
+    idx = np.concatenate([idx, np.array(np.unravel_index(np.arange(64), (2,) * 6 + (1,) * 4)).T])
+    ref = np.ones(len(idx), dtype=np.complex128)
+    for j in range(10):
+        ref *= singles[j][idx[:, j]]
+    got = grid[tuple(idx.T)]
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) / scale < MIXED_TOL
+    st = w.states[0]
+    # expectation: product of single-mode expectations of the evolved factors
+    Jref = 1.0 + 0j
+    for j in range(10):
+        sj = synth.System((6,), w.system.detuning[j:j + 1], w.system.kerr[j:j + 1], np.zeros((1, 1)),
+                          w.system.gamma1[j:j + 1], w.system.gamma_phi[j:j + 1], w.system.n_th[j:j + 1])
+        oj = oracle.evolve_steps(sj, oracle.product_sectors([w.factors[j]]), steps, w.dt)
+        Jref *= oracle.expectation((6,), oj, ("coherent", [st[1][j]]))
+    assert rel(hgf.expectation(op, st), Jref) < MIXED_TOL
+
+
+# ----------------------------------------------------------------- edge cases
+
+def test_edge_cases(hgf):
+    announce("edge cases")
+    # one level per mode: a single grid point, nothing moves
+    s = synth.random_system((1, 1), 2)
+    op = hgf.map_operator(hgf.define_system(s), factors=[np.array([[2.0]]), np.array([[1.5j]])])
+    hgf.evolve(op, 0.1, 1e-3)
+    assert abs(hgf.expectation(op, synth.fock_state([0, 0])) - 3.0j) < 1e-14
+    # zero operator: no functions, expectation 0
+    s = synth.random_system((3,), 2)
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, factors=[np.zeros((3, 3))])
+    assert op.info()["n_functions"] == 0
+    hgf.evolve(op, 0.1, 1e-3)
+    assert hgf.expectation(op, synth.fock_state([1])) == 0
+    # zero time
+    op = hgf.map_operator(S, factors=[np.eye(3)])
+    hgf.evolve(op, 0.0, 1e-3)
+    assert op.info()["steps_done"] == 0
+    assert abs(hgf.expectation(op, synth.coherent_state([0.5])) - 1.0) < 1e-14
+    # identity stays the identity (adjoint master equation is unital)
+    hgf.evolve(op, 0.5, 1e-3)
+    assert abs(hgf.expectation(op, synth.coherent_state([0.5 + 0.5j])) - 1.0) < 1e-13
+
+
+def test_error_paths(hgf):
+    announce("error paths")
+    s = synth.random_system((3,), 2)
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, factors=[np.eye(3)])
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.evolve(op, 0.15, 0.1)
+    assert e.value.status == "HGF_EINVAL"
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.evolve(op, 100.0, 10.0)
+    assert e.value.status == "HGF_EUNSTABLE"
+    assert op.info()["steps_done"] == 0
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.expectation(op, synth.fock_state([3]))
+    assert e.value.status == "HGF_EINVAL"
+    with pytest.raises(hgf.HgfError):
+        hgf.map_operator(S, sparse=(np.array([[3]]), np.array([[0]]), np.array([1.0])))
+
+
+def test_nonfinite_detected_and_state_restored(hgf):
+    """An overflowing stage (|h L y| > DBL_MAX) is caught: HGF_ENONFINITE,
+    the function is restored and further evolves are refused."""
+    announce("non-finite detection")
+    s = synth.System((2,), np.zeros(1), np.zeros(1), np.zeros((1, 1)), np.array([2.0]), np.zeros(1),
+                     np.zeros(1))
+    S = hgf.define_system(s)
+    big = 1.7e308
+    op = hgf.map_operator(S, factors=[np.array([[0.0, 0.0], [0.0, big]])])
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.evolve(op, 0.6, 0.6)
+    assert e.value.status == "HGF_ENONFINITE"
+    _, _, grid, _ = op.function(0)
+    assert grid[1] == big
+    assert op.info()["error_state"] == 1
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.evolve(op, 0.6, 0.6)
+    assert e.value.status == "HGF_ESTATE"
+
+
+# ----------------------------------------------------------------- batching
+
+def test_batch_equals_individual(hgf):
+    announce("batch vs individual")
+    ws = synth.batch_c2(n_even=2, n_uneven=2)
+    ops_a, ops_b = [], []
+    for w in ws:
+        S = hgf.define_system(w.system)
+        ops_a.append(hgf.map_operator(S, factors=w.factors, precision="mixed"))
+        ops_b.append(hgf.map_operator(S, factors=w.factors, precision="mixed"))
+    hgf.evolve_batch(ops_a, [0.01] * len(ws), [1e-4] * len(ws))
+    for op in ops_b:
+        hgf.evolve(op, 0.01, 1e-4)
+    for w, a, b in zip(ws, ops_a, ops_b):
+        st = w.states[0]
+        assert hgf.expectation(a, st) == hgf.expectation(b, st)
+
+
+# ----------------------------------------------------------------- gradient
+
+def test_gradient_matches_oracle_sensitivities(hgf):
+    """Reverse sweep (discrete adjoint of the RK4 steps, checkpointed) against
+    the oracle's forward sensitivities, all sectors of a Hermitian operator."""
+    cutoff = (3, 4)
+    announce("gradient vs oracle")
+    s = synth.random_system(cutoff, 9, scale=2.0, n_th=0.2)
+    M = _dense_random_operator(cutoff, 9, hermitian=True)
+    ops = oracle.sectors_from_dense(cutoff, M)
+    T, dt = 0.1, 1e-3
+    st = synth.coherent_state([0.6 + 0.2j, 0.9])
+    a_t, sens = oracle.evolve_sens(s, ops, T, dt)
+    ref_val = oracle.expectation(cutoff, a_t, st)
+    ref_grad = np.array([oracle.expectation(cutoff, sp, st) for sp in sens])
+    S = hgf.define_system(s)
+    for ce in (1, 7, 100):
+        val, g = hgf.grad(S, st, T, dt, sparse=_sparse_from_dense(cutoff, M), checkpoint_every=ce)
+        assert rel(val, ref_val) < FP64_TOL
+        assert np.max(np.abs(g - ref_grad)) / np.max(np.abs(ref_grad)) < 1e-9
