@@ -1,0 +1,195 @@
+"""Benchmark: grid-point RK4 stage updates per second of the generating-function
+stencil on one MI355X, with the HBM roofline of the stage kernel and the CPU
+oracle timed beside it.
+
+Workload (default): 10 Kerr modes at cutoff 6 (6^10 = 60,466,176 grid points
+in the diagonal occupation-difference sector), seeded parameters, observable
+prod_j (|0><0| - |1><1|), merged layout, mixed precision (complex64 stage
+grids with FP32 stencil arithmetic, complex128 state, FP64 expectation),
+dt = 0.05 ns.  One benchmark step is one RK4 time step (four fused stage
+launches over the whole grid); the timed region is K steps through
+hgf_evolve followed by one hgf_expectation.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point RK stage updates/s + % HBM peak; time-to-1e-5 vs FP64 plain"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per grid point of one stage launch, averaged over the
+# four stages of one step (stage grids complex64, state complex128):
+#   stage 1: read y (16) + write X1 (8)            = 24
+#   stage 2: read X1 (8) + write V1 (8)            = 16
+#   stage 3: read V1, X1 (16) + write V2 (8)       = 24
+#   stage 4: read V2, X1 (16) + read/write y (32)  = 48     -> 112 / 4 = 28
+BYTES_PER_POINT_STAGE = {"mixed": 28.0, "fp64": 44.0}
+STAGE_KERNEL = "k_rk4_stage"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_05526_amd", "csrc", "hgf_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_10mode_mixed_traffic.json")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per stage launch from committed rocprofv3 counter runs, or
+    None when the kernel source changed since they were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(w, steps: int):
+    """The CPU oracle (number-basis adjoint master equation, classical RK4) on
+    the same grid for a few steps, all host threads."""
+    import oracle
+    ops = oracle.product_sectors(w.factors)
+    t0 = time.perf_counter()
+    oracle.evolve_steps(w.system, ops, steps, w.dt)
+    el = time.perf_counter() - t0
+    pts = int(np.prod(w.system.cutoff))
+    return {"value": pts * 4 * steps / el, "unit": "point-stage updates/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} RK4 steps over all {pts} points of the same 10-mode grid ({el:.1f} s)"}
+
+
+def time_to_tolerance(hgf, torch):
+    """Wall time of the full 3-mode horizon (1e5 steps) in mixed precision and
+    in FP64, each with its error against the FP64 oracle's stored value."""
+    import synth
+    gold_path = os.path.join(ROOT, "tests", "golden", "three_mode.json")
+    with open(gold_path) as fh:
+        gold = json.load(fh)
+    w = synth.three_mode_c1()
+    S = hgf.define_system(w.system)
+    ref = complex(*gold["values"][0])
+    out = {"workload": "3 Kerr modes, cutoff 12, bitstring projector, T = 10 us, dt = 0.1 ns (1e5 steps)"}
+    for prec in ("mixed", "fp64"):
+        op = hgf.map_operator(S, factors=w.factors, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hgf.evolve(op, w.t_total, w.dt)
+        J = hgf.expectation(op, w.states[0])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{prec}_s"] = el
+        out[f"{prec}_rel_err"] = abs(J - ref) / abs(ref)
+    out["mixed_within_1e-5"] = out["mixed_rel_err"] <= 1e-5
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each function would shard whole onto one GPU; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2203_05526_amd as hgf
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    hgf.load_library()
+    w = synth.large_c4()
+    pts = int(np.prod(w.system.cutoff))
+    S = hgf.define_system(w.system)
+
+    def run(precision, steps, warmup):
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        if warmup:
+            hgf.evolve(op, warmup * w.dt, w.dt)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record()
+        hgf.evolve(op, steps * w.dt, w.dt)
+        end.record()
+        J = hgf.expectation(op, w.states[0])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        launch_s = start.elapsed_time(end) * 1e-3 / (4 * steps)
+        del op
+        return el, launch_s, J
+
+    log(f"timing {args.steps} steps ({args.precision}) over {pts} points")
+    el, launch_s, J = run(args.precision, args.steps, args.warmup)
+    log(f"done: {el:.3f} s, stage launch {launch_s * 1e6:.1f} us")
+    value = pts * 4 * args.steps / el
+    bytes_launch = BYTES_PER_POINT_STAGE[args.precision] * pts
+    achieved = bytes_launch / launch_s / 1e9
+    traffic = stored_traffic()
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "point-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64/f32 stencil, c128/f64 state" if args.precision == "mixed" else "c128/f64",
+        "data": "synthetic (seeded parameters, no dataset)",
+        "config": {"workload": "10 Kerr modes, cutoff 6 (6^10 grid points), parity-weighted projector, "
+                               "dt = 0.05 ns, merged layout",
+                   "precision": args.precision, "grid_points": pts, "seed": 4},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": STAGE_KERNEL, "avg_launch_us": launch_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "expectation": [J.real, J.imag],
+    }
+    if not args.no_extras:
+        log("fp64 comparison")
+        el64, launch64, J64 = run("fp64", max(10, args.steps // 4), 2)
+        n64 = max(10, args.steps // 4)
+        line["fp64_plain"] = {"value": pts * 4 * n64 / el64, "steps": n64,
+                              "achieved_GBs": BYTES_PER_POINT_STAGE["fp64"] * pts / launch64 / 1e9}
+        log("time-to-1e-5 on the 3-mode workload")
+        line["time_to_1e-5"] = time_to_tolerance(hgf, torch)
+    if not args.no_cpu_baseline:
+        log("cpu oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,9 +189,9 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // complex64 keeps the state's FP64 accuracy to first order in hL.
 
 template <int STAGE, typename R, typename TIN, typename TS>
-__global__ __launch_bounds__(256) void k_horner(GridArgs g, StrideDigits sd, const TIN* __restrict__ in,
-                                                const TS* __restrict__ x1, double2* __restrict__ y,
-                                                TS* __restrict__ out, double h, int* __restrict__ flag) {
+__device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigits& sd, const TIN* __restrict__ in,
+                                            const TS* __restrict__ x1, double2* __restrict__ y,
+                                            TS* __restrict__ out, double h, int* __restrict__ flag) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 >= g.points) return;
   Walker w;
@@ -217,6 +217,22 @@ __global__ __launch_bounds__(256) void k_horner(GridArgs g, StrideDigits sd, con
     walker_step(w, g, sd);
   }
   if (STAGE == 4 && bad) atomicOr(flag, 1);
+}
+
+// One kernel symbol for the four stages (the stage is a uniform argument), so
+// that profiles report the RK4 stage work as one kernel.  TS is the storage
+// type of the stage grids; RS the arithmetic type of stages 2-4 (stage 1
+// reads the complex128 state and works in FP64).
+template <typename TS, typename RS>
+__global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, int stage, const void* in,
+                                                   const TS* __restrict__ x1, double2* __restrict__ y,
+                                                   TS* __restrict__ out, double h, int* __restrict__ flag) {
+  switch (stage) {
+    case 1: horner_body<1, double>(g, sd, (const double2*)in, x1, y, out, h, flag); break;
+    case 2: horner_body<2, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
+    case 3: horner_body<3, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
+    default: horner_body<4, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
+  }
 }
 
 // ------------------------------------------------------------ RK4, classical form
@@ -465,27 +481,12 @@ void launch_horner(int stage, int precision, const GridArgs& g, const void* in, 
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   dim3 gr(ls.blocks), bl(ls.threads);
-  double2* yd = (double2*)y;
-  if (precision == HGF_FP64) {
-    const double2* i2 = (const double2*)in;
-    const double2* x = (const double2*)x1;
-    double2* o = (double2*)out;
-    switch (stage) {
-      case 1: hipLaunchKernelGGL((k_horner<1, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
-      case 2: hipLaunchKernelGGL((k_horner<2, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
-      case 3: hipLaunchKernelGGL((k_horner<3, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
-      default: hipLaunchKernelGGL((k_horner<4, double, double2, double2>), gr, bl, 0, st, g, sd, i2, x, yd, o, h, flag); break;
-    }
-  } else {
-    const float2* x = (const float2*)x1;
-    float2* o = (float2*)out;
-    switch (stage) {
-      case 1: hipLaunchKernelGGL((k_horner<1, double, double2, float2>), gr, bl, 0, st, g, sd, (const double2*)in, x, yd, o, h, flag); break;
-      case 2: hipLaunchKernelGGL((k_horner<2, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
-      case 3: hipLaunchKernelGGL((k_horner<3, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
-      default: hipLaunchKernelGGL((k_horner<4, float, float2, float2>), gr, bl, 0, st, g, sd, (const float2*)in, x, yd, o, h, flag); break;
-    }
-  }
+  if (precision == HGF_FP64)
+    hipLaunchKernelGGL((k_rk4_stage<double2, double>), gr, bl, 0, st, g, sd, stage, in, (const double2*)x1,
+                       (double2*)y, (double2*)out, h, flag);
+  else
+    hipLaunchKernelGGL((k_rk4_stage<float2, float>), gr, bl, 0, st, g, sd, stage, in, (const float2*)x1,
+                       (double2*)y, (float2*)out, h, flag);
 }
 
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
