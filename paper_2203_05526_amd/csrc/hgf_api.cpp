@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <stdexcept>
@@ -125,6 +126,56 @@ static void check_stability(const std::vector<Function>& fns, double dt) {
 
 // ------------------------------------------------------------------ functions
 
+// Choose the fast (LDS-tiled) axes of the tiled stage kernel: the largest
+// number `nfast` <= 4 of trailing axes whose padded tile and tables fit in
+// 64 KB of LDS (nfast_req > 0 forces a value when it fits).  Sets
+// g.blocks = 0 (generic kernel) when HGF_STAGE_KERNEL=generic.
+static void configure_tiles(GridArgs& g, int precision, int nfast_req) {
+  g.blocks = 0;
+  g.nfast = 0;
+  const char* env = std::getenv("HGF_STAGE_KERNEL");
+  if (env && std::string(env) == "generic") return;
+  const int ts = precision == HGF_FP64 ? 16 : 8, rs = precision == HGF_FP64 ? 8 : 4;
+  int best = 0;
+  for (int F = std::min(4, g.n); F >= 1; --F) {
+    if (nfast_req > 0 && F != nfast_req) continue;
+    if (g.n - F > tiled_max_slow_axes()) continue;
+    int64_t T = 1, padded = 1, esum = 0;
+    int emax = 0;
+    for (int q = 0; q < F; ++q) {
+      const int e = g.ext[g.n - F + q];
+      T *= e;
+      padded *= e + 2;
+      esum += e;
+      emax = std::max(emax, e);
+    }
+    const int cbits = F == 4 ? 4 : 5;
+    if (emax > (1 << cbits) || padded >= 65536) continue;
+    const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + esum * rs + 64;
+    if (bytes > 65536) continue;
+    best = F;
+    g.nfast = F;
+    g.cbits = cbits;
+    g.tile_points = T;
+    g.lds_elems = (int)padded;
+    g.lds_bytes = (int)bytes;
+    int64_t pst = 1;
+    for (int q = F - 1; q >= 0; --q) {
+      g.pstride[q] = (int)pst;
+      pst *= g.ext[g.n - F + q] + 2;
+    }
+    break;
+  }
+  if (best == 0) return;
+  g.ntiles = g.points / g.tile_points;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, precision, g.lds_bytes);
+  const int64_t want = (int64_t)cus * occ;
+  const int64_t cap = 8 * ((g.ntiles + 7) / 8);
+  g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
+}
+
 static void fill_grid_args(Function& f, int precision) {
   GridArgs& g = f.ga;
   std::memset(&g, 0, sizeof(g));
@@ -148,6 +199,7 @@ static void fill_grid_args(Function& f, int precision) {
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
+  configure_tiles(g, precision, -1);
   // device tables: lam (double2), beta (double), lam_f (float2), beta_f (float)
   const int tot = off;
   std::vector<double> lam(2 * tot), beta(tot);
@@ -187,6 +239,7 @@ static void alloc_function_buffers(Function& f, int precision) {
   f.s2 = dmalloc(P * cs);
   f.s3 = dmalloc(P * cs);
   if (f.split) f.s4 = dmalloc(P * sizeof(double2));
+  if (precision == HGF_MIXED) f.yf = dmalloc(P * sizeof(float2));
 }
 
 static void free_function(Function& f) {
@@ -196,6 +249,7 @@ static void free_function(Function& f) {
   dfree(f.s3);
   dfree(f.s4);
   dfree(f.ybak);
+  dfree(f.yf);
   dfree(f.dtab);
 }
 
@@ -379,9 +433,11 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
   }
 }
 
-static void upload_state(Function& f, const std::vector<cd>& grid) {
+static void upload_state(Function& f, const std::vector<cd>& grid, int precision) {
   static_assert(sizeof(cd) == sizeof(double2), "layout");
   hip_check(hipMemcpy(f.y, grid.data(), grid.size() * sizeof(double2), hipMemcpyHostToDevice), "upload state");
+  launch_shadow(precision, f.ga, f.y, f.yf, nullptr);
+  hip_check(hipGetLastError(), "shadow copy");
 }
 
 // energy of the number state |k>
@@ -467,7 +523,7 @@ static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
       f.tab = sector_tables(op->sys, kv.first.data());
       fill_grid_args(f, op->precision);
       alloc_function_buffers(f, op->precision);
-      upload_state(f, kv.second);
+      upload_state(f, kv.second, op->precision);
     }
   } else {
     for (const Coeff& c : coeffs) {
@@ -482,7 +538,7 @@ static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
       fill_grid_args(f, op->precision);
       alloc_function_buffers(f, op->precision);
       std::vector<cd> zero(f.ga.points, 0.0);
-      upload_state(f, zero);
+      upload_state(f, zero, op->precision);
       setup_split(f, op->sys, c);
     }
   }
@@ -495,10 +551,11 @@ static void reset_flag(hgf_operator_s* op, hipStream_t st) {
 }
 
 static void merged_step(hgf_operator_s* op, Function& f, double h, hipStream_t st) {
-  launch_horner(1, op->precision, f.ga, f.y, nullptr, f.y, f.s1, h, op->dflag, st);
-  launch_horner(2, op->precision, f.ga, f.s1, f.s1, f.y, f.s2, h, op->dflag, st);
-  launch_horner(3, op->precision, f.ga, f.s2, f.s1, f.y, f.s3, h, op->dflag, st);
-  launch_horner(4, op->precision, f.ga, f.s3, f.s1, f.y, nullptr, h, op->dflag, st);
+  const void* in1 = op->precision == HGF_MIXED ? f.yf : f.y;
+  launch_horner(1, op->precision, f.ga, in1, nullptr, f.y, f.yf, f.s1, h, op->dflag, st);
+  launch_horner(2, op->precision, f.ga, f.s1, f.s1, f.y, f.yf, f.s2, h, op->dflag, st);
+  launch_horner(3, op->precision, f.ga, f.s2, f.s1, f.y, f.yf, f.s3, h, op->dflag, st);
+  launch_horner(4, op->precision, f.ga, f.s3, f.s1, f.y, f.yf, nullptr, h, op->dflag, st);
 }
 
 static void drop_graph(hgf_operator_s* op) {
@@ -607,6 +664,7 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
     for (size_t i = 0; i < op->fn.size(); ++i) {
       const size_t bytes = op->fn[i].ga.points * sizeof(double2);
       hip_check(hipMemcpyAsync(op->fn[i].y, op->fn[i].ybak, bytes, hipMemcpyDeviceToDevice, st), "restore");
+      launch_shadow(op->precision, op->fn[i].ga, op->fn[i].y, op->fn[i].yf, st);
       op->fn[i].cx = cx0[i];
       op->fn[i].cy = cy0[i];
     }
@@ -798,9 +856,9 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
       for (int64_t i = L - 1; i >= 0; --i) {
         double2* yn = seg + i * pts;
         // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
-        launch_horner(1, HGF_FP64, f.ga, yn, nullptr, yn, f.s1, dt, op.dflag, st);
-        launch_horner(2, HGF_FP64, f.ga, f.s1, f.s1, yn, f.s2, dt, op.dflag, st);
-        launch_horner(3, HGF_FP64, f.ga, f.s2, f.s1, yn, f.s3, dt, op.dflag, st);
+        launch_horner(1, HGF_FP64, f.ga, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, st);
+        launch_horner(2, HGF_FP64, f.ga, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, st);
+        launch_horner(3, HGF_FP64, f.ga, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, st);
         double2* Qp = Q.as<double2>();
         launch_adjoint(1, f.ga, mu.as<double2>(), (const double2*)f.s3, nullptr, nullptr, vb2.as<double2>(), Qp, dt, st);
         launch_adjoint(2, f.ga, vb2.as<double2>(), (const double2*)f.s2, nullptr, nullptr, vb1.as<double2>(), Qp, dt, st);

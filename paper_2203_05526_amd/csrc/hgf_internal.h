@@ -79,6 +79,13 @@ struct GridArgs {
   int64_t tile_points;      // product of the fast extents
   int64_t ntiles;
   int off[kMaxModes];       // start of axis j in the concatenated tables
+  // tiled stage kernel: the trailing `nfast` axes form one tile held in LDS
+  // with a zero halo of one point on each side of every fast axis
+  int pstride[4];           // padded LDS strides of the fast axes
+  int lds_elems;            // padded tile size in elements
+  int cbits;                // bits per packed fast coordinate
+  int blocks;               // persistent grid size (0: generic kernel)
+  int lds_bytes;            // dynamic LDS of the tiled kernel
   double lam0_re, lam0_im;
   double alpha[kMaxModes];
   const double2* lam;       // concatenated lam_j(m)
@@ -98,6 +105,7 @@ struct Function {
   void* s2 = nullptr;
   void* s3 = nullptr;
   void* s4 = nullptr;  // classical (split) form only: RK accumulator, complex128
+  void* yf = nullptr;  // mixed precision: complex64 copy of y, the stencil input of stage 1
   void* dtab = nullptr;  // device tables
   // split mode
   bool split = false;

@@ -113,18 +113,14 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
       const CT lj = lam[g.off[j] + m];
       lr += lj.x;
       li += lj.y;
-      if (m >= 1) {
-        const CT nb = load_as<R>(in, w.i - g.stride[j]);
-        const R a = (R)g.alpha[j];
-        acc.x += a * nb.x;
-        acc.y += a * nb.y;
-      }
-      if (m + 1 < g.ext[j]) {
-        const CT nb = load_as<R>(in, w.i + g.stride[j]);
-        const R b = beta[g.off[j] + m];
-        acc.x += b * nb.x;
-        acc.y += b * nb.y;
-      }
+      // out-of-range neighbours read the centre with a zero coefficient
+      // (beta is zero at the top of an axis), keeping the loads branch-free
+      const CT dn = load_as<R>(in, m >= 1 ? w.i - g.stride[j] : w.i);
+      const CT upv = load_as<R>(in, m + 1 < g.ext[j] ? w.i + g.stride[j] : w.i);
+      const R a = m >= 1 ? (R)g.alpha[j] : (R)0;
+      const R b = beta[g.off[j] + m];
+      acc.x += a * dn.x + b * upv.x;
+      acc.y += a * dn.y + b * upv.y;
     }
   }
   const CT c = load_as<R>(in, w.i);
@@ -146,17 +142,15 @@ __device__ __forceinline__ double2 apply_LT(const GridArgs& g, const TIN* __rest
       const double2 lj = g.lam[g.off[j] + m];
       lr += lj.x;
       li += lj.y;
-      if (m + 1 < g.ext[j]) {  // L[m+e, m] = alpha
-        const double2 nb = to_d2(in[w.i + g.stride[j]]);
-        acc.x += g.alpha[j] * nb.x;
-        acc.y += g.alpha[j] * nb.y;
-      }
-      if (m >= 1) {  // L[m-e, m] = beta(m-1)
-        const double2 nb = to_d2(in[w.i - g.stride[j]]);
-        const double b = g.beta[g.off[j] + m - 1];
-        acc.x += b * nb.x;
-        acc.y += b * nb.y;
-      }
+      // L[m+e, m] = alpha, L[m-e, m] = beta(m-1); out-of-range neighbours
+      // read the centre with a zero coefficient
+      const bool uv = m + 1 < g.ext[j], dv = m >= 1;
+      const double2 upv = to_d2(in[uv ? w.i + g.stride[j] : w.i]);
+      const double2 dn = to_d2(in[dv ? w.i - g.stride[j] : w.i]);
+      const double a = uv ? g.alpha[j] : 0.0;
+      const double b = dv ? g.beta[g.off[j] + m - 1] : 0.0;
+      acc.x += a * upv.x + b * dn.x;
+      acc.y += a * upv.y + b * dn.y;
     }
   }
   const double2 c = to_d2(in[w.i]);
@@ -188,10 +182,11 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // The stage grids hold only increments (small next to y), so storing them in
 // complex64 keeps the state's FP64 accuracy to first order in hL.
 
-template <int STAGE, typename R, typename TIN, typename TS>
-__device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigits& sd, const TIN* __restrict__ in,
+template <int STAGE, typename R, typename TS>
+__device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigits& sd, const TS* __restrict__ in,
                                             const TS* __restrict__ x1, double2* __restrict__ y,
-                                            TS* __restrict__ out, double h, int* __restrict__ flag) {
+                                            TS* __restrict__ yf, TS* __restrict__ out, double h,
+                                            int* __restrict__ flag) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 >= g.points) return;
   Walker w;
@@ -213,26 +208,235 @@ __device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigit
       yv.y += base.y + c * (double)lv.y;
       bad |= !(isfinite(yv.x) && isfinite(yv.y));
       y[w.i] = yv;
+      if (yf) yf[w.i] = from_d2<TS>(yv);
     }
     walker_step(w, g, sd);
   }
   if (STAGE == 4 && bad) atomicOr(flag, 1);
 }
 
-// One kernel symbol for the four stages (the stage is a uniform argument), so
-// that profiles report the RK4 stage work as one kernel.  TS is the storage
-// type of the stage grids; RS the arithmetic type of stages 2-4 (stage 1
-// reads the complex128 state and works in FP64).
+// Generic stage kernel (any number of axes and extents, grid-stride loop).
+// One kernel symbol serves the four stages (the stage is a uniform argument).
+// TS is the storage type of the stage grids, RS the stencil arithmetic type;
+// the stencil input of stage 1 is y itself (FP64) or its complex64 copy yf
+// (mixed), which stage 4 refreshes.
 template <typename TS, typename RS>
-__global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, int stage, const void* in,
+__global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, int stage, const TS* in,
                                                    const TS* __restrict__ x1, double2* __restrict__ y,
-                                                   TS* __restrict__ out, double h, int* __restrict__ flag) {
+                                                   TS* __restrict__ yf, TS* __restrict__ out, double h,
+                                                   int* __restrict__ flag) {
   switch (stage) {
-    case 1: horner_body<1, double>(g, sd, (const double2*)in, x1, y, out, h, flag); break;
-    case 2: horner_body<2, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
-    case 3: horner_body<3, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
-    default: horner_body<4, RS>(g, sd, (const TS*)in, x1, y, out, h, flag); break;
+    case 1: horner_body<1, RS>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 2: horner_body<2, RS>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 3: horner_body<3, RS>(g, sd, in, x1, y, yf, out, h, flag); break;
+    default: horner_body<4, RS>(g, sd, in, x1, y, yf, out, h, flag); break;
   }
+}
+
+// ------------------------------------------------------------ RK4, tiled form
+//
+// The trailing NF axes of the grid form a tile of T points that is contiguous
+// in memory.  A workgroup stages the tile's stencil input in LDS with a zero
+// halo around every fast axis, so the fast-axis neighbours are unconditional
+// LDS reads; the neighbours along the remaining (slow) axes are whole tiles at
+// a fixed offset and are read from global memory (they are reused across
+// workgroups through L2 and the Infinity Cache).  Coefficients that depend on
+// a fast coordinate (lam_fast, beta) come from per-position LDS tables built
+// once per workgroup; the slow-axis terms are uniform over a tile.
+//
+// Work distribution: the workgroups are persistent.  Workgroup b runs on XCD
+// b % 8, so each XCD is given a contiguous range of tiles and walks it with its
+// own workgroups in step: at any time an XCD's L2 holds a compact window of
+// the grid.  Streaming operands (x1, y, outputs) use non-temporal loads and
+// stores so that they do not evict the stencil input from the caches.
+
+template <typename TS>
+struct Real;
+template <>
+struct Real<float2> {
+  using T = float;
+  typedef float v2 __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Real<double2> {
+  using T = double;
+  typedef double v2 __attribute__((ext_vector_type(2)));
+};
+
+template <typename TS>
+__device__ __forceinline__ TS nt_load(const TS* p) {
+  using V = typename Real<TS>::v2;
+  const V v = __builtin_nontemporal_load((const V*)p);
+  TS o;
+  o.x = v.x;
+  o.y = v.y;
+  return o;
+}
+template <typename TS>
+__device__ __forceinline__ void nt_store(TS* p, TS a) {
+  using V = typename Real<TS>::v2;
+  V v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (V*)p);
+}
+
+template <int NF, int NS, typename TS>
+__global__ __launch_bounds__(256) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
+                                                   const TS* __restrict__ x1, double2* __restrict__ y,
+                                                   TS* __restrict__ yf, TS* __restrict__ out, double h,
+                                                   int* __restrict__ flag) {
+  using R = typename Real<TS>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int T = (int)g.tile_points;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  TS* tile = (TS*)smem;
+  TS* lamf = tile + g.lds_elems;
+  uint32_t* info = (uint32_t*)(lamf + T);
+  R* btab = (R*)(info + ((T + 1) & ~1));
+  const double2* lamt = g.lam;
+  const double* betat = g.beta;
+
+  // ---- once per workgroup: zero halo, per-position tables
+  for (int i = tid; i < g.lds_elems; i += nt) {
+    tile[i].x = 0;
+    tile[i].y = 0;
+  }
+  const uint32_t cmask = (1u << g.cbits) - 1u;
+  for (int p = tid; p < T; p += nt) {
+    int rem = p;
+    uint32_t off = 0, coords = 0;
+    double lr = 0.0, li = 0.0;
+#pragma unroll
+    for (int q = NF - 1; q >= 0; --q) {
+      const int j = NS + q;
+      const int e = g.ext[j];
+      const int c = rem % e;
+      rem /= e;
+      off += (uint32_t)(c + 1) * (uint32_t)g.pstride[q];
+      coords |= (uint32_t)c << (g.cbits * q);
+      const double2 lj = lamt[g.off[j] + c];
+      lr += lj.x;
+      li += lj.y;
+    }
+    info[p] = off | (coords << 16);
+    lamf[p].x = (R)lr;
+    lamf[p].y = (R)li;
+  }
+  int boff[NF];
+  {
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      boff[q] = o;
+      const int j = NS + q;
+      for (int c = tid; c < g.ext[j]; c += nt) btab[o + c] = (R)betat[g.off[j] + c];
+      o += g.ext[j];
+    }
+  }
+  __syncthreads();
+
+  // ---- XCD-aware persistent walk over tiles
+  const int xcd = blockIdx.x & 7;
+  const int nwx = ((int)gridDim.x - xcd + 7) >> 3;
+  const int64_t lo = g.ntiles * xcd / 8, hi = g.ntiles * (xcd + 1) / 8;
+  int bad = 0;
+  for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nwx) {
+    // slow-axis terms, uniform over the tile: an out-of-range direction
+    // reads the centre with a zero coefficient, so every load is issued
+    // unconditionally and the loads of a point overlap in flight
+    double lsr = g.lam0_re, lsi = g.lam0_im;
+    int64_t dno[NS > 0 ? NS : 1], upo[NS > 0 ? NS : 1];
+    R dnc[NS > 0 ? NS : 1], upc[NS > 0 ? NS : 1];
+    {
+      int64_t rem = t;
+#pragma unroll
+      for (int j = NS - 1; j >= 0; --j) {
+        const int e = g.ext[j];
+        const int sj = (int)(rem % e);
+        rem /= e;
+        const double2 lj = lamt[g.off[j] + sj];
+        lsr += lj.x;
+        lsi += lj.y;
+        const bool dv = sj >= 1, uv = sj + 1 < e;
+        dno[j] = dv ? -g.stride[j] : 0;
+        dnc[j] = dv ? (R)g.alpha[j] : (R)0;
+        upo[j] = uv ? g.stride[j] : 0;
+        upc[j] = uv ? (R)betat[g.off[j] + sj] : (R)0;
+      }
+    }
+    const int64_t tbase = t * (int64_t)T;
+    const TS* tin = in + tbase;
+    for (int p = tid; p < T; p += nt) tile[info[p] & 0xffffu] = tin[p];
+    __syncthreads();
+    for (int p = tid; p < T; p += nt) {
+      TS sv[2 * (NS > 0 ? NS : 1)];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        sv[2 * j] = tin[p + dno[j]];
+        sv[2 * j + 1] = tin[p + upo[j]];
+      }
+      const int64_t i = tbase + p;
+      TS xb;
+      double2 yv;
+      if (stage >= 2) xb = nt_load(x1 + i);
+      if (stage == 4) yv = nt_load(y + i);
+      const uint32_t inf = info[p];
+      const int lo_ = (int)(inf & 0xffffu);
+      const TS zc = tile[lo_];
+      const TS lf = lamf[p];
+      const R lr = (R)lsr + lf.x, li = (R)lsi + lf.y;
+      R ar = lr * zc.x - li * zc.y;
+      R ai = lr * zc.y + li * zc.x;
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const TS dn = tile[lo_ - g.pstride[q]];
+        const TS upv = tile[lo_ + g.pstride[q]];
+        const int c = (int)((inf >> (16 + g.cbits * q)) & cmask);
+        const R b = btab[boff[q] + c];
+        const R a = (R)g.alpha[NS + q];
+        ar += a * dn.x + b * upv.x;
+        ai += a * dn.y + b * upv.y;
+      }
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        ar += dnc[j] * sv[2 * j].x + upc[j] * sv[2 * j + 1].x;
+        ai += dnc[j] * sv[2 * j].y + upc[j] * sv[2 * j + 1].y;
+      }
+      if (stage == 1) {
+        TS o;
+        o.x = (R)(h * (double)ar);
+        o.y = (R)(h * (double)ai);
+        nt_store(out + i, o);
+      } else if (stage == 2 || stage == 3) {
+        const R c = (R)(stage == 2 ? 0.25 * h : h / 3.0);
+        TS o;
+        o.x = xb.x + c * ar;
+        o.y = xb.y + c * ai;
+        nt_store(out + i, o);
+      } else {
+        const double c = 0.5 * h;
+        yv.x += (double)xb.x + c * (double)ar;
+        yv.y += (double)xb.y + c * (double)ai;
+        bad |= !(isfinite(yv.x) && isfinite(yv.y));
+        nt_store(y + i, yv);
+        if (yf) {
+          TS f;
+          f.x = (R)yv.x;
+          f.y = (R)yv.y;
+          yf[i] = f;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename TS>
+__global__ void k_shadow(const double2* __restrict__ y, TS* __restrict__ yf, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    yf[i] = from_d2<TS>(y[i]);
 }
 
 // ------------------------------------------------------------ RK4, classical form
@@ -476,17 +680,101 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks) {
 
 static const int kStageBlocks = 4096;
 
-void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+// Instantiations of the tiled kernel: NF fast axes (1..4) and NS slow axes
+// (0..12), i.e. every grid of up to 16 modes whose slow part has at most 12 axes.
+#define HGF_NS_CASES(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12)
+constexpr int kMaxSlow = 12;
+
+template <typename TS, int NF>
+static void tiled_launch_nf(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
+                            void* out, double h, int* flag, hipStream_t st) {
+  const int ns = g.n - NF;
+  switch (ns) {
+#define HGF_CASE(K)                                                                                          \
+  case K:                                                                                                    \
+    hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS>), dim3(g.blocks), dim3(256), g.lds_bytes, st, g, stage,       \
+                       (const TS*)in, (const TS*)x1, (double2*)y, (TS*)yf, (TS*)out, h, flag);              \
+    break;
+    HGF_NS_CASES(HGF_CASE)
+#undef HGF_CASE
+    default: break;
+  }
+}
+
+template <typename TS>
+static void tiled_dispatch(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
+                           void* out, double h, int* flag, hipStream_t st) {
+  switch (g.nfast) {
+    case 1: tiled_launch_nf<TS, 1>(g, stage, in, x1, y, yf, out, h, flag, st); break;
+    case 2: tiled_launch_nf<TS, 2>(g, stage, in, x1, y, yf, out, h, flag, st); break;
+    case 3: tiled_launch_nf<TS, 3>(g, stage, in, x1, y, yf, out, h, flag, st); break;
+    default: tiled_launch_nf<TS, 4>(g, stage, in, x1, y, yf, out, h, flag, st); break;
+  }
+}
+
+template <typename TS, int NF>
+static int occ_nf(int ns, int lds_bytes) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (ns) {
+#define HGF_CASE(K)                                                                                  \
+  case K:                                                                                            \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS>, 256, lds_bytes);   \
+    break;
+    HGF_NS_CASES(HGF_CASE)
+#undef HGF_CASE
+    default: break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+int tiled_max_slow_axes() { return kMaxSlow; }
+
+int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes) {
+  int nb = 0;
+  if (precision == HGF_FP64) {
+    switch (nfast) {
+      case 1: nb = occ_nf<double2, 1>(nslow, lds_bytes); break;
+      case 2: nb = occ_nf<double2, 2>(nslow, lds_bytes); break;
+      case 3: nb = occ_nf<double2, 3>(nslow, lds_bytes); break;
+      default: nb = occ_nf<double2, 4>(nslow, lds_bytes); break;
+    }
+  } else {
+    switch (nfast) {
+      case 1: nb = occ_nf<float2, 1>(nslow, lds_bytes); break;
+      case 2: nb = occ_nf<float2, 2>(nslow, lds_bytes); break;
+      case 3: nb = occ_nf<float2, 3>(nslow, lds_bytes); break;
+      default: nb = occ_nf<float2, 4>(nslow, lds_bytes); break;
+    }
+  }
+  return nb < 1 ? 1 : nb;
+}
+
+void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st) {
+  if (g.blocks > 0) {
+    if (precision == HGF_FP64)
+      tiled_dispatch<double2>(g, stage, in, x1, y, yf, out, h, flag, st);
+    else
+      tiled_dispatch<float2>(g, stage, in, x1, y, yf, out, h, flag, st);
+    return;
+  }
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   dim3 gr(ls.blocks), bl(ls.threads);
   if (precision == HGF_FP64)
-    hipLaunchKernelGGL((k_rk4_stage<double2, double>), gr, bl, 0, st, g, sd, stage, in, (const double2*)x1,
-                       (double2*)y, (double2*)out, h, flag);
+    hipLaunchKernelGGL((k_rk4_stage<double2, double>), gr, bl, 0, st, g, sd, stage, (const double2*)in,
+                       (const double2*)x1, (double2*)y, (double2*)yf, (double2*)out, h, flag);
   else
-    hipLaunchKernelGGL((k_rk4_stage<float2, float>), gr, bl, 0, st, g, sd, stage, in, (const float2*)x1,
-                       (double2*)y, (float2*)out, h, flag);
+    hipLaunchKernelGGL((k_rk4_stage<float2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
+                       (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
+}
+
+void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st) {
+  if (precision == HGF_FP64 || !yf) return;
+  int blocks = (int)std::min<int64_t>((g.points + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((k_shadow<float2>), dim3(blocks), dim3(256), 0, st, (const double2*)y, (float2*)yf, g.points);
 }
 
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,

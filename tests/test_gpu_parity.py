@@ -324,3 +324,30 @@ def test_gradient_matches_oracle_sensitivities(hgf):
         val, g = hgf.grad(S, st, T, dt, sparse=_sparse_from_dense(cutoff, M), checkpoint_every=ce)
         assert rel(val, ref_val) < FP64_TOL
         assert np.max(np.abs(g - ref_grad)) / np.max(np.abs(ref_grad)) < 1e-9
+
+
+# ----------------------------------------------------------------- kernel variants
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("cutoff,seed", [((4, 5, 3, 6, 2), 21), ((9, 3, 7), 22), ((2, 3, 2, 4, 3, 2), 23)])
+def test_tiled_and_generic_stage_kernels_agree(hgf, monkeypatch, cutoff, seed, precision):
+    """The LDS-tiled stage kernel and the generic grid-stride kernel compute
+    the same RK4 steps (to rounding) on several axis splits, and both match
+    the oracle."""
+    announce(f"tiled vs generic cutoff={cutoff} {precision}")
+    s = synth.random_system(cutoff, seed, scale=3.0)
+    rng = np.random.default_rng(seed)
+    # upper bidiagonal factors: sectors d_j in {0, +1}, 2^N functions
+    fac = [np.triu(np.tril(rng.normal(size=(c, c)) + 1j * rng.normal(size=(c, c)), 1)) for c in cutoff]
+    S = hgf.define_system(s)
+    T, dt = 0.02, 1e-3
+    ops = {}
+    for kind in ("generic", "tiled"):
+        monkeypatch.setenv("HGF_STAGE_KERNEL", kind)
+        ops[kind] = hgf.map_operator(S, factors=fac, precision=precision)
+        hgf.evolve(ops[kind], T, dt)
+    monkeypatch.delenv("HGF_STAGE_KERNEL")
+    a, b = gpu_grids(ops["generic"]), gpu_grids(ops["tiled"])
+    assert max_rel_err(b, a) < (1e-13 if precision == "fp64" else 1e-6)
+    ref = oracle_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    assert max_rel_err(b, ref) < (FP64_TOL if precision == "fp64" else MIXED_TOL)
