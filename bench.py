@@ -31,15 +31,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point RK stage updates/s + % HBM peak; time-to-1e-5 vs FP64 plain"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per grid point of one stage launch, averaged over the
-# four stages of one step (stage grids complex64, state complex128):
-#   stage 1: read y (16) + write X1 (8)            = 24
-#   stage 2: read X1 (8) + write V1 (8)            = 16
-#   stage 3: read V1, X1 (16) + write V2 (8)       = 24
-#   stage 4: read V2, X1 (16) + read/write y (32)  = 48     -> 112 / 4 = 28
-BYTES_PER_POINT_STAGE = {"mixed": 28.0, "fp64": 44.0}
-STAGE_KERNEL = "k_rk4_stage"
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_05526_amd", "csrc", "hgf_kernels.hip")
+# Algorithmic HBM bytes per grid point of one stage launch, averaged over the
+# four stages of one RK4 step.  With s = size of a stage-grid element and
+# w = size of a state element (y), the stages move
+#   stage 1: read yf (s) + write X1 (s)                        = 2s
+#   stage 2: read X1 (s) + write V1 (s)                        = 2s
+#   stage 3: read V1, X1 (2s) + write V2 (s)                   = 3s
+#   stage 4: read V2, X1 (2s) + read/write y (2w) + write yf (s) = 3s + 2w
+# in mixed precision (yf is the stage-1 stencil input, a copy of y in the
+# stage precision); in FP64 the stencil input of stage 1 is y itself and
+# there is no yf:  stage 1 = 2s, stage 4 = 2s + 2w.
+#   complex64 stages, complex128 state (mixed):  s = 8,  w = 16 -> 112 / 4 = 28
+#   real float stages, real double state (mixed): s = 4, w = 8  ->  56 / 4 = 14
+#   complex128 (fp64): s = w = 16 -> 176 / 4 = 44;   real double (fp64): 22
+def bytes_per_point_stage(precision: str, real: bool) -> float:
+    s = (4 if precision == "mixed" else 8) * (1 if real else 2)
+    w = 8 * (1 if real else 2)
+    if precision == "mixed":
+        return (2 * s + 2 * s + 3 * s + 3 * s + 2 * w) / 4.0
+    return (2 * s + 2 * s + 3 * s + 2 * s + 2 * w) / 4.0
+STAGE_KERNEL = "k_rk4_tiled"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_05526_amd", "csrc", "hgf_tiled.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_10mode_mixed_traffic.json")
 
 
@@ -112,6 +124,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -125,12 +139,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     hgf.load_library()
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 copies of 1 GiB")
+        del a, b
     w = synth.large_c4()
     pts = int(np.prod(w.system.cutoff))
     S = hgf.define_system(w.system)
 
     def run(precision, steps, warmup):
         op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        real = op.info()["real_functions"] == 1
         if warmup:
             hgf.evolve(op, warmup * w.dt, w.dt)
         torch.cuda.synchronize()
@@ -144,13 +167,13 @@ def main():
         el = time.perf_counter() - t0
         launch_s = start.elapsed_time(end) * 1e-3 / (4 * steps)
         del op
-        return el, launch_s, J
+        return el, launch_s, J, real
 
     log(f"timing {args.steps} steps ({args.precision}) over {pts} points")
-    el, launch_s, J = run(args.precision, args.steps, args.warmup)
+    el, launch_s, J, real = run(args.precision, args.steps, args.warmup)
     log(f"done: {el:.3f} s, stage launch {launch_s * 1e6:.1f} us")
     value = pts * 4 * args.steps / el
-    bytes_launch = BYTES_PER_POINT_STAGE[args.precision] * pts
+    bytes_launch = bytes_per_point_stage(args.precision, real) * pts
     achieved = bytes_launch / launch_s / 1e9
     traffic = stored_traffic()
     line = {
@@ -164,11 +187,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64/f32 stencil, c128/f64 state" if args.precision == "mixed" else "c128/f64",
+        "dtype": ({"mixed": "f32 stencil, f64 state", "fp64": "f64"}[args.precision]
+                  + (" (real grids: real generator and data on the diagonal sector)" if real else " (complex)")),
         "data": "synthetic (seeded parameters, no dataset)",
         "config": {"workload": "10 Kerr modes, cutoff 6 (6^10 grid points), parity-weighted projector, "
                                "dt = 0.05 ns, merged layout",
-                   "precision": args.precision, "grid_points": pts, "seed": 4},
+                   "precision": args.precision, "grid_points": pts, "seed": 4, "real_grids": real},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": STAGE_KERNEL, "avg_launch_us": launch_s * 1e6,
@@ -177,10 +201,11 @@ def main():
     }
     if not args.no_extras:
         log("fp64 comparison")
-        el64, launch64, J64 = run("fp64", max(10, args.steps // 4), 2)
         n64 = max(10, args.steps // 4)
-        line["fp64_plain"] = {"value": pts * 4 * n64 / el64, "steps": n64,
-                              "achieved_GBs": BYTES_PER_POINT_STAGE["fp64"] * pts / launch64 / 1e9}
+        el64, launch64, J64, real64 = run("fp64", n64, 2)
+        line["fp64_plain"] = {"value": pts * 4 * n64 / el64, "steps": n64, "real_grids": real64,
+                              "achieved_GBs": bytes_per_point_stage("fp64", real64) * pts / launch64 / 1e9,
+                              "rel_diff_vs_mixed": abs(J64 - J) / abs(J64)}
         log("time-to-1e-5 on the 3-mode workload")
         line["time_to_1e-5"] = time_to_tolerance(hgf, torch)
     if not args.no_cpu_baseline:

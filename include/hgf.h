@@ -202,6 +202,7 @@ typedef struct {
   double time_us;         /* t reached so far */
   int64_t fp32_underflow; /* MIXED: nonzero initial coefficients below FP32's normal range */
   int32_t error_state;    /* nonzero after HGF_ENONFINITE */
+  int32_t real_functions; /* functions held as real grids (real generator and data) */
 } hgf_operator_info;
 
 hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);

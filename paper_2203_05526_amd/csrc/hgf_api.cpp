@@ -130,27 +130,30 @@ static void check_stability(const std::vector<Function>& fns, double dt) {
 // number `nfast` <= 4 of trailing axes whose padded tile and tables fit in
 // 64 KB of LDS (nfast_req > 0 forces a value when it fits).  Sets
 // g.blocks = 0 (generic kernel) when HGF_STAGE_KERNEL=generic.
-static void configure_tiles(GridArgs& g, int precision, int nfast_req) {
+static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real) {
   g.blocks = 0;
   g.nfast = 0;
+  g.real = 0;
   const char* env = std::getenv("HGF_STAGE_KERNEL");
   if (env && std::string(env) == "generic") return;
-  const int ts = precision == HGF_FP64 ? 16 : 8, rs = precision == HGF_FP64 ? 8 : 4;
+  const int rs = precision == HGF_FP64 ? 8 : 4, ts = real ? rs : 2 * rs;
   int best = 0;
   for (int F = std::min(4, g.n); F >= 1; --F) {
     if (nfast_req > 0 && F != nfast_req) continue;
     if (g.n - F > tiled_max_slow_axes()) continue;
+    // padded LDS tile: (e_0 + 2) x prod_{q>=1} (e_q + 1), see k_rk4_tiled
     int64_t T = 1, padded = 1, esum = 0;
     int emax = 0;
     for (int q = 0; q < F; ++q) {
       const int e = g.ext[g.n - F + q];
       T *= e;
-      padded *= e + 2;
+      padded *= (q == 0) ? e + 2 : e + 1;
       esum += e;
       emax = std::max(emax, e);
     }
     const int cbits = F == 4 ? 4 : 5;
     if (emax > (1 << cbits) || padded >= 65536) continue;
+    if (T > tiled_max_tile_points()) continue;
     const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + esum * rs + 64;
     if (bytes > 65536) continue;
     best = F;
@@ -162,21 +165,74 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req) {
     int64_t pst = 1;
     for (int q = F - 1; q >= 0; --q) {
       g.pstride[q] = (int)pst;
-      pst *= g.ext[g.n - F + q] + 2;
+      pst *= g.ext[g.n - F + q] + 1;
     }
     break;
   }
   if (best == 0) return;
   g.ntiles = g.points / g.tile_points;
+  // 32-bit byte offsets in the tiled kernel (complex128 y is the widest operand)
+  if (g.ntiles >= (int64_t)1 << 31 || g.points * 16 > (int64_t)0xffffffffLL) {
+    g.blocks = 0;
+    g.nfast = 0;
+    return;
+  }
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, precision, g.lds_bytes);
+  g.real = real ? 1 : 0;
+  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, precision, g.lds_bytes, real);
   const int64_t want = (int64_t)cus * occ;
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
 }
 
-static void fill_grid_args(Function& f, int precision) {
+// Per-tile records of the slow-axis terms for k_rk4_tiled (layout of
+// TileRec<NS, R>): lam_slow (R re, im), 2*NS int32 element offsets, 2*NS R
+// coefficients; the record size is padded to a multiple of 16 bytes.
+template <typename R>
+static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) {
+  const int ns = g.n - g.nfast, nd = 2 * std::max(ns, 1);
+  size_t bytes = 2 * sizeof(R) + nd * sizeof(int32_t);
+  bytes = (bytes + sizeof(R) - 1) / sizeof(R) * sizeof(R);
+  const size_t coef_at = bytes;
+  bytes += nd * sizeof(R);
+  std::vector<char> out(bytes * g.ntiles, 0);
+  for (int64_t tt = 0; tt < g.ntiles; ++tt) {
+    char* r = out.data() + bytes * tt;
+    int64_t rem = tt;
+    cd lam = t.lam0;
+    std::vector<int32_t> off(nd, 0);
+    std::vector<R> coef(nd, 0);
+    for (int j = ns - 1; j >= 0; --j) {
+      const int sj = (int)(rem % t.ext[j]);
+      rem /= t.ext[j];
+      lam += t.lam[j][sj];
+      if (sj >= 1) {
+        off[2 * j] = -(int32_t)g.stride[j];
+        coef[2 * j] = (R)t.alpha[j];
+      }
+      if (sj + 1 < t.ext[j]) {
+        off[2 * j + 1] = (int32_t)g.stride[j];
+        coef[2 * j + 1] = (R)t.beta[j][sj];
+      }
+    }
+    R lr = (R)lam.real(), li = (R)lam.imag();
+    std::memcpy(r, &lr, sizeof(R));
+    std::memcpy(r + sizeof(R), &li, sizeof(R));
+    std::memcpy(r + 2 * sizeof(R), off.data(), nd * sizeof(int32_t));
+    std::memcpy(r + coef_at, coef.data(), nd * sizeof(R));
+  }
+  return out;
+}
+
+static void build_tile_records(Function& f, int precision) {
+  std::vector<char> rec = precision == HGF_FP64 ? tile_records<double>(f.ga, f.tab) : tile_records<float>(f.ga, f.tab);
+  f.ttab = dmalloc(rec.size());
+  hip_check(hipMemcpy(f.ttab, rec.data(), rec.size(), hipMemcpyHostToDevice), "upload tile records");
+  f.ga.tiles = f.ttab;
+}
+
+static void fill_grid_args(Function& f, int precision, bool want_real) {
   GridArgs& g = f.ga;
   std::memset(&g, 0, sizeof(g));
   const SectorTables& t = f.tab;
@@ -199,7 +255,8 @@ static void fill_grid_args(Function& f, int precision) {
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
-  configure_tiles(g, precision, -1);
+  configure_tiles(g, precision, -1, want_real);
+  f.real = g.real != 0;
   // device tables: lam (double2), beta (double), lam_f (float2), beta_f (float)
   const int tot = off;
   std::vector<double> lam(2 * tot), beta(tot);
@@ -228,18 +285,22 @@ static void fill_grid_args(Function& f, int precision) {
   g.beta = (const double*)(base + b_lam);
   g.lam_f = (const float2*)(base + b_lam + b_beta);
   g.beta_f = (const float*)(base + b_lam + b_beta + b_lamf);
-  (void)precision;
+  g.tiles = nullptr;
+  if (g.blocks > 0) build_tile_records(f, precision);
 }
+
+static size_t state_bytes(const Function& f) { return f.ga.points * (f.real ? sizeof(double) : sizeof(double2)); }
 
 static void alloc_function_buffers(Function& f, int precision) {
   const int64_t P = f.ga.points;
-  const size_t cs = precision == HGF_FP64 ? sizeof(double2) : sizeof(float2);
-  f.y = dmalloc(P * sizeof(double2));
+  const size_t rs = precision == HGF_FP64 ? sizeof(double) : sizeof(float);
+  const size_t cs = f.real ? rs : 2 * rs;
+  f.y = dmalloc(state_bytes(f));
   f.s1 = dmalloc(P * cs);
   f.s2 = dmalloc(P * cs);
   f.s3 = dmalloc(P * cs);
   if (f.split) f.s4 = dmalloc(P * sizeof(double2));
-  if (precision == HGF_MIXED) f.yf = dmalloc(P * sizeof(float2));
+  if (precision == HGF_MIXED) f.yf = dmalloc(P * (f.real ? sizeof(float) : sizeof(float2)));
 }
 
 static void free_function(Function& f) {
@@ -251,6 +312,7 @@ static void free_function(Function& f) {
   dfree(f.ybak);
   dfree(f.yf);
   dfree(f.dtab);
+  dfree(f.ttab);
 }
 
 static int64_t flat_index(const SectorTables& t, const int* m) {
@@ -435,7 +497,13 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
 
 static void upload_state(Function& f, const std::vector<cd>& grid, int precision) {
   static_assert(sizeof(cd) == sizeof(double2), "layout");
-  hip_check(hipMemcpy(f.y, grid.data(), grid.size() * sizeof(double2), hipMemcpyHostToDevice), "upload state");
+  if (f.real) {
+    std::vector<double> r(grid.size());
+    for (size_t i = 0; i < grid.size(); ++i) r[i] = grid[i].real();
+    hip_check(hipMemcpy(f.y, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice), "upload state");
+  } else {
+    hip_check(hipMemcpy(f.y, grid.data(), grid.size() * sizeof(double2), hipMemcpyHostToDevice), "upload state");
+  }
   launch_shadow(precision, f.ga, f.y, f.yf, nullptr);
   hip_check(hipGetLastError(), "shadow copy");
 }
@@ -503,7 +571,7 @@ static void setup_split(Function& f, const System& s, const Coeff& c) {
   }
 }
 
-static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
+static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d, bool allow_real = true) {
   std::map<std::vector<int>, std::vector<cd>> merged;
   std::vector<Coeff> coeffs;
   const bool split = op->layout == HGF_SPLIT;
@@ -521,7 +589,18 @@ static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
       op->fn.emplace_back();
       Function& f = op->fn.back();
       f.tab = sector_tables(op->sys, kv.first.data());
-      fill_grid_args(f, op->precision);
+      bool real = allow_real;
+      if (real) {
+        const char* env = std::getenv("HGF_REAL_GRIDS");
+        if (env && std::string(env) == "0") real = false;
+      }
+      if (f.tab.lam0.imag() != 0.0) real = false;
+      for (int j = 0; j < f.tab.n && real; ++j)
+        for (const cd& l : f.tab.lam[j])
+          if (l.imag() != 0.0) real = false;
+      for (const cd& v : kv.second)
+        if (v.imag() != 0.0) real = false;
+      fill_grid_args(f, op->precision, real);
       alloc_function_buffers(f, op->precision);
       upload_state(f, kv.second, op->precision);
     }
@@ -535,7 +614,7 @@ static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d) {
       Function& f = op->fn.back();
       f.split = true;
       f.tab = sector_tables(op->sys, dv);
-      fill_grid_args(f, op->precision);
+      fill_grid_args(f, op->precision, false);
       alloc_function_buffers(f, op->precision);
       std::vector<cd> zero(f.ga.points, 0.0);
       upload_state(f, zero, op->precision);
@@ -635,7 +714,7 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   check_stability(op->fn, h);
   // keep a copy of the states for recovery after a non-finite result
   for (auto& f : op->fn) {
-    const size_t bytes = f.ga.points * sizeof(double2);
+    const size_t bytes = state_bytes(f);
     if (!f.ybak) f.ybak = dmalloc(bytes);
     hip_check(hipMemcpyAsync(f.ybak, f.y, bytes, hipMemcpyDeviceToDevice, st), "backup");
   }
@@ -662,7 +741,7 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   hip_check(hipGetLastError(), "kernel launch");
   if (read_flag(op, st)) {
     for (size_t i = 0; i < op->fn.size(); ++i) {
-      const size_t bytes = op->fn[i].ga.points * sizeof(double2);
+      const size_t bytes = state_bytes(op->fn[i]);
       hip_check(hipMemcpyAsync(op->fn[i].y, op->fn[i].ybak, bytes, hipMemcpyDeviceToDevice, st), "restore");
       launch_shadow(op->precision, op->fn[i].ga, op->fn[i].y, op->fn[i].yf, st);
       op->fn[i].cx = cx0[i];
@@ -767,7 +846,7 @@ static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStr
   hip_check(hipMemcpyAsync(dcoef.p, coef.data(), nf * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
   for (int i = 0; i < nf; ++i)
     launch_expect_partial(op->fn[i].ga, op->fn[i].y, true, dw.as<double2>() + woff[i],
-                          dpart.as<double2>() + start[i], st);
+                          dpart.as<double2>() + start[i], st, op->fn[i].real);
   launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), nf,
                       make_double2(analytic.real(), analytic.imag()), dout.as<double2>(), st);
   hip_check(hipGetLastError(), "kernel launch");
@@ -800,7 +879,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     }
   } guard{op};
   op.dflag = (int*)dmalloc(sizeof(int));
-  build_functions(&op, &d2);
+  build_functions(&op, &d2, false);
   check_stability(op.fn, dt);
   const auto amps = all_amps(sys, psi);
   const int P = num_params(sys.n);
@@ -1057,6 +1136,9 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
     info->time_us = op->time_us;
     info->fp32_underflow = op->underflow;
     info->error_state = op->error_state;
+    int nreal = 0;
+    for (auto& f : op->fn) nreal += f.real ? 1 : 0;
+    info->real_functions = nreal;
   });
 }
 
@@ -1074,10 +1156,22 @@ hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int
     if (grid) {
       if (n_points < f.ga.points) fail(HGF_EINVAL, "grid buffer too small");
       hip_check(hipSetDevice(op->device), "hipSetDevice");
-      hip_check(hipMemcpyAsync(grid, f.y, f.ga.points * sizeof(double2), hipMemcpyDeviceToHost,
-                               (hipStream_t)hip_stream),
-                "download");
-      hip_check(hipStreamSynchronize((hipStream_t)hip_stream), "synchronize");
+      if (f.real) {
+        std::vector<double> r(f.ga.points);
+        hip_check(hipMemcpyAsync(r.data(), f.y, f.ga.points * sizeof(double), hipMemcpyDeviceToHost,
+                                 (hipStream_t)hip_stream),
+                  "download");
+        hip_check(hipStreamSynchronize((hipStream_t)hip_stream), "synchronize");
+        for (int64_t i = 0; i < f.ga.points; ++i) {
+          grid[2 * i] = r[i];
+          grid[2 * i + 1] = 0.0;
+        }
+      } else {
+        hip_check(hipMemcpyAsync(grid, f.y, f.ga.points * sizeof(double2), hipMemcpyDeviceToHost,
+                                 (hipStream_t)hip_stream),
+                  "download");
+        hip_check(hipStreamSynchronize((hipStream_t)hip_stream), "synchronize");
+      }
     }
     if (split_out) {
       std::vector<double> o(4 * n + 6, 0.0);

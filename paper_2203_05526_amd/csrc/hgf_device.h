@@ -1,0 +1,103 @@
+// Device-side helpers shared by the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hgf {
+
+// Value traits of grid element types: complex (float2, double2) or real
+// (float, double).  A real grid holds a sector whose generator and data are
+// real (the imaginary part stays identically zero).
+template <typename TS>
+struct Real;
+template <>
+struct Real<float2> {
+  using T = float;
+  static constexpr bool cplx = true;
+};
+template <>
+struct Real<double2> {
+  using T = double;
+  static constexpr bool cplx = true;
+};
+template <>
+struct Real<float> {
+  using T = float;
+  static constexpr bool cplx = false;
+};
+template <>
+struct Real<double> {
+  using T = double;
+  static constexpr bool cplx = false;
+};
+
+__device__ __forceinline__ float re_(float2 v) { return v.x; }
+__device__ __forceinline__ float im_(float2 v) { return v.y; }
+__device__ __forceinline__ double re_(double2 v) { return v.x; }
+__device__ __forceinline__ double im_(double2 v) { return v.y; }
+__device__ __forceinline__ float re_(float v) { return v; }
+__device__ __forceinline__ float im_(float) { return 0.0f; }
+__device__ __forceinline__ double re_(double v) { return v; }
+__device__ __forceinline__ double im_(double) { return 0.0; }
+template <typename T>
+__device__ __forceinline__ T mk_(typename Real<T>::T r, typename Real<T>::T i);
+template <>
+__device__ __forceinline__ float2 mk_<float2>(float r, float i) { return make_float2(r, i); }
+template <>
+__device__ __forceinline__ double2 mk_<double2>(double r, double i) { return make_double2(r, i); }
+template <>
+__device__ __forceinline__ float mk_<float>(float r, float) { return r; }
+template <>
+__device__ __forceinline__ double mk_<double>(double r, double) { return r; }
+
+typedef float hgf_v2f __attribute__((ext_vector_type(2)));
+typedef double hgf_v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 nt_load(const float2* p) {
+  const hgf_v2f v = __builtin_nontemporal_load((const hgf_v2f*)p);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+  const hgf_v2d v = __builtin_nontemporal_load((const hgf_v2d*)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float nt_load(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double nt_load(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void nt_store(float2* p, float2 a) {
+  hgf_v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (hgf_v2f*)p);
+}
+__device__ __forceinline__ void nt_store(double2* p, double2 a) {
+  hgf_v2d v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (hgf_v2d*)p);
+}
+__device__ __forceinline__ void nt_store(float* p, float a) { __builtin_nontemporal_store(a, p); }
+__device__ __forceinline__ void nt_store(double* p, double a) { __builtin_nontemporal_store(a, p); }
+
+// Element access by a 32-bit element index from a base pointer, written so
+// that the compiler uses the scalar-base + 32-bit vector-offset addressing
+// form of global memory instructions.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t idx) {
+  return *(const T*)((const char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T ldg_nt(const T* base, uint32_t idx) {
+  return nt_load((const T*)((const char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, uint32_t idx, T v) {
+  *(T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+}
+template <typename T>
+__device__ __forceinline__ void stg_nt(T* base, uint32_t idx, T v) {
+  nt_store((T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))), v);
+}
+
+}  // namespace hgf

@@ -14,6 +14,9 @@ namespace hgf {
 
 constexpr int kMaxModes = HGF_MAX_MODES;
 constexpr int kMaxCutoff = HGF_MAX_CUTOFF;
+// Points of a tile handled by one thread of the tiled stage kernel:
+// tile points <= kTileRounds * 256.
+constexpr int kTileRounds = 8;
 
 using cd = std::complex<double>;
 
@@ -85,7 +88,9 @@ struct GridArgs {
   int lds_elems;            // padded tile size in elements
   int cbits;                // bits per packed fast coordinate
   int blocks;               // persistent grid size (0: generic kernel)
+  int real;                 // tiled kernel on a real grid (real generator and data)
   int lds_bytes;            // dynamic LDS of the tiled kernel
+  const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
   double lam0_re, lam0_im;
   double alpha[kMaxModes];
   const double2* lam;       // concatenated lam_j(m)
@@ -107,8 +112,10 @@ struct Function {
   void* s4 = nullptr;  // classical (split) form only: RK accumulator, complex128
   void* yf = nullptr;  // mixed precision: complex64 copy of y, the stencil input of stage 1
   void* dtab = nullptr;  // device tables
+  void* ttab = nullptr;  // per-tile records of the tiled stage kernel
   // split mode
   bool split = false;
+  bool real = false;  // real generator and data: real grids, half the bytes
   int p[kMaxModes] = {}, q[kMaxModes] = {};
   int64_t mono_index = 0;  // flat index of (p, q) in the grid
   cd g0 = 0.0, cx = 1.0, cy = 1.0;

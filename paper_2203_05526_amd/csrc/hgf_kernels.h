@@ -33,13 +33,14 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
-int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes);
+int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes, bool real);
 int tiled_max_slow_axes();
+int tiled_max_tile_points();
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
                       double h, const PointSources& src, int* flag, hipStream_t st);
 int expect_blocks(const GridArgs& g);
 void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, const double2* wtab,
-                           double2* partial, hipStream_t st);
+                           double2* partial, hipStream_t st, bool real = false);
 void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
                          double2 analytic, double2* out, hipStream_t st);
 void launch_adjoint(int stage, const GridArgs& g, const double2* in, const double2* fwd, const double2* mu,

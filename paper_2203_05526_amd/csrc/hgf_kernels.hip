@@ -9,6 +9,7 @@
 // with lam(m) = lam0 + sum_j lam_j(m_j).
 #include <hip/hip_runtime.h>
 
+#include "hgf_device.h"
 #include "hgf_internal.h"
 #include "hgf_kernels.h"
 
@@ -250,193 +251,11 @@ __global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, 
 // the grid.  Streaming operands (x1, y, outputs) use non-temporal loads and
 // stores so that they do not evict the stencil input from the caches.
 
-template <typename TS>
-struct Real;
-template <>
-struct Real<float2> {
-  using T = float;
-  typedef float v2 __attribute__((ext_vector_type(2)));
-};
-template <>
-struct Real<double2> {
-  using T = double;
-  typedef double v2 __attribute__((ext_vector_type(2)));
-};
 
-template <typename TS>
-__device__ __forceinline__ TS nt_load(const TS* p) {
-  using V = typename Real<TS>::v2;
-  const V v = __builtin_nontemporal_load((const V*)p);
-  TS o;
-  o.x = v.x;
-  o.y = v.y;
-  return o;
-}
-template <typename TS>
-__device__ __forceinline__ void nt_store(TS* p, TS a) {
-  using V = typename Real<TS>::v2;
-  V v;
-  v.x = a.x;
-  v.y = a.y;
-  __builtin_nontemporal_store(v, (V*)p);
-}
-
-template <int NF, int NS, typename TS>
-__global__ __launch_bounds__(256) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
-                                                   const TS* __restrict__ x1, double2* __restrict__ y,
-                                                   TS* __restrict__ yf, TS* __restrict__ out, double h,
-                                                   int* __restrict__ flag) {
-  using R = typename Real<TS>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int T = (int)g.tile_points;
-  const int nt = blockDim.x, tid = threadIdx.x;
-  TS* tile = (TS*)smem;
-  TS* lamf = tile + g.lds_elems;
-  uint32_t* info = (uint32_t*)(lamf + T);
-  R* btab = (R*)(info + ((T + 1) & ~1));
-  const double2* lamt = g.lam;
-  const double* betat = g.beta;
-
-  // ---- once per workgroup: zero halo, per-position tables
-  for (int i = tid; i < g.lds_elems; i += nt) {
-    tile[i].x = 0;
-    tile[i].y = 0;
-  }
-  const uint32_t cmask = (1u << g.cbits) - 1u;
-  for (int p = tid; p < T; p += nt) {
-    int rem = p;
-    uint32_t off = 0, coords = 0;
-    double lr = 0.0, li = 0.0;
-#pragma unroll
-    for (int q = NF - 1; q >= 0; --q) {
-      const int j = NS + q;
-      const int e = g.ext[j];
-      const int c = rem % e;
-      rem /= e;
-      off += (uint32_t)(c + 1) * (uint32_t)g.pstride[q];
-      coords |= (uint32_t)c << (g.cbits * q);
-      const double2 lj = lamt[g.off[j] + c];
-      lr += lj.x;
-      li += lj.y;
-    }
-    info[p] = off | (coords << 16);
-    lamf[p].x = (R)lr;
-    lamf[p].y = (R)li;
-  }
-  int boff[NF];
-  {
-    int o = 0;
-#pragma unroll
-    for (int q = 0; q < NF; ++q) {
-      boff[q] = o;
-      const int j = NS + q;
-      for (int c = tid; c < g.ext[j]; c += nt) btab[o + c] = (R)betat[g.off[j] + c];
-      o += g.ext[j];
-    }
-  }
-  __syncthreads();
-
-  // ---- XCD-aware persistent walk over tiles
-  const int xcd = blockIdx.x & 7;
-  const int nwx = ((int)gridDim.x - xcd + 7) >> 3;
-  const int64_t lo = g.ntiles * xcd / 8, hi = g.ntiles * (xcd + 1) / 8;
-  int bad = 0;
-  for (int64_t t = lo + (blockIdx.x >> 3); t < hi; t += nwx) {
-    // slow-axis terms, uniform over the tile: an out-of-range direction
-    // reads the centre with a zero coefficient, so every load is issued
-    // unconditionally and the loads of a point overlap in flight
-    double lsr = g.lam0_re, lsi = g.lam0_im;
-    int64_t dno[NS > 0 ? NS : 1], upo[NS > 0 ? NS : 1];
-    R dnc[NS > 0 ? NS : 1], upc[NS > 0 ? NS : 1];
-    {
-      int64_t rem = t;
-#pragma unroll
-      for (int j = NS - 1; j >= 0; --j) {
-        const int e = g.ext[j];
-        const int sj = (int)(rem % e);
-        rem /= e;
-        const double2 lj = lamt[g.off[j] + sj];
-        lsr += lj.x;
-        lsi += lj.y;
-        const bool dv = sj >= 1, uv = sj + 1 < e;
-        dno[j] = dv ? -g.stride[j] : 0;
-        dnc[j] = dv ? (R)g.alpha[j] : (R)0;
-        upo[j] = uv ? g.stride[j] : 0;
-        upc[j] = uv ? (R)betat[g.off[j] + sj] : (R)0;
-      }
-    }
-    const int64_t tbase = t * (int64_t)T;
-    const TS* tin = in + tbase;
-    for (int p = tid; p < T; p += nt) tile[info[p] & 0xffffu] = tin[p];
-    __syncthreads();
-    for (int p = tid; p < T; p += nt) {
-      TS sv[2 * (NS > 0 ? NS : 1)];
-#pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        sv[2 * j] = tin[p + dno[j]];
-        sv[2 * j + 1] = tin[p + upo[j]];
-      }
-      const int64_t i = tbase + p;
-      TS xb;
-      double2 yv;
-      if (stage >= 2) xb = nt_load(x1 + i);
-      if (stage == 4) yv = nt_load(y + i);
-      const uint32_t inf = info[p];
-      const int lo_ = (int)(inf & 0xffffu);
-      const TS zc = tile[lo_];
-      const TS lf = lamf[p];
-      const R lr = (R)lsr + lf.x, li = (R)lsi + lf.y;
-      R ar = lr * zc.x - li * zc.y;
-      R ai = lr * zc.y + li * zc.x;
-#pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        const TS dn = tile[lo_ - g.pstride[q]];
-        const TS upv = tile[lo_ + g.pstride[q]];
-        const int c = (int)((inf >> (16 + g.cbits * q)) & cmask);
-        const R b = btab[boff[q] + c];
-        const R a = (R)g.alpha[NS + q];
-        ar += a * dn.x + b * upv.x;
-        ai += a * dn.y + b * upv.y;
-      }
-#pragma unroll
-      for (int j = 0; j < NS; ++j) {
-        ar += dnc[j] * sv[2 * j].x + upc[j] * sv[2 * j + 1].x;
-        ai += dnc[j] * sv[2 * j].y + upc[j] * sv[2 * j + 1].y;
-      }
-      if (stage == 1) {
-        TS o;
-        o.x = (R)(h * (double)ar);
-        o.y = (R)(h * (double)ai);
-        nt_store(out + i, o);
-      } else if (stage == 2 || stage == 3) {
-        const R c = (R)(stage == 2 ? 0.25 * h : h / 3.0);
-        TS o;
-        o.x = xb.x + c * ar;
-        o.y = xb.y + c * ai;
-        nt_store(out + i, o);
-      } else {
-        const double c = 0.5 * h;
-        yv.x += (double)xb.x + c * (double)ar;
-        yv.y += (double)xb.y + c * (double)ai;
-        bad |= !(isfinite(yv.x) && isfinite(yv.y));
-        nt_store(y + i, yv);
-        if (yf) {
-          TS f;
-          f.x = (R)yv.x;
-          f.y = (R)yv.y;
-          yf[i] = f;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (bad) atomicOr(flag, 1);
-}
-
-template <typename TS>
-__global__ void k_shadow(const double2* __restrict__ y, TS* __restrict__ yf, int64_t n) {
+template <typename TY, typename TS>
+__global__ void k_shadow(const TY* __restrict__ y, TS* __restrict__ yf, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    yf[i] = from_d2<TS>(y[i]);
+    yf[i] = mk_<TS>((typename Real<TS>::T)re_(y[i]), (typename Real<TS>::T)im_(y[i]));
 }
 
 // ------------------------------------------------------------ RK4, classical form
@@ -526,7 +345,7 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_partial(GridArgs g, Stri
 #pragma unroll
       for (int j = 0; j < kMaxModes; ++j)
         if (j < g.n) wt = cmul(wt, wtab[g.off[j] + w.c[j]]);
-      s = cadd(s, cmul(wt, to_d2(grid[w.i])));
+      s = cadd(s, cmul(wt, make_double2((double)re_(grid[w.i]), (double)im_(grid[w.i]))));
       walker_step(w, g, sd);
     }
   }
@@ -680,83 +499,38 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks) {
 
 static const int kStageBlocks = 4096;
 
-// Instantiations of the tiled kernel: NF fast axes (1..4) and NS slow axes
-// (0..12), i.e. every grid of up to 16 modes whose slow part has at most 12 axes.
-#define HGF_NS_CASES(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12)
+// Tiled kernel instantiations live in hgf_tiled_{c64,c128,r32,r64}.hip.
+void launch_tiled_c64(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
+void launch_tiled_c128(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
+void launch_tiled_r32(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
+void launch_tiled_r64(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
+int occupancy_tiled_c64(int, int, int);
+int occupancy_tiled_c128(int, int, int);
+int occupancy_tiled_r32(int, int, int);
+int occupancy_tiled_r64(int, int, int);
+
 constexpr int kMaxSlow = 12;
-
-template <typename TS, int NF>
-static void tiled_launch_nf(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
-                            void* out, double h, int* flag, hipStream_t st) {
-  const int ns = g.n - NF;
-  switch (ns) {
-#define HGF_CASE(K)                                                                                          \
-  case K:                                                                                                    \
-    hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS>), dim3(g.blocks), dim3(256), g.lds_bytes, st, g, stage,       \
-                       (const TS*)in, (const TS*)x1, (double2*)y, (TS*)yf, (TS*)out, h, flag);              \
-    break;
-    HGF_NS_CASES(HGF_CASE)
-#undef HGF_CASE
-    default: break;
-  }
-}
-
-template <typename TS>
-static void tiled_dispatch(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
-                           void* out, double h, int* flag, hipStream_t st) {
-  switch (g.nfast) {
-    case 1: tiled_launch_nf<TS, 1>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    case 2: tiled_launch_nf<TS, 2>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    case 3: tiled_launch_nf<TS, 3>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    default: tiled_launch_nf<TS, 4>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-  }
-}
-
-template <typename TS, int NF>
-static int occ_nf(int ns, int lds_bytes) {
-  int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
-  switch (ns) {
-#define HGF_CASE(K)                                                                                  \
-  case K:                                                                                            \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS>, 256, lds_bytes);   \
-    break;
-    HGF_NS_CASES(HGF_CASE)
-#undef HGF_CASE
-    default: break;
-  }
-  return e == hipSuccess ? nb : 0;
-}
-
 int tiled_max_slow_axes() { return kMaxSlow; }
+int tiled_max_tile_points() { return kTileRounds * 256; }
 
-int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes) {
-  int nb = 0;
-  if (precision == HGF_FP64) {
-    switch (nfast) {
-      case 1: nb = occ_nf<double2, 1>(nslow, lds_bytes); break;
-      case 2: nb = occ_nf<double2, 2>(nslow, lds_bytes); break;
-      case 3: nb = occ_nf<double2, 3>(nslow, lds_bytes); break;
-      default: nb = occ_nf<double2, 4>(nslow, lds_bytes); break;
-    }
-  } else {
-    switch (nfast) {
-      case 1: nb = occ_nf<float2, 1>(nslow, lds_bytes); break;
-      case 2: nb = occ_nf<float2, 2>(nslow, lds_bytes); break;
-      case 3: nb = occ_nf<float2, 3>(nslow, lds_bytes); break;
-      default: nb = occ_nf<float2, 4>(nslow, lds_bytes); break;
-    }
-  }
+int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes, bool real) {
+  int nb;
+  if (real)
+    nb = precision == HGF_FP64 ? occupancy_tiled_r64(nfast, nslow, lds_bytes)
+                               : occupancy_tiled_r32(nfast, nslow, lds_bytes);
+  else
+    nb = precision == HGF_FP64 ? occupancy_tiled_c128(nfast, nslow, lds_bytes)
+                               : occupancy_tiled_c64(nfast, nslow, lds_bytes);
   return nb < 1 ? 1 : nb;
 }
 
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st) {
   if (g.blocks > 0) {
-    if (precision == HGF_FP64)
-      tiled_dispatch<double2>(g, stage, in, x1, y, yf, out, h, flag, st);
+    if (g.real)
+      (precision == HGF_FP64 ? launch_tiled_r64 : launch_tiled_r32)(g, stage, in, x1, y, yf, out, h, flag, st);
     else
-      tiled_dispatch<float2>(g, stage, in, x1, y, yf, out, h, flag, st);
+      (precision == HGF_FP64 ? launch_tiled_c128 : launch_tiled_c64)(g, stage, in, x1, y, yf, out, h, flag, st);
     return;
   }
   const LaunchShape ls = shape_for(g, kStageBlocks);
@@ -774,7 +548,12 @@ void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hi
   if (precision == HGF_FP64 || !yf) return;
   int blocks = (int)std::min<int64_t>((g.points + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_shadow<float2>), dim3(blocks), dim3(256), 0, st, (const double2*)y, (float2*)yf, g.points);
+  if (g.real)
+    hipLaunchKernelGGL((k_shadow<double, float>), dim3(blocks), dim3(256), 0, st, (const double*)y, (float*)yf,
+                       g.points);
+  else
+    hipLaunchKernelGGL((k_shadow<double2, float2>), dim3(blocks), dim3(256), 0, st, (const double2*)y,
+                       (float2*)yf, g.points);
 }
 
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
@@ -807,10 +586,13 @@ void launch_classical(int stage, int precision, const GridArgs& g, const void* i
 int expect_blocks(const GridArgs& g) { return shape_for(g, 1024).blocks; }
 
 void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, const double2* wtab,
-                           double2* partial, hipStream_t st) {
+                           double2* partial, hipStream_t st, bool real) {
   const LaunchShape ls = shape_for(g, 1024);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
-  if (grid_fp64)
+  if (real)
+    hipLaunchKernelGGL((k_expect_partial<double>), dim3(ls.blocks), dim3(kRedThreads), 0, st, g, sd,
+                       (const double*)grid, wtab, partial);
+  else if (grid_fp64)
     hipLaunchKernelGGL((k_expect_partial<double2>), dim3(ls.blocks), dim3(kRedThreads), 0, st, g, sd,
                        (const double2*)grid, wtab, partial);
   else

@@ -1,0 +1,6 @@
+// Instantiations of the tiled RK4 stage kernel for double2 stage grids and a double2 state.
+#include "hgf_tiled.h"
+
+namespace hgf {
+HGF_TILED_INSTANTIATE(double2, double2, c128)
+}  // namespace hgf

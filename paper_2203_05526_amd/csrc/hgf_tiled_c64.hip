@@ -1,0 +1,6 @@
+// Instantiations of the tiled RK4 stage kernel for float2 stage grids and a double2 state.
+#include "hgf_tiled.h"
+
+namespace hgf {
+HGF_TILED_INSTANTIATE(float2, double2, c64)
+}  // namespace hgf

@@ -1,0 +1,6 @@
+// Instantiations of the tiled RK4 stage kernel for double stage grids and a double state.
+#include "hgf_tiled.h"
+
+namespace hgf {
+HGF_TILED_INSTANTIATE(double, double, r64)
+}  // namespace hgf

@@ -61,7 +61,7 @@ class _Info(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("n_modes", ctypes.c_int32),
                 ("total_points", ctypes.c_int64), ("steps_done", ctypes.c_int64),
                 ("time_us", ctypes.c_double), ("fp32_underflow", ctypes.c_int64),
-                ("error_state", ctypes.c_int32)]
+                ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32)]
 
 
 _lib = None

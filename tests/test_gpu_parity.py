@@ -351,3 +351,33 @@ def test_tiled_and_generic_stage_kernels_agree(hgf, monkeypatch, cutoff, seed, p
     assert max_rel_err(b, a) < (1e-13 if precision == "fp64" else 1e-6)
     ref = oracle_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
     assert max_rel_err(b, ref) < (FP64_TOL if precision == "fp64" else MIXED_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_real_grids_on_diagonal_sector(hgf, monkeypatch, precision):
+    """On the diagonal sector the generator is real; a real observable is held
+    as a real grid (half the bytes).  Real and complex storage agree and match
+    the oracle."""
+    cutoff = (5, 6, 4, 7)
+    announce(f"real grids {precision}")
+    s, bits, alpha = synth.seeded_system(cutoff, 31, n_th=0.2)
+    s.gamma1 *= 30.0
+    fac = synth.parity_factors(cutoff)
+    S = hgf.define_system(s)
+    T, dt = 0.05, 1e-4
+    ops = {}
+    for kind in ("0", "1"):
+        monkeypatch.setenv("HGF_REAL_GRIDS", kind)
+        ops[kind] = hgf.map_operator(S, factors=fac, precision=precision)
+        hgf.evolve(ops[kind], T, dt)
+    monkeypatch.delenv("HGF_REAL_GRIDS")
+    assert ops["1"].info()["real_functions"] == 1
+    assert ops["0"].info()["real_functions"] == 0
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    ref = oracle_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    assert max_rel_err(gpu_grids(ops["1"]), ref) < tol
+    assert max_rel_err(gpu_grids(ops["1"]), gpu_grids(ops["0"])) < (1e-13 if precision == "fp64" else 1e-6)
+    st = synth.coherent_state(alpha)
+    assert rel(hgf.expectation(ops["1"], st), oracle.expectation(cutoff, ops_ref := oracle.evolve(
+        s, oracle.product_sectors(fac), T, dt), st)) < tol
+    del ops_ref
