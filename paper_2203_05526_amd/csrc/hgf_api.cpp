@@ -153,11 +153,21 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
     }
     const int cbits = F == 4 ? 4 : 5;
     if (emax > (1 << cbits) || padded >= 65536) continue;
-    if (T > tiled_max_tile_points()) continue;
+    // one point per lane; the workgroup is sized so that a tile takes at most
+    // kTileRounds rounds of lanes (the kernel's prefetch registers)
+    if (T > tiled_max_lane_groups()) continue;
+    // 256 lanes when they cover the tile in at most kTileRounds rounds (the
+    // fastest shape measured on the 6^10 grid), else the smallest multiple
+    // of 64 that does
+    int threads = T >= 256 ? 256 : (int)((T + 63) / 64 * 64);
+    if ((T + threads - 1) / threads > kTileRounds)
+      threads = (int)std::min<int64_t>(512, ((T + kTileRounds - 1) / kTileRounds + 63) / 64 * 64);
+    if ((T + threads - 1) / threads > kTileRounds) continue;
     const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + esum * rs + 64;
     if (bytes > 65536) continue;
     best = F;
     g.nfast = F;
+    g.threads = threads;
     g.cbits = cbits;
     g.tile_points = T;
     g.lds_elems = (int)padded;
@@ -180,7 +190,7 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   g.real = real ? 1 : 0;
-  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, precision, g.lds_bytes, real);
+  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, g.threads, precision, g.lds_bytes, real);
   const int64_t want = (int64_t)cus * occ;
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
@@ -188,7 +198,7 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
 
 // Per-tile records of the slow-axis terms for k_rk4_tiled (layout of
 // TileRec<NS, R>): lam_slow (R re, im), 2*NS int32 element offsets, 2*NS R
-// coefficients; the record size is padded to a multiple of 16 bytes.
+// coefficients, with the coefficient array aligned to sizeof(R).
 template <typename R>
 static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) {
   const int ns = g.n - g.nfast, nd = 2 * std::max(ns, 1);
@@ -739,7 +749,12 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
       for (auto& f : op->fn) split_step(op, f, h, st);
   }
   hip_check(hipGetLastError(), "kernel launch");
-  if (read_flag(op, st)) {
+  const int flag = read_flag(op, st);
+  if (flag & 2) {
+    op->error_state = 1;
+    fail(HGF_EDEVICE, "stage kernel launched outside its configuration contract");
+  }
+  if (flag) {
     for (size_t i = 0; i < op->fn.size(); ++i) {
       const size_t bytes = state_bytes(op->fn[i]);
       hip_check(hipMemcpyAsync(op->fn[i].y, op->fn[i].ybak, bytes, hipMemcpyDeviceToDevice, st), "restore");

@@ -15,7 +15,7 @@ namespace hgf {
 constexpr int kMaxModes = HGF_MAX_MODES;
 constexpr int kMaxCutoff = HGF_MAX_CUTOFF;
 // Points of a tile handled by one thread of the tiled stage kernel:
-// tile points <= kTileRounds * 256.
+// lane groups of a tile <= kTileRounds * 512.
 constexpr int kTileRounds = 8;
 
 using cd = std::complex<double>;
@@ -88,6 +88,7 @@ struct GridArgs {
   int lds_elems;            // padded tile size in elements
   int cbits;                // bits per packed fast coordinate
   int blocks;               // persistent grid size (0: generic kernel)
+  int threads;              // workgroup size of the tiled kernel
   int real;                 // tiled kernel on a real grid (real generator and data)
   int lds_bytes;            // dynamic LDS of the tiled kernel
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)

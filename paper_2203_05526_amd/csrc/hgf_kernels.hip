@@ -504,23 +504,23 @@ void launch_tiled_c64(const GridArgs&, int, const void*, const void*, void*, voi
 void launch_tiled_c128(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
 void launch_tiled_r32(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
 void launch_tiled_r64(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
-int occupancy_tiled_c64(int, int, int);
-int occupancy_tiled_c128(int, int, int);
-int occupancy_tiled_r32(int, int, int);
-int occupancy_tiled_r64(int, int, int);
+int occupancy_tiled_c64(int, int, int, int);
+int occupancy_tiled_c128(int, int, int, int);
+int occupancy_tiled_r32(int, int, int, int);
+int occupancy_tiled_r64(int, int, int, int);
 
 constexpr int kMaxSlow = 12;
 int tiled_max_slow_axes() { return kMaxSlow; }
-int tiled_max_tile_points() { return kTileRounds * 256; }
+int tiled_max_lane_groups() { return kTileRounds * 512; }
 
-int tiled_max_blocks_per_cu(int nfast, int nslow, int precision, int lds_bytes, bool real) {
+int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real) {
   int nb;
   if (real)
-    nb = precision == HGF_FP64 ? occupancy_tiled_r64(nfast, nslow, lds_bytes)
-                               : occupancy_tiled_r32(nfast, nslow, lds_bytes);
+    nb = precision == HGF_FP64 ? occupancy_tiled_r64(nfast, nslow, threads, lds_bytes)
+                               : occupancy_tiled_r32(nfast, nslow, threads, lds_bytes);
   else
-    nb = precision == HGF_FP64 ? occupancy_tiled_c128(nfast, nslow, lds_bytes)
-                               : occupancy_tiled_c64(nfast, nslow, lds_bytes);
+    nb = precision == HGF_FP64 ? occupancy_tiled_c128(nfast, nslow, threads, lds_bytes)
+                               : occupancy_tiled_c64(nfast, nslow, threads, lds_bytes);
   return nb < 1 ? 1 : nb;
 }
 

@@ -56,3 +56,27 @@ def max_rel_err(got: dict, ref: dict) -> float:
 
 def rel(a: complex, b: complex) -> float:
     return abs(a - b) / max(abs(b), 1e-300)
+
+
+def number_scale(cutoff, d):
+    """sqrt(prod_j k_j! l_j!) over the grid of sector d (m = min(k, l))."""
+    import math
+    scale = np.ones(tuple(nc - abs(dj) for nc, dj in zip(cutoff, d)))
+    for j, (nc, dj) in enumerate(zip(cutoff, d)):
+        u, v = max(0, -dj), max(0, dj)
+        s = np.array([math.sqrt(math.factorial(m + u) * math.factorial(m + v)) for m in range(nc - abs(dj))])
+        shape = [1] * len(cutoff)
+        shape[j] = len(s)
+        scale = scale * s.reshape(shape)
+    return scale
+
+
+def gpu_number_grids(op, cutoff):
+    """Library functions converted back to number-basis elements
+    <k|A|l> = g_{k,l} sqrt(k! l!), where every entry of a generic operator is
+    of order one (a comparison of g alone hides errors at high occupation)."""
+    return {d: g * number_scale(cutoff, d) for d, g in gpu_grids(op).items()}
+
+
+def oracle_number_grids(cutoff, ops):
+    return {d: oracle.sector_grid(cutoff, d, box) for d, box in ops.items()}

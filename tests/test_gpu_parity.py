@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import announce, gpu_grids, library, max_rel_err, oracle_grids, rel
+from tests.gpu_util import (announce, gpu_grids, gpu_number_grids, library, max_rel_err, oracle_grids,
+                            oracle_number_grids, rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +108,7 @@ def test_random_operator_all_sectors(hgf, cutoff, seed, precision, tol):
     hgf.evolve(op, T / 2, dt)
     hgf.evolve(op, T / 2, dt)  # two calls compose
     assert max_rel_err(gpu_grids(op), oracle_grids(cutoff, ref)) < tol
+    assert max_rel_err(gpu_number_grids(op, cutoff), oracle_number_grids(cutoff, ref)) < tol
     state = synth.coherent_state([0.4 + 0.1j * j for j in range(len(cutoff))])
     assert rel(hgf.expectation(op, state), oracle.expectation(cutoff, ref, state)) < (
         10 * tol if precision == "mixed" else tol)
@@ -161,6 +163,7 @@ def test_five_mode_ragged_grid(hgf, precision, tol):
     op = hgf.map_operator(hgf.define_system(s), factors=fac, precision=precision)
     hgf.evolve(op, T, dt)
     assert max_rel_err(gpu_grids(op), oracle_grids(cutoff, ref)) < tol
+    assert max_rel_err(gpu_number_grids(op, cutoff), oracle_number_grids(cutoff, ref)) < tol
     st = synth.coherent_state(alpha)
     assert rel(hgf.expectation(op, st), oracle.expectation(cutoff, ref, st)) < tol
 
@@ -200,14 +203,16 @@ def test_large_grid_factorises(hgf):
         sj = synth.System((6,), w.system.detuning[j:j + 1], w.system.kerr[j:j + 1], np.zeros((1, 1)),
                           w.system.gamma1[j:j + 1], w.system.gamma_phi[j:j + 1], w.system.n_th[j:j + 1])
         oj = oracle.evolve_steps(sj, oracle.product_sectors([w.factors[j]]), steps, w.dt)
-        singles.append(oracle_grids((6,), oj)[(0,)])
+        singles.append(oracle_number_grids((6,), oj)[(0,)])
     rng = np.random.default_rng(0)
     idx = rng.integers(0, 6, size=(20000, 10))
     idx = np.concatenate([idx, np.array(np.unravel_index(np.arange(64), (2,) * 6 + (1,) * 4)).T])
     ref = np.ones(len(idx), dtype=np.complex128)
     for j in range(10):
         ref *= singles[j][idx[:, j]]
-    got = grid[tuple(idx.T)]
+    import math
+    fact = np.array([float(math.factorial(m)) for m in range(6)])
+    got = grid[tuple(idx.T)] * np.prod(fact[idx], axis=1)  # number basis: g * prod_j k_j!
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(got - ref)) / scale < MIXED_TOL
     st = w.states[0]
@@ -347,9 +352,9 @@ def test_tiled_and_generic_stage_kernels_agree(hgf, monkeypatch, cutoff, seed, p
         ops[kind] = hgf.map_operator(S, factors=fac, precision=precision)
         hgf.evolve(ops[kind], T, dt)
     monkeypatch.delenv("HGF_STAGE_KERNEL")
-    a, b = gpu_grids(ops["generic"]), gpu_grids(ops["tiled"])
+    a, b = gpu_number_grids(ops["generic"], cutoff), gpu_number_grids(ops["tiled"], cutoff)
     assert max_rel_err(b, a) < (1e-13 if precision == "fp64" else 1e-6)
-    ref = oracle_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
     assert max_rel_err(b, ref) < (FP64_TOL if precision == "fp64" else MIXED_TOL)
 
 
@@ -374,10 +379,28 @@ def test_real_grids_on_diagonal_sector(hgf, monkeypatch, precision):
     assert ops["1"].info()["real_functions"] == 1
     assert ops["0"].info()["real_functions"] == 0
     tol = FP64_TOL if precision == "fp64" else MIXED_TOL
-    ref = oracle_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
-    assert max_rel_err(gpu_grids(ops["1"]), ref) < tol
-    assert max_rel_err(gpu_grids(ops["1"]), gpu_grids(ops["0"])) < (1e-13 if precision == "fp64" else 1e-6)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    assert max_rel_err(gpu_number_grids(ops["1"], cutoff), ref) < tol
+    assert max_rel_err(gpu_number_grids(ops["1"], cutoff), gpu_number_grids(ops["0"], cutoff)) < (
+        1e-13 if precision == "fp64" else 1e-6)
     st = synth.coherent_state(alpha)
     assert rel(hgf.expectation(ops["1"], st), oracle.expectation(cutoff, ops_ref := oracle.evolve(
         s, oracle.product_sectors(fac), T, dt), st)) < tol
     del ops_ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_tile_random_diagonal_operator(hgf, precision):
+    """A tile of 1296 points (four trailing axes of extent 6) with O(1)
+    number-basis entries everywhere: every point of every tile is checked."""
+    cutoff = (3, 6, 6, 6, 6)
+    announce(f"large tile random diagonal {precision}")
+    s = synth.random_system(cutoff, 41, scale=3.0, n_th=0.3)
+    rng = np.random.default_rng(41)
+    fac = [np.diag(rng.uniform(0.5, 1.5, size=c)).astype(np.complex128) for c in cutoff]
+    op = hgf.map_operator(hgf.define_system(s), factors=fac, precision=precision)
+    T, dt = 0.02, 1e-3
+    hgf.evolve(op, T, dt)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
