@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -190,7 +191,7 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   g.real = real ? 1 : 0;
-  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, g.threads, precision, g.lds_bytes, real);
+  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, g.threads, precision, g.lds_bytes, real, true);
   const int64_t want = (int64_t)cus * occ;
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
@@ -639,12 +640,101 @@ static void reset_flag(hgf_operator_s* op, hipStream_t st) {
   hip_check(hipMemsetAsync(op->dflag, 0, sizeof(int), st), "reset flag");
 }
 
-static void merged_step(hgf_operator_s* op, Function& f, double h, hipStream_t st) {
-  const void* in1 = op->precision == HGF_MIXED ? f.yf : f.y;
-  launch_horner(1, op->precision, f.ga, in1, nullptr, f.y, f.yf, f.s1, h, op->dflag, st);
-  launch_horner(2, op->precision, f.ga, f.s1, f.s1, f.y, f.yf, f.s2, h, op->dflag, st);
-  launch_horner(3, op->precision, f.ga, f.s2, f.s1, f.y, f.yf, f.s3, h, op->dflag, st);
-  launch_horner(4, op->precision, f.ga, f.s3, f.s1, f.y, f.yf, nullptr, h, op->dflag, st);
+// ---- merged-layout stepping
+// A StepPlan runs one RK4 step of a set of (function, precision, step size)
+// items: functions with a tiled configuration as grouped launches (one launch
+// per axis split, element type and precision, covering every member's tiles),
+// the others with the generic kernel.
+struct PlanItem {
+  Function* f;
+  int precision;
+  double h;
+};
+
+struct StepPlan {
+  std::vector<GroupLaunch> groups;
+  std::vector<void*> dmem;
+  std::vector<PlanItem> generic;
+  ~StepPlan() {
+    for (auto& p : dmem) dfree(p);
+  }
+};
+
+static MemberArgs member_args(const PlanItem& it) {
+  Function& f = *it.f;
+  MemberArgs m{};
+  m.g = f.ga;
+  m.in[0] = it.precision == HGF_MIXED ? f.yf : f.y;
+  m.in[1] = f.s1;
+  m.in[2] = f.s2;
+  m.in[3] = f.s3;
+  m.x1 = f.s1;
+  m.y = f.y;
+  m.yf = it.precision == HGF_MIXED ? f.yf : nullptr;
+  m.out[0] = f.s1;
+  m.out[1] = f.s2;
+  m.out[2] = f.s3;
+  m.out[3] = nullptr;
+  m.h = it.h;
+  return m;
+}
+
+static StepPlan* build_plan(const std::vector<PlanItem>& items) {
+  std::unique_ptr<StepPlan> plan(new StepPlan);
+  std::map<std::vector<int>, std::vector<PlanItem>> by_key;
+  for (const PlanItem& it : items) {
+    const GridArgs& g = it.f->ga;
+    if (g.blocks > 0)
+      by_key[{g.nfast, g.n - g.nfast, g.real, it.precision}].push_back(it);
+    else
+      plan->generic.push_back(it);
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  for (auto& kv : by_key) {
+    std::vector<MemberArgs> mem;
+    GroupLaunch gl{};
+    gl.nfast = kv.first[0];
+    gl.nslow = kv.first[1];
+    gl.real = kv.first[2];
+    gl.precision = kv.first[3];
+    int64_t tiles = 0;
+    for (const PlanItem& it : kv.second) {
+      MemberArgs m = member_args(it);
+      m.tile_begin = tiles;
+      tiles += it.f->ga.ntiles;
+      gl.threads = std::max(gl.threads, it.f->ga.threads);
+      gl.lds_bytes = std::max(gl.lds_bytes, it.f->ga.lds_bytes);
+      mem.push_back(m);
+    }
+    gl.nmem = (int)mem.size();
+    gl.total_tiles = tiles;
+    const int occ =
+        tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real, mem.size() == 1);
+    gl.blocks = (int)std::max<int64_t>(8, std::min<int64_t>((int64_t)cus * occ, 8 * ((tiles + 7) / 8)));
+    void* d = dmalloc(mem.size() * sizeof(MemberArgs));
+    plan->dmem.push_back(d);
+    hip_check(hipMemcpy(d, mem.data(), mem.size() * sizeof(MemberArgs), hipMemcpyHostToDevice), "upload members");
+    gl.members = (const MemberArgs*)d;
+    gl.single = mem[0];
+    plan->groups.push_back(gl);
+  }
+  return plan.release();
+}
+
+static void generic_stage(const PlanItem& it, int s, int* flag, hipStream_t st) {
+  Function& f = *it.f;
+  const void* in[4] = {it.precision == HGF_MIXED ? f.yf : f.y, f.s1, f.s2, f.s3};
+  void* out[4] = {f.s1, f.s2, f.s3, nullptr};
+  launch_horner(s, it.precision, f.ga, in[s - 1], f.s1, f.y, it.precision == HGF_MIXED ? f.yf : nullptr, out[s - 1],
+                it.h, flag, st);
+}
+
+static void run_plan_step(const StepPlan& plan, int* flag, hipStream_t st) {
+  for (int s = 1; s <= 4; ++s) {
+    for (const GroupLaunch& gl : plan.groups) launch_group(gl, s, flag, st);
+    for (const PlanItem& it : plan.generic) generic_stage(it, s, flag, st);
+  }
 }
 
 static void drop_graph(hgf_operator_s* op) {
@@ -653,23 +743,41 @@ static void drop_graph(hgf_operator_s* op) {
   op->graph_steps = 0;
 }
 
-// One graph holds `chunk` merged steps of every function of the operator.
-static void ensure_graph(hgf_operator_s* op, double h, int chunk) {
-  if (op->graph_exec && op->graph_dt == h && op->graph_steps == chunk) return;
+static void drop_plan(hgf_operator_s* op) {
   drop_graph(op);
-  if (!op->cap_stream) hip_check(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking), "stream");
+  delete op->plan;
+  op->plan = nullptr;
+}
+
+static void ensure_plan(hgf_operator_s* op, double h) {
+  if (op->plan && op->graph_dt == h) return;
+  drop_plan(op);
+  std::vector<PlanItem> items;
+  for (auto& f : op->fn) items.push_back({&f, op->precision, h});
+  op->plan = build_plan(items);
+  op->graph_dt = h;
+}
+
+static hipGraphExec_t capture_steps(const StepPlan& plan, int* flag, int chunk, hipStream_t cap) {
   hipGraph_t graph;
-  hip_check(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  for (int s = 0; s < chunk; ++s)
-    for (auto& f : op->fn) merged_step(op, f, h, op->cap_stream);
-  hip_check(hipStreamEndCapture(op->cap_stream, &graph), "end capture");
+  hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  for (int s = 0; s < chunk; ++s) run_plan_step(plan, flag, cap);
+  hip_check(hipStreamEndCapture(cap, &graph), "end capture");
   hipGraphExec_t exec;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   hip_check(e, "graph instantiate");
-  op->graph_exec = exec;
+  return exec;
+}
+
+// One graph holds `chunk` merged steps of every function of the operator.
+static void ensure_graph(hgf_operator_s* op, double h, int chunk) {
+  ensure_plan(op, h);
+  if (op->graph_exec && op->graph_steps == chunk) return;
+  drop_graph(op);
+  if (!op->cap_stream) hip_check(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking), "stream");
+  op->graph_exec = capture_steps(*op->plan, op->dflag, chunk, op->cap_stream);
   op->graph_steps = chunk;
-  op->graph_dt = h;
 }
 
 static void split_step(hgf_operator_s* op, Function& f, double h, hipStream_t st) {
@@ -742,8 +850,7 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
       hip_check(hipGraphLaunch((hipGraphExec_t)op->graph_exec, st), "graph launch");
       done += chunk;
     }
-    for (; done < steps; ++done)
-      for (auto& f : op->fn) merged_step(op, f, h, st);
+    for (; done < steps; ++done) run_plan_step(*op->plan, op->dflag, st);
   } else {
     for (int64_t s = 0; s < steps; ++s)
       for (auto& f : op->fn) split_step(op, f, h, st);
@@ -768,6 +875,79 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   }
   op->steps_done += steps;
   op->time_us += steps * h;
+}
+
+// Batched evolve: all members' functions advance together, one grouped launch
+// per stage and element-type group, captured in a HIP graph.  Members with
+// fewer steps drop out: the batch runs in phases between consecutive distinct
+// step counts, each phase with its own launch plan and graph.
+static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& steps, const double* dt, hipStream_t st) {
+  DBuf dflag(sizeof(int));
+  hip_check(hipMemsetAsync(dflag.p, 0, sizeof(int), st), "reset flag");
+  for (int i = 0; i < n; ++i)
+    for (auto& f : ops[i]->fn) {
+      const size_t bytes = state_bytes(f);
+      if (!f.ybak) f.ybak = dmalloc(bytes);
+      hip_check(hipMemcpyAsync(f.ybak, f.y, bytes, hipMemcpyDeviceToDevice, st), "backup");
+    }
+  std::vector<int64_t> levels(steps.begin(), steps.end());
+  std::sort(levels.begin(), levels.end());
+  levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
+  hipStream_t cap = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } sg{cap};
+  int64_t prev = 0;
+  for (int64_t level : levels) {
+    const int64_t nst = level - prev;
+    prev = level;
+    if (nst <= 0) continue;
+    std::vector<PlanItem> items;
+    for (int i = 0; i < n; ++i)
+      if (steps[i] >= level)
+        for (auto& f : ops[i]->fn) items.push_back({&f, ops[i]->precision, dt[i]});
+    if (items.empty()) continue;
+    std::unique_ptr<StepPlan> plan(build_plan(items));
+    const int chunk = (int)std::min<int64_t>(nst, 64);
+    hipGraphExec_t exec = capture_steps(*plan, dflag.as<int>(), chunk, cap);
+    struct ExecGuard {
+      hipGraphExec_t e;
+      ~ExecGuard() { (void)hipGraphExecDestroy(e); }
+    } eg{exec};
+    int64_t done = 0;
+    while (nst - done >= chunk) {
+      hip_check(hipGraphLaunch(exec, st), "graph launch");
+      done += chunk;
+    }
+    for (; done < nst; ++done) run_plan_step(*plan, dflag.as<int>(), st);
+    // the plan's device buffers must outlive the launches that read them
+    hip_check(hipStreamSynchronize(st), "synchronize");
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+  int flag = 0;
+  hip_check(hipMemcpyAsync(&flag, dflag.p, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  if (flag) {
+    for (int i = 0; i < n; ++i) {
+      for (auto& f : ops[i]->fn) {
+        hip_check(hipMemcpyAsync(f.y, f.ybak, state_bytes(f), hipMemcpyDeviceToDevice, st), "restore");
+        launch_shadow(ops[i]->precision, f.ga, f.y, f.yf, st);
+      }
+      ops[i]->error_state = 1;
+    }
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    fail((flag & 2) ? HGF_EDEVICE : HGF_ENONFINITE,
+         "non-finite value (or a launch outside its contract) in a batch member; every member restored to the start "
+         "of this call");
+  }
+  for (int i = 0; i < n; ++i) {
+    ops[i]->steps_done += steps[i];
+    ops[i]->time_us += steps[i] * dt[i];
+  }
 }
 
 // ------------------------------------------------------------------ expectation
@@ -916,8 +1096,9 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
     DBuf y0(gb);
     hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
+    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}));
     for (int64_t s = 0; s < M; ++s) {
-      merged_step(&op, f, dt, st);
+      run_plan_step(*fplan, op.dflag, st);
       if ((s + 1) % ce == 0) hip_check(hipMemcpyAsync(ck + ((s + 1) / ce) * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
     }
     // value
@@ -945,7 +1126,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
       hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
       for (int64_t i = 0; i < L; ++i) {
         hip_check(hipMemcpyAsync(seg + i * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "save");
-        if (i + 1 < L) merged_step(&op, f, dt, st);
+        if (i + 1 < L) run_plan_step(*fplan, op.dflag, st);
       }
       for (int64_t i = L - 1; i >= 0; --i) {
         double2* yn = seg + i * pts;
@@ -1081,7 +1262,7 @@ hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_o
 void hgf_destroy_operator(hgf_operator op) {
   if (!op) return;
   (void)hipSetDevice(op->device);
-  drop_graph(op);
+  drop_plan(op);
   for (auto& f : op->fn) free_function(f);
   if (op->dflag) (void)hipFree(op->dflag);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
@@ -1112,7 +1293,12 @@ hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_
       steps[i] = check_steps(t_total_us[i], dt_us[i]);
       check_stability(ops[i]->fn, dt_us[i]);
     }
-    for (int i = 0; i < n; ++i) evolve_impl(ops[i], steps[i], dt_us[i], (hipStream_t)hip_stream);
+    for (int i = 0; i < n; ++i)
+      if (ops[i]->device != ops[0]->device) fail(HGF_EINVAL, "batch members must live on one device");
+    if (n > 0) {
+      hip_check(hipSetDevice(ops[0]->device), "hipSetDevice");
+      batch_impl(ops, n, steps, dt_us, (hipStream_t)hip_stream);
+    }
   });
 }
 

@@ -100,6 +100,29 @@ struct GridArgs {
   const float* beta_f;
 };
 
+// Arguments of one member of a grouped (tiled) stage launch, kept in device
+// memory: the member's grid, its buffers per stage and its step size.
+struct MemberArgs {
+  GridArgs g;
+  const void* in[4];  // stencil input of stages 1..4
+  const void* x1;     // X1 (stages 2..4)
+  void* y;            // state
+  void* yf;           // stage-precision copy of y (mixed) or NULL
+  void* out[4];       // output of stages 1..3 (stage 4 writes y)
+  double h;
+  int64_t tile_begin;  // first tile of the member in the group's tile space
+};
+
+// One grouped launch: members sharing the axis split and element types.
+struct GroupLaunch {
+  MemberArgs single;          // the member itself when nmem == 1 (passed by value)
+  const MemberArgs* members;  // device array
+  int nmem;
+  int64_t total_tiles;
+  int nfast, nslow, threads, lds_bytes, blocks;
+  int real, precision;
+};
+
 // ------------------------------------------------------------------ functions
 struct Function {
   SectorTables tab;
@@ -124,6 +147,8 @@ struct Function {
   std::vector<std::pair<int64_t, cd>> sources;  // R' = L R + c_x c_y S
 };
 
+struct StepPlan;
+
 }  // namespace hgf
 
 struct hgf_system_s {
@@ -141,7 +166,8 @@ struct hgf_operator_s {
   int64_t underflow = 0;
   int error_state = 0;
   int* dflag = nullptr;  // device non-finite flag
-  // cached graph of merged-mode steps
+  // launch plan and cached graph of merged-mode steps
+  hgf::StepPlan* plan = nullptr;
   void* graph_exec = nullptr;
   int graph_steps = 0;
   double graph_dt = 0.0;

@@ -33,9 +33,11 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
-int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real);
+int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real,
+                            bool single);
 int tiled_max_slow_axes();
 int tiled_max_lane_groups();
+void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st);
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
                       double h, const PointSources& src, int* flag, hipStream_t st);
 int expect_blocks(const GridArgs& g);

@@ -499,40 +499,40 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks) {
 
 static const int kStageBlocks = 4096;
 
-// Tiled kernel instantiations live in hgf_tiled_{c64,c128,r32,r64}.hip.
-void launch_tiled_c64(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
-void launch_tiled_c128(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
-void launch_tiled_r32(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
-void launch_tiled_r64(const GridArgs&, int, const void*, const void*, void*, void*, void*, double, int*, hipStream_t);
-int occupancy_tiled_c64(int, int, int, int);
-int occupancy_tiled_c128(int, int, int, int);
-int occupancy_tiled_r32(int, int, int, int);
-int occupancy_tiled_r64(int, int, int, int);
+// Grouped tiled kernel instantiations live in hgf_tiled_{c64,c128,r32,r64}.hip.
+void launch_group_c64(const GroupLaunch&, int, int*, hipStream_t);
+void launch_group_c128(const GroupLaunch&, int, int*, hipStream_t);
+void launch_group_r32(const GroupLaunch&, int, int*, hipStream_t);
+void launch_group_r64(const GroupLaunch&, int, int*, hipStream_t);
+int occupancy_group_c64(int, int, int, int, bool);
+int occupancy_group_c128(int, int, int, int, bool);
+int occupancy_group_r32(int, int, int, int, bool);
+int occupancy_group_r64(int, int, int, int, bool);
 
 constexpr int kMaxSlow = 12;
 int tiled_max_slow_axes() { return kMaxSlow; }
 int tiled_max_lane_groups() { return kTileRounds * 512; }
 
-int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real) {
+int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real, bool single) {
   int nb;
   if (real)
-    nb = precision == HGF_FP64 ? occupancy_tiled_r64(nfast, nslow, threads, lds_bytes)
-                               : occupancy_tiled_r32(nfast, nslow, threads, lds_bytes);
+    nb = precision == HGF_FP64 ? occupancy_group_r64(nfast, nslow, threads, lds_bytes, single)
+                               : occupancy_group_r32(nfast, nslow, threads, lds_bytes, single);
   else
-    nb = precision == HGF_FP64 ? occupancy_tiled_c128(nfast, nslow, threads, lds_bytes)
-                               : occupancy_tiled_c64(nfast, nslow, threads, lds_bytes);
+    nb = precision == HGF_FP64 ? occupancy_group_c128(nfast, nslow, threads, lds_bytes, single)
+                               : occupancy_group_c64(nfast, nslow, threads, lds_bytes, single);
   return nb < 1 ? 1 : nb;
+}
+
+void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {
+  if (gl.real)
+    (gl.precision == HGF_FP64 ? launch_group_r64 : launch_group_r32)(gl, stage, flag, st);
+  else
+    (gl.precision == HGF_FP64 ? launch_group_c128 : launch_group_c64)(gl, stage, flag, st);
 }
 
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st) {
-  if (g.blocks > 0) {
-    if (g.real)
-      (precision == HGF_FP64 ? launch_tiled_r64 : launch_tiled_r32)(g, stage, in, x1, y, yf, out, h, flag, st);
-    else
-      (precision == HGF_FP64 ? launch_tiled_c128 : launch_tiled_c64)(g, stage, in, x1, y, yf, out, h, flag, st);
-    return;
-  }
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   dim3 gr(ls.blocks), bl(ls.threads);

@@ -1,18 +1,24 @@
 // The LDS-tiled, XCD-aware RK4 stage kernel of the merged layout (delta-Horner
-// stages), templated on the number of fast and slow axes, on the element
-// types and on the points per lane.  Included by one translation unit per
-// element type.
+// stages), templated on the number of fast and slow axes and on the element
+// types.  Included by one translation unit per element type.
 //
-// Tile: the trailing NF axes of the grid form a tile of T points that is
+// One launch serves a group of grids ("members": the sector grids of one
+// operator, or the members of a batch) that share the axis split and element
+// types; extents, coefficients and step size are per member.  The tiles of all
+// members form one tile space.
+//
+// Tile: the trailing NF axes of a grid form a tile of T points that is
 // contiguous in memory.  A workgroup stages the tile's stencil input in LDS
 // with a zero halo around every fast axis, so the fast-axis neighbours are
 // unconditional LDS reads.  The neighbours along the remaining NS (slow) axes
 // are whole tiles at a fixed element offset; they are read from global memory
-// and reused across workgroups through L2 and the Infinity Cache.
+// and reused across workgroups through L2 and the Infinity Cache.  Every
+// neighbour load is issued unconditionally (an out-of-range direction reads
+// the centre with a zero coefficient), so the loads of a point overlap.
 //
 // Work distribution: persistent workgroups; workgroup b runs on XCD b % 8, so
-// each XCD is given a contiguous range of tiles and walks it with its own
-// workgroups in step.  The next tile's centre values are prefetched into
+// each XCD is given a contiguous range of the tile space and walks it with its
+// own workgroups in step.  The next tile's centre values are prefetched into
 // registers while the current tile is computed.  Streaming operands (x1, y,
 // outputs) use non-temporal accesses so that they do not evict the stencil
 // input from the caches.
@@ -35,6 +41,75 @@ struct TileRec {
   int32_t off[2 * (NS > 0 ? NS : 1)];
   R coef[2 * (NS > 0 ? NS : 1)];
 };
+
+// Element access by a 32-bit index from a base pointer of a member record.
+// The pointers are cast to the global address space: loaded from memory they
+// would otherwise be generic pointers and compile to flat instructions.
+#define HGF_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ float ldg(const HGF_GLOBAL float* p) { return *p; }
+__device__ __forceinline__ double ldg(const HGF_GLOBAL double* p) { return *p; }
+__device__ __forceinline__ float2 ldg(const HGF_GLOBAL float2* p) {
+  const hgf_v2f v = *(const HGF_GLOBAL hgf_v2f*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ldg(const HGF_GLOBAL double2* p) {
+  const hgf_v2d v = *(const HGF_GLOBAL hgf_v2d*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stg(HGF_GLOBAL float* p, float a) { *p = a; }
+__device__ __forceinline__ void stg(HGF_GLOBAL double* p, double a) { *p = a; }
+__device__ __forceinline__ void stg(HGF_GLOBAL float2* p, float2 a) {
+  hgf_v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  *(HGF_GLOBAL hgf_v2f*)p = v;
+}
+__device__ __forceinline__ void stg(HGF_GLOBAL double2* p, double2 a) {
+  hgf_v2d v;
+  v.x = a.x;
+  v.y = a.y;
+  *(HGF_GLOBAL hgf_v2d*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const void* base, uint32_t idx) {
+  return ldg((const HGF_GLOBAL T*)((const HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)));
+}
+__device__ __forceinline__ float ldg_nt(const HGF_GLOBAL float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ldg_nt(const HGF_GLOBAL double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float2 ldg_nt(const HGF_GLOBAL float2* p) {
+  const hgf_v2f v = __builtin_nontemporal_load((const HGF_GLOBAL hgf_v2f*)p);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ldg_nt(const HGF_GLOBAL double2* p) {
+  const hgf_v2d v = __builtin_nontemporal_load((const HGF_GLOBAL hgf_v2d*)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stg_nt(HGF_GLOBAL float* p, float a) { __builtin_nontemporal_store(a, p); }
+__device__ __forceinline__ void stg_nt(HGF_GLOBAL double* p, double a) { __builtin_nontemporal_store(a, p); }
+__device__ __forceinline__ void stg_nt(HGF_GLOBAL float2* p, float2 a) {
+  hgf_v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (HGF_GLOBAL hgf_v2f*)p);
+}
+__device__ __forceinline__ void stg_nt(HGF_GLOBAL double2* p, double2 a) {
+  hgf_v2d v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, (HGF_GLOBAL hgf_v2d*)p);
+}
+template <typename T>
+__device__ __forceinline__ T ld_at_nt(const void* base, uint32_t idx) {
+  return ldg_nt((const HGF_GLOBAL T*)((const HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st_at_nt(void* base, uint32_t idx, T v) {
+  stg_nt((HGF_GLOBAL T*)((HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)), v);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(void* base, uint32_t idx, T v) {
+  stg((HGF_GLOBAL T*)((HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)), v);
+}
 
 template <typename T, int V>
 struct alignas(sizeof(T) * V) Pack {
@@ -68,6 +143,10 @@ __device__ __forceinline__ void st_pack(P* base, uint32_t byte_off, const P& v) 
 // (double2, or double for a real grid).  Each lane owns V consecutive points
 // of a tile (V = 1: wider lanes were measured slower on the 6^10 grid, the
 // per-lane LDS work then serialises while the L2 request count is unchanged).
+
+// ---- single-grid form: one member, its record passed by value as kernel
+// arguments (a separate kernel: reading member fields through a pointer kept
+// more values live and lowered the occupancy measured on the 6^10 grid).
 template <int NF, int NS, typename TS, typename TY>
 __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
                                                    const TS* __restrict__ x1, TY* __restrict__ y,
@@ -249,18 +328,201 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
   if (bad) atomicOr(flag, 1);
 }
 
+
+// ---- grouped form: several members, records in device memory.
+// TS: storage of the stage grids (complex or real); TY: the state y
+// (double2, or double for a real grid).  One point per lane (wider lanes were
+// measured slower on the 6^10 grid: the per-lane LDS work then serialises
+// while the L2 request count is unchanged).
+template <int NF, int NS, typename TS, typename TY>
+__global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict__ mem, int nmem,
+                                                   int64_t total_tiles, int stage, int* __restrict__ flag) {
+  using R = typename Real<TS>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int si = stage - 1;
+
+  const uint32_t xcd = blockIdx.x & 7u;
+  const uint32_t nwx = (gridDim.x - xcd + 7u) >> 3;
+  const int64_t lo = total_tiles * xcd / 8, hi = total_tiles * (xcd + 1) / 8;
+  int bad = 0;
+
+  TS* const tile = (TS*)smem;
+  TS nxt[kTileRounds];
+  int64_t t = lo + (blockIdx.x >> 3);
+  int m = 0;
+  while (t < hi) {
+    // ---- the member owning tile t; its per-position tables.  Member values
+    // are read from the member record where they are used (scalar loads)
+    // rather than held in registers across the tile loop.
+    while (m + 1 < nmem && mem[m + 1].tile_begin <= t) ++m;
+    const MemberArgs* __restrict__ mp = mem + m;
+    const int64_t mbeg = mp->tile_begin;
+    const int64_t run_end = min(hi, mbeg + mp->g.ntiles);
+    const int T = (int)mp->g.tile_points;
+    const int rounds = (T + nt - 1) / nt;
+    if (rounds > kTileRounds) {  // launch contract broken: report, compute nothing
+      if (tid == 0) atomicOr(flag, 2);
+      return;
+    }
+    TS* const lamf = tile + mp->g.lds_elems;
+    uint32_t* const info = (uint32_t*)(lamf + T);
+    R* const btab = (R*)(info + ((T + 1) & ~1));
+    const int cbits = mp->g.cbits;
+    const uint32_t cmask = (1u << cbits) - 1u;
+    __syncthreads();  // a previous member's tile is no longer read
+    // zero halo and per-position tables.  LDS layout of the tile: fast
+    // coordinate c_q sits at c_q + 1 with stride pstride[q]; the slots with
+    // some coordinate at 0 (and the last row of the outermost fast axis) are
+    // never written and read as the zero neighbours.
+    for (int i = tid; i < mp->g.lds_elems; i += nt) tile[i] = mk_<TS>(0, 0);
+    for (int p = tid; p < T; p += nt) {
+      int rem = p;
+      uint32_t off = 0, coords = 0;
+      double lr = 0.0, li = 0.0;
+#pragma unroll
+      for (int q = NF - 1; q >= 0; --q) {
+        const int j = NS + q;
+        const int e = mp->g.ext[j];
+        const int c = rem % e;
+        rem /= e;
+        off += (uint32_t)(c + 1) * (uint32_t)mp->g.pstride[q];
+        coords |= (uint32_t)c << (cbits * q);
+        const double2 lj = mp->g.lam[mp->g.off[j] + c];
+        lr += lj.x;
+        li += lj.y;
+      }
+      info[p] = off | (coords << 16);
+      lamf[p] = mk_<TS>((R)lr, (R)li);
+    }
+    {
+      int o = 0;
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const int j = NS + q;
+        for (int c = tid; c < mp->g.ext[j]; c += nt) btab[o + c] = (R)mp->g.beta[mp->g.off[j] + c];
+        o += mp->g.ext[j];
+      }
+    }
+    __syncthreads();
+    const TS* __restrict__ in = (const TS*)mp->in[si];
+
+    // ---- the member's tiles of this workgroup; the centre values of the
+    // first one are loaded here, those of the next during each tile
+    if (t < run_end) {
+      const uint32_t b0 = (uint32_t)(t - mbeg) * (uint32_t)T;
+#pragma unroll
+      for (int r = 0; r < kTileRounds; ++r) {
+        const uint32_t p = min((uint32_t)(tid + r * nt), (uint32_t)(T - 1));
+        if (r < rounds) nxt[r] = ld_at<TS>(in, b0 + p);
+      }
+    }
+    for (; t < run_end; t += nwx) {
+      const uint32_t lt = (uint32_t)(t - mbeg);  // tile index inside the member
+      const uint32_t tbase = lt * (uint32_t)T;
+#pragma unroll
+      for (int r = 0; r < kTileRounds; ++r) {
+        const int p = tid + r * nt;
+        if (r < rounds && p < T) tile[info[p] & 0xffffu] = nxt[r];
+      }
+      __syncthreads();
+      {
+        const int64_t tn = t + nwx;
+        if (tn < run_end) {
+          const uint32_t b0 = (uint32_t)(tn - mbeg) * (uint32_t)T;
+#pragma unroll
+          for (int r = 0; r < kTileRounds; ++r) {
+            const uint32_t p = min((uint32_t)(tid + r * nt), (uint32_t)(T - 1));
+            if (r < rounds) nxt[r] = ld_at<TS>(in, b0 + p);
+          }
+        }
+      }
+      // slow-axis terms, uniform over the tile (scalar loads of its record)
+      const TileRec<NS, R>* rec = (const TileRec<NS, R>*)mp->g.tiles + lt;
+      const R lsr = rec->lam_re, lsi = rec->lam_im;
+      int32_t soff[2 * (NS > 0 ? NS : 1)];
+      R scoef[2 * (NS > 0 ? NS : 1)];
+#pragma unroll
+      for (int j = 0; j < 2 * NS; ++j) {
+        soff[j] = rec->off[j];
+        scoef[j] = rec->coef[j];
+      }
+      for (int r = 0; r < rounds; ++r) {
+        const int pr = tid + r * nt;
+        const int p = min(pr, T - 1);
+        const uint32_t e0 = tbase + (uint32_t)p;
+        TS sv[2 * (NS > 0 ? NS : 1)];
+#pragma unroll
+        for (int j = 0; j < 2 * NS; ++j) sv[j] = ld_at<TS>(in, e0 + (uint32_t)soff[j]);
+        TS xb;
+        TY yv;
+        if (stage >= 2) xb = ld_at_nt<TS>(mp->x1, e0);
+        if (stage == 4) yv = ld_at_nt<TY>(mp->y, e0);
+        const uint32_t inf = info[p];
+        const int lo_ = (int)(inf & 0xffffu);
+        const TS zc = tile[lo_];
+        const TS lf = lamf[p];
+        const R lr = lsr + re_(lf), li = lsi + im_(lf);
+        R ar = lr * re_(zc) - li * im_(zc);
+        R ai = lr * im_(zc) + li * re_(zc);
+        int bo = 0;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+          const int ps = mp->g.pstride[q];
+          const TS dn = tile[lo_ - ps];
+          const TS upv = tile[lo_ + ps];
+          const int c = (int)((inf >> (16 + cbits * q)) & cmask);
+          const R bq = btab[bo + c];
+          const R aq = (R)mp->g.alpha[NS + q];
+          ar += aq * re_(dn) + bq * re_(upv);
+          ai += aq * im_(dn) + bq * im_(upv);
+          bo += mp->g.ext[NS + q];
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * NS; ++j) {
+          ar += scoef[j] * re_(sv[j]);
+          ai += scoef[j] * im_(sv[j]);
+        }
+        if (pr < T) {
+          const double h = mp->h;
+          if (stage == 1) {
+            st_at_nt<TS>(mp->out[0], e0, mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai)));
+          } else if (stage == 2 || stage == 3) {
+            const R c = (R)(stage == 2 ? 0.25 * h : h / 3.0);
+            st_at_nt<TS>(mp->out[si], e0, mk_<TS>(re_(xb) + c * ar, im_(xb) + c * ai));
+          } else {
+            const double c = 0.5 * h;
+            const double nr = re_(yv) + (double)re_(xb) + c * (double)ar;
+            const double ni = im_(yv) + (double)im_(xb) + c * (double)ai;
+            bad |= !(isfinite(nr) && isfinite(ni));
+            st_at_nt<TY>(mp->y, e0, mk_<TY>(nr, ni));
+            if (mp->yf) st_at<TS>(mp->yf, e0, mk_<TS>((R)nr, (R)ni));
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // Instantiation helpers: NF fast axes (1..4) and NS slow axes (0..12).
 #define HGF_NS_CASES(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12)
 
 template <typename TS, typename TY, int NF>
-static void tiled_launch_nf(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
-                            void* out, double h, int* flag, hipStream_t st) {
-  const int ns = g.n - NF;
-  switch (ns) {
+static void group_launch_nf(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {
+  switch (gl.nslow) {
 #define HGF_CASE(K)                                                                                          \
   case K:                                                                                                    \
-    hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY>), dim3(g.blocks), dim3(g.threads), g.lds_bytes, st, g,    \
-                       stage, (const TS*)in, (const TS*)x1, (TY*)y, (TS*)yf, (TS*)out, h, flag);            \
+    if (gl.nmem == 1) {                                                                                      \
+      const MemberArgs& a = gl.single;                                                                       \
+      hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY>), dim3(gl.blocks), dim3(gl.threads), gl.lds_bytes, st,  \
+                         a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1, (TY*)a.y, (TS*)a.yf,       \
+                         (TS*)a.out[stage - 1], a.h, flag);                                                  \
+    } else {                                                                                                 \
+      hipLaunchKernelGGL((k_rk4_group<NF, K, TS, TY>), dim3(gl.blocks), dim3(gl.threads), gl.lds_bytes, st,  \
+                         gl.members, gl.nmem, gl.total_tiles, stage, flag);                                  \
+    }                                                                                                        \
     break;
     HGF_NS_CASES(HGF_CASE)
 #undef HGF_CASE
@@ -269,25 +531,29 @@ static void tiled_launch_nf(const GridArgs& g, int stage, const void* in, const 
 }
 
 template <typename TS, typename TY>
-static void tiled_launch_all(const GridArgs& g, int stage, const void* in, const void* x1, void* y, void* yf,
-                             void* out, double h, int* flag, hipStream_t st) {
-  switch (g.nfast) {
-    case 1: tiled_launch_nf<TS, TY, 1>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    case 2: tiled_launch_nf<TS, TY, 2>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    case 3: tiled_launch_nf<TS, TY, 3>(g, stage, in, x1, y, yf, out, h, flag, st); break;
-    default: tiled_launch_nf<TS, TY, 4>(g, stage, in, x1, y, yf, out, h, flag, st); break;
+static void group_launch_all(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {
+  switch (gl.nfast) {
+    case 1: group_launch_nf<TS, TY, 1>(gl, stage, flag, st); break;
+    case 2: group_launch_nf<TS, TY, 2>(gl, stage, flag, st); break;
+    case 3: group_launch_nf<TS, TY, 3>(gl, stage, flag, st); break;
+    default: group_launch_nf<TS, TY, 4>(gl, stage, flag, st); break;
   }
 }
 
 template <typename TS, typename TY, int NF>
-static int tiled_occ_nf(int ns, int threads, int lds_bytes) {
+static int group_occ_nf(int ns, int threads, int lds_bytes, bool single) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (ns) {
 #define HGF_CASE(K)                                                                                          \
-  case K:                                                                                                    \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY>, threads, lds_bytes);   \
-    break;
+  case K: {                                                                                                  \
+    int a = 0, b = 0;                                                                                        \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_rk4_group<NF, K, TS, TY>, threads, lds_bytes);    \
+    if (e == hipSuccess)                                                                                     \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rk4_tiled<NF, K, TS, TY>, threads, lds_bytes);  \
+    nb = single ? b : a;                                                                                     \
+    break;                                                                                                   \
+  }
     HGF_NS_CASES(HGF_CASE)
 #undef HGF_CASE
     default: break;
@@ -296,22 +562,21 @@ static int tiled_occ_nf(int ns, int threads, int lds_bytes) {
 }
 
 template <typename TS, typename TY>
-static int tiled_occ_all(int nfast, int nslow, int threads, int lds_bytes) {
+static int group_occ_all(int nfast, int nslow, int threads, int lds_bytes, bool single) {
   switch (nfast) {
-    case 1: return tiled_occ_nf<TS, TY, 1>(nslow, threads, lds_bytes);
-    case 2: return tiled_occ_nf<TS, TY, 2>(nslow, threads, lds_bytes);
-    case 3: return tiled_occ_nf<TS, TY, 3>(nslow, threads, lds_bytes);
-    default: return tiled_occ_nf<TS, TY, 4>(nslow, threads, lds_bytes);
+    case 1: return group_occ_nf<TS, TY, 1>(nslow, threads, lds_bytes, single);
+    case 2: return group_occ_nf<TS, TY, 2>(nslow, threads, lds_bytes, single);
+    case 3: return group_occ_nf<TS, TY, 3>(nslow, threads, lds_bytes, single);
+    default: return group_occ_nf<TS, TY, 4>(nslow, threads, lds_bytes, single);
   }
 }
 
 #define HGF_TILED_INSTANTIATE(TS, TY, SUFFIX)                                                            \
-  void launch_tiled_##SUFFIX(const GridArgs& g, int stage, const void* in, const void* x1, void* y,      \
-                             void* yf, void* out, double h, int* flag, hipStream_t st) {                \
-    tiled_launch_all<TS, TY>(g, stage, in, x1, y, yf, out, h, flag, st);                                 \
+  void launch_group_##SUFFIX(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {              \
+    group_launch_all<TS, TY>(gl, stage, flag, st);                                                       \
   }                                                                                                      \
-  int occupancy_tiled_##SUFFIX(int nfast, int nslow, int threads, int lds_bytes) {                       \
-    return tiled_occ_all<TS, TY>(nfast, nslow, threads, lds_bytes);                                      \
+  int occupancy_group_##SUFFIX(int nfast, int nslow, int threads, int lds_bytes, bool single) {          \
+    return group_occ_all<TS, TY>(nfast, nslow, threads, lds_bytes, single);                              \
   }
 
 }  // namespace hgf

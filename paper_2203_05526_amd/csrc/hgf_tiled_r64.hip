@@ -1,4 +1,4 @@
-// Instantiations of the tiled RK4 stage kernel for double stage grids and a double state.
+// Instantiations of the grouped tiled RK4 stage kernel for double stage grids and a double state.
 #include "hgf_tiled.h"
 
 namespace hgf {

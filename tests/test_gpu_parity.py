@@ -293,20 +293,31 @@ def test_nonfinite_detected_and_state_restored(hgf):
 
 # ----------------------------------------------------------------- batching
 
-def test_batch_equals_individual(hgf):
-    announce("batch vs individual")
-    ws = synth.batch_c2(n_even=2, n_uneven=2)
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batch_equals_individual(hgf, precision):
+    """Grouped batch launches (members of different shapes, step sizes and
+    horizons) give the same numbers as evolving each member alone, and a
+    member matches the oracle."""
+    announce(f"batch vs individual {precision}")
+    ws = synth.batch_c2(n_even=3, n_uneven=4)
+    T = [0.01, 0.02, 0.01, 0.03, 0.004, 0.01, 0.02]
+    dt = [1e-4, 2e-4, 1e-4, 1e-4, 1e-4, 5e-5, 1e-4]
     ops_a, ops_b = [], []
     for w in ws:
         S = hgf.define_system(w.system)
-        ops_a.append(hgf.map_operator(S, factors=w.factors, precision="mixed"))
-        ops_b.append(hgf.map_operator(S, factors=w.factors, precision="mixed"))
-    hgf.evolve_batch(ops_a, [0.01] * len(ws), [1e-4] * len(ws))
-    for op in ops_b:
-        hgf.evolve(op, 0.01, 1e-4)
-    for w, a, b in zip(ws, ops_a, ops_b):
+        ops_a.append(hgf.map_operator(S, factors=w.factors, precision=precision))
+        ops_b.append(hgf.map_operator(S, factors=w.factors, precision=precision))
+    hgf.evolve_batch(ops_a, T, dt)
+    for op, t, h in zip(ops_b, T, dt):
+        hgf.evolve(op, t, h)
+    for w, a, b, t in zip(ws, ops_a, ops_b, T):
         st = w.states[0]
         assert hgf.expectation(a, st) == hgf.expectation(b, st)
+        assert a.info()["steps_done"] == b.info()["steps_done"]
+    w = ws[3]
+    ref = oracle.evolve(w.system, oracle.product_sectors(w.factors), T[3], dt[3])
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    assert max_rel_err(gpu_number_grids(ops_a[3], w.system.cutoff), oracle_number_grids(w.system.cutoff, ref)) < tol
 
 
 # ----------------------------------------------------------------- gradient
