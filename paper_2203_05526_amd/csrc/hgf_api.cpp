@@ -195,6 +195,8 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
   const int64_t want = (int64_t)cus * occ;
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
+  g.xblock = 0;
+  if (const char* xb = std::getenv("HGF_XCD_BLOCK")) g.xblock = std::max(0, std::atoi(xb));
 }
 
 // Per-tile records of the slow-axis terms for k_rk4_tiled (layout of

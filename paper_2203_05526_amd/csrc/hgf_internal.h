@@ -91,6 +91,7 @@ struct GridArgs {
   int threads;              // workgroup size of the tiled kernel
   int real;                 // tiled kernel on a real grid (real generator and data)
   int lds_bytes;            // dynamic LDS of the tiled kernel
+  int xblock;               // tile order across XCDs: 0 contiguous eighths, B > 0 blocks of B tiles
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
   double lam0_re, lam0_im;
   double alpha[kMaxModes];

@@ -207,10 +207,21 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
   // ---- persistent walk.  Elements are addressed by 32-bit byte offsets from
   // the grid base (the host selects this kernel only when they fit); lane
   // groups past the tile's end are clamped to its last group and store nothing.
+  // Tile order of an XCD: with g.xblock = 0 its contiguous eighth of the grid;
+  // with g.xblock = B > 0 the blocks of B consecutive tiles whose index is
+  // congruent to the XCD modulo 8 (all XCDs then sweep one compact region of
+  // the grid together).  Workgroup wx of the XCD takes positions wx, wx + nwx, ...
   const uint32_t xcd = blockIdx.x & 7u;
   const uint32_t nwx = (gridDim.x - xcd + 7u) >> 3;
   const uint32_t nti = (uint32_t)g.ntiles;
   const uint32_t lo = (uint32_t)(((uint64_t)nti * xcd) >> 3), hi = (uint32_t)(((uint64_t)nti * (xcd + 1)) >> 3);
+  const uint32_t xb = (uint32_t)g.xblock;
+  constexpr uint32_t kNone = 0xffffffffu;
+  auto tile_at = [&](uint32_t pos) -> uint32_t {
+    if (xb == 0) return lo + pos < hi ? lo + pos : kNone;
+    const uint32_t tt = (xcd + 8u * (pos / xb)) * xb + pos % xb;
+    return tt < nti ? tt : kNone;
+  };
   const int G = T / V;
   const int rounds = (G + nt - 1) / nt;
   if (rounds > kTileRounds) {  // launch contract broken: report, compute nothing
@@ -220,8 +231,9 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
   constexpr uint32_t SB = sizeof(TS), YB = sizeof(TY);
   int bad = 0;
   PS nxt[kTileRounds];
-  uint32_t t = lo + (blockIdx.x >> 3);
-  if (t < hi) {
+  uint32_t pos = blockIdx.x >> 3;
+  uint32_t t = tile_at(pos);
+  if (t != kNone) {
     const uint32_t b0 = t * (uint32_t)T;
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
       if (r < rounds) nxt[r] = ld_pack((const PS*)in, (b0 + V * gi) * SB);
     }
   }
-  for (; t < hi; t += nwx) {
+  while (t != kNone) {
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
       const int gi = tid + r * nt;
@@ -240,15 +252,13 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
     }
     __syncthreads();
     const uint32_t tbase = t * (uint32_t)T;
-    {
-      const uint32_t tn = t + nwx;
-      if (tn < hi) {
-        const uint32_t b0 = tn * (uint32_t)T;
+    const uint32_t tn = tile_at(pos + nwx);
+    if (tn != kNone) {
+      const uint32_t b0 = tn * (uint32_t)T;
 #pragma unroll
-        for (int r = 0; r < kTileRounds; ++r) {
-          const uint32_t gi = min((uint32_t)(tid + r * nt), (uint32_t)(G - 1));
-          if (r < rounds) nxt[r] = ld_pack((const PS*)in, (b0 + V * gi) * SB);
-        }
+      for (int r = 0; r < kTileRounds; ++r) {
+        const uint32_t gi = min((uint32_t)(tid + r * nt), (uint32_t)(G - 1));
+        if (r < rounds) nxt[r] = ld_pack((const PS*)in, (b0 + V * gi) * SB);
       }
     }
     // slow-axis terms, uniform over the tile (scalar loads of the tile's
@@ -324,6 +334,8 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
       }
     }
     __syncthreads();
+    pos += nwx;
+    t = tn;
   }
   if (bad) atomicOr(flag, 1);
 }
