@@ -124,14 +124,17 @@ def batch_throughput(hgf, torch, steps: int):
     ops = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
     pts = sum(op.info()["total_points"] for op in ops)
     dt = ws[0].dt
+    # sequential reference: the same members evolved one hgf_evolve call at a time
+    ops2 = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
+    t0 = time.perf_counter()
+    hgf.autotune(ops + ops2, dt)  # each distinct grid shape measured once, applied to all
+    tune_s = time.perf_counter() - t0
     hgf.evolve_batch(ops, [2 * dt] * len(ops), [dt] * len(ops))  # warm-up (plan, graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hgf.evolve_batch(ops, [steps * dt] * len(ops), [dt] * len(ops))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    # sequential reference: the same members evolved one hgf_evolve call at a time
-    ops2 = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
     for op in ops2:
         hgf.evolve(op, 2 * dt, dt)
     torch.cuda.synchronize()
@@ -143,7 +146,7 @@ def batch_throughput(hgf, torch, steps: int):
     return {"workload": "96 systems: 64 x (6 modes, cutoff 8) + 32 x (2-5 modes, cutoffs 6-20), mixed",
             "members": len(ops), "grid_points": pts, "steps": steps,
             "value": pts * 4 * steps / el, "unit": "point-stage updates/s", "seconds": el,
-            "sequential_seconds": el_seq}
+            "sequential_seconds": el_seq, "autotune_seconds": tune_s}
 
 
 def gradient_timing(hgf, torch, t_total: float):
@@ -169,7 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -202,6 +205,10 @@ def main():
     def run(precision, steps, warmup):
         op = hgf.map_operator(S, factors=w.factors, precision=precision)
         real = op.info()["real_functions"] == 1
+        t0 = time.perf_counter()
+        hgf.autotune([op], w.dt)  # launch shape of the stage kernel, measured on this GPU
+        tune = dict(op.tile_config(0), seconds=time.perf_counter() - t0)
+        log(f"autotuned shape {tune}")
         if warmup:
             hgf.evolve(op, warmup * w.dt, w.dt)
         torch.cuda.synchronize()
@@ -215,10 +222,10 @@ def main():
         el = time.perf_counter() - t0
         launch_s = start.elapsed_time(end) * 1e-3 / (4 * steps)
         del op
-        return el, launch_s, J, real
+        return el, launch_s, J, real, tune
 
     log(f"timing {args.steps} steps ({args.precision}) over {pts} points")
-    el, launch_s, J, real = run(args.precision, args.steps, args.warmup)
+    el, launch_s, J, real, tune = run(args.precision, args.steps, args.warmup)
     log(f"done: {el:.3f} s, stage launch {launch_s * 1e6:.1f} us")
     value = pts * 4 * args.steps / el
     bytes_launch = bytes_per_point_stage(args.precision, real) * pts
@@ -240,7 +247,8 @@ def main():
         "data": "synthetic (seeded parameters, no dataset)",
         "config": {"workload": "10 Kerr modes, cutoff 6 (6^10 grid points), parity-weighted projector, "
                                "dt = 0.05 ns, merged layout",
-                   "precision": args.precision, "grid_points": pts, "seed": 4, "real_grids": real},
+                   "precision": args.precision, "grid_points": pts, "seed": 4, "real_grids": real,
+                   "tile_shape": tune},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": STAGE_KERNEL, "avg_launch_us": launch_s * 1e6,
@@ -250,7 +258,7 @@ def main():
     if not args.no_extras:
         log("fp64 comparison")
         n64 = max(10, args.steps // 4)
-        el64, launch64, J64, real64 = run("fp64", n64, 2)
+        el64, launch64, J64, real64, _ = run("fp64", n64, 2)
         line["fp64_plain"] = {"value": pts * 4 * n64 / el64, "steps": n64, "real_grids": real64,
                               "achieved_GBs": bytes_per_point_stage("fp64", real64) * pts / launch64 / 1e9}
         log("time-to-1e-5 on the 3-mode workload")

@@ -218,6 +218,62 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
 hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int32_t* extents,
                             double* grid, int64_t n_points, double* split_out, void* hip_stream);
 
+/*
+ * Launch shape of the RK4 stage kernel of one function (merged layout).  The
+ * stencil of Eq. (17) in sector form is evaluated on tiles: the trailing
+ * `nfast` axes of the grid form a tile staged in LDS, the other axes are read
+ * as neighbour tiles from HBM, and a persistent grid of workgroups walks the
+ * tiles.  Shapes change the order of additions across axes only: results
+ * agree to rounding.
+ */
+typedef struct {
+  int32_t nfast;       /* trailing axes staged in LDS; 0 = untiled (generic) kernel */
+  int32_t threads;     /* workgroup size: multiple of 64 in [64, 512]; 0 = default rule */
+  int32_t xblock;      /* tile order over the 8 XCDs: 0 = contiguous eighths of the grid,
+                          B > 0 = interleaved blocks of B consecutive tiles */
+  int32_t pipe;        /* 1 = neighbour loads of the next lane round issued before the
+                          current round computes */
+  int32_t blocks;      /* out: persistent workgroups per launch */
+  int32_t tile_points; /* out: points per tile */
+  double stage_us;     /* out: stage time measured by hgf_autotune for this shape, else 0 */
+} hgf_tile_config;
+
+/* Current launch shape of function idx.  Errors: HGF_EINVAL. */
+hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* out);
+
+/*
+ * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe).
+ * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
+ * register budget) or asks a real grid for the untiled kernel;
+ * HGF_EUNSUPPORTED for split-layout functions (classical kernel only).  The
+ * function is unchanged on error.
+ */
+hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_config* cfg);
+
+/* flags of hgf_autotune */
+enum {
+  HGF_TUNE_DEFAULT = 0,     /* use cached shapes, measure the others and add them to the cache */
+  HGF_TUNE_CACHED_ONLY = 1, /* apply cached shapes only; measure nothing */
+  HGF_TUNE_FORCE = 2        /* measure every shape again and overwrite its cache entry */
+};
+
+/*
+ * Launch-shape autotuner.  For every distinct grid shape among the merged-
+ * layout functions of ops[0..n) (extents, precision, real or complex grid),
+ * times the RK4 step of one such function with step dt_us under each
+ * candidate shape (fast axes: the default and one fewer; every workgroup
+ * size whose last lane round is at least 3/4 full; both XCD orders; with
+ * and without pipelined loads) and applies the fastest to every function of
+ * that shape.  The timed steps run on the function's own buffers; its state
+ * is restored afterwards, so results are unaffected.  cache_path (may be NULL:
+ * no cache) names a text file of measured shapes keyed by device
+ * architecture and CU count; it is read first and rewritten when shapes were
+ * measured.  Errors: HGF_EINVAL (NULL ops, dt <= 0, unwritable cache),
+ * HGF_EDEVICE.  Synchronises hip_stream.
+ */
+hgf_status hgf_autotune(hgf_operator* ops, int32_t n, double dt_us, const char* cache_path, int32_t flags,
+                        void* hip_stream);
+
 /* Thread-local message describing the last error of this thread ("" if none). */
 const char* hgf_last_error(void);
 

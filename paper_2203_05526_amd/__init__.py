@@ -9,6 +9,7 @@ from .hgf import (  # noqa: F401
     HgfError,
     Operator,
     System,
+    autotune,
     define_system,
     evolve,
     evolve_batch,

@@ -8,9 +8,13 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
+#include <set>
+#include <sstream>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -127,20 +131,40 @@ static void check_stability(const std::vector<Function>& fns, double dt) {
 
 // ------------------------------------------------------------------ functions
 
-// Choose the fast (LDS-tiled) axes of the tiled stage kernel: the largest
-// number `nfast` <= 4 of trailing axes whose padded tile and tables fit in
-// 64 KB of LDS (nfast_req > 0 forces a value when it fits).  Sets
-// g.blocks = 0 (generic kernel) when HGF_STAGE_KERNEL=generic.
-static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real) {
+// HGF_STAGE_KERNEL=generic selects the untiled stage kernel for every grid.
+static bool stage_kernel_generic() {
+  const char* env = std::getenv("HGF_STAGE_KERNEL");
+  return env && std::string(env) == "generic";
+}
+
+// Launch shape of the tiled stage kernel.  Fields at -1 (nfast, xblock, pipe)
+// or 0 (threads) take the default rule below.
+struct TileChoice {
+  int nfast = -1;
+  int threads = 0;
+  int xblock = -1;
+  int pipe = -1;
+};
+
+// Pipelined neighbour loads keep the register budget only up to this many
+// slow axes (more spill to scratch).
+constexpr int kPipeMaxSlow = 9;
+
+// Configure the tiled stage kernel for grid g.  Default rule: the largest
+// number nfast <= 4 of trailing axes whose padded tile and tables fit in 64 KB
+// of LDS; 256 lanes when they cover the tile in at most kTileRounds rounds (the
+// fastest shape measured on the 6^10 grid), else the smallest multiple of 64
+// that does; contiguous XCD order; no pipelining.  Returns false (and sets
+// g.blocks = 0, the generic kernel) when the request cannot be met.
+static bool configure_tiles(GridArgs& g, int precision, bool real, const TileChoice& c) {
   g.blocks = 0;
   g.nfast = 0;
   g.real = 0;
-  const char* env = std::getenv("HGF_STAGE_KERNEL");
-  if (env && std::string(env) == "generic") return;
+  if (c.nfast == 0) return true;
   const int rs = precision == HGF_FP64 ? 8 : 4, ts = real ? rs : 2 * rs;
   int best = 0;
   for (int F = std::min(4, g.n); F >= 1; --F) {
-    if (nfast_req > 0 && F != nfast_req) continue;
+    if (c.nfast > 0 && F != c.nfast) continue;
     if (g.n - F > tiled_max_slow_axes()) continue;
     // padded LDS tile: (e_0 + 2) x prod_{q>=1} (e_q + 1), see k_rk4_tiled
     int64_t T = 1, padded = 1, esum = 0;
@@ -154,15 +178,16 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
     }
     const int cbits = F == 4 ? 4 : 5;
     if (emax > (1 << cbits) || padded >= 65536) continue;
-    // one point per lane; the workgroup is sized so that a tile takes at most
-    // kTileRounds rounds of lanes (the kernel's prefetch registers)
+    // one point per lane; a tile takes at most kTileRounds rounds of lanes
+    // (the kernel's prefetch registers)
     if (T > tiled_max_lane_groups()) continue;
-    // 256 lanes when they cover the tile in at most kTileRounds rounds (the
-    // fastest shape measured on the 6^10 grid), else the smallest multiple
-    // of 64 that does
-    int threads = T >= 256 ? 256 : (int)((T + 63) / 64 * 64);
-    if ((T + threads - 1) / threads > kTileRounds)
-      threads = (int)std::min<int64_t>(512, ((T + kTileRounds - 1) / kTileRounds + 63) / 64 * 64);
+    int threads = c.threads;
+    if (threads == 0) {
+      threads = T >= 256 ? 256 : (int)((T + 63) / 64 * 64);
+      if ((T + threads - 1) / threads > kTileRounds)
+        threads = (int)std::min<int64_t>(512, ((T + kTileRounds - 1) / kTileRounds + 63) / 64 * 64);
+    }
+    if (threads < 64 || threads > 512 || threads % 64 != 0) continue;
     if ((T + threads - 1) / threads > kTileRounds) continue;
     const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + esum * rs + 64;
     if (bytes > 65536) continue;
@@ -180,23 +205,36 @@ static void configure_tiles(GridArgs& g, int precision, int nfast_req, bool real
     }
     break;
   }
-  if (best == 0) return;
+  if (best == 0) return false;
   g.ntiles = g.points / g.tile_points;
   // 32-bit byte offsets in the tiled kernel (complex128 y is the widest operand)
   if (g.ntiles >= (int64_t)1 << 31 || g.points * 16 > (int64_t)0xffffffffLL) {
     g.blocks = 0;
     g.nfast = 0;
-    return;
+    return false;
+  }
+  g.xblock = std::max(0, c.xblock);
+  g.pipe = c.pipe > 0 ? 1 : 0;
+  if (g.pipe && g.n - g.nfast > kPipeMaxSlow) {
+    g.blocks = 0;
+    g.nfast = 0;
+    return false;
   }
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   g.real = real ? 1 : 0;
-  const int occ = tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, g.threads, precision, g.lds_bytes, real, true);
+  const int occ =
+      tiled_max_blocks_per_cu(g.nfast, g.n - g.nfast, g.threads, precision, g.lds_bytes, real, g.pipe ? 2 : 1);
+  if (occ <= 0) {
+    g.blocks = 0;
+    g.nfast = 0;
+    g.real = 0;
+    return false;
+  }
   const int64_t want = (int64_t)cus * occ;
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
-  g.xblock = 0;
-  if (const char* xb = std::getenv("HGF_XCD_BLOCK")) g.xblock = std::max(0, std::atoi(xb));
+  return true;
 }
 
 // Per-tile records of the slow-axis terms for k_rk4_tiled (layout of
@@ -238,10 +276,20 @@ static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) 
   return out;
 }
 
+// Device copy of the tile records of grid g (caller owns the buffer).
+static void* upload_tile_records(const GridArgs& g, const SectorTables& t, int precision) {
+  std::vector<char> rec = precision == HGF_FP64 ? tile_records<double>(g, t) : tile_records<float>(g, t);
+  void* d = dmalloc(rec.size());
+  hipError_t e = hipMemcpy(d, rec.data(), rec.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dfree(d);
+    hip_check(e, "upload tile records");
+  }
+  return d;
+}
+
 static void build_tile_records(Function& f, int precision) {
-  std::vector<char> rec = precision == HGF_FP64 ? tile_records<double>(f.ga, f.tab) : tile_records<float>(f.ga, f.tab);
-  f.ttab = dmalloc(rec.size());
-  hip_check(hipMemcpy(f.ttab, rec.data(), rec.size(), hipMemcpyHostToDevice), "upload tile records");
+  f.ttab = upload_tile_records(f.ga, f.tab, precision);
   f.ga.tiles = f.ttab;
 }
 
@@ -268,7 +316,7 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
-  configure_tiles(g, precision, -1, want_real);
+  if (!stage_kernel_generic()) configure_tiles(g, precision, want_real, TileChoice{});
   f.real = g.real != 0;
   // device tables: lam (double2), beta (double), lam_f (float2), beta_f (float)
   const int tot = off;
@@ -712,7 +760,8 @@ static StepPlan* build_plan(const std::vector<PlanItem>& items) {
     gl.nmem = (int)mem.size();
     gl.total_tiles = tiles;
     const int occ =
-        tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real, mem.size() == 1);
+        tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real,
+                                mem.size() == 1 ? (kv.second[0].f->ga.pipe ? 2 : 1) : 0);
     gl.blocks = (int)std::max<int64_t>(8, std::min<int64_t>((int64_t)cus * occ, 8 * ((tiles + 7) / 8)));
     void* d = dmalloc(mem.size() * sizeof(MemberArgs));
     plan->dmem.push_back(d);
@@ -950,6 +999,240 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
     ops[i]->steps_done += steps[i];
     ops[i]->time_us += steps[i] * dt[i];
   }
+}
+
+// ------------------------------------------------------------------ launch-shape autotuner
+// The tiled stage kernel's launch shape (fast axes, workgroup size, XCD tile
+// order, pipelined loads) is chosen per grid shape by timing candidate shapes
+// on the function's own buffers.  Results are kept in a text cache, one line
+// per shape: "<key> <nfast> <threads> <xblock> <pipe> <stage_us>", the key
+// naming the device (architecture, CU count), precision, real or complex grid
+// and the extents.
+
+// Re-configure one function's stage kernel; the function is left unchanged
+// when the shape is not feasible (HGF_EINVAL).
+static void retile(Function& f, int precision, const TileChoice& c) {
+  if (f.split) {
+    if (c.nfast == 0) return;
+    fail(HGF_EUNSUPPORTED, "split-layout functions run the classical stage kernel only");
+  }
+  GridArgs g = f.ga;
+  if (c.nfast == 0) {
+    if (f.real) fail(HGF_EINVAL, "a real grid needs the tiled stage kernel (nfast >= 1)");
+    g.blocks = 0;
+    g.nfast = 0;
+    g.real = 0;
+    g.tile_points = 1;
+    g.ntiles = g.points;
+    g.xblock = 0;
+    g.pipe = 0;
+  } else if (!configure_tiles(g, precision, f.real, c) || (g.real != 0) != f.real) {
+    fail(HGF_EINVAL, "tile configuration not feasible for this grid");
+  }
+  g.tiles = nullptr;
+  void* rec = g.blocks > 0 ? upload_tile_records(g, f.tab, precision) : nullptr;
+  dfree(f.ttab);
+  f.ttab = rec;
+  f.ga = g;
+  f.ga.tiles = rec;
+  f.tuned_us = 0.0;
+}
+
+static std::string device_tag() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t prop;
+  hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+static std::string tune_key(const std::string& dev, const Function& f, int precision) {
+  std::string k = dev + (precision == HGF_FP64 ? ":fp64" : ":mixed") + (f.real ? ":real:" : ":complex:");
+  for (int j = 0; j < f.ga.n; ++j) k += (j ? "x" : "") + std::to_string(f.ga.ext[j]);
+  return k;
+}
+
+struct TuneEntry {
+  TileChoice c;
+  double us = 0.0;
+};
+
+static std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
+  std::map<std::string, TuneEntry> m;
+  if (!path || !*path) return m;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    TuneEntry e;
+    if (ls >> key >> e.c.nfast >> e.c.threads >> e.c.xblock >> e.c.pipe >> e.us) m[key] = e;
+  }
+  return m;
+}
+
+static void write_tune_cache(const char* path, const std::map<std::string, TuneEntry>& m) {
+  if (!path || !*path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) fail(HGF_EINVAL, std::string("cannot write tuning cache ") + path);
+    out.precision(6);
+    for (auto& kv : m)
+      out << kv.first << ' ' << kv.second.c.nfast << ' ' << kv.second.c.threads << ' ' << kv.second.c.xblock << ' '
+          << kv.second.c.pipe << ' ' << kv.second.us << '\n';
+    if (!out) fail(HGF_EINVAL, std::string("cannot write tuning cache ") + path);
+  }
+  if (std::rename(tmp.c_str(), path) != 0) fail(HGF_EINVAL, std::string("cannot replace tuning cache ") + path);
+}
+
+// Candidate launch shapes of a function: the default number of fast axes and
+// one fewer; every workgroup size (multiple of 64, <= 512) whose last lane
+// round is at least 3/4 full or that the default rule picks; contiguous and
+// interleaved XCD orders; pipelined loads where the registers allow.
+static std::vector<TileChoice> tune_candidates(const Function& f, int precision) {
+  std::vector<TileChoice> out;
+  if (f.split || f.ga.blocks == 0) return out;
+  const int fmax = f.ga.nfast;
+  for (int F = fmax; F >= std::max(1, fmax - 1); --F) {
+    int64_t T = 1;
+    for (int q = 0; q < F; ++q) T *= f.ga.ext[f.ga.n - F + q];
+    GridArgs probe = f.ga;
+    TileChoice dflt;
+    dflt.nfast = F;
+    if (!configure_tiles(probe, precision, f.real, dflt)) continue;
+    for (int th = 64; th <= 512; th += 64) {
+      const int64_t rounds = (T + th - 1) / th;
+      if (rounds > kTileRounds) continue;
+      const double fill = (double)T / (double)(rounds * th);
+      if (fill < 0.75 && th != probe.threads) continue;
+      for (int xb : {0, 128})
+        for (int pp : {0, 1}) {
+          if (pp && f.ga.n - F > kPipeMaxSlow) continue;
+          TileChoice c;
+          c.nfast = F;
+          c.threads = th;
+          c.xblock = xb;
+          c.pipe = pp;
+          GridArgs g = f.ga;
+          if (configure_tiles(g, precision, f.real, c)) out.push_back(c);
+        }
+    }
+  }
+  return out;
+}
+
+// Mean stage time (us) of `steps` RK4 steps of one function alone.
+static double time_function_steps(Function& f, int precision, double h, int* flag, int steps, hipStream_t st) {
+  std::unique_ptr<StepPlan> plan(build_plan({PlanItem{&f, precision, h}}));
+  run_plan_step(*plan, flag, st);  // warm-up
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "event");
+  hipError_t e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    hip_check(e, "event");
+  }
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eg{a, b};
+  hip_check(hipEventRecord(a, st), "event record");
+  for (int i = 0; i < steps; ++i) run_plan_step(*plan, flag, st);
+  hip_check(hipEventRecord(b, st), "event record");
+  hip_check(hipEventSynchronize(b), "event sync");
+  hip_check(hipGetLastError(), "kernel launch");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, a, b), "event time");
+  return 1e3 * (double)ms / (4.0 * steps);
+}
+
+static TileChoice current_choice(const Function& f) {
+  TileChoice c;
+  c.nfast = f.ga.blocks > 0 ? f.ga.nfast : 0;
+  c.threads = f.ga.threads;
+  c.xblock = f.ga.xblock;
+  c.pipe = f.ga.pipe;
+  return c;
+}
+
+static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_path, int flags, hipStream_t st) {
+  const std::string dev = device_tag();
+  std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
+  std::set<std::string> fresh;  // shapes measured by this call
+  bool measured = false;
+  DBuf dflag(sizeof(int));
+  for (int i = 0; i < n; ++i) {
+    hgf_operator_s* op = ops[i];
+    if (op->layout != HGF_MERGED) continue;
+    for (auto& f : op->fn) {
+      if (f.ga.blocks == 0 && f.real) continue;
+      const std::string key = tune_key(dev, f, op->precision);
+      auto it = cache.find(key);
+      const bool known = it != cache.end() && (!(flags & HGF_TUNE_FORCE) || fresh.count(key));
+      if (known) {
+        if (f.ga.blocks > 0 || it->second.c.nfast == 0) {
+          try {
+            retile(f, op->precision, it->second.c);
+            f.tuned_us = it->second.us;
+          } catch (const Error&) {
+            // a cached shape that no longer fits (another build): keep the current one
+          }
+        }
+        continue;
+      }
+      if (flags & HGF_TUNE_CACHED_ONLY) continue;
+      std::vector<TileChoice> cands = tune_candidates(f, op->precision);
+      if (cands.empty()) continue;
+      // state backup: the timed steps advance y
+      const size_t bytes = state_bytes(f);
+      if (!f.ybak) f.ybak = dmalloc(bytes);
+      hip_check(hipMemcpyAsync(f.ybak, f.y, bytes, hipMemcpyDeviceToDevice, st), "backup");
+      const TileChoice start = current_choice(f);
+      TuneEntry best;
+      best.us = 1e300;
+      try {
+        // enough steps for ~2 ms of timed work per candidate
+        const double t0 = time_function_steps(f, op->precision, h, dflag.as<int>(), 1, st);
+        const int steps = (int)std::max(2.0, std::min(200.0, 2000.0 / std::max(1e-3, 4.0 * t0)));
+        for (const TileChoice& c : cands) {
+          retile(f, op->precision, c);
+          const double us = time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st);
+          if (us < best.us) {
+            best.us = us;
+            best.c = c;
+          }
+        }
+        retile(f, op->precision, best.c);
+      } catch (const Error&) {
+        (void)hipStreamSynchronize(st);
+        try {
+          retile(f, op->precision, start);
+        } catch (const Error&) {
+        }
+        (void)hipMemcpy(f.y, f.ybak, bytes, hipMemcpyDeviceToDevice);
+        launch_shadow(op->precision, f.ga, f.y, f.yf, nullptr);
+        (void)hipDeviceSynchronize();
+        drop_plan(op);
+        throw;
+      }
+      f.tuned_us = best.us;
+      hip_check(hipMemcpyAsync(f.y, f.ybak, bytes, hipMemcpyDeviceToDevice, st), "restore");
+      launch_shadow(op->precision, f.ga, f.y, f.yf, st);
+      hip_check(hipStreamSynchronize(st), "synchronize");
+      cache[key] = best;
+      fresh.insert(key);
+      measured = true;
+    }
+    drop_plan(op);
+  }
+  if (measured) write_tune_cache(cache_path, cache);
 }
 
 // ------------------------------------------------------------------ expectation
@@ -1342,6 +1625,58 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
     int nreal = 0;
     for (auto& f : op->fn) nreal += f.real ? 1 : 0;
     info->real_functions = nreal;
+  });
+}
+
+hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* out) {
+  return guarded([&] {
+    if (!op || !out) fail(HGF_EINVAL, "NULL argument");
+    if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
+    const Function& f = op->fn[idx];
+    const bool tiled = f.ga.blocks > 0;
+    out->nfast = tiled ? f.ga.nfast : 0;
+    out->threads = tiled ? f.ga.threads : 0;
+    out->xblock = tiled ? f.ga.xblock : 0;
+    out->pipe = tiled ? f.ga.pipe : 0;
+    out->blocks = tiled ? f.ga.blocks : 0;
+    out->tile_points = tiled ? (int32_t)f.ga.tile_points : 1;
+    out->stage_us = f.tuned_us;
+  });
+}
+
+hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_config* cfg) {
+  return guarded([&] {
+    if (!op || !cfg) fail(HGF_EINVAL, "NULL argument");
+    if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
+    if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || (cfg->pipe != 0 && cfg->pipe != 1))
+      fail(HGF_EINVAL, "negative tile parameter or pipe not 0/1");
+    TileChoice c;
+    c.nfast = cfg->nfast;
+    c.threads = cfg->threads;
+    c.xblock = cfg->xblock;
+    c.pipe = cfg->pipe;
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
+    retile(op->fn[idx], op->precision, c);
+    drop_plan(op);
+  });
+}
+
+hgf_status hgf_autotune(hgf_operator* ops, int32_t n, double dt_us, const char* cache_path, int32_t flags,
+                        void* hip_stream) {
+  return guarded([&] {
+    if (!ops || n < 0) fail(HGF_EINVAL, "NULL ops or negative count");
+    if (!(dt_us > 0.0) || !std::isfinite(dt_us)) fail(HGF_EINVAL, "dt must be positive and finite");
+    if (flags & ~(HGF_TUNE_CACHED_ONLY | HGF_TUNE_FORCE)) fail(HGF_EINVAL, "unknown autotune flag");
+    for (int i = 0; i < n; ++i) {
+      if (!ops[i]) fail(HGF_EINVAL, "NULL operator");
+      if (ops[i]->device != ops[0]->device) fail(HGF_EINVAL, "operators on different devices");
+    }
+    if (n == 0) return;
+    hip_check(hipSetDevice(ops[0]->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    autotune_impl(ops, n, dt_us, cache_path, flags, st);
   });
 }
 

@@ -66,12 +66,6 @@ int num_params(int n);
 double generator_bound(const SectorTables& t);
 
 // ------------------------------------------------------------------ device layout
-// Device coefficient block of one grid, in FP64 and FP32 copies.
-struct DevTables {
-  // offsets into the concatenated per-axis arrays
-  int off[kMaxModes];
-};
-
 // Everything a stage kernel needs to know about one grid; passed by value.
 struct GridArgs {
   int n;                    // number of axes
@@ -92,6 +86,7 @@ struct GridArgs {
   int real;                 // tiled kernel on a real grid (real generator and data)
   int lds_bytes;            // dynamic LDS of the tiled kernel
   int xblock;               // tile order across XCDs: 0 contiguous eighths, B > 0 blocks of B tiles
+  int pipe;                 // single-grid kernel issues the loads of the next lane round early
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
   double lam0_re, lam0_im;
   double alpha[kMaxModes];
@@ -146,6 +141,7 @@ struct Function {
   cd g0 = 0.0, cx = 1.0, cy = 1.0;
   cd ax = 0.0, ay = 0.0;   // dc_x/dt = ax c_x, dc_y/dt = ay c_y
   std::vector<std::pair<int64_t, cd>> sources;  // R' = L R + c_x c_y S
+  double tuned_us = 0.0;  // stage time measured by the autotuner for the current shape
 };
 
 struct StepPlan;

@@ -33,8 +33,9 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
+// form: 0 grouped kernel, 1 single-grid kernel, 2 single-grid pipelined kernel
 int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real,
-                            bool single);
+                            int form);
 int tiled_max_slow_axes();
 int tiled_max_lane_groups();
 void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st);

@@ -504,23 +504,23 @@ void launch_group_c64(const GroupLaunch&, int, int*, hipStream_t);
 void launch_group_c128(const GroupLaunch&, int, int*, hipStream_t);
 void launch_group_r32(const GroupLaunch&, int, int*, hipStream_t);
 void launch_group_r64(const GroupLaunch&, int, int*, hipStream_t);
-int occupancy_group_c64(int, int, int, int, bool);
-int occupancy_group_c128(int, int, int, int, bool);
-int occupancy_group_r32(int, int, int, int, bool);
-int occupancy_group_r64(int, int, int, int, bool);
+int occupancy_group_c64(int, int, int, int, int);
+int occupancy_group_c128(int, int, int, int, int);
+int occupancy_group_r32(int, int, int, int, int);
+int occupancy_group_r64(int, int, int, int, int);
 
 constexpr int kMaxSlow = 12;
 int tiled_max_slow_axes() { return kMaxSlow; }
 int tiled_max_lane_groups() { return kTileRounds * 512; }
 
-int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real, bool single) {
+int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real, int form) {
   int nb;
   if (real)
-    nb = precision == HGF_FP64 ? occupancy_group_r64(nfast, nslow, threads, lds_bytes, single)
-                               : occupancy_group_r32(nfast, nslow, threads, lds_bytes, single);
+    nb = precision == HGF_FP64 ? occupancy_group_r64(nfast, nslow, threads, lds_bytes, form)
+                               : occupancy_group_r32(nfast, nslow, threads, lds_bytes, form);
   else
-    nb = precision == HGF_FP64 ? occupancy_group_c128(nfast, nslow, threads, lds_bytes, single)
-                               : occupancy_group_c64(nfast, nslow, threads, lds_bytes, single);
+    nb = precision == HGF_FP64 ? occupancy_group_c128(nfast, nslow, threads, lds_bytes, form)
+                               : occupancy_group_c64(nfast, nslow, threads, lds_bytes, form);
   return nb < 1 ? 1 : nb;
 }
 

@@ -147,8 +147,15 @@ __device__ __forceinline__ void st_pack(P* base, uint32_t byte_off, const P& v) 
 // ---- single-grid form: one member, its record passed by value as kernel
 // arguments (a separate kernel: reading member fields through a pointer kept
 // more values live and lowered the occupancy measured on the 6^10 grid).
-template <int NF, int NS, typename TS, typename TY>
-__global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
+// Wave target of the tiled kernel: the pipelined float form is held to 5 waves
+// per SIMD (<= 102 VGPRs), the occupancy of the unpipelined form.
+template <bool PIPE, typename TS>
+struct TiledWaves {
+  static constexpr int value = (PIPE && sizeof(TS) == 4) ? 5 : 1;
+};
+
+template <int NF, int NS, typename TS, typename TY, bool PIPE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<PIPE, TS>::value))) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
                                                    const TS* __restrict__ x1, TY* __restrict__ y,
                                                    TS* __restrict__ yf, TS* __restrict__ out, double h,
                                                    int* __restrict__ flag) {
@@ -272,17 +279,34 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
       soff[j] = rec->off[j];
       scoef[j] = rec->coef[j];
     }
+    // PIPE: the global loads of round r + 1 are issued before round r
+    // computes, so that two rounds of neighbour loads are in flight per wave
+    PS sv[2 * (NS > 0 ? NS : 1)], sn[2 * (NS > 0 ? NS : 1)];
+    PS xb, xn;
+    PY yv, yn;
+    if constexpr (PIPE) {
+      const uint32_t e0 = tbase + (uint32_t)(V * min(tid, G - 1));
+#pragma unroll
+      for (int j = 0; j < 2 * NS; ++j) sv[j] = ld_pack((const PS*)in, (e0 + (uint32_t)soff[j]) * SB);
+      if (stage >= 2) xb = ld_pack_nt((const PS*)x1, e0 * SB);
+      if (stage == 4) yv = ld_pack_nt((const PY*)y, e0 * YB);
+    }
     for (int r = 0; r < rounds; ++r) {
       const int gi = tid + r * nt;
       const int pb = V * min(gi, G - 1);
       const uint32_t e0 = tbase + (uint32_t)pb;
-      PS sv[2 * (NS > 0 ? NS : 1)];
+      if constexpr (!PIPE) {
 #pragma unroll
-      for (int j = 0; j < 2 * NS; ++j) sv[j] = ld_pack((const PS*)in, (e0 + (uint32_t)soff[j]) * SB);
-      PS xb;
-      PY yv;
-      if (stage >= 2) xb = ld_pack_nt((const PS*)x1, e0 * SB);
-      if (stage == 4) yv = ld_pack_nt((const PY*)y, e0 * YB);
+        for (int j = 0; j < 2 * NS; ++j) sv[j] = ld_pack((const PS*)in, (e0 + (uint32_t)soff[j]) * SB);
+        if (stage >= 2) xb = ld_pack_nt((const PS*)x1, e0 * SB);
+        if (stage == 4) yv = ld_pack_nt((const PY*)y, e0 * YB);
+      } else if (r + 1 < rounds) {
+        const uint32_t e1 = tbase + (uint32_t)(V * min(gi + nt, G - 1));
+#pragma unroll
+        for (int j = 0; j < 2 * NS; ++j) sn[j] = ld_pack((const PS*)in, (e1 + (uint32_t)soff[j]) * SB);
+        if (stage >= 2) xn = ld_pack_nt((const PS*)x1, e1 * SB);
+        if (stage == 4) yn = ld_pack_nt((const PY*)y, e1 * YB);
+      }
       PS o;
       PY yo;
 #pragma unroll
@@ -331,6 +355,12 @@ __global__ __launch_bounds__(512) void k_rk4_tiled(GridArgs g, int stage, const 
           st_pack_nt((PY*)y, e0 * YB, yo);
           if (yf) st_pack((PS*)yf, e0 * SB, o);
         }
+      }
+      if constexpr (PIPE) {
+#pragma unroll
+        for (int j = 0; j < 2 * NS; ++j) sv[j] = sn[j];
+        xb = xn;
+        yv = yn;
       }
     }
     __syncthreads();
@@ -528,9 +558,14 @@ static void group_launch_nf(const GroupLaunch& gl, int stage, int* flag, hipStre
   case K:                                                                                                    \
     if (gl.nmem == 1) {                                                                                      \
       const MemberArgs& a = gl.single;                                                                       \
-      hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY>), dim3(gl.blocks), dim3(gl.threads), gl.lds_bytes, st,  \
-                         a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1, (TY*)a.y, (TS*)a.yf,       \
-                         (TS*)a.out[stage - 1], a.h, flag);                                                  \
+      if (a.g.pipe)                                                                                          \
+        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, true>), dim3(gl.blocks), dim3(gl.threads),            \
+                           gl.lds_bytes, st, a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1,        \
+                           (TY*)a.y, (TS*)a.yf, (TS*)a.out[stage - 1], a.h, flag);                           \
+      else                                                                                                   \
+        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, false>), dim3(gl.blocks), dim3(gl.threads),           \
+                           gl.lds_bytes, st, a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1,        \
+                           (TY*)a.y, (TS*)a.yf, (TS*)a.out[stage - 1], a.h, flag);                           \
     } else {                                                                                                 \
       hipLaunchKernelGGL((k_rk4_group<NF, K, TS, TY>), dim3(gl.blocks), dim3(gl.threads), gl.lds_bytes, st,  \
                          gl.members, gl.nmem, gl.total_tiles, stage, flag);                                  \
@@ -553,17 +588,20 @@ static void group_launch_all(const GroupLaunch& gl, int stage, int* flag, hipStr
 }
 
 template <typename TS, typename TY, int NF>
-static int group_occ_nf(int ns, int threads, int lds_bytes, bool single) {
+static int group_occ_nf(int ns, int threads, int lds_bytes, int single) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (ns) {
 #define HGF_CASE(K)                                                                                          \
   case K: {                                                                                                  \
-    int a = 0, b = 0;                                                                                        \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_rk4_group<NF, K, TS, TY>, threads, lds_bytes);    \
-    if (e == hipSuccess)                                                                                     \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_rk4_tiled<NF, K, TS, TY>, threads, lds_bytes);  \
-    nb = single ? b : a;                                                                                     \
+    if (single == 0)                                                                                         \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_group<NF, K, TS, TY>, threads, lds_bytes); \
+    else if (single == 1)                                                                                    \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, false>, threads,      \
+                                                       lds_bytes);                                           \
+    else                                                                                                     \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, true>, threads,       \
+                                                       lds_bytes);                                           \
     break;                                                                                                   \
   }
     HGF_NS_CASES(HGF_CASE)
@@ -574,7 +612,7 @@ static int group_occ_nf(int ns, int threads, int lds_bytes, bool single) {
 }
 
 template <typename TS, typename TY>
-static int group_occ_all(int nfast, int nslow, int threads, int lds_bytes, bool single) {
+static int group_occ_all(int nfast, int nslow, int threads, int lds_bytes, int single) {
   switch (nfast) {
     case 1: return group_occ_nf<TS, TY, 1>(nslow, threads, lds_bytes, single);
     case 2: return group_occ_nf<TS, TY, 2>(nslow, threads, lds_bytes, single);
@@ -587,7 +625,7 @@ static int group_occ_all(int nfast, int nslow, int threads, int lds_bytes, bool 
   void launch_group_##SUFFIX(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {              \
     group_launch_all<TS, TY>(gl, stage, flag, st);                                                       \
   }                                                                                                      \
-  int occupancy_group_##SUFFIX(int nfast, int nslow, int threads, int lds_bytes, bool single) {          \
+  int occupancy_group_##SUFFIX(int nfast, int nslow, int threads, int lds_bytes, int single) {           \
     return group_occ_all<TS, TY>(nfast, nslow, threads, lds_bytes, single);                              \
   }
 

@@ -64,6 +64,14 @@ class _Info(ctypes.Structure):
                 ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32)]
 
 
+class _TileConfig(ctypes.Structure):
+    _fields_ = [("nfast", ctypes.c_int32), ("threads", ctypes.c_int32), ("xblock", ctypes.c_int32),
+                ("pipe", ctypes.c_int32), ("blocks", ctypes.c_int32), ("tile_points", ctypes.c_int32),
+                ("stage_us", ctypes.c_double)]
+
+
+TUNE_FLAGS = {"default": 0, "cached_only": 1, "force": 2}
+
 _lib = None
 
 
@@ -91,6 +99,10 @@ def load_library(path: str = LIB_PATH):
                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
     lib.hgf_get_function.argtypes = [vp, ctypes.c_int32, _i32p, _i32p, _f64p, ctypes.c_int64, _f64p, vp]
+    lib.hgf_get_tile_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(_TileConfig)]
+    lib.hgf_set_tile_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(_TileConfig)]
+    lib.hgf_autotune.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_double, ctypes.c_char_p,
+                                 ctypes.c_int32, vp]
     lib.hgf_last_error.restype = ctypes.c_char_p
     lib.hgf_last_error.argtypes = []
     lib.hgf_version.restype = ctypes.c_char_p
@@ -242,6 +254,17 @@ class Operator:
                  "cy": complex(extra[2 * n + 4], extra[2 * n + 5])}
         return tuple(int(x) for x in d), tuple(int(x) for x in e), grid.reshape(tuple(e)), split
 
+    def tile_config(self, idx: int) -> dict:
+        """hgf_get_tile_config: launch shape of function ``idx``."""
+        c = _TileConfig()
+        _check(_lib.hgf_get_tile_config(self._h, idx, ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in _TileConfig._fields_}
+
+    def set_tile_config(self, idx: int, nfast: int, threads: int = 0, xblock: int = 0, pipe: int = 0) -> None:
+        """hgf_set_tile_config: force the launch shape of function ``idx``."""
+        c = _TileConfig(nfast, threads, xblock, pipe, 0, 0, 0.0)
+        _check(_lib.hgf_set_tile_config(self._h, idx, ctypes.byref(c)))
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hgf_destroy_operator(self._h)
@@ -268,6 +291,17 @@ def evolve_batch(ops: Sequence[Operator], t_total, dt, stream=None) -> None:
     t = _f64(np.broadcast_to(np.asarray(t_total, dtype=np.float64), (n,)))
     h = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)))
     _check(_lib.hgf_evolve_batch(arr, n, t.ctypes.data_as(_f64p), h.ctypes.data_as(_f64p), _stream(stream)))
+
+
+def autotune(ops: Sequence[Operator], dt: float, cache: Optional[str] = None, mode: str = "default",
+             stream=None) -> None:
+    """hgf_autotune: measure (or load from the text cache ``cache``) the
+    fastest stage-kernel launch shape of every grid shape among ``ops`` for
+    steps of ``dt``; mode is "default", "cached_only" or "force"."""
+    n = len(ops)
+    arr = (ctypes.c_void_p * max(n, 1))(*[o.handle.value for o in ops])
+    path = cache.encode() if cache else None
+    _check(_lib.hgf_autotune(arr, n, float(dt), path, TUNE_FLAGS[mode], _stream(stream)))
 
 
 def _state_desc(system: System, state):

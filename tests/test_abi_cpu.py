@@ -81,3 +81,7 @@ def test_null_arguments_are_rejected(hgf):
     assert b"NULL" in lib.hgf_last_error()
     assert lib.hgf_evolve(None, 1.0, 0.1, None) == -1
     assert lib.hgf_num_params(None) == -1
+    assert lib.hgf_get_tile_config(None, 0, None) == -1
+    assert lib.hgf_set_tile_config(None, 0, None) == -1
+    assert lib.hgf_autotune(None, 1, 1e-3, None, 0, None) == -1
+    assert b"NULL" in lib.hgf_last_error()

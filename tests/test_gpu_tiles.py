@@ -1,0 +1,159 @@
+"""Launch shapes of the tiled RK4 stage kernel and the autotuner that picks
+them: every shape computes the same RK4 steps (to rounding) and matches the
+FP64 oracle; the autotuner's cache round-trips; infeasible shapes are
+rejected without changing the operator."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import announce, gpu_number_grids, library, max_rel_err, oracle_number_grids
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hgf():
+    return library()
+
+
+def _shapes(tile_points):
+    """(nfast, threads, xblock, pipe) samples for one tile size: the default
+    workgroup, the smallest and the largest feasible one, odd XCD blocks."""
+    ths = [t for t in range(64, 513, 64) if -(-tile_points // t) <= 8]
+    return [(0, 0, 0), (ths[0], 3, 1), (ths[-1], 128, 0), (ths[len(ths) // 2], 1, 1)]
+
+
+def _apply(hgf, op, nfast, threads, xblock, pipe):
+    """Set the shape on every function where it is feasible; returns how many took it."""
+    took = 0
+    for i in range(op.info()["n_functions"]):
+        try:
+            op.set_tile_config(i, nfast, threads, xblock, pipe)
+            took += 1
+        except hgf.HgfError as e:
+            assert e.status == "HGF_EINVAL"
+    return took
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["real-diagonal", "complex-bidiagonal"])
+def test_forced_tile_shapes_agree_and_match_oracle(hgf, precision, kind):
+    cutoff = (3, 6, 6, 6, 6) if kind == "real-diagonal" else (3, 5, 4, 6, 3)
+    announce(f"forced tile shapes {kind} {precision}")
+    s = synth.random_system(cutoff, 51, scale=3.0, n_th=0.3)
+    rng = np.random.default_rng(51)
+    if kind == "real-diagonal":
+        fac = [np.diag(rng.uniform(0.5, 1.5, size=c)).astype(np.complex128) for c in cutoff]
+    else:
+        fac = [np.triu(np.tril(rng.normal(size=(c, c)) + 1j * rng.normal(size=(c, c)), 1)) for c in cutoff]
+    S = hgf.define_system(s)
+    T, dt = 0.02, 1e-3
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    same = 1e-13 if precision == "fp64" else 1e-6
+    base = hgf.map_operator(S, factors=fac, precision=precision)
+    hgf.evolve(base, T, dt)
+    base_grids = gpu_number_grids(base, cutoff)
+    assert max_rel_err(base_grids, ref) < tol
+    tried = 0
+    for nfast in (1, 2, 3, 4):
+        tile = int(np.prod(cutoff[len(cutoff) - nfast:]))
+        for threads, xblock, pipe in _shapes(tile):
+            op = hgf.map_operator(S, factors=fac, precision=precision)
+            if _apply(hgf, op, nfast, threads, xblock, pipe) == 0:
+                continue
+            announce(f"  nfast={nfast} threads={threads} xblock={xblock} pipe={pipe}")
+            hgf.evolve(op, T, dt)
+            got = gpu_number_grids(op, cutoff)
+            assert max_rel_err(got, ref) < tol, (nfast, threads, xblock, pipe)
+            assert max_rel_err(got, base_grids) < same, (nfast, threads, xblock, pipe)
+            tried += 1
+    assert tried >= 10
+    if kind == "complex-bidiagonal":  # the untiled kernel too
+        op = hgf.map_operator(S, factors=fac, precision=precision)
+        assert _apply(hgf, op, 0, 0, 0, 0) == op.info()["n_functions"]
+        assert op.tile_config(0)["nfast"] == 0
+        hgf.evolve(op, T, dt)
+        assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
+
+
+def test_tile_config_rejects_infeasible_shapes(hgf):
+    cutoff = (3, 6, 6, 6, 6)
+    announce("tile config errors")
+    s = synth.random_system(cutoff, 52, scale=3.0)
+    S = hgf.define_system(s)
+    fac = [np.eye(c, dtype=np.complex128) * 0.5 for c in cutoff]
+    op = hgf.map_operator(S, factors=fac, precision="mixed")
+    assert op.info()["real_functions"] == 1
+    before = op.tile_config(0)
+    assert before["nfast"] >= 1 and before["blocks"] > 0
+    bad = [(0, 0, 0, 0),      # a real grid needs the tiled kernel
+           (4, 100, 0, 0),    # not a multiple of 64
+           (4, 128, 0, 0),    # 1296-point tile in more than 8 lane rounds
+           (4, 1024, 0, 0),   # above 512 lanes
+           (6, 0, 0, 0),      # more fast axes than the grid has
+           (4, 256, 0, 2)]    # pipe is 0 or 1
+    for cfg in bad:
+        with pytest.raises(hgf.HgfError) as e:
+            op.set_tile_config(0, *cfg)
+        assert e.value.status == "HGF_EINVAL", cfg
+        assert op.tile_config(0) == before
+    with pytest.raises(hgf.HgfError) as e:
+        op.set_tile_config(3, 4)
+    assert e.value.status == "HGF_EINVAL"
+    one = np.ones((1, len(cutoff)), dtype=np.int32)
+    sp = hgf.map_operator(S, sparse=(one, one, np.array([1.0 + 0j])), layout="split", precision="fp64")
+    with pytest.raises(hgf.HgfError) as e:
+        sp.set_tile_config(0, 2)
+    assert e.value.status == "HGF_EUNSUPPORTED"
+
+
+def test_autotune_cache_and_results(hgf, tmp_path):
+    """The autotuner measures each distinct shape once, writes the cache,
+    leaves the evolved states unchanged, and a later call applies the cached
+    shapes without measuring."""
+    announce("autotune")
+    cache = str(tmp_path / "tune.txt")
+    T, dt = 0.02, 1e-3
+    cases = []
+    for cutoff, seed in (((3, 6, 6, 6, 6), 53), ((4, 5, 7), 54)):
+        s = synth.random_system(cutoff, seed, scale=3.0, n_th=0.2)
+        rng = np.random.default_rng(seed)
+        fac = [np.diag(rng.uniform(0.5, 1.5, size=c)).astype(np.complex128) for c in cutoff]
+        S = hgf.define_system(s)
+        ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+        cases.append((cutoff, S, fac, ref))
+    ops = [hgf.map_operator(S, factors=fac, precision="mixed") for _, S, fac, _ in cases]
+    twin = hgf.map_operator(cases[0][1], factors=cases[0][2], precision="mixed")
+    hgf.autotune(ops + [twin], dt, cache=cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 2, lines
+    assert any(":mixed:real:3x6x6x6x6 " in ln for ln in lines)
+    assert any(":mixed:real:4x5x7 " in ln for ln in lines)
+    for op in ops:
+        cfg = op.tile_config(0)
+        assert cfg["stage_us"] > 0.0 and cfg["blocks"] > 0
+    assert twin.tile_config(0) == ops[0].tile_config(0)
+    for op, (cutoff, _, _, ref) in zip(ops, cases):
+        hgf.evolve(op, T, dt)
+        assert max_rel_err(gpu_number_grids(op, cutoff), ref) < MIXED_TOL
+    # cached shapes are applied to new operators without measuring
+    fresh = hgf.map_operator(cases[0][1], factors=cases[0][2], precision="mixed")
+    hgf.autotune([fresh], dt, cache=cache, mode="cached_only")
+    a, b = fresh.tile_config(0), ops[0].tile_config(0)
+    assert {k: a[k] for k in ("nfast", "threads", "xblock", "pipe")} == \
+        {k: b[k] for k in ("nfast", "threads", "xblock", "pipe")}
+    # force re-measures and rewrites the entry in place
+    hgf.autotune([fresh], dt, cache=cache, mode="force")
+    assert len(open(cache).read().splitlines()) == 2
+    hgf.evolve(fresh, T, dt)
+    assert max_rel_err(gpu_number_grids(fresh, cases[0][0]), cases[0][3]) < MIXED_TOL
+    # no cache path: measure and apply only
+    nocache = hgf.map_operator(cases[1][1], factors=cases[1][2], precision="mixed")
+    hgf.autotune([nocache], dt)
+    assert nocache.tile_config(0)["stage_us"] > 0.0
