@@ -52,7 +52,7 @@ def bytes_per_point_stage(precision: str, real: bool) -> float:
     return (2 * s + 2 * s + 3 * s + 2 * s + 2 * w) / 4.0
 STAGE_KERNEL = "k_rk4_tiled"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_05526_amd", "csrc", "hgf_tiled.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rk4_stage_10mode_mixed_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rk4_tiled_10mode_mixed_traffic.json")
 
 
 def log(msg: str) -> None:
@@ -64,14 +64,18 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(shape: dict):
     """HBM bytes per stage launch from committed rocprofv3 counter runs, or
-    None when the kernel source changed since they were taken."""
+    None when the kernel source or the launch shape differs from the one the
+    counters were taken with."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    taken = [int(x) for x in t.get("tune_cache_line", "").split()[1:5]]
+    if taken != [shape[k] for k in ("nfast", "threads", "xblock", "pipe")]:
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -175,6 +179,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
+    ap.add_argument("--tune-cache", default=None,
+                    help="launch-shape cache file: shapes found there are applied without measuring")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -206,7 +212,7 @@ def main():
         op = hgf.map_operator(S, factors=w.factors, precision=precision)
         real = op.info()["real_functions"] == 1
         t0 = time.perf_counter()
-        hgf.autotune([op], w.dt)  # launch shape of the stage kernel, measured on this GPU
+        hgf.autotune([op], w.dt, cache=args.tune_cache)  # stage-kernel launch shape, measured on this GPU
         tune = dict(op.tile_config(0), seconds=time.perf_counter() - t0)
         log(f"autotuned shape {tune}")
         if warmup:
@@ -230,7 +236,7 @@ def main():
     value = pts * 4 * args.steps / el
     bytes_launch = bytes_per_point_stage(args.precision, real) * pts
     achieved = bytes_launch / launch_s / 1e9
-    traffic = stored_traffic()
+    traffic = stored_traffic(tune)
     line = {
         "metric": METRIC,
         "value": value,
