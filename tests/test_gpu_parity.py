@@ -195,6 +195,10 @@ def test_large_grid_factorises(hgf):
     steps = 200
     announce("10-mode grid, 200 steps, mixed")
     op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed")
+    hgf.autotune([op], w.dt)  # the launch shape the benchmark times
+    cfg = op.tile_config(0)
+    announce(f"  tuned shape {cfg}")
+    assert cfg["blocks"] > 0 and cfg["stage_us"] > 0
     hgf.evolve(op, steps * w.dt, w.dt)
     d, e, grid, _ = op.function(0)
     assert d == (0,) * 10 and e == (6,) * 10
@@ -250,6 +254,35 @@ def test_edge_cases(hgf):
     # identity stays the identity (adjoint master equation is unital)
     hgf.evolve(op, 0.5, 1e-3)
     assert abs(hgf.expectation(op, synth.coherent_state([0.5 + 0.5j])) - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_maximum_modes_and_cutoff(hgf, precision, tol):
+    """The largest shapes the ABI accepts along each limit: 16 modes (twelve
+    slow axes in the tiled kernel) and a cutoff of 32 (63 sectors)."""
+    announce(f"16 modes x cutoff 2, {precision}")
+    cutoff = (2,) * 16
+    s = synth.random_system(cutoff, 61, scale=3.0, n_th=0.3)
+    rng = np.random.default_rng(61)
+    fac = [np.diag(rng.uniform(0.5, 1.5, size=2)).astype(np.complex128) for _ in cutoff]
+    op = hgf.map_operator(hgf.define_system(s), factors=fac, precision=precision)
+    assert op.tile_config(0)["blocks"] > 0
+    T, dt = 0.02, 1e-3
+    hgf.evolve(op, T, dt)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
+    announce(f"1 mode x cutoff 32, {precision}")
+    cutoff = (32,)
+    s = synth.random_system(cutoff, 62, scale=0.5, n_th=0.05)
+    s.kerr[:] = 0.3
+    M = _dense_random_operator(cutoff, 62)
+    op = hgf.map_operator(hgf.define_system(s), sparse=_sparse_from_dense(cutoff, M), precision=precision)
+    assert op.info()["n_functions"] == 63
+    T, dt = 0.01, 2e-4
+    hgf.evolve(op, T, dt)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.sparse_sectors(cutoff, *_sparse_from_dense(cutoff, M)),
+                                                    T, dt))
+    assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
 
 
 def test_error_paths(hgf):
