@@ -74,37 +74,66 @@ template <typename T>
 __device__ __forceinline__ T ld_at(const void* base, uint32_t idx) {
   return ldg((const HGF_GLOBAL T*)((const HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)));
 }
-__device__ __forceinline__ float ldg_nt(const HGF_GLOBAL float* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ double ldg_nt(const HGF_GLOBAL double* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ float2 ldg_nt(const HGF_GLOBAL float2* p) {
-  const hgf_v2f v = __builtin_nontemporal_load((const HGF_GLOBAL hgf_v2f*)p);
+// Grids streamed once per stage (X1 and y read, stage outputs written) go
+// through buffer instructions with the nontemporal policy, measured faster on
+// gfx950 than global instructions with the same hint.  The descriptor spans
+// 4 GB from the base (the host keeps every byte offset in 32 bits); dword 3 is
+// the raw-buffer format word.
+typedef unsigned int hgf_u2 __attribute__((ext_vector_type(2)));
+typedef unsigned int hgf_u4 __attribute__((ext_vector_type(4)));
+constexpr int kStreamPolicy = 2;  // nt
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)0xffffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T stream_load(const void* base, uint32_t byte_off);
+template <>
+__device__ __forceinline__ float stream_load<float>(const void* base, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(stream_rsrc(base), (int)off, 0, kStreamPolicy));
+}
+template <>
+__device__ __forceinline__ double stream_load<double>(const void* base, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(stream_rsrc(base), (int)off, 0, kStreamPolicy));
+}
+template <>
+__device__ __forceinline__ float2 stream_load<float2>(const void* base, uint32_t off) {
+  const hgf_v2f v =
+      __builtin_bit_cast(hgf_v2f, __builtin_amdgcn_raw_buffer_load_b64(stream_rsrc(base), (int)off, 0, kStreamPolicy));
   return make_float2(v.x, v.y);
 }
-__device__ __forceinline__ double2 ldg_nt(const HGF_GLOBAL double2* p) {
-  const hgf_v2d v = __builtin_nontemporal_load((const HGF_GLOBAL hgf_v2d*)p);
+template <>
+__device__ __forceinline__ double2 stream_load<double2>(const void* base, uint32_t off) {
+  const hgf_v2d v = __builtin_bit_cast(
+      hgf_v2d, __builtin_amdgcn_raw_buffer_load_b128(stream_rsrc(base), (int)off, 0, kStreamPolicy));
   return make_double2(v.x, v.y);
 }
-__device__ __forceinline__ void stg_nt(HGF_GLOBAL float* p, float a) { __builtin_nontemporal_store(a, p); }
-__device__ __forceinline__ void stg_nt(HGF_GLOBAL double* p, double a) { __builtin_nontemporal_store(a, p); }
-__device__ __forceinline__ void stg_nt(HGF_GLOBAL float2* p, float2 a) {
+__device__ __forceinline__ void stream_store(void* base, uint32_t off, float a) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, a), stream_rsrc(base), (int)off, 0,
+                                        kStreamPolicy);
+}
+__device__ __forceinline__ void stream_store(void* base, uint32_t off, double a) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(hgf_u2, a), stream_rsrc(base), (int)off, 0, kStreamPolicy);
+}
+__device__ __forceinline__ void stream_store(void* base, uint32_t off, float2 a) {
   hgf_v2f v;
   v.x = a.x;
   v.y = a.y;
-  __builtin_nontemporal_store(v, (HGF_GLOBAL hgf_v2f*)p);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(hgf_u2, v), stream_rsrc(base), (int)off, 0, kStreamPolicy);
 }
-__device__ __forceinline__ void stg_nt(HGF_GLOBAL double2* p, double2 a) {
+__device__ __forceinline__ void stream_store(void* base, uint32_t off, double2 a) {
   hgf_v2d v;
   v.x = a.x;
   v.y = a.y;
-  __builtin_nontemporal_store(v, (HGF_GLOBAL hgf_v2d*)p);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(hgf_u4, v), stream_rsrc(base), (int)off, 0,
+                                         kStreamPolicy);
 }
 template <typename T>
 __device__ __forceinline__ T ld_at_nt(const void* base, uint32_t idx) {
-  return ldg_nt((const HGF_GLOBAL T*)((const HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)));
+  return stream_load<T>(base, idx * (uint32_t)sizeof(T));
 }
 template <typename T>
 __device__ __forceinline__ void st_at_nt(void* base, uint32_t idx, T v) {
-  stg_nt((HGF_GLOBAL T*)((HGF_GLOBAL char*)base + idx * (uint32_t)sizeof(T)), v);
+  stream_store(base, idx * (uint32_t)sizeof(T), v);
 }
 template <typename T>
 __device__ __forceinline__ void st_at(void* base, uint32_t idx, T v) {
@@ -122,17 +151,15 @@ __device__ __forceinline__ P ld_pack(const P* base, uint32_t byte_off) {
 }
 template <typename T, int V>
 __device__ __forceinline__ Pack<T, V> ld_pack_nt(const Pack<T, V>* base, uint32_t byte_off) {
-  const T* s = (const T*)((const char*)base + byte_off);
   Pack<T, V> out;
 #pragma unroll
-  for (int i = 0; i < V; ++i) out.e[i] = nt_load(s + i);
+  for (int i = 0; i < V; ++i) out.e[i] = stream_load<T>(base, byte_off + i * (uint32_t)sizeof(T));
   return out;
 }
 template <typename T, int V>
 __device__ __forceinline__ void st_pack_nt(Pack<T, V>* base, uint32_t byte_off, const Pack<T, V>& v) {
-  T* d = (T*)((char*)base + byte_off);
 #pragma unroll
-  for (int i = 0; i < V; ++i) nt_store(d + i, v.e[i]);
+  for (int i = 0; i < V; ++i) stream_store(base, byte_off + i * (uint32_t)sizeof(T), v.e[i]);
 }
 template <typename P>
 __device__ __forceinline__ void st_pack(P* base, uint32_t byte_off, const P& v) {
@@ -384,23 +411,28 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
   const int nt = blockDim.x, tid = threadIdx.x;
   const int si = stage - 1;
 
+  // Each XCD takes a contiguous eighth of the concatenated tile space and
+  // each of its workgroups a contiguous run inside it, so that a workgroup
+  // rebuilds its member tables only where its run crosses into another member.
   const uint32_t xcd = blockIdx.x & 7u;
   const uint32_t nwx = (gridDim.x - xcd + 7u) >> 3;
+  const uint32_t wx = blockIdx.x >> 3;
   const int64_t lo = total_tiles * xcd / 8, hi = total_tiles * (xcd + 1) / 8;
+  const int64_t clo = lo + (hi - lo) * wx / nwx, chi = lo + (hi - lo) * (wx + 1) / nwx;
   int bad = 0;
 
   TS* const tile = (TS*)smem;
   TS nxt[kTileRounds];
-  int64_t t = lo + (blockIdx.x >> 3);
+  int64_t t = clo;
   int m = 0;
-  while (t < hi) {
+  while (t < chi) {
     // ---- the member owning tile t; its per-position tables.  Member values
     // are read from the member record where they are used (scalar loads)
     // rather than held in registers across the tile loop.
     while (m + 1 < nmem && mem[m + 1].tile_begin <= t) ++m;
     const MemberArgs* __restrict__ mp = mem + m;
     const int64_t mbeg = mp->tile_begin;
-    const int64_t run_end = min(hi, mbeg + mp->g.ntiles);
+    const int64_t run_end = min(chi, mbeg + mp->g.ntiles);
     const int T = (int)mp->g.tile_points;
     const int rounds = (T + nt - 1) / nt;
     if (rounds > kTileRounds) {  // launch contract broken: report, compute nothing
@@ -459,7 +491,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
         if (r < rounds) nxt[r] = ld_at<TS>(in, b0 + p);
       }
     }
-    for (; t < run_end; t += nwx) {
+    for (; t < run_end; ++t) {
       const uint32_t lt = (uint32_t)(t - mbeg);  // tile index inside the member
       const uint32_t tbase = lt * (uint32_t)T;
 #pragma unroll
@@ -469,7 +501,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       }
       __syncthreads();
       {
-        const int64_t tn = t + nwx;
+        const int64_t tn = t + 1;
         if (tn < run_end) {
           const uint32_t b0 = (uint32_t)(tn - mbeg) * (uint32_t)T;
 #pragma unroll
