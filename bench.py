@@ -74,8 +74,8 @@ def stored_traffic(shape: dict):
         t = json.load(fh)
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
-    taken = [int(x) for x in t.get("tune_cache_line", "").split()[1:5]]
-    if taken != [shape[k] for k in ("nfast", "threads", "xblock", "pipe")]:
+    taken = [int(x) for x in t.get("tune_cache_line", "").split()[1:6]]
+    if taken != [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")]:
         return None
     return t.get("traffic_bytes_per_launch")
 

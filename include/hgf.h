@@ -233,6 +233,8 @@ typedef struct {
                           B > 0 = interleaved blocks of B consecutive tiles */
   int32_t pipe;        /* 1 = neighbour loads of the next lane round issued before the
                           current round computes */
+  int32_t wgs_per_cu;  /* resident workgroups per CU in the persistent grid; 0 = as many as
+                          fit (fewer narrow the band of tiles each XCD works on) */
   int32_t blocks;      /* out: persistent workgroups per launch */
   int32_t tile_points; /* out: points per tile */
   double stage_us;     /* out: stage time measured by hgf_autotune for this shape, else 0 */
@@ -242,7 +244,8 @@ typedef struct {
 hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* out);
 
 /*
- * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe).
+ * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe,
+ * wgs_per_cu).
  * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
  * register budget) or asks a real grid for the untiled kernel;
  * HGF_EUNSUPPORTED for split-layout functions (classical kernel only).  The
@@ -263,7 +266,8 @@ enum {
  * times the RK4 step of one such function with step dt_us under each
  * candidate shape (fast axes: the default and one fewer; every workgroup
  * size whose last lane round is at least 3/4 full; both XCD orders; with
- * and without pipelined loads) and applies the fastest to every function of
+ * and without pipelined loads; all resident workgroups per CU or one or two
+ * fewer) and applies the fastest to every function of
  * that shape.  The timed steps run on the function's own buffers; its state
  * is restored afterwards, so results are unaffected.  cache_path (may be NULL:
  * no cache) names a text file of measured shapes keyed by device

@@ -144,6 +144,7 @@ struct TileChoice {
   int threads = 0;
   int xblock = -1;
   int pipe = -1;
+  int wgs_per_cu = 0;  // resident workgroups per CU in the persistent grid (0: as many as fit)
 };
 
 // Pipelined neighbour loads keep the register budget only up to this many
@@ -231,7 +232,15 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
     g.real = 0;
     return false;
   }
-  const int64_t want = (int64_t)cus * occ;
+  if (c.wgs_per_cu > occ) {
+    g.blocks = 0;
+    g.nfast = 0;
+    g.real = 0;
+    return false;
+  }
+  g.occ_cap = c.wgs_per_cu > 0 ? c.wgs_per_cu : 0;
+  g.occ_max = occ;
+  const int64_t want = (int64_t)cus * (c.wgs_per_cu > 0 ? c.wgs_per_cu : occ);
   const int64_t cap = 8 * ((g.ntiles + 7) / 8);
   g.blocks = (int)std::max<int64_t>(8, std::min(want, cap));
   return true;
@@ -763,6 +772,7 @@ static StepPlan* build_plan(const std::vector<PlanItem>& items) {
         tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real,
                                 mem.size() == 1 ? (kv.second[0].f->ga.pipe ? 2 : 1) : 0);
     gl.blocks = (int)std::max<int64_t>(8, std::min<int64_t>((int64_t)cus * occ, 8 * ((tiles + 7) / 8)));
+    if (mem.size() == 1) gl.blocks = kv.second[0].f->ga.blocks;  // the function's own (possibly tuned) grid
     void* d = dmalloc(mem.size() * sizeof(MemberArgs));
     plan->dmem.push_back(d);
     hip_check(hipMemcpy(d, mem.data(), mem.size() * sizeof(MemberArgs), hipMemcpyHostToDevice), "upload members");
@@ -1005,7 +1015,7 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
 // The tiled stage kernel's launch shape (fast axes, workgroup size, XCD tile
 // order, pipelined loads) is chosen per grid shape by timing candidate shapes
 // on the function's own buffers.  Results are kept in a text cache, one line
-// per shape: "<key> <nfast> <threads> <xblock> <pipe> <stage_us>", the key
+// per shape: "<key> <nfast> <threads> <xblock> <pipe> <wgs_per_cu> <stage_us>", the key
 // naming the device (architecture, CU count), precision, real or complex grid
 // and the extents.
 
@@ -1069,7 +1079,7 @@ static std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
     std::istringstream ls(line);
     std::string key;
     TuneEntry e;
-    if (ls >> key >> e.c.nfast >> e.c.threads >> e.c.xblock >> e.c.pipe >> e.us) m[key] = e;
+    if (ls >> key >> e.c.nfast >> e.c.threads >> e.c.xblock >> e.c.pipe >> e.c.wgs_per_cu >> e.us) m[key] = e;
   }
   return m;
 }
@@ -1083,7 +1093,7 @@ static void write_tune_cache(const char* path, const std::map<std::string, TuneE
     out.precision(6);
     for (auto& kv : m)
       out << kv.first << ' ' << kv.second.c.nfast << ' ' << kv.second.c.threads << ' ' << kv.second.c.xblock << ' '
-          << kv.second.c.pipe << ' ' << kv.second.us << '\n';
+          << kv.second.c.pipe << ' ' << kv.second.c.wgs_per_cu << ' ' << kv.second.us << '\n';
     if (!out) fail(HGF_EINVAL, std::string("cannot write tuning cache ") + path);
   }
   if (std::rename(tmp.c_str(), path) != 0) fail(HGF_EINVAL, std::string("cannot replace tuning cache ") + path);
@@ -1118,7 +1128,17 @@ static std::vector<TileChoice> tune_candidates(const Function& f, int precision)
           c.xblock = xb;
           c.pipe = pp;
           GridArgs g = f.ga;
-          if (configure_tiles(g, precision, f.real, c)) out.push_back(c);
+          if (!configure_tiles(g, precision, f.real, c)) continue;
+          out.push_back(c);
+          // fewer resident workgroups: a narrower front of tiles per XCD
+          // keeps more neighbour tiles in L2 (measured faster on the 6^10 grid)
+          const int occ = g.occ_max;
+          for (int w = occ - 1; w >= std::max(1, occ - 2); --w) {
+            TileChoice d = c;
+            d.wgs_per_cu = w;
+            GridArgs g2 = f.ga;
+            if (configure_tiles(g2, precision, f.real, d)) out.push_back(d);
+          }
         }
     }
   }
@@ -1159,6 +1179,7 @@ static TileChoice current_choice(const Function& f) {
   c.threads = f.ga.threads;
   c.xblock = f.ga.xblock;
   c.pipe = f.ga.pipe;
+  c.wgs_per_cu = f.ga.occ_cap;
   return c;
 }
 
@@ -1198,9 +1219,9 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
       TuneEntry best;
       best.us = 1e300;
       try {
-        // enough steps for ~2 ms of timed work per candidate
+        // enough steps for ~1 ms of timed work per candidate
         const double t0 = time_function_steps(f, op->precision, h, dflag.as<int>(), 1, st);
-        const int steps = (int)std::max(2.0, std::min(200.0, 2000.0 / std::max(1e-3, 4.0 * t0)));
+        const int steps = (int)std::max(2.0, std::min(100.0, 1000.0 / std::max(1e-3, 4.0 * t0)));
         for (const TileChoice& c : cands) {
           retile(f, op->precision, c);
           const double us = time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st);
@@ -1638,6 +1659,7 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
     out->threads = tiled ? f.ga.threads : 0;
     out->xblock = tiled ? f.ga.xblock : 0;
     out->pipe = tiled ? f.ga.pipe : 0;
+    out->wgs_per_cu = tiled ? f.ga.occ_cap : 0;
     out->blocks = tiled ? f.ga.blocks : 0;
     out->tile_points = tiled ? (int32_t)f.ga.tile_points : 1;
     out->stage_us = f.tuned_us;
@@ -1648,13 +1670,15 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
   return guarded([&] {
     if (!op || !cfg) fail(HGF_EINVAL, "NULL argument");
     if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
-    if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || (cfg->pipe != 0 && cfg->pipe != 1))
+    if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || cfg->wgs_per_cu < 0 ||
+        (cfg->pipe != 0 && cfg->pipe != 1))
       fail(HGF_EINVAL, "negative tile parameter or pipe not 0/1");
     TileChoice c;
     c.nfast = cfg->nfast;
     c.threads = cfg->threads;
     c.xblock = cfg->xblock;
     c.pipe = cfg->pipe;
+    c.wgs_per_cu = cfg->wgs_per_cu;
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
     retile(op->fn[idx], op->precision, c);

@@ -87,6 +87,8 @@ struct GridArgs {
   int lds_bytes;            // dynamic LDS of the tiled kernel
   int xblock;               // tile order across XCDs: 0 contiguous eighths, B > 0 blocks of B tiles
   int pipe;                 // single-grid kernel issues the loads of the next lane round early
+  int occ_cap;              // resident workgroups per CU requested for the persistent grid (0: all that fit)
+  int occ_max;              // resident workgroups per CU that fit (registers, LDS, waves)
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
   double lam0_re, lam0_im;
   double alpha[kMaxModes];

@@ -25,15 +25,15 @@ def _shapes(tile_points):
     """(nfast, threads, xblock, pipe) samples for one tile size: the default
     workgroup, the smallest and the largest feasible one, odd XCD blocks."""
     ths = [t for t in range(64, 513, 64) if -(-tile_points // t) <= 8]
-    return [(0, 0, 0), (ths[0], 3, 1), (ths[-1], 128, 0), (ths[len(ths) // 2], 1, 1)]
+    return [(0, 0, 0, 0), (ths[0], 3, 1, 0), (ths[-1], 128, 0, 1), (ths[len(ths) // 2], 1, 1, 2)]
 
 
-def _apply(hgf, op, nfast, threads, xblock, pipe):
+def _apply(hgf, op, nfast, threads, xblock, pipe, wgs=0):
     """Set the shape on every function where it is feasible; returns how many took it."""
     took = 0
     for i in range(op.info()["n_functions"]):
         try:
-            op.set_tile_config(i, nfast, threads, xblock, pipe)
+            op.set_tile_config(i, nfast, threads, xblock, pipe, wgs)
             took += 1
         except hgf.HgfError as e:
             assert e.status == "HGF_EINVAL"
@@ -63,15 +63,15 @@ def test_forced_tile_shapes_agree_and_match_oracle(hgf, precision, kind):
     tried = 0
     for nfast in (1, 2, 3, 4):
         tile = int(np.prod(cutoff[len(cutoff) - nfast:]))
-        for threads, xblock, pipe in _shapes(tile):
+        for threads, xblock, pipe, wgs in _shapes(tile):
             op = hgf.map_operator(S, factors=fac, precision=precision)
-            if _apply(hgf, op, nfast, threads, xblock, pipe) == 0:
+            if _apply(hgf, op, nfast, threads, xblock, pipe, wgs) == 0:
                 continue
-            announce(f"  nfast={nfast} threads={threads} xblock={xblock} pipe={pipe}")
+            announce(f"  nfast={nfast} threads={threads} xblock={xblock} pipe={pipe} wgs_per_cu={wgs}")
             hgf.evolve(op, T, dt)
             got = gpu_number_grids(op, cutoff)
-            assert max_rel_err(got, ref) < tol, (nfast, threads, xblock, pipe)
-            assert max_rel_err(got, base_grids) < same, (nfast, threads, xblock, pipe)
+            assert max_rel_err(got, ref) < tol, (nfast, threads, xblock, pipe, wgs)
+            assert max_rel_err(got, base_grids) < same, (nfast, threads, xblock, pipe, wgs)
             tried += 1
     assert tried >= 10
     if kind == "complex-bidiagonal":  # the untiled kernel too
@@ -97,7 +97,8 @@ def test_tile_config_rejects_infeasible_shapes(hgf):
            (4, 128, 0, 0),    # 1296-point tile in more than 8 lane rounds
            (4, 1024, 0, 0),   # above 512 lanes
            (6, 0, 0, 0),      # more fast axes than the grid has
-           (4, 256, 0, 2)]    # pipe is 0 or 1
+           (4, 256, 0, 2),    # pipe is 0 or 1
+           (4, 256, 0, 0, 64)]  # more resident workgroups than fit on a CU
     for cfg in bad:
         with pytest.raises(hgf.HgfError) as e:
             op.set_tile_config(0, *cfg)
@@ -146,8 +147,8 @@ def test_autotune_cache_and_results(hgf, tmp_path):
     fresh = hgf.map_operator(cases[0][1], factors=cases[0][2], precision="mixed")
     hgf.autotune([fresh], dt, cache=cache, mode="cached_only")
     a, b = fresh.tile_config(0), ops[0].tile_config(0)
-    assert {k: a[k] for k in ("nfast", "threads", "xblock", "pipe")} == \
-        {k: b[k] for k in ("nfast", "threads", "xblock", "pipe")}
+    assert {k: a[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")} == \
+        {k: b[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")}
     # force re-measures and rewrites the entry in place
     hgf.autotune([fresh], dt, cache=cache, mode="force")
     assert len(open(cache).read().splitlines()) == 2
