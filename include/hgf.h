@@ -235,6 +235,10 @@ typedef struct {
                           current round computes */
   int32_t wgs_per_cu;  /* resident workgroups per CU in the persistent grid; 0 = as many as
                           fit (fewer narrow the band of tiles each XCD works on) */
+  int32_t resident;    /* 1 = the whole grid is one tile and one workgroup integrates it on
+                          chip through all the steps of a call (state in registers, stage
+                          grids in LDS); 0 = one launch per RK4 stage.  Set by default
+                          where the grid allows it */
   int32_t blocks;      /* out: persistent workgroups per launch */
   int32_t tile_points; /* out: points per tile */
   double stage_us;     /* out: stage time measured by hgf_autotune for this shape, else 0 */
@@ -245,9 +249,10 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
 
 /*
  * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe,
- * wgs_per_cu).
+ * wgs_per_cu, resident).
  * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
- * register budget) or asks a real grid for the untiled kernel;
+ * register budget), asks a real grid for the untiled kernel, or asks for the
+ * resident form where the grid is not a single tile of at most 4096 points;
  * HGF_EUNSUPPORTED for split-layout functions (classical kernel only).  The
  * function is unchanged on error.
  */

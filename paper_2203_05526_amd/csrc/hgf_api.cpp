@@ -302,6 +302,17 @@ static void build_tile_records(Function& f, int precision) {
   f.ga.tiles = f.ttab;
 }
 
+// A function runs on the resident kernel when its tiled configuration is a
+// single tile holding every axis (then one workgroup does a stage's work in any
+// case) and the tile fits the resident kernel's lane rounds.
+static bool resident_eligible(Function& f) {
+  const GridArgs& g = f.ga;
+  if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
+  if (g.tile_points > resident_max_points()) return false;
+  f.res_threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (g.tile_points + 63) / 64 * 64));
+  return true;
+}
+
 static void fill_grid_args(Function& f, int precision, bool want_real) {
   GridArgs& g = f.ga;
   std::memset(&g, 0, sizeof(g));
@@ -357,6 +368,9 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   g.beta_f = (const float*)(base + b_lam + b_beta + b_lamf);
   g.tiles = nullptr;
   if (g.blocks > 0) build_tile_records(f, precision);
+  f.resident = resident_eligible(f);
+  const char* env = std::getenv("HGF_RESIDENT");
+  if (env && std::string(env) == "0") f.resident = false;
 }
 
 static size_t state_bytes(const Function& f) { return f.ga.points * (f.real ? sizeof(double) : sizeof(double2)); }
@@ -714,6 +728,10 @@ struct StepPlan {
   std::vector<GroupLaunch> groups;
   std::vector<void*> dmem;
   std::vector<PlanItem> generic;
+  // resident launches, with host copies of their items (the step count is set
+  // per call)
+  std::vector<ResidentLaunch> resident;
+  std::vector<std::vector<ResidentItem>> res_host;
   ~StepPlan() {
     for (auto& p : dmem) dfree(p);
   }
@@ -738,12 +756,14 @@ static MemberArgs member_args(const PlanItem& it) {
   return m;
 }
 
-static StepPlan* build_plan(const std::vector<PlanItem>& items) {
+static StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resident = true) {
   std::unique_ptr<StepPlan> plan(new StepPlan);
-  std::map<std::vector<int>, std::vector<PlanItem>> by_key;
+  std::map<std::vector<int>, std::vector<PlanItem>> by_key, res_key;
   for (const PlanItem& it : items) {
     const GridArgs& g = it.f->ga;
-    if (g.blocks > 0)
+    if (allow_resident && it.f->resident)
+      res_key[{g.nfast, g.real, it.precision}].push_back(it);
+    else if (g.blocks > 0)
       by_key[{g.nfast, g.n - g.nfast, g.real, it.precision}].push_back(it);
     else
       plan->generic.push_back(it);
@@ -780,7 +800,52 @@ static StepPlan* build_plan(const std::vector<PlanItem>& items) {
     gl.single = mem[0];
     plan->groups.push_back(gl);
   }
+  for (auto& kv : res_key) {
+    ResidentLaunch rl{};
+    rl.nfast = kv.first[0];
+    rl.real = kv.first[1];
+    rl.precision = kv.first[2];
+    std::vector<ResidentItem> host;
+    for (const PlanItem& it : kv.second) {
+      ResidentItem ri{};
+      ri.g = it.f->ga;
+      ri.y = it.f->y;
+      ri.yf = it.precision == HGF_MIXED ? it.f->yf : nullptr;
+      ri.steps = 0;
+      ri.h = it.h;
+      host.push_back(ri);
+      rl.threads = std::max(rl.threads, it.f->res_threads);
+      rl.lds_bytes = std::max(rl.lds_bytes, it.f->ga.lds_bytes);
+    }
+    rl.count = (int)host.size();
+    void* d = dmalloc(host.size() * sizeof(ResidentItem));
+    plan->dmem.push_back(d);
+    rl.items = (const ResidentItem*)d;
+    plan->resident.push_back(rl);
+    plan->res_host.push_back(std::move(host));
+  }
   return plan.release();
+}
+
+// Advance the plan's resident functions by `steps` RK4 steps (launches of at
+// most kResidentChunk steps each).
+constexpr int64_t kResidentChunk = 8192;
+static void run_resident(StepPlan& plan, int64_t steps, int* flag, hipStream_t st) {
+  for (size_t k = 0; k < plan.resident.size(); ++k) {
+    std::vector<ResidentItem>& host = plan.res_host[k];
+    for (int64_t done = 0; done < steps;) {
+      const int n = (int)std::min(kResidentChunk, steps - done);
+      if (host[0].steps != n) {
+        for (auto& ri : host) ri.steps = n;
+        hip_check(hipMemcpyAsync((void*)plan.resident[k].items, host.data(), host.size() * sizeof(ResidentItem),
+                                 hipMemcpyHostToDevice, st),
+                  "upload resident items");
+        hip_check(hipStreamSynchronize(st), "synchronize");  // the host copy may change before the next launch
+      }
+      launch_resident(plan.resident[k], flag, st);
+      done += n;
+    }
+  }
 }
 
 static void generic_stage(const PlanItem& it, int s, int* flag, hipStream_t st) {
@@ -904,14 +969,18 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   }
   reset_flag(op, st);
   if (op->layout == HGF_MERGED) {
-    const int chunk = (int)std::min<int64_t>(steps, 64);
-    ensure_graph(op, h, chunk);
-    int64_t done = 0;
-    while (steps - done >= chunk) {
-      hip_check(hipGraphLaunch((hipGraphExec_t)op->graph_exec, st), "graph launch");
-      done += chunk;
+    ensure_plan(op, h);
+    run_resident(*op->plan, steps, op->dflag, st);
+    if (!op->plan->groups.empty() || !op->plan->generic.empty()) {
+      const int chunk = (int)std::min<int64_t>(steps, 64);
+      ensure_graph(op, h, chunk);
+      int64_t done = 0;
+      while (steps - done >= chunk) {
+        hip_check(hipGraphLaunch((hipGraphExec_t)op->graph_exec, st), "graph launch");
+        done += chunk;
+      }
+      for (; done < steps; ++done) run_plan_step(*op->plan, op->dflag, st);
     }
-    for (; done < steps; ++done) run_plan_step(*op->plan, op->dflag, st);
   } else {
     for (int64_t s = 0; s < steps; ++s)
       for (auto& f : op->fn) split_step(op, f, h, st);
@@ -973,18 +1042,23 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
         for (auto& f : ops[i]->fn) items.push_back({&f, ops[i]->precision, dt[i]});
     if (items.empty()) continue;
     std::unique_ptr<StepPlan> plan(build_plan(items));
-    const int chunk = (int)std::min<int64_t>(nst, 64);
-    hipGraphExec_t exec = capture_steps(*plan, dflag.as<int>(), chunk, cap);
-    struct ExecGuard {
-      hipGraphExec_t e;
-      ~ExecGuard() { (void)hipGraphExecDestroy(e); }
-    } eg{exec};
-    int64_t done = 0;
-    while (nst - done >= chunk) {
-      hip_check(hipGraphLaunch(exec, st), "graph launch");
-      done += chunk;
+    run_resident(*plan, nst, dflag.as<int>(), st);
+    if (!plan->groups.empty() || !plan->generic.empty()) {
+      const int chunk = (int)std::min<int64_t>(nst, 64);
+      hipGraphExec_t exec = capture_steps(*plan, dflag.as<int>(), chunk, cap);
+      struct ExecGuard {
+        hipGraphExec_t e;
+        ~ExecGuard() { (void)hipGraphExecDestroy(e); }
+      } eg{exec};
+      int64_t done = 0;
+      while (nst - done >= chunk) {
+        hip_check(hipGraphLaunch(exec, st), "graph launch");
+        done += chunk;
+      }
+      for (; done < nst; ++done) run_plan_step(*plan, dflag.as<int>(), st);
+      // the graph and the plan's device buffers must outlive the launches
+      hip_check(hipStreamSynchronize(st), "synchronize");
     }
-    for (; done < nst; ++done) run_plan_step(*plan, dflag.as<int>(), st);
     // the plan's device buffers must outlive the launches that read them
     hip_check(hipStreamSynchronize(st), "synchronize");
   }
@@ -1147,7 +1221,7 @@ static std::vector<TileChoice> tune_candidates(const Function& f, int precision)
 
 // Mean stage time (us) of `steps` RK4 steps of one function alone.
 static double time_function_steps(Function& f, int precision, double h, int* flag, int steps, hipStream_t st) {
-  std::unique_ptr<StepPlan> plan(build_plan({PlanItem{&f, precision, h}}));
+  std::unique_ptr<StepPlan> plan(build_plan({PlanItem{&f, precision, h}}, false));
   run_plan_step(*plan, flag, st);  // warm-up
   hipEvent_t a, b;
   hip_check(hipEventCreate(&a), "event");
@@ -1193,7 +1267,7 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
     hgf_operator_s* op = ops[i];
     if (op->layout != HGF_MERGED) continue;
     for (auto& f : op->fn) {
-      if (f.ga.blocks == 0 && f.real) continue;
+      if ((f.ga.blocks == 0 && f.real) || f.resident) continue;  // resident: one workgroup, nothing to tune
       const std::string key = tune_key(dev, f, op->precision);
       auto it = cache.find(key);
       const bool known = it != cache.end() && (!(flags & HGF_TUNE_FORCE) || fresh.count(key));
@@ -1402,7 +1476,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
     DBuf y0(gb);
     hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
-    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}));
+    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, false));
     for (int64_t s = 0; s < M; ++s) {
       run_plan_step(*fplan, op.dflag, st);
       if ((s + 1) % ce == 0) hip_check(hipMemcpyAsync(ck + ((s + 1) / ce) * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
@@ -1660,6 +1734,7 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
     out->xblock = tiled ? f.ga.xblock : 0;
     out->pipe = tiled ? f.ga.pipe : 0;
     out->wgs_per_cu = tiled ? f.ga.occ_cap : 0;
+    out->resident = f.resident ? 1 : 0;
     out->blocks = tiled ? f.ga.blocks : 0;
     out->tile_points = tiled ? (int32_t)f.ga.tile_points : 1;
     out->stage_us = f.tuned_us;
@@ -1671,8 +1746,8 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     if (!op || !cfg) fail(HGF_EINVAL, "NULL argument");
     if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
     if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || cfg->wgs_per_cu < 0 ||
-        (cfg->pipe != 0 && cfg->pipe != 1))
-      fail(HGF_EINVAL, "negative tile parameter or pipe not 0/1");
+        (cfg->pipe != 0 && cfg->pipe != 1) || (cfg->resident != 0 && cfg->resident != 1))
+      fail(HGF_EINVAL, "negative tile parameter, or pipe or resident not 0/1");
     TileChoice c;
     c.nfast = cfg->nfast;
     c.threads = cfg->threads;
@@ -1681,7 +1756,16 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     c.wgs_per_cu = cfg->wgs_per_cu;
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
-    retile(op->fn[idx], op->precision, c);
+    Function& f = op->fn[idx];
+    if (cfg->resident) {  // check on a copy first: the function is unchanged on error
+      Function probe;
+      probe.split = f.split;
+      probe.ga = f.ga;
+      if (c.nfast == 0 || !configure_tiles(probe.ga, op->precision, f.real, c) || !resident_eligible(probe))
+        fail(HGF_EINVAL, "the resident form needs the whole grid in one tile of at most 4096 points");
+    }
+    retile(f, op->precision, c);
+    f.resident = cfg->resident && resident_eligible(f);
     drop_plan(op);
   });
 }

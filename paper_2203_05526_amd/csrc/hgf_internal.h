@@ -111,6 +111,25 @@ struct MemberArgs {
   int64_t tile_begin;  // first tile of the member in the group's tile space
 };
 
+// One function integrated on chip by the resident kernel (the whole grid is
+// one LDS tile): its grid, state buffers, step count and step size.
+struct ResidentItem {
+  GridArgs g;
+  void* y;   // state
+  void* yf;  // stage-precision copy of y (mixed) or NULL
+  int steps;
+  double h;
+};
+
+// One resident launch: one workgroup per item, items sharing the number of
+// axes and element types.
+struct ResidentLaunch {
+  const ResidentItem* items;  // device array
+  int count;
+  int nfast, threads, lds_bytes;
+  int real, precision;
+};
+
 // One grouped launch: members sharing the axis split and element types.
 struct GroupLaunch {
   MemberArgs single;          // the member itself when nmem == 1 (passed by value)
@@ -144,6 +163,8 @@ struct Function {
   cd ax = 0.0, ay = 0.0;   // dc_x/dt = ax c_x, dc_y/dt = ay c_y
   std::vector<std::pair<int64_t, cd>> sources;  // R' = L R + c_x c_y S
   double tuned_us = 0.0;  // stage time measured by the autotuner for the current shape
+  bool resident = false;  // integrated on chip by the resident kernel
+  int res_threads = 0;    // workgroup size of the resident kernel
 };
 
 struct StepPlan;

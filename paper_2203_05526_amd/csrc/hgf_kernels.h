@@ -39,6 +39,9 @@ int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, in
 int tiled_max_slow_axes();
 int tiled_max_lane_groups();
 void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st);
+// resident (on-chip, many-step) integrator; grids of at most this many points
+int resident_max_points();
+void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st);
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
                       double h, const PointSources& src, int* flag, hipStream_t st);
 int expect_blocks(const GridArgs& g);

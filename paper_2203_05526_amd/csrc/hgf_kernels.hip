@@ -508,6 +508,18 @@ int occupancy_group_c64(int, int, int, int, int);
 int occupancy_group_c128(int, int, int, int, int);
 int occupancy_group_r32(int, int, int, int, int);
 int occupancy_group_r64(int, int, int, int, int);
+void launch_resident_c64(const ResidentLaunch&, int*, hipStream_t);
+void launch_resident_c128(const ResidentLaunch&, int*, hipStream_t);
+void launch_resident_r32(const ResidentLaunch&, int*, hipStream_t);
+void launch_resident_r64(const ResidentLaunch&, int*, hipStream_t);
+int resident_max_points() { return 4 * 1024; }
+
+void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st) {
+  if (rl.real)
+    (rl.precision == HGF_FP64 ? launch_resident_r64 : launch_resident_r32)(rl, flag, st);
+  else
+    (rl.precision == HGF_FP64 ? launch_resident_c128 : launch_resident_c64)(rl, flag, st);
+}
 
 constexpr int kMaxSlow = 12;
 int tiled_max_slow_axes() { return kMaxSlow; }

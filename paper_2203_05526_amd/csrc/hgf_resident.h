@@ -1,0 +1,191 @@
+// Resident RK4 integrator for grids that fit in one workgroup's LDS.
+//
+// When every axis of a function is a fast axis of the tiled stage kernel (the
+// whole grid is a single tile), one workgroup does all the work of a stage
+// launch anyway.  The resident form keeps that workgroup's grid on chip for
+// many RK4 steps: the stencil input of the current stage lives in LDS (the
+// padded zero-halo layout of the tiled kernel), and each lane keeps its
+// points' state y and X1 in registers.  A stage is: read the neighbours from
+// LDS, compute the stage value (the same delta-Horner arithmetic as the
+// tiled kernel), barrier, write the stage value back to LDS, barrier.  HBM is
+// touched only to load y at the start and store y (and its stage-precision
+// copy) at the end.
+//
+// One launch covers a list of such functions, one workgroup each (all the
+// small sectors of an operator, or the small members of a batch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hgf_device.h"
+#include "hgf_internal.h"
+
+namespace hgf {
+
+// Lane rounds per workgroup of the resident kernel: a grid of at most
+// kResidentRounds * 1024 points.
+constexpr int kResidentRounds = 4;
+
+template <int NF, typename TS, typename TY>
+__global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __restrict__ items,
+                                                       int* __restrict__ flag) {
+  using R = typename Real<TS>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ResidentItem* __restrict__ it = items + blockIdx.x;
+  const int T = (int)it->g.tile_points;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int rounds = (T + nt - 1) / nt;
+  if (rounds > kResidentRounds || it->g.ntiles != 1) {  // launch contract broken: report, compute nothing
+    if (tid == 0) atomicOr(flag, 2);
+    return;
+  }
+  TS* const tile = (TS*)smem;
+  TS* const lamf = tile + it->g.lds_elems;
+  uint32_t* const info = (uint32_t*)(lamf + T);
+  R* const btab = (R*)(info + ((T + 1) & ~1));
+  const int cbits = it->g.cbits;
+  const uint32_t cmask = (1u << cbits) - 1u;
+
+  // ---- zero halo and per-position tables (layout of the tiled kernel with
+  // every axis fast)
+  for (int i = tid; i < it->g.lds_elems; i += nt) tile[i] = mk_<TS>(0, 0);
+  for (int p = tid; p < T; p += nt) {
+    int rem = p;
+    uint32_t off = 0, coords = 0;
+    double lr = 0.0, li = 0.0;
+#pragma unroll
+    for (int q = NF - 1; q >= 0; --q) {
+      const int e = it->g.ext[q];
+      const int c = rem % e;
+      rem /= e;
+      off += (uint32_t)(c + 1) * (uint32_t)it->g.pstride[q];
+      coords |= (uint32_t)c << (cbits * q);
+      const double2 lj = it->g.lam[it->g.off[q] + c];
+      lr += lj.x;
+      li += lj.y;
+    }
+    info[p] = off | (coords << 16);
+    lamf[p] = mk_<TS>((R)lr, (R)li);
+  }
+  {
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      for (int c = tid; c < it->g.ext[q]; c += nt) btab[o + c] = (R)it->g.beta[it->g.off[q] + c];
+      o += it->g.ext[q];
+    }
+  }
+  __syncthreads();
+
+  // ---- state into registers, stage-1 stencil input (y in the stage
+  // precision) into LDS
+  const TY* __restrict__ y = (const TY*)it->y;
+  TY yr[kResidentRounds];
+  TS xr[kResidentRounds], orr[kResidentRounds];
+  // lanes past the grid's end (last round) work on a copy of the last point
+  // and store nothing
+#pragma unroll
+  for (int r = 0; r < kResidentRounds; ++r) {
+    const int p = tid + r * nt;
+    if (r < rounds) {
+      yr[r] = y[min(p, T - 1)];
+      orr[r] = mk_<TS>((R)re_(yr[r]), (R)im_(yr[r]));
+      if (p < T) tile[info[p] & 0xffffu] = orr[r];
+    }
+  }
+  const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
+  const double h = it->h;
+  const int steps = it->steps;
+  int bad = 0;
+  for (int s = 0; s < steps; ++s) {
+#pragma unroll 1
+    for (int stage = 1; stage <= 4; ++stage) {
+      __syncthreads();  // LDS holds this stage's stencil input
+#pragma unroll
+      for (int r = 0; r < kResidentRounds; ++r) {
+        if (r < rounds) {
+          const int p = min(tid + r * nt, T - 1);
+          const uint32_t inf = info[p];
+          const int lo_ = (int)(inf & 0xffffu);
+          const TS zc = tile[lo_];
+          const TS lf = lamf[p];
+          const R lr = lr0 + re_(lf), li = li0 + im_(lf);
+          R ar = lr * re_(zc) - li * im_(zc);
+          R ai = lr * im_(zc) + li * re_(zc);
+          int bo = 0;
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            const TS dn = tile[lo_ - it->g.pstride[q]];
+            const TS upv = tile[lo_ + it->g.pstride[q]];
+            const int c = (int)((inf >> (16 + cbits * q)) & cmask);
+            const R bq = btab[bo + c];
+            const R aq = (R)it->g.alpha[q];
+            ar += aq * re_(dn) + bq * re_(upv);
+            ai += aq * im_(dn) + bq * im_(upv);
+            bo += it->g.ext[q];
+          }
+          if (stage == 1) {
+            xr[r] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));
+            orr[r] = xr[r];
+          } else if (stage == 2 || stage == 3) {
+            const R c = (R)(stage == 2 ? 0.25 * h : h / 3.0);
+            orr[r] = mk_<TS>(re_(xr[r]) + c * ar, im_(xr[r]) + c * ai);
+          } else {
+            const double c = 0.5 * h;
+            const double nr = re_(yr[r]) + (double)re_(xr[r]) + c * (double)ar;
+            const double ni = im_(yr[r]) + (double)im_(xr[r]) + c * (double)ai;
+            bad |= (tid + r * nt < T) && !(isfinite(nr) && isfinite(ni));
+            yr[r] = mk_<TY>(nr, ni);
+            orr[r] = mk_<TS>((R)nr, (R)ni);
+          }
+        }
+      }
+      __syncthreads();  // every read of this stage's input is done
+#pragma unroll
+      for (int r = 0; r < kResidentRounds; ++r) {
+        const int p = tid + r * nt;
+        if (r < rounds && p < T) tile[info[p] & 0xffffu] = orr[r];
+      }
+    }
+  }
+  // ---- state (and its stage-precision copy) back to HBM
+  if (steps > 0) {
+    TY* __restrict__ yo = (TY*)it->y;
+    TS* __restrict__ yfo = (TS*)it->yf;
+#pragma unroll
+    for (int r = 0; r < kResidentRounds; ++r) {
+      const int p = tid + r * nt;
+      if (r < rounds && p < T) {
+        yo[p] = yr[r];
+        if (yfo) yfo[p] = orr[r];
+      }
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+template <typename TS, typename TY>
+static void resident_launch_all(const ResidentLaunch& rl, int* flag, hipStream_t st) {
+  dim3 gr(rl.count), bl(rl.threads);
+  switch (rl.nfast) {
+    case 1:
+      hipLaunchKernelGGL((k_rk4_resident<1, TS, TY>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_rk4_resident<2, TS, TY>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_rk4_resident<3, TS, TY>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+      break;
+    default:
+      hipLaunchKernelGGL((k_rk4_resident<4, TS, TY>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+      break;
+  }
+}
+
+#define HGF_RESIDENT_INSTANTIATE(TS, TY, SUFFIX)                                    \
+  void launch_resident_##SUFFIX(const ResidentLaunch& rl, int* flag, hipStream_t st) { \
+    resident_launch_all<TS, TY>(rl, flag, st);                                      \
+  }
+
+}  // namespace hgf

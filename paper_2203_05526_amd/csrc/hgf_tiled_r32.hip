@@ -1,6 +1,8 @@
 // Instantiations of the grouped tiled RK4 stage kernel for float stage grids and a double state.
+#include "hgf_resident.h"
 #include "hgf_tiled.h"
 
 namespace hgf {
 HGF_TILED_INSTANTIATE(float, double, r32)
+HGF_RESIDENT_INSTANTIATE(float, double, r32)
 }  // namespace hgf

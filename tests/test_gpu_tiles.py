@@ -122,7 +122,7 @@ def test_autotune_cache_and_results(hgf, tmp_path):
     cache = str(tmp_path / "tune.txt")
     T, dt = 0.02, 1e-3
     cases = []
-    for cutoff, seed in (((3, 6, 6, 6, 6), 53), ((4, 5, 7), 54)):
+    for cutoff, seed in (((3, 6, 6, 6, 6), 53), ((2, 4, 5, 7, 3), 54)):
         s = synth.random_system(cutoff, seed, scale=3.0, n_th=0.2)
         rng = np.random.default_rng(seed)
         fac = [np.diag(rng.uniform(0.5, 1.5, size=c)).astype(np.complex128) for c in cutoff]
@@ -135,7 +135,7 @@ def test_autotune_cache_and_results(hgf, tmp_path):
     lines = open(cache).read().splitlines()
     assert len(lines) == 2, lines
     assert any(":mixed:real:3x6x6x6x6 " in ln for ln in lines)
-    assert any(":mixed:real:4x5x7 " in ln for ln in lines)
+    assert any(":mixed:real:2x4x5x7x3 " in ln for ln in lines)
     for op in ops:
         cfg = op.tile_config(0)
         assert cfg["stage_us"] > 0.0 and cfg["blocks"] > 0
@@ -158,3 +158,78 @@ def test_autotune_cache_and_results(hgf, tmp_path):
     nocache = hgf.map_operator(cases[1][1], factors=cases[1][2], precision="mixed")
     hgf.autotune([nocache], dt)
     assert nocache.tile_config(0)["stage_us"] > 0.0
+    # a single-tile grid runs on the resident integrator: nothing to tune
+    small = hgf.map_operator(hgf.define_system(synth.random_system((4, 5, 7), 55)),
+                             factors=[np.eye(c, dtype=np.complex128) for c in (4, 5, 7)], precision="mixed")
+    assert small.tile_config(0)["resident"] == 1
+    hgf.autotune([small], dt, cache=cache)
+    assert small.tile_config(0)["stage_us"] == 0.0
+    assert len(open(cache).read().splitlines()) == 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_integrator_matches_stage_launches(hgf, precision):
+    """Grids that are one tile are integrated on chip by one workgroup through
+    all steps of a call.  The result equals the per-stage launches (to
+    rounding) and the oracle, for the 3-mode workload (one real sector) and
+    for a random operator whose 35 sectors all run in one resident launch."""
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    same = 1e-13 if precision == "fp64" else 1e-6
+    announce(f"resident 3-mode {precision}")
+    w = synth.three_mode_c1()
+    S = hgf.define_system(w.system)
+    ops = {}
+    for res in (1, 0):
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        assert op.tile_config(0)["resident"] == 1  # the default for a single-tile grid
+        if res == 0:
+            op.set_tile_config(0, 3, 0, 0, 0, 0, 0)
+            assert op.tile_config(0)["resident"] == 0
+        hgf.evolve(op, 0.05, w.dt)
+        hgf.evolve(op, 0.03, w.dt)  # a second call continues from the stored state
+        ops[res] = op
+    a, b = gpu_number_grids(ops[1], w.system.cutoff), gpu_number_grids(ops[0], w.system.cutoff)
+    assert max_rel_err(a, b) < same
+    ref = oracle_number_grids(w.system.cutoff, oracle.evolve(w.system, oracle.product_sectors(w.factors), 0.08, w.dt))
+    assert max_rel_err(a, ref) < tol
+    assert ops[1].info()["steps_done"] == 800
+
+    announce(f"resident multi-sector {precision}")
+    cutoff = (4, 5, 3)
+    s = synth.random_system(cutoff, 71, scale=3.0, n_th=0.2)
+    rng = np.random.default_rng(71)
+    fac = [rng.normal(size=(c, c)) + 1j * rng.normal(size=(c, c)) for c in cutoff]
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, factors=fac, precision=precision)
+    nf = op.info()["n_functions"]
+    assert nf == 7 * 9 * 5
+    assert all(op.tile_config(i)["resident"] == 1 for i in range(nf))
+    T, dt = 0.05, 1e-3
+    hgf.evolve(op, T, dt)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.product_sectors(fac), T, dt))
+    assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
+
+
+def test_resident_members_in_a_batch(hgf):
+    """A batch mixing resident members (small grids) with tiled ones advances
+    each member as its own evolve does and matches the oracle."""
+    announce("resident members in a batch")
+    shapes = [(6, 7), (3, 4, 5), (2, 6, 6, 6, 3), (9,), (3, 3, 3, 3, 3)]
+    T, dt = [0.02, 0.03, 0.01, 0.04, 0.02], 1e-3
+    systems, facs = [], []
+    for i, c in enumerate(shapes):
+        systems.append(synth.random_system(c, 80 + i, scale=3.0, n_th=0.2))
+        rng = np.random.default_rng(80 + i)
+        facs.append([np.triu(np.tril(rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k)), 1)) for k in c])
+    batch = [hgf.map_operator(hgf.define_system(s), factors=f, precision="mixed") for s, f in zip(systems, facs)]
+    single = [hgf.map_operator(hgf.define_system(s), factors=f, precision="mixed") for s, f in zip(systems, facs)]
+    kinds = {op.tile_config(0)["resident"] for op in batch}
+    assert kinds == {0, 1}
+    hgf.evolve_batch(batch, T, [dt] * len(batch))
+    for op, t in zip(single, T):
+        hgf.evolve(op, t, dt)
+    for op_b, op_s, c, s, f, t in zip(batch, single, shapes, systems, facs, T):
+        a, b = gpu_number_grids(op_b, c), gpu_number_grids(op_s, c)
+        assert max_rel_err(a, b) < 1e-6, c
+        ref = oracle_number_grids(c, oracle.evolve(s, oracle.product_sectors(f), t, dt))
+        assert max_rel_err(a, ref) < MIXED_TOL, c
