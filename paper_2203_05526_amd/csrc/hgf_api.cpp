@@ -309,11 +309,20 @@ static bool resident_eligible(Function& f) {
   const GridArgs& g = f.ga;
   if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
   if (g.tile_points > resident_max_points()) return false;
-  f.res_threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (g.tile_points + 63) / 64 * 64));
+  // two padded copies of the grid in LDS
+  const int es = (f.ga.real ? 1 : 2) * (f.precision_fp64 ? 8 : 4);
+  const int64_t lds = 2 * (int64_t)g.lds_elems * es;
+  if (lds > 65536) return false;
+  f.res_lds_bytes = (int)lds;
+  // lanes: enough for the fewest rounds, spread evenly over them
+  const int64_t rounds = (g.tile_points + 1023) / 1024;
+  const int64_t per = (g.tile_points + rounds - 1) / rounds;
+  f.res_threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (per + 63) / 64 * 64));
   return true;
 }
 
 static void fill_grid_args(Function& f, int precision, bool want_real) {
+  f.precision_fp64 = precision == HGF_FP64;
   GridArgs& g = f.ga;
   std::memset(&g, 0, sizeof(g));
   const SectorTables& t = f.tab;
@@ -815,7 +824,7 @@ static StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resid
       ri.h = it.h;
       host.push_back(ri);
       rl.threads = std::max(rl.threads, it.f->res_threads);
-      rl.lds_bytes = std::max(rl.lds_bytes, it.f->ga.lds_bytes);
+      rl.lds_bytes = std::max(rl.lds_bytes, it.f->res_lds_bytes);
     }
     rl.count = (int)host.size();
     void* d = dmalloc(host.size() * sizeof(ResidentItem));
@@ -1760,6 +1769,7 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     if (cfg->resident) {  // check on a copy first: the function is unchanged on error
       Function probe;
       probe.split = f.split;
+      probe.precision_fp64 = f.precision_fp64;
       probe.ga = f.ga;
       if (c.nfast == 0 || !configure_tiles(probe.ga, op->precision, f.real, c) || !resident_eligible(probe))
         fail(HGF_EINVAL, "the resident form needs the whole grid in one tile of at most 4096 points");

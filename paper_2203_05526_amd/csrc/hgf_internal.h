@@ -165,6 +165,8 @@ struct Function {
   double tuned_us = 0.0;  // stage time measured by the autotuner for the current shape
   bool resident = false;  // integrated on chip by the resident kernel
   int res_threads = 0;    // workgroup size of the resident kernel
+  int res_lds_bytes = 0;  // its LDS (two padded copies of the grid)
+  bool precision_fp64 = false;
 };
 
 struct StepPlan;

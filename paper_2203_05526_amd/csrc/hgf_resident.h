@@ -4,12 +4,12 @@
 // whole grid is a single tile), one workgroup does all the work of a stage
 // launch anyway.  The resident form keeps that workgroup's grid on chip for
 // many RK4 steps: the stencil input of the current stage lives in LDS (the
-// padded zero-halo layout of the tiled kernel), and each lane keeps its
-// points' state y and X1 in registers.  A stage is: read the neighbours from
-// LDS, compute the stage value (the same delta-Horner arithmetic as the
-// tiled kernel), barrier, write the stage value back to LDS, barrier.  HBM is
-// touched only to load y at the start and store y (and its stage-precision
-// copy) at the end.
+// padded zero-halo layout of the tiled kernel, two copies used in turn), and
+// each lane keeps its points' state y, X1 and per-point coefficients in
+// registers.  A stage is: read the neighbours from one LDS copy, compute the
+// stage value (the same delta-Horner arithmetic as the tiled kernel), write
+// it into the other copy, barrier.  HBM is touched only to load y at the
+// start and store y (and its stage-precision copy) at the end.
 //
 // One launch covers a list of such functions, one workgroup each (all the
 // small sectors of an operator, or the small members of a batch).
@@ -39,90 +39,85 @@ __global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __res
     if (tid == 0) atomicOr(flag, 2);
     return;
   }
-  TS* const tile = (TS*)smem;
-  TS* const lamf = tile + it->g.lds_elems;
-  uint32_t* const info = (uint32_t*)(lamf + T);
-  R* const btab = (R*)(info + ((T + 1) & ~1));
-  const int cbits = it->g.cbits;
-  const uint32_t cmask = (1u << cbits) - 1u;
+  // Two padded tiles (zero halo, the tiled kernel's layout with every axis
+  // fast): a stage reads one and writes the other, so one barrier per stage
+  // separates the writes of a stage from the reads of the next.
+  const int E = it->g.lds_elems;
+  TS* const buf0 = (TS*)smem;
+  TS* const buf1 = buf0 + E;
+  for (int i = tid; i < 2 * E; i += nt) buf0[i] = mk_<TS>(0, 0);
 
-  // ---- zero halo and per-position tables (layout of the tiled kernel with
-  // every axis fast)
-  for (int i = tid; i < it->g.lds_elems; i += nt) tile[i] = mk_<TS>(0, 0);
-  for (int p = tid; p < T; p += nt) {
-    int rem = p;
-    uint32_t off = 0, coords = 0;
-    double lr = 0.0, li = 0.0;
+  // ---- per-point constants in registers: LDS slot, diagonal coefficient,
+  // up-jump coefficient per axis.  Lanes past the grid's end (last round)
+  // work on a copy of the last point and store nothing.
+  const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
+  int slot[kResidentRounds];
+  R lrr[kResidentRounds], lir[kResidentRounds], bqr[kResidentRounds][NF];
 #pragma unroll
-    for (int q = NF - 1; q >= 0; --q) {
-      const int e = it->g.ext[q];
-      const int c = rem % e;
-      rem /= e;
-      off += (uint32_t)(c + 1) * (uint32_t)it->g.pstride[q];
-      coords |= (uint32_t)c << (cbits * q);
-      const double2 lj = it->g.lam[it->g.off[q] + c];
-      lr += lj.x;
-      li += lj.y;
-    }
-    info[p] = off | (coords << 16);
-    lamf[p] = mk_<TS>((R)lr, (R)li);
-  }
-  {
-    int o = 0;
+  for (int r = 0; r < kResidentRounds; ++r) {
+    if (r < rounds) {
+      int rem = min(tid + r * nt, T - 1);
+      int off = 0;
+      double lr = 0.0, li = 0.0;
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-      for (int c = tid; c < it->g.ext[q]; c += nt) btab[o + c] = (R)it->g.beta[it->g.off[q] + c];
-      o += it->g.ext[q];
+      for (int q = NF - 1; q >= 0; --q) {
+        const int e = it->g.ext[q];
+        const int c = rem % e;
+        rem /= e;
+        off += (c + 1) * it->g.pstride[q];
+        const double2 lj = it->g.lam[it->g.off[q] + c];
+        lr += lj.x;
+        li += lj.y;
+        bqr[r][q] = (R)it->g.beta[it->g.off[q] + c];
+      }
+      slot[r] = off;
+      // the same rounding as the tiled kernel: per-point sum in FP64, then the
+      // stage type, then the constant part added in the stage type
+      lrr[r] = lr0 + (R)lr;
+      lir[r] = li0 + (R)li;
     }
   }
-  __syncthreads();
+  R aq[NF];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) aq[q] = (R)it->g.alpha[q];
+  __syncthreads();  // halo zeroed before the interior is written
 
   // ---- state into registers, stage-1 stencil input (y in the stage
-  // precision) into LDS
+  // precision) into buffer 0
   const TY* __restrict__ y = (const TY*)it->y;
   TY yr[kResidentRounds];
   TS xr[kResidentRounds], orr[kResidentRounds];
-  // lanes past the grid's end (last round) work on a copy of the last point
-  // and store nothing
 #pragma unroll
   for (int r = 0; r < kResidentRounds; ++r) {
     const int p = tid + r * nt;
     if (r < rounds) {
       yr[r] = y[min(p, T - 1)];
       orr[r] = mk_<TS>((R)re_(yr[r]), (R)im_(yr[r]));
-      if (p < T) tile[info[p] & 0xffffu] = orr[r];
+      if (p < T) buf0[slot[r]] = orr[r];
     }
   }
-  const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
   const double h = it->h;
   const int steps = it->steps;
   int bad = 0;
+  const TS* cur = buf0;
+  TS* nxt = buf1;
   for (int s = 0; s < steps; ++s) {
 #pragma unroll 1
     for (int stage = 1; stage <= 4; ++stage) {
-      __syncthreads();  // LDS holds this stage's stencil input
+      __syncthreads();  // `cur` holds this stage's stencil input
 #pragma unroll
       for (int r = 0; r < kResidentRounds; ++r) {
         if (r < rounds) {
-          const int p = min(tid + r * nt, T - 1);
-          const uint32_t inf = info[p];
-          const int lo_ = (int)(inf & 0xffffu);
-          const TS zc = tile[lo_];
-          const TS lf = lamf[p];
-          const R lr = lr0 + re_(lf), li = li0 + im_(lf);
-          R ar = lr * re_(zc) - li * im_(zc);
-          R ai = lr * im_(zc) + li * re_(zc);
-          int bo = 0;
+          const int lo_ = slot[r];
+          const TS zc = cur[lo_];
+          R ar = lrr[r] * re_(zc) - lir[r] * im_(zc);
+          R ai = lrr[r] * im_(zc) + lir[r] * re_(zc);
 #pragma unroll
           for (int q = 0; q < NF; ++q) {
-            const TS dn = tile[lo_ - it->g.pstride[q]];
-            const TS upv = tile[lo_ + it->g.pstride[q]];
-            const int c = (int)((inf >> (16 + cbits * q)) & cmask);
-            const R bq = btab[bo + c];
-            const R aq = (R)it->g.alpha[q];
-            ar += aq * re_(dn) + bq * re_(upv);
-            ai += aq * im_(dn) + bq * im_(upv);
-            bo += it->g.ext[q];
+            const TS dn = cur[lo_ - it->g.pstride[q]];
+            const TS upv = cur[lo_ + it->g.pstride[q]];
+            ar += aq[q] * re_(dn) + bqr[r][q] * re_(upv);
+            ai += aq[q] * im_(dn) + bqr[r][q] * im_(upv);
           }
           if (stage == 1) {
             xr[r] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));
@@ -138,14 +133,12 @@ __global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __res
             yr[r] = mk_<TY>(nr, ni);
             orr[r] = mk_<TS>((R)nr, (R)ni);
           }
+          if (tid + r * nt < T) nxt[lo_] = orr[r];
         }
       }
-      __syncthreads();  // every read of this stage's input is done
-#pragma unroll
-      for (int r = 0; r < kResidentRounds; ++r) {
-        const int p = tid + r * nt;
-        if (r < rounds && p < T) tile[info[p] & 0xffffu] = orr[r];
-      }
+      const TS* t = cur;
+      cur = nxt;
+      nxt = const_cast<TS*>(t);
     }
   }
   // ---- state (and its stage-precision copy) back to HBM
