@@ -353,18 +353,84 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_partial(GridArgs g, Stri
   if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// out = analytic + sum_f coef_f * sum_{b in f} partial[b], in a fixed order
-__global__ void k_expect_final(const double2* __restrict__ partial, const int* __restrict__ start,
-                               const double2* __restrict__ coef, int nfun, double2 analytic,
-                               double2* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Tiled form for grids with a tiled stage configuration: the weight factorises
+// into a fast part (the trailing nfast axes, one tile) and a slow part (one
+// value per tile).  The fast weights of a tile are built once per block in LDS;
+// a block then sums w_fast(p) g(t, p) over each of its tiles t and adds the
+// tile sum times w_slow(t).  Per point: one LDS read, one grid read, one
+// complex multiply-add.
+constexpr int kExpectTileBlocksPerCU = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_expect_tiled(GridArgs g, const T* __restrict__ grid,
+                                                             const double2* __restrict__ wtab,
+                                                             double2* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2* wf = (double2*)smem;
+  const int Tp = (int)g.tile_points;
+  const int ns = g.n - g.nfast;
+  for (int p = threadIdx.x; p < Tp; p += blockDim.x) {
+    int rem = p;
+    double2 w = make_double2(1.0, 0.0);
+    for (int j = g.n - 1; j >= ns; --j) {
+      const int c = rem % g.ext[j];
+      rem /= g.ext[j];
+      w = cmul(w, wtab[g.off[j] + c]);
+    }
+    wf[p] = w;
+  }
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+  const uint32_t ntiles = (uint32_t)g.ntiles;  // < 2^31 for a tiled grid
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t rem = t;
+    double2 wsl = make_double2(1.0, 0.0);
+    for (int j = ns - 1; j >= 0; --j) {
+      const uint32_t e = (uint32_t)g.ext[j];
+      const uint32_t q = rem / e;
+      wsl = cmul(wsl, wtab[g.off[j] + (int)(rem - q * e)]);
+      rem = q;
+    }
+    const T* __restrict__ gt = grid + (size_t)t * (size_t)Tp;
+    double2 acc = make_double2(0.0, 0.0);
+    // the tile's values are loaded kBatch at a time before they are used, so
+    // that a lane has several loads in flight
+    constexpr int kBatch = 8;
+    for (int p0 = threadIdx.x; p0 < Tp; p0 += kBatch * blockDim.x) {
+      T v[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int p = p0 + k * blockDim.x;
+        if (p < Tp) v[k] = gt[p];
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int p = p0 + k * blockDim.x;
+        if (p < Tp) acc = cadd(acc, cmul(wf[p], make_double2((double)re_(v[k]), (double)im_(v[k]))));
+      }
+    }
+    s = cadd(s, cmul(wsl, acc));
+  }
+  const double2 r = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// out = analytic + sum_f coef_f * sum_{b in f} partial[b]: one block; lane i
+// sums partials i, i + 256, ... of a function, then the block sum; a fixed
+// order throughout, so the result is reproducible.
+__global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __restrict__ partial,
+                                                             const int* __restrict__ start,
+                                                             const double2* __restrict__ coef, int nfun,
+                                                             double2 analytic, double2* __restrict__ out) {
   double2 tot = analytic;
   for (int f = 0; f < nfun; ++f) {
     double2 s = make_double2(0.0, 0.0);
-    for (int b = start[f]; b < start[f + 1]; ++b) s = cadd(s, partial[b]);
-    tot = cadd(tot, cmul(coef[f], s));
+    for (int b = start[f] + (int)threadIdx.x; b < start[f + 1]; b += blockDim.x) s = cadd(s, partial[b]);
+    const double2 r = block_sum(s);
+    tot = cadd(tot, cmul(coef[f], r));
+    __syncthreads();  // block_sum's shared slots are reused by the next function
   }
-  *out = tot;
+  if (threadIdx.x == 0) *out = tot;
 }
 
 // ------------------------------------------------------------ adjoint sweep
@@ -595,10 +661,29 @@ void launch_classical(int stage, int precision, const GridArgs& g, const void* i
   }
 }
 
-int expect_blocks(const GridArgs& g) { return shape_for(g, 1024).blocks; }
+static bool expect_tiled(const GridArgs& g) { return g.blocks > 0 && g.tile_points * 16 <= 65536; }
+
+static int expect_tile_blocks(const GridArgs& g) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g.ntiles, (int64_t)cus * kExpectTileBlocksPerCU));
+}
+
+int expect_blocks(const GridArgs& g) { return expect_tiled(g) ? expect_tile_blocks(g) : shape_for(g, 1024).blocks; }
 
 void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, const double2* wtab,
                            double2* partial, hipStream_t st, bool real) {
+  if (expect_tiled(g)) {
+    const dim3 gr(expect_tile_blocks(g)), bl(kRedThreads);
+    const size_t lds = (size_t)g.tile_points * sizeof(double2);
+    if (real)
+      hipLaunchKernelGGL((k_expect_tiled<double>), gr, bl, lds, st, g, (const double*)grid, wtab, partial);
+    else if (grid_fp64)
+      hipLaunchKernelGGL((k_expect_tiled<double2>), gr, bl, lds, st, g, (const double2*)grid, wtab, partial);
+    else
+      hipLaunchKernelGGL((k_expect_tiled<float2>), gr, bl, lds, st, g, (const float2*)grid, wtab, partial);
+    return;
+  }
   const LaunchShape ls = shape_for(g, 1024);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   if (real)
@@ -614,7 +699,7 @@ void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, 
 
 void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
                          double2 analytic, double2* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(64), 0, st, partial, start, coef, nfun, analytic, out);
+  hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, partial, start, coef, nfun, analytic, out);
 }
 
 void launch_adjoint(int stage, const GridArgs& g, const double2* in, const double2* fwd, const double2* mu,
