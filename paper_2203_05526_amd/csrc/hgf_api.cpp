@@ -857,6 +857,37 @@ static void run_resident(StepPlan& plan, int64_t steps, int* flag, hipStream_t s
   }
 }
 
+// One Horner stage of one function with explicit buffers (stage input `in`,
+// X1, state, stage output), on the tiled kernel where the function has a
+// tiled configuration, else the generic one.
+static void stage_launch(const Function& f, int precision, int stage, const void* in, const void* x1, void* y,
+                         void* yf, void* out, double h, int* flag, hipStream_t st) {
+  if (f.ga.blocks == 0) {
+    launch_horner(stage, precision, f.ga, in, x1, y, yf, out, h, flag, st);
+    return;
+  }
+  GroupLaunch gl{};
+  MemberArgs& m = gl.single;
+  m.g = f.ga;
+  m.in[stage - 1] = in;
+  m.x1 = x1;
+  m.y = y;
+  m.yf = yf;
+  m.out[stage - 1] = out;
+  m.h = h;
+  gl.members = nullptr;
+  gl.nmem = 1;
+  gl.total_tiles = f.ga.ntiles;
+  gl.nfast = f.ga.nfast;
+  gl.nslow = f.ga.n - f.ga.nfast;
+  gl.threads = f.ga.threads;
+  gl.lds_bytes = f.ga.lds_bytes;
+  gl.blocks = f.ga.blocks;
+  gl.real = f.ga.real;
+  gl.precision = precision;
+  launch_group(gl, stage, flag, st);
+}
+
 static void generic_stage(const PlanItem& it, int s, int* flag, hipStream_t st) {
   Function& f = *it.f;
   const void* in[4] = {it.precision == HGF_MIXED ? f.yf : f.y, f.s1, f.s2, f.s3};
@@ -892,6 +923,15 @@ static void ensure_plan(hgf_operator_s* op, double h) {
   op->plan = build_plan(items);
   op->graph_dt = h;
 }
+
+// Owns an executable graph.
+struct GraphHolder {
+  hipGraphExec_t e;
+  explicit GraphHolder(hipGraphExec_t x) : e(x) {}
+  ~GraphHolder() { (void)hipGraphExecDestroy(e); }
+  GraphHolder(const GraphHolder&) = delete;
+  GraphHolder& operator=(const GraphHolder&) = delete;
+};
 
 static hipGraphExec_t capture_steps(const StepPlan& plan, int* flag, int chunk, hipStream_t cap) {
   hipGraph_t graph;
@@ -1442,6 +1482,9 @@ static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStr
 
 // ------------------------------------------------------------------ gradient
 
+// Longest reverse segment captured as one graph (about 12 nodes per step).
+constexpr int64_t kGradGraphSteps = 512;
+
 static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
                       double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
   const int64_t M = check_steps(T, dt);
@@ -1463,6 +1506,14 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     }
   } guard{op};
   op.dflag = (int*)dmalloc(sizeof(int));
+  hipStream_t cap = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } sg{cap};
   build_functions(&op, &d2, false);
   check_stability(op.fn, dt);
   const auto amps = all_amps(sys, psi);
@@ -1486,9 +1537,21 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     DBuf y0(gb);
     hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
     std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, false));
-    for (int64_t s = 0; s < M; ++s) {
-      run_plan_step(*fplan, op.dflag, st);
-      if ((s + 1) % ce == 0) hip_check(hipMemcpyAsync(ck + ((s + 1) / ce) * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+    // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
+    {
+      const int64_t full = M / ce;
+      if (full > 0) {
+        const int chunk = (int)std::min<int64_t>(ce, 64);
+        GraphHolder g(capture_steps(*fplan, op.dflag, chunk, cap));
+        for (int64_t c = 1; c <= full; ++c) {
+          int64_t done = 0;
+          for (; done + chunk <= ce; done += chunk) hip_check(hipGraphLaunch(g.e, st), "graph launch");
+          for (; done < ce; ++done) run_plan_step(*fplan, op.dflag, st);
+          hip_check(hipMemcpyAsync(ck + c * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+        }
+        hip_check(hipStreamSynchronize(st), "synchronize");
+      }
+      for (int64_t s = full * ce; s < M; ++s) run_plan_step(*fplan, op.dflag, st);
     }
     // value
     {
@@ -1509,28 +1572,54 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     hip_check(hipMemcpyAsync(mu.p, wt.p, gb, hipMemcpyDeviceToDevice, st), "seed");
     launch_fill_zero(Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
     double2* seg = segbuf.as<double2>();
-    for (int64_t c = nseg - 1; c >= 0; --c) {
-      const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
-      // recompute y_{s0} .. y_{s0+L-1} into the segment buffer
-      hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+    double2* Qp = Q.as<double2>();
+    // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
+    // f.y into the segment buffer, then sweep them in reverse.  The work of a
+    // segment depends only on L, so it is captured once per length.
+    auto segment = [&](int64_t L, hipStream_t s) {
       for (int64_t i = 0; i < L; ++i) {
-        hip_check(hipMemcpyAsync(seg + i * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "save");
-        if (i + 1 < L) run_plan_step(*fplan, op.dflag, st);
+        launch_copy2(seg + i * pts, (const double2*)f.y, pts, s);
+        if (i + 1 < L) run_plan_step(*fplan, op.dflag, s);
       }
       for (int64_t i = L - 1; i >= 0; --i) {
         double2* yn = seg + i * pts;
         // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
-        launch_horner(1, HGF_FP64, f.ga, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, st);
-        launch_horner(2, HGF_FP64, f.ga, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, st);
-        launch_horner(3, HGF_FP64, f.ga, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, st);
-        double2* Qp = Q.as<double2>();
-        launch_adjoint(1, f.ga, mu.as<double2>(), (const double2*)f.s3, nullptr, nullptr, vb2.as<double2>(), Qp, dt, st);
-        launch_adjoint(2, f.ga, vb2.as<double2>(), (const double2*)f.s2, nullptr, nullptr, vb1.as<double2>(), Qp, dt, st);
-        launch_adjoint(3, f.ga, vb1.as<double2>(), (const double2*)f.s1, mu.as<double2>(), vb2.as<double2>(),
-                       xb1.as<double2>(), Qp, dt, st);
-        launch_adjoint(4, f.ga, xb1.as<double2>(), yn, mu.as<double2>(), nullptr, mu.as<double2>(), Qp, dt, st);
+        stage_launch(f, HGF_FP64, 1, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
+        launch_adjoint_noq(1, f.ga, mu.as<double2>(), nullptr, nullptr, vb2.as<double2>(), dt, s);
+        launch_adjoint_noq(2, f.ga, vb2.as<double2>(), nullptr, nullptr, vb1.as<double2>(), dt, s);
+        launch_adjoint_noq(3, f.ga, vb1.as<double2>(), mu.as<double2>(), vb2.as<double2>(), xb1.as<double2>(), dt,
+                           s);
+        launch_adjoint_q(f.ga, mu.as<double2>(), vb2.as<double2>(), vb1.as<double2>(), xb1.as<double2>(),
+                         (const double2*)f.s3, (const double2*)f.s2, (const double2*)f.s1, yn, Qp, dt, s);
+        launch_adjoint_noq(4, f.ga, xb1.as<double2>(), mu.as<double2>(), nullptr, mu.as<double2>(), dt, s);
       }
+    };
+    std::map<int64_t, std::unique_ptr<GraphHolder>> seg_graphs;
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
+      hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+      if (L > kGradGraphSteps) {  // long segments run without a graph
+        segment(L, st);
+        continue;
+      }
+      auto it = seg_graphs.find(L);
+      if (it == seg_graphs.end()) {
+        hip_check(hipStreamSynchronize(st), "synchronize");
+        hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        segment(L, cap);
+        hipGraph_t graph;
+        hip_check(hipStreamEndCapture(cap, &graph), "end capture");
+        hipGraphExec_t exec;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "graph instantiate");
+        it = seg_graphs.emplace(L, std::unique_ptr<GraphHolder>(new GraphHolder(exec))).first;
+      }
+      hip_check(hipGraphLaunch(it->second->e, st), "graph launch");
     }
+    hip_check(hipStreamSynchronize(st), "synchronize");  // graphs are destroyed with seg_graphs
     // leave the function at its initial state
     hip_check(hipMemcpyAsync(f.y, y0.p, gb, hipMemcpyDeviceToDevice, st), "restore");
     // marginals of Q -> parameter derivatives

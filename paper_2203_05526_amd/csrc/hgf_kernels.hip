@@ -434,7 +434,8 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __r
 }
 
 // ------------------------------------------------------------ adjoint sweep
-// One reverse RK4 step in the merged form (see k_horner):
+// One reverse RK4 step in the merged form (see k_horner); the stages run as
+// k_adjoint_noq and the products "Q += ..." of all four as one k_adjoint_q:
 //   B1: Vb2 = (h/2) L^T mu                 Q += (h/2) mu  (x) V2
 //   B2: Vb1 = (h/3) L^T Vb2                Q += (h/3) Vb2 (x) V1
 //   B3: Xb1 = mu + Vb2 + Vb1 + (h/4) L^T Vb1   Q += (h/4) Vb1 (x) X1
@@ -444,11 +445,12 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __r
 //   Q0(m) += a(m) b(m),  Qd_j(m) += a(m) b(m-e_j),  Qu_j(m) += a(m) b(m+e_j).
 // Q is laid out as (1 + 2N) consecutive planes of `points` complex values.
 
+// The four stages without the parameter products (those of a whole step are
+// accumulated by k_adjoint_q in one pass).
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_adjoint(GridArgs g, StrideDigits sd, const double2* __restrict__ in,
-                                                 const double2* __restrict__ fwd, const double2* mu,
-                                                 const double2* __restrict__ vb2, double2* out,
-                                                 double2* __restrict__ Q, double h) {
+__global__ __launch_bounds__(256) void k_adjoint_noq(GridArgs g, StrideDigits sd, const double2* __restrict__ in,
+                                                     const double2* mu, const double2* __restrict__ vb2,
+                                                     double2* out, double h) {
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 >= g.points) return;
   const double c = STAGE == 1 ? 0.5 * h : STAGE == 2 ? h / 3.0 : STAGE == 3 ? 0.25 * h : h;
@@ -456,28 +458,67 @@ __global__ __launch_bounds__(256) void k_adjoint(GridArgs g, StrideDigits sd, co
   walker_init(w, g, i0);
   while (w.i < g.points) {
     const double2 lt = apply_LT(g, in, w);
-    const double2 a = cscale(c, in[w.i]);
     double2 o = cscale(c, lt);
     if (STAGE == 3) o = cadd(o, cadd(mu[w.i], cadd(vb2[w.i], in[w.i])));
     if (STAGE == 4) o = cadd(o, mu[w.i]);
-    // parameter products
-    const int64_t P = g.points;
-    Q[w.i] = cadd(Q[w.i], cmul(a, fwd[w.i]));
+    out[w.i] = o;
+    walker_step(w, g, sd);
+  }
+}
+
+// Parameter products of one reverse step, in the order the four stages would
+// add them: Q += (h/2) mu (x) V2, (h/3) Vb2 (x) V1, (h/4) Vb1 (x) X1, h Xb1 (x) y.
+// Runs after B3 and before B4 (which overwrites mu).  One read-modify-write of
+// the 1 + 2N planes per step instead of one per stage.
+__global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, const double2* __restrict__ mu,
+                                                   const double2* __restrict__ vb2,
+                                                   const double2* __restrict__ vb1,
+                                                   const double2* __restrict__ xb1,
+                                                   const double2* __restrict__ v2, const double2* __restrict__ v1,
+                                                   const double2* __restrict__ x1, const double2* __restrict__ y,
+                                                   double2* __restrict__ Q, double h) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  const int64_t P = g.points;
+  while (w.i < g.points) {
+    const double2 a1 = cscale(0.5 * h, mu[w.i]), a2 = cscale(h / 3.0, vb2[w.i]);
+    const double2 a3 = cscale(0.25 * h, vb1[w.i]), a4 = cscale(h, xb1[w.i]);
+    {
+      double2 q = Q[w.i];
+      q = cadd(q, cmul(a1, v2[w.i]));
+      q = cadd(q, cmul(a2, v1[w.i]));
+      q = cadd(q, cmul(a3, x1[w.i]));
+      q = cadd(q, cmul(a4, y[w.i]));
+      Q[w.i] = q;
+    }
 #pragma unroll
     for (int j = 0; j < kMaxModes; ++j) {
       if (j < g.n) {
         const int m = w.c[j];
         if (m >= 1) {
-          double2& q = Q[(1 + j) * P + w.i];
-          q = cadd(q, cmul(a, fwd[w.i - g.stride[j]]));
+          const int64_t k = w.i - g.stride[j];
+          double2& qr = Q[(1 + j) * P + w.i];
+          double2 q = qr;
+          q = cadd(q, cmul(a1, v2[k]));
+          q = cadd(q, cmul(a2, v1[k]));
+          q = cadd(q, cmul(a3, x1[k]));
+          q = cadd(q, cmul(a4, y[k]));
+          qr = q;
         }
         if (m + 1 < g.ext[j]) {
-          double2& q = Q[(1 + g.n + j) * P + w.i];
-          q = cadd(q, cmul(a, fwd[w.i + g.stride[j]]));
+          const int64_t k = w.i + g.stride[j];
+          double2& qr = Q[(1 + g.n + j) * P + w.i];
+          double2 q = qr;
+          q = cadd(q, cmul(a1, v2[k]));
+          q = cadd(q, cmul(a2, v1[k]));
+          q = cadd(q, cmul(a3, x1[k]));
+          q = cadd(q, cmul(a4, y[k]));
+          qr = q;
         }
       }
     }
-    out[w.i] = o;
     walker_step(w, g, sd);
   }
 }
@@ -485,12 +526,13 @@ __global__ __launch_bounds__(256) void k_adjoint(GridArgs g, StrideDigits sd, co
 // Marginals of Q: bins[0 .. sum e) hold sum over m with m_j = v of Q0,
 // bins[sum e .. sum e + N) hold sum of Qd_j, bins[sum e + N ..) sum over
 // m_j = v of Qu_j.  One thread per bin walks its slice in a fixed order.
-__global__ void k_marginals(GridArgs g, const double2* __restrict__ Q, double2* __restrict__ bins) {
+// One block per bin; the block's lanes sum fixed strided subsets of the bin's
+// points, then the block sum (a fixed order: reproducible).
+__global__ __launch_bounds__(kRedThreads) void k_marginals(GridArgs g, const double2* __restrict__ Q,
+                                                          double2* __restrict__ bins) {
   int tot_e = 0;
   for (int j = 0; j < g.n; ++j) tot_e += g.ext[j];
-  const int nb = 2 * tot_e + g.n;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+  const int b = blockIdx.x;
   int kind, axis = 0, val = 0;
   if (b < tot_e) {
     kind = 0;
@@ -510,21 +552,29 @@ __global__ void k_marginals(GridArgs g, const double2* __restrict__ Q, double2* 
       Q + (kind == 0 ? 0 : kind == 1 ? (int64_t)(1 + axis) * g.points : (int64_t)(1 + g.n + axis) * g.points);
   double2 s = make_double2(0.0, 0.0);
   if (kind == 1) {
-    for (int64_t i = 0; i < g.points; ++i) s = cadd(s, plane[i]);
+    for (int64_t i = threadIdx.x; i < g.points; i += blockDim.x) s = cadd(s, plane[i]);
   } else {
-    // iterate over all points whose coordinate `axis` equals val
+    // the points whose coordinate `axis` equals val: (outer, val, inner)
     const int64_t st = g.stride[axis];
-    const int64_t outer = g.points / (st * g.ext[axis]);
-    for (int64_t o = 0; o < outer; ++o)
-      for (int64_t inner = 0; inner < st; ++inner) s = cadd(s, plane[(o * g.ext[axis] + val) * st + inner]);
+    const int64_t n = g.points / g.ext[axis];
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+      const int64_t o = k / st, inner = k - o * st;
+      s = cadd(s, plane[(o * g.ext[axis] + val) * st + inner]);
+    }
   }
-  bins[b] = s;
+  const double2 r = block_sum(s);
+  if (threadIdx.x == 0) bins[b] = r;
 }
 
 // ------------------------------------------------------------ misc
 __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_copy2(double2* __restrict__ dst, const double2* __restrict__ src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 __global__ void k_fill_weights(GridArgs g, StrideDigits sd, const double2* __restrict__ wtab,
@@ -702,17 +752,26 @@ void launch_expect_final(const double2* partial, const int* start, const double2
   hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, partial, start, coef, nfun, analytic, out);
 }
 
-void launch_adjoint(int stage, const GridArgs& g, const double2* in, const double2* fwd, const double2* mu,
-                    const double2* vb2, double2* out, double2* Q, double h, hipStream_t st) {
+void launch_adjoint_noq(int stage, const GridArgs& g, const double2* in, const double2* mu, const double2* vb2,
+                       double2* out, double h, hipStream_t st) {
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   dim3 gr(ls.blocks), bl(ls.threads);
   switch (stage) {
-    case 1: hipLaunchKernelGGL((k_adjoint<1>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
-    case 2: hipLaunchKernelGGL((k_adjoint<2>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
-    case 3: hipLaunchKernelGGL((k_adjoint<3>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
-    default: hipLaunchKernelGGL((k_adjoint<4>), gr, bl, 0, st, g, sd, in, fwd, mu, vb2, out, Q, h); break;
+    case 1: hipLaunchKernelGGL((k_adjoint_noq<1>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
+    case 2: hipLaunchKernelGGL((k_adjoint_noq<2>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
+    case 3: hipLaunchKernelGGL((k_adjoint_noq<3>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
+    default: hipLaunchKernelGGL((k_adjoint_noq<4>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
   }
+}
+
+void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, const double2* vb1,
+                      const double2* xb1, const double2* v2, const double2* v1, const double2* x1,
+                      const double2* y, double2* Q, double h, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  hipLaunchKernelGGL(k_adjoint_q, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, mu, vb2, vb1, xb1, v2, v1, x1, y,
+                     Q, h);
 }
 
 int marginal_bins(const GridArgs& g) {
@@ -723,13 +782,19 @@ int marginal_bins(const GridArgs& g) {
 
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st) {
   const int nb = marginal_bins(g);
-  hipLaunchKernelGGL(k_marginals, dim3((nb + 63) / 64), dim3(64), 0, st, g, Q, bins);
+  hipLaunchKernelGGL(k_marginals, dim3(nb), dim3(kRedThreads), 0, st, g, Q, bins);
 }
 
 void launch_fill_zero(double2* p, int64_t n, hipStream_t st) {
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, p, n);
+}
+
+void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy2, dim3(blocks), dim3(256), 0, st, dst, src, n);
 }
 
 void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st) {
