@@ -234,24 +234,10 @@ __global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, 
   }
 }
 
-// ------------------------------------------------------------ RK4, tiled form
-//
-// The trailing NF axes of the grid form a tile of T points that is contiguous
-// in memory.  A workgroup stages the tile's stencil input in LDS with a zero
-// halo around every fast axis, so the fast-axis neighbours are unconditional
-// LDS reads; the neighbours along the remaining (slow) axes are whole tiles at
-// a fixed offset and are read from global memory (they are reused across
-// workgroups through L2 and the Infinity Cache).  Coefficients that depend on
-// a fast coordinate (lam_fast, beta) come from per-position LDS tables built
-// once per workgroup; the slow-axis terms are uniform over a tile.
-//
-// Work distribution: the workgroups are persistent.  Workgroup b runs on XCD
-// b % 8, so each XCD is given a contiguous range of tiles and walks it with its
-// own workgroups in step: at any time an XCD's L2 holds a compact window of
-// the grid.  Streaming operands (x1, y, outputs) use non-temporal loads and
-// stores so that they do not evict the stencil input from the caches.
-
-
+// ------------------------------------------------------------ stage-precision copy
+// The tiled RK4 stage kernel lives in hgf_tiled.h, the resident integrator in
+// hgf_resident.h.  yf = y in the stage precision (the stage-1 stencil input of
+// the mixed form), written after a state upload or restore.
 template <typename TY, typename TS>
 __global__ void k_shadow(const TY* __restrict__ y, TS* __restrict__ yf, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -1,4 +1,4 @@
-// Instantiations of the grouped tiled RK4 stage kernel for float2 stage grids and a double2 state.
+// Instantiations of the tiled RK4 stage kernels and the resident integrator for float2 stage grids and a double2 state.
 #include "hgf_resident.h"
 #include "hgf_tiled.h"
 
