@@ -797,9 +797,12 @@ static StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resid
     }
     gl.nmem = (int)mem.size();
     gl.total_tiles = tiles;
-    const int occ =
-        tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real,
-                                mem.size() == 1 ? (kv.second[0].f->ga.pipe ? 2 : 1) : 0);
+    int occ = tiled_max_blocks_per_cu(gl.nfast, gl.nslow, gl.threads, gl.precision, gl.lds_bytes, gl.real,
+                                      mem.size() == 1 ? (kv.second[0].f->ga.pipe ? 2 : 1) : 0);
+    int cap_all = kv.second[0].f->ga.occ_cap;  // members' common cap on resident workgroups per CU
+    for (const PlanItem& it : kv.second)
+      if (it.f->ga.occ_cap != cap_all) cap_all = 0;
+    if (cap_all > 0) occ = std::min(occ, cap_all);
     gl.blocks = (int)std::max<int64_t>(8, std::min<int64_t>((int64_t)cus * occ, 8 * ((tiles + 7) / 8)));
     if (mem.size() == 1) gl.blocks = kv.second[0].f->ga.blocks;  // the function's own (possibly tuned) grid
     void* d = dmalloc(mem.size() * sizeof(MemberArgs));
@@ -1306,6 +1309,151 @@ static TileChoice current_choice(const Function& f) {
   return c;
 }
 
+// Mean stage time (us) of `steps` steps of a set of functions run as one plan.
+static double time_plan_steps(const std::vector<PlanItem>& items, int* flag, int steps, hipStream_t st) {
+  std::unique_ptr<StepPlan> plan(build_plan(items, false));
+  run_plan_step(*plan, flag, st);  // warm-up
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "event");
+  hipError_t e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    hip_check(e, "event");
+  }
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } eg{a, b};
+  hip_check(hipEventRecord(a, st), "event record");
+  for (int i = 0; i < steps; ++i) run_plan_step(*plan, flag, st);
+  hip_check(hipEventRecord(b, st), "event record");
+  hip_check(hipEventSynchronize(b), "event sync");
+  hip_check(hipGetLastError(), "kernel launch");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, a, b), "event time");
+  return 1e3 * (double)ms / (4.0 * steps);
+}
+
+// Grouped launches: the functions of all operators that share an axis split
+// and element types run as one grouped launch per stage (a batch, or the
+// sectors of one operator).  The grouped kernel is tuned as a whole: workgroup
+// size and resident workgroups per CU, applied to every member (their numbers
+// of fast axes are kept).  The cache key names the group's composition.
+static void tune_groups(hgf_operator* ops, int n, double h, const std::string& dev,
+                        std::map<std::string, TuneEntry>& cache, std::set<std::string>& fresh, int flags,
+                        bool& measured, int* flag, hipStream_t st) {
+  std::map<std::vector<int>, std::vector<std::pair<hgf_operator_s*, Function*>>> groups;
+  for (int i = 0; i < n; ++i) {
+    hgf_operator_s* op = ops[i];
+    if (op->layout != HGF_MERGED) continue;
+    for (auto& f : op->fn)
+      if (f.ga.blocks > 0 && !f.resident)
+        groups[{f.ga.nfast, f.ga.n - f.ga.nfast, f.ga.real, op->precision}].push_back({op, &f});
+  }
+  for (auto& kv : groups) {
+    auto& mem = kv.second;
+    if (mem.size() < 2) continue;
+    const int nfast = kv.first[0], prec = kv.first[3];
+    // key: device, element types, axis split, member count and a digest of the
+    // members' extents (order-independent)
+    std::vector<std::string> shapes;
+    for (auto& m : mem) shapes.push_back(tune_key("", *m.second, prec));
+    std::sort(shapes.begin(), shapes.end());
+    uint64_t dig = 1469598103934665603ull;
+    for (auto& sh : shapes)
+      for (char c : sh) dig = (dig ^ (uint64_t)(unsigned char)c) * 1099511628211ull;
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%016llx", (unsigned long long)dig);
+    const std::string key = dev + (prec == HGF_FP64 ? ":fp64" : ":mixed") + (kv.first[2] ? ":real" : ":complex") +
+                            ":group:nf" + std::to_string(nfast) + ":ns" + std::to_string(kv.first[1]) + ":m" +
+                            std::to_string(mem.size()) + ":" + buf;
+    auto apply = [&](const TileChoice& c) {
+      for (auto& m : mem) retile(*m.second, prec, c);
+      for (int i = 0; i < n; ++i) drop_plan(ops[i]);
+    };
+    auto it = cache.find(key);
+    if (it != cache.end() && (!(flags & HGF_TUNE_FORCE) || fresh.count(key))) {
+      try {
+        apply(it->second.c);
+        for (auto& m : mem) m.second->tuned_us = it->second.us;
+      } catch (const Error&) {
+      }
+      continue;
+    }
+    if (flags & HGF_TUNE_CACHED_ONLY) continue;
+    // candidates: workgroup sizes every member can use, full occupancy or one
+    // to three workgroups per CU fewer
+    std::vector<TileChoice> cands;
+    for (int th = 64; th <= 512; th += 64)
+      for (int w : {0, 1, 2, 3, 4, 6}) {
+        TileChoice c;
+        c.nfast = nfast;
+        c.threads = th;
+        c.xblock = 0;
+        c.pipe = 0;
+        c.wgs_per_cu = w;
+        bool ok = true;
+        for (auto& m : mem) {
+          GridArgs g = m.second->ga;
+          if (!configure_tiles(g, prec, m.second->real, c)) {
+            ok = false;
+            break;
+          }
+        }
+        if (ok) cands.push_back(c);
+      }
+    if (cands.empty()) continue;
+    std::vector<PlanItem> items;
+    for (auto& m : mem) items.push_back({m.second, prec, h});
+    std::vector<TileChoice> start;
+    for (auto& m : mem) start.push_back(current_choice(*m.second));
+    for (auto& m : mem) {
+      Function& f = *m.second;
+      const size_t bytes = state_bytes(f);
+      if (!f.ybak) f.ybak = dmalloc(bytes);
+      hip_check(hipMemcpyAsync(f.ybak, f.y, bytes, hipMemcpyDeviceToDevice, st), "backup");
+    }
+    TuneEntry best;
+    best.us = 1e300;
+    try {
+      const double t0 = time_plan_steps(items, flag, 1, st);
+      const int steps = (int)std::max(2.0, std::min(50.0, 2000.0 / std::max(1e-3, 4.0 * t0)));
+      for (const TileChoice& c : cands) {
+        apply(c);
+        const double us = time_plan_steps(items, flag, steps, st);
+        if (us < best.us) {
+          best.us = us;
+          best.c = c;
+        }
+      }
+      apply(best.c);
+    } catch (const Error&) {
+      (void)hipStreamSynchronize(st);
+      for (size_t k = 0; k < mem.size(); ++k) {
+        try {
+          retile(*mem[k].second, prec, start[k]);
+        } catch (const Error&) {
+        }
+      }
+      for (int i = 0; i < n; ++i) drop_plan(ops[i]);
+      throw;
+    }
+    for (auto& m : mem) {
+      Function& f = *m.second;
+      f.tuned_us = best.us;
+      hip_check(hipMemcpyAsync(f.y, f.ybak, state_bytes(f), hipMemcpyDeviceToDevice, st), "restore");
+      launch_shadow(prec, f.ga, f.y, f.yf, st);
+    }
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    cache[key] = best;
+    fresh.insert(key);
+    measured = true;
+  }
+}
+
 static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_path, int flags, hipStream_t st) {
   const std::string dev = device_tag();
   std::map<std::string, TuneEntry> cache = read_tune_cache(cache_path);
@@ -1376,6 +1524,7 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
     }
     drop_plan(op);
   }
+  tune_groups(ops, n, h, dev, cache, fresh, flags, measured, dflag.as<int>(), st);
   if (measured) write_tune_cache(cache_path, cache);
 }
 
