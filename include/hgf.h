@@ -272,9 +272,15 @@ enum {
  * candidate shape (fast axes: the default and one fewer; every workgroup
  * size whose last lane round is at least 3/4 full; both XCD orders; with
  * and without pipelined loads; all resident workgroups per CU or one or two
- * fewer) and applies the fastest to every function of
- * that shape.  The timed steps run on the function's own buffers; its state
- * is restored afterwards, so results are unaffected.  cache_path (may be NULL:
+ * fewer) and applies the fastest to every function of that shape.  Then
+ * each group of two or more functions that run as one grouped launch per
+ * stage (same axis split and element types: the members of a batch, the
+ * sectors of one operator) is timed as a whole over workgroup sizes and
+ * resident workgroups per CU, and the fastest is applied to all its members
+ * (which keep it when evolved alone).  Grid functions that run on the
+ * resident integrator are not tuned.  The timed steps run on the functions'
+ * own buffers; their states are restored afterwards, so results are
+ * unaffected.  cache_path (may be NULL:
  * no cache) names a text file of measured shapes keyed by device
  * architecture and CU count; it is read first and rewritten when shapes were
  * measured.  Errors: HGF_EINVAL (NULL ops, dt <= 0, unwritable cache),
