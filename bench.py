@@ -66,18 +66,19 @@ def kernel_source_hash() -> str:
 
 def stored_traffic(shape: dict):
     """HBM bytes per stage launch from committed rocprofv3 counter runs, or
-    None when the kernel source or the launch shape differs from the one the
-    counters were taken with."""
+    None when the kernel source changed since, or no run used this launch
+    shape."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
-    taken = [int(x) for x in t.get("tune_cache_line", "").split()[1:6]]
-    if taken != [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")]:
-        return None
-    return t.get("traffic_bytes_per_launch")
+    want = [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")]
+    for entry in t.get("shapes", []):
+        if [int(x) for x in entry["tune_cache_line"].split()[1:6]] == want:
+            return entry["traffic_bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(w, steps: int):

@@ -1271,6 +1271,21 @@ static std::vector<TileChoice> tune_candidates(const Function& f, int precision)
   return out;
 }
 
+// The first candidate (in candidate order) within 1 % of the fastest: shapes
+// that time alike within run-to-run noise resolve to the same choice.
+static TuneEntry pick_shape(const std::vector<TileChoice>& cands, const std::vector<double>& times) {
+  double tmin = 1e300;
+  for (double t : times) tmin = std::min(tmin, t);
+  TuneEntry e;
+  for (size_t k = 0; k < cands.size(); ++k)
+    if (times[k] <= 1.01 * tmin) {
+      e.c = cands[k];
+      e.us = times[k];
+      break;
+    }
+  return e;
+}
+
 // Mean stage time (us) of `steps` RK4 steps of one function alone.
 static double time_function_steps(Function& f, int precision, double h, int* flag, int steps, hipStream_t st) {
   std::unique_ptr<StepPlan> plan(build_plan({PlanItem{&f, precision, h}}, false));
@@ -1421,14 +1436,12 @@ static void tune_groups(hgf_operator* ops, int n, double h, const std::string& d
     try {
       const double t0 = time_plan_steps(items, flag, 1, st);
       const int steps = (int)std::max(2.0, std::min(50.0, 2000.0 / std::max(1e-3, 4.0 * t0)));
+      std::vector<double> times;
       for (const TileChoice& c : cands) {
         apply(c);
-        const double us = time_plan_steps(items, flag, steps, st);
-        if (us < best.us) {
-          best.us = us;
-          best.c = c;
-        }
+        times.push_back(time_plan_steps(items, flag, steps, st));
       }
+      best = pick_shape(cands, times);
       apply(best.c);
     } catch (const Error&) {
       (void)hipStreamSynchronize(st);
@@ -1493,14 +1506,12 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
         // enough steps for ~1 ms of timed work per candidate
         const double t0 = time_function_steps(f, op->precision, h, dflag.as<int>(), 1, st);
         const int steps = (int)std::max(2.0, std::min(100.0, 1000.0 / std::max(1e-3, 4.0 * t0)));
+        std::vector<double> times;
         for (const TileChoice& c : cands) {
           retile(f, op->precision, c);
-          const double us = time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st);
-          if (us < best.us) {
-            best.us = us;
-            best.c = c;
-          }
+          times.push_back(time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st));
         }
+        best = pick_shape(cands, times);
         retile(f, op->precision, best.c);
       } catch (const Error&) {
         (void)hipStreamSynchronize(st);
