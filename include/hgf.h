@@ -38,6 +38,7 @@
 #ifndef HGF_H
 #define HGF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -72,7 +73,8 @@ enum {
 /* operator input forms */
 enum {
   HGF_OP_PRODUCT = 0, /* A = tensor product of per-mode Nc_j x Nc_j matrices */
-  HGF_OP_SPARSE = 1   /* A = sum_t value_t M(k_t, l_t) */
+  HGF_OP_SPARSE = 1,  /* A = sum_t value_t M(k_t, l_t) */
+  HGF_OP_DENSE = 2    /* A given entry by entry over the whole truncated space (tiny systems) */
 };
 enum {
   HGF_BASIS_NUMBER = 0, /* entries are number-basis elements <k|A|l> */
@@ -122,7 +124,10 @@ typedef struct {
   int32_t basis;          /* HGF_BASIS_NUMBER or HGF_BASIS_NORMAL */
   const double* values;   /* PRODUCT: the N matrices one after another, each
                              Nc_j x Nc_j row-major complex (2*sum Nc_j^2 doubles);
-                             SPARSE: n_terms complex values (2*n_terms doubles) */
+                             SPARSE: n_terms complex values (2*n_terms doubles);
+                             DENSE: D x D row-major complex, D = prod_j Nc_j <= 4096,
+                             rows and columns k flattened with the last mode fastest
+                             (entry (k, l) is the coefficient of M(k, l)) */
   const int32_t* indices; /* SPARSE only: n_terms rows of 2N ints (k_0..k_{N-1}, l_0..l_{N-1});
                              NUMBER basis: M = |k><l|; NORMAL basis: M = prod_j (a_j^+)^{k_j} a_j^{l_j} */
   int64_t n_terms;        /* SPARSE only */
@@ -142,17 +147,23 @@ typedef struct {
 hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_operator* out);
 void hgf_destroy_operator(hgf_operator op);
 
+/* time-stepping schemes of hgf_evolve */
+enum {
+  HGF_RK4 = 0 /* classical fourth-order Runge-Kutta with a fixed step */
+};
+
 /*
  * Step (ii): advance every function of the operator by t_total_us with
  * classical RK4 steps of dt_us (Heisenberg picture: A(0) -> A(t)).
+ * scheme must be HGF_RK4 (HGF_EUNSUPPORTED otherwise).
  * t_total_us / dt_us must be a non-negative integer (to 1e-9 relative).
  * Errors: HGF_EINVAL; HGF_EUNSTABLE when dt times a bound on the generator's
  * spectral radius leaves the RK4 stability region (nothing is run);
  * HGF_ENONFINITE when a NaN/Inf appears (the functions are restored to the
  * last state checked finite and the operator moves to an error state in which
- * further evolves return HGF_ESTATE); HGF_EDEVICE.
+ * further evolves return HGF_ESTATE until hgf_clear_error); HGF_EDEVICE.
  */
-hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, void* hip_stream);
+hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, int32_t scheme, void* hip_stream);
 
 /*
  * Batched form of hgf_evolve: every member advances by its own t_total/dt
@@ -288,6 +299,25 @@ enum {
  */
 hgf_status hgf_autotune(hgf_operator* ops, int32_t n, double dt_us, const char* cache_path, int32_t flags,
                         void* hip_stream);
+
+/* Leave the error state entered after HGF_ENONFINITE (the functions hold the
+ * state from the start of the failed call).  Errors: HGF_EINVAL. */
+hgf_status hgf_clear_error(hgf_operator op);
+
+/*
+ * Device-memory hook.  With alloc and free set, every device buffer the
+ * library allocates afterwards comes from alloc(bytes, device, user) (which
+ * returns NULL on failure: HGF_ENOMEM) and goes back through
+ * free(ptr, device, user), on the device that allocated it.  Both NULL
+ * restores hipMalloc / hipFree for later allocations; blocks still held from
+ * a replaced hook are then dropped rather than freed (their memory belongs to
+ * the hook's owner, e.g. a framework's caching allocator that is shutting
+ * down).  Buffers are used on the streams passed to the other calls.
+ * Errors: HGF_EINVAL when only one of alloc and free is NULL.
+ */
+typedef void* (*hgf_alloc_fn)(size_t bytes, int32_t device, void* user);
+typedef void (*hgf_free_fn)(void* ptr, int32_t device, void* user);
+hgf_status hgf_set_allocator(hgf_alloc_fn alloc, hgf_free_fn free_fn, void* user);
 
 /* Thread-local message describing the last error of this thread ("" if none). */
 const char* hgf_last_error(void);

@@ -10,6 +10,7 @@ from .hgf import (  # noqa: F401
     Operator,
     System,
     autotune,
+    clear_error,
     define_system,
     evolve,
     evolve_batch,
@@ -19,5 +20,6 @@ from .hgf import (  # noqa: F401
     map_operator,
     param_names,
     params_vector,
+    use_torch_allocator,
     version,
 )

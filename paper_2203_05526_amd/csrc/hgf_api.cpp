@@ -13,10 +13,12 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <set>
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "hgf.h"
@@ -83,15 +85,63 @@ static double factorial(int n) {
   return f;
 }
 
+// ---- device memory: hipMalloc, or the caller's allocator hook
+// Every block remembers where it came from: a block of a hook is returned to
+// that hook, or dropped (left to the hook's owner) once the hook has been
+// replaced, never passed to hipFree.
+struct AllocHook {
+  hgf_alloc_fn alloc = nullptr;
+  hgf_free_fn free = nullptr;
+  void* user = nullptr;
+  uint64_t generation = 0;  // 0: hipMalloc
+};
+static std::mutex g_alloc_mu;
+static AllocHook g_hook;
+static uint64_t g_hook_generation = 0;
+static std::unordered_map<void*, uint64_t> g_hooked;  // block -> generation of its hook
+
 static void* dmalloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
-  hip_check(hipMalloc(&p, bytes), "hipMalloc");
+  AllocHook h;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    h = g_hook;
+  }
+  if (!h.alloc) {
+    hip_check(hipMalloc(&p, bytes), "hipMalloc");
+    return p;
+  }
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  p = h.alloc(bytes, dev, h.user);
+  if (!p) fail(HGF_ENOMEM, "allocator hook returned NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_hooked[p] = h.generation;
   return p;
 }
 
 static void dfree(void*& p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  AllocHook h;
+  bool hooked = false, current = false;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_hooked.find(p);
+    if (it != g_hooked.end()) {
+      hooked = true;
+      current = g_hook.alloc && it->second == g_hook.generation;
+      h = g_hook;
+      g_hooked.erase(it);
+    }
+  }
+  if (!hooked) {
+    (void)hipFree(p);
+  } else if (current) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    h.free(p, dev, h.user);
+  }
   p = nullptr;
 }
 
@@ -436,6 +486,9 @@ struct Coeff {
   cd v;
 };
 
+// Largest total dimension of an HGF_OP_DENSE operator.
+constexpr int64_t kMaxDenseDim = 4096;
+
 // All nonzero g_{k,l}(0) of the operator, as (k, l, value).
 static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map<std::vector<int>, std::vector<cd>>& merged,
                            std::vector<Coeff>& split, bool want_split) {
@@ -515,6 +568,42 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
       while (j >= 0 && ++idx[j] == (int)diags[j].size()) idx[j--] = 0;
       if (j < 0) break;
     }
+    return;
+  }
+  if (d->kind == HGF_OP_DENSE) {
+    // a dense matrix over the whole truncated space: its nonzero entries as a
+    // sparse operator
+    if (!d->values) fail(HGF_EINVAL, "operator values is NULL");
+    int64_t dim = 1;
+    for (int j = 0; j < n; ++j) {
+      dim *= s.nc[j];
+      if (dim > kMaxDenseDim) fail(HGF_EINVAL, "dense operator larger than 4096 x 4096; use HGF_OP_SPARSE");
+    }
+    std::vector<int32_t> idx;
+    std::vector<double> vals;
+    for (int64_t r = 0; r < dim; ++r)
+      for (int64_t c = 0; c < dim; ++c) {
+        const double re = d->values[2 * (r * dim + c)], im = d->values[2 * (r * dim + c) + 1];
+        if (re == 0.0 && im == 0.0) continue;
+        int64_t kr = r, kc = c;
+        std::vector<int32_t> k(n), l(n);
+        for (int j = n - 1; j >= 0; --j) {
+          k[j] = (int32_t)(kr % s.nc[j]);
+          kr /= s.nc[j];
+          l[j] = (int32_t)(kc % s.nc[j]);
+          kc /= s.nc[j];
+        }
+        idx.insert(idx.end(), k.begin(), k.end());
+        idx.insert(idx.end(), l.begin(), l.end());
+        vals.push_back(re);
+        vals.push_back(im);
+      }
+    hgf_operator_desc sp = *d;
+    sp.kind = HGF_OP_SPARSE;
+    sp.values = vals.data();
+    sp.indices = idx.data();
+    sp.n_terms = (int64_t)(vals.size() / 2);
+    collect_coeffs(s, &sp, merged, split, want_split);
     return;
   }
   if (d->kind != HGF_OP_SPARSE) fail(HGF_EINVAL, "unknown operator kind");
@@ -1662,7 +1751,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     hgf_operator_s& o;
     ~OpGuard() {
       for (auto& f : o.fn) free_function(f);
-      if (o.dflag) (void)hipFree(o.dflag);
+      if (o.dflag) dfree(*(void**)&o.dflag);
     }
   } guard{op};
   op.dflag = (int*)dmalloc(sizeof(int));
@@ -1902,14 +1991,33 @@ void hgf_destroy_operator(hgf_operator op) {
   (void)hipSetDevice(op->device);
   drop_plan(op);
   for (auto& f : op->fn) free_function(f);
-  if (op->dflag) (void)hipFree(op->dflag);
+  if (op->dflag) dfree(*(void**)&op->dflag);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   delete op;
 }
 
-hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, void* hip_stream) {
+hgf_status hgf_set_allocator(hgf_alloc_fn alloc, hgf_free_fn free_fn, void* user) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (free_fn == nullptr)) fail(HGF_EINVAL, "alloc and free must both be set or both NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_hook.alloc = alloc;
+    g_hook.free = free_fn;
+    g_hook.user = user;
+    g_hook.generation = alloc ? ++g_hook_generation : 0;
+  });
+}
+
+hgf_status hgf_clear_error(hgf_operator op) {
   return guarded([&] {
     if (!op) fail(HGF_EINVAL, "operator is NULL");
+    op->error_state = 0;
+  });
+}
+
+hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, int32_t scheme, void* hip_stream) {
+  return guarded([&] {
+    if (!op) fail(HGF_EINVAL, "operator is NULL");
+    if (scheme != HGF_RK4) fail(HGF_EUNSUPPORTED, "only the classical RK4 scheme is implemented");
     if (op->error_state) fail(HGF_ESTATE, "operator is in an error state after a non-finite result");
     const int64_t m = check_steps(t_total_us, dt_us);
     hip_check(hipSetDevice(op->device), "hipSetDevice");

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhgf.so")
 
 HGF_FP64, HGF_MIXED = 0, 1
 HGF_MERGED, HGF_SPLIT = 0, 1
-HGF_OP_PRODUCT, HGF_OP_SPARSE = 0, 1
+HGF_OP_PRODUCT, HGF_OP_SPARSE, HGF_OP_DENSE = 0, 1, 2
 HGF_BASIS_NUMBER, HGF_BASIS_NORMAL = 0, 1
 HGF_PSI_FOCK, HGF_PSI_COHERENT, HGF_PSI_PRODUCT = 0, 1, 2
 
@@ -38,6 +38,8 @@ class HgfError(RuntimeError):
 
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
 _f64p = ctypes.POINTER(ctypes.c_double)
 
 
@@ -83,6 +85,12 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libhgf.so not found at {path}; build it with "
                            "`python -m paper_2203_05526_amd.build`")
+    # torch brings its own HIP runtime; load it first so that libhgf binds to
+    # the same one and torch's streams and allocator are valid for it
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.hgf_define_system.argtypes = [ctypes.POINTER(_SystemDesc), ctypes.POINTER(vp)]
@@ -92,7 +100,9 @@ def load_library(path: str = LIB_PATH):
     lib.hgf_map_operator.argtypes = [vp, ctypes.POINTER(_OperatorDesc), ctypes.POINTER(vp)]
     lib.hgf_destroy_operator.argtypes = [vp]
     lib.hgf_destroy_operator.restype = None
-    lib.hgf_evolve.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
+    lib.hgf_evolve.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
+    lib.hgf_clear_error.argtypes = [vp]
+    lib.hgf_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     lib.hgf_evolve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_expectation.argtypes = [vp, ctypes.POINTER(_StateDesc), _f64p, vp]
     lib.hgf_grad.argtypes = [vp, ctypes.POINTER(_OperatorDesc), ctypes.POINTER(_StateDesc),
@@ -197,11 +207,19 @@ _BASIS = {"number": HGF_BASIS_NUMBER, "normal": HGF_BASIS_NORMAL}
 
 
 def _operator_desc(system: System, factors=None, sparse=None, basis="number", precision="fp64",
-                   layout="merged", drop_tol=0.0):
+                   layout="merged", drop_tol=0.0, dense=None):
     keep = []
-    if (factors is None) == (sparse is None):
-        raise HgfError(-1, "give exactly one of factors= or sparse=")
-    if factors is not None:
+    if sum(x is not None for x in (factors, sparse, dense)) != 1:
+        raise HgfError(-1, "give exactly one of factors=, sparse= or dense=")
+    if dense is not None:
+        dim = int(np.prod(system.cutoff))
+        if np.shape(dense) != (dim, dim):
+            raise HgfError(-1, "dense operator shape does not match the truncated space")
+        vals = _cplx_flat(dense)
+        keep.append(vals)
+        d = _OperatorDesc(HGF_OP_DENSE, _BASIS[basis], vals.ctypes.data_as(_f64p), None, 0,
+                          _PREC[precision], _LAYOUT[layout], float(drop_tol))
+    elif factors is not None:
         if len(factors) != system.n_modes:
             raise HgfError(-1, "one factor per mode is needed")
         for f, nc in zip(factors, system.cutoff):
@@ -273,17 +291,69 @@ class Operator:
 
 
 def map_operator(system: System, factors=None, sparse=None, basis="number", precision="fp64",
-                 layout="merged", drop_tol=0.0) -> Operator:
+                 layout="merged", drop_tol=0.0, dense=None) -> Operator:
     """hgf_map_operator: ``factors`` is a list of per-mode (Nc, Nc) matrices of
-    a product operator; ``sparse`` is (k[T, N], l[T, N], values[T])."""
-    d, keep = _operator_desc(system, factors, sparse, basis, precision, layout, drop_tol)
+    a product operator; ``sparse`` is (k[T, N], l[T, N], values[T]); ``dense``
+    is a (D, D) matrix over the whole truncated space (D = prod Nc, last mode
+    fastest)."""
+    d, keep = _operator_desc(system, factors, sparse, basis, precision, layout, drop_tol, dense)
     h = ctypes.c_void_p()
     _check(_lib.hgf_map_operator(system.handle, ctypes.byref(d), ctypes.byref(h)))
     return Operator(h, system)
 
 
 def evolve(op: Operator, t_total: float, dt: float, stream=None) -> None:
-    _check(_lib.hgf_evolve(op.handle, float(t_total), float(dt), _stream(stream)))
+    _check(_lib.hgf_evolve(op.handle, float(t_total), float(dt), 0, _stream(stream)))  # HGF_RK4
+
+
+def clear_error(op: Operator) -> None:
+    """hgf_clear_error: leave the error state after HGF_ENONFINITE."""
+    _check(_lib.hgf_clear_error(op.handle))
+
+
+_hooks = None  # keeps the ctypes callbacks alive while registered
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device allocations through torch's caching
+    allocator (hgf_set_allocator), or back to hipMalloc.  Blocks allocated
+    while the hook is set return to torch when freed; at interpreter exit the
+    hook is removed first, so that later frees do not call back into a
+    finalising interpreter."""
+    global _hooks
+    import torch
+
+    if not enable:
+        _check(_lib.hgf_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        _hooks = None
+        return
+
+    def alloc(nbytes, device, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device),
+                                                      stream=torch.cuda.current_stream(int(device)))
+        except Exception:
+            return None
+
+    def free(ptr, device, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (_ALLOC_FN(alloc), _FREE_FN(free))
+    _check(_lib.hgf_set_allocator(hooks[0], hooks[1], None))
+    if _hooks is None:
+        import atexit
+        atexit.register(_drop_hooks)
+    _hooks = hooks
+
+
+def _drop_hooks() -> None:
+    global _hooks
+    if _hooks is not None and _lib is not None:
+        _lib.hgf_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
+        _hooks = None
 
 
 def evolve_batch(ops: Sequence[Operator], t_total, dt, stream=None) -> None:

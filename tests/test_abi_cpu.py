@@ -79,9 +79,20 @@ def test_null_arguments_are_rejected(hgf):
     out = ctypes.c_void_p()
     assert lib.hgf_define_system(None, ctypes.byref(out)) == -1
     assert b"NULL" in lib.hgf_last_error()
-    assert lib.hgf_evolve(None, 1.0, 0.1, None) == -1
+    assert lib.hgf_evolve(None, 1.0, 0.1, 0, None) == -1
+    assert lib.hgf_clear_error(None) == -1
     assert lib.hgf_num_params(None) == -1
     assert lib.hgf_get_tile_config(None, 0, None) == -1
     assert lib.hgf_set_tile_config(None, 0, None) == -1
     assert lib.hgf_autotune(None, 1, 1e-3, None, 0, None) == -1
     assert b"NULL" in lib.hgf_last_error()
+
+
+def test_allocator_hook_arguments(hgf):
+    """hgf_set_allocator takes both callbacks or neither (no device call is made)."""
+    from paper_2203_05526_amd import hgf as mod
+    lib = mod.load_library()
+    alloc = mod._ALLOC_FN(lambda n, d, u: None)
+    assert lib.hgf_set_allocator(alloc, mod._FREE_FN(), None) == -1
+    assert b"both" in lib.hgf_last_error()
+    assert lib.hgf_set_allocator(mod._ALLOC_FN(), mod._FREE_FN(), None) == 0

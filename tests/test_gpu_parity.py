@@ -114,6 +114,52 @@ def test_random_operator_all_sectors(hgf, cutoff, seed, precision, tol):
         10 * tol if precision == "mixed" else tol)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_dense_operator_input(hgf, precision, tol):
+    """HGF_OP_DENSE: a matrix over the whole truncated space maps to the same
+    functions as its sparse form and evolves like the oracle."""
+    cutoff = (3, 4, 2)
+    announce(f"dense operator {precision}")
+    s = synth.random_system(cutoff, 9, scale=3.0, n_th=0.2)
+    S = hgf.define_system(s)
+    M = _dense_random_operator(cutoff, 9)
+    M[np.abs(M) < 0.5] = 0.0
+    a = hgf.map_operator(S, dense=M, precision=precision)
+    b = hgf.map_operator(S, sparse=_sparse_from_dense(cutoff, M), precision=precision)
+    assert a.info()["n_functions"] == b.info()["n_functions"]
+    assert max_rel_err(gpu_grids(a), gpu_grids(b)) == 0.0
+    T, dt = 0.05, 1e-3
+    hgf.evolve(a, T, dt)
+    ref = oracle_number_grids(cutoff, oracle.evolve(s, oracle.sparse_sectors(cutoff, *_sparse_from_dense(cutoff, M)),
+                                                    T, dt))
+    assert max_rel_err(gpu_number_grids(a, cutoff), ref) < tol
+
+
+def test_torch_allocator_hook(hgf):
+    """Device buffers come from torch's caching allocator while the hook is
+    set; results equal the hipMalloc path; freed blocks return to torch."""
+    import torch
+    announce("torch allocator hook")
+    w = synth.three_mode_c1()
+    S = hgf.define_system(w.system)
+    ref = hgf.map_operator(S, factors=w.factors, precision="mixed")
+    hgf.evolve(ref, 0.02, w.dt)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    hgf.use_torch_allocator(True)
+    try:
+        op = hgf.map_operator(S, factors=w.factors, precision="mixed")
+        assert torch.cuda.memory_allocated() > before
+        hgf.evolve(op, 0.02, w.dt)
+        assert max_rel_err(gpu_grids(op), gpu_grids(ref)) == 0.0
+        assert hgf.expectation(op, w.states[0]) == hgf.expectation(ref, w.states[0])
+        del op
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == before
+    finally:
+        hgf.use_torch_allocator(False)
+
+
 def test_split_layout_matches_oracle(hgf):
     """The paper's separated form G = Gx Gy + R (Eqs. (9)-(10), (19)-(20)),
     one function per coefficient, against the oracle."""
@@ -290,6 +336,9 @@ def test_error_paths(hgf):
     s = synth.random_system((3,), 2)
     S = hgf.define_system(s)
     op = hgf.map_operator(S, factors=[np.eye(3)])
+    from paper_2203_05526_amd import hgf as mod
+    assert mod._lib.hgf_evolve(op.handle, 0.1, 0.01, 1, None) == -6  # only HGF_RK4
+    assert op.info()["steps_done"] == 0
     with pytest.raises(hgf.HgfError) as e:
         hgf.evolve(op, 0.15, 0.1)
     assert e.value.status == "HGF_EINVAL"
@@ -322,6 +371,11 @@ def test_nonfinite_detected_and_state_restored(hgf):
     with pytest.raises(hgf.HgfError) as e:
         hgf.evolve(op, 0.6, 0.6)
     assert e.value.status == "HGF_ESTATE"
+    hgf.clear_error(op)
+    assert op.info()["error_state"] == 0
+    hgf.evolve(op, 0.0, 0.6)
+    _, _, grid, _ = op.function(0)
+    assert grid[1] == big
 
 
 # ----------------------------------------------------------------- batching
