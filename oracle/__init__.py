@@ -53,7 +53,7 @@ def _load():
         build()
     lib = ctypes.CDLL(_LIB)
     ip, dp, vp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
-    sysargs = [ctypes.c_int, ip, dp, dp, dp, dp, dp, dp]
+    sysargs = [ctypes.c_int, ip, dp, dp, dp, dp, dp, dp, ctypes.c_int, dp]
     lib.oracle_rhs.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_int]
     lib.oracle_evolve.argtypes = sysargs + [ctypes.c_int, ip, vp, ctypes.c_long,
                                             ctypes.c_double, ctypes.c_int]
@@ -78,10 +78,13 @@ def _sysargs(system):
         keep.append(a)
         return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int if dt == np.int32 else ctypes.c_double))
 
+    secular = getattr(system, "dissipator", "lindblad") == "secular"
+    levels = getattr(system, "n_th_levels", None)
     args = [n, arr(system.cutoff, np.int32), arr(system.detuning, np.float64),
             arr(system.kerr, np.float64), arr(system.cross_kerr, np.float64),
             arr(system.gamma1, np.float64), arr(system.gamma_phi, np.float64),
-            arr(system.n_th, np.float64)]
+            arr(system.n_th, np.float64), 1 if secular else 0,
+            arr(levels, np.float64) if (secular and levels is not None) else None]
     return args, keep
 
 

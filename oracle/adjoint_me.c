@@ -27,6 +27,17 @@
  * together), which is why a sector can be evolved on its own; the full
  * operator is the set of all sectors.
  *
+ * Secular variant (the first-principles dissipator of Eq. (15), in the form
+ * of the supplement's derivation): the emission and absorption channels of
+ * mode j are replaced by one channel per transition n <-> n+1 of that mode,
+ *   down: |n><n+1|  at rate gamma1_j (n+1) (nbar_{j,n} + 1)
+ *   up:   |n+1><n|  at rate gamma1_j (n+1) nbar_{j,n}
+ * with nbar_{j,n} the bath occupation at the transition's frequency (given per
+ * transition, or n_th_j for every transition).  In the Heisenberg picture a
+ * jump maps A to L^+ A L, which is non-zero only where k_j = l_j (populations
+ * of mode j), and the anticommutator damps A[k,l] by half the total rate out of
+ * level k_j plus that out of level l_j.  Pure dephasing keeps its Lindblad form.
+ *
  * Parameter order for sensitivities: K[N], chi[i<j lexicographic], Delta[N],
  * gamma1[N], gamma_phi[N].
  */
@@ -40,6 +51,7 @@
 #endif
 
 #define OMAXN 16
+#define OMAXC 64
 
 typedef double complex cplx;
 
@@ -48,12 +60,24 @@ typedef struct {
   int nc[OMAXN];
   double det[OMAXN], kerr[OMAXN], chi[OMAXN * OMAXN];
   double g1[OMAXN], gphi[OMAXN], nth[OMAXN];
+  int secular;               /* 0: Lindblad channels a, a^+; 1: secular transitions */
+  double nlev[OMAXN][OMAXC]; /* secular: bath occupation of transition n <-> n+1 of mode j */
 } osys;
 
+/* diss: 0 Lindblad, 1 secular; nlev (secular, may be NULL): per mode j the
+ * nc[j] - 1 transition occupations, modes one after another. */
 static int load_sys(osys *s, int n, const int *nc, const double *det, const double *kerr,
-                    const double *chi, const double *g1, const double *gphi, const double *nth) {
-  if (n < 1 || n > OMAXN) return -1;
+                    const double *chi, const double *g1, const double *gphi, const double *nth,
+                    int diss, const double *nlev) {
+  if (n < 1 || n > OMAXN || (diss != 0 && diss != 1)) return -1;
   s->n = n;
+  s->secular = diss;
+  long off = 0;
+  for (int j = 0; j < n; ++j) {
+    if (nc[j] < 1 || nc[j] > OMAXC) return -1;
+    for (int t = 0; t + 1 < nc[j]; ++t) s->nlev[j][t] = nlev ? nlev[off + t] : nth[j];
+    off += nc[j] - 1;
+  }
   for (int j = 0; j < n; ++j) {
     if (nc[j] < 1) return -1;
     s->nc[j] = nc[j];
@@ -126,6 +150,29 @@ static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out) {
     for (int j = 0; j < n; ++j) {
       const int nc = s->nc[j];
       const int kj = k[j], lj = l[j];
+      if (s->secular) {
+        /* transitions t <-> t+1 of mode j: down |t><t+1|, up |t+1><t| */
+        const double *nb = s->nlev[j];
+        const double g = s->g1[j];
+        /* jumps: L^+ A L is non-zero only for k_j = l_j */
+        if (kj == lj) {
+          if (kj >= 1) /* down from kj: (|kj><kj-1|) A (|kj-1><kj|) picks A[k-e_j, l-e_j] */
+            r += g * kj * (nb[kj - 1] + 1.0) * A[f - stride[j]];
+          if (kj + 1 < nc) /* up from kj: picks A[k+e_j, l+e_j] */
+            r += g * (kj + 1) * nb[kj] * A[f + stride[j]];
+        }
+        /* anticommutators: total rate out of a level m of mode j */
+        double out_k = 0.0, out_l = 0.0;
+        if (kj >= 1) out_k += g * kj * (nb[kj - 1] + 1.0);
+        if (kj + 1 < nc) out_k += g * (kj + 1) * nb[kj];
+        if (lj >= 1) out_l += g * lj * (nb[lj - 1] + 1.0);
+        if (lj + 1 < nc) out_l += g * (lj + 1) * nb[lj];
+        r -= 0.5 * (out_k + out_l) * a;
+        /* pure dephasing as in the Lindblad form: L = n_j at rate 2 gamma_phi */
+        const double kap = 2.0 * s->gphi[j];
+        r += 0.5 * kap * (2.0 * (double)kj * (double)lj - (double)(kj * kj) - (double)(lj * lj)) * a;
+        continue;
+      }
       /* channel L = a_j: L^+ A L = a^+ A a; (a^+ a)[m,m] = m */
       {
         const double kap = s->g1[j] * (1.0 + s->nth[j]);
@@ -183,10 +230,10 @@ int oracle_max_threads(void) {
 }
 
 int oracle_rhs(int n, const int *nc, const double *det, const double *kerr, const double *chi,
-               const double *g1, const double *gphi, const double *nth, int nsec, const int *d,
-               const cplx *A, cplx *out, int nthreads) {
+               const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+               int nsec, const int *d, const cplx *A, cplx *out, int nthreads) {
   osys s;
-  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev)) return -1;
   set_threads(nthreads);
   rhs_all(&s, nsec, d, A, out);
   return 0;
@@ -198,10 +245,10 @@ int oracle_rhs(int n, const int *nc, const double *det, const double *kerr, cons
  *   A <- A + h/6 (k1 + 2 k2 + 2 k3 + k4).
  */
 int oracle_evolve(int n, const int *nc, const double *det, const double *kerr, const double *chi,
-                  const double *g1, const double *gphi, const double *nth, int nsec, const int *d,
-                  cplx *A, long nsteps, double h, int nthreads) {
+                  const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+                  int nsec, const int *d, cplx *A, long nsteps, double h, int nthreads) {
   osys s;
-  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev)) return -1;
   set_threads(nthreads);
   const long len = box_size(&s) * nsec;
   cplx *kk = malloc(sizeof(cplx) * len);
@@ -271,10 +318,10 @@ static void unit_system(const osys *s, int p, osys *u) {
  */
 int oracle_evolve_sens(int n, const int *nc, const double *det, const double *kerr,
                        const double *chi, const double *g1, const double *gphi, const double *nth,
-                       int nsec, const int *d, cplx *A, cplx *S, long nsteps, double h,
-                       int nthreads) {
+                       int diss, const double *nlev, int nsec, const int *d, cplx *A, cplx *S,
+                       long nsteps, double h, int nthreads) {
   osys s;
-  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth)) return -1;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev)) return -1;
   set_threads(nthreads);
   const int P = oracle_num_params(n);
   const long len = box_size(&s) * nsec;

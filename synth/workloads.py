@@ -40,6 +40,11 @@ class System:
     gamma1: np.ndarray
     gamma_phi: np.ndarray
     n_th: np.ndarray
+    # "lindblad" (emission/absorption channels a, a^+) or "secular" (one channel
+    # per transition n <-> n+1); n_th_levels (secular only, optional): the bath
+    # occupation of every transition, sum_j (cutoff_j - 1) values, modes in order
+    dissipator: str = "lindblad"
+    n_th_levels: Optional[np.ndarray] = None
 
     @property
     def n_modes(self) -> int:
@@ -48,7 +53,8 @@ class System:
     def copy(self) -> "System":
         return System(tuple(self.cutoff), self.detuning.copy(), self.kerr.copy(),
                       self.cross_kerr.copy(), self.gamma1.copy(),
-                      self.gamma_phi.copy(), self.n_th.copy())
+                      self.gamma_phi.copy(), self.n_th.copy(), self.dissipator,
+                      None if self.n_th_levels is None else self.n_th_levels.copy())
 
 
 @dataclass

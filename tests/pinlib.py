@@ -39,15 +39,36 @@ def hamiltonian(system) -> np.ndarray:
     return H
 
 
+def transition_occupations(system, j: int) -> np.ndarray:
+    """Bath occupation of every transition n <-> n+1 of mode j (secular form)."""
+    nc = system.cutoff[j]
+    lv = getattr(system, "n_th_levels", None)
+    if lv is None:
+        return np.full(nc - 1, system.n_th[j])
+    off = sum(c - 1 for c in system.cutoff[:j])
+    return np.asarray(lv[off:off + nc - 1], dtype=float)
+
+
 def jump_channels(system):
-    """(rate, L) for every channel of every mode."""
+    """(rate, L) for every channel of every mode: the Lindblad form (a, a^+,
+    n), or the secular form of Eq. (15) (one lowering and one raising jump per
+    transition n <-> n+1, plus dephasing n)."""
     cutoff = system.cutoff
     out = []
+    secular = getattr(system, "dissipator", "lindblad") == "secular"
     for j, nc in enumerate(cutoff):
         a = embed(ladder(nc), j, cutoff)
         n = a.conj().T @ a
-        out.append((system.gamma1[j] * (1 + system.n_th[j]), a))
-        out.append((system.gamma1[j] * system.n_th[j], a.conj().T))
+        if secular:
+            nbar = transition_occupations(system, j)
+            for t in range(nc - 1):
+                down = np.zeros((nc, nc), dtype=np.complex128)
+                down[t, t + 1] = 1.0  # |t><t+1|
+                out.append((system.gamma1[j] * (t + 1) * (nbar[t] + 1), embed(down, j, cutoff)))
+                out.append((system.gamma1[j] * (t + 1) * nbar[t], embed(down.T.copy(), j, cutoff)))
+        else:
+            out.append((system.gamma1[j] * (1 + system.n_th[j]), a))
+            out.append((system.gamma1[j] * system.n_th[j], a.conj().T))
         out.append((2 * system.gamma_phi[j], n))
     return out
 

@@ -242,10 +242,13 @@ def test_coefficient_maps(nc):
 
 # ------------------------------------------------------- sensitivities
 
-def test_sensitivities_match_finite_differences(oracle_lib):
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+def test_sensitivities_match_finite_differences(oracle_lib, dissipator):
     """Forward sensitivities of the discrete RK4 map against central finite
     differences of the oracle's own expectation value."""
     s = small_system(61, (3, 4), n_th=0.2)
+    if dissipator == "secular":
+        s = with_secular(s, np.random.default_rng(62))
     rng = np.random.default_rng(61)
     A0 = rng.normal(size=(12, 12)) + 1j * rng.normal(size=(12, 12))
     A0 = A0 + A0.conj().T
@@ -281,3 +284,92 @@ def test_sensitivities_match_finite_differences(oracle_lib):
         fd = (J(h) - J(-h)) / (2 * h)
         an = oracle.expectation(s.cutoff, sens[p], state)
         assert abs(an - fd) < 1e-7 * max(1.0, abs(fd)), (field, idx, an, fd)
+
+
+# ------------------------------------------------------- secular dissipator (Eq. (15))
+
+def with_secular(s, rng, constant=False):
+    """The same system with the secular dissipator; per-transition bath
+    occupations drawn at random (or n_th for every transition)."""
+    s2 = s.copy()
+    s2.dissipator = "secular"
+    if not constant:
+        s2.n_th_levels = rng.uniform(0.0, 0.5, size=sum(c - 1 for c in s.cutoff))
+    return s2
+
+
+@pytest.mark.parametrize("cutoff,seed", [((3, 3), 91), ((5,), 92), ((2, 3, 2), 93)])
+def test_secular_against_dense_superoperator_expm(oracle_lib, cutoff, seed):
+    """Secular form: the oracle's element-wise right-hand side integrated with
+    RK4 equals exp(S T) with S built from the paper's transition jump
+    operators |n><n+1|, |n+1><n| as Kronecker products."""
+    rng = np.random.default_rng(seed)
+    s = with_secular(small_system(seed, cutoff, n_th=0.2), rng)
+    dim = int(np.prod(cutoff))
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    ops = oracle.sectors_from_dense(cutoff, A0)
+    T, dt = 0.5, 1e-3
+    got = oracle.dense_from_sectors(cutoff, oracle.evolve(s, ops, T, dt))
+    ref = pinlib.expm_evolve(s, A0, T)
+    assert pinlib.rel(got, ref) < 1e-10
+
+
+def test_secular_equals_lindblad_on_the_diagonal_sector(oracle_lib):
+    """With one bath occupation for every transition the secular and Lindblad
+    forms agree on populations (the diagonal sector) and differ on coherences,
+    where the secular form has no jump terms."""
+    s = small_system(94, (4, 3), n_th=0.3)
+    sec = with_secular(s, None, constant=True)
+    rng = np.random.default_rng(94)
+    diag = {(0, 0): rng.normal(size=s.cutoff) + 1j * rng.normal(size=s.cutoff)}
+    assert pinlib.rel(oracle.rhs(sec, diag)[(0, 0)], oracle.rhs(s, diag)[(0, 0)]) < 1e-14
+    off = {(1, 0): rng.normal(size=s.cutoff) + 1j * rng.normal(size=s.cutoff)}
+    assert pinlib.rel(oracle.rhs(sec, off)[(1, 0)], oracle.rhs(s, off)[(1, 0)]) > 1e-3
+
+
+def test_secular_identity_and_thermal_state_are_stationary(oracle_lib):
+    """Secular form with level-dependent bath occupations: the identity is a
+    fixed point of the adjoint equation (trace preservation), and the state
+    with detailed-balance populations p_{n+1} / p_n = nbar_n / (nbar_n + 1)
+    per mode is stationary: <psi| L^+(A) |psi>-weights vanish for every A."""
+    rng = np.random.default_rng(95)
+    s = with_secular(small_system(95, (4, 5), n_th=0.2), rng)
+    ones = {(0, 0): np.ones(s.cutoff, dtype=np.complex128)}
+    assert np.max(np.abs(oracle.rhs(s, ones)[(0, 0)])) < 1e-13
+    # thermal populations, a product over modes
+    pops = []
+    for j, nc in enumerate(s.cutoff):
+        nb = pinlib.transition_occupations(s, j)
+        p = np.ones(nc)
+        for t in range(nc - 1):
+            p[t + 1] = p[t] * nb[t] / (nb[t] + 1.0)
+        pops.append(p / p.sum())
+    rho = np.einsum("i,j->ij", *pops)
+    dim = int(np.prod(s.cutoff))
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    dA = oracle.dense_from_sectors(s.cutoff, oracle.rhs(s, oracle.sectors_from_dense(s.cutoff, A0)))
+    rate = np.sum(rho.reshape(-1) * np.diag(dA))
+    assert abs(rate) < 1e-12 * np.max(np.abs(dA))
+    # a non-thermal population distribution is not stationary
+    assert abs(np.sum(np.ones(dim) / dim * np.diag(dA))) > 1e-6
+
+
+def test_secular_coherence_decays_without_feeding(oracle_lib):
+    """Zero-temperature secular form, one mode: a coherence |k><l| (k != l)
+    evolves into a multiple of itself, exp((i (E_k - E_l) - gamma1 (k + l) / 2
+    - gamma_phi (k - l)^2) t) in the continuous limit (the Lindblad form would
+    also feed |k+1><l+1|); checked against RK4's polynomial of that rate."""
+    s = synth.System((6,), np.array([0.7]), np.array([-2.0]), np.zeros((1, 1)), np.array([0.9]),
+                     np.array([0.3]), np.array([0.0]), "secular")
+    T, dt = 0.3, 1e-3
+    steps = oracle.n_steps(T, dt)
+    for k, l in ((3, 1), (0, 4), (5, 2)):
+        A = np.zeros((6, 6), dtype=np.complex128)
+        A[k, l] = 1.0
+        out = oracle.dense_from_sectors((6,), oracle.evolve(s, oracle.sectors_from_dense((6,), A), T, dt))
+        E = lambda m: 0.7 * m + 0.5 * (-2.0) * m * (m - 1)
+        lam = 1j * (E(k) - E(l)) - 0.9 * (k + l) / 2 - 0.3 * (k - l) ** 2
+        expect = pinlib.rk4_polynomial(lam * dt) ** steps
+        assert abs(out[k, l] - expect) < 1e-13
+        out[k, l] = 0.0
+        assert np.max(np.abs(out)) == 0.0
