@@ -100,17 +100,31 @@ typedef struct {
   const double* gamma1;     /* [N] 1/T1, 1/us, >= 0 */
   const double* gamma_phi;  /* [N] 1/Tphi, 1/us, >= 0 */
   const double* n_th;       /* [N] bath occupation, >= 0 */
+  int32_t dissipator;       /* HGF_DISS_LINDBLAD or HGF_DISS_SECULAR */
+  const double* n_th_levels; /* SECULAR only, may be NULL: bath occupation of every
+                                transition n <-> n+1, sum_j (Nc_j - 1) values, modes in
+                                order (NULL: n_th_j for every transition of mode j) */
 } hgf_system_desc;
+
+/* dissipators (per mode; dephasing is the Lindblad channel n at rate 2 gamma_phi in both) */
+enum {
+  HGF_DISS_LINDBLAD = 0, /* emission a at gamma1 (1 + n_th), absorption a^+ at gamma1 n_th (Eq. (3)) */
+  HGF_DISS_SECULAR = 1   /* first-principles form of Eq. (15): per transition n <-> n+1,
+                            lowering |n><n+1| at gamma1 (n+1)(nbar_n + 1) and raising |n+1><n|
+                            at gamma1 (n+1) nbar_n, nbar_n the bath occupation at the
+                            transition's frequency; jumps act on populations only */
+};
 
 #define HGF_MAX_MODES 16
 #define HGF_MAX_CUTOFF 32
 
 /*
  * Validate and copy a system description (the Hamiltonian of Eq. (1) and the
- * dissipators of Eq. (3), restricted as above).  Errors: HGF_EINVAL for a
- * NULL pointer, N or a cutoff out of range, a negative or non-finite rate,
- * or a non-symmetric cross_kerr.  *out is owned by the caller and freed by
- * hgf_destroy_system.
+ * dissipators of Eq. (3) or Eq. (15), restricted as above).  Errors:
+ * HGF_EINVAL for a NULL pointer, N or a cutoff out of range, a negative or
+ * non-finite rate or occupation, a non-symmetric cross_kerr, an unknown
+ * dissipator, or n_th_levels given with HGF_DISS_LINDBLAD.  *out is owned by
+ * the caller and freed by hgf_destroy_system.
  */
 hgf_status hgf_define_system(const hgf_system_desc* desc, hgf_system* out);
 void hgf_destroy_system(hgf_system sys);

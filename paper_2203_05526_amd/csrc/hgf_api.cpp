@@ -240,7 +240,7 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
     }
     if (threads < 64 || threads > 512 || threads % 64 != 0) continue;
     if ((T + threads - 1) / threads > kTileRounds) continue;
-    const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + esum * rs + 64;
+    const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + 2 * esum * rs + 64;
     if (bytes > 65536) continue;
     best = F;
     g.nfast = F;
@@ -319,7 +319,7 @@ static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) 
       lam += t.lam[j][sj];
       if (sj >= 1) {
         off[2 * j] = -(int32_t)g.stride[j];
-        coef[2 * j] = (R)t.alpha[j];
+        coef[2 * j] = (R)t.alpha[j][sj];
       }
       if (sj + 1 < t.ext[j]) {
         off[2 * j + 1] = (int32_t)g.stride[j];
@@ -358,16 +358,22 @@ static void build_tile_records(Function& f, int precision) {
 static bool resident_eligible(Function& f) {
   const GridArgs& g = f.ga;
   if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
-  if (g.tile_points > resident_max_points()) return false;
-  // two padded copies of the grid in LDS
-  const int es = (f.ga.real ? 1 : 2) * (f.precision_fp64 ? 8 : 4);
-  const int64_t lds = 2 * (int64_t)g.lds_elems * es;
+  const int max_threads = f.precision_fp64 ? 512 : 1024;  // the kernel's workgroup limit
+  if (g.tile_points > (int64_t)resident_max_points() * max_threads / 1024) return false;
+  // two padded copies of the grid and the down-jump tables in LDS
+  const int rs = f.precision_fp64 ? 8 : 4, es = (f.ga.real ? 1 : 2) * rs;
+  int esum = 0;
+  for (int j = 0; j < g.n; ++j) esum += g.ext[j];
+  if (g.n > 4) return false;
+  for (int j = 0; j < g.n; ++j)
+    if (g.ext[j] > 32) return false;  // 5-bit coordinates
+  const int64_t lds = 2 * (int64_t)g.lds_elems * es + (int64_t)esum * rs;
   if (lds > 65536) return false;
   f.res_lds_bytes = (int)lds;
   // lanes: enough for the fewest rounds, spread evenly over them
-  const int64_t rounds = (g.tile_points + 1023) / 1024;
+  const int64_t rounds = (g.tile_points + max_threads - 1) / max_threads;
   const int64_t per = (g.tile_points + rounds - 1) / rounds;
-  f.res_threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (per + 63) / 64 * 64));
+  f.res_threads = (int)std::min<int64_t>(max_threads, std::max<int64_t>(64, (per + 63) / 64 * 64));
   return true;
 }
 
@@ -391,40 +397,46 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   for (int j = 0; j < t.n; ++j) {
     g.off[j] = off;
     off += t.ext[j];
-    g.alpha[j] = t.alpha[j];
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
   if (!stage_kernel_generic()) configure_tiles(g, precision, want_real, TileChoice{});
   f.real = g.real != 0;
-  // device tables: lam (double2), beta (double), lam_f (float2), beta_f (float)
+  // device tables, one block: lam (double2), beta, alpha (double), lam_f
+  // (float2), beta_f, alpha_f (float), each concatenated over the axes
   const int tot = off;
-  std::vector<double> lam(2 * tot), beta(tot);
-  std::vector<float> lamf(2 * tot), betaf(tot);
+  std::vector<double> lam(2 * tot), beta(tot), alpha(tot);
+  std::vector<float> lamf(2 * tot), betaf(tot), alphaf(tot);
   for (int j = 0; j < t.n; ++j)
     for (int m = 0; m < t.ext[j]; ++m) {
       const int o = g.off[j] + m;
       lam[2 * o] = t.lam[j][m].real();
       lam[2 * o + 1] = t.lam[j][m].imag();
       beta[o] = t.beta[j][m];
+      alpha[o] = t.alpha[j][m];
       lamf[2 * o] = (float)lam[2 * o];
       lamf[2 * o + 1] = (float)lam[2 * o + 1];
       betaf[o] = (float)beta[o];
+      alphaf[o] = (float)alpha[o];
     }
-  const size_t b_lam = sizeof(double) * 2 * tot, b_beta = sizeof(double) * tot;
-  const size_t b_lamf = sizeof(float) * 2 * tot, b_betaf = sizeof(float) * tot;
-  const size_t total = b_lam + b_beta + b_lamf + b_betaf + 64;
+  const size_t b_lam = sizeof(double) * 2 * tot, b_d = sizeof(double) * tot;
+  const size_t b_lamf = sizeof(float) * 2 * tot, b_f = sizeof(float) * tot;
+  const size_t o_beta = b_lam, o_alpha = o_beta + b_d, o_lamf = o_alpha + b_d, o_betaf = o_lamf + b_lamf,
+               o_alphaf = o_betaf + b_f, total = o_alphaf + b_f + 64;
   f.dtab = dmalloc(total);
   char* base = (char*)f.dtab;
   hip_check(hipMemcpy(base, lam.data(), b_lam, hipMemcpyHostToDevice), "upload tables");
-  hip_check(hipMemcpy(base + b_lam, beta.data(), b_beta, hipMemcpyHostToDevice), "upload tables");
-  hip_check(hipMemcpy(base + b_lam + b_beta, lamf.data(), b_lamf, hipMemcpyHostToDevice), "upload tables");
-  hip_check(hipMemcpy(base + b_lam + b_beta + b_lamf, betaf.data(), b_betaf, hipMemcpyHostToDevice),
-            "upload tables");
+  hip_check(hipMemcpy(base + o_beta, beta.data(), b_d, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + o_alpha, alpha.data(), b_d, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + o_lamf, lamf.data(), b_lamf, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + o_betaf, betaf.data(), b_f, hipMemcpyHostToDevice), "upload tables");
+  hip_check(hipMemcpy(base + o_alphaf, alphaf.data(), b_f, hipMemcpyHostToDevice), "upload tables");
   g.lam = (const double2*)base;
-  g.beta = (const double*)(base + b_lam);
-  g.lam_f = (const float2*)(base + b_lam + b_beta);
-  g.beta_f = (const float*)(base + b_lam + b_beta + b_lamf);
+  g.beta = (const double*)(base + o_beta);
+  g.alpha = (const double*)(base + o_alpha);
+  g.lam_f = (const float2*)(base + o_lamf);
+  g.beta_f = (const float*)(base + o_betaf);
+  g.alpha_f = (const float*)(base + o_alphaf);
   g.tiles = nullptr;
   if (g.blocks > 0) build_tile_records(f, precision);
   f.resident = resident_eligible(f);
@@ -741,9 +753,10 @@ static void setup_split(Function& f, const System& s, const Coeff& c) {
   for (int j = 0; j < n; ++j) {
     int mm[kMaxModes];
     std::memcpy(mm, m, sizeof(int) * n);
-    if (m[j] + 1 < t.ext[j]) {  // (L delta)(m*+e_j) = alpha_j
+    if (m[j] + 1 < t.ext[j]) {  // (L delta)(m*+e_j) = alpha_j(m*_j + 1)
       mm[j] = m[j] + 1;
-      f.sources.push_back({flat_index(t, mm), cd(t.alpha[j], 0.0)});
+      const double a = t.alpha[j][m[j] + 1];
+      if (a != 0.0) f.sources.push_back({flat_index(t, mm), cd(a, 0.0)});
     }
     if (m[j] >= 1) {  // (L delta)(m*-e_j) = beta_j(m*_j - 1)
       mm[j] = m[j] - 1;
@@ -1037,6 +1050,16 @@ static hipGraphExec_t capture_steps(const StepPlan& plan, int* flag, int chunk, 
   return exec;
 }
 
+// Steps per captured graph: at most 64, and at most kMaxGraphNodes kernel
+// nodes (an operator whose many functions each take their own generic launch
+// would otherwise capture graphs of millions of nodes).  0: launch eagerly.
+constexpr int64_t kMaxGraphNodes = 16384;
+static int graph_chunk(const StepPlan& plan, int64_t steps) {
+  const int64_t per_step = 4 * (int64_t)(plan.groups.size() + plan.generic.size());
+  if (per_step == 0) return 0;
+  return (int)std::min<int64_t>({steps, 64, kMaxGraphNodes / per_step});
+}
+
 // One graph holds `chunk` merged steps of every function of the operator.
 static void ensure_graph(hgf_operator_s* op, double h, int chunk) {
   ensure_plan(op, h);
@@ -1112,16 +1135,17 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   if (op->layout == HGF_MERGED) {
     ensure_plan(op, h);
     run_resident(*op->plan, steps, op->dflag, st);
-    if (!op->plan->groups.empty() || !op->plan->generic.empty()) {
-      const int chunk = (int)std::min<int64_t>(steps, 64);
+    const int chunk = graph_chunk(*op->plan, steps);
+    int64_t done = 0;
+    if (chunk > 0) {
       ensure_graph(op, h, chunk);
-      int64_t done = 0;
       while (steps - done >= chunk) {
         hip_check(hipGraphLaunch((hipGraphExec_t)op->graph_exec, st), "graph launch");
         done += chunk;
       }
-      for (; done < steps; ++done) run_plan_step(*op->plan, op->dflag, st);
     }
+    if (!op->plan->groups.empty() || !op->plan->generic.empty())
+      for (; done < steps; ++done) run_plan_step(*op->plan, op->dflag, st);
   } else {
     for (int64_t s = 0; s < steps; ++s)
       for (auto& f : op->fn) split_step(op, f, h, st);
@@ -1184,22 +1208,19 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
     if (items.empty()) continue;
     std::unique_ptr<StepPlan> plan(build_plan(items));
     run_resident(*plan, nst, dflag.as<int>(), st);
-    if (!plan->groups.empty() || !plan->generic.empty()) {
-      const int chunk = (int)std::min<int64_t>(nst, 64);
-      hipGraphExec_t exec = capture_steps(*plan, dflag.as<int>(), chunk, cap);
-      struct ExecGuard {
-        hipGraphExec_t e;
-        ~ExecGuard() { (void)hipGraphExecDestroy(e); }
-      } eg{exec};
-      int64_t done = 0;
+    const int chunk = graph_chunk(*plan, nst);
+    int64_t done = 0;
+    if (chunk > 0) {
+      GraphHolder g(capture_steps(*plan, dflag.as<int>(), chunk, cap));
       while (nst - done >= chunk) {
-        hip_check(hipGraphLaunch(exec, st), "graph launch");
+        hip_check(hipGraphLaunch(g.e, st), "graph launch");
         done += chunk;
       }
-      for (; done < nst; ++done) run_plan_step(*plan, dflag.as<int>(), st);
-      // the graph and the plan's device buffers must outlive the launches
+      // the graph must outlive its launches
       hip_check(hipStreamSynchronize(st), "synchronize");
     }
+    if (!plan->groups.empty() || !plan->generic.empty())
+      for (; done < nst; ++done) run_plan_step(*plan, dflag.as<int>(), st);
     // the plan's device buffers must outlive the launches that read them
     hip_check(hipStreamSynchronize(st), "synchronize");
   }
@@ -1888,10 +1909,10 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
       const SectorTables tp = sector_tables(u, f.tab.d);
       cd g = tp.lam0 * S0;
       for (int j = 0; j < sys.n; ++j) {
-        g += tp.alpha[j] * bins[tot_e + j];
         for (int v = 0; v < f.ga.ext[j]; ++v) {
           g += tp.lam[j][v] * bins[f.ga.off[j] + v];
-          g += tp.beta[j][v] * bins[tot_e + sys.n + f.ga.off[j] + v];
+          g += tp.alpha[j][v] * bins[tot_e + f.ga.off[j] + v];
+          g += tp.beta[j][v] * bins[2 * tot_e + f.ga.off[j] + v];
         }
       }
       grad[p] += g;
@@ -1933,6 +1954,18 @@ static System system_from_desc(const hgf_system_desc* d) {
       if (i != j && a != b) fail(HGF_EINVAL, "cross_kerr must be symmetric");
       s.chi[i][j] = (i == j) ? 0.0 : a;
     }
+  if (d->dissipator != HGF_DISS_LINDBLAD && d->dissipator != HGF_DISS_SECULAR) fail(HGF_EINVAL, "unknown dissipator");
+  s.secular = d->dissipator == HGF_DISS_SECULAR ? 1 : 0;
+  if (!s.secular && d->n_th_levels) fail(HGF_EINVAL, "n_th_levels applies to the secular dissipator only");
+  size_t off = 0;
+  for (int j = 0; j < n; ++j) {
+    for (int t = 0; t + 1 < s.nc[j]; ++t) {
+      const double v = d->n_th_levels ? d->n_th_levels[off + t] : s.nth[j];
+      if (!std::isfinite(v) || v < 0) fail(HGF_EINVAL, "n_th_levels must be finite and >= 0");
+      s.nlev[j][t] = v;
+    }
+    off += s.nc[j] - 1;
+  }
   return s;
 }
 

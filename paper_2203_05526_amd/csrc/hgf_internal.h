@@ -36,13 +36,18 @@ struct System {
   double det[kMaxModes] = {}, kerr[kMaxModes] = {}, g1[kMaxModes] = {}, gphi[kMaxModes] = {},
          nth[kMaxModes] = {};
   double chi[kMaxModes][kMaxModes] = {};
+  // HGF_DISS_SECULAR: one emission and one absorption channel per transition
+  // n <-> n+1 of each mode, bath occupation nlev[j][n]
+  int secular = 0;
+  double nlev[kMaxModes][kMaxCutoff] = {};
 };
 
 // Coefficients of the generator restricted to one occupation-difference
 // sector d (Eq. (17) with the dissipators of Eq. (3); derivation in the
 // sector form): for grid point m,
 //   (L g)(m) = [lam0 + sum_j lam_j(m_j)] g(m)
-//            + sum_j [ alpha_j g(m - e_j) [m_j >= 1] + beta_j(m_j) g(m + e_j) [m_j + 1 < ext_j] ]
+//            + sum_j [ alpha_j(m_j) g(m - e_j) [m_j >= 1] + beta_j(m_j) g(m + e_j) [m_j + 1 < ext_j] ]
+// (alpha_j is the same at every level in the Lindblad form)
 struct SectorTables {
   int n = 0;
   int d[kMaxModes] = {};
@@ -50,8 +55,8 @@ struct SectorTables {
   int u[kMaxModes] = {}, v[kMaxModes] = {};  // k = m + u, l = m + v
   cd lam0;
   std::vector<cd> lam[kMaxModes];      // [ext_j]
-  std::vector<double> beta[kMaxModes]; // [ext_j]; zero at the top of the axis
-  double alpha[kMaxModes] = {};
+  std::vector<double> beta[kMaxModes];  // [ext_j]; zero at the top of the axis
+  std::vector<double> alpha[kMaxModes]; // [ext_j]; zero at m = 0
   int64_t points() const {
     int64_t p = 1;
     for (int j = 0; j < n; ++j) p *= ext[j];
@@ -75,7 +80,7 @@ struct GridArgs {
   int64_t points;
   int64_t tile_points;      // product of the fast extents
   int64_t ntiles;
-  int off[kMaxModes];       // start of axis j in the concatenated tables
+  int off[kMaxModes];       // start of axis j in the concatenated tables (lam, alpha, beta)
   // tiled stage kernel: the trailing `nfast` axes form one tile held in LDS
   // with a zero halo of one point on each side of every fast axis
   int pstride[4];           // padded LDS strides of the fast axes
@@ -91,11 +96,12 @@ struct GridArgs {
   int occ_max;              // resident workgroups per CU that fit (registers, LDS, waves)
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
   double lam0_re, lam0_im;
-  double alpha[kMaxModes];
   const double2* lam;       // concatenated lam_j(m)
   const double* beta;       // concatenated beta_j(m)
+  const double* alpha;      // concatenated alpha_j(m) (0 at m = 0)
   const float2* lam_f;
   const float* beta_f;
+  const float* alpha_f;
 };
 
 // Arguments of one member of a grouped (tiled) stage launch, kept in device

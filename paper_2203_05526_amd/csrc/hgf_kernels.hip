@@ -60,6 +60,12 @@ template <>
 __device__ __forceinline__ const double* beta_table<double>(const GridArgs& g) { return g.beta; }
 template <>
 __device__ __forceinline__ const float* beta_table<float>(const GridArgs& g) { return g.beta_f; }
+template <typename R>
+__device__ __forceinline__ const R* alpha_table(const GridArgs& g);
+template <>
+__device__ __forceinline__ const double* alpha_table<double>(const GridArgs& g) { return g.alpha; }
+template <>
+__device__ __forceinline__ const float* alpha_table<float>(const GridArgs& g) { return g.alpha_f; }
 
 // Mixed-radix bookkeeping for a grid-stride loop: each thread keeps the
 // coordinates of its current point and adds the digits of the loop stride.
@@ -103,6 +109,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
   using CT = typename C2<R>::T;
   const CT* lam = lam_table<R>(g);
   const R* beta = beta_table<R>(g);
+  const R* alpha = alpha_table<R>(g);
   R lr = (R)g.lam0_re, li = (R)g.lam0_im;
   CT acc;
   acc.x = 0;
@@ -118,7 +125,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
       // (beta is zero at the top of an axis), keeping the loads branch-free
       const CT dn = load_as<R>(in, m >= 1 ? w.i - g.stride[j] : w.i);
       const CT upv = load_as<R>(in, m + 1 < g.ext[j] ? w.i + g.stride[j] : w.i);
-      const R a = m >= 1 ? (R)g.alpha[j] : (R)0;
+      const R a = alpha[g.off[j] + m];  // zero at m = 0
       const R b = beta[g.off[j] + m];
       acc.x += a * dn.x + b * upv.x;
       acc.y += a * dn.y + b * upv.y;
@@ -143,12 +150,12 @@ __device__ __forceinline__ double2 apply_LT(const GridArgs& g, const TIN* __rest
       const double2 lj = g.lam[g.off[j] + m];
       lr += lj.x;
       li += lj.y;
-      // L[m+e, m] = alpha, L[m-e, m] = beta(m-1); out-of-range neighbours
-      // read the centre with a zero coefficient
+      // L[m+e, m] = alpha(m+1), L[m-e, m] = beta(m-1); out-of-range
+      // neighbours read the centre with a zero coefficient
       const bool uv = m + 1 < g.ext[j], dv = m >= 1;
       const double2 upv = to_d2(in[uv ? w.i + g.stride[j] : w.i]);
       const double2 dn = to_d2(in[dv ? w.i - g.stride[j] : w.i]);
-      const double a = uv ? g.alpha[j] : 0.0;
+      const double a = uv ? g.alpha[g.off[j] + m + 1] : 0.0;
       const double b = dv ? g.beta[g.off[j] + m - 1] : 0.0;
       acc.x += a * upv.x + b * dn.x;
       acc.y += a * upv.y + b * dn.y;
@@ -509,9 +516,8 @@ __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, 
   }
 }
 
-// Marginals of Q: bins[0 .. sum e) hold sum over m with m_j = v of Q0,
-// bins[sum e .. sum e + N) hold sum of Qd_j, bins[sum e + N ..) sum over
-// m_j = v of Qu_j.  One thread per bin walks its slice in a fixed order.
+// Marginals of Q: bins[0 .. E), [E .. 2E), [2E .. 3E) (E = sum_j e_j) hold, for
+// every axis j and value v, the sum over m with m_j = v of Q0, Qd_j and Qu_j.
 // One block per bin; the block's lanes sum fixed strided subsets of the bin's
 // points, then the block sum (a fixed order: reproducible).
 __global__ __launch_bounds__(kRedThreads) void k_marginals(GridArgs g, const double2* __restrict__ Q,
@@ -519,27 +525,15 @@ __global__ __launch_bounds__(kRedThreads) void k_marginals(GridArgs g, const dou
   int tot_e = 0;
   for (int j = 0; j < g.n; ++j) tot_e += g.ext[j];
   const int b = blockIdx.x;
-  int kind, axis = 0, val = 0;
-  if (b < tot_e) {
-    kind = 0;
-    int r = b;
-    while (r >= g.ext[axis]) r -= g.ext[axis++];
-    val = r;
-  } else if (b < tot_e + g.n) {
-    kind = 1;
-    axis = b - tot_e;
-  } else {
-    kind = 2;
-    int r = b - tot_e - g.n;
-    while (r >= g.ext[axis]) r -= g.ext[axis++];
-    val = r;
-  }
+  // bins: [Q0 by (axis, value)] [Qd_j by (j, value)] [Qu_j by (j, value)]
+  const int kind = b / tot_e;
+  int axis = 0, rem = b - kind * tot_e;
+  while (rem >= g.ext[axis]) rem -= g.ext[axis++];
+  const int val = rem;
   const double2* plane =
       Q + (kind == 0 ? 0 : kind == 1 ? (int64_t)(1 + axis) * g.points : (int64_t)(1 + g.n + axis) * g.points);
   double2 s = make_double2(0.0, 0.0);
-  if (kind == 1) {
-    for (int64_t i = threadIdx.x; i < g.points; i += blockDim.x) s = cadd(s, plane[i]);
-  } else {
+  {
     // the points whose coordinate `axis` equals val: (outer, val, inner)
     const int64_t st = g.stride[axis];
     const int64_t n = g.points / g.ext[axis];
@@ -763,7 +757,7 @@ void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, 
 int marginal_bins(const GridArgs& g) {
   int tot = 0;
   for (int j = 0; j < g.n; ++j) tot += g.ext[j];
-  return 2 * tot + g.n;
+  return 3 * tot;
 }
 
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st) {

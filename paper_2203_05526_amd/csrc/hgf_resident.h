@@ -23,12 +23,18 @@
 namespace hgf {
 
 // Lane rounds per workgroup of the resident kernel: a grid of at most
-// kResidentRounds * 1024 points.
+// kResidentRounds * (1024 lanes, 512 in FP64) points.
 constexpr int kResidentRounds = 4;
 
+// Workgroup size limit: FP64 grids need more registers per lane.
+template <typename TS>
+struct ResidentThreads {
+  static constexpr int value = sizeof(typename Real<TS>::T) == 8 ? 512 : 1024;
+};
+
 template <int NF, typename TS, typename TY>
-__global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __restrict__ items,
-                                                       int* __restrict__ flag) {
+__global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(const ResidentItem* __restrict__ items,
+                                                                             int* __restrict__ flag) {
   using R = typename Real<TS>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   const ResidentItem* __restrict__ it = items + blockIdx.x;
@@ -46,18 +52,32 @@ __global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __res
   TS* const buf0 = (TS*)smem;
   TS* const buf1 = buf0 + E;
   for (int i = tid; i < 2 * E; i += nt) buf0[i] = mk_<TS>(0, 0);
+  // down-jump coefficients alpha_q(c) of every axis, after the two copies
+  R* const atab = (R*)(buf1 + E);
+  int aoff[NF];
+  {
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+      aoff[q] = o;
+      for (int c = tid; c < it->g.ext[q]; c += nt) atab[o + c] = (R)it->g.alpha[it->g.off[q] + c];
+      o += it->g.ext[q];
+    }
+  }
 
-  // ---- per-point constants in registers: LDS slot, diagonal coefficient,
-  // up-jump coefficient per axis.  Lanes past the grid's end (last round)
+  // ---- per-point constants in registers: LDS slot, coordinates, diagonal
+  // coefficient, up-jump coefficient per axis.  Lanes past the grid's end (last round)
   // work on a copy of the last point and store nothing.
   const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
   int slot[kResidentRounds];
+  uint32_t cpk[kResidentRounds];  // the point's coordinates, 5 bits per axis
   R lrr[kResidentRounds], lir[kResidentRounds], bqr[kResidentRounds][NF];
 #pragma unroll
   for (int r = 0; r < kResidentRounds; ++r) {
     if (r < rounds) {
       int rem = min(tid + r * nt, T - 1);
       int off = 0;
+      uint32_t cp = 0;
       double lr = 0.0, li = 0.0;
 #pragma unroll
       for (int q = NF - 1; q >= 0; --q) {
@@ -69,17 +89,16 @@ __global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __res
         lr += lj.x;
         li += lj.y;
         bqr[r][q] = (R)it->g.beta[it->g.off[q] + c];
+        cp |= (uint32_t)c << (5 * q);
       }
       slot[r] = off;
+      cpk[r] = cp;
       // the same rounding as the tiled kernel: per-point sum in FP64, then the
       // stage type, then the constant part added in the stage type
       lrr[r] = lr0 + (R)lr;
       lir[r] = li0 + (R)li;
     }
   }
-  R aq[NF];
-#pragma unroll
-  for (int q = 0; q < NF; ++q) aq[q] = (R)it->g.alpha[q];
   __syncthreads();  // halo zeroed before the interior is written
 
   // ---- state into registers, stage-1 stencil input (y in the stage
@@ -116,8 +135,9 @@ __global__ __launch_bounds__(1024) void k_rk4_resident(const ResidentItem* __res
           for (int q = 0; q < NF; ++q) {
             const TS dn = cur[lo_ - it->g.pstride[q]];
             const TS upv = cur[lo_ + it->g.pstride[q]];
-            ar += aq[q] * re_(dn) + bqr[r][q] * re_(upv);
-            ai += aq[q] * im_(dn) + bqr[r][q] * im_(upv);
+            const R aq = atab[aoff[q] + (int)((cpk[r] >> (5 * q)) & 31u)];
+            ar += aq * re_(dn) + bqr[r][q] * re_(upv);
+            ai += aq * im_(dn) + bqr[r][q] * im_(upv);
           }
           if (stage == 1) {
             xr[r] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));

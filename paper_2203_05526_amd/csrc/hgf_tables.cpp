@@ -22,6 +22,16 @@
 //              - gamma1_j (1+n_th_j)(k+l)/2 - gamma1_j n_th_j (kt+lt)/2
 //   lam0     = -i sum_j [Delta_j d_j + (K_j/2) d_j (|d_j| - 1)]
 //              + i sum_{i<j} chi_ij (u_i u_j - v_i v_j) - sum_j gamma_phi_j d_j^2
+// Secular form (Eq. (15) with the transition occupations of the supplement's
+// derivation, per mode): with out(n) = gamma1 [n (nbar_{n-1} + 1) + (n+1) nbar_n]
+// the total rate out of level n (terms beyond the cutoff dropped),
+//   lam_j(m) = -i m (...) - (out(k) + out(l)) / 2
+//   alpha_j(m) = gamma1 (nbar_{m-1} + 1),  beta_j(m) = gamma1 nbar_m (m+1)^2   if d_j = 0
+//   alpha_j = beta_j = 0                                                        if d_j != 0
+// (jumps of mode j only act on its populations; in coefficients g the
+// population jump A[m-1,m-1] -> A[m,m] at rate gamma1 m (nbar_{m-1}+1) becomes
+// gamma1 (nbar_{m-1}+1) g(m-1), since g(m) = A[m,m] / m!).  With one nbar for
+// every transition these reduce to the Lindblad values on d_j = 0.
 #include <cmath>
 #include <cstring>
 
@@ -51,17 +61,36 @@ SectorTables sector_tables(const System& s, const int* d) {
     double phase = s.kerr[j] * d[j];
     for (int i = 0; i < s.n; ++i)
       if (i != j) phase += s.chi[i][j] * d[i];
-    const double down = s.g1[j] * (1.0 + s.nth[j]);
-    const double up = s.g1[j] * s.nth[j];
     const int nc = s.nc[j];
-    t.alpha[j] = down;
     t.lam[j].resize(t.ext[j]);
     t.beta[j].resize(t.ext[j]);
-    for (int m = 0; m < t.ext[j]; ++m) {
-      const int k = m + t.u[j], l = m + t.v[j];
-      const double kt = (k + 1 < nc) ? k + 1 : 0, lt = (l + 1 < nc) ? l + 1 : 0;
-      t.lam[j][m] = -I * (double(m) * phase) - 0.5 * down * (k + l) - 0.5 * up * (kt + lt);
-      t.beta[j][m] = (m + 1 < t.ext[j]) ? up * double(k + 1) * double(l + 1) : 0.0;
+    t.alpha[j].resize(t.ext[j]);
+    if (!s.secular) {
+      const double down = s.g1[j] * (1.0 + s.nth[j]);
+      const double up = s.g1[j] * s.nth[j];
+      for (int m = 0; m < t.ext[j]; ++m) {
+        const int k = m + t.u[j], l = m + t.v[j];
+        const double kt = (k + 1 < nc) ? k + 1 : 0, lt = (l + 1 < nc) ? l + 1 : 0;
+        t.lam[j][m] = -I * (double(m) * phase) - 0.5 * down * (k + l) - 0.5 * up * (kt + lt);
+        t.beta[j][m] = (m + 1 < t.ext[j]) ? up * double(k + 1) * double(l + 1) : 0.0;
+        t.alpha[j][m] = (m >= 1) ? down : 0.0;
+      }
+    } else {
+      const double* nb = s.nlev[j];
+      const double g = s.g1[j];
+      auto out = [&](int n) {
+        double r = 0.0;
+        if (n >= 1) r += g * n * (nb[n - 1] + 1.0);
+        if (n + 1 < nc) r += g * (n + 1) * nb[n];
+        return r;
+      };
+      for (int m = 0; m < t.ext[j]; ++m) {
+        const int k = m + t.u[j], l = m + t.v[j];
+        t.lam[j][m] = -I * (double(m) * phase) - 0.5 * (out(k) + out(l));
+        const bool pop = d[j] == 0;
+        t.beta[j][m] = (pop && m + 1 < t.ext[j]) ? g * nb[m] * double(m + 1) * double(m + 1) : 0.0;
+        t.alpha[j][m] = (pop && m >= 1) ? g * (nb[m - 1] + 1.0) : 0.0;
+      }
     }
   }
   return t;
@@ -108,7 +137,7 @@ double generator_bound(const SectorTables& t) {
   for (int j = 0; j < t.n; ++j) {
     double mx = 0.0;
     for (int m = 0; m < t.ext[j]; ++m) {
-      double v = std::abs(t.lam[j][m]) + t.beta[j][m] + (m >= 1 ? t.alpha[j] : 0.0);
+      double v = std::abs(t.lam[j][m]) + t.beta[j][m] + t.alpha[j][m];
       if (v > mx) mx = v;
     }
     b += mx;

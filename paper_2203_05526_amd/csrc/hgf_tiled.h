@@ -199,6 +199,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   R* btab = (R*)(info + ((T + 1) & ~1));
   const double2* lamt = g.lam;
   const double* betat = g.beta;
+  const double* alphat = g.alpha;
 
   // ---- once per workgroup: zero halo, per-position tables.  LDS layout of
   // the tile: fast coordinate c_q sits at c_q + 1 with stride pstride[q]; the
@@ -225,14 +226,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
     info[p] = off | (coords << 16);
     lamf[p] = mk_<TS>((R)lr, (R)li);
   }
+  // per-axis coefficient tables of the fast axes: btab (beta_j(c)) and, after
+  // it, atab (alpha_j(c))
   int boff[NF];
+  int esum = 0;
+#pragma unroll
+  for (int q = 0; q < NF; ++q) esum += g.ext[NS + q];
+  R* atab = btab + esum;
   {
     int o = 0;
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
       boff[q] = o;
       const int j = NS + q;
-      for (int c = tid; c < g.ext[j]; c += nt) btab[o + c] = (R)betat[g.off[j] + c];
+      for (int c = tid; c < g.ext[j]; c += nt) {
+        btab[o + c] = (R)betat[g.off[j] + c];
+        atab[o + c] = (R)alphat[g.off[j] + c];
+      }
       o += g.ext[j];
     }
   }
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
           const TS upv = tile[lo_ + g.pstride[q]];
           const int c = (int)((inf >> (16 + g.cbits * q)) & cmask);
           const R bq = btab[boff[q] + c];
-          const R aq = (R)g.alpha[NS + q];
+          const R aq = atab[boff[q] + c];
           ar += aq * re_(dn) + bq * re_(upv);
           ai += aq * im_(dn) + bq * im_(upv);
         }
@@ -469,12 +479,19 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       info[p] = off | (coords << 16);
       lamf[p] = mk_<TS>((R)lr, (R)li);
     }
+    int esum = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) esum += mp->g.ext[NS + q];
+    R* const atab = btab + esum;
     {
       int o = 0;
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
         const int j = NS + q;
-        for (int c = tid; c < mp->g.ext[j]; c += nt) btab[o + c] = (R)mp->g.beta[mp->g.off[j] + c];
+        for (int c = tid; c < mp->g.ext[j]; c += nt) {
+          btab[o + c] = (R)mp->g.beta[mp->g.off[j] + c];
+          atab[o + c] = (R)mp->g.alpha[mp->g.off[j] + c];
+        }
         o += mp->g.ext[j];
       }
     }
@@ -547,7 +564,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
           const TS upv = tile[lo_ + ps];
           const int c = (int)((inf >> (16 + cbits * q)) & cmask);
           const R bq = btab[bo + c];
-          const R aq = (R)mp->g.alpha[NS + q];
+          const R aq = atab[bo + c];
           ar += aq * re_(dn) + bq * re_(upv);
           ai += aq * im_(dn) + bq * im_(upv);
           bo += mp->g.ext[NS + q];

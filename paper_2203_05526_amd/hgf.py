@@ -45,7 +45,12 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 
 class _SystemDesc(ctypes.Structure):
     _fields_ = [("n_modes", ctypes.c_int32), ("cutoff", _i32p), ("detuning", _f64p), ("kerr", _f64p),
-                ("cross_kerr", _f64p), ("gamma1", _f64p), ("gamma_phi", _f64p), ("n_th", _f64p)]
+                ("cross_kerr", _f64p), ("gamma1", _f64p), ("gamma_phi", _f64p), ("n_th", _f64p),
+                ("dissipator", ctypes.c_int32), ("n_th_levels", _f64p)]
+
+
+HGF_DISS_LINDBLAD, HGF_DISS_SECULAR = 0, 1
+_DISS = {"lindblad": HGF_DISS_LINDBLAD, "secular": HGF_DISS_SECULAR}
 
 
 class _OperatorDesc(ctypes.Structure):
@@ -164,7 +169,8 @@ def _cplx_flat(x) -> np.ndarray:
 class System:
     """A handle on hgf_system (copy of the parameters, validated)."""
 
-    def __init__(self, cutoff, detuning, kerr, cross_kerr, gamma1, gamma_phi, n_th):
+    def __init__(self, cutoff, detuning, kerr, cross_kerr, gamma1, gamma_phi, n_th, dissipator="lindblad",
+                 n_th_levels=None):
         lib = load_library()
         n = len(cutoff)
         self.n_modes = n
@@ -174,7 +180,14 @@ class System:
         for a, ln in zip(self._arrays, (n, n, n, n * n, n, n, n)):
             if a.size != ln:
                 raise HgfError(-1, "system array has the wrong length")
-        d = _SystemDesc(n, *(a.ctypes.data_as(_i32p if i == 0 else _f64p) for i, a in enumerate(self._arrays)))
+        levels = None
+        if n_th_levels is not None:
+            levels = _f64(n_th_levels)
+            if levels.size != sum(c - 1 for c in self.cutoff):
+                raise HgfError(-1, "n_th_levels needs sum(cutoff - 1) values")
+            self._arrays.append(levels)
+        d = _SystemDesc(n, *(a.ctypes.data_as(_i32p if i == 0 else _f64p) for i, a in enumerate(self._arrays[:7])),
+                        _DISS[dissipator], levels.ctypes.data_as(_f64p) if levels is not None else None)
         h = ctypes.c_void_p()
         _check(lib.hgf_define_system(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -196,7 +209,8 @@ def define_system(system) -> System:
     """hgf_define_system from an object with cutoff, detuning, kerr,
     cross_kerr, gamma1, gamma_phi and n_th (e.g. ``synth.System``)."""
     return System(system.cutoff, system.detuning, system.kerr, system.cross_kerr, system.gamma1,
-                  system.gamma_phi, system.n_th)
+                  system.gamma_phi, system.n_th, getattr(system, "dissipator", "lindblad"),
+                  getattr(system, "n_th_levels", None))
 
 
 # ------------------------------------------------------------------ operators
@@ -401,9 +415,9 @@ def expectation(op: Operator, state, stream=None) -> complex:
 
 
 def grad(system: System, state, t_total: float, dt: float, factors=None, sparse=None, basis="number",
-         checkpoint_every: int = 100, stream=None) -> Tuple[complex, np.ndarray]:
+         checkpoint_every: int = 100, stream=None, dense=None) -> Tuple[complex, np.ndarray]:
     """hgf_grad: (J, dJ/dtheta) with theta = K[N], chi[i<j], Delta[N], gamma1[N], gamma_phi[N]."""
-    od, keep = _operator_desc(system, factors, sparse, basis, "fp64", "merged", 0.0)
+    od, keep = _operator_desc(system, factors, sparse, basis, "fp64", "merged", 0.0, dense)
     sd, keep2 = _state_desc(system, state)
     P = system.num_params()
     val = np.zeros(2)

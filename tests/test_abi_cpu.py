@@ -96,3 +96,16 @@ def test_allocator_hook_arguments(hgf):
     assert lib.hgf_set_allocator(alloc, mod._FREE_FN(), None) == -1
     assert b"both" in lib.hgf_last_error()
     assert lib.hgf_set_allocator(mod._ALLOC_FN(), mod._FREE_FN(), None) == 0
+
+
+def test_dissipator_validation(hgf):
+    """Secular dissipator options are validated when the system is defined."""
+    args = ((3, 2), [0.0, 0.0], [0.0, 0.0], [0.0] * 4, [0.1, 0.1], [0.1, 0.1], [0.0, 0.0])
+    hgf.System(*args, dissipator="secular")
+    hgf.System(*args, dissipator="secular", n_th_levels=[0.1, 0.2, 0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, dissipator="lindblad", n_th_levels=[0.1, 0.2, 0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, dissipator="secular", n_th_levels=[0.1, -0.2, 0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, dissipator="secular", n_th_levels=[0.1, 0.2])
