@@ -74,9 +74,9 @@ def stored_traffic(shape: dict):
         t = json.load(fh)
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
-    want = [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")]
+    want = [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu", "walk_block")]
     for entry in t.get("shapes", []):
-        if [int(x) for x in entry["tune_cache_line"].split()[1:6]] == want:
+        if [int(x) for x in entry["tune_cache_line"].split()[1:7]] == want:
             return entry["traffic_bytes_per_launch"]
     return None
 

@@ -264,6 +264,10 @@ typedef struct {
                           chip through all the steps of a call (state in registers, stage
                           grids in LDS); 0 = one launch per RK4 stage.  Set by default
                           where the grid allows it */
+  int32_t walk_block;  /* order in which the persistent grid walks the tiles: 0 = row-major
+                          over the slow axes; B >= 2 = blocks of B along every slow axis,
+                          row-major inside a block and across blocks (neighbour tiles along
+                          every slow axis are then visited close together in time) */
   int32_t blocks;      /* out: persistent workgroups per launch */
   int32_t tile_points; /* out: points per tile */
   double stage_us;     /* out: stage time measured by hgf_autotune for this shape, else 0 */
@@ -274,7 +278,7 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
 
 /*
  * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe,
- * wgs_per_cu, resident).
+ * wgs_per_cu, resident, walk_block).
  * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
  * register budget), asks a real grid for the untiled kernel, or asks for the
  * resident form where the grid is not a single tile of at most 4096 points;

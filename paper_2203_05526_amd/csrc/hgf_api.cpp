@@ -195,6 +195,7 @@ struct TileChoice {
   int xblock = -1;
   int pipe = -1;
   int wgs_per_cu = 0;  // resident workgroups per CU in the persistent grid (0: as many as fit)
+  int wblock = -1;     // tile walk order (-1, 0: row-major; B >= 2: blocks of B per slow axis)
 };
 
 // Pipelined neighbour loads keep the register budget only up to this many
@@ -265,6 +266,8 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
     return false;
   }
   g.xblock = std::max(0, c.xblock);
+  g.wblock = c.wblock >= 2 ? c.wblock : 0;
+  g.walk = nullptr;
   g.pipe = c.pipe > 0 ? 1 : 0;
   if (g.pipe && g.n - g.nfast > kPipeMaxSlow) {
     g.blocks = 0;
@@ -335,22 +338,68 @@ static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) 
   return out;
 }
 
-// Device copy of the tile records of grid g (caller owns the buffer).
-static void* upload_tile_records(const GridArgs& g, const SectorTables& t, int precision) {
+// Walk order of the tiles for g.wblock = B >= 2: the slow-axis coordinate
+// space is cut into blocks of B along every slow axis (smaller at the ends);
+// blocks are visited in row-major order, and the tiles of a block in row-major
+// order.  A row-major walk visits the neighbours along the slowest axes
+// prod(other slow extents) tiles apart, further than L2 holds; inside a block
+// every neighbour is at most B^(NS-1) tiles away and only the tiles on a
+// block face have neighbours outside it.
+static std::vector<uint32_t> walk_order(const GridArgs& g) {
+  const int ns = g.n - g.nfast, B = g.wblock;
+  std::vector<uint32_t> order;
+  int nb[kMaxModes], ob[kMaxModes], ib[kMaxModes], be[kMaxModes];
+  int64_t nblocks = 1, nunits = 1;
+  for (int j = 0; j < ns; ++j) {
+    nb[j] = (g.ext[j] + B - 1) / B;
+    nblocks *= nb[j];
+    nunits *= g.ext[j];
+  }
+  order.reserve((size_t)nunits);
+  for (int64_t o = 0; o < nblocks; ++o) {
+    int64_t rem = o, inner = 1;
+    for (int j = ns - 1; j >= 0; --j) {
+      ob[j] = (int)(rem % nb[j]);
+      rem /= nb[j];
+      be[j] = std::min(B, g.ext[j] - ob[j] * B);
+      inner *= be[j];
+    }
+    for (int64_t i = 0; i < inner; ++i) {
+      int64_t r = i;
+      for (int j = ns - 1; j >= 0; --j) {
+        ib[j] = (int)(r % be[j]);
+        r /= be[j];
+      }
+      int64_t t = 0;
+      for (int j = 0; j < ns; ++j) t = t * g.ext[j] + ob[j] * B + ib[j];
+      order.push_back((uint32_t)t);
+    }
+  }
+  return order;
+}
+
+// Device copy of the tile records of grid g, followed by its walk order when
+// g.wblock >= 2; sets g.tiles and g.walk (the caller owns the buffer).
+static void* upload_tile_records(GridArgs& g, const SectorTables& t, int precision) {
   std::vector<char> rec = precision == HGF_FP64 ? tile_records<double>(g, t) : tile_records<float>(g, t);
-  void* d = dmalloc(rec.size());
-  hipError_t e = hipMemcpy(d, rec.data(), rec.size(), hipMemcpyHostToDevice);
+  const size_t rec_bytes = (rec.size() + 255) / 256 * 256;
+  std::vector<uint32_t> order;
+  if (g.wblock >= 2 && g.n - g.nfast >= 1) order = walk_order(g);
+  const size_t bytes = rec_bytes + order.size() * sizeof(uint32_t);
+  rec.resize(bytes, 0);
+  if (!order.empty()) std::memcpy(rec.data() + rec_bytes, order.data(), order.size() * sizeof(uint32_t));
+  void* d = dmalloc(bytes);
+  hipError_t e = hipMemcpy(d, rec.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     dfree(d);
     hip_check(e, "upload tile records");
   }
+  g.tiles = d;
+  g.walk = order.empty() ? nullptr : (const uint32_t*)((const char*)d + rec_bytes);
   return d;
 }
 
-static void build_tile_records(Function& f, int precision) {
-  f.ttab = upload_tile_records(f.ga, f.tab, precision);
-  f.ga.tiles = f.ttab;
-}
+static void build_tile_records(Function& f, int precision) { f.ttab = upload_tile_records(f.ga, f.tab, precision); }
 
 // A function runs on the resident kernel when its tiled configuration is a
 // single tile holding every axis (then one workgroup does a stage's work in any
@@ -1251,7 +1300,7 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
 // The tiled stage kernel's launch shape (fast axes, workgroup size, XCD tile
 // order, pipelined loads) is chosen per grid shape by timing candidate shapes
 // on the function's own buffers.  Results are kept in a text cache, one line
-// per shape: "<key> <nfast> <threads> <xblock> <pipe> <wgs_per_cu> <stage_us>", the key
+// per shape: "<key> <nfast> <threads> <xblock> <pipe> <wgs_per_cu> <walk_block> <stage_us>", the key
 // naming the device (architecture, CU count), precision, real or complex grid
 // and the extents.
 
@@ -1276,11 +1325,11 @@ static void retile(Function& f, int precision, const TileChoice& c) {
     fail(HGF_EINVAL, "tile configuration not feasible for this grid");
   }
   g.tiles = nullptr;
+  g.walk = nullptr;
   void* rec = g.blocks > 0 ? upload_tile_records(g, f.tab, precision) : nullptr;
   dfree(f.ttab);
   f.ttab = rec;
   f.ga = g;
-  f.ga.tiles = rec;
   f.tuned_us = 0.0;
 }
 
@@ -1315,7 +1364,8 @@ static std::map<std::string, TuneEntry> read_tune_cache(const char* path) {
     std::istringstream ls(line);
     std::string key;
     TuneEntry e;
-    if (ls >> key >> e.c.nfast >> e.c.threads >> e.c.xblock >> e.c.pipe >> e.c.wgs_per_cu >> e.us) m[key] = e;
+    if (ls >> key >> e.c.nfast >> e.c.threads >> e.c.xblock >> e.c.pipe >> e.c.wgs_per_cu >> e.c.wblock >> e.us)
+      m[key] = e;
   }
   return m;
 }
@@ -1329,7 +1379,8 @@ static void write_tune_cache(const char* path, const std::map<std::string, TuneE
     out.precision(6);
     for (auto& kv : m)
       out << kv.first << ' ' << kv.second.c.nfast << ' ' << kv.second.c.threads << ' ' << kv.second.c.xblock << ' '
-          << kv.second.c.pipe << ' ' << kv.second.c.wgs_per_cu << ' ' << kv.second.us << '\n';
+          << kv.second.c.pipe << ' ' << kv.second.c.wgs_per_cu << ' ' << std::max(0, kv.second.c.wblock) << ' '
+          << kv.second.us << '\n';
     if (!out) fail(HGF_EINVAL, std::string("cannot write tuning cache ") + path);
   }
   if (std::rename(tmp.c_str(), path) != 0) fail(HGF_EINVAL, std::string("cannot replace tuning cache ") + path);
@@ -1431,6 +1482,7 @@ static TileChoice current_choice(const Function& f) {
   c.xblock = f.ga.xblock;
   c.pipe = f.ga.pipe;
   c.wgs_per_cu = f.ga.occ_cap;
+  c.wblock = f.ga.wblock;
   return c;
 }
 
@@ -1613,15 +1665,47 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
       TuneEntry best;
       best.us = 1e300;
       try {
-        // enough steps for ~1 ms of timed work per candidate
+        // enough steps for ~3 ms of timed work per candidate (at least 4:
+        // shorter runs left run-to-run noise above the 1 % tie margin)
         const double t0 = time_function_steps(f, op->precision, h, dflag.as<int>(), 1, st);
-        const int steps = (int)std::max(2.0, std::min(100.0, 1000.0 / std::max(1e-3, 4.0 * t0)));
+        const int steps = (int)std::max(4.0, std::min(100.0, 3000.0 / std::max(1e-3, 4.0 * t0)));
         std::vector<double> times;
         for (const TileChoice& c : cands) {
           retile(f, op->precision, c);
           times.push_back(time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st));
         }
         best = pick_shape(cands, times);
+        // then the walk order, on the chosen shape with the resident
+        // workgroups per CU it had and with one more and one fewer (a blocked
+        // walk keeps more neighbour tiles in L2 and moves the best occupancy)
+        std::vector<TileChoice> wc{best.c};
+        const int ns = f.ga.n - best.c.nfast;
+        int occ_now = 0;
+        {
+          GridArgs g = f.ga;
+          if (configure_tiles(g, op->precision, f.real, best.c)) occ_now = best.c.wgs_per_cu > 0 ? best.c.wgs_per_cu : g.occ_max;
+        }
+        for (int B : {2, 3}) {
+          bool useful = false;
+          for (int j = 0; j < ns; ++j) useful |= f.ga.ext[j] > B;
+          if (!useful || ns < 2) continue;
+          for (int w : {occ_now, occ_now + 1, occ_now - 1}) {
+            if (w < 1) continue;
+            TileChoice c = best.c;
+            c.wblock = B;
+            c.wgs_per_cu = w;
+            GridArgs g = f.ga;
+            if (configure_tiles(g, op->precision, f.real, c)) wc.push_back(c);
+          }
+        }
+        if (wc.size() > 1) {
+          std::vector<double> wt;
+          for (const TileChoice& c : wc) {
+            retile(f, op->precision, c);
+            wt.push_back(time_function_steps(f, op->precision, h, dflag.as<int>(), steps, st));
+          }
+          best = pick_shape(wc, wt);
+        }
         retile(f, op->precision, best.c);
       } catch (const Error&) {
         (void)hipStreamSynchronize(st);
@@ -2134,6 +2218,7 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
     out->pipe = tiled ? f.ga.pipe : 0;
     out->wgs_per_cu = tiled ? f.ga.occ_cap : 0;
     out->resident = f.resident ? 1 : 0;
+    out->walk_block = tiled ? f.ga.wblock : 0;
     out->blocks = tiled ? f.ga.blocks : 0;
     out->tile_points = tiled ? (int32_t)f.ga.tile_points : 1;
     out->stage_us = f.tuned_us;
@@ -2144,7 +2229,7 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
   return guarded([&] {
     if (!op || !cfg) fail(HGF_EINVAL, "NULL argument");
     if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
-    if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || cfg->wgs_per_cu < 0 ||
+    if (cfg->nfast < 0 || cfg->threads < 0 || cfg->xblock < 0 || cfg->wgs_per_cu < 0 || cfg->walk_block < 0 ||
         (cfg->pipe != 0 && cfg->pipe != 1) || (cfg->resident != 0 && cfg->resident != 1))
       fail(HGF_EINVAL, "negative tile parameter, or pipe or resident not 0/1");
     TileChoice c;
@@ -2153,6 +2238,7 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     c.xblock = cfg->xblock;
     c.pipe = cfg->pipe;
     c.wgs_per_cu = cfg->wgs_per_cu;
+    c.wblock = cfg->walk_block;
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
     Function& f = op->fn[idx];

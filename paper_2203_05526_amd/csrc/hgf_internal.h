@@ -94,7 +94,9 @@ struct GridArgs {
   int pipe;                 // single-grid kernel issues the loads of the next lane round early
   int occ_cap;              // resident workgroups per CU requested for the persistent grid (0: all that fit)
   int occ_max;              // resident workgroups per CU that fit (registers, LDS, waves)
+  int wblock;               // tile walk order: 0 row-major, B >= 2 blocks of B along every slow axis
   const void* tiles;        // per-tile records of the slow-axis terms (tiled kernel)
+  const uint32_t* walk;     // tile index at each walk position (NULL: the identity)
   double lam0_re, lam0_im;
   const double2* lam;       // concatenated lam_j(m)
   const double* beta;       // concatenated beta_j(m)

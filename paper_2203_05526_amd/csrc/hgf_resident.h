@@ -148,7 +148,7 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
           } else {
             const double c = 0.5 * h;
             const double nr = re_(yr[r]) + (double)re_(xr[r]) + c * (double)ar;
-            const double ni = im_(yr[r]) + (double)im_(xr[r]) + c * (double)ai;
+            const double ni = Real<TS>::cplx ? im_(yr[r]) + (double)im_(xr[r]) + c * (double)ai : 0.0;
             bad |= (tid + r * nt < T) && !(isfinite(nr) && isfinite(ni));
             yr[r] = mk_<TY>(nr, ni);
             orr[r] = mk_<TS>((R)nr, (R)ni);

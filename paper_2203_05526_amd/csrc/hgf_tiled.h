@@ -176,18 +176,20 @@ __device__ __forceinline__ void st_pack(P* base, uint32_t byte_off, const P& v) 
 // more values live and lowered the occupancy measured on the 6^10 grid).
 // Wave target of the tiled kernel: the pipelined float form is held to 5 waves
 // per SIMD (<= 102 VGPRs), the occupancy of the unpipelined form.
-template <bool PIPE, typename TS>
+template <int MODE, typename TS>
 struct TiledWaves {
-  static constexpr int value = (PIPE && sizeof(TS) == 4) ? 5 : 1;
+  static constexpr int value = (MODE == 1 && sizeof(TS) == 4) ? 5 : 1;
 };
 
-template <int NF, int NS, typename TS, typename TY, bool PIPE>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<PIPE, TS>::value))) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
+// MODE 0: one tile at a time; 1: pipelined neighbour loads.
+template <int NF, int NS, typename TS, typename TY, int MODE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<MODE, TS>::value))) void k_rk4_tiled(GridArgs g, int stage, const TS* __restrict__ in,
                                                    const TS* __restrict__ x1, TY* __restrict__ y,
                                                    TS* __restrict__ yf, TS* __restrict__ out, double h,
                                                    int* __restrict__ flag) {
   using R = typename Real<TS>::T;
   constexpr int V = 1;
+  constexpr bool PIPE = MODE == 1;
   using PS = Pack<TS, V>;
   using PY = Pack<TY, V>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -255,16 +257,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   // with g.xblock = B > 0 the blocks of B consecutive tiles whose index is
   // congruent to the XCD modulo 8 (all XCDs then sweep one compact region of
   // the grid together).  Workgroup wx of the XCD takes positions wx, wx + nwx, ...
+  // These are walk positions; g.walk (when set) maps them to tile indices.
   const uint32_t xcd = blockIdx.x & 7u;
   const uint32_t nwx = (gridDim.x - xcd + 7u) >> 3;
   const uint32_t nti = (uint32_t)g.ntiles;
   const uint32_t lo = (uint32_t)(((uint64_t)nti * xcd) >> 3), hi = (uint32_t)(((uint64_t)nti * (xcd + 1)) >> 3);
   const uint32_t xb = (uint32_t)g.xblock;
   constexpr uint32_t kNone = 0xffffffffu;
+  const uint32_t* __restrict__ walk = g.walk;
   auto tile_at = [&](uint32_t pos) -> uint32_t {
-    if (xb == 0) return lo + pos < hi ? lo + pos : kNone;
-    const uint32_t tt = (xcd + 8u * (pos / xb)) * xb + pos % xb;
-    return tt < nti ? tt : kNone;
+    uint32_t w;
+    if (xb == 0) {
+      if (lo + pos >= hi) return kNone;
+      w = lo + pos;
+    } else {
+      w = (xcd + 8u * (pos / xb)) * xb + pos % xb;
+      if (w >= nti) return kNone;
+    }
+    return walk ? walk[w] : w;
   };
   const int G = T / V;
   const int rounds = (G + nt - 1) / nt;
@@ -274,17 +284,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   }
   constexpr uint32_t SB = sizeof(TS), YB = sizeof(TY);
   int bad = 0;
+  // centre values of the next tile, one lane group per round
   PS nxt[kTileRounds];
-  uint32_t pos = blockIdx.x >> 3;
-  uint32_t t = tile_at(pos);
-  if (t != kNone) {
+  auto load_centres = [&](uint32_t t) {
     const uint32_t b0 = t * (uint32_t)T;
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
       const uint32_t gi = min((uint32_t)(tid + r * nt), (uint32_t)(G - 1));
       if (r < rounds) nxt[r] = ld_pack((const PS*)in, (b0 + V * gi) * SB);
     }
-  }
+  };
+  uint32_t pos = blockIdx.x >> 3;
+  uint32_t t = tile_at(pos);
+  if (t != kNone) load_centres(t);
   while (t != kNone) {
 #pragma unroll
     for (int r = 0; r < kTileRounds; ++r) {
@@ -297,14 +309,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
     __syncthreads();
     const uint32_t tbase = t * (uint32_t)T;
     const uint32_t tn = tile_at(pos + nwx);
-    if (tn != kNone) {
-      const uint32_t b0 = tn * (uint32_t)T;
-#pragma unroll
-      for (int r = 0; r < kTileRounds; ++r) {
-        const uint32_t gi = min((uint32_t)(tid + r * nt), (uint32_t)(G - 1));
-        if (r < rounds) nxt[r] = ld_pack((const PS*)in, (b0 + V * gi) * SB);
-      }
-    }
+    if (tn != kNone) load_centres(tn);
     // slow-axis terms, uniform over the tile (scalar loads of the tile's
     // record); every neighbour load is issued unconditionally
     const TileRec<NS, R>* rec = (const TileRec<NS, R>*)g.tiles + t;
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
         } else {
           const double c = 0.5 * h;
           const double nr = re_(yv.e[v]) + (double)re_(xb.e[v]) + c * (double)ar;
-          const double ni = im_(yv.e[v]) + (double)im_(xb.e[v]) + c * (double)ai;
+          const double ni = Real<TS>::cplx ? im_(yv.e[v]) + (double)im_(xb.e[v]) + c * (double)ai : 0.0;
           bad |= !(isfinite(nr) && isfinite(ni));
           yo.e[v] = mk_<TY>(nr, ni);
           o.e[v] = mk_<TS>((R)nr, (R)ni);
@@ -500,8 +505,14 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
 
     // ---- the member's tiles of this workgroup; the centre values of the
     // first one are loaded here, those of the next during each tile
+    // walk position -> tile index inside the member
+    const uint32_t* __restrict__ walk = mp->g.walk;
+    auto member_tile = [&](int64_t tt) -> uint32_t {
+      const uint32_t w = (uint32_t)(tt - mbeg);
+      return walk ? walk[w] : w;
+    };
     if (t < run_end) {
-      const uint32_t b0 = (uint32_t)(t - mbeg) * (uint32_t)T;
+      const uint32_t b0 = member_tile(t) * (uint32_t)T;
 #pragma unroll
       for (int r = 0; r < kTileRounds; ++r) {
         const uint32_t p = min((uint32_t)(tid + r * nt), (uint32_t)(T - 1));
@@ -509,7 +520,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       }
     }
     for (; t < run_end; ++t) {
-      const uint32_t lt = (uint32_t)(t - mbeg);  // tile index inside the member
+      const uint32_t lt = member_tile(t);  // tile index inside the member
       const uint32_t tbase = lt * (uint32_t)T;
 #pragma unroll
       for (int r = 0; r < kTileRounds; ++r) {
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       {
         const int64_t tn = t + 1;
         if (tn < run_end) {
-          const uint32_t b0 = (uint32_t)(tn - mbeg) * (uint32_t)T;
+          const uint32_t b0 = member_tile(tn) * (uint32_t)T;
 #pragma unroll
           for (int r = 0; r < kTileRounds; ++r) {
             const uint32_t p = min((uint32_t)(tid + r * nt), (uint32_t)(T - 1));
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
           } else {
             const double c = 0.5 * h;
             const double nr = re_(yv) + (double)re_(xb) + c * (double)ar;
-            const double ni = im_(yv) + (double)im_(xb) + c * (double)ai;
+            const double ni = Real<TS>::cplx ? im_(yv) + (double)im_(xb) + c * (double)ai : 0.0;
             bad |= !(isfinite(nr) && isfinite(ni));
             st_at_nt<TY>(mp->y, e0, mk_<TY>(nr, ni));
             if (mp->yf) st_at<TS>(mp->yf, e0, mk_<TS>((R)nr, (R)ni));
@@ -608,11 +619,11 @@ static void group_launch_nf(const GroupLaunch& gl, int stage, int* flag, hipStre
     if (gl.nmem == 1) {                                                                                      \
       const MemberArgs& a = gl.single;                                                                       \
       if (a.g.pipe)                                                                                          \
-        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, true>), dim3(gl.blocks), dim3(gl.threads),            \
+        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, 1>), dim3(gl.blocks), dim3(gl.threads),               \
                            gl.lds_bytes, st, a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1,        \
                            (TY*)a.y, (TS*)a.yf, (TS*)a.out[stage - 1], a.h, flag);                           \
       else                                                                                                   \
-        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, false>), dim3(gl.blocks), dim3(gl.threads),           \
+        hipLaunchKernelGGL((k_rk4_tiled<NF, K, TS, TY, 0>), dim3(gl.blocks), dim3(gl.threads),               \
                            gl.lds_bytes, st, a.g, stage, (const TS*)a.in[stage - 1], (const TS*)a.x1,        \
                            (TY*)a.y, (TS*)a.yf, (TS*)a.out[stage - 1], a.h, flag);                           \
     } else {                                                                                                 \
@@ -646,10 +657,10 @@ static int group_occ_nf(int ns, int threads, int lds_bytes, int single) {
     if (single == 0)                                                                                         \
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_group<NF, K, TS, TY>, threads, lds_bytes); \
     else if (single == 1)                                                                                    \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, false>, threads,      \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, 0>, threads,          \
                                                        lds_bytes);                                           \
     else                                                                                                     \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, true>, threads,       \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_tiled<NF, K, TS, TY, 1>, threads,          \
                                                        lds_bytes);                                           \
     break;                                                                                                   \
   }

@@ -74,7 +74,7 @@ class _Info(ctypes.Structure):
 class _TileConfig(ctypes.Structure):
     _fields_ = [("nfast", ctypes.c_int32), ("threads", ctypes.c_int32), ("xblock", ctypes.c_int32),
                 ("pipe", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("resident", ctypes.c_int32),
-                ("blocks", ctypes.c_int32), ("tile_points", ctypes.c_int32), ("stage_us", ctypes.c_double)]
+                ("walk_block", ctypes.c_int32), ("blocks", ctypes.c_int32), ("tile_points", ctypes.c_int32), ("stage_us", ctypes.c_double)]
 
 
 TUNE_FLAGS = {"default": 0, "cached_only": 1, "force": 2}
@@ -293,9 +293,9 @@ class Operator:
         return {f: getattr(c, f) for f, _ in _TileConfig._fields_}
 
     def set_tile_config(self, idx: int, nfast: int, threads: int = 0, xblock: int = 0, pipe: int = 0,
-                        wgs_per_cu: int = 0, resident: int = 0) -> None:
+                        wgs_per_cu: int = 0, resident: int = 0, walk_block: int = 0) -> None:
         """hgf_set_tile_config: force the launch shape of function ``idx``."""
-        c = _TileConfig(nfast, threads, xblock, pipe, wgs_per_cu, resident, 0, 0, 0.0)
+        c = _TileConfig(nfast, threads, xblock, pipe, wgs_per_cu, resident, walk_block, 0, 0, 0.0)
         _check(_lib.hgf_set_tile_config(self._h, idx, ctypes.byref(c)))
 
     def __del__(self):

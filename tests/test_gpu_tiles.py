@@ -22,18 +22,21 @@ def hgf():
 
 
 def _shapes(tile_points):
-    """(nfast, threads, xblock, pipe) samples for one tile size: the default
-    workgroup, the smallest and the largest feasible one, odd XCD blocks."""
+    """(threads, xblock, pipe, wgs_per_cu, walk_block) samples for one tile
+    size: the default workgroup, the smallest and the largest feasible one,
+    odd XCD blocks, blocked walk orders (blocks of 2 and 3, with interleaved
+    XCD blocks, and blocks wider than some axes)."""
     ths = [t for t in range(64, 513, 64) if -(-tile_points // t) <= 8]
-    return [(0, 0, 0, 0), (ths[0], 3, 1, 0), (ths[-1], 128, 0, 1), (ths[len(ths) // 2], 1, 1, 2)]
+    return [(0, 0, 0, 0, 0), (ths[0], 3, 1, 0, 2), (ths[-1], 128, 0, 1, 0), (ths[len(ths) // 2], 1, 1, 2, 3),
+            (0, 0, 0, 0, 4), (ths[-1], 5, 0, 0, 3)]
 
 
-def _apply(hgf, op, nfast, threads, xblock, pipe, wgs=0):
+def _apply(hgf, op, nfast, threads, xblock, pipe, wgs=0, walk=0):
     """Set the shape on every function where it is feasible; returns how many took it."""
     took = 0
     for i in range(op.info()["n_functions"]):
         try:
-            op.set_tile_config(i, nfast, threads, xblock, pipe, wgs)
+            op.set_tile_config(i, nfast, threads, xblock, pipe, wgs, walk_block=walk)
             took += 1
         except hgf.HgfError as e:
             assert e.status == "HGF_EINVAL"
@@ -63,15 +66,23 @@ def test_forced_tile_shapes_agree_and_match_oracle(hgf, precision, kind):
     tried = 0
     for nfast in (1, 2, 3, 4):
         tile = int(np.prod(cutoff[len(cutoff) - nfast:]))
-        for threads, xblock, pipe, wgs in _shapes(tile):
+        for threads, xblock, pipe, wgs, walk in _shapes(tile):
             op = hgf.map_operator(S, factors=fac, precision=precision)
-            if _apply(hgf, op, nfast, threads, xblock, pipe, wgs) == 0:
+            if _apply(hgf, op, nfast, threads, xblock, pipe, wgs, walk) == 0:
                 continue
-            announce(f"  nfast={nfast} threads={threads} xblock={xblock} pipe={pipe} wgs_per_cu={wgs}")
+            shape = (nfast, threads, xblock, pipe, wgs, walk)
+            announce(f"  nfast={nfast} threads={threads} xblock={xblock} pipe={pipe} wgs_per_cu={wgs} walk={walk}")
             hgf.evolve(op, T, dt)
             got = gpu_number_grids(op, cutoff)
-            assert max_rel_err(got, ref) < tol, (nfast, threads, xblock, pipe, wgs)
-            assert max_rel_err(got, base_grids) < same, (nfast, threads, xblock, pipe, wgs)
+            assert max_rel_err(got, ref) < tol, shape
+            assert max_rel_err(got, base_grids) < same, shape
+            if walk and nfast < len(cutoff):
+                assert any(op.tile_config(i)["walk_block"] == walk for i in range(op.info()["n_functions"]))
+                # the walk order moves no arithmetic: the same numbers as the row-major walk
+                rm = hgf.map_operator(S, factors=fac, precision=precision)
+                _apply(hgf, rm, nfast, threads, xblock, pipe, wgs, 0)
+                hgf.evolve(rm, T, dt)
+                assert max_rel_err(got, gpu_number_grids(rm, cutoff)) == 0.0, shape
             tried += 1
     assert tried >= 10
     if kind == "complex-bidiagonal":  # the untiled kernel too
@@ -98,7 +109,8 @@ def test_tile_config_rejects_infeasible_shapes(hgf):
            (4, 1024, 0, 0),   # above 512 lanes
            (6, 0, 0, 0),      # more fast axes than the grid has
            (4, 256, 0, 2),    # pipe is 0 or 1
-           (4, 256, 0, 0, 64)]  # more resident workgroups than fit on a CU
+           (4, 256, 0, 0, 64),  # more resident workgroups than fit on a CU
+           (4, 256, 0, 0, 0, 0, -2)]  # negative walk block
     for cfg in bad:
         with pytest.raises(hgf.HgfError) as e:
             op.set_tile_config(0, *cfg)
@@ -153,8 +165,9 @@ def test_autotune_cache_and_results(hgf, tmp_path):
     fresh = hgf.map_operator(cases[0][1], factors=cases[0][2], precision="mixed")
     hgf.autotune([fresh], dt, cache=cache, mode="cached_only")
     a = fresh.tile_config(0)
-    fields = shape_line[0].split()[1:6]
-    assert [a[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu")] == [int(v) for v in fields]
+    fields = shape_line[0].split()[1:7]
+    assert [a[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu", "walk_block")] == [
+        int(v) for v in fields]
     # force re-measures and rewrites the entry in place
     hgf.autotune([fresh], dt, cache=cache, mode="force")
     assert len(open(cache).read().splitlines()) == 3
