@@ -206,6 +206,21 @@ hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double ou
                            void* hip_stream);
 
 /*
+ * Step (iii) at the operator level: the number-basis matrix elements
+ * <k|A(t)|l> (Eq. (11): the generating-function coefficients g_{k,l} of the
+ * evolved operator times sqrt(k! l!), with o1 = a^+, o2 = a, r = 1) for every
+ * k, l whose occupations are all below `levels`, as a dense row-major matrix:
+ * row index sum_j k_j * levels^(N-1-j) (last mode fastest), column index the
+ * same for l.  out receives 2 * levels^(2N) doubles (re, im), owned by the
+ * caller; elements of sectors the operator does not hold are 0.  In split
+ * layout each function contributes g0 (c_x c_y x^p y^q + R).  levels = 3 gives
+ * the three-level truncation on which the paper measures operator errors.
+ * Errors: HGF_EINVAL (NULL, levels outside [1, every cutoff], levels^(2N) above
+ * 2^24), HGF_EDEVICE.  Synchronises hip_stream.
+ */
+hgf_status hgf_reconstruct(hgf_operator op, int32_t levels, double* out, void* hip_stream);
+
+/*
  * Gradient of J = <psi0| A(T) |psi0> with respect to every parameter of
  * hgf_num_params, by a discrete adjoint (reverse) sweep of the RK4 steps over
  * checkpoints taken every `checkpoint_every` steps, in FP64 and merged layout

@@ -15,6 +15,7 @@ from .hgf import (  # noqa: F401
     evolve,
     evolve_batch,
     expectation,
+    reconstruct,
     grad,
     load_library,
     map_operator,

@@ -1834,6 +1834,81 @@ static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStr
   return cd(r.x, r.y);
 }
 
+// ------------------------------------------------------------------ reconstruction
+
+// Largest output of hgf_reconstruct, in matrix elements.
+constexpr int64_t kMaxReconstructElems = (int64_t)1 << 24;
+
+// <k|A|l> for every k, l below `levels` in every mode (Eq. (11)): each
+// function's grid points in that box, times sqrt(k! l!), scattered into a
+// dense matrix on the device, then copied to `out`.
+static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStream_t st) {
+  const int n = op->sys.n;
+  int64_t ln = 1;
+  for (int j = 0; j < n; ++j) {
+    if (levels < 1 || levels > op->sys.nc[j]) fail(HGF_EINVAL, "levels must be in [1, every cutoff]");
+    ln *= levels;
+    if (ln * ln > kMaxReconstructElems) fail(HGF_EINVAL, "levels^(2N) exceeds 2^24 matrix elements");
+  }
+  const int64_t elems = ln * ln;
+  std::vector<GatherBox> boxes;
+  std::vector<int> fidx;
+  std::vector<double> fac;
+  for (size_t i = 0; i < op->fn.size(); ++i) {
+    const Function& f = op->fn[i];
+    GatherBox b{};
+    b.ln = ln;
+    b.total = 1;
+    b.pq = -1;
+    b.coef = make_double2(1.0, 0.0);
+    int64_t place = ln;
+    for (int j = 0; j < n; ++j) {
+      place /= levels;
+      b.lp[j] = place;
+      b.u[j] = f.tab.u[j];
+      b.v[j] = f.tab.v[j];
+      b.b[j] = std::max(0, levels - std::max(b.u[j], b.v[j]));
+      b.foff[j] = (int)fac.size();
+      for (int m = 0; m < b.b[j]; ++m) fac.push_back(sqrt_factorial(m + b.u[j]) * sqrt_factorial(m + b.v[j]));
+      b.total *= b.b[j];
+    }
+    if (b.total == 0) continue;
+    if (f.split) {  // G = g0 (c_x c_y x^p y^q + R): the separable part sits at m = min(p, q)
+      b.coef = make_double2(f.g0.real(), f.g0.imag());
+      int64_t gi = 0;
+      bool inside = true;
+      for (int j = 0; j < n; ++j) {
+        const int m = std::min(f.p[j], f.q[j]);
+        inside &= m < b.b[j];
+        gi += m * f.ga.stride[j];
+      }
+      if (inside) {
+        const cd a = f.cx * f.cy;
+        b.pq = gi;
+        b.add = make_double2(a.real(), a.imag());
+      }
+    }
+    boxes.push_back(b);
+    fidx.push_back((int)i);
+  }
+  DBuf dout((size_t)elems * sizeof(double2));
+  launch_fill_zero(dout.as<double2>(), elems, st);
+  if (!boxes.empty()) {
+    DBuf dfac(fac.size() * sizeof(double));
+    hip_check(hipMemcpyAsync(dfac.p, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+    for (size_t k = 0; k < boxes.size(); ++k) {
+      const Function& f = op->fn[fidx[k]];
+      launch_gather_levels(f.ga, f.y, f.real, boxes[k], dfac.as<double>(), dout.as<double2>(), st);
+    }
+    hip_check(hipGetLastError(), "kernel launch");
+    hip_check(hipMemcpyAsync(out, dout.p, (size_t)elems * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+    hip_check(hipStreamSynchronize(st), "synchronize");  // dfac and dout outlive the launches
+  } else {
+    hip_check(hipMemcpyAsync(out, dout.p, (size_t)elems * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+  }
+}
+
 // ------------------------------------------------------------------ gradient
 
 // Longest reverse segment captured as one graph (about 12 nodes per step).
@@ -2162,6 +2237,14 @@ hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_
       hip_check(hipSetDevice(ops[0]->device), "hipSetDevice");
       batch_impl(ops, n, steps, dt_us, (hipStream_t)hip_stream);
     }
+  });
+}
+
+hgf_status hgf_reconstruct(hgf_operator op, int32_t levels, double* out, void* hip_stream) {
+  return guarded([&] {
+    if (!op || !out) fail(HGF_EINVAL, "NULL argument");
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    reconstruct_impl(op, levels, out, (hipStream_t)hip_stream);
   });
 }
 

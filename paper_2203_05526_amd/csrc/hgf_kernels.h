@@ -58,6 +58,21 @@ void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, 
 int marginal_bins(const GridArgs& g);
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st);
 void launch_fill_zero(double2* p, int64_t n, hipStream_t st);
+// Number-basis matrix elements of one function on the lowest levels of every
+// mode: the sub-box m_j < b[j] of the grid, scattered to out[row * ln + col].
+struct GatherBox {
+  int b[kMaxModes];        // sub-box extents (levels - max(u_j, v_j))
+  int u[kMaxModes], v[kMaxModes];
+  int foff[kMaxModes];     // start of axis j in the factor table sqrt(k! l!)(m)
+  int64_t lp[kMaxModes];   // levels^(N-1-j): row/column place value of mode j
+  int64_t ln;              // levels^N: the output's row length
+  int64_t total;           // prod_j b[j]
+  int64_t pq;              // grid index that gets `add` (split layout), or -1
+  double2 add;             // separable part at (p, q) (split layout)
+  double2 coef;            // overall factor (g0 in split layout, else 1)
+};
+void launch_gather_levels(const GridArgs& g, const void* y, bool real, const GatherBox& box, const double* fac,
+                          double2* out, hipStream_t st);
 // device-to-device copy as a kernel (safe to record in a captured graph)
 void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st);
 void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st);

@@ -552,6 +552,32 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
     p[i] = make_double2(0.0, 0.0);
 }
 
+// <k|A|l> = g(m) sqrt(k! l!) on the sub-box of grid points whose levels are
+// all below the output's level count (Eq. (11) with o1 = a^+, o2 = a, r = 1)
+__global__ void k_gather_levels(GridArgs g, const double* __restrict__ y, int real, GatherBox box,
+                                const double* __restrict__ fac, double2* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < box.total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = i, gi = 0, row = 0, col = 0;
+    double f = 1.0;
+    for (int j = g.n - 1; j >= 0; --j) {
+      const int m = (int)(rem % box.b[j]);
+      rem /= box.b[j];
+      gi += m * g.stride[j];
+      row += (int64_t)(m + box.u[j]) * box.lp[j];
+      col += (int64_t)(m + box.v[j]) * box.lp[j];
+      f *= fac[box.foff[j] + m];
+    }
+    double2 val = real ? make_double2(y[gi], 0.0) : make_double2(y[2 * gi], y[2 * gi + 1]);
+    if (gi == box.pq) val = make_double2(val.x + box.add.x, val.y + box.add.y);
+    val = cmul(box.coef, val);
+    // split layout: several functions share a sector (one launch each, in
+    // stream order), so contributions are added
+    double2* o = out + row * box.ln + col;
+    *o = make_double2(o->x + f * val.x, o->y + f * val.y);
+  }
+}
+
 __global__ void k_copy2(double2* __restrict__ dst, const double2* __restrict__ src, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -763,6 +789,14 @@ int marginal_bins(const GridArgs& g) {
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st) {
   const int nb = marginal_bins(g);
   hipLaunchKernelGGL(k_marginals, dim3(nb), dim3(kRedThreads), 0, st, g, Q, bins);
+}
+
+void launch_gather_levels(const GridArgs& g, const void* y, bool real, const GatherBox& box, const double* fac,
+                          double2* out, hipStream_t st) {
+  if (box.total <= 0) return;
+  const int blocks = (int)std::min<int64_t>((box.total + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_gather_levels, dim3(blocks), dim3(256), 0, st, g, (const double*)y, real ? 1 : 0, box, fac,
+                     out);
 }
 
 void launch_fill_zero(double2* p, int64_t n, hipStream_t st) {

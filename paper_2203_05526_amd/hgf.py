@@ -26,7 +26,7 @@ STATUS = {0: "HGF_OK", -1: "HGF_EINVAL", -2: "HGF_ENOMEM", -3: "HGF_EDEVICE", -4
           -5: "HGF_ENONFINITE", -6: "HGF_EUNSUPPORTED", -7: "HGF_ESTATE"}
 
 EXPORTED = ["hgf_define_system", "hgf_destroy_system", "hgf_num_params", "hgf_map_operator",
-            "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_grad",
+            "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_reconstruct", "hgf_grad",
             "hgf_get_info", "hgf_get_function", "hgf_last_error", "hgf_version"]
 
 
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.hgf_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     lib.hgf_evolve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_expectation.argtypes = [vp, ctypes.POINTER(_StateDesc), _f64p, vp]
+    lib.hgf_reconstruct.argtypes = [vp, ctypes.c_int32, _f64p, vp]
     lib.hgf_grad.argtypes = [vp, ctypes.POINTER(_OperatorDesc), ctypes.POINTER(_StateDesc),
                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -412,6 +413,16 @@ def expectation(op: Operator, state, stream=None) -> complex:
     out = np.zeros(2)
     _check(_lib.hgf_expectation(op.handle, ctypes.byref(d), out.ctypes.data_as(_f64p), _stream(stream)))
     return complex(out[0], out[1])
+
+
+def reconstruct(op: Operator, levels: int, stream=None) -> np.ndarray:
+    """hgf_reconstruct: <k|A(t)|l> for all occupations below ``levels``, as a
+    (levels^N, levels^N) complex matrix (last mode fastest)."""
+    n = op.system.n_modes
+    ln = int(levels) ** n
+    out = np.zeros(2 * ln * ln)
+    _check(_lib.hgf_reconstruct(op.handle, int(levels), out.ctypes.data_as(_f64p), _stream(stream)))
+    return out.view(np.complex128).reshape(ln, ln)
 
 
 def grad(system: System, state, t_total: float, dt: float, factors=None, sparse=None, basis="number",

@@ -85,6 +85,7 @@ def test_null_arguments_are_rejected(hgf):
     assert lib.hgf_get_tile_config(None, 0, None) == -1
     assert lib.hgf_set_tile_config(None, 0, None) == -1
     assert lib.hgf_autotune(None, 1, 1e-3, None, 0, None) == -1
+    assert lib.hgf_reconstruct(None, 3, None, None) == -1
     assert b"NULL" in lib.hgf_last_error()
 
 
