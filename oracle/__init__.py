@@ -57,6 +57,8 @@ def _load():
     lib.oracle_rhs.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_int]
     lib.oracle_evolve.argtypes = sysargs + [ctypes.c_int, ip, vp, ctypes.c_long,
                                             ctypes.c_double, ctypes.c_int]
+    lib.oracle_evolve_lawson.argtypes = sysargs + [ctypes.c_int, ip, vp, ctypes.c_long,
+                                            ctypes.c_double, ctypes.c_int]
     lib.oracle_evolve_sens.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_long,
                                                  ctypes.c_double, ctypes.c_int]
     lib.oracle_num_params.argtypes = [ctypes.c_int]
@@ -132,6 +134,20 @@ def evolve(system, ops: Sectors, t_total: float, dt: float, nthreads: int = 0) -
                            A.ctypes.data, n_steps(t_total, dt), float(dt), nthreads)
     if rc:
         raise RuntimeError(f"oracle_evolve failed ({rc})")
+    return {k: A[i] for i, k in enumerate(keys)}
+
+
+def evolve_lawson(system, ops: Sectors, t_total: float, dt: float, nthreads: int = 0) -> Sectors:
+    """A(T) from A(0) by the integrating-factor (Lawson) RK4: the diagonal
+    part of the right-hand side of Eq. (3) taken exactly, the jump terms by
+    classical RK4 in the interaction picture."""
+    lib = _load()
+    keys, d, A = _pack(system, ops)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve_lawson(*args, len(keys), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  A.ctypes.data, n_steps(t_total, dt), float(dt), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve_lawson failed ({rc})")
     return {k: A[i] for i, k in enumerate(keys)}
 
 

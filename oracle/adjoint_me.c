@@ -123,7 +123,7 @@ static double elem_adag(int row, int col, int nc) { /* <row| a^+ |col> */
  * number state, so L^+ A L touches exactly one element of A and L^+ L is
  * diagonal.
  */
-static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out) {
+static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out, int part) {
   const int n = s->n;
   const long total = box_size(s);
   long stride[OMAXN];
@@ -145,7 +145,9 @@ static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out) {
       out[f] = 0.0;
       continue;
     }
-    const cplx a = A[f];
+    /* part 1 (jump terms only): every term proportional to A[k,l] itself is
+     * left out, i.e. the whole right-hand side is evaluated with a = 0 */
+    const cplx a = part == 1 ? 0.0 : A[f];
     cplx r = I * (energy(s, k) - energy(s, l)) * a;
     for (int j = 0; j < n; ++j) {
       const int nc = s->nc[j];
@@ -204,7 +206,35 @@ static void rhs_sector(const osys *s, const int *d, const cplx *A, cplx *out) {
 
 static void rhs_all(const osys *s, int nsec, const int *d, const cplx *A, cplx *out) {
   const long box = box_size(s);
-  for (int q = 0; q < nsec; ++q) rhs_sector(s, d + q * s->n, A + q * box, out + q * box);
+  for (int q = 0; q < nsec; ++q) rhs_sector(s, d + q * s->n, A + q * box, out + q * box, 0);
+}
+
+static void jumps_all(const osys *s, int nsec, const int *d, const cplx *A, cplx *out) {
+  const long box = box_size(s);
+  for (int q = 0; q < nsec; ++q) rhs_sector(s, d + q * s->n, A + q * box, out + q * box, 1);
+}
+
+/*
+ * Diagonal coefficient of the right-hand side: the factor D[k,l] with which
+ * A[k,l] enters its own derivative (Hamiltonian phase, damping from the
+ * anticommutators, dephasing).  Both right-hand sides are linear, and on the
+ * all-ones state the full one is D + J(ones) element by element while the
+ * jump-only one is J(ones); their difference is D, term by term as written
+ * above.
+ */
+static int diagonal_all(const osys *s, int nsec, const int *d, cplx *D) {
+  const long len = box_size(s) * nsec;
+  cplx *one = malloc(sizeof(cplx) * len), *full = malloc(sizeof(cplx) * len), *jmp = malloc(sizeof(cplx) * len);
+  if (!one || !full || !jmp) {
+    free(one); free(full); free(jmp);
+    return -2;
+  }
+  for (long i = 0; i < len; ++i) one[i] = 1.0;
+  rhs_all(s, nsec, d, one, full);
+  jumps_all(s, nsec, d, one, jmp);
+  for (long i = 0; i < len; ++i) D[i] = full[i] - jmp[i];
+  free(one); free(full); free(jmp);
+  return 0;
 }
 
 /* y <- x + c * z, elementwise */
@@ -272,6 +302,59 @@ int oracle_evolve(int n, const int *nc, const double *det, const double *kerr, c
     axpy_into(len, A, acc, h / 6.0, kk);
   }
   free(kk); free(Y); free(acc);
+  return 0;
+}
+
+/*
+ * Integrating-factor ("Lawson") fourth-order Runge-Kutta with fixed step h.
+ * Write the right-hand side as D A + J(A), D the diagonal coefficients above
+ * and J the jump terms.  With u(tau) = exp(-D tau) A(t_n + tau) the equation
+ * becomes u' = f(tau, u) = exp(-D tau) J(exp(D tau) u), integrated by the
+ * classical RK4 stages from u(0) = A(t_n); then A(t_n + h) = exp(D h) u(h).
+ * Elements outside the box (l out of range) stay zero.
+ */
+static void lawson_f(const osys *s, int nsec, const int *d, const cplx *D, double tau, const cplx *u, cplx *tmp,
+                     cplx *out, long len) {
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < len; ++i) tmp[i] = cexp(D[i] * tau) * u[i];
+  jumps_all(s, nsec, d, tmp, out);
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < len; ++i) out[i] *= cexp(-D[i] * tau);
+}
+
+int oracle_evolve_lawson(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+                         const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+                         int nsec, const int *d, cplx *A, long nsteps, double h, int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev)) return -1;
+  set_threads(nthreads);
+  const long len = box_size(&s) * nsec;
+  cplx *D = malloc(sizeof(cplx) * len), *kk = malloc(sizeof(cplx) * len), *Y = malloc(sizeof(cplx) * len),
+       *acc = malloc(sizeof(cplx) * len), *tmp = malloc(sizeof(cplx) * len);
+  if (!D || !kk || !Y || !acc || !tmp) {
+    free(D); free(kk); free(Y); free(acc); free(tmp);
+    return -2;
+  }
+  if (diagonal_all(&s, nsec, d, D)) {
+    free(D); free(kk); free(Y); free(acc); free(tmp);
+    return -2;
+  }
+  for (long step = 0; step < nsteps; ++step) {
+    lawson_f(&s, nsec, d, D, 0.0, A, tmp, kk, len);       /* k1 */
+    axpy_into(len, acc, A, h / 6.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    lawson_f(&s, nsec, d, D, 0.5 * h, Y, tmp, kk, len);   /* k2 */
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    lawson_f(&s, nsec, d, D, 0.5 * h, Y, tmp, kk, len);   /* k3 */
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h, kk);
+    lawson_f(&s, nsec, d, D, h, Y, tmp, kk, len);         /* k4 */
+    axpy_into(len, acc, acc, h / 6.0, kk);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < len; ++i) A[i] = cexp(D[i] * h) * acc[i];
+  }
+  free(D); free(kk); free(Y); free(acc); free(tmp);
   return 0;
 }
 

@@ -373,3 +373,58 @@ def test_secular_coherence_decays_without_feeding(oracle_lib):
         assert abs(out[k, l] - expect) < 1e-13
         out[k, l] = 0.0
         assert np.max(np.abs(out)) == 0.0
+
+
+# --------------------------------------------------------------- integrating-factor RK4
+
+def test_lawson_exact_without_jumps(oracle_lib):
+    """With no emission or absorption (gamma1 = 0) the right-hand side of
+    Eq. (3) is diagonal element by element, D[k,l] = i(E_k - E_l) -
+    sum_j gamma_phi_j (k_j - l_j)^2, and the integrating-factor step takes it
+    exactly: A(T) = exp(D T) A(0) whatever the step size."""
+    cutoff = (4, 3)
+    s = small_system(120, cutoff, scale=40.0)
+    s.gamma1 = np.zeros(2)
+    rng = np.random.default_rng(120)
+    dim = 12
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    E = np.real(np.diag(pinlib.hamiltonian(s)))
+    occ = np.array([np.unravel_index(i, cutoff) for i in range(dim)])
+    D = 1j * (E[:, None] - E[None, :])
+    for j in range(2):
+        D -= s.gamma_phi[j] * (occ[:, None, j] - occ[None, :, j]) ** 2
+    T = 0.1
+    got = oracle.dense_from_sectors(cutoff, oracle.evolve_lawson(s, oracle.sectors_from_dense(cutoff, A0), T, 0.05))
+    assert pinlib.rel(got, np.exp(D * T) * A0) < 1e-13
+    # classical RK4 at this step is far off (|D| dt ~ 10)
+    rk = oracle.dense_from_sectors(cutoff, oracle.evolve(s, oracle.sectors_from_dense(cutoff, A0), T, 0.05))
+    assert pinlib.rel(rk, np.exp(D * T) * A0) > 1.0
+
+
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+def test_lawson_converges_to_expm_at_fourth_order(oracle_lib, dissipator):
+    """Stiff Kerr phases with weak jumps: against exp(S T) of the Kronecker
+    superoperator the integrating-factor result converges at fourth order
+    (error / 16 per halving of dt) and at a step where classical RK4 is
+    unstable it is already accurate."""
+    cutoff = (5, 4)
+    rng = np.random.default_rng(121)
+    s = small_system(121, cutoff, scale=1.0, n_th=0.3)
+    s.kerr = np.array([-300.0, -250.0])
+    s.cross_kerr = np.array([[0.0, -20.0], [-20.0, 0.0]])
+    if dissipator == "secular":
+        s = with_secular(s, rng)
+    dim = 20
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    ops = oracle.sectors_from_dense(cutoff, A0)
+    T = 0.2
+    ref = pinlib.expm_evolve(s, A0, T)
+    # the jump terms oscillate in the interaction picture at the neighbours'
+    # phase difference (K d ~ 300 rad/us): the fourth-order regime starts at
+    # a step of a few thousandths of a microsecond
+    errs = [pinlib.rel(oracle.dense_from_sectors(cutoff, oracle.evolve_lawson(s, ops, T, dt)), ref)
+            for dt in (0.002, 0.001, 0.0005)]
+    assert errs[0] < 1e-5
+    assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0
+    rk = oracle.dense_from_sectors(cutoff, oracle.evolve(s, ops, T, 0.002))
+    assert not np.all(np.isfinite(rk)) or pinlib.rel(rk, ref) > 1.0
