@@ -117,6 +117,36 @@ def time_to_tolerance(hgf, torch):
         out[f"{prec}_s"] = el
         out[f"{prec}_rel_err"] = abs(J - ref) / abs(ref)
     out["mixed_within_1e-5"] = out["mixed_rel_err"] <= 1e-5
+    out["off_diagonal"] = stiff_time_to_tolerance(hgf, torch)
+    return out
+
+
+def stiff_time_to_tolerance(hgf, torch):
+    """Wall time and error against the FP64 oracle's stored value on the
+    product-of-quadratures workload (4 modes, cutoff 8, 16 off-diagonal
+    sectors with Kerr phases of ~1.5e3 rad/us, T = 0.02 us): classical RK4 at
+    dt = 1 ps (2e4 steps) against the integrating-factor RK4 at dt = 1 ns (20
+    steps), in FP64 and mixed precision."""
+    import synth
+    with open(os.path.join(ROOT, "tests", "golden", "quadratures.json")) as fh:
+        gold = json.load(fh)
+    ref = complex(*gold["value"])
+    w = synth.grad_c3b()
+    S = hgf.define_system(w.system)
+    warm = hgf.map_operator(S, factors=w.factors, precision="fp64")  # load the kernels once
+    hgf.evolve(warm, 4 * w.dt, w.dt)
+    hgf.evolve(warm, 2e-3, 1e-3, scheme="lawson")
+    out = {"workload": "4 Kerr modes, cutoff 8, product of quadratures, T = 0.02 us (16 sectors of 7^4 points)"}
+    for scheme, dt in (("rk4", w.dt), ("lawson", 1e-3)):
+        for prec in ("fp64", "mixed"):
+            op = hgf.map_operator(S, factors=w.factors, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hgf.evolve(op, w.t_total, dt, scheme=scheme)
+            J = hgf.expectation(op, w.states[0])
+            torch.cuda.synchronize()
+            out[f"{scheme}_{prec}"] = {"dt_us": dt, "steps": int(round(w.t_total / dt)),
+                                       "seconds": time.perf_counter() - t0, "rel_err": abs(J - ref) / abs(ref)}
     return out
 
 
@@ -278,7 +308,7 @@ def main():
         log("batched evolve")
         line["batch"] = batch_throughput(hgf, torch, 500)
         log("gradient")
-        line["gradient"] = gradient_timing(hgf, torch, 0.5)
+        line["gradient"] = gradient_timing(hgf, torch, 5.0)
     if not args.no_cpu_baseline:
         log("cpu oracle baseline")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

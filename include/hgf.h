@@ -163,16 +163,23 @@ void hgf_destroy_operator(hgf_operator op);
 
 /* time-stepping schemes of hgf_evolve */
 enum {
-  HGF_RK4 = 0 /* classical fourth-order Runge-Kutta with a fixed step */
+  HGF_RK4 = 0,       /* classical fourth-order Runge-Kutta with a fixed step (the paper's scheme) */
+  HGF_LAWSON_RK4 = 1 /* integrating-factor RK4: the diagonal part of the generator (phases,
+                        damping, dephasing) taken exactly, the jump terms by classical RK4 in
+                        its interaction picture; merged layout only */
 };
 
 /*
  * Step (ii): advance every function of the operator by t_total_us with
- * classical RK4 steps of dt_us (Heisenberg picture: A(0) -> A(t)).
- * scheme must be HGF_RK4 (HGF_EUNSUPPORTED otherwise).
+ * fixed steps of dt_us (Heisenberg picture: A(0) -> A(t)) of the given
+ * scheme: HGF_RK4, or HGF_LAWSON_RK4, whose step is exact without jumps and so
+ * is not limited by large Kerr phases in off-diagonal sectors (every function
+ * then runs on the untiled stage kernel).  Other values: HGF_EUNSUPPORTED, as
+ * is HGF_LAWSON_RK4 on a split-layout operator.
  * t_total_us / dt_us must be a non-negative integer (to 1e-9 relative).
- * Errors: HGF_EINVAL; HGF_EUNSTABLE when dt times a bound on the generator's
- * spectral radius leaves the RK4 stability region (nothing is run);
+ * Errors: HGF_EINVAL; HGF_EUNSTABLE when dt times a bound on the spectral
+ * radius of the generator (HGF_RK4) or of its jump terms (HGF_LAWSON_RK4)
+ * leaves the RK4 stability region (nothing is run);
  * HGF_ENONFINITE when a NaN/Inf appears (the functions are restored to the
  * last state checked finite and the operator moves to an error state in which
  * further evolves return HGF_ESTATE until hgf_clear_error); HGF_EDEVICE.

@@ -168,11 +168,23 @@ static int64_t check_steps(double t_total, double dt) {
   return m;
 }
 
-static void check_stability(const std::vector<Function>& fns, double dt) {
+static void check_stability(const std::vector<Function>& fns, double dt, bool jumps_only = false) {
   // RK4's stability region holds the left half-disc of radius ~2.6; the
-  // Gershgorin bound of the sector generator must fit in it.
+  // Gershgorin bound of the sector generator (of its jump terms alone for the
+  // integrating-factor scheme, whose diagonal part is exact and has a
+  // non-positive real part) must fit in it.
   for (const auto& f : fns) {
-    const double b = generator_bound(f.tab) * dt;
+    double b = 0.0;
+    if (jumps_only) {
+      for (int j = 0; j < f.tab.n; ++j) {
+        double mx = 0.0;
+        for (int m = 0; m < f.tab.ext[j]; ++m) mx = std::max(mx, f.tab.alpha[j][m] + f.tab.beta[j][m]);
+        b += mx;
+      }
+    } else {
+      b = generator_bound(f.tab);
+    }
+    b *= dt;
     if (b > 2.5)
       fail(HGF_EUNSTABLE, "dt * spectral bound = " + std::to_string(b) +
                               " exceeds the RK4 stability limit 2.5; reduce dt");
@@ -517,6 +529,7 @@ static void free_function(Function& f) {
   dfree(f.yf);
   dfree(f.dtab);
   dfree(f.ttab);
+  dfree(f.ehtab);
 }
 
 static int64_t flat_index(const SectorTables& t, const int* m) {
@@ -1154,6 +1167,61 @@ static void split_step(hgf_operator_s* op, Function& f, double h, hipStream_t st
   f.cy = cy + h / 6.0 * (ky[0] + 2.0 * ky[1] + 2.0 * ky[2] + ky[3]);
 }
 
+// Integrating-factor scheme: per-axis factors exp(lam_j(m) h/2) of a function
+// for step h (uploaded once per step size).
+static void ensure_lawson_tables(Function& f, double h, hipStream_t st) {
+  if (f.ehtab && f.eh_h == h) return;
+  std::vector<double2> t;
+  for (int j = 0; j < f.tab.n; ++j)
+    for (int m = 0; m < f.tab.ext[j]; ++m) {
+      const cd e = std::exp(f.tab.lam[j][m] * (0.5 * h));
+      t.push_back(make_double2(e.real(), e.imag()));
+    }
+  if (!f.ehtab) f.ehtab = dmalloc(t.size() * sizeof(double2));
+  hip_check(hipMemcpyAsync(f.ehtab, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipStreamSynchronize(st), "synchronize");  // the host table is freed on return
+  f.eh0 = std::exp(f.tab.lam0 * (0.5 * h));
+  f.eh_h = h;
+}
+
+// One integrating-factor RK4 step of every function (stage buffers: s1 and s2
+// take v2, v3, v4 in turn, s3 the increment).
+static void lawson_step(hgf_operator_s* op, double h, hipStream_t st) {
+  const bool mixed = op->precision == HGF_MIXED;
+  for (int s = 1; s <= 4; ++s)
+    for (auto& f : op->fn) {
+      const void* ye = mixed ? f.yf : f.y;
+      const void* in[4] = {ye, f.s1, f.s2, f.s1};
+      void* vout[4] = {f.s1, f.s2, f.s1, nullptr};
+      launch_lawson(s, op->precision, f.real, f.ga, in[s - 1], ye, f.y, mixed ? f.yf : nullptr, vout[s - 1], f.s3,
+                    (const double2*)f.ehtab, make_double2(f.eh0.real(), f.eh0.imag()), h, op->dflag, st);
+    }
+}
+
+static void lawson_steps(hgf_operator_s* op, int64_t steps, double h, hipStream_t st) {
+  for (auto& f : op->fn) ensure_lawson_tables(f, h, st);
+  // graphs of up to 64 steps and at most kMaxGraphNodes kernel nodes
+  const int64_t per_step = 4 * (int64_t)op->fn.size();
+  const int chunk = (int)std::min<int64_t>({steps, 64, kMaxGraphNodes / std::max<int64_t>(1, per_step)});
+  int64_t done = 0;
+  if (chunk > 1) {
+    if (!op->cap_stream) hip_check(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking), "stream");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    hip_check(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    for (int s = 0; s < chunk; ++s) lawson_step(op, h, op->cap_stream);
+    hipGraph_t graph;
+    hip_check(hipStreamEndCapture(op->cap_stream, &graph), "end capture");
+    hipGraphExec_t exec;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "graph instantiate");
+    GraphHolder g(exec);
+    for (; done + chunk <= steps; done += chunk) hip_check(hipGraphLaunch(g.e, st), "graph launch");
+    hip_check(hipStreamSynchronize(st), "synchronize");  // the graph must outlive its launches
+  }
+  for (; done < steps; ++done) lawson_step(op, h, st);
+}
+
 static int read_flag(hgf_operator_s* op, hipStream_t st) {
   int flag = 0;
   hip_check(hipMemcpyAsync(&flag, op->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
@@ -1161,14 +1229,16 @@ static int read_flag(hgf_operator_s* op, hipStream_t st) {
   return flag;
 }
 
-static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st) {
+static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, int scheme = HGF_RK4) {
+  if (scheme == HGF_LAWSON_RK4 && op->layout != HGF_MERGED)
+    fail(HGF_EUNSUPPORTED, "the integrating-factor scheme runs on merged-layout operators only");
   if (steps == 0) return;
   if (op->fn.empty()) {  // the zero operator stays zero
     op->steps_done += steps;
     op->time_us += steps * h;
     return;
   }
-  check_stability(op->fn, h);
+  check_stability(op->fn, h, scheme == HGF_LAWSON_RK4);
   // keep a copy of the states for recovery after a non-finite result
   for (auto& f : op->fn) {
     const size_t bytes = state_bytes(f);
@@ -1181,7 +1251,9 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
     cy0.push_back(f.cy);
   }
   reset_flag(op, st);
-  if (op->layout == HGF_MERGED) {
+  if (scheme == HGF_LAWSON_RK4) {
+    lawson_steps(op, steps, h, st);
+  } else if (op->layout == HGF_MERGED) {
     ensure_plan(op, h);
     run_resident(*op->plan, steps, op->dflag, st);
     const int chunk = graph_chunk(*op->plan, steps);
@@ -2209,11 +2281,11 @@ hgf_status hgf_clear_error(hgf_operator op) {
 hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, int32_t scheme, void* hip_stream) {
   return guarded([&] {
     if (!op) fail(HGF_EINVAL, "operator is NULL");
-    if (scheme != HGF_RK4) fail(HGF_EUNSUPPORTED, "only the classical RK4 scheme is implemented");
+    if (scheme != HGF_RK4 && scheme != HGF_LAWSON_RK4) fail(HGF_EUNSUPPORTED, "unknown time-stepping scheme");
     if (op->error_state) fail(HGF_ESTATE, "operator is in an error state after a non-finite result");
     const int64_t m = check_steps(t_total_us, dt_us);
     hip_check(hipSetDevice(op->device), "hipSetDevice");
-    evolve_impl(op, m, dt_us, (hipStream_t)hip_stream);
+    evolve_impl(op, m, dt_us, (hipStream_t)hip_stream, scheme);
   });
 }
 

@@ -175,6 +175,11 @@ struct Function {
   int res_threads = 0;    // workgroup size of the resident kernel
   int res_lds_bytes = 0;  // its LDS (two padded copies of the grid)
   bool precision_fp64 = false;
+  // integrating-factor scheme: per-axis factors exp(lam_j(m) h/2) on the
+  // device (concatenated like lam), exp(lam0 h/2), and the h they are for
+  void* ehtab = nullptr;
+  cd eh0 = 0.0;
+  double eh_h = 0.0;
 };
 
 struct StepPlan;

@@ -33,6 +33,13 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
+// One stage of the integrating-factor RK4 step (stencil input `in`, state in
+// the stage precision `ye`, state y, its stage-precision copy yf, stage output
+// `vout`, the step's increment `delta`; eh: per-axis exp(lam_j(m) h/2), e0 =
+// exp(lam0 h/2)).
+void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const void* in, const void* ye, void* y,
+                   void* yf, void* vout, void* delta, const double2* eh, double2 e0, double h, int* flag,
+                   hipStream_t st);
 // form: 0 grouped kernel, 1 single-grid kernel, 2 single-grid pipelined kernel
 int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real,
                             int form);

@@ -241,6 +241,120 @@ __global__ __launch_bounds__(256) void k_rk4_stage(GridArgs g, StrideDigits sd, 
   }
 }
 
+// ------------------------------------------------------------ integrating-factor RK4
+//
+// The generator splits into its diagonal part D(m) = lam0 + sum_j lam_j(m_j)
+// (phases, damping, dephasing) and the jump stencil J (the alpha and beta
+// neighbour terms).  With E = exp(D h/2), classical RK4 applied to
+// u = exp(-D tau) y (whose derivative is exp(-D tau) J exp(D tau) u) gives,
+// written in terms of y,
+//   stage 1: j1 = J y;   v2 = E (y + h/2 j1);          delta  = h/6 E^2 j1
+//   stage 2: j2 = J v2;  v3 = E y + h/2 j2;            delta += h/3 E j2
+//   stage 3: j3 = J v3;  v4 = E^2 y + h E j3;          delta += h/3 E j3
+//   stage 4: j4 = J v4;  y  = E^2 y + delta + h/6 j4
+// The diagonal part is taken exactly: without jumps a step is y <- E^2 y for
+// any h.  v2, v3, v4 and the increment delta live in the stage precision; E,
+// E^2 and the state update are FP64.
+
+template <typename T>
+__device__ __forceinline__ double2 ld_c(const T* p, int64_t i);
+template <>
+__device__ __forceinline__ double2 ld_c<double2>(const double2* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ double2 ld_c<float2>(const float2* p, int64_t i) {
+  return make_double2(p[i].x, p[i].y);
+}
+template <>
+__device__ __forceinline__ double2 ld_c<double>(const double* p, int64_t i) { return make_double2(p[i], 0.0); }
+template <>
+__device__ __forceinline__ double2 ld_c<float>(const float* p, int64_t i) { return make_double2(p[i], 0.0); }
+__device__ __forceinline__ void st_c(double2* p, int64_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void st_c(float2* p, int64_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void st_c(double* p, int64_t i, double2 v) { p[i] = v.x; }
+__device__ __forceinline__ void st_c(float* p, int64_t i, double2 v) { p[i] = (float)v.x; }
+
+// (J in)(m) in precision R: the neighbour terms of the stencil
+template <typename R, typename TIN>
+__device__ __forceinline__ double2 apply_J(const GridArgs& g, const TIN* __restrict__ in, const Walker& w) {
+  const R* beta = beta_table<R>(g);
+  const R* alpha = alpha_table<R>(g);
+  R ar = 0, ai = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxModes; ++j) {
+    if (j < g.n) {
+      const int m = w.c[j];
+      // out-of-range neighbours read the centre with a zero coefficient
+      const double2 dn = ld_c(in, m >= 1 ? w.i - g.stride[j] : w.i);
+      const double2 upv = ld_c(in, m + 1 < g.ext[j] ? w.i + g.stride[j] : w.i);
+      const R a = alpha[g.off[j] + m];
+      const R b = beta[g.off[j] + m];
+      ar += a * (R)dn.x + b * (R)upv.x;
+      ai += a * (R)dn.y + b * (R)upv.y;
+    }
+  }
+  return make_double2(ar, ai);
+}
+
+// E(m) = exp(D(m) h/2) as e0 * prod_j eh[off_j + m_j]
+__device__ __forceinline__ double2 lawson_factor(const GridArgs& g, const double2* __restrict__ eh, double2 e0,
+                                                 const Walker& w) {
+  double2 e = e0;
+#pragma unroll
+  for (int j = 0; j < kMaxModes; ++j)
+    if (j < g.n) e = cmul(e, eh[g.off[j] + w.c[j]]);
+  return e;
+}
+
+template <int STAGE, typename R, typename TS, typename TY>
+__device__ __forceinline__ void lawson_body(const GridArgs& g, const StrideDigits& sd, const TS* __restrict__ in,
+                                            const TS* __restrict__ ye, TY* __restrict__ y, TS* __restrict__ yf,
+                                            TS* __restrict__ vout, TS* __restrict__ delta,
+                                            const double2* __restrict__ eh, double2 e0, double h,
+                                            int* __restrict__ flag) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  int bad = 0;
+  while (w.i < g.points) {
+    const double2 jv = apply_J<R>(g, in, w);
+    const double2 E = lawson_factor(g, eh, e0, w);
+    if (STAGE == 1) {
+      const double2 c = ld_c(in, w.i);
+      st_c(vout, w.i, cmul(E, cadd(c, cscale(0.5 * h, jv))));
+      st_c(delta, w.i, cscale(h / 6.0, cmul(cmul(E, E), jv)));
+    } else if (STAGE == 2 || STAGE == 3) {
+      const double2 yc = ld_c(ye, w.i);
+      const double2 Ej = cmul(E, jv);
+      if (STAGE == 2)
+        st_c(vout, w.i, cadd(cmul(E, yc), cscale(0.5 * h, jv)));
+      else
+        st_c(vout, w.i, cadd(cmul(cmul(E, E), yc), cscale(h, Ej)));
+      st_c(delta, w.i, cadd(ld_c(delta, w.i), cscale(h / 3.0, Ej)));
+    } else {
+      const double2 yn = cadd(cadd(cmul(cmul(E, E), ld_c(y, w.i)), ld_c(delta, w.i)), cscale(h / 6.0, jv));
+      bad |= !(isfinite(yn.x) && isfinite(yn.y));
+      st_c(y, w.i, yn);
+      if (yf) st_c(yf, w.i, yn);
+    }
+    walker_step(w, g, sd);
+  }
+  if (STAGE == 4 && bad) atomicOr(flag, 1);
+}
+
+template <typename TS, typename TY, typename RS>
+__global__ __launch_bounds__(256) void k_lawson_stage(GridArgs g, StrideDigits sd, int stage, const TS* in,
+                                                      const TS* ye, TY* y, TS* yf, TS* vout, TS* delta,
+                                                      const double2* __restrict__ eh, double2 e0, double h,
+                                                      int* __restrict__ flag) {
+  switch (stage) {
+    case 1: lawson_body<1, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+    case 2: lawson_body<2, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+    case 3: lawson_body<3, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+    default: lawson_body<4, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+  }
+}
+
 // ------------------------------------------------------------ stage-precision copy
 // The tiled RK4 stage kernel lives in hgf_tiled.h, the resident integrator in
 // hgf_resident.h.  yf = y in the stage precision (the stage-1 stencil input of
@@ -676,6 +790,31 @@ void launch_horner(int stage, int precision, const GridArgs& g, const void* in, 
   else
     hipLaunchKernelGGL((k_rk4_stage<float2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
                        (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
+}
+
+void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const void* in, const void* ye, void* y,
+                   void* yf, void* vout, void* delta, const double2* eh, double2 e0, double h, int* flag,
+                   hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  dim3 gr(ls.blocks), bl(ls.threads);
+  if (precision == HGF_FP64) {
+    if (real)
+      hipLaunchKernelGGL((k_lawson_stage<double, double, double>), gr, bl, 0, st, g, sd, stage, (const double*)in,
+                         (const double*)ye, (double*)y, (double*)yf, (double*)vout, (double*)delta, eh, e0, h, flag);
+    else
+      hipLaunchKernelGGL((k_lawson_stage<double2, double2, double>), gr, bl, 0, st, g, sd, stage,
+                         (const double2*)in, (const double2*)ye, (double2*)y, (double2*)yf, (double2*)vout,
+                         (double2*)delta, eh, e0, h, flag);
+  } else {
+    if (real)
+      hipLaunchKernelGGL((k_lawson_stage<float, double, float>), gr, bl, 0, st, g, sd, stage, (const float*)in,
+                         (const float*)ye, (double*)y, (float*)yf, (float*)vout, (float*)delta, eh, e0, h, flag);
+    else
+      hipLaunchKernelGGL((k_lawson_stage<float2, double2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
+                         (const float2*)ye, (double2*)y, (float2*)yf, (float2*)vout, (float2*)delta, eh, e0, h,
+                         flag);
+  }
 }
 
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st) {

@@ -317,8 +317,12 @@ def map_operator(system: System, factors=None, sparse=None, basis="number", prec
     return Operator(h, system)
 
 
-def evolve(op: Operator, t_total: float, dt: float, stream=None) -> None:
-    _check(_lib.hgf_evolve(op.handle, float(t_total), float(dt), 0, _stream(stream)))  # HGF_RK4
+SCHEMES = {"rk4": 0, "lawson": 1}  # HGF_RK4, HGF_LAWSON_RK4
+
+
+def evolve(op: Operator, t_total: float, dt: float, stream=None, scheme: str = "rk4") -> None:
+    """hgf_evolve with scheme "rk4" (classical RK4) or "lawson" (integrating-factor RK4)."""
+    _check(_lib.hgf_evolve(op.handle, float(t_total), float(dt), SCHEMES[scheme], _stream(stream)))
 
 
 def clear_error(op: Operator) -> None:

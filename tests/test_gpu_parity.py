@@ -337,7 +337,7 @@ def test_error_paths(hgf):
     S = hgf.define_system(s)
     op = hgf.map_operator(S, factors=[np.eye(3)])
     from paper_2203_05526_amd import hgf as mod
-    assert mod._lib.hgf_evolve(op.handle, 0.1, 0.01, 1, None) == -6  # only HGF_RK4
+    assert mod._lib.hgf_evolve(op.handle, 0.1, 0.01, 7, None) == -6  # unknown scheme
     assert op.info()["steps_done"] == 0
     with pytest.raises(hgf.HgfError) as e:
         hgf.evolve(op, 0.15, 0.1)
