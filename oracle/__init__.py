@@ -61,6 +61,8 @@ def _load():
                                             ctypes.c_double, ctypes.c_int]
     lib.oracle_evolve_sens.argtypes = sysargs + [ctypes.c_int, ip, vp, vp, ctypes.c_long,
                                                  ctypes.c_double, ctypes.c_int]
+    lib.oracle_rhs_full.argtypes = sysargs + [dp, dp, vp, vp, ctypes.c_int]
+    lib.oracle_evolve_full.argtypes = sysargs + [dp, dp, vp, ctypes.c_long, ctypes.c_double, ctypes.c_int]
     lib.oracle_num_params.argtypes = [ctypes.c_int]
     lib.oracle_max_threads.argtypes = []
     _lib = lib
@@ -90,6 +92,58 @@ def _sysargs(system):
     return args, keep
 
 
+def _network_args(system, keep):
+    """Drive (2N doubles, re/im) and exchange (N*N) pointers, or NULL."""
+    out = []
+    for x, dt in ((getattr(system, "drive", None), np.complex128), (getattr(system, "exchange", None), np.float64)):
+        if x is None:
+            out.append(None)
+            continue
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt).reshape(-1))
+        if dt == np.complex128:
+            a = a.view(np.float64)
+        keep.append(a)
+        out.append(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def is_network(system) -> bool:
+    """True when drive or exchange is present: the sectors are coupled and
+    only the full-matrix functions apply."""
+    d, x = getattr(system, "drive", None), getattr(system, "exchange", None)
+    return (d is not None and np.any(np.asarray(d) != 0)) or (x is not None and np.any(np.asarray(x) != 0))
+
+
+def _require_sectors(system):
+    if is_network(system):
+        raise ValueError("drive and exchange couple the sectors: use the full-matrix functions")
+
+
+def rhs_full(system, A: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """One evaluation of the right-hand side of Eq. (3) on the full matrix A,
+    with the network Hamiltonian of Eq. (16) (drive, exchange)."""
+    lib = _load()
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    out = np.zeros_like(A)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_rhs_full(*args, *_network_args(system, keep), A.ctypes.data, out.ctypes.data, nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_rhs_full failed ({rc})")
+    return out
+
+
+def evolve_full(system, A: np.ndarray, t_total: float, dt: float, nthreads: int = 0) -> np.ndarray:
+    """A(T) from the full matrix A(0) by classical RK4 with step dt."""
+    lib = _load()
+    A = np.array(A, dtype=np.complex128, order="C")
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve_full(*args, *_network_args(system, keep), A.ctypes.data, n_steps(t_total, dt),
+                                float(dt), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve_full failed ({rc})")
+    return A
+
+
 def _pack(system, ops: Sectors):
     keys = sorted(ops.keys())
     n = system.n_modes
@@ -106,6 +160,7 @@ def num_params(n: int) -> int:
 
 def rhs(system, ops: Sectors, nthreads: int = 0) -> Sectors:
     """One evaluation of the right-hand side of Eq. (3) on every sector."""
+    _require_sectors(system)
     lib = _load()
     keys, d, A = _pack(system, ops)
     out = np.zeros_like(A)
@@ -127,6 +182,7 @@ def n_steps(t_total: float, dt: float) -> int:
 def evolve(system, ops: Sectors, t_total: float, dt: float, nthreads: int = 0) -> Sectors:
     """A(T) from A(0) by classical RK4 with step dt (same scheme as the paper's
     fourth-order Runge-Kutta integration)."""
+    _require_sectors(system)
     lib = _load()
     keys, d, A = _pack(system, ops)
     args, keep = _sysargs(system)

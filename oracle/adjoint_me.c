@@ -38,6 +38,13 @@
  * of mode j), and the anticommutator damps A[k,l] by half the total rate out of
  * level k_j plus that out of level l_j.  Pure dephasing keeps its Lindblad form.
  *
+ * Full-matrix form (the driven, exchange-coupled network of Eq. (16)): a drive
+ * Omega_j a_j^+ + conj(Omega_j) a_j per mode (static in the frame rotating at
+ * the drive frequency) and exchange J_ij (a_i^+ a_j + a_j^+ a_i) couple the
+ * difference sectors, so these systems are held as one dense matrix A[k, l]
+ * (row and column indices row-major over the modes, last mode fastest) and
+ * the commutator with the added terms is written out element by element.
+ *
  * Parameter order for sensitivities: K[N], chi[i<j lexicographic], Delta[N],
  * gamma1[N], gamma_phi[N].
  */
@@ -62,6 +69,8 @@ typedef struct {
   double g1[OMAXN], gphi[OMAXN], nth[OMAXN];
   int secular;               /* 0: Lindblad channels a, a^+; 1: secular transitions */
   double nlev[OMAXN][OMAXC]; /* secular: bath occupation of transition n <-> n+1 of mode j */
+  cplx drive[OMAXN];         /* full-matrix form only: H += Omega_j a_j^+ + conj(Omega_j) a_j */
+  double exch[OMAXN * OMAXN];/* full-matrix form only: H += sum_{i<j} J_ij (a_i^+ a_j + a_j^+ a_i) */
 } osys;
 
 /* diss: 0 Lindblad, 1 secular; nlev (secular, may be NULL): per mode j the
@@ -355,6 +364,144 @@ int oracle_evolve_lawson(int n, const int *nc, const double *det, const double *
     for (long i = 0; i < len; ++i) A[i] = cexp(D[i] * h) * acc[i];
   }
   free(D); free(kk); free(Y); free(acc); free(tmp);
+  return 0;
+}
+
+/*
+ * Right-hand side on the full matrix.  Element (k, l), with K and L the row
+ * and column indices and s_j the index stride of mode j:
+ *   i (E_k - E_l) A[k,l] + dissipator terms (as in rhs_sector, with the
+ *   neighbours A[k -+ e_j, l -+ e_j] taken from the full matrix)
+ *   + i (Omega_j (a^+A) + conj(Omega_j) (aA) - Omega_j (Aa^+) - conj(Omega_j) (Aa))[k,l]
+ *   + i J_ij ((a_i^+ a_j A) + (a_j^+ a_i A) - (A a_i^+ a_j) - (A a_j^+ a_i))[k,l]
+ * with the truncated matrix elements
+ *   (a_j^+ A)[k,l] = sqrt(k_j) A[k-e_j, l]        (a_j A)[k,l] = sqrt(k_j+1) A[k+e_j, l]
+ *   (A a_j^+)[k,l] = sqrt(l_j+1) A[k, l+e_j]      (A a_j)[k,l] = sqrt(l_j) A[k, l-e_j]
+ *   (a_i^+ a_j A)[k,l] = sqrt(k_i (k_j+1)) A[k-e_i+e_j, l]
+ *   (A a_i^+ a_j)[k,l] = sqrt(l_j (l_i+1)) A[k, l-e_j+e_i]
+ * (zero where an index leaves [0, Nc)).
+ */
+static void rhs_full(const osys *s, const cplx *A, cplx *out) {
+  const int n = s->n;
+  const long dim = box_size(s);
+  long stride[OMAXN];
+  stride[n - 1] = 1;
+  for (int j = n - 2; j >= 0; --j) stride[j] = stride[j + 1] * s->nc[j + 1];
+
+#pragma omp parallel for schedule(static)
+  for (long f = 0; f < dim * dim; ++f) {
+    const long K = f / dim, L = f % dim;
+    int k[OMAXN], l[OMAXN];
+    long rk = K, rl = L;
+    for (int j = 0; j < n; ++j) {
+      k[j] = (int)(rk / stride[j]);
+      rk %= stride[j];
+      l[j] = (int)(rl / stride[j]);
+      rl %= stride[j];
+    }
+#define AT(KK, LL) A[(KK) * dim + (LL)]
+    const cplx a = A[f];
+    cplx r = I * (energy(s, k) - energy(s, l)) * a;
+    for (int j = 0; j < n; ++j) {
+      const int nc = s->nc[j];
+      const int kj = k[j], lj = l[j];
+      const long sj = stride[j];
+      if (s->secular) {
+        const double *nb = s->nlev[j];
+        const double g = s->g1[j];
+        if (kj == lj) {
+          if (kj >= 1) r += g * kj * (nb[kj - 1] + 1.0) * AT(K - sj, L - sj);
+          if (kj + 1 < nc) r += g * (kj + 1) * nb[kj] * AT(K + sj, L + sj);
+        }
+        double out_k = 0.0, out_l = 0.0;
+        if (kj >= 1) out_k += g * kj * (nb[kj - 1] + 1.0);
+        if (kj + 1 < nc) out_k += g * (kj + 1) * nb[kj];
+        if (lj >= 1) out_l += g * lj * (nb[lj - 1] + 1.0);
+        if (lj + 1 < nc) out_l += g * (lj + 1) * nb[lj];
+        r -= 0.5 * (out_k + out_l) * a;
+      } else {
+        const double kd = s->g1[j] * (1.0 + s->nth[j]), ku = s->g1[j] * s->nth[j];
+        if (kj >= 1 && lj >= 1) r += kd * sqrt((double)kj * lj) * AT(K - sj, L - sj);
+        r -= 0.5 * kd * (kj + lj) * a;
+        if (kj + 1 < nc && lj + 1 < nc) r += ku * sqrt((double)(kj + 1) * (lj + 1)) * AT(K + sj, L + sj);
+        const double tk = (kj + 1 < nc) ? kj + 1 : 0, tl = (lj + 1 < nc) ? lj + 1 : 0;
+        r -= 0.5 * ku * (tk + tl) * a;
+      }
+      /* dephasing, L = n_j at rate 2 gamma_phi: gamma_phi (2 k l - k^2 - l^2) */
+      r += s->gphi[j] * (2.0 * kj * lj - (double)kj * kj - (double)lj * lj) * a;
+      /* drive */
+      const cplx om = s->drive[j];
+      if (om != 0.0) {
+        cplx c = 0.0;
+        if (kj >= 1) c += om * sqrt((double)kj) * AT(K - sj, L);
+        if (kj + 1 < nc) c += conj(om) * sqrt((double)(kj + 1)) * AT(K + sj, L);
+        if (lj + 1 < nc) c -= om * sqrt((double)(lj + 1)) * AT(K, L + sj);
+        if (lj >= 1) c -= conj(om) * sqrt((double)lj) * AT(K, L - sj);
+        r += I * c;
+      }
+    }
+    /* exchange */
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        const double J = s->exch[i * n + j];
+        if (J == 0.0) continue;
+        const long si = stride[i], sj = stride[j];
+        const int nci = s->nc[i], ncj = s->nc[j];
+        cplx c = 0.0;
+        if (k[i] >= 1 && k[j] + 1 < ncj) c += sqrt((double)k[i] * (k[j] + 1)) * AT(K - si + sj, L);
+        if (k[j] >= 1 && k[i] + 1 < nci) c += sqrt((double)k[j] * (k[i] + 1)) * AT(K - sj + si, L);
+        if (l[j] >= 1 && l[i] + 1 < nci) c -= sqrt((double)l[j] * (l[i] + 1)) * AT(K, L - sj + si);
+        if (l[i] >= 1 && l[j] + 1 < ncj) c -= sqrt((double)l[i] * (l[j] + 1)) * AT(K, L - si + sj);
+        r += I * J * c;
+      }
+#undef AT
+    out[f] = r;
+  }
+}
+
+static int load_full(osys *s, const double *drive, const double *exch) {
+  for (int j = 0; j < s->n; ++j) s->drive[j] = drive ? drive[2 * j] + I * drive[2 * j + 1] : 0.0;
+  for (int i = 0; i < s->n * s->n; ++i) s->exch[i] = exch ? exch[i] : 0.0;
+  return 0;
+}
+
+int oracle_rhs_full(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+                    const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+                    const double *drive, const double *exch, const cplx *A, cplx *out, int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev) || load_full(&s, drive, exch)) return -1;
+  set_threads(nthreads);
+  rhs_full(&s, A, out);
+  return 0;
+}
+
+/* Classical RK4 on the full matrix (stages as in oracle_evolve). */
+int oracle_evolve_full(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+                       const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+                       const double *drive, const double *exch, cplx *A, long nsteps, double h, int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev) || load_full(&s, drive, exch)) return -1;
+  set_threads(nthreads);
+  const long dim = box_size(&s), len = dim * dim;
+  cplx *kk = malloc(sizeof(cplx) * len), *Y = malloc(sizeof(cplx) * len), *acc = malloc(sizeof(cplx) * len);
+  if (!kk || !Y || !acc) {
+    free(kk); free(Y); free(acc);
+    return -2;
+  }
+  for (long step = 0; step < nsteps; ++step) {
+    rhs_full(&s, A, kk);
+    axpy_into(len, acc, A, h / 6.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    rhs_full(&s, Y, kk);
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h / 2.0, kk);
+    rhs_full(&s, Y, kk);
+    axpy_into(len, acc, acc, h / 3.0, kk);
+    axpy_into(len, Y, A, h, kk);
+    rhs_full(&s, Y, kk);
+    axpy_into(len, A, acc, h / 6.0, kk);
+  }
+  free(kk); free(Y); free(acc);
   return 0;
 }
 

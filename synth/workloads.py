@@ -45,6 +45,11 @@ class System:
     # occupation of every transition, sum_j (cutoff_j - 1) values, modes in order
     dissipator: str = "lindblad"
     n_th_levels: Optional[np.ndarray] = None
+    # driven, exchange-coupled network (optional): complex drive amplitudes
+    # Omega_j (H += Omega_j a_j^+ + conj(Omega_j) a_j, static in the drive
+    # frame) and a symmetric exchange matrix J (H += sum_{i<j} J_ij (a_i^+ a_j + h.c.))
+    drive: Optional[np.ndarray] = None
+    exchange: Optional[np.ndarray] = None
 
     @property
     def n_modes(self) -> int:
@@ -54,7 +59,9 @@ class System:
         return System(tuple(self.cutoff), self.detuning.copy(), self.kerr.copy(),
                       self.cross_kerr.copy(), self.gamma1.copy(),
                       self.gamma_phi.copy(), self.n_th.copy(), self.dissipator,
-                      None if self.n_th_levels is None else self.n_th_levels.copy())
+                      None if self.n_th_levels is None else self.n_th_levels.copy(),
+                      None if self.drive is None else self.drive.copy(),
+                      None if self.exchange is None else self.exchange.copy())
 
 
 @dataclass

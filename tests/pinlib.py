@@ -31,11 +31,17 @@ def hamiltonian(system) -> np.ndarray:
     dim = int(np.prod(cutoff))
     H = np.zeros((dim, dim), dtype=np.complex128)
     a = [embed(ladder(nc), j, cutoff) for j, nc in enumerate(cutoff)]
+    drive = getattr(system, "drive", None)
+    exch = getattr(system, "exchange", None)
     for j in range(system.n_modes):
         ad = a[j].conj().T
         H += system.detuning[j] * ad @ a[j] + 0.5 * system.kerr[j] * ad @ ad @ a[j] @ a[j]
         for i in range(j):
             H += system.cross_kerr[i, j] * (a[i].conj().T @ a[i]) @ (ad @ a[j])
+            if exch is not None:
+                H += exch[i, j] * (a[i].conj().T @ a[j] + ad @ a[i])
+        if drive is not None:
+            H += drive[j] * ad + np.conj(drive[j]) * a[j]
     return H
 
 

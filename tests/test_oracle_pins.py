@@ -428,3 +428,52 @@ def test_lawson_converges_to_expm_at_fourth_order(oracle_lib, dissipator):
     assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0
     rk = oracle.dense_from_sectors(cutoff, oracle.evolve(s, ops, T, 0.002))
     assert not np.all(np.isfinite(rk)) or pinlib.rel(rk, ref) > 1.0
+
+
+# --------------------------------------------------------------- driven, exchange-coupled network (full matrix)
+
+def network(seed, cutoff, dissipator="lindblad"):
+    rng = np.random.default_rng(seed)
+    s = small_system(seed, cutoff, scale=2.0, n_th=0.2)
+    n = len(cutoff)
+    s.drive = rng.normal(size=n) * 3.0 + 1j * rng.normal(size=n) * 3.0
+    J = np.zeros((n, n))
+    for i in range(n - 1):
+        J[i, i + 1] = J[i + 1, i] = rng.uniform(1.0, 4.0)
+    s.exchange = J
+    if dissipator == "secular":
+        s = with_secular(s, rng)
+    return s
+
+
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+@pytest.mark.parametrize("cutoff,seed", [((3, 4), 130), ((2, 3, 2), 131), ((6,), 132)])
+def test_network_against_dense_superoperator_expm(oracle_lib, cutoff, seed, dissipator):
+    """Drive Omega_j a_j^+ + h.c. and exchange J_ij (a_i^+ a_j + h.c.) (Eq. (16)
+    in the drive frame): the oracle's element-wise full-matrix right-hand side,
+    integrated with RK4, equals exp(S T) of the Kronecker superoperator."""
+    s = network(seed, cutoff, dissipator)
+    dim = int(np.prod(cutoff))
+    rng = np.random.default_rng(seed)
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    T, dt = 0.3, 1.25e-4
+    got = oracle.evolve_full(s, A0, T, dt)
+    assert pinlib.rel(got, pinlib.expm_evolve(s, A0, T)) < 1e-10  # RK4 error <= 5e-12 at this step
+    # one right-hand side against the superoperator itself
+    assert pinlib.rel(oracle.rhs_full(s, A0), (pinlib.adjoint_superop(s) @ A0.reshape(-1)).reshape(A0.shape)) < 1e-13
+
+
+def test_network_identity_stationary_and_hermiticity(oracle_lib):
+    """Eq. (3) with the network Hamiltonian: L^+(I) = 0 and A = A^+ stays
+    Hermitian; the sector oracle refuses coupled sectors."""
+    cutoff = (3, 3, 2)
+    s = network(133, cutoff)
+    dim = 18
+    assert np.max(np.abs(oracle.rhs_full(s, np.eye(dim)))) < 1e-12
+    rng = np.random.default_rng(133)
+    M = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    M = M + M.conj().T
+    out = oracle.evolve_full(s, M, 0.2, 1e-3)
+    assert np.max(np.abs(out - out.conj().T)) < 1e-12 * np.max(np.abs(out))
+    with pytest.raises(ValueError):
+        oracle.evolve(s, oracle.sectors_from_dense(cutoff, M), 0.1, 1e-3)
