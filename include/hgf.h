@@ -104,6 +104,17 @@ typedef struct {
   const double* n_th_levels; /* SECULAR only, may be NULL: bath occupation of every
                                 transition n <-> n+1, sum_j (Nc_j - 1) values, modes in
                                 order (NULL: n_th_j for every transition of mode j) */
+  /* The driven, exchange-coupled network of Eq. (16), in the frame rotating at
+   * the drive frequency (a drive on resonance is static there; Delta_j is the
+   * mode's detuning from the drive).  Either may be NULL (none).  When any
+   * entry is non-zero the sectors are coupled: every operator is then one
+   * function on the full (k, l) grid (2N axes, at most 8 modes and 2^28
+   * points), merged layout and HGF_RK4 only, and hgf_grad and
+   * hgf_get_function return HGF_EUNSUPPORTED (read it with hgf_reconstruct). */
+  const double* drive;      /* [2N] complex Omega_j (re, im), rad/us:
+                               H += Omega_j a_j^+ + conj(Omega_j) a_j */
+  const double* exchange;   /* [N*N] J_ij, rad/us, symmetric, diagonal ignored:
+                               H += sum_{i<j} J_ij (a_i^+ a_j + a_j^+ a_i) */
 } hgf_system_desc;
 
 /* dissipators (per mode; dephasing is the Lindblad channel n at rate 2 gamma_phi in both) */

@@ -175,7 +175,9 @@ static void check_stability(const std::vector<Function>& fns, double dt, bool ju
   // non-positive real part) must fit in it.
   for (const auto& f : fns) {
     double b = 0.0;
-    if (jumps_only) {
+    if (f.full) {
+      b = f.full_bound;
+    } else if (jumps_only) {
       for (int j = 0; j < f.tab.n; ++j) {
         double mx = 0.0;
         for (int m = 0; m < f.tab.ext[j]; ++m) mx = std::max(mx, f.tab.alpha[j][m] + f.tab.beta[j][m]);
@@ -461,7 +463,7 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
-  if (!stage_kernel_generic()) configure_tiles(g, precision, want_real, TileChoice{});
+  if (!stage_kernel_generic() && !f.full) configure_tiles(g, precision, want_real, TileChoice{});
   f.real = g.real != 0;
   // device tables, one block: lam (double2), beta, alpha (double), lam_f
   // (float2), beta_f, alpha_f (float), each concatenated over the axes
@@ -499,6 +501,7 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   g.beta_f = (const float*)(base + o_betaf);
   g.alpha_f = (const float*)(base + o_alphaf);
   g.tiles = nullptr;
+  g.full = (const FullTables*)f.ftab;
   if (g.blocks > 0) build_tile_records(f, precision);
   f.resident = resident_eligible(f);
   const char* env = std::getenv("HGF_RESIDENT");
@@ -530,6 +533,7 @@ static void free_function(Function& f) {
   dfree(f.dtab);
   dfree(f.ttab);
   dfree(f.ehtab);
+  dfree(f.ftab);
 }
 
 static int64_t flat_index(const SectorTables& t, const int* m) {
@@ -828,7 +832,138 @@ static void setup_split(Function& f, const System& s, const Coeff& c) {
   }
 }
 
+// Largest full (k, l) grid of a network operator, in points.
+constexpr int64_t kMaxFullPoints = (int64_t)1 << 28;
+
+// Generator tables of a network operator's full grid (see FullTables).
+static FullTables full_tables(const System& s) {
+  FullTables ft{};
+  ft.n = s.n;
+  ft.secular = s.secular;
+  for (int j = 0; j < s.n; ++j) {
+    const int nc = s.nc[j];
+    ft.nc[j] = nc;
+    ft.gphi[j] = s.gphi[j];
+    ft.drive_re[j] = s.drive_re[j];
+    ft.drive_im[j] = s.drive_im[j];
+    for (int i = 0; i < s.n; ++i) {
+      ft.chi[i][j] = s.chi[i][j];
+      ft.exch[i][j] = s.exch[i][j];
+    }
+    const double g = s.g1[j];
+    for (int k = 0; k < nc; ++k) {
+      ft.e[j][k] = s.det[j] * k + 0.5 * s.kerr[j] * k * (k - 1);
+      if (s.secular) {
+        const double* nb = s.nlev[j];
+        double out = 0.0;
+        if (k >= 1) out += g * k * (nb[k - 1] + 1.0);
+        if (k + 1 < nc) out += g * (k + 1) * nb[k];
+        ft.dk[j][k] = -0.5 * out;
+        ft.adn[j][k] = k >= 1 ? g * (nb[k - 1] + 1.0) : 0.0;
+        ft.aup[j][k] = k + 1 < nc ? g * nb[k] * (double)(k + 1) * (double)(k + 1) : 0.0;
+      } else {
+        const double kt = (k + 1 < nc) ? k + 1 : 0;
+        ft.dk[j][k] = -0.5 * (g * (1.0 + s.nth[j]) * k + g * s.nth[j] * kt);
+        ft.adn[j][k] = g * (1.0 + s.nth[j]);
+        ft.aup[j][k] = g * s.nth[j];
+      }
+    }
+  }
+  return ft;
+}
+
+// Gershgorin-type bound on the generator of a network operator's full grid:
+// the largest diagonal entry plus every neighbour coefficient at its largest.
+static double full_generator_bound(const FullTables& ft) {
+  double emax = 0.0, dmax = 0.0, b = 0.0;
+  for (int j = 0; j < ft.n; ++j) {
+    const int nc = ft.nc[j];
+    double ej = 0.0, dj = 0.0, a = 0.0, u = 0.0;
+    for (int k = 0; k < nc; ++k) {
+      ej = std::max(ej, std::abs(ft.e[j][k]));
+      dj = std::max(dj, std::abs(ft.dk[j][k]));
+      a = std::max(a, ft.adn[j][k]);
+      u = std::max(u, ft.secular ? ft.aup[j][k] : ft.aup[j][k] * nc * nc);
+    }
+    emax += ej;
+    dmax += 2.0 * dj + ft.gphi[j] * (nc - 1) * (nc - 1);
+    for (int i = 0; i < j; ++i) emax += std::abs(ft.chi[i][j]) * (ft.nc[i] - 1) * (nc - 1);
+    b += a + u + std::hypot(ft.drive_re[j], ft.drive_im[j]) * 2.0 * (nc + 1);
+    for (int i = 0; i < j; ++i) b += std::abs(ft.exch[i][j]) * 2.0 * (ft.nc[i] + nc);
+  }
+  return 2.0 * emax + dmax + b;
+}
+
+// A network operator: every sector of the input scattered into one full
+// (k, l) grid, g(k, l) = <k|A|l> / sqrt(k! l!).
+static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) {
+  if (op->layout != HGF_MERGED) fail(HGF_EUNSUPPORTED, "a driven or exchange-coupled system needs the merged layout");
+  const System& s = op->sys;
+  const int n = s.n;
+  int64_t dim = 1;
+  for (int j = 0; j < n; ++j) dim *= s.nc[j];
+  if (dim * dim > kMaxFullPoints) fail(HGF_EINVAL, "full (k, l) grid of the network exceeds 2^28 points");
+  std::map<std::vector<int>, std::vector<cd>> merged;
+  std::vector<Coeff> coeffs;
+  collect_coeffs(s, d, merged, coeffs, false);
+  std::vector<cd> grid((size_t)(dim * dim), 0.0);
+  bool any = false;
+  for (auto& kv : merged) {
+    const std::vector<int>& dv = kv.first;
+    int u[kMaxModes], v[kMaxModes], e[kMaxModes];
+    for (int j = 0; j < n; ++j) {
+      u[j] = dv[j] < 0 ? -dv[j] : 0;
+      v[j] = dv[j] > 0 ? dv[j] : 0;
+      e[j] = s.nc[j] - std::abs(dv[j]);
+    }
+    std::vector<int> m(n, 0);
+    for (size_t p = 0; p < kv.second.size(); ++p) {
+      cd val = kv.second[p];
+      if (std::abs(val) <= d->drop_tol) val = 0.0;
+      if (val != 0.0) {
+        any = true;
+        if (std::abs(val) < FLT_MIN) op->underflow++;
+        int64_t K = 0, L = 0;
+        for (int j = 0; j < n; ++j) {
+          K = K * s.nc[j] + m[j] + u[j];
+          L = L * s.nc[j] + m[j] + v[j];
+        }
+        grid[(size_t)(K * dim + L)] = val;
+      }
+      for (int j = n - 1; j >= 0; --j) {
+        if (++m[j] < e[j]) break;
+        m[j] = 0;
+      }
+    }
+  }
+  if (!any) return;  // the zero operator
+  op->fn.emplace_back();
+  Function& f = op->fn.back();
+  f.full = true;
+  SectorTables& t = f.tab;
+  t.n = 2 * n;
+  t.lam0 = 0.0;
+  for (int a = 0; a < 2 * n; ++a) {
+    t.d[a] = t.u[a] = t.v[a] = 0;
+    t.ext[a] = s.nc[a % n];
+    t.lam[a].assign(t.ext[a], cd(0.0));
+    t.alpha[a].assign(t.ext[a], 0.0);
+    t.beta[a].assign(t.ext[a], 0.0);
+  }
+  const FullTables ft = full_tables(s);
+  f.full_bound = full_generator_bound(ft);
+  f.ftab = dmalloc(sizeof(FullTables));
+  hip_check(hipMemcpy(f.ftab, &ft, sizeof(FullTables), hipMemcpyHostToDevice), "upload tables");
+  fill_grid_args(f, op->precision, false);
+  alloc_function_buffers(f, op->precision);
+  upload_state(f, grid, op->precision);
+}
+
 static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d, bool allow_real = true) {
+  if (op->sys.full) {
+    build_full_function(op, d);
+    return;
+  }
   std::map<std::vector<int>, std::vector<cd>> merged;
   std::vector<Coeff> coeffs;
   const bool split = op->layout == HGF_SPLIT;
@@ -1059,8 +1194,9 @@ static void generic_stage(const PlanItem& it, int s, int* flag, hipStream_t st) 
   Function& f = *it.f;
   const void* in[4] = {it.precision == HGF_MIXED ? f.yf : f.y, f.s1, f.s2, f.s3};
   void* out[4] = {f.s1, f.s2, f.s3, nullptr};
-  launch_horner(s, it.precision, f.ga, in[s - 1], f.s1, f.y, it.precision == HGF_MIXED ? f.yf : nullptr, out[s - 1],
-                it.h, flag, st);
+  (f.full ? launch_full_horner : launch_horner)(s, it.precision, f.ga, in[s - 1], f.s1, f.y,
+                                                it.precision == HGF_MIXED ? f.yf : nullptr, out[s - 1], it.h, flag,
+                                                st);
 }
 
 static void run_plan_step(const StepPlan& plan, int* flag, hipStream_t st) {
@@ -1232,6 +1368,8 @@ static int read_flag(hgf_operator_s* op, hipStream_t st) {
 static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, int scheme = HGF_RK4) {
   if (scheme == HGF_LAWSON_RK4 && op->layout != HGF_MERGED)
     fail(HGF_EUNSUPPORTED, "the integrating-factor scheme runs on merged-layout operators only");
+  if (scheme == HGF_LAWSON_RK4 && op->sys.full)
+    fail(HGF_EUNSUPPORTED, "the integrating-factor scheme needs uncoupled sectors (no drive or exchange)");
   if (steps == 0) return;
   if (op->fn.empty()) {  // the zero operator stays zero
     op->steps_done += steps;
@@ -1379,6 +1517,10 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
 // Re-configure one function's stage kernel; the function is left unchanged
 // when the shape is not feasible (HGF_EINVAL).
 static void retile(Function& f, int precision, const TileChoice& c) {
+  if (f.full) {
+    if (c.nfast == 0) return;
+    fail(HGF_EINVAL, "a network operator's full grid runs the untiled stage kernel only");
+  }
   if (f.split) {
     if (c.nfast == 0) return;
     fail(HGF_EUNSUPPORTED, "split-layout functions run the classical stage kernel only");
@@ -1845,15 +1987,25 @@ static void validate_state(const System& s, const hgf_state_desc* psi) {
   }
 }
 
-// per-axis weights w_j(m) = sqrt(k! l!) conj(c_k) c_l of one sector, concatenated
-static std::vector<cd> sector_weights(const System& s, const SectorTables& t, const std::vector<std::vector<cd>>& amps) {
+// per-axis weights w_j(m) = sqrt(k! l!) conj(c_k) c_l of one sector, concatenated;
+// on a network operator's full grid the k axes take sqrt(k!) conj(c_k) and the
+// l axes sqrt(l!) c_l (the weight of <k|A|l> factorises over them)
+static std::vector<cd> sector_weights(const System& s, const Function& f, const std::vector<std::vector<cd>>& amps) {
+  const SectorTables& t = f.tab;
   std::vector<cd> w;
+  if (f.full) {
+    for (int a = 0; a < t.n; ++a) {
+      const int j = a % s.n;
+      for (int m = 0; m < t.ext[a]; ++m)
+        w.push_back(a < s.n ? sqrt_factorial(m) * std::conj(amps[j][m]) : sqrt_factorial(m) * amps[j][m]);
+    }
+    return w;
+  }
   for (int j = 0; j < t.n; ++j)
     for (int m = 0; m < t.ext[j]; ++m) {
       const int k = m + t.u[j], l = m + t.v[j];
       w.push_back(sqrt_factorial(k) * sqrt_factorial(l) * std::conj(amps[j][k]) * amps[j][l]);
     }
-  (void)s;
   return w;
 }
 
@@ -1878,7 +2030,7 @@ static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStr
   cd analytic = 0.0;
   for (int i = 0; i < nf; ++i) {
     Function& f = op->fn[i];
-    const auto w = sector_weights(op->sys, f.tab, amps);
+    const auto w = sector_weights(op->sys, f, amps);
     woff[i] = (int)wall.size();
     wall.insert(wall.end(), w.begin(), w.end());
     start[i + 1] = start[i] + expect_blocks(f.ga);
@@ -1933,16 +2085,32 @@ static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStr
     b.total = 1;
     b.pq = -1;
     b.coef = make_double2(1.0, 0.0);
-    int64_t place = ln;
-    for (int j = 0; j < n; ++j) {
-      place /= levels;
-      b.lp[j] = place;
-      b.u[j] = f.tab.u[j];
-      b.v[j] = f.tab.v[j];
-      b.b[j] = std::max(0, levels - std::max(b.u[j], b.v[j]));
-      b.foff[j] = (int)fac.size();
-      for (int m = 0; m < b.b[j]; ++m) fac.push_back(sqrt_factorial(m + b.u[j]) * sqrt_factorial(m + b.v[j]));
-      b.total *= b.b[j];
+    std::vector<int64_t> place(n);
+    {
+      int64_t p = ln;
+      for (int j = 0; j < n; ++j) place[j] = p /= levels;
+    }
+    if (f.full) {  // axes k_0 .. k_{N-1}, l_0 .. l_{N-1}
+      for (int a = 0; a < 2 * n; ++a) {
+        const int j = a % n;
+        b.rp[a] = a < n ? place[j] : 0;
+        b.cp[a] = a < n ? 0 : place[j];
+        b.ur[a] = b.uc[a] = 0;
+        b.b[a] = levels;
+        b.foff[a] = (int)fac.size();
+        for (int m = 0; m < levels; ++m) fac.push_back(sqrt_factorial(m));
+        b.total *= levels;
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        b.rp[j] = b.cp[j] = place[j];
+        b.ur[j] = f.tab.u[j];
+        b.uc[j] = f.tab.v[j];
+        b.b[j] = std::max(0, levels - std::max(b.ur[j], b.uc[j]));
+        b.foff[j] = (int)fac.size();
+        for (int m = 0; m < b.b[j]; ++m) fac.push_back(sqrt_factorial(m + b.ur[j]) * sqrt_factorial(m + b.uc[j]));
+        b.total *= b.b[j];
+      }
     }
     if (b.total == 0) continue;
     if (f.split) {  // G = g0 (c_x c_y x^p y^q + R): the separable part sits at m = min(p, q)
@@ -1990,6 +2158,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
                       double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
   const int64_t M = check_steps(T, dt);
   if (ce < 1) fail(HGF_EINVAL, "checkpoint_every must be >= 1");
+  if (sys.full) fail(HGF_EUNSUPPORTED, "gradients need uncoupled sectors (no drive or exchange)");
   validate_state(sys, psi);
   hgf_operator_s op;
   op.sys = sys;
@@ -2028,7 +2197,7 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     const int64_t nseg = (M + ce - 1) / ce;
     DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)std::min<int64_t>(ce, std::max<int64_t>(M, 1)) * gb),
         mu(gb), vb2(gb), vb1(gb), xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
-    const auto w = sector_weights(sys, f.tab, amps);
+    const auto w = sector_weights(sys, f, amps);
     DBuf dw(w.size() * sizeof(double2));
     hip_check(hipMemcpyAsync(dw.p, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
     launch_fill_weights(f.ga, dw.as<double2>(), wt.as<double2>(), st);
@@ -2197,6 +2366,21 @@ static System system_from_desc(const hgf_system_desc* d) {
     }
     off += s.nc[j] - 1;
   }
+  for (int j = 0; j < n; ++j) {
+    s.drive_re[j] = d->drive ? d->drive[2 * j] : 0.0;
+    s.drive_im[j] = d->drive ? d->drive[2 * j + 1] : 0.0;
+    if (!std::isfinite(s.drive_re[j]) || !std::isfinite(s.drive_im[j])) fail(HGF_EINVAL, "non-finite drive");
+    if (s.drive_re[j] != 0.0 || s.drive_im[j] != 0.0) s.full = 1;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double a = d->exchange ? d->exchange[i * n + j] : 0.0, b = d->exchange ? d->exchange[j * n + i] : 0.0;
+      if (!std::isfinite(a)) fail(HGF_EINVAL, "non-finite exchange");
+      if (i != j && a != b) fail(HGF_EINVAL, "exchange must be symmetric");
+      s.exch[i][j] = (i == j) ? 0.0 : a;
+      if (s.exch[i][j] != 0.0) s.full = 1;
+    }
+  if (s.full && n > kMaxFullModes) fail(HGF_EINVAL, "a driven or exchange-coupled system has at most 8 modes");
   return s;
 }
 
@@ -2435,6 +2619,7 @@ hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int
     if (!op) fail(HGF_EINVAL, "operator is NULL");
     if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
     Function& f = op->fn[idx];
+    if (f.full) fail(HGF_EUNSUPPORTED, "a network operator is one full (k, l) grid: read it with hgf_reconstruct");
     const int n = op->sys.n;
     if (sector_d)
       for (int j = 0; j < n; ++j) sector_d[j] = f.tab.d[j];

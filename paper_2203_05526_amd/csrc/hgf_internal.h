@@ -40,6 +40,29 @@ struct System {
   // n <-> n+1 of each mode, bath occupation nlev[j][n]
   int secular = 0;
   double nlev[kMaxModes][kMaxCutoff] = {};
+  // driven, exchange-coupled network: H += Omega_j a_j^+ + conj(Omega_j) a_j
+  // + sum_{i<j} J_ij (a_i^+ a_j + a_j^+ a_i); `full` when any is non-zero (the
+  // sectors are then coupled and an operator is one full (k, l) grid)
+  int full = 0;
+  double drive_re[kMaxModes] = {}, drive_im[kMaxModes] = {};
+  double exch[kMaxModes][kMaxModes] = {};
+};
+
+// Full (k, l) grid of a network operator: g(k, l) = <k|A|l> / sqrt(k! l!) on
+// 2N axes (k_0 .. k_{N-1}, l_0 .. l_{N-1}), row-major, i.e. the matrix A[K, L]
+// scaled.  Per-mode tables of its generator (device copy read by the kernel).
+constexpr int kMaxFullModes = kMaxModes / 2;
+struct FullTables {
+  int n, secular;
+  int nc[kMaxFullModes];
+  double e[kMaxFullModes][kMaxCutoff];    // E_j(k) = Delta_j k + (K_j / 2) k (k - 1)
+  double dk[kMaxFullModes][kMaxCutoff];   // minus half the rate out of level k (damping)
+  double adn[kMaxFullModes][kMaxCutoff];  // coefficient of g(k - e_j, l - e_j)
+  double aup[kMaxFullModes][kMaxCutoff];  // coefficient of g(k + e_j, l + e_j) (Lindblad: per (k+1)(l+1))
+  double chi[kMaxFullModes][kMaxFullModes];
+  double gphi[kMaxFullModes];
+  double drive_re[kMaxFullModes], drive_im[kMaxFullModes];
+  double exch[kMaxFullModes][kMaxFullModes];
 };
 
 // Coefficients of the generator restricted to one occupation-difference
@@ -104,6 +127,7 @@ struct GridArgs {
   const float2* lam_f;
   const float* beta_f;
   const float* alpha_f;
+  const FullTables* full;   // network operator on the full (k, l) grid, else NULL
 };
 
 // Arguments of one member of a grouped (tiled) stage launch, kept in device
@@ -180,6 +204,10 @@ struct Function {
   void* ehtab = nullptr;
   cd eh0 = 0.0;
   double eh_h = 0.0;
+  // network operator: one full (k, l) grid, generator tables in ftab
+  bool full = false;
+  void* ftab = nullptr;
+  double full_bound = 0.0;  // bound on the spectral radius of its generator
 };
 
 struct StepPlan;

@@ -33,6 +33,9 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
+// Horner RK4 stage of a network operator on its full (k, l) grid (g.full set).
+void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+                        void* yf, void* out, double h, int* flag, hipStream_t st);
 // One stage of the integrating-factor RK4 step (stencil input `in`, state in
 // the stage precision `ye`, state y, its stage-precision copy yf, stage output
 // `vout`, the step's increment `delta`; eh: per-axis exp(lam_j(m) h/2), e0 =
@@ -66,12 +69,15 @@ int marginal_bins(const GridArgs& g);
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st);
 void launch_fill_zero(double2* p, int64_t n, hipStream_t st);
 // Number-basis matrix elements of one function on the lowest levels of every
-// mode: the sub-box m_j < b[j] of the grid, scattered to out[row * ln + col].
+// mode: the sub-box m_a < b[a] of the grid, scattered to out[row * ln + col]
+// with row = sum_a (m_a + ur[a]) rp[a] and col = sum_a (m_a + uc[a]) cp[a]
+// (a sector axis adds to both, a full grid's k axis to the row only and its l
+// axis to the column only).
 struct GatherBox {
-  int b[kMaxModes];        // sub-box extents (levels - max(u_j, v_j))
-  int u[kMaxModes], v[kMaxModes];
-  int foff[kMaxModes];     // start of axis j in the factor table sqrt(k! l!)(m)
-  int64_t lp[kMaxModes];   // levels^(N-1-j): row/column place value of mode j
+  int b[kMaxModes];        // sub-box extents
+  int ur[kMaxModes], uc[kMaxModes];
+  int foff[kMaxModes];     // start of axis a in the factor table (sqrt(k! l!) per point)
+  int64_t rp[kMaxModes], cp[kMaxModes];
   int64_t ln;              // levels^N: the output's row length
   int64_t total;           // prod_j b[j]
   int64_t pq;              // grid index that gets `add` (split layout), or -1

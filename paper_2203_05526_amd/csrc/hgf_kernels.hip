@@ -177,6 +177,125 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// ------------------------------------------------------------ network operator, full (k, l) grid
+//
+// With a drive and exchange (Eq. (16)) the sectors are coupled; the operator
+// is one grid g(k, l) on 2N axes.  In g the adjoint equation reads, per point
+// (k_j, l_j the coordinates of axes j and N + j, s_kj, s_lj their strides):
+//   diagonal  i (E(k) - E(l)) + sum_j [dk_j(k_j) + dk_j(l_j) - gphi_j (k_j - l_j)^2]
+//   jumps     adn_j g(k - e_j, l - e_j) + aup_j g(k + e_j, l + e_j)
+//             (Lindblad: adn = gamma1 (1 + nth), aup = gamma1 nth (k_j+1)(l_j+1);
+//              secular: only where k_j = l_j, per-level coefficients)
+//   drive     i [Om g(k - e_j, l) + conj(Om) (k_j+1) g(k + e_j, l)
+//                - Om (l_j+1) g(k, l + e_j) - conj(Om) g(k, l - e_j)]
+//   exchange  i J_ij [(k_j+1) g(k - e_i + e_j, l) + (k_i+1) g(k - e_j + e_i, l)
+//                     - (l_i+1) g(k, l - e_j + e_i) - (l_j+1) g(k, l - e_i + e_j)]
+// (every neighbour term only where its point is inside the grid).
+template <typename R, typename TIN>
+__device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, const TIN* __restrict__ in,
+                                                          const Walker& w) {
+  using CT = typename C2<R>::T;
+  const FullTables* __restrict__ ft = g.full;
+  const int n = ft->n;
+  const int64_t i0 = w.i;
+  double ek = 0.0, el = 0.0, dr = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int kj = w.c[j], lj = w.c[n + j];
+    ek += ft->e[j][kj];
+    el += ft->e[j][lj];
+    dr += ft->dk[j][kj] + ft->dk[j][lj] - ft->gphi[j] * (double)((kj - lj) * (kj - lj));
+    for (int i = 0; i < j; ++i) {
+      ek += ft->chi[i][j] * (double)(w.c[i] * kj);
+      el += ft->chi[i][j] * (double)(w.c[n + i] * lj);
+    }
+  }
+  const CT c = load_as<R>(in, i0);
+  const R lr = (R)dr, li = (R)(ek - el);
+  R ar = lr * c.x - li * c.y, ai = lr * c.y + li * c.x;
+  for (int j = 0; j < n; ++j) {
+    const int kj = w.c[j], lj = w.c[n + j], nc = ft->nc[j];
+    const int64_t sk = g.stride[j], sl = g.stride[n + j];
+    if (!ft->secular || kj == lj) {
+      if (kj >= 1 && lj >= 1) {
+        const R a = (R)ft->adn[j][ft->secular ? kj : 0];
+        const CT v = load_as<R>(in, i0 - sk - sl);
+        ar += a * v.x;
+        ai += a * v.y;
+      }
+      if (kj + 1 < nc && lj + 1 < nc) {
+        const R b = (R)(ft->secular ? ft->aup[j][kj] : ft->aup[j][0] * (double)((kj + 1) * (lj + 1)));
+        const CT v = load_as<R>(in, i0 + sk + sl);
+        ar += b * v.x;
+        ai += b * v.y;
+      }
+    }
+    const R orr = (R)ft->drive_re[j], oi = (R)ft->drive_im[j];
+    if (orr != 0 || oi != 0) {
+      // t = Om g(k-e) + conj(Om)(k+1) g(k+e) - Om (l+1) g(l+e) - conj(Om) g(l-e); acc += i t
+      R tr = 0, ti = 0;
+      if (kj >= 1) {
+        const CT v = load_as<R>(in, i0 - sk);
+        tr += orr * v.x - oi * v.y;
+        ti += orr * v.y + oi * v.x;
+      }
+      if (kj + 1 < nc) {
+        const CT v = load_as<R>(in, i0 + sk);
+        const R f = (R)(kj + 1);
+        tr += f * (orr * v.x + oi * v.y);
+        ti += f * (orr * v.y - oi * v.x);
+      }
+      if (lj + 1 < nc) {
+        const CT v = load_as<R>(in, i0 + sl);
+        const R f = (R)(lj + 1);
+        tr -= f * (orr * v.x - oi * v.y);
+        ti -= f * (orr * v.y + oi * v.x);
+      }
+      if (lj >= 1) {
+        const CT v = load_as<R>(in, i0 - sl);
+        tr -= orr * v.x + oi * v.y;
+        ti -= orr * v.y - oi * v.x;
+      }
+      ar -= ti;
+      ai += tr;
+    }
+  }
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      const R J = (R)ft->exch[i][j];
+      if (J == 0) continue;
+      const int ki = w.c[i], kj = w.c[j], li = w.c[n + i], lj = w.c[n + j];
+      const int nci = ft->nc[i], ncj = ft->nc[j];
+      const int64_t ski = g.stride[i], skj = g.stride[j], sli = g.stride[n + i], slj = g.stride[n + j];
+      R tr = 0, ti = 0;
+      if (ki >= 1 && kj + 1 < ncj) {
+        const CT v = load_as<R>(in, i0 - ski + skj);
+        tr += (R)(kj + 1) * v.x;
+        ti += (R)(kj + 1) * v.y;
+      }
+      if (kj >= 1 && ki + 1 < nci) {
+        const CT v = load_as<R>(in, i0 - skj + ski);
+        tr += (R)(ki + 1) * v.x;
+        ti += (R)(ki + 1) * v.y;
+      }
+      if (lj >= 1 && li + 1 < nci) {
+        const CT v = load_as<R>(in, i0 - slj + sli);
+        tr -= (R)(li + 1) * v.x;
+        ti -= (R)(li + 1) * v.y;
+      }
+      if (li >= 1 && lj + 1 < ncj) {
+        const CT v = load_as<R>(in, i0 - sli + slj);
+        tr -= (R)(lj + 1) * v.x;
+        ti -= (R)(lj + 1) * v.y;
+      }
+      ar -= J * ti;
+      ai += J * tr;
+    }
+  CT out;
+  out.x = ar;
+  out.y = ai;
+  return out;
+}
+
 // ------------------------------------------------------------ RK4, merged form
 //
 // For a linear, time-independent generator the classical RK4 step is
@@ -190,7 +309,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // The stage grids hold only increments (small next to y), so storing them in
 // complex64 keeps the state's FP64 accuracy to first order in hL.
 
-template <int STAGE, typename R, typename TS>
+template <int STAGE, typename R, typename TS, bool FULL = false>
 __device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigits& sd, const TS* __restrict__ in,
                                             const TS* __restrict__ x1, double2* __restrict__ y,
                                             TS* __restrict__ yf, TS* __restrict__ out, double h,
@@ -201,7 +320,11 @@ __device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigit
   walker_init(w, g, i0);
   int bad = 0;
   while (w.i < g.points) {
-    const auto lv = apply_L<R>(g, in, w);
+    typename C2<R>::T lv;
+    if constexpr (FULL)
+      lv = apply_L_full<R>(g, in, w);
+    else
+      lv = apply_L<R>(g, in, w);
     if (STAGE == 1) {
       out[w.i] = from_d2<TS>(make_double2(h * (double)lv.x, h * (double)lv.y));
     } else if (STAGE == 2 || STAGE == 3) {
@@ -352,6 +475,20 @@ __global__ __launch_bounds__(256) void k_lawson_stage(GridArgs g, StrideDigits s
     case 2: lawson_body<2, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
     case 3: lawson_body<3, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
     default: lawson_body<4, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+  }
+}
+
+// Generic stage kernel of a network operator on its full (k, l) grid.
+template <typename TS, typename RS>
+__global__ __launch_bounds__(256) void k_full_stage(GridArgs g, StrideDigits sd, int stage, const TS* in,
+                                                   const TS* __restrict__ x1, double2* __restrict__ y,
+                                                   TS* __restrict__ yf, TS* __restrict__ out, double h,
+                                                   int* __restrict__ flag) {
+  switch (stage) {
+    case 1: horner_body<1, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 2: horner_body<2, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 3: horner_body<3, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
+    default: horner_body<4, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
   }
 }
 
@@ -678,8 +815,8 @@ __global__ void k_gather_levels(GridArgs g, const double* __restrict__ y, int re
       const int m = (int)(rem % box.b[j]);
       rem /= box.b[j];
       gi += m * g.stride[j];
-      row += (int64_t)(m + box.u[j]) * box.lp[j];
-      col += (int64_t)(m + box.v[j]) * box.lp[j];
+      row += (int64_t)(m + box.ur[j]) * box.rp[j];
+      col += (int64_t)(m + box.uc[j]) * box.cp[j];
       f *= fac[box.foff[j] + m];
     }
     double2 val = real ? make_double2(y[gi], 0.0) : make_double2(y[2 * gi], y[2 * gi + 1]);
@@ -815,6 +952,19 @@ void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const
                          (const float2*)ye, (double2*)y, (float2*)yf, (float2*)vout, (float2*)delta, eh, e0, h,
                          flag);
   }
+}
+
+void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+                        void* yf, void* out, double h, int* flag, hipStream_t st) {
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  dim3 gr(ls.blocks), bl(ls.threads);
+  if (precision == HGF_FP64)
+    hipLaunchKernelGGL((k_full_stage<double2, double>), gr, bl, 0, st, g, sd, stage, (const double2*)in,
+                       (const double2*)x1, (double2*)y, (double2*)yf, (double2*)out, h, flag);
+  else
+    hipLaunchKernelGGL((k_full_stage<float2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
+                       (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
 }
 
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st) {

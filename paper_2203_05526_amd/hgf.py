@@ -46,7 +46,7 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 class _SystemDesc(ctypes.Structure):
     _fields_ = [("n_modes", ctypes.c_int32), ("cutoff", _i32p), ("detuning", _f64p), ("kerr", _f64p),
                 ("cross_kerr", _f64p), ("gamma1", _f64p), ("gamma_phi", _f64p), ("n_th", _f64p),
-                ("dissipator", ctypes.c_int32), ("n_th_levels", _f64p)]
+                ("dissipator", ctypes.c_int32), ("n_th_levels", _f64p), ("drive", _f64p), ("exchange", _f64p)]
 
 
 HGF_DISS_LINDBLAD, HGF_DISS_SECULAR = 0, 1
@@ -171,7 +171,7 @@ class System:
     """A handle on hgf_system (copy of the parameters, validated)."""
 
     def __init__(self, cutoff, detuning, kerr, cross_kerr, gamma1, gamma_phi, n_th, dissipator="lindblad",
-                 n_th_levels=None):
+                 n_th_levels=None, drive=None, exchange=None):
         lib = load_library()
         n = len(cutoff)
         self.n_modes = n
@@ -187,8 +187,20 @@ class System:
             if levels.size != sum(c - 1 for c in self.cutoff):
                 raise HgfError(-1, "n_th_levels needs sum(cutoff - 1) values")
             self._arrays.append(levels)
+        net = []
+        for x, ln in ((drive, n), (exchange, n * n)):
+            if x is None:
+                net.append(None)
+                continue
+            a = np.ascontiguousarray(np.asarray(x, dtype=np.complex128 if ln == n else np.float64).reshape(-1))
+            if a.size != ln:
+                raise HgfError(-1, "drive needs N complex values and exchange N*N values")
+            a = a.view(np.float64) if ln == n else a
+            self._arrays.append(a)
+            net.append(a.ctypes.data_as(_f64p))
+        self.network = any(x is not None for x in net)
         d = _SystemDesc(n, *(a.ctypes.data_as(_i32p if i == 0 else _f64p) for i, a in enumerate(self._arrays[:7])),
-                        _DISS[dissipator], levels.ctypes.data_as(_f64p) if levels is not None else None)
+                        _DISS[dissipator], levels.ctypes.data_as(_f64p) if levels is not None else None, *net)
         h = ctypes.c_void_p()
         _check(lib.hgf_define_system(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -211,7 +223,8 @@ def define_system(system) -> System:
     cross_kerr, gamma1, gamma_phi and n_th (e.g. ``synth.System``)."""
     return System(system.cutoff, system.detuning, system.kerr, system.cross_kerr, system.gamma1,
                   system.gamma_phi, system.n_th, getattr(system, "dissipator", "lindblad"),
-                  getattr(system, "n_th_levels", None))
+                  getattr(system, "n_th_levels", None), getattr(system, "drive", None),
+                  getattr(system, "exchange", None))
 
 
 # ------------------------------------------------------------------ operators

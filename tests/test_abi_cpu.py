@@ -110,3 +110,19 @@ def test_dissipator_validation(hgf):
         hgf.System(*args, dissipator="secular", n_th_levels=[0.1, -0.2, 0.0])
     with pytest.raises(hgf.HgfError):
         hgf.System(*args, dissipator="secular", n_th_levels=[0.1, 0.2])
+
+
+def test_network_validation(hgf):
+    """Drive and exchange are validated when the system is defined (no GPU)."""
+    args = ((3, 2), [0.0, 0.0], [0.0, 0.0], [0.0] * 4, [0.1, 0.1], [0.1, 0.1], [0.0, 0.0])
+    assert hgf.System(*args, drive=[1.0 + 0.5j, 0.0], exchange=[[0.0, 2.0], [2.0, 0.0]]).network
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, exchange=[[0.0, 2.0], [1.0, 0.0]])  # not symmetric
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, drive=[np.nan, 0.0])
+    with pytest.raises(hgf.HgfError):
+        hgf.System(*args, drive=[1.0])  # wrong length
+    n = 9  # the full (k, l) grid has 2N axes: at most 8 modes
+    with pytest.raises(hgf.HgfError):
+        hgf.System((2,) * n, [0.0] * n, [0.0] * n, [0.0] * (n * n), [0.1] * n, [0.0] * n, [0.0] * n,
+                   drive=[1.0] + [0.0] * (n - 1))
