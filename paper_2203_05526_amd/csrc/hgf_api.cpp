@@ -873,25 +873,28 @@ static FullTables full_tables(const System& s) {
 }
 
 // Gershgorin-type bound on the generator of a network operator's full grid:
-// the largest diagonal entry plus every neighbour coefficient at its largest.
+// the largest diagonal entry (|E(k) - E(l)| is at most the range of E over
+// the grid, plus the damping and dephasing) plus every neighbour coefficient
+// at its largest.
 static double full_generator_bound(const FullTables& ft) {
-  double emax = 0.0, dmax = 0.0, b = 0.0;
+  double erange = 0.0, dmax = 0.0, b = 0.0;
   for (int j = 0; j < ft.n; ++j) {
     const int nc = ft.nc[j];
-    double ej = 0.0, dj = 0.0, a = 0.0, u = 0.0;
+    double elo = ft.e[j][0], ehi = ft.e[j][0], dj = 0.0, a = 0.0, u = 0.0;
     for (int k = 0; k < nc; ++k) {
-      ej = std::max(ej, std::abs(ft.e[j][k]));
+      elo = std::min(elo, ft.e[j][k]);
+      ehi = std::max(ehi, ft.e[j][k]);
       dj = std::max(dj, std::abs(ft.dk[j][k]));
       a = std::max(a, ft.adn[j][k]);
       u = std::max(u, ft.secular ? ft.aup[j][k] : ft.aup[j][k] * nc * nc);
     }
-    emax += ej;
+    erange += ehi - elo;
     dmax += 2.0 * dj + ft.gphi[j] * (nc - 1) * (nc - 1);
-    for (int i = 0; i < j; ++i) emax += std::abs(ft.chi[i][j]) * (ft.nc[i] - 1) * (nc - 1);
+    for (int i = 0; i < j; ++i) erange += std::abs(ft.chi[i][j]) * (ft.nc[i] - 1) * (nc - 1);
     b += a + u + std::hypot(ft.drive_re[j], ft.drive_im[j]) * 2.0 * (nc + 1);
     for (int i = 0; i < j; ++i) b += std::abs(ft.exch[i][j]) * 2.0 * (ft.nc[i] + nc);
   }
-  return 2.0 * emax + dmax + b;
+  return erange + dmax + b;
 }
 
 // A network operator: every sector of the input scattered into one full

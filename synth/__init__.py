@@ -20,6 +20,8 @@ from .workloads import (  # noqa: F401
     projector_factors,
     parity_factors,
     quadrature_factors,
+    annihilation_factors,
+    table1_network,
     fock_state,
     coherent_state,
     random_system,

@@ -121,6 +121,34 @@ def quadrature_factors(cutoff: Sequence[int]) -> List[np.ndarray]:
     return out
 
 
+def annihilation_factors(cutoff: Sequence[int]) -> List[np.ndarray]:
+    """Per-mode truncated annihilation operators a_j (the product is the test
+    operator prod_j a_j of the network example)."""
+    return [np.diag(np.sqrt(np.arange(1, c, dtype=float)), 1).astype(np.complex128) for c in cutoff]
+
+
+def table1_network(n_modes: int, cutoff: int = 6) -> Workload:
+    """The network example's parameters: a chain of anharmonic modes, each at
+    the drive frequency (zero detuning in the drive frame), anharmonicity
+    eta = 2 pi 250 MHz (K = 2 eta), the first driven with Omega = 2 pi 125 MHz
+    (i Omega a e^{i w t} + h.c. is -i conj(Omega) a^+ + h.c. in the drive
+    frame), nearest-neighbour exchange J = 2 pi 10 MHz, decay kappa = 0.02/us
+    under the secular dissipator at zero bath temperature; observable
+    prod_j a_j; horizon w_q t / pi = 10 with w_q = 2 pi 3500 MHz."""
+    n = n_modes
+    two_pi = TWO_PI
+    sysm = System((cutoff,) * n, np.zeros(n), np.full(n, 2 * two_pi * 250.0), np.zeros((n, n)),
+                  np.full(n, 0.02), np.zeros(n), np.zeros(n), dissipator="secular")
+    sysm.drive = np.array([-1j * two_pi * 125.0] + [0.0] * (n - 1), dtype=np.complex128)
+    J = np.zeros((n, n))
+    for i in range(n - 1):
+        J[i, i + 1] = J[i + 1, i] = two_pi * 10.0
+    sysm.exchange = J
+    t_total = 10 * np.pi / (two_pi * 3500.0)
+    return Workload(f"network of {n} driven anharmonic modes (Table I), cutoff {cutoff}", sysm,
+                    annihilation_factors(sysm.cutoff), [coherent_state([0.5] * n)], t_total, t_total / 100)
+
+
 def fock_state(occ: Sequence[int]) -> Tuple[str, np.ndarray]:
     return ("fock", np.asarray(occ, dtype=np.int64))
 
