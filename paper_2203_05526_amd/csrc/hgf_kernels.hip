@@ -177,6 +177,18 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Grid-stride range of the stage kernels, XCD-aware: the launch has a multiple
+// of 8 blocks, dealt round-robin to the 8 XCDs (block b runs on XCD b mod 8);
+// XCD x sweeps the contiguous eighth [P x / 8, P (x + 1) / 8) of the points with
+// its own blocks, so that the neighbours a point reads at short strides were
+// loaded into the same XCD's L2.  The loop stride, (blocks / 8) * threads, is
+// the caller's StrideDigits.
+__device__ __forceinline__ void xcd_range(int64_t points, int64_t& begin, int64_t& end) {
+  const int64_t x = blockIdx.x & 7;
+  end = points * (x + 1) / 8;
+  begin = points * x / 8 + (int64_t)(blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+}
+
 // ------------------------------------------------------------ network operator, full (k, l) grid
 //
 // With a drive and exchange (Eq. (16)) the sectors are coupled; the operator
@@ -190,20 +202,29 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 //                - Om (l_j+1) g(k, l + e_j) - conj(Om) g(k, l - e_j)]
 //   exchange  i J_ij [(k_j+1) g(k - e_i + e_j, l) + (k_i+1) g(k - e_j + e_i, l)
 //                     - (l_i+1) g(k, l - e_j + e_i) - (l_j+1) g(k, l - e_i + e_j)]
-// (every neighbour term only where its point is inside the grid).
-template <typename R, typename TIN>
+// (every neighbour term only where its point is inside the grid).  N, the
+// number of modes, is a template parameter so that every coordinate index is a
+// compile-time constant (the coordinates stay in registers).
+template <int N, typename R, typename TIN>
 __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, const TIN* __restrict__ in,
                                                           const Walker& w) {
   using CT = typename C2<R>::T;
   const FullTables* __restrict__ ft = g.full;
-  const int n = ft->n;
+  constexpr int n = N;
   const int64_t i0 = w.i;
   double ek = 0.0, el = 0.0, dr = 0.0;
+  // the coordinates, 5 bits each, for the rolled loops below (an array
+  // indexed at run time would live in scratch memory)
+  uint64_t kp = 0, lp = 0;
+#pragma unroll
   for (int j = 0; j < n; ++j) {
     const int kj = w.c[j], lj = w.c[n + j];
+    kp |= (uint64_t)kj << (5 * j);
+    lp |= (uint64_t)lj << (5 * j);
     ek += ft->e[j][kj];
     el += ft->e[j][lj];
     dr += ft->dk[j][kj] + ft->dk[j][lj] - ft->gphi[j] * (double)((kj - lj) * (kj - lj));
+#pragma unroll
     for (int i = 0; i < j; ++i) {
       ek += ft->chi[i][j] * (double)(w.c[i] * kj);
       el += ft->chi[i][j] * (double)(w.c[n + i] * lj);
@@ -212,8 +233,11 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
   const CT c = load_as<R>(in, i0);
   const R lr = (R)dr, li = (R)(ek - el);
   R ar = lr * c.x - li * c.y, ai = lr * c.y + li * c.x;
+  // neighbour loops not unrolled: unrolled, their loads are all issued up
+  // front and the registers they hold cost more occupancy than they save
+#pragma unroll 1
   for (int j = 0; j < n; ++j) {
-    const int kj = w.c[j], lj = w.c[n + j], nc = ft->nc[j];
+    const int kj = (int)((kp >> (5 * j)) & 31u), lj = (int)((lp >> (5 * j)) & 31u), nc = ft->nc[j];
     const int64_t sk = g.stride[j], sl = g.stride[n + j];
     if (!ft->secular || kj == lj) {
       if (kj >= 1 && lj >= 1) {
@@ -259,11 +283,14 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
       ai += tr;
     }
   }
+#pragma unroll 1
   for (int j = 1; j < n; ++j)
+#pragma unroll 1
     for (int i = 0; i < j; ++i) {
       const R J = (R)ft->exch[i][j];
       if (J == 0) continue;
-      const int ki = w.c[i], kj = w.c[j], li = w.c[n + i], lj = w.c[n + j];
+      const int ki = (int)((kp >> (5 * i)) & 31u), kj = (int)((kp >> (5 * j)) & 31u);
+      const int li = (int)((lp >> (5 * i)) & 31u), lj = (int)((lp >> (5 * j)) & 31u);
       const int nci = ft->nc[i], ncj = ft->nc[j];
       const int64_t ski = g.stride[i], skj = g.stride[j], sli = g.stride[n + i], slj = g.stride[n + j];
       R tr = 0, ti = 0;
@@ -309,20 +336,21 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
 // The stage grids hold only increments (small next to y), so storing them in
 // complex64 keeps the state's FP64 accuracy to first order in hL.
 
-template <int STAGE, typename R, typename TS, bool FULL = false>
+template <int STAGE, typename R, typename TS, int FULLN = 0>
 __device__ __forceinline__ void horner_body(const GridArgs& g, const StrideDigits& sd, const TS* __restrict__ in,
                                             const TS* __restrict__ x1, double2* __restrict__ y,
                                             TS* __restrict__ yf, TS* __restrict__ out, double h,
                                             int* __restrict__ flag) {
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 >= g.points) return;
+  int64_t i0, iend;
+  xcd_range(g.points, i0, iend);
+  if (i0 >= iend) return;
   Walker w;
   walker_init(w, g, i0);
   int bad = 0;
-  while (w.i < g.points) {
+  while (w.i < iend) {
     typename C2<R>::T lv;
-    if constexpr (FULL)
-      lv = apply_L_full<R>(g, in, w);
+    if constexpr (FULLN > 0)
+      lv = apply_L_full<FULLN, R>(g, in, w);
     else
       lv = apply_L<R>(g, in, w);
     if (STAGE == 1) {
@@ -434,12 +462,13 @@ __device__ __forceinline__ void lawson_body(const GridArgs& g, const StrideDigit
                                             TS* __restrict__ vout, TS* __restrict__ delta,
                                             const double2* __restrict__ eh, double2 e0, double h,
                                             int* __restrict__ flag) {
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 >= g.points) return;
+  int64_t i0, iend;
+  xcd_range(g.points, i0, iend);
+  if (i0 >= iend) return;
   Walker w;
   walker_init(w, g, i0);
   int bad = 0;
-  while (w.i < g.points) {
+  while (w.i < iend) {
     const double2 jv = apply_J<R>(g, in, w);
     const double2 E = lawson_factor(g, eh, e0, w);
     if (STAGE == 1) {
@@ -478,18 +507,30 @@ __global__ __launch_bounds__(256) void k_lawson_stage(GridArgs g, StrideDigits s
   }
 }
 
-// Generic stage kernel of a network operator on its full (k, l) grid.
-template <typename TS, typename RS>
+// Generic stage kernel of a network operator of N modes on its full (k, l) grid.
+template <int N, typename TS, typename RS>
 __global__ __launch_bounds__(256) void k_full_stage(GridArgs g, StrideDigits sd, int stage, const TS* in,
                                                    const TS* __restrict__ x1, double2* __restrict__ y,
                                                    TS* __restrict__ yf, TS* __restrict__ out, double h,
                                                    int* __restrict__ flag) {
   switch (stage) {
-    case 1: horner_body<1, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
-    case 2: horner_body<2, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
-    case 3: horner_body<3, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
-    default: horner_body<4, RS, TS, true>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 1: horner_body<1, RS, TS, N>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 2: horner_body<2, RS, TS, N>(g, sd, in, x1, y, yf, out, h, flag); break;
+    case 3: horner_body<3, RS, TS, N>(g, sd, in, x1, y, yf, out, h, flag); break;
+    default: horner_body<4, RS, TS, N>(g, sd, in, x1, y, yf, out, h, flag); break;
   }
+}
+
+template <int N>
+static void full_launch_n(int stage, int precision, const GridArgs& g, const StrideDigits& sd, dim3 gr, dim3 bl,
+                          const void* in, const void* x1, void* y, void* yf, void* out, double h, int* flag,
+                          hipStream_t st) {
+  if (precision == HGF_FP64)
+    hipLaunchKernelGGL((k_full_stage<N, double2, double>), gr, bl, 0, st, g, sd, stage, (const double2*)in,
+                       (const double2*)x1, (double2*)y, (double2*)yf, (double2*)out, h, flag);
+  else
+    hipLaunchKernelGGL((k_full_stage<N, float2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
+                       (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
 }
 
 // ------------------------------------------------------------ stage-precision copy
@@ -872,6 +913,17 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks) {
 
 static const int kStageBlocks = 4096;
 
+// Launch of the XCD-aware stage kernels (see xcd_range): a multiple of 8
+// blocks, and the loop stride inside one XCD's eighth of the grid.
+static LaunchShape xcd_stage_shape(const GridArgs& g, StrideDigits& sd) {
+  LaunchShape ls;
+  ls.threads = 256;
+  const int64_t need = (g.points + ls.threads - 1) / ls.threads;
+  ls.blocks = (int)((std::min<int64_t>(std::max<int64_t>(need, 1), kStageBlocks) + 7) / 8 * 8);
+  sd = digits_for(g, (int64_t)(ls.blocks / 8) * ls.threads);
+  return ls;
+}
+
 // Grouped tiled kernel instantiations live in hgf_tiled_{c64,c128,r32,r64}.hip.
 void launch_group_c64(const GroupLaunch&, int, int*, hipStream_t);
 void launch_group_c128(const GroupLaunch&, int, int*, hipStream_t);
@@ -918,8 +970,8 @@ void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st) {
 
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st) {
-  const LaunchShape ls = shape_for(g, kStageBlocks);
-  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  StrideDigits sd;
+  const LaunchShape ls = xcd_stage_shape(g, sd);
   dim3 gr(ls.blocks), bl(ls.threads);
   if (precision == HGF_FP64)
     hipLaunchKernelGGL((k_rk4_stage<double2, double>), gr, bl, 0, st, g, sd, stage, (const double2*)in,
@@ -932,8 +984,8 @@ void launch_horner(int stage, int precision, const GridArgs& g, const void* in, 
 void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const void* in, const void* ye, void* y,
                    void* yf, void* vout, void* delta, const double2* eh, double2 e0, double h, int* flag,
                    hipStream_t st) {
-  const LaunchShape ls = shape_for(g, kStageBlocks);
-  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  StrideDigits sd;
+  const LaunchShape ls = xcd_stage_shape(g, sd);
   dim3 gr(ls.blocks), bl(ls.threads);
   if (precision == HGF_FP64) {
     if (real)
@@ -956,15 +1008,19 @@ void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const
 
 void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
                         void* yf, void* out, double h, int* flag, hipStream_t st) {
-  const LaunchShape ls = shape_for(g, kStageBlocks);
-  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  StrideDigits sd;
+  const LaunchShape ls = xcd_stage_shape(g, sd);
   dim3 gr(ls.blocks), bl(ls.threads);
-  if (precision == HGF_FP64)
-    hipLaunchKernelGGL((k_full_stage<double2, double>), gr, bl, 0, st, g, sd, stage, (const double2*)in,
-                       (const double2*)x1, (double2*)y, (double2*)yf, (double2*)out, h, flag);
-  else
-    hipLaunchKernelGGL((k_full_stage<float2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
-                       (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
+  switch (g.n / 2) {
+    case 1: full_launch_n<1>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 2: full_launch_n<2>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 3: full_launch_n<3>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 4: full_launch_n<4>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 5: full_launch_n<5>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 6: full_launch_n<6>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    case 7: full_launch_n<7>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+    default: full_launch_n<8>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+  }
 }
 
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st) {
