@@ -251,6 +251,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
+    ap.add_argument("--only", choices=["network"], default=None,
+                    help="run one section alone and print its JSON (for profiling it): network = the Table I "
+                         "network for 1 to 5 modes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -266,6 +269,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     hgf.load_library()
+    if args.only == "network":
+        print(json.dumps({"network": network_timing(hgf, torch)}))
+        return
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
