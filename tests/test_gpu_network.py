@@ -71,6 +71,23 @@ def test_network_matches_oracle(hgf, cutoff, seed, dissipator, precision, tol):
     assert abs(J - want) / abs(want) < (10 * tol if precision == "mixed" else tol)
 
 
+def test_network_maximum_modes(hgf):
+    """Eight modes (16 grid axes, the limit) of two levels each, both
+    dissipators' tables through the coordinate packing, against the oracle."""
+    cutoff = (2,) * 8
+    announce("network 8 modes")
+    for dissipator in ("lindblad", "secular"):
+        s = network_system(cutoff, 509, dissipator, scale=1.0)
+        rng = np.random.default_rng(509)
+        M = rng.normal(size=(256, 256)) + 1j * rng.normal(size=(256, 256))
+        op = hgf.map_operator(hgf.define_system(s), dense=M, precision="fp64")
+        assert op.info()["total_points"] == 2 ** 16
+        T, dt = 0.01, 5e-4
+        hgf.evolve(op, T, dt)
+        ref = oracle.evolve_full(s, M, T, dt)
+        assert rel_fro(hgf.reconstruct(op, 2), ref) < FP64_TOL
+
+
 def test_qubit_chain_driven_on_one_end(hgf):
     """Table I's structure: a chain of anharmonic modes (three levels each),
     the first driven on resonance, nearest-neighbour exchange, weak decay; the
