@@ -90,9 +90,19 @@ def cpu_baseline(w, steps: int):
     oracle.evolve_steps(w.system, ops, steps, w.dt)
     el = time.perf_counter() - t0
     pts = int(np.prod(w.system.cutoff))
+    # one host thread: the same ten modes at cutoff 4 (4^10 points; the same
+    # per-point work, a grid small enough for a few steps in seconds)
+    s1 = w.system.copy()
+    s1.cutoff = (4,) * s1.n_modes
+    f1 = [f[:4, :4] for f in w.factors]
+    t1 = time.perf_counter()
+    oracle.evolve_steps(s1, oracle.product_sectors(f1), 3, w.dt, nthreads=1)
+    el1 = time.perf_counter() - t1
     return {"value": pts * 4 * steps / el, "unit": "point-stage updates/s", "cores": oracle.max_threads(),
             "kind": "oracle",
-            "sample": f"{steps} RK4 steps over all {pts} points of the same 10-mode grid ({el:.1f} s)"}
+            "sample": f"{steps} RK4 steps over all {pts} points of the same 10-mode grid ({el:.1f} s)",
+            "single_thread": {"value": 4 ** s1.n_modes * 4 * 3 / el1, "unit": "point-stage updates/s",
+                              "sample": f"3 RK4 steps of the same 10 modes at cutoff 4 on one thread ({el1:.1f} s)"}}
 
 
 def time_to_tolerance(hgf, torch):
