@@ -1323,31 +1323,64 @@ static void ensure_lawson_tables(Function& f, double h, hipStream_t st) {
   f.eh_h = h;
 }
 
-// One integrating-factor RK4 step of every function (stage buffers: s1 and s2
-// take v2, v3, v4 in turn, s3 the increment).
-static void lawson_step(hgf_operator_s* op, double h, hipStream_t st) {
-  const bool mixed = op->precision == HGF_MIXED;
-  for (int s = 1; s <= 4; ++s)
-    for (auto& f : op->fn) {
-      const void* ye = mixed ? f.yf : f.y;
-      const void* in[4] = {ye, f.s1, f.s2, f.s1};
-      void* vout[4] = {f.s1, f.s2, f.s1, nullptr};
-      launch_lawson(s, op->precision, f.real, f.ga, in[s - 1], ye, f.y, mixed ? f.yf : nullptr, vout[s - 1], f.s3,
-                    (const double2*)f.ehtab, make_double2(f.eh0.real(), f.eh0.imag()), h, op->dflag, st);
-    }
-}
-
+// Integrating-factor RK4 steps of every function of an operator: one grouped
+// launch per stage and element type (complex and real grids), items in device
+// memory for the call (stage buffers: s1 and s2 take v2, v3, v4 in turn, s3 the
+// increment).  Steps are captured in HIP graphs of up to 64 steps.
 static void lawson_steps(hgf_operator_s* op, int64_t steps, double h, hipStream_t st) {
   for (auto& f : op->fn) ensure_lawson_tables(f, h, st);
-  // graphs of up to 64 steps and at most kMaxGraphNodes kernel nodes
-  const int64_t per_step = 4 * (int64_t)op->fn.size();
-  const int chunk = (int)std::min<int64_t>({steps, 64, kMaxGraphNodes / std::max<int64_t>(1, per_step)});
+  const bool mixed = op->precision == HGF_MIXED;
+  constexpr int kMaxRows = 65535;  // grid rows per launch
+  struct Group {
+    bool real;
+    std::vector<LawsonItem> items;
+    int row_blocks = 1;
+    size_t offset = 0;
+  };
+  Group groups[2] = {{false, {}}, {true, {}}};
+  for (auto& f : op->fn) groups[f.real ? 1 : 0].row_blocks = std::max(groups[f.real ? 1 : 0].row_blocks,
+                                                                         lawson_row_blocks(f.ga));
+  for (auto& f : op->fn) {
+    Group& gr = groups[f.real ? 1 : 0];
+    LawsonItem it{};
+    it.g = f.ga;
+    it.sd = lawson_row_digits(f.ga, gr.row_blocks);
+    it.y = f.y;
+    it.yf = mixed ? f.yf : nullptr;
+    it.s1 = f.s1;
+    it.s2 = f.s2;
+    it.s3 = f.s3;
+    it.eh = (const double2*)f.ehtab;
+    it.e0 = make_double2(f.eh0.real(), f.eh0.imag());
+    gr.items.push_back(it);
+  }
+  std::vector<LawsonItem> all;
+  for (auto& gr : groups) {
+    gr.offset = all.size();
+    all.insert(all.end(), gr.items.begin(), gr.items.end());
+  }
+  DBuf ditems(all.size() * sizeof(LawsonItem));
+  hip_check(hipMemcpyAsync(ditems.p, all.data(), all.size() * sizeof(LawsonItem), hipMemcpyHostToDevice, st),
+            "upload items");
+  hip_check(hipStreamSynchronize(st), "synchronize");  // the host copy is freed on return
+  int launches = 0;
+  for (auto& gr : groups) launches += (int)((gr.items.size() + kMaxRows - 1) / kMaxRows);
+  auto step = [&](hipStream_t s) {
+    for (int stage = 1; stage <= 4; ++stage)
+      for (auto& gr : groups)
+        for (size_t b = 0; b < gr.items.size(); b += kMaxRows) {
+          const int n = (int)std::min<size_t>(kMaxRows, gr.items.size() - b);
+          launch_lawson_group(stage, op->precision, gr.real, ditems.as<LawsonItem>() + gr.offset + b, n,
+                              gr.row_blocks, h, op->dflag, s);
+        }
+  };
+  const int64_t per_step = 4 * (int64_t)std::max(1, launches);
+  const int chunk = (int)std::min<int64_t>({steps, 64, kMaxGraphNodes / per_step});
   int64_t done = 0;
   if (chunk > 1) {
     if (!op->cap_stream) hip_check(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking), "stream");
-    hip_check(hipStreamSynchronize(st), "synchronize");
     hip_check(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-    for (int s = 0; s < chunk; ++s) lawson_step(op, h, op->cap_stream);
+    for (int k = 0; k < chunk; ++k) step(op->cap_stream);
     hipGraph_t graph;
     hip_check(hipStreamEndCapture(op->cap_stream, &graph), "end capture");
     hipGraphExec_t exec;
@@ -1358,7 +1391,8 @@ static void lawson_steps(hgf_operator_s* op, int64_t steps, double h, hipStream_
     for (; done + chunk <= steps; done += chunk) hip_check(hipGraphLaunch(g.e, st), "graph launch");
     hip_check(hipStreamSynchronize(st), "synchronize");  // the graph must outlive its launches
   }
-  for (; done < steps; ++done) lawson_step(op, h, st);
+  for (; done < steps; ++done) step(st);
+  hip_check(hipStreamSynchronize(st), "synchronize");  // the items must outlive the launches
 }
 
 static int read_flag(hgf_operator_s* op, hipStream_t st) {

@@ -33,16 +33,27 @@ LaunchShape shape_for(const GridArgs& g, int max_blocks);
 void launch_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y, void* yf,
                    void* out, double h, int* flag, hipStream_t st);
 void launch_shadow(int precision, const GridArgs& g, const void* y, void* yf, hipStream_t st);
+// Integrating-factor RK4 over many functions in one launch per stage (all the
+// functions of an operator that share element types): one row of blocks per
+// function, device array of items.
+struct LawsonItem {
+  GridArgs g;
+  StrideDigits sd;     // loop stride: (blocks per row) * threads
+  void* y;             // state
+  void* yf;            // stage-precision copy of y (mixed) or NULL
+  void* s1;            // v2, then v4
+  void* s2;            // v3
+  void* s3;            // the step's increment
+  const double2* eh;   // per-axis exp(lam_j(m) h/2)
+  double2 e0;          // exp(lam0 h/2)
+};
+void launch_lawson_group(int stage, int precision, bool real, const LawsonItem* items, int nitems, int row_blocks,
+                         double h, int* flag, hipStream_t st);
+int lawson_row_blocks(const GridArgs& g);
+StrideDigits lawson_row_digits(const GridArgs& g, int row_blocks);
 // Horner RK4 stage of a network operator on its full (k, l) grid (g.full set).
 void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
                         void* yf, void* out, double h, int* flag, hipStream_t st);
-// One stage of the integrating-factor RK4 step (stencil input `in`, state in
-// the stage precision `ye`, state y, its stage-precision copy yf, stage output
-// `vout`, the step's increment `delta`; eh: per-axis exp(lam_j(m) h/2), e0 =
-// exp(lam0 h/2)).
-void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const void* in, const void* ye, void* y,
-                   void* yf, void* vout, void* delta, const double2* eh, double2 e0, double h, int* flag,
-                   hipStream_t st);
 // form: 0 grouped kernel, 1 single-grid kernel, 2 single-grid pipelined kernel
 int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real,
                             int form);

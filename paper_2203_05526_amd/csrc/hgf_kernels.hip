@@ -456,21 +456,26 @@ __device__ __forceinline__ double2 lawson_factor(const GridArgs& g, const double
   return e;
 }
 
+// All the functions of an operator in one launch per stage: block row
+// blockIdx.y works on item blockIdx.y with a grid-stride loop over its points
+// (the scheme is meant for the small off-diagonal sectors, where one launch
+// per function and stage would be launch-bound).
 template <int STAGE, typename R, typename TS, typename TY>
-__device__ __forceinline__ void lawson_body(const GridArgs& g, const StrideDigits& sd, const TS* __restrict__ in,
-                                            const TS* __restrict__ ye, TY* __restrict__ y, TS* __restrict__ yf,
-                                            TS* __restrict__ vout, TS* __restrict__ delta,
-                                            const double2* __restrict__ eh, double2 e0, double h,
-                                            int* __restrict__ flag) {
-  int64_t i0, iend;
-  xcd_range(g.points, i0, iend);
-  if (i0 >= iend) return;
+__device__ __forceinline__ void lawson_group_body(const LawsonItem& it, double h, int* __restrict__ flag) {
+  const GridArgs& g = it.g;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  const TS* const ye = it.yf ? (const TS*)it.yf : (const TS*)it.y;  // the state in the stage precision
+  const TS* const in = STAGE == 1 ? ye : (STAGE == 3 ? (const TS*)it.s2 : (const TS*)it.s1);
+  TS* const vout = STAGE == 2 ? (TS*)it.s2 : (TS*)it.s1;
+  TS* const delta = (TS*)it.s3;
+  TY* const y = (TY*)it.y;
   Walker w;
   walker_init(w, g, i0);
   int bad = 0;
-  while (w.i < iend) {
+  while (w.i < g.points) {
     const double2 jv = apply_J<R>(g, in, w);
-    const double2 E = lawson_factor(g, eh, e0, w);
+    const double2 E = lawson_factor(g, it.eh, it.e0, w);
     if (STAGE == 1) {
       const double2 c = ld_c(in, w.i);
       st_c(vout, w.i, cmul(E, cadd(c, cscale(0.5 * h, jv))));
@@ -487,23 +492,22 @@ __device__ __forceinline__ void lawson_body(const GridArgs& g, const StrideDigit
       const double2 yn = cadd(cadd(cmul(cmul(E, E), ld_c(y, w.i)), ld_c(delta, w.i)), cscale(h / 6.0, jv));
       bad |= !(isfinite(yn.x) && isfinite(yn.y));
       st_c(y, w.i, yn);
-      if (yf) st_c(yf, w.i, yn);
+      if (it.yf) st_c((TS*)it.yf, w.i, yn);
     }
-    walker_step(w, g, sd);
+    walker_step(w, g, it.sd);
   }
   if (STAGE == 4 && bad) atomicOr(flag, 1);
 }
 
 template <typename TS, typename TY, typename RS>
-__global__ __launch_bounds__(256) void k_lawson_stage(GridArgs g, StrideDigits sd, int stage, const TS* in,
-                                                      const TS* ye, TY* y, TS* yf, TS* vout, TS* delta,
-                                                      const double2* __restrict__ eh, double2 e0, double h,
+__global__ __launch_bounds__(256) void k_lawson_group(const LawsonItem* __restrict__ items, int stage, double h,
                                                       int* __restrict__ flag) {
+  const LawsonItem& it = items[blockIdx.y];
   switch (stage) {
-    case 1: lawson_body<1, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
-    case 2: lawson_body<2, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
-    case 3: lawson_body<3, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
-    default: lawson_body<4, RS>(g, sd, in, ye, y, yf, vout, delta, eh, e0, h, flag); break;
+    case 1: lawson_group_body<1, RS, TS, TY>(it, h, flag); break;
+    case 2: lawson_group_body<2, RS, TS, TY>(it, h, flag); break;
+    case 3: lawson_group_body<3, RS, TS, TY>(it, h, flag); break;
+    default: lawson_group_body<4, RS, TS, TY>(it, h, flag); break;
   }
 }
 
@@ -981,31 +985,6 @@ void launch_horner(int stage, int precision, const GridArgs& g, const void* in, 
                        (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
 }
 
-void launch_lawson(int stage, int precision, bool real, const GridArgs& g, const void* in, const void* ye, void* y,
-                   void* yf, void* vout, void* delta, const double2* eh, double2 e0, double h, int* flag,
-                   hipStream_t st) {
-  StrideDigits sd;
-  const LaunchShape ls = xcd_stage_shape(g, sd);
-  dim3 gr(ls.blocks), bl(ls.threads);
-  if (precision == HGF_FP64) {
-    if (real)
-      hipLaunchKernelGGL((k_lawson_stage<double, double, double>), gr, bl, 0, st, g, sd, stage, (const double*)in,
-                         (const double*)ye, (double*)y, (double*)yf, (double*)vout, (double*)delta, eh, e0, h, flag);
-    else
-      hipLaunchKernelGGL((k_lawson_stage<double2, double2, double>), gr, bl, 0, st, g, sd, stage,
-                         (const double2*)in, (const double2*)ye, (double2*)y, (double2*)yf, (double2*)vout,
-                         (double2*)delta, eh, e0, h, flag);
-  } else {
-    if (real)
-      hipLaunchKernelGGL((k_lawson_stage<float, double, float>), gr, bl, 0, st, g, sd, stage, (const float*)in,
-                         (const float*)ye, (double*)y, (float*)yf, (float*)vout, (float*)delta, eh, e0, h, flag);
-    else
-      hipLaunchKernelGGL((k_lawson_stage<float2, double2, float>), gr, bl, 0, st, g, sd, stage, (const float2*)in,
-                         (const float2*)ye, (double2*)y, (float2*)yf, (float2*)vout, (float2*)delta, eh, e0, h,
-                         flag);
-  }
-}
-
 void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
                         void* yf, void* out, double h, int* flag, hipStream_t st) {
   StrideDigits sd;
@@ -1020,6 +999,28 @@ void launch_full_horner(int stage, int precision, const GridArgs& g, const void*
     case 6: full_launch_n<6>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
     case 7: full_launch_n<7>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
     default: full_launch_n<8>(stage, precision, g, sd, gr, bl, in, x1, y, yf, out, h, flag, st); break;
+  }
+}
+
+int lawson_row_blocks(const GridArgs& g) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((g.points + 255) / 256, 1024));
+}
+
+StrideDigits lawson_row_digits(const GridArgs& g, int row_blocks) { return digits_for(g, (int64_t)row_blocks * 256); }
+
+void launch_lawson_group(int stage, int precision, bool real, const LawsonItem* items, int nitems, int row_blocks,
+                         double h, int* flag, hipStream_t st) {
+  dim3 gr(row_blocks, nitems), bl(256);
+  if (precision == HGF_FP64) {
+    if (real)
+      hipLaunchKernelGGL((k_lawson_group<double, double, double>), gr, bl, 0, st, items, stage, h, flag);
+    else
+      hipLaunchKernelGGL((k_lawson_group<double2, double2, double>), gr, bl, 0, st, items, stage, h, flag);
+  } else {
+    if (real)
+      hipLaunchKernelGGL((k_lawson_group<float, double, float>), gr, bl, 0, st, items, stage, h, flag);
+    else
+      hipLaunchKernelGGL((k_lawson_group<float2, double2, float>), gr, bl, 0, st, items, stage, h, flag);
   }
 }
 
