@@ -199,26 +199,34 @@ def batch_throughput(hgf, torch, steps: int):
             "sequential_seconds": el_seq, "autotune_seconds": tune_s}
 
 
-def network_timing(hgf, torch):
+def network_timing(hgf, torch, five_only: bool = False):
     """The driven, exchange-coupled network of the paper's example (Table I
     parameters, secular dissipator at zero temperature, observable prod_j a_j,
     horizon w_q t / pi = 10, 100 RK4 steps) for 1 to 5 modes at cutoff 6, FP64,
     on the full (k, l) grid; the operator error on the three-level truncation
     against the paper's reference recipe (cutoff 7, half the step) for up to 4
-    modes."""
+    modes.  Five modes are also run in mixed precision, and on the untiled
+    stage kernel in both precisions; per stage: the wall time of the 400
+    stages over 4, and the algorithmic bandwidth (44 B per point-stage in
+    FP64, 28 B in mixed: the stage grids once, the state twice in stage 4)."""
     import synth
     runs = []
-    for n in (1, 2, 3, 4, 5):
-        w = synth.table1_network(n, 6)
-        op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="fp64")
-        pts = op.info()["total_points"]
+
+    def timed(op, w):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hgf.evolve(op, w.t_total, w.dt)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    for n in () if five_only else (1, 2, 3, 4, 5):
+        w = synth.table1_network(n, 6)
+        op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="fp64")
+        pts = op.info()["total_points"]
+        el = timed(op, w)
         rec = {"modes": n, "cutoff": 6, "grid_points": pts, "steps": w.n_steps, "seconds": el,
-               "value": pts * 4 * w.n_steps / el, "unit": "point-stage updates/s"}
+               "value": pts * 4 * w.n_steps / el, "unit": "point-stage updates/s",
+               "kernel": "tiled" if op.tile_config(0)["nfast"] else "untiled"}
         if n <= 4:
             wr = synth.table1_network(n, 7)
             ref = hgf.map_operator(hgf.define_system(wr.system), factors=wr.factors, precision="fp64")
@@ -229,8 +237,25 @@ def network_timing(hgf, torch):
         del op
         runs.append(rec)
         log(f"network {n} modes: {el:.3f} s")
+    five = []
+    w = synth.table1_network(5, 6)
+    for prec, nbytes in (("fp64", 44), ("mixed", 28)):
+        for kernel in ("tiled", "untiled"):
+            op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision=prec)
+            if kernel == "untiled":
+                op.set_tile_config(0, 0)
+            hgf.evolve(op, 2 * w.dt, w.dt)  # warm-up (graph capture)
+            el = timed(op, w)
+            pts = op.info()["total_points"]
+            stage_s = el / (4 * w.n_steps)
+            five.append({"precision": prec, "kernel": kernel, "stage_us": 1e6 * stage_s,
+                         "value": pts / stage_s, "unit": "point-stage updates/s",
+                         "algorithmic_GBps": nbytes * pts / stage_s / 1e9,
+                         "hbm_frac": nbytes * pts / stage_s / 1e9 / HBM_PEAK_GBS})
+            del op
+            log(f"network 5 modes {prec} {kernel}: {1e6 * stage_s:.0f} us per stage")
     return {"workload": "Table I network (chain, drive on mode 1), cutoff 6, T = 1/700 us, dt = T/100, FP64",
-            "runs": runs}
+            "runs": runs, "five_modes": five}
 
 
 def gradient_timing(hgf, torch, t_total: float):
@@ -261,9 +286,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
-    ap.add_argument("--only", choices=["network"], default=None,
+    ap.add_argument("--only", choices=["network", "network5"], default=None,
                     help="run one section alone and print its JSON (for profiling it): network = the Table I "
-                         "network for 1 to 5 modes")
+                         "network for 1 to 5 modes, network5 = its five-mode runs alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -279,9 +304,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     hgf.load_library()
-    if args.only == "network":
-        print(json.dumps({"network": network_timing(hgf, torch)}))
-        return
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -290,6 +312,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 elementwise passes reading and writing 1 GiB")
         del a, b
+    if args.only in ("network", "network5"):
+        print(json.dumps({"network": network_timing(hgf, torch, five_only=args.only == "network5")}))
+        return
     w = synth.large_c4()
     pts = int(np.prod(w.system.cutoff))
     S = hgf.define_system(w.system)

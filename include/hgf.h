@@ -110,7 +110,12 @@ typedef struct {
    * entry is non-zero the sectors are coupled: every operator is then one
    * function on the full (k, l) grid (2N axes, at most 8 modes and 2^28
    * points), merged layout and HGF_RK4 only, and hgf_grad and
-   * hgf_get_function return HGF_EUNSUPPORTED (read it with hgf_reconstruct). */
+   * hgf_get_function return HGF_EUNSUPPORTED (read it with hgf_reconstruct).
+   * The modes are laid out by coupling (the pair with the most drive and
+   * exchange terms between them last).  Its stage kernel tiles the (k, l)
+   * block of the last two when there are at least three modes, that block
+   * holds 256 to 4096 points and the grid at least 256 such tiles (see
+   * hgf_set_tile_config); otherwise it runs untiled. */
   const double* drive;      /* [2N] complex Omega_j (re, im), rad/us:
                                H += Omega_j a_j^+ + conj(Omega_j) a_j */
   const double* exchange;   /* [N*N] J_ij, rad/us, symmetric, diagonal ignored:
@@ -312,6 +317,10 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
 /*
  * Set the launch shape of function idx (inputs nfast, threads, xblock, pipe,
  * wgs_per_cu, resident, walk_block).
+ * On a network operator's full (k, l) grid nfast is 0 (untiled kernel) or 4
+ * (tiles of the last two modes' (k, l) block, the four fastest axes), with
+ * threads, wgs_per_cu and walk_block; xblock, pipe and resident must be 0.
+ * hgf_autotune leaves network operators alone.
  * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
  * register budget), asks a real grid for the untiled kernel, or asks for the
  * resident form where the grid is not a single tile of at most 4096 points;

@@ -897,6 +897,246 @@ static double full_generator_bound(const FullTables& ft) {
   return erange + dmax + b;
 }
 
+// Tile records of a network operator's tiled stage kernel (layout: FullTileRec
+// then FullTerm entries, `rec_bytes` per tile).  Tile t is the (k, l) block of
+// the last two modes at slow coordinates (k_0, l_0, ..., k_{N-3}, l_{N-3}) =
+// the mixed-radix digits of t.  Terms: for every slow mode its jumps and
+// drive; for every exchange pair with a slow mode its four shifts (an
+// exchange with P or Q also shifts that fast axis, checked per point).
+static std::vector<char> full_tile_records(const GridArgs& g, const FullTables& ft, int& rec_bytes) {
+  const int n = ft.n, P = n - 2, Q = n - 1, ns = n - 2;
+  int64_t ntiles = 1;
+  for (int j = 0; j < ns; ++j) ntiles *= (int64_t)ft.nc[j] * ft.nc[j];
+  auto sk = [&](int j) { return (int32_t)g.stride[2 * j]; };
+  auto sl = [&](int j) { return (int32_t)g.stride[2 * j + 1]; };
+  std::vector<std::vector<FullTerm>> terms((size_t)ntiles);
+  std::vector<FullTileRec> heads((size_t)ntiles);
+  size_t umax = 0;
+  int k[kMaxFullModes], l[kMaxFullModes];
+  for (int64_t t = 0; t < ntiles; ++t) {
+    int64_t r = t;
+    for (int j = ns - 1; j >= 0; --j) {
+      l[j] = (int)(r % ft.nc[j]);
+      r /= ft.nc[j];
+      k[j] = (int)(r % ft.nc[j]);
+      r /= ft.nc[j];
+    }
+    FullTileRec h{};
+    std::vector<FullTerm>& tv = terms[(size_t)t];
+    auto add = [&](int32_t off, double cr, double ci, int32_t meta) {
+      if (cr != 0.0 || ci != 0.0) tv.push_back(FullTerm{off, meta, cr, ci});
+    };
+    for (int j = 0; j < ns; ++j) {
+      const int kj = k[j], lj = l[j], nc = ft.nc[j];
+      h.lam_re += ft.dk[j][kj] + ft.dk[j][lj] - ft.gphi[j] * (double)((kj - lj) * (kj - lj));
+      h.lam_im += ft.e[j][kj] - ft.e[j][lj];
+      for (int i = 0; i < j; ++i) h.lam_im += ft.chi[i][j] * (double)(k[i] * kj - l[i] * lj);
+      for (int m = 0; m < 2; ++m) {
+        h.ck[m] += ft.chi[j][P + m] * kj;
+        h.cl[m] += ft.chi[j][P + m] * lj;
+      }
+      // jumps: g(k - e_j, l - e_j), g(k + e_j, l + e_j)
+      if (!ft.secular || kj == lj) {
+        if (kj >= 1 && lj >= 1) add(-(sk(j) + sl(j)), ft.adn[j][ft.secular ? kj : 0], 0.0, 0);
+        if (kj + 1 < nc && lj + 1 < nc)
+          add(sk(j) + sl(j), ft.secular ? ft.aup[j][kj] : ft.aup[j][0] * (double)((kj + 1) * (lj + 1)), 0.0, 0);
+      }
+      // drive: i [Om g(k-e) + conj(Om)(k+1) g(k+e) - Om (l+1) g(l+e) - conj(Om) g(l-e)]
+      const double orr = ft.drive_re[j], oi = ft.drive_im[j];
+      if (orr != 0.0 || oi != 0.0) {
+        if (kj >= 1) add(-sk(j), -oi, orr, 0);
+        if (kj + 1 < nc) add(sk(j), oi * (kj + 1), orr * (kj + 1), 0);
+        if (lj + 1 < nc) add(sl(j), oi * (lj + 1), -orr * (lj + 1), 0);
+        if (lj >= 1) add(-sl(j), -oi, -orr, 0);
+      }
+    }
+    // exchange i < j with i slow: i J [(k_j+1) g(k - e_i + e_j) + (k_i+1) g(k - e_j + e_i)
+    //                                  - (l_i+1) g(l - e_j + e_i) - (l_j+1) g(l - e_i + e_j)]
+    for (int j = 1; j < n; ++j)
+      for (int i = 0; i < std::min(j, ns); ++i) {
+        const double J = ft.exch[i][j];
+        if (J == 0.0) continue;
+        const int nci = ft.nc[i], ncj = ft.nc[j], ki = k[i], li = l[i];
+        if (j < ns) {
+          const int kj = k[j], lj = l[j];
+          if (ki >= 1 && kj + 1 < ncj) add(-sk(i) + sk(j), 0.0, J * (kj + 1), 0);
+          if (kj >= 1 && ki + 1 < nci) add(-sk(j) + sk(i), 0.0, J * (ki + 1), 0);
+          if (lj >= 1 && li + 1 < nci) add(-sl(j) + sl(i), 0.0, -J * (li + 1), 0);
+          if (li >= 1 && lj + 1 < ncj) add(-sl(i) + sl(j), 0.0, -J * (lj + 1), 0);
+        } else {  // j = P or Q: fast axes 2 (j - P) (k_j) and 2 (j - P) + 1 (l_j)
+          const int32_t ak = 2 * (j - P), al = ak + 1;
+          if (ki >= 1) add(-sk(i) + sk(j), 0.0, J, ak | kFullShift | kFullUp | kFullFactor);
+          if (ki + 1 < nci) add(-sk(j) + sk(i), 0.0, J * (ki + 1), ak | kFullShift);
+          if (li + 1 < nci) add(-sl(j) + sl(i), 0.0, -J * (li + 1), al | kFullShift);
+          if (li >= 1) add(-sl(i) + sl(j), 0.0, -J, al | kFullShift | kFullUp | kFullFactor);
+        }
+      }
+    (void)Q;
+    h.nterms = (int32_t)tv.size();
+    heads[(size_t)t] = h;
+    umax = std::max(umax, tv.size());
+  }
+  rec_bytes = (int)(sizeof(FullTileRec) + umax * sizeof(FullTerm));
+  std::vector<char> out((size_t)ntiles * rec_bytes, 0);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    char* b = out.data() + (size_t)t * rec_bytes;
+    std::memcpy(b, &heads[(size_t)t], sizeof(FullTileRec));
+    if (!terms[(size_t)t].empty())
+      std::memcpy(b + sizeof(FullTileRec), terms[(size_t)t].data(), terms[(size_t)t].size() * sizeof(FullTerm));
+  }
+  return out;
+}
+
+// Configure the tiled stage kernel of a network operator (at least three
+// modes; a tile of 256 to 4096 points whose LDS fits 64 KB; records at most a
+// quarter of the grid's state bytes; unless c.nfast asks for it, at least 256
+// tiles).  c.threads (0: the size with the least
+// idle lanes in the last round), c.wgs_per_cu and c.wblock (-1: 3 from four
+// modes on) apply.  Returns false, leaving f unchanged, when the kernel does
+// not fit.
+static bool configure_full_tiles(Function& f, const FullTables& ft, int precision, const TileChoice& c) {
+  const int n = ft.n;
+  if (n < 3) return false;
+  const int ncP = ft.nc[n - 2], ncQ = ft.nc[n - 1];
+  const int T = ncP * ncP * ncQ * ncQ;
+  if (T < 256 || T > 512 * full_tiled_max_rounds()) return false;
+  // by default only grids of at least 256 tiles (fewer leave CUs idle: the
+  // untiled kernel was faster on the three-mode network of 36 tiles)
+  if (c.nfast < 0 && f.ga.points / T < 256) return false;
+  const size_t lds = full_tiled_lds_bytes(precision, T);
+  if (lds > 65536) return false;
+  int threads = c.threads;
+  if (threads == 0) {
+    int64_t best = -1;
+    for (int th = 128; th <= 512; th += 64) {
+      const int64_t r = (T + th - 1) / th;
+      if (r > full_tiled_max_rounds()) continue;
+      if (best < 0 || r * th < best) {
+        best = r * th;
+        threads = th;
+      }
+    }
+  }
+  if (threads < 64 || threads > 512 || threads % 64 != 0 || (T + threads - 1) / threads > full_tiled_max_rounds())
+    return false;
+  int occ = full_tiled_blocks_per_cu(precision, threads, (int)lds);
+  if (occ <= 0 || c.wgs_per_cu > occ) return false;
+  if (c.wgs_per_cu > 0) occ = c.wgs_per_cu;
+  GridArgs g = f.ga;
+  int rec_bytes = 0;
+  std::vector<char> rec = full_tile_records(g, ft, rec_bytes);
+  const int64_t ntiles = g.points / T;
+  if ((int64_t)rec.size() > std::max<int64_t>((int64_t)64 << 20, g.points * 16 / 4)) return false;
+  // walk order: blocks of 3 along every slow axis unless set (fastest
+  // measured on the five-mode, cutoff-6 network in both precisions)
+  const int wblock = c.wblock >= 0 ? c.wblock : (n >= 4 ? 3 : 0);
+  std::vector<uint32_t> order;
+  if (wblock >= 2) {
+    GridArgs w = g;
+    w.nfast = 4;
+    w.wblock = wblock;
+    order = walk_order(w);
+  }
+  const size_t rb = (rec.size() + 255) / 256 * 256;
+  rec.resize(rb + order.size() * sizeof(uint32_t), 0);
+  if (!order.empty()) std::memcpy(rec.data() + rb, order.data(), order.size() * sizeof(uint32_t));
+  void* d = dmalloc(rec.size());
+  const hipError_t e = hipMemcpy(d, rec.data(), rec.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    dfree(d);
+    hip_check(e, "upload tile records");
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  g.tiles = d;
+  g.walk = order.empty() ? nullptr : (const uint32_t*)((const char*)d + rb);
+  g.ftile = T;
+  g.fntiles = ntiles;
+  g.frec = rec_bytes;
+  g.fthreads = threads;
+  g.flds = (int)lds;
+  g.fwblock = order.empty() ? 0 : wblock;
+  g.fwgs = c.wgs_per_cu;
+  g.fblocks = (int)std::max<int64_t>(8, std::min<int64_t>((int64_t)cus * occ, 8 * ((ntiles + 7) / 8)));
+  dfree(f.ttab);
+  f.ttab = d;
+  f.ga = g;
+  return true;
+}
+
+// Back to the untiled stage kernel.
+static void drop_full_tiles(Function& f) {
+  f.ga.fblocks = 0;
+  f.ga.tiles = nullptr;
+  f.ga.walk = nullptr;
+  dfree(f.ttab);
+}
+
+// Order of the modes on a network operator's full grid: position p holds mode
+// perm[p] (slowest first) and the last two positions form the tiles.  The
+// pair whose own drives and mutual exchange give the most neighbour terms
+// goes last (those terms then read LDS); then, from the fast end, the mode
+// with the most exchange terms to the modes already placed, plus its own
+// drive terms (so the remaining terms reach near tiles).  Ties keep the given
+// order.
+static void full_mode_order(const System& s, int* perm) {
+  const int n = s.n;
+  for (int p = 0; p < n; ++p) perm[p] = p;
+  if (n < 3) return;
+  auto drv = [&](int j) { return (s.drive_re[j] != 0.0 || s.drive_im[j] != 0.0) ? 4 : 0; };
+  auto ex = [&](int i, int j) { return s.exch[i][j] != 0.0 ? 4 : 0; };
+  int bp = n - 2, bq = n - 1, best = drv(n - 2) + drv(n - 1) + ex(n - 2, n - 1);
+  for (int j = n - 1; j >= 1; --j)
+    for (int i = j - 1; i >= 0; --i) {
+      const int sc = drv(i) + drv(j) + ex(i, j);
+      if (sc > best) {
+        best = sc;
+        bp = i;
+        bq = j;
+      }
+    }
+  bool placed[kMaxFullModes] = {};
+  perm[n - 2] = bp;
+  perm[n - 1] = bq;
+  placed[bp] = placed[bq] = true;
+  for (int p = n - 3; p >= 0; --p) {
+    int bj = -1, bs = -1;
+    for (int j = n - 1; j >= 0; --j) {
+      if (placed[j]) continue;
+      int sc = drv(j);
+      for (int q = p + 1; q < n; ++q) sc += ex(j, perm[q]);
+      if (sc > bs) {
+        bs = sc;
+        bj = j;
+      }
+    }
+    perm[p] = bj;
+    placed[bj] = true;
+  }
+}
+
+// The system with its modes reordered: mode p of the result is mode perm[p].
+static System permute_modes(const System& s, const int* perm) {
+  System t = s;
+  for (int p = 0; p < s.n; ++p) {
+    const int j = perm[p];
+    t.nc[p] = s.nc[j];
+    t.det[p] = s.det[j];
+    t.kerr[p] = s.kerr[j];
+    t.g1[p] = s.g1[j];
+    t.gphi[p] = s.gphi[j];
+    t.nth[p] = s.nth[j];
+    for (int c = 0; c < kMaxCutoff; ++c) t.nlev[p][c] = s.nlev[j][c];
+    t.drive_re[p] = s.drive_re[j];
+    t.drive_im[p] = s.drive_im[j];
+    for (int q = 0; q < s.n; ++q) {
+      t.chi[p][q] = s.chi[j][perm[q]];
+      t.exch[p][q] = s.exch[j][perm[q]];
+    }
+  }
+  return t;
+}
+
 // A network operator: every sector of the input scattered into one full
 // (k, l) grid, g(k, l) = <k|A|l> / sqrt(k! l!).
 static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) {
@@ -909,6 +1149,8 @@ static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) 
   std::map<std::vector<int>, std::vector<cd>> merged;
   std::vector<Coeff> coeffs;
   collect_coeffs(s, d, merged, coeffs, false);
+  int perm[kMaxFullModes];
+  full_mode_order(s, perm);
   std::vector<cd> grid((size_t)(dim * dim), 0.0);
   bool any = false;
   for (auto& kv : merged) {
@@ -926,12 +1168,13 @@ static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) 
       if (val != 0.0) {
         any = true;
         if (std::abs(val) < FLT_MIN) op->underflow++;
-        int64_t K = 0, L = 0;
-        for (int j = 0; j < n; ++j) {
-          K = K * s.nc[j] + m[j] + u[j];
-          L = L * s.nc[j] + m[j] + v[j];
+        int64_t at = 0;  // axes k, l of the mode at each position
+        for (int p = 0; p < n; ++p) {
+          const int j = perm[p];
+          at = at * s.nc[j] + m[j] + u[j];
+          at = at * s.nc[j] + m[j] + v[j];
         }
-        grid[(size_t)(K * dim + L)] = val;
+        grid[(size_t)at] = val;
       }
       for (int j = n - 1; j >= 0; --j) {
         if (++m[j] < e[j]) break;
@@ -948,16 +1191,19 @@ static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) 
   t.lam0 = 0.0;
   for (int a = 0; a < 2 * n; ++a) {
     t.d[a] = t.u[a] = t.v[a] = 0;
-    t.ext[a] = s.nc[a % n];
+    t.ext[a] = s.nc[perm[a / 2]];
     t.lam[a].assign(t.ext[a], cd(0.0));
     t.alpha[a].assign(t.ext[a], 0.0);
     t.beta[a].assign(t.ext[a], 0.0);
   }
-  const FullTables ft = full_tables(s);
+  const FullTables ft = full_tables(permute_modes(s, perm));
+  std::copy(perm, perm + n, f.fperm);
+  f.fhost.assign(1, ft);
   f.full_bound = full_generator_bound(ft);
   f.ftab = dmalloc(sizeof(FullTables));
   hip_check(hipMemcpy(f.ftab, &ft, sizeof(FullTables), hipMemcpyHostToDevice), "upload tables");
   fill_grid_args(f, op->precision, false);
+  if (!stage_kernel_generic()) configure_full_tiles(f, ft, op->precision, TileChoice{});
   alloc_function_buffers(f, op->precision);
   upload_state(f, grid, op->precision);
 }
@@ -1197,7 +1443,7 @@ static void generic_stage(const PlanItem& it, int s, int* flag, hipStream_t st) 
   Function& f = *it.f;
   const void* in[4] = {it.precision == HGF_MIXED ? f.yf : f.y, f.s1, f.s2, f.s3};
   void* out[4] = {f.s1, f.s2, f.s3, nullptr};
-  (f.full ? launch_full_horner : launch_horner)(s, it.precision, f.ga, in[s - 1], f.s1, f.y,
+  (f.full ? (f.ga.fblocks > 0 ? launch_full_tiled : launch_full_horner) : launch_horner)(s, it.precision, f.ga, in[s - 1], f.s1, f.y,
                                                 it.precision == HGF_MIXED ? f.yf : nullptr, out[s - 1], it.h, flag,
                                                 st);
 }
@@ -1891,6 +2137,7 @@ static void autotune_impl(hgf_operator* ops, int n, double h, const char* cache_
     if (op->layout != HGF_MERGED) continue;
     for (auto& f : op->fn) {
       if ((f.ga.blocks == 0 && f.real) || f.resident) continue;  // resident: one workgroup, nothing to tune
+      if (f.full) continue;  // network operators keep their shape (hgf_set_tile_config sets it)
       const std::string key = tune_key(dev, f, op->precision);
       auto it = cache.find(key);
       const bool known = it != cache.end() && (!(flags & HGF_TUNE_FORCE) || fresh.count(key));
@@ -2025,16 +2272,16 @@ static void validate_state(const System& s, const hgf_state_desc* psi) {
 }
 
 // per-axis weights w_j(m) = sqrt(k! l!) conj(c_k) c_l of one sector, concatenated;
-// on a network operator's full grid the k axes take sqrt(k!) conj(c_k) and the
-// l axes sqrt(l!) c_l (the weight of <k|A|l> factorises over them)
+// on a network operator's full grid the k axes (even) take sqrt(k!) conj(c_k)
+// and the l axes (odd) sqrt(l!) c_l (the weight of <k|A|l> factorises over them)
 static std::vector<cd> sector_weights(const System& s, const Function& f, const std::vector<std::vector<cd>>& amps) {
   const SectorTables& t = f.tab;
   std::vector<cd> w;
   if (f.full) {
     for (int a = 0; a < t.n; ++a) {
-      const int j = a % s.n;
+      const int j = f.fperm[a / 2];
       for (int m = 0; m < t.ext[a]; ++m)
-        w.push_back(a < s.n ? sqrt_factorial(m) * std::conj(amps[j][m]) : sqrt_factorial(m) * amps[j][m]);
+        w.push_back(a % 2 == 0 ? sqrt_factorial(m) * std::conj(amps[j][m]) : sqrt_factorial(m) * amps[j][m]);
     }
     return w;
   }
@@ -2127,11 +2374,11 @@ static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStr
       int64_t p = ln;
       for (int j = 0; j < n; ++j) place[j] = p /= levels;
     }
-    if (f.full) {  // axes k_0 .. k_{N-1}, l_0 .. l_{N-1}
+    if (f.full) {  // axes k, l of the mode at each position
       for (int a = 0; a < 2 * n; ++a) {
-        const int j = a % n;
-        b.rp[a] = a < n ? place[j] : 0;
-        b.cp[a] = a < n ? 0 : place[j];
+        const int j = f.fperm[a / 2];
+        b.rp[a] = a % 2 == 0 ? place[j] : 0;
+        b.cp[a] = a % 2 == 0 ? 0 : place[j];
         b.ur[a] = b.uc[a] = 0;
         b.b[a] = levels;
         b.foff[a] = (int)fac.size();
@@ -2587,6 +2834,17 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
     if (!op || !out) fail(HGF_EINVAL, "NULL argument");
     if (idx < 0 || idx >= (int32_t)op->fn.size()) fail(HGF_EINVAL, "function index out of range");
     const Function& f = op->fn[idx];
+    if (f.full) {  // network operator: tiles of its last two modes, or untiled
+      const bool ft = f.ga.fblocks > 0;
+      *out = hgf_tile_config{};
+      out->nfast = ft ? 4 : 0;
+      out->threads = ft ? f.ga.fthreads : 0;
+      out->wgs_per_cu = ft ? f.ga.fwgs : 0;
+      out->walk_block = ft ? f.ga.fwblock : 0;
+      out->blocks = ft ? f.ga.fblocks : 0;
+      out->tile_points = ft ? f.ga.ftile : 1;
+      return;
+    }
     const bool tiled = f.ga.blocks > 0;
     out->nfast = tiled ? f.ga.nfast : 0;
     out->threads = tiled ? f.ga.threads : 0;
@@ -2618,6 +2876,17 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
     Function& f = op->fn[idx];
+    if (f.full) {
+      if (cfg->xblock != 0 || cfg->pipe != 0 || cfg->resident != 0 || (cfg->nfast != 0 && cfg->nfast != 4))
+        fail(HGF_EINVAL, "a network operator takes nfast 0 (untiled) or 4 (tiles of its last two modes), "
+                         "without xblock, pipe or the resident form");
+      if (cfg->nfast == 0)
+        drop_full_tiles(f);
+      else if (!configure_full_tiles(f, f.fhost.at(0), op->precision, c))
+        fail(HGF_EINVAL, "tile configuration not feasible for this network grid");
+      drop_plan(op);
+      return;
+    }
     if (cfg->resident) {  // check on a copy first: the function is unchanged on error
       Function probe;
       probe.split = f.split;

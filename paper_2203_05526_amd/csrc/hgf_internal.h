@@ -49,8 +49,12 @@ struct System {
 };
 
 // Full (k, l) grid of a network operator: g(k, l) = <k|A|l> / sqrt(k! l!) on
-// 2N axes (k_0 .. k_{N-1}, l_0 .. l_{N-1}), row-major, i.e. the matrix A[K, L]
-// scaled.  Per-mode tables of its generator (device copy read by the kernel).
+// 2N axes, the k and l axes of each mode side by side (k, l of the mode at
+// position 0, then position 1, ...), row-major: the (k, l) blocks of the last
+// positions are contiguous, so a tile of the last two holds every neighbour
+// along their axes.  The modes are placed by coupling (Function::fperm); the
+// per-mode tables of the generator are in position order (device copy read
+// by the kernels).
 constexpr int kMaxFullModes = kMaxModes / 2;
 struct FullTables {
   int n, secular;
@@ -128,7 +132,41 @@ struct GridArgs {
   const float* beta_f;
   const float* alpha_f;
   const FullTables* full;   // network operator on the full (k, l) grid, else NULL
+  // tiled stage kernel of a network operator (tiles: the last two modes'
+  // (k, l) block; records at `tiles`, walk order at `walk`)
+  int fblocks;              // persistent grid size (0: the untiled kernel)
+  int fthreads;             // workgroup size
+  int flds;                 // dynamic LDS bytes
+  int ftile;                // points per tile
+  int frec;                 // bytes per tile record
+  int fwblock;              // walk order: 0 row-major, B >= 2 blocks of B along every slow axis
+  int fwgs;                 // resident workgroups per CU requested (0: all that fit)
+  int64_t fntiles;          // tiles
 };
+
+// Per-tile record of a network operator's tiled stage kernel (host-built, read
+// with scalar loads), followed by `nterms` FullTerm entries: the slow modes'
+// part of the diagonal (real: damping and dephasing; imaginary: E(k) - E(l)
+// with the cross-Kerr products among slow modes), the cross-Kerr sums that
+// multiply the fast coordinates (ck[m] = sum_i chi_{i,P+m} k_i over slow i,
+// cl[m] the same with l_i), and the neighbour terms that leave the tile.
+struct FullTileRec {
+  double lam_re, lam_im;
+  double ck[2], cl[2];
+  int32_t nterms, pad;
+};
+// One neighbour term: element offset from the point (slow and fast shifts),
+// complex coefficient, and an optional shift of one fast axis (meta bits 0-1:
+// axis k_P, l_P, k_Q, l_Q; kFullShift: a shift is present; kFullUp: +1, else
+// -1; kFullFactor: the coefficient takes the factor (x + 1) of that axis'
+// coordinate x).  The kernel drops the term where the shifted coordinate
+// leaves the grid.
+struct FullTerm {
+  int32_t off;
+  int32_t meta;
+  double cr, ci;
+};
+constexpr int32_t kFullShift = 4, kFullUp = 8, kFullFactor = 16;
 
 // Arguments of one member of a grouped (tiled) stage launch, kept in device
 // memory: the member's grid, its buffers per stage and its step size.
@@ -208,6 +246,8 @@ struct Function {
   bool full = false;
   void* ftab = nullptr;
   double full_bound = 0.0;  // bound on the spectral radius of its generator
+  int fperm[kMaxFullModes] = {};   // mode held at each position of the grid (slowest first)
+  std::vector<FullTables> fhost;   // host copy of the tables (one entry), in position order
 };
 
 struct StepPlan;

@@ -54,6 +54,14 @@ StrideDigits lawson_row_digits(const GridArgs& g, int row_blocks);
 // Horner RK4 stage of a network operator on its full (k, l) grid (g.full set).
 void launch_full_horner(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
                         void* yf, void* out, double h, int* flag, hipStream_t st);
+// Tiled form of the same stage (g.fblocks > 0): persistent grid, tile records
+// at g.tiles; its LDS bytes for a tile of `tile_points`, its lane-round limit
+// and its resident workgroups per CU.
+void launch_full_tiled(int stage, int precision, const GridArgs& g, const void* in, const void* x1, void* y,
+                       void* yf, void* out, double h, int* flag, hipStream_t st);
+size_t full_tiled_lds_bytes(int precision, int tile_points);
+int full_tiled_max_rounds();
+int full_tiled_blocks_per_cu(int precision, int threads, int lds_bytes);
 // form: 0 grouped kernel, 1 single-grid kernel, 2 single-grid pipelined kernel
 int tiled_max_blocks_per_cu(int nfast, int nslow, int threads, int precision, int lds_bytes, bool real,
                             int form);

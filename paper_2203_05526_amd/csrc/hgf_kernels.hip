@@ -192,8 +192,9 @@ __device__ __forceinline__ void xcd_range(int64_t points, int64_t& begin, int64_
 // ------------------------------------------------------------ network operator, full (k, l) grid
 //
 // With a drive and exchange (Eq. (16)) the sectors are coupled; the operator
-// is one grid g(k, l) on 2N axes.  In g the adjoint equation reads, per point
-// (k_j, l_j the coordinates of axes j and N + j, s_kj, s_lj their strides):
+// is one grid g(k, l) on 2N axes, interleaved per mode (k_0, l_0, k_1, l_1,
+// ...; the last axis fastest).  In g the adjoint equation reads, per point
+// (k_j, l_j the coordinates of axes 2j and 2j + 1):
 //   diagonal  i (E(k) - E(l)) + sum_j [dk_j(k_j) + dk_j(l_j) - gphi_j (k_j - l_j)^2]
 //   jumps     adn_j g(k - e_j, l - e_j) + aup_j g(k + e_j, l + e_j)
 //             (Lindblad: adn = gamma1 (1 + nth), aup = gamma1 nth (k_j+1)(l_j+1);
@@ -218,7 +219,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
   uint64_t kp = 0, lp = 0;
 #pragma unroll
   for (int j = 0; j < n; ++j) {
-    const int kj = w.c[j], lj = w.c[n + j];
+    const int kj = w.c[2 * j], lj = w.c[2 * j + 1];
     kp |= (uint64_t)kj << (5 * j);
     lp |= (uint64_t)lj << (5 * j);
     ek += ft->e[j][kj];
@@ -226,8 +227,8 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
     dr += ft->dk[j][kj] + ft->dk[j][lj] - ft->gphi[j] * (double)((kj - lj) * (kj - lj));
 #pragma unroll
     for (int i = 0; i < j; ++i) {
-      ek += ft->chi[i][j] * (double)(w.c[i] * kj);
-      el += ft->chi[i][j] * (double)(w.c[n + i] * lj);
+      ek += ft->chi[i][j] * (double)(w.c[2 * i] * kj);
+      el += ft->chi[i][j] * (double)(w.c[2 * i + 1] * lj);
     }
   }
   const CT c = load_as<R>(in, i0);
@@ -238,7 +239,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
 #pragma unroll 1
   for (int j = 0; j < n; ++j) {
     const int kj = (int)((kp >> (5 * j)) & 31u), lj = (int)((lp >> (5 * j)) & 31u), nc = ft->nc[j];
-    const int64_t sk = g.stride[j], sl = g.stride[n + j];
+    const int64_t sk = g.stride[2 * j], sl = g.stride[2 * j + 1];
     if (!ft->secular || kj == lj) {
       if (kj >= 1 && lj >= 1) {
         const R a = (R)ft->adn[j][ft->secular ? kj : 0];
@@ -292,7 +293,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
       const int ki = (int)((kp >> (5 * i)) & 31u), kj = (int)((kp >> (5 * j)) & 31u);
       const int li = (int)((lp >> (5 * i)) & 31u), lj = (int)((lp >> (5 * j)) & 31u);
       const int nci = ft->nc[i], ncj = ft->nc[j];
-      const int64_t ski = g.stride[i], skj = g.stride[j], sli = g.stride[n + i], slj = g.stride[n + j];
+      const int64_t ski = g.stride[2 * i], skj = g.stride[2 * j], sli = g.stride[2 * i + 1], slj = g.stride[2 * j + 1];
       R tr = 0, ti = 0;
       if (ki >= 1 && kj + 1 < ncj) {
         const CT v = load_as<R>(in, i0 - ski + skj);
