@@ -86,6 +86,7 @@ def cpu_baseline(w, steps: int):
     the same grid for a few steps, all host threads."""
     import oracle
     ops = oracle.product_sectors(w.factors)
+    cores = oracle.max_threads()  # before the one-thread run below sets the count to 1
     t0 = time.perf_counter()
     oracle.evolve_steps(w.system, ops, steps, w.dt)
     el = time.perf_counter() - t0
@@ -98,7 +99,7 @@ def cpu_baseline(w, steps: int):
     t1 = time.perf_counter()
     oracle.evolve_steps(s1, oracle.product_sectors(f1), 3, w.dt, nthreads=1)
     el1 = time.perf_counter() - t1
-    return {"value": pts * 4 * steps / el, "unit": "point-stage updates/s", "cores": oracle.max_threads(),
+    return {"value": pts * 4 * steps / el, "unit": "point-stage updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} RK4 steps over all {pts} points of the same 10-mode grid ({el:.1f} s)",
             "single_thread": {"value": 4 ** s1.n_modes * 4 * 3 / el1, "unit": "point-stage updates/s",
