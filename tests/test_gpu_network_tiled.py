@@ -129,23 +129,25 @@ def test_tiled_network_table1_four_modes(hgf):
 
 
 def test_tiled_network_table1_five_modes_against_untiled(hgf):
-    """Five modes, cutoff 6 (60,466,176 points, the bench's grid): two steps of
-    the tiled kernel against the untiled kernel (itself checked against the
-    oracle on smaller grids), on the three lowest levels and the expectation
-    value."""
+    """Five modes, cutoff 6 (60,466,176 points, the bench's grid and launch
+    shape): two steps of the tiled kernel, FP64 and mixed, against the untiled
+    FP64 kernel (itself checked against the oracle on smaller grids), on the
+    three lowest levels and the expectation value."""
     announce("tiled network Table I, 5 modes")
     w = synth.table1_network(5, 6)
-    out = []
-    for nfast in (4, 0):
-        op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="fp64")
+    out = {}
+    for prec, nfast in (("fp64", 4), ("mixed", 4), ("fp64", 0)):
+        op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision=prec)
         if nfast == 0:
             op.set_tile_config(0, 0)
         assert op.tile_config(0)["nfast"] == nfast
         hgf.evolve(op, 2 * w.dt, w.dt)
-        out.append((hgf.reconstruct(op, 3), hgf.expectation(op, w.states[0])))
+        out[prec, nfast] = (hgf.reconstruct(op, 3), hgf.expectation(op, w.states[0]))
         del op
-    assert rel_fro(out[0][0], out[1][0]) < 1e-13
-    assert abs(out[0][1] - out[1][1]) <= 1e-12 * abs(out[1][1])
+    ref = out["fp64", 0]
+    for key, tol in ((("fp64", 4), 1e-13), (("mixed", 4), MIXED_TOL)):
+        assert rel_fro(out[key][0], ref[0]) < tol, key
+        assert abs(out[key][1] - ref[1]) <= 10 * tol * abs(ref[1]), key
 
 
 def test_network_modes_reordered_for_tiles(hgf):
@@ -184,6 +186,29 @@ def test_network_modes_reordered_for_tiles(hgf):
         want = np.conj(c) @ ref @ c
         got = hgf.expectation(op, synth.coherent_state(alphas))
         assert abs(got - want) / abs(want) < (10 * tol if precision == "mixed" else tol)
+
+
+def test_tiled_network_in_a_batch(hgf):
+    """A network operator on the tiled kernel and a sector operator evolved in
+    one batch equal their separate evolves bit for bit."""
+    announce("tiled network batch")
+    a = all_pairs_network((3, 3, 4, 5), 641, "secular")
+    b = synth.random_system((4, 5, 3), 642, scale=2.0)
+    Ma = random_matrix(180, 641)
+    fb = synth.parity_factors((4, 5, 3))
+    runs = []
+    for batched in (True, False):
+        ops = [hgf.map_operator(hgf.define_system(a), dense=Ma, precision="mixed"),
+               hgf.map_operator(hgf.define_system(b), factors=fb, precision="mixed")]
+        ops[0].set_tile_config(0, 4)
+        if batched:
+            hgf.evolve_batch(ops, [0.02, 0.03], [1e-3, 1e-3])
+        else:
+            hgf.evolve(ops[0], 0.02, 1e-3)
+            hgf.evolve(ops[1], 0.03, 1e-3)
+        runs.append([hgf.reconstruct(op, 3) for op in ops])
+    for x, y in zip(*runs):
+        assert np.array_equal(x, y)
 
 
 def test_network_tile_config_errors(hgf):
