@@ -904,7 +904,7 @@ static double full_generator_bound(const FullTables& ft) {
 // drive; for every exchange pair with a slow mode its four shifts (an
 // exchange with P or Q also shifts that fast axis, checked per point).
 static std::vector<char> full_tile_records(const GridArgs& g, const FullTables& ft, int& rec_bytes) {
-  const int n = ft.n, P = n - 2, Q = n - 1, ns = n - 2;
+  const int n = ft.n, P = n - 2, ns = n - 2;  // P, P + 1: the fast modes
   int64_t ntiles = 1;
   for (int j = 0; j < ns; ++j) ntiles *= (int64_t)ft.nc[j] * ft.nc[j];
   auto sk = [&](int j) { return (int32_t)g.stride[2 * j]; };
@@ -971,7 +971,6 @@ static std::vector<char> full_tile_records(const GridArgs& g, const FullTables& 
           if (li >= 1) add(-sl(i) + sl(j), 0.0, -J, al | kFullShift | kFullUp | kFullFactor);
         }
       }
-    (void)Q;
     h.nterms = (int32_t)tv.size();
     heads[(size_t)t] = h;
     umax = std::max(umax, tv.size());
@@ -2437,6 +2436,12 @@ static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStr
 
 // Longest reverse segment captured as one graph (about 12 nodes per step).
 constexpr int64_t kGradGraphSteps = 512;
+// A segment keeps every step's stage grids X1, V1, V2 next to its state when
+// they fit in this many bytes (the reverse sweep then recomputes nothing);
+// otherwise, or with HGF_GRAD_STORE=0 in the environment, it keeps the states
+// only and recomputes the three stages of each step in the sweep (the same
+// numbers either way).
+constexpr int64_t kGradStoreBytes = (int64_t)2 << 30;
 
 static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
                       double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
@@ -2479,8 +2484,12 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     const int64_t pts = f.ga.points;
     const size_t gb = pts * sizeof(double2);
     const int64_t nseg = (M + ce - 1) / ce;
-    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)std::min<int64_t>(ce, std::max<int64_t>(M, 1)) * gb),
-        mu(gb), vb2(gb), vb1(gb), xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
+    const int64_t seg_steps = std::min<int64_t>(ce, std::max<int64_t>(M, 1));
+    const char* store_env = std::getenv("HGF_GRAD_STORE");  // "0": keep states only
+    const bool store = 4 * seg_steps * (int64_t)gb <= kGradStoreBytes && !(store_env && std::string(store_env) == "0");
+    const int64_t per_step = store ? 4 : 1;  // grids kept per step: y (and X1, V1, V2)
+    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)(seg_steps * per_step) * gb), mu(gb), vb2(gb), vb1(gb),
+        xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
     const auto w = sector_weights(sys, f, amps);
     DBuf dw(w.size() * sizeof(double2));
     hip_check(hipMemcpyAsync(dw.p, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
@@ -2528,25 +2537,43 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     double2* seg = segbuf.as<double2>();
     double2* Qp = Q.as<double2>();
     // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
-    // f.y into the segment buffer, then sweep them in reverse.  The work of a
-    // segment depends only on L, so it is captured once per length.
+    // f.y into the segment buffer (with each step's X1, V1, V2 when `store`),
+    // then sweep them in reverse.  The work of a segment depends only on L, so
+    // it is captured once per length.  The stage launches are those of the
+    // forward pass (same kernel, shape and operands), so the recomputed states
+    // equal the checkpointed trajectory bit for bit.
+    auto slot = [&](int64_t i, int k) { return seg + (i * per_step + k) * pts; };  // k: y, X1, V1, V2
     auto segment = [&](int64_t L, hipStream_t s) {
       for (int64_t i = 0; i < L; ++i) {
-        launch_copy2(seg + i * pts, (const double2*)f.y, pts, s);
-        if (i + 1 < L) run_plan_step(*fplan, op.dflag, s);
+        launch_copy2(slot(i, 0), (const double2*)f.y, pts, s);
+        if (!store) {
+          if (i + 1 < L) run_plan_step(*fplan, op.dflag, s);
+          continue;
+        }
+        stage_launch(f, HGF_FP64, 1, slot(i, 0), nullptr, slot(i, 0), nullptr, slot(i, 1), dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 2, slot(i, 1), slot(i, 1), slot(i, 0), nullptr, slot(i, 2), dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 3, slot(i, 2), slot(i, 1), slot(i, 0), nullptr, slot(i, 3), dt, op.dflag, s);
+        if (i + 1 < L)
+          stage_launch(f, HGF_FP64, 4, slot(i, 3), slot(i, 1), f.y, nullptr, nullptr, dt, op.dflag, s);
       }
       for (int64_t i = L - 1; i >= 0; --i) {
-        double2* yn = seg + i * pts;
-        // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
-        stage_launch(f, HGF_FP64, 1, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, s);
-        stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
-        stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
+        double2* yn = slot(i, 0);
+        const double2 *x1 = (const double2*)f.s1, *v1 = (const double2*)f.s2, *v2 = (const double2*)f.s3;
+        if (store) {
+          x1 = slot(i, 1);
+          v1 = slot(i, 2);
+          v2 = slot(i, 3);
+        } else {  // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
+          stage_launch(f, HGF_FP64, 1, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, s);
+          stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
+          stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
+        }
         launch_adjoint_noq(1, f.ga, mu.as<double2>(), nullptr, nullptr, vb2.as<double2>(), dt, s);
         launch_adjoint_noq(2, f.ga, vb2.as<double2>(), nullptr, nullptr, vb1.as<double2>(), dt, s);
         launch_adjoint_noq(3, f.ga, vb1.as<double2>(), mu.as<double2>(), vb2.as<double2>(), xb1.as<double2>(), dt,
                            s);
-        launch_adjoint_q(f.ga, mu.as<double2>(), vb2.as<double2>(), vb1.as<double2>(), xb1.as<double2>(),
-                         (const double2*)f.s3, (const double2*)f.s2, (const double2*)f.s1, yn, Qp, dt, s);
+        launch_adjoint_q(f.ga, mu.as<double2>(), vb2.as<double2>(), vb1.as<double2>(), xb1.as<double2>(), v2, v1,
+                         x1, yn, Qp, dt, s);
         launch_adjoint_noq(4, f.ga, xb1.as<double2>(), mu.as<double2>(), nullptr, mu.as<double2>(), dt, s);
       }
     };
