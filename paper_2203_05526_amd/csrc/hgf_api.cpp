@@ -2434,7 +2434,23 @@ static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStr
 
 // ------------------------------------------------------------------ gradient
 
-// Longest reverse segment captured as one graph (about 12 nodes per step).
+// L^T of a sector's generator as tables of the same stencil form:
+// (L^T mu)(m) = lam(m) mu(m) + sum_j [alpha_j(m_j + 1) mu(m + e_j) + beta_j(m_j - 1) mu(m - e_j)],
+// i.e. alpha'_j(m) = beta_j(m - 1) (0 at m = 0) and beta'_j(m) = alpha_j(m + 1)
+// (0 at the top of the axis): transpose only, no conjugation.
+static SectorTables transposed_tables(const SectorTables& t) {
+  SectorTables r = t;
+  for (int j = 0; j < t.n; ++j) {
+    const int e = t.ext[j];
+    for (int m = 0; m < e; ++m) {
+      r.alpha[j][m] = m >= 1 ? t.beta[j][m - 1] : 0.0;
+      r.beta[j][m] = m + 1 < e ? t.alpha[j][m + 1] : 0.0;
+    }
+  }
+  return r;
+}
+
+// Longest reverse segment captured as one graph (about 10 nodes per step).
 constexpr int64_t kGradGraphSteps = 512;
 // A segment keeps every step's stage grids X1, V1, V2 next to its state when
 // they fit in this many bytes (the reverse sweep then recomputes nothing);
@@ -2490,6 +2506,16 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
     const int64_t per_step = store ? 4 : 1;  // grids kept per step: y (and X1, V1, V2)
     DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)(seg_steps * per_step) * gb), mu(gb), vb2(gb), vb1(gb),
         xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
+    // the adjoint stencils run on the forward stage kernels of L^T
+    Function fa;
+    struct FreeOnExit {
+      Function& f;
+      ~FreeOnExit() { free_function(f); }
+    } fa_guard{fa};
+    fa.tab = transposed_tables(f.tab);
+    fill_grid_args(fa, HGF_FP64, false);
+    DBuf zero(gb);
+    launch_fill_zero(zero.as<double2>(), pts, st);
     const auto w = sector_weights(sys, f, amps);
     DBuf dw(w.size() * sizeof(double2));
     hip_check(hipMemcpyAsync(dw.p, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
@@ -2568,13 +2594,14 @@ static void grad_impl(const System& sys, const hgf_operator_desc* desc, const hg
           stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
           stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
         }
-        launch_adjoint_noq(1, f.ga, mu.as<double2>(), nullptr, nullptr, vb2.as<double2>(), dt, s);
-        launch_adjoint_noq(2, f.ga, vb2.as<double2>(), nullptr, nullptr, vb1.as<double2>(), dt, s);
-        launch_adjoint_noq(3, f.ga, vb1.as<double2>(), mu.as<double2>(), vb2.as<double2>(), xb1.as<double2>(), dt,
-                           s);
-        launch_adjoint_q(f.ga, mu.as<double2>(), vb2.as<double2>(), vb1.as<double2>(), xb1.as<double2>(), v2, v1,
-                         x1, yn, Qp, dt, s);
-        launch_adjoint_noq(4, f.ga, xb1.as<double2>(), mu.as<double2>(), nullptr, mu.as<double2>(), dt, s);
+        double2 *pm = mu.as<double2>(), *pv2 = vb2.as<double2>(), *pv1 = vb1.as<double2>(), *px = xb1.as<double2>();
+        // stage-1 form (out = h' L^T in): B1, B2 and B3's stencil part
+        stage_launch(fa, HGF_FP64, 1, pm, nullptr, pm, nullptr, pv2, 0.5 * dt, op.dflag, s);
+        stage_launch(fa, HGF_FP64, 1, pv2, nullptr, pv2, nullptr, pv1, dt / 3.0, op.dflag, s);
+        stage_launch(fa, HGF_FP64, 1, pv1, nullptr, pv1, nullptr, px, 0.25 * dt, op.dflag, s);
+        launch_adjoint_q(f.ga, pm, pv2, pv1, px, v2, v1, x1, yn, Qp, dt, s);
+        // stage-4 form (y += x1 + (h'/2) L^T in) with x1 = 0, h' = 2h: B4
+        stage_launch(fa, HGF_FP64, 4, px, zero.p, pm, nullptr, nullptr, 2.0 * dt, op.dflag, s);
       }
     };
     std::map<int64_t, std::unique_ptr<GraphHolder>> seg_graphs;

@@ -78,11 +78,9 @@ void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, 
                            double2* partial, hipStream_t st, bool real = false);
 void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
                          double2 analytic, double2* out, hipStream_t st);
-// adjoint stages without parameter products, and the products of a whole step
-void launch_adjoint_noq(int stage, const GridArgs& g, const double2* in, const double2* mu, const double2* vb2,
-                       double2* out, double h, hipStream_t st);
+// parameter products of a reverse step (completes Xb1 in place first)
 void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, const double2* vb1,
-                      const double2* xb1, const double2* v2, const double2* v1, const double2* x1,
+                      double2* xb1, const double2* v2, const double2* v1, const double2* x1,
                       const double2* y, double2* Q, double h, hipStream_t st);
 int marginal_bins(const GridArgs& g);
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st);

@@ -137,36 +137,6 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
   return acc;
 }
 
-// (L^T in)(m): down and up neighbours swap roles, no conjugation.
-template <typename TIN>
-__device__ __forceinline__ double2 apply_LT(const GridArgs& g, const TIN* __restrict__ in,
-                                            const Walker& w) {
-  double lr = g.lam0_re, li = g.lam0_im;
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int j = 0; j < kMaxModes; ++j) {
-    if (j < g.n) {
-      const int m = w.c[j];
-      const double2 lj = g.lam[g.off[j] + m];
-      lr += lj.x;
-      li += lj.y;
-      // L[m+e, m] = alpha(m+1), L[m-e, m] = beta(m-1); out-of-range
-      // neighbours read the centre with a zero coefficient
-      const bool uv = m + 1 < g.ext[j], dv = m >= 1;
-      const double2 upv = to_d2(in[uv ? w.i + g.stride[j] : w.i]);
-      const double2 dn = to_d2(in[dv ? w.i - g.stride[j] : w.i]);
-      const double a = uv ? g.alpha[g.off[j] + m + 1] : 0.0;
-      const double b = dv ? g.beta[g.off[j] + m - 1] : 0.0;
-      acc.x += a * upv.x + b * dn.x;
-      acc.y += a * upv.y + b * dn.y;
-    }
-  }
-  const double2 c = to_d2(in[w.i]);
-  acc.x += lr * c.x - li * c.y;
-  acc.y += lr * c.y + li * c.x;
-  return acc;
-}
-
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
@@ -724,8 +694,7 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __r
 }
 
 // ------------------------------------------------------------ adjoint sweep
-// One reverse RK4 step in the merged form (see k_horner); the stages run as
-// k_adjoint_noq and the products "Q += ..." of all four as one k_adjoint_q:
+// One reverse RK4 step in the merged form (see k_horner):
 //   B1: Vb2 = (h/2) L^T mu                 Q += (h/2) mu  (x) V2
 //   B2: Vb1 = (h/3) L^T Vb2                Q += (h/3) Vb2 (x) V1
 //   B3: Xb1 = mu + Vb2 + Vb1 + (h/4) L^T Vb1   Q += (h/4) Vb1 (x) X1
@@ -734,36 +703,19 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __r
 // parameter derivative of the generator needs:
 //   Q0(m) += a(m) b(m),  Qd_j(m) += a(m) b(m-e_j),  Qu_j(m) += a(m) b(m+e_j).
 // Q is laid out as (1 + 2N) consecutive planes of `points` complex values.
-
-// The four stages without the parameter products (those of a whole step are
-// accumulated by k_adjoint_q in one pass).
-template <int STAGE>
-__global__ __launch_bounds__(256) void k_adjoint_noq(GridArgs g, StrideDigits sd, const double2* __restrict__ in,
-                                                     const double2* mu, const double2* __restrict__ vb2,
-                                                     double2* out, double h) {
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 >= g.points) return;
-  const double c = STAGE == 1 ? 0.5 * h : STAGE == 2 ? h / 3.0 : STAGE == 3 ? 0.25 * h : h;
-  Walker w;
-  walker_init(w, g, i0);
-  while (w.i < g.points) {
-    const double2 lt = apply_LT(g, in, w);
-    double2 o = cscale(c, lt);
-    if (STAGE == 3) o = cadd(o, cadd(mu[w.i], cadd(vb2[w.i], in[w.i])));
-    if (STAGE == 4) o = cadd(o, mu[w.i]);
-    out[w.i] = o;
-    walker_step(w, g, sd);
-  }
-}
+// L^T is a stencil of the same form as L (transposed per-level tables), so
+// the stencils of B1..B4 run on the forward stage kernels; B3's stencil
+// leaves (h/4) L^T Vb1 in Xb1 and k_adjoint_q adds mu + Vb2 + Vb1 to it.
 
 // Parameter products of one reverse step, in the order the four stages would
 // add them: Q += (h/2) mu (x) V2, (h/3) Vb2 (x) V1, (h/4) Vb1 (x) X1, h Xb1 (x) y.
-// Runs after B3 and before B4 (which overwrites mu).  One read-modify-write of
+// Runs after B3's stencil and before B4 (which overwrites mu); first completes
+// Xb1 = (h/4) L^T Vb1 + (mu + (Vb2 + Vb1)) in place.  One read-modify-write of
 // the 1 + 2N planes per step instead of one per stage.
 __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, const double2* __restrict__ mu,
                                                    const double2* __restrict__ vb2,
                                                    const double2* __restrict__ vb1,
-                                                   const double2* __restrict__ xb1,
+                                                   double2* __restrict__ xb1,
                                                    const double2* __restrict__ v2, const double2* __restrict__ v1,
                                                    const double2* __restrict__ x1, const double2* __restrict__ y,
                                                    double2* __restrict__ Q, double h) {
@@ -773,8 +725,11 @@ __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, 
   walker_init(w, g, i0);
   const int64_t P = g.points;
   while (w.i < g.points) {
-    const double2 a1 = cscale(0.5 * h, mu[w.i]), a2 = cscale(h / 3.0, vb2[w.i]);
-    const double2 a3 = cscale(0.25 * h, vb1[w.i]), a4 = cscale(h, xb1[w.i]);
+    const double2 mv = mu[w.i], b2 = vb2[w.i], b1 = vb1[w.i];
+    const double2 xb = cadd(xb1[w.i], cadd(mv, cadd(b2, b1)));
+    xb1[w.i] = xb;
+    const double2 a1 = cscale(0.5 * h, mv), a2 = cscale(h / 3.0, b2);
+    const double2 a3 = cscale(0.25 * h, b1), a4 = cscale(h, xb);
     {
       double2 q = Q[w.i];
       q = cadd(q, cmul(a1, v2[w.i]));
@@ -1105,21 +1060,8 @@ void launch_expect_final(const double2* partial, const int* start, const double2
   hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, partial, start, coef, nfun, analytic, out);
 }
 
-void launch_adjoint_noq(int stage, const GridArgs& g, const double2* in, const double2* mu, const double2* vb2,
-                       double2* out, double h, hipStream_t st) {
-  const LaunchShape ls = shape_for(g, kStageBlocks);
-  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
-  dim3 gr(ls.blocks), bl(ls.threads);
-  switch (stage) {
-    case 1: hipLaunchKernelGGL((k_adjoint_noq<1>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
-    case 2: hipLaunchKernelGGL((k_adjoint_noq<2>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
-    case 3: hipLaunchKernelGGL((k_adjoint_noq<3>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
-    default: hipLaunchKernelGGL((k_adjoint_noq<4>), gr, bl, 0, st, g, sd, in, mu, vb2, out, h); break;
-  }
-}
-
 void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, const double2* vb1,
-                      const double2* xb1, const double2* v2, const double2* v1, const double2* x1,
+                      double2* xb1, const double2* v2, const double2* v1, const double2* x1,
                       const double2* y, double2* Q, double h, hipStream_t st) {
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
