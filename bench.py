@@ -287,9 +287,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
-    ap.add_argument("--only", choices=["network", "network5"], default=None,
+    ap.add_argument("--only", choices=["network", "network5", "gradient"], default=None,
                     help="run one section alone and print its JSON (for profiling it): network = the Table I "
-                         "network for 1 to 5 modes, network5 = its five-mode runs alone")
+                         "network for 1 to 5 modes, network5 = its five-mode runs alone, gradient = the gradient "
+                         "workload over 0.5 us (5,000 steps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -315,6 +316,10 @@ def main():
         del a, b
     if args.only in ("network", "network5"):
         print(json.dumps({"network": network_timing(hgf, torch, five_only=args.only == "network5")}))
+        return
+    if args.only == "gradient":
+        gradient_timing(hgf, torch, 0.01)  # first call: loads the kernels, captures the graphs
+        print(json.dumps({"gradient": gradient_timing(hgf, torch, 0.5)}))
         return
     w = synth.large_c4()
     pts = int(np.prod(w.system.cutoff))
