@@ -477,3 +477,50 @@ def test_network_identity_stationary_and_hermiticity(oracle_lib):
     assert np.max(np.abs(out - out.conj().T)) < 1e-12 * np.max(np.abs(out))
     with pytest.raises(ValueError):
         oracle.evolve(s, oracle.sectors_from_dense(cutoff, M), 0.1, 1e-3)
+
+
+def _annihilation(nc):
+    return np.diag(np.sqrt(np.arange(1, nc, dtype=float)), 1).astype(np.complex128)
+
+
+def test_network_driven_damped_mode_closed_form(oracle_lib):
+    """A resonantly driven, damped mode (Eq. (16), one mode, H = Delta n +
+    Omega a^+ + conj(Omega) a, emission at gamma1): the Heisenberg equation
+    d<a>/dt = -(gamma1/2 + i Delta) <a> - i Omega gives, from the vacuum,
+    <a>(t) = -i Omega / (gamma1/2 + i Delta) (1 - exp(-(gamma1/2 + i Delta) t)).
+    Checked on a(T) from the oracle's full-matrix RK4 (cutoff 14: the field
+    stays near 0.17, the truncation is far below the tolerance)."""
+    nc, delta, g1, om = 14, 2.0, 1.0, 0.3 + 0.2j
+    s = synth.System((nc,), np.array([delta]), np.zeros(1), np.zeros((1, 1)), np.array([g1]), np.zeros(1),
+                     np.zeros(1))
+    s.drive = np.array([om])
+    s.exchange = np.zeros((1, 1))
+    T, dt = 2.0, 1e-3
+    aT = oracle.evolve_full(s, _annihilation(nc), T, dt)
+    z = g1 / 2 + 1j * delta
+    want = -1j * om / z * (1 - np.exp(-z * T))
+    assert abs(aT[0, 0] - want) < 1e-10 * abs(want)
+    # <a^+ a> in the same state: |<a>|^2 (the state stays coherent)
+    n_op = _annihilation(nc).conj().T @ _annihilation(nc)
+    nT = oracle.evolve_full(s, n_op, T, dt)
+    assert abs(nT[0, 0] - abs(want) ** 2) < 1e-10 * abs(want) ** 2
+
+
+def test_network_exchange_swaps_a_coherent_field(oracle_lib):
+    """Two lossless modes coupled by exchange J (a_1^+ a_2 + a_2^+ a_1): the
+    Heisenberg equations da_1/dt = -i J a_2, da_2/dt = -i J a_1 give, for the
+    state |alpha> (x) |0>, <a_1>(t) = alpha cos(J t) and <a_2>(t) =
+    -i alpha sin(J t).  The excitation number is conserved, so at cutoff 12 and
+    |alpha| = 0.4 the truncation is negligible."""
+    nc, J, alpha = 12, 3.0, 0.4 - 0.1j
+    s = synth.System((nc, nc), np.zeros(2), np.zeros(2), np.zeros((2, 2)), np.zeros(2), np.zeros(2), np.zeros(2))
+    s.drive = np.zeros(2, dtype=np.complex128)
+    s.exchange = np.array([[0.0, J], [J, 0.0]])
+    T, dt = 0.7, 5e-4
+    a = _annihilation(nc)
+    eye = np.eye(nc, dtype=np.complex128)
+    c = np.kron(*oracle.state_amplitudes((nc, nc), synth.coherent_state([alpha, 0.0])))
+    for op, want in ((np.kron(a, eye), alpha * np.cos(J * T)), (np.kron(eye, a), -1j * alpha * np.sin(J * T))):
+        opT = oracle.evolve_full(s, op, T, dt)
+        got = np.conj(c) @ opT @ c
+        assert abs(got - want) < 1e-9 * abs(alpha), (got, want)
