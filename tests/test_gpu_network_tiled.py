@@ -230,3 +230,37 @@ def test_network_tile_config_errors(hgf):
     with pytest.raises(hgf.HgfError) as e:
         op2.set_tile_config(0, 4)
     assert e.value.status == "HGF_EINVAL"
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("mixed", MIXED_TOL)])
+def test_tiled_network_harmonic_chain_closed_form(hgf, precision, tol):
+    """The five-mode, cutoff-6 grid of the bench (60,466,176 points, default
+    tiled launch) with the Kerr terms set to zero and the Lindblad dissipator:
+    the first moments then obey the closed linear equation
+    d<a>/dt = -(i H1 + Gamma/2) <a> - i Omega (H1: detunings and exchange,
+    Gamma: decay rates), so from the vacuum <a_k>(T) = [-i M^-1 (1 - exp(-M T)) Omega]_k
+    with M = i H1 + Gamma/2.  A weak drive keeps the field near 0.1, where the
+    six-level truncation is far below the tolerance."""
+    import scipy.linalg
+    n, nc = 5, 6
+    announce(f"tiled network harmonic chain closed form {precision}")
+    w = synth.table1_network(n, nc)
+    s = w.system.copy()
+    s.kerr = np.zeros(n)
+    s.dissipator = "lindblad"
+    s.n_th = np.zeros(n)
+    s.drive = np.array([-1j * 2 * np.pi * 12.5] + [0.0] * (n - 1), dtype=np.complex128)
+    H1 = np.diag(s.detuning).astype(np.complex128) + s.exchange
+    M = 1j * H1 + np.diag(s.gamma1) / 2
+    T, dt = w.t_total, w.dt
+    field = -1j * np.linalg.solve(M, (np.eye(n) - scipy.linalg.expm(-M * T)) @ s.drive)
+    a = np.diag(np.sqrt(np.arange(1, nc, dtype=float)), 1).astype(np.complex128)
+    vacuum = synth.fock_state([0] * n)
+    for k in (0, n - 1):
+        fac = [a if j == k else np.eye(nc, dtype=np.complex128) for j in range(n)]
+        op = hgf.map_operator(hgf.define_system(s), factors=fac, precision=precision)
+        assert op.tile_config(0)["nfast"] == 4
+        hgf.evolve(op, T, dt)
+        got = hgf.expectation(op, vacuum)
+        assert abs(got - field[k]) < tol * np.max(np.abs(field)), (k, got, field[k])
+        del op
