@@ -34,6 +34,14 @@
  *    enqueued on it; calls that return host values synchronise it.
  *  - Handles are not thread-safe; calls on different handles may run on
  *    different threads.
+ *
+ * Environment (read when an operator is mapped or a gradient is taken; for
+ * comparisons and tests, every setting gives the same results to rounding):
+ *  - HGF_STAGE_KERNEL=generic: every function runs the untiled stage kernel.
+ *  - HGF_RESIDENT=0: no function runs the resident (on-chip) integrator.
+ *  - HGF_REAL_GRIDS=0: diagonal-sector functions keep complex grids.
+ *  - HGF_GRAD_STORE=0: hgf_grad keeps only the states of a segment and
+ *    recomputes each step's stage grids in the reverse sweep (bit-identical).
  */
 #ifndef HGF_H
 #define HGF_H
