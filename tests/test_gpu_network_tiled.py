@@ -211,6 +211,41 @@ def test_tiled_network_in_a_batch(hgf):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("cutoff,precision,tol,points", [((2, 8, 8), "mixed", MIXED_TOL, 4096),
+                                                         ((3, 7, 7), "fp64", FP64_TOL, 2401)])
+def test_tiled_network_largest_tiles(hgf, cutoff, precision, tol, points):
+    """The largest tiles the kernel takes: 8 x 8 levels (4096 points, eight
+    lane rounds of 512 lanes; mixed precision, whose LDS allows it) and 7 x 7
+    levels in FP64, against the oracle."""
+    announce(f"tiled network largest tiles {cutoff} {precision}")
+    s = all_pairs_network(cutoff, 651, "lindblad")
+    dim = int(np.prod(cutoff))
+    M = random_matrix(dim, 651)
+    op = hgf.map_operator(hgf.define_system(s), dense=M, precision=precision)
+    op.set_tile_config(0, 4)
+    cfg = op.tile_config(0)
+    assert cfg["nfast"] == 4 and cfg["tile_points"] == points
+    assert (points + cfg["threads"] - 1) // cfg["threads"] <= 8
+    T, dt = 0.01, 2.5e-4
+    hgf.evolve(op, T, dt)
+    ref = oracle.evolve_full(s, M, T, dt)
+    L = min(cutoff)
+    idx = [np.ravel_multi_index(k, cutoff) for k in np.ndindex(*(L,) * len(cutoff))]
+    assert rel_fro(hgf.reconstruct(op, L), ref[np.ix_(idx, idx)]) < tol
+    alphas = [0.5, 0.3 - 0.4j, 0.6j]
+    c = np.ones(1, dtype=np.complex128)
+    for a in oracle.state_amplitudes(cutoff, synth.coherent_state(alphas)):
+        c = np.kron(c, a)
+    want = np.conj(c) @ ref @ c
+    assert abs(hgf.expectation(op, synth.coherent_state(alphas)) - want) / abs(want) < 10 * tol
+    if precision == "fp64":  # 8 x 8 levels do not fit the FP64 tile's LDS
+        s8 = all_pairs_network((2, 8, 8), 652)
+        op8 = hgf.map_operator(hgf.define_system(s8), dense=random_matrix(128, 652), precision="fp64")
+        with pytest.raises(hgf.HgfError) as e:
+            op8.set_tile_config(0, 4)
+        assert e.value.status == "HGF_EINVAL"
+
+
 def test_network_tile_config_errors(hgf):
     s = all_pairs_network((3, 4, 4), 621)
     M = random_matrix(48, 621)
