@@ -246,6 +246,36 @@ def test_tiled_network_largest_tiles(hgf, cutoff, precision, tol, points):
         assert e.value.status == "HGF_EINVAL"
 
 
+def test_tiled_network_six_modes_all_pairs(hgf):
+    """Six modes (cutoffs 3, 3, 3, 3, 4, 4: 1,679,616 points, 6,561 tiles of
+    256, tiled by default), a drive on every mode and exchange between every
+    pair, secular dissipator: the records then hold four slow modes' jumps and
+    drives, six slow-slow and eight slow-fast exchange pairs.  Ten steps
+    against the oracle, FP64 and mixed."""
+    cutoff = (3, 3, 3, 3, 4, 4)
+    announce(f"tiled network six modes {cutoff}")
+    s = all_pairs_network(cutoff, 661, "secular")
+    dim = int(np.prod(cutoff))
+    M = random_matrix(dim, 661)
+    T, dt = 0.005, 5e-4
+    ref = oracle.evolve_full(s, M, T, dt)
+    alphas = [0.3, -0.2j, 0.25, 0.1 + 0.1j, 0.4, -0.3]
+    c = np.ones(1, dtype=np.complex128)
+    for a in oracle.state_amplitudes(cutoff, synth.coherent_state(alphas)):
+        c = np.kron(c, a)
+    want = np.conj(c) @ ref @ c
+    L = min(cutoff)
+    idx = [np.ravel_multi_index(k, cutoff) for k in np.ndindex(*(L,) * len(cutoff))]
+    for precision, tol in (("fp64", FP64_TOL), ("mixed", MIXED_TOL)):
+        op = hgf.map_operator(hgf.define_system(s), dense=M, precision=precision)
+        cfg = op.tile_config(0)
+        assert cfg["nfast"] == 4 and cfg["tile_points"] == 256
+        hgf.evolve(op, T, dt)
+        assert rel_fro(hgf.reconstruct(op, L), ref[np.ix_(idx, idx)]) < tol
+        assert abs(hgf.expectation(op, synth.coherent_state(alphas)) - want) / abs(want) < 10 * tol
+        del op
+
+
 def test_network_tile_config_errors(hgf):
     s = all_pairs_network((3, 4, 4), 621)
     M = random_matrix(48, 621)
