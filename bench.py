@@ -384,7 +384,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": STAGE_KERNEL, "avg_launch_us": launch_s * 1e6,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     # the counted HBM bytes per launch over the launch time
+                     "traffic_GBps": None if traffic is None else traffic / launch_s / 1e9},
         "expectation": [J.real, J.imag],
     }
     if not args.no_extras:
