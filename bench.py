@@ -335,7 +335,10 @@ def main():
     S = hgf.define_system(w.system)
 
     def run(precision, steps, warmup):
-        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        tm = time.perf_counter()
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)  # step (i): host build and upload
+        torch.cuda.synchronize()
+        log(f"map_operator: {time.perf_counter() - tm:.3f} s")
         real = op.info()["real_functions"] == 1
         t0 = time.perf_counter()
         hgf.autotune([op], w.dt, cache=args.tune_cache)  # stage-kernel launch shape, measured on this GPU
