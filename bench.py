@@ -304,8 +304,8 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each function would shard whole onto one GPU; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a function is never "
+              "split; the functions of a batch would be placed whole on separate GPUs).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -60,7 +60,7 @@ typedef enum {
   HGF_EDEVICE = -3,      /* a HIP runtime call failed */
   HGF_EUNSTABLE = -4,    /* dt outside the RK4 stability bound of the generator */
   HGF_ENONFINITE = -5,   /* a NaN or Inf appeared in an evolved function */
-  HGF_EUNSUPPORTED = -6, /* valid request this build does not implement */
+  HGF_EUNSUPPORTED = -6, /* valid request the library does not implement */
   HGF_ESTATE = -7        /* handle in a state that forbids the call */
 } hgf_status;
 
