@@ -1,9 +1,10 @@
 // LDS-tiled RK4 stage kernel of a network operator (drive and exchange,
 // Eq. (16)) on its full (k, l) grid.
 //
-// The grid's axes are interleaved per mode (k_0, l_0, k_1, l_1, ...), so the
-// (k, l) block of the last two modes P = N-2 and Q = N-1 is contiguous: a
-// tile of T = nc_P^2 nc_Q^2 points.  A workgroup stages a tile of the stencil
+// The grid holds the k and l axes of each mode side by side, mode by mode
+// (the host places the modes by coupling; the tables here are in that
+// position order), so the (k, l) block of the last two positions P = N-2 and
+// Q = N-1 is contiguous: a tile of T = nc_P^2 nc_Q^2 points.  A workgroup stages a tile of the stencil
 // input in LDS; every term that moves only along P's and Q's axes (their jumps,
 // drives and their mutual exchange) reads LDS.  The terms that move along a
 // slow mode's axes read the tile at a fixed element offset from global memory
@@ -171,10 +172,9 @@ struct FullWaves {
   static constexpr int value = sizeof(TS) == 16 ? 4 : 1;
 };
 template <typename TS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FullWaves<TS>::value))) void k_full_tiled(GridArgs g, int stage, const TS* __restrict__ in,
-                                                    const TS* __restrict__ x1, double2* __restrict__ y,
-                                                    TS* __restrict__ yf, TS* __restrict__ out, double h,
-                                                    int* __restrict__ flag) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FullWaves<TS>::value))) void k_full_tiled(
+    GridArgs g, int stage, const TS* __restrict__ in, const TS* __restrict__ x1, double2* __restrict__ y,
+    TS* __restrict__ yf, TS* __restrict__ out, double h, int* __restrict__ flag) {
   using R = typename Real<TS>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   const HGF_CONST FullTables* __restrict__ ft = (const HGF_CONST FullTables*)g.full;
