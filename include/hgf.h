@@ -299,7 +299,9 @@ hgf_status hgf_get_function(hgf_operator op, int32_t idx, int32_t* sector_d, int
  */
 typedef struct {
   int32_t nfast;       /* trailing axes staged in LDS; 0 = untiled (generic) kernel */
-  int32_t threads;     /* workgroup size: multiple of 64 in [64, 512]; 0 = default rule */
+  int32_t threads;     /* workgroup size: multiple of 64 in [64, 512] (the resident form: up to
+                          1024 in mixed precision, 512 in FP64, covering the grid in at most 4
+                          lane rounds); 0 = default rule */
   int32_t xblock;      /* tile order over the 8 XCDs: 0 = contiguous eighths of the grid,
                           B > 0 = interleaved blocks of B consecutive tiles */
   int32_t pipe;        /* 1 = neighbour loads of the next lane round issued before the

@@ -417,8 +417,10 @@ static void build_tile_records(Function& f, int precision) { f.ttab = upload_til
 
 // A function runs on the resident kernel when its tiled configuration is a
 // single tile holding every axis (then one workgroup does a stage's work in any
-// case) and the tile fits the resident kernel's lane rounds.
-static bool resident_eligible(Function& f) {
+// case) and the tile fits the resident kernel's lane rounds.  `threads` > 0
+// asks for that workgroup size (a multiple of 64 that covers the grid in the
+// kernel's lane rounds), else the fewest rounds with lanes spread evenly.
+static bool resident_eligible(Function& f, int threads = 0) {
   const GridArgs& g = f.ga;
   if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
   const int max_threads = f.precision_fp64 ? 512 : 1024;  // the kernel's workgroup limit
@@ -433,6 +435,13 @@ static bool resident_eligible(Function& f) {
   const int64_t lds = 2 * (int64_t)g.lds_elems * es + (int64_t)esum * rs;
   if (lds > 65536) return false;
   f.res_lds_bytes = (int)lds;
+  if (threads > 0) {
+    if (threads % 64 != 0 || threads > max_threads ||
+        (g.tile_points + threads - 1) / threads * (int64_t)1024 > (int64_t)resident_max_points())
+      return false;
+    f.res_threads = threads;
+    return true;
+  }
   // lanes: enough for the fewest rounds, spread evenly over them
   const int64_t rounds = (g.tile_points + max_threads - 1) / max_threads;
   const int64_t per = (g.tile_points + rounds - 1) / rounds;
@@ -2901,7 +2910,7 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
     }
     const bool tiled = f.ga.blocks > 0;
     out->nfast = tiled ? f.ga.nfast : 0;
-    out->threads = tiled ? f.ga.threads : 0;
+    out->threads = f.resident ? f.res_threads : tiled ? f.ga.threads : 0;
     out->xblock = tiled ? f.ga.xblock : 0;
     out->pipe = tiled ? f.ga.pipe : 0;
     out->wgs_per_cu = tiled ? f.ga.occ_cap : 0;
@@ -2942,15 +2951,20 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
       return;
     }
     if (cfg->resident) {  // check on a copy first: the function is unchanged on error
+      // `threads` is the resident workgroup's size; the stage-kernel shape
+      // kept beside it (for other calls) takes its default
+      c.threads = 0;
       Function probe;
       probe.split = f.split;
       probe.precision_fp64 = f.precision_fp64;
       probe.ga = f.ga;
-      if (c.nfast == 0 || !configure_tiles(probe.ga, op->precision, f.real, c) || !resident_eligible(probe))
-        fail(HGF_EINVAL, "the resident form needs the whole grid in one tile of at most 4096 points");
+      if (c.nfast == 0 || !configure_tiles(probe.ga, op->precision, f.real, c) ||
+          !resident_eligible(probe, cfg->threads))
+        fail(HGF_EINVAL, "the resident form needs the whole grid in one tile of at most 4096 points "
+                         "(and threads, if set, a multiple of 64 covering it in at most 4 lane rounds)");
     }
     retile(f, op->precision, c);
-    f.resident = cfg->resident && resident_eligible(f);
+    f.resident = cfg->resident && resident_eligible(f, cfg->threads);
     drop_plan(op);
   });
 }

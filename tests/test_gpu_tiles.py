@@ -229,6 +229,36 @@ def test_resident_integrator_matches_stage_launches(hgf, precision):
     assert max_rel_err(gpu_number_grids(op, cutoff), ref) < tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_workgroup_sizes(hgf, precision):
+    """The resident integrator's workgroup size, set through
+    hgf_set_tile_config: every size that covers the 3-mode grid (1,728
+    points) in at most four lane rounds gives the same result bit for bit
+    (each point's arithmetic does not depend on it); other sizes are
+    rejected and leave the function as it was."""
+    w = synth.three_mode_c1()
+    S = hgf.define_system(w.system)
+    announce(f"resident workgroup sizes {precision}")
+    sizes = (448, 512) if precision == "fp64" else (448, 576, 896, 1024)
+    grids = []
+    for th in sizes:
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        op.set_tile_config(0, 3, th, 0, 0, 0, 1)
+        cfg = op.tile_config(0)
+        assert cfg["resident"] == 1 and cfg["threads"] == th, cfg
+        hgf.evolve(op, 0.02, w.dt)
+        grids.append(op.function(0)[2])
+    for g in grids[1:]:
+        assert np.array_equal(g, grids[0])
+    op = hgf.map_operator(S, factors=w.factors, precision=precision)
+    before = op.tile_config(0)
+    for th in (100, 384 if precision == "fp64" else 320, 2048):
+        with pytest.raises(hgf.HgfError) as e:
+            op.set_tile_config(0, 3, th, 0, 0, 0, 1)
+        assert e.value.status == "HGF_EINVAL", th
+        assert op.tile_config(0) == before
+
+
 def test_resident_members_in_a_batch(hgf):
     """A batch mixing resident members (small grids) with tiled ones advances
     each member as its own evolve does and matches the oracle."""
