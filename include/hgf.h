@@ -199,7 +199,7 @@ enum {
  * scheme: HGF_RK4, or HGF_LAWSON_RK4, whose step is exact without jumps and so
  * is not limited by large Kerr phases in off-diagonal sectors (every function
  * then runs on the untiled stage kernel).  Other values: HGF_EUNSUPPORTED, as
- * is HGF_LAWSON_RK4 on a split-layout operator.
+ * is HGF_LAWSON_RK4 on a split-layout or a network operator.
  * t_total_us / dt_us must be a non-negative integer (to 1e-9 relative).
  * Errors: HGF_EINVAL; HGF_EUNSTABLE when dt times a bound on the spectral
  * radius of the generator (HGF_RK4) or of its jump terms (HGF_LAWSON_RK4)

@@ -1808,10 +1808,7 @@ static void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& ste
 // Re-configure one function's stage kernel; the function is left unchanged
 // when the shape is not feasible (HGF_EINVAL).
 static void retile(Function& f, int precision, const TileChoice& c) {
-  if (f.full) {
-    if (c.nfast == 0) return;
-    fail(HGF_EINVAL, "a network operator's full grid runs the untiled stage kernel only");
-  }
+  if (f.full) fail(HGF_EINVAL, "a network operator's shape is set by hgf_set_tile_config's network form");
   if (f.split) {
     if (c.nfast == 0) return;
     fail(HGF_EUNSUPPORTED, "split-layout functions run the classical stage kernel only");
