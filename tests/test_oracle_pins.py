@@ -240,6 +240,46 @@ def test_coefficient_maps(nc):
     assert np.max(np.abs(recon - A)) < 1e-10 * max(1.0, np.max(np.abs(A)))
 
 
+@pytest.mark.parametrize("cutoff,seed", [((4, 3), 71), ((3, 5, 2), 72)])
+def test_generating_coefficients_and_sector_grid(cutoff, seed):
+    """The oracle's coefficient map (number-basis sectors -> g of Eqs. (6)-(8))
+    and its sector slicing (m = min(k, l), extent Nc_j - |d_j|), checked
+    against a product operator built from normal-ordered per-mode
+    coefficients: Eq. (2) by matrix products gives the number-basis operator,
+    Eq. (6) by its sum gives every g_{k,l} = prod_j g_j[k_j, l_j], and each
+    sector grid point m is compared with the product at k = m + u, l = m + v
+    (u_j = max(0, -d_j), v_j = max(0, d_j)), looped over explicitly."""
+    import itertools
+    fs = [synth.random_normal_coeffs(nc, seed + j) for j, nc in enumerate(cutoff)]
+    gs = [oracle.g_from_f(f) for f in fs]
+    ops = oracle.product_sectors([oracle.number_from_normal(f) for f in fs])
+    gco = oracle.generating_coefficients(cutoff, ops)
+    assert set(gco) == set(ops)
+    assert any(min(d) < 0 for d in ops) and any(max(d) > 0 for d in ops)
+    scale = max(float(np.max(np.abs(g))) for g in gs) ** len(cutoff)
+    for d, box in gco.items():
+        grid = oracle.sector_grid(cutoff, d, box)
+        ext = tuple(nc - abs(dj) for nc, dj in zip(cutoff, d))
+        assert grid.shape == ext
+        for m in itertools.product(*[range(e) for e in ext]):
+            k = [mj + max(0, -dj) for mj, dj in zip(m, d)]
+            l = [mj + max(0, dj) for mj, dj in zip(m, d)]
+            ref = np.prod([g[kj, lj] for g, kj, lj in zip(gs, k, l)])
+            assert abs(grid[m] - ref) < 1e-12 * scale, (d, m)
+
+
+def test_sector_grid_hand_sliced():
+    """One sector sliced by hand: cutoff (3, 4), d = (1, -2) keeps k_0 in
+    {0, 1} (l_0 = k_0 + 1 < 3) and k_1 in {2, 3} (l_1 = k_1 - 2 >= 0)."""
+    box = np.arange(12, dtype=np.complex128).reshape(3, 4) * (1 + 0.5j)
+    grid = oracle.sector_grid((3, 4), (1, -2), box)
+    assert grid.shape == (2, 2)
+    assert np.array_equal(grid, np.array([[box[0, 2], box[0, 3]], [box[1, 2], box[1, 3]]]))
+    assert np.array_equal(oracle.sector_grid((3, 4), (0, 0), box), box)
+    assert oracle.sector_grid((3, 4), (-2, 3), box).shape == (1, 1)
+    assert oracle.sector_grid((3, 4), (-2, 3), box)[0, 0] == box[2, 0]
+
+
 # ------------------------------------------------------- sensitivities
 
 @pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
