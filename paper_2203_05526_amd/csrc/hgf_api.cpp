@@ -168,6 +168,32 @@ static int64_t check_steps(double t_total, double dt) {
   return m;
 }
 
+// Largest number of grid points in one operator (summed over its functions).
+// Every kernel indexes a grid with 64-bit element counts; the cap keeps the
+// point counts, their byte sizes and the sums over sectors far from int64
+// overflow, and is beyond what HBM holds anyway (2^32 points of the smallest
+// element set, a real mixed grid with its stage grids, take over 100 GB).
+constexpr int64_t kMaxOperatorPoints = (int64_t)1 << 32;
+
+// prod_j ext[j] with an overflow check against kMaxOperatorPoints.
+static int64_t checked_points(const int* ext, int n) {
+  int64_t p = 1;
+  for (int j = 0; j < n; ++j) {
+    if (ext[j] <= 0) return 0;
+    if (p > kMaxOperatorPoints / ext[j])
+      fail(HGF_EINVAL, "a sector grid would exceed 2^32 points; reduce the modes or cutoffs");
+    p *= ext[j];
+  }
+  return p;
+}
+
+// total += add, failing once the operator's points exceed the cap.
+static void add_points(int64_t& total, int64_t add) {
+  if (add > kMaxOperatorPoints - total)
+    fail(HGF_EINVAL, "the operator's sector grids would exceed 2^32 points in total");
+  total += add;
+}
+
 static void check_stability(const std::vector<Function>& fns, double dt, bool jumps_only = false) {
   // RK4's stability region holds the left half-disc of radius ~2.6; the
   // Gershgorin bound of the sector generator (of its jump terms alone for the
@@ -456,6 +482,7 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   const SectorTables& t = f.tab;
   g.n = t.n;
   g.nfast = 0;
+  checked_points(t.ext, t.n);
   int64_t s = 1;
   for (int j = t.n - 1; j >= 0; --j) {
     g.ext[j] = t.ext[j];
@@ -601,6 +628,17 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
       }
       if (diags[j].empty()) return;  // zero operator
     }
+    // the sum of the sector sizes factorises over the modes: check it (and
+    // so every sector) before enumerating the sectors
+    {
+      int tot[kMaxModes];
+      for (int j = 0; j < n; ++j) {
+        int64_t sj = 0;
+        for (int dj : diags[j]) sj += s.nc[j] - std::abs(dj);
+        tot[j] = (int)sj;
+      }
+      checked_points(tot, n);
+    }
     // enumerate sectors as the product of per-mode diagonals
     std::vector<int> idx(n, 0);
     while (true) {
@@ -608,14 +646,13 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
       for (int j = 0; j < n; ++j) dv[j] = diags[j][idx[j]];
       SectorTables t;
       t.n = n;
-      int64_t pts = 1;
       int u[kMaxModes], v[kMaxModes], e[kMaxModes];
       for (int j = 0; j < n; ++j) {
         u[j] = dv[j] < 0 ? -dv[j] : 0;
         v[j] = dv[j] > 0 ? dv[j] : 0;
         e[j] = s.nc[j] - std::abs(dv[j]);
-        pts *= e[j];
       }
+      const int64_t pts = checked_points(e, n);
       if (!want_split) {
         std::vector<cd> grid(pts);
         std::vector<int> m(n, 0);
@@ -739,6 +776,7 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
       }
     }
   }
+  int64_t total_points = 0;
   for (auto& kv : acc) {
     const auto& k = kv.first.first;
     const auto& l = kv.first.second;
@@ -747,19 +785,79 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
       split.push_back(Coeff{k, l, kv.second});
     } else {
       std::vector<int> dv(n);
-      int64_t pts = 1;
       int e[kMaxModes], m[kMaxModes];
       for (int j = 0; j < n; ++j) {
         dv[j] = l[j] - k[j];
         e[j] = s.nc[j] - std::abs(dv[j]);
         m[j] = std::min(k[j], l[j]);
-        pts *= e[j];
       }
       auto it = merged.find(dv);
-      if (it == merged.end()) it = merged.emplace(dv, std::vector<cd>(pts, 0.0)).first;
+      if (it == merged.end()) {
+        const int64_t pts = checked_points(e, n);
+        add_points(total_points, pts);
+        it = merged.emplace(dv, std::vector<cd>(pts, 0.0)).first;
+      }
       int64_t f = 0;
       for (int j = 0; j < n; ++j) f = f * e[j] + m[j];
       it->second[f] += kv.second;
+    }
+  }
+}
+
+// Largest full (k, l) grid of a network operator, in points.
+constexpr int64_t kMaxFullPoints = (int64_t)1 << 28;
+
+// Host-side size check of an operator before any device work: the grids its
+// coefficients populate must stay within kMaxOperatorPoints (per sector and in
+// total), and a network operator's full (k, l) grid within kMaxFullPoints.
+// Product operators: the sector sizes factorise over the modes, so the total
+// is the product of the per-mode sums over their nonzero diagonals.  Sparse
+// operators: each distinct sector's size once.  Dense operators are bounded
+// by their own dimension limit.
+static void precheck_operator_size(const System& s, const hgf_operator_desc* d) {
+  const int n = s.n;
+  if (s.full) {
+    int64_t dim = 1;
+    for (int j = 0; j < n; ++j) {
+      dim *= s.nc[j];
+      if (dim * dim > kMaxFullPoints) fail(HGF_EINVAL, "full (k, l) grid of the network exceeds 2^28 points");
+    }
+    return;
+  }
+  if (d->kind == HGF_OP_PRODUCT && d->values) {
+    int tot[kMaxModes];
+    size_t off = 0;
+    for (int j = 0; j < n; ++j) {
+      const int nc = s.nc[j];
+      int sj = 0;
+      for (int dj = -nc + 1; dj < nc; ++dj) {
+        bool nz = false;
+        for (int k = 0; k < nc && !nz; ++k) {
+          const int l = k + dj;
+          if (l >= 0 && l < nc)
+            nz = d->values[off + 2 * (k * nc + l)] != 0.0 || d->values[off + 2 * (k * nc + l) + 1] != 0.0;
+        }
+        if (nz) sj += nc - std::abs(dj);
+      }
+      if (sj == 0) return;  // zero operator
+      tot[j] = sj;
+      off += 2 * (size_t)nc * nc;
+    }
+    checked_points(tot, n);
+  } else if (d->kind == HGF_OP_SPARSE && d->indices && d->n_terms > 0) {
+    std::set<std::vector<int>> seen;
+    int64_t total = 0;
+    for (int64_t t = 0; t < d->n_terms; ++t) {
+      std::vector<int> dv(n);
+      int e[kMaxModes];
+      for (int j = 0; j < n; ++j) {
+        const int k = d->indices[t * 2 * n + j], l = d->indices[t * 2 * n + n + j];
+        if (k < 0 || k >= s.nc[j] || l < 0 || l >= s.nc[j])
+          fail(HGF_EINVAL, "sparse operator index outside the cutoff box");
+        dv[j] = l - k;
+        e[j] = s.nc[j] - std::abs(dv[j]);
+      }
+      if (seen.insert(dv).second) add_points(total, checked_points(e, n));
     }
   }
 }
@@ -841,8 +939,6 @@ static void setup_split(Function& f, const System& s, const Coeff& c) {
   }
 }
 
-// Largest full (k, l) grid of a network operator, in points.
-constexpr int64_t kMaxFullPoints = (int64_t)1 << 28;
 
 // Generator tables of a network operator's full grid (see FullTables).
 static FullTables full_tables(const System& s) {
@@ -1152,8 +1248,10 @@ static void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) 
   const System& s = op->sys;
   const int n = s.n;
   int64_t dim = 1;
-  for (int j = 0; j < n; ++j) dim *= s.nc[j];
-  if (dim * dim > kMaxFullPoints) fail(HGF_EINVAL, "full (k, l) grid of the network exceeds 2^28 points");
+  for (int j = 0; j < n; ++j) {
+    dim *= s.nc[j];
+    if (dim * dim > kMaxFullPoints) fail(HGF_EINVAL, "full (k, l) grid of the network exceeds 2^28 points");
+  }
   std::map<std::vector<int>, std::vector<cd>> merged;
   std::vector<Coeff> coeffs;
   collect_coeffs(s, d, merged, coeffs, false);
@@ -2761,6 +2859,7 @@ hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_o
     if (desc->layout != HGF_MERGED && desc->layout != HGF_SPLIT) fail(HGF_EINVAL, "unknown layout");
     if (desc->basis != HGF_BASIS_NUMBER && desc->basis != HGF_BASIS_NORMAL) fail(HGF_EINVAL, "unknown basis");
     if (!(desc->drop_tol >= 0)) fail(HGF_EINVAL, "drop_tol must be >= 0");
+    hgf::precheck_operator_size(sys->sys, desc);
     auto* op = new hgf_operator_s;
     try {
       op->sys = sys->sys;
@@ -2864,6 +2963,7 @@ hgf_status hgf_grad(hgf_system sys, const hgf_operator_desc* desc, const hgf_sta
   return guarded([&] {
     if (!sys || !desc || !psi || !value_out || !grad_out) fail(HGF_EINVAL, "NULL argument");
     if (desc->basis != HGF_BASIS_NUMBER && desc->basis != HGF_BASIS_NORMAL) fail(HGF_EINVAL, "unknown basis");
+    hgf::precheck_operator_size(sys->sys, desc);
     grad_impl(sys->sys, desc, psi, t_total_us, dt_us, checkpoint_every, value_out, grad_out,
               (hipStream_t)hip_stream);
   });

@@ -126,3 +126,38 @@ def test_network_validation(hgf):
     with pytest.raises(hgf.HgfError):
         hgf.System((2,) * n, [0.0] * n, [0.0] * n, [0.0] * (n * n), [0.1] * n, [0.0] * n, [0.0] * n,
                    drive=[1.0] + [0.0] * (n - 1))
+
+
+def test_over_large_operators_are_rejected_before_device_work(hgf):
+    """Sector grids whose point count would overflow (16 modes at cutoff 16:
+    16^16 = 2^64 points) or exceed the library's 2^32-point cap are refused
+    with HGF_EINVAL by a host-side check that runs before any device call."""
+    n = 16
+    S = hgf.System((16,) * n, [0.0] * n, [0.0] * n, [0.0] * (n * n), [0.1] * n, [0.0] * n, [0.0] * n)
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.map_operator(S, factors=[np.eye(16)] * n)
+    assert e.value.status == "HGF_EINVAL" and "2^32" in str(e.value)
+    # sparse input: one term in the diagonal sector (16^16 points)
+    ks = np.zeros((1, n), dtype=np.int32)
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.map_operator(S, sparse=(ks, ks, np.array([1.0])))
+    assert e.value.status == "HGF_EINVAL" and "2^32" in str(e.value)
+    # gradient requests go through the same check
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.grad(S, synth.fock_state([0] * n), 0.1, 0.01, factors=[np.eye(16)] * n)
+    assert e.value.status == "HGF_EINVAL"
+    # just over the cap in total over sectors: 8 modes at cutoff 16 with
+    # bidiagonal factors (sum over the two diagonals 16 + 15 = 31 per mode,
+    # 31^8 = 8.5e11 points in total, 16^8 = 2^32 in the diagonal sector alone)
+    n = 8
+    S = hgf.System((16,) * n, [0.0] * n, [0.0] * n, [0.0] * (n * n), [0.1] * n, [0.0] * n, [0.0] * n)
+    fac = np.eye(16) + np.eye(16, k=1)
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.map_operator(S, factors=[fac] * n)
+    assert e.value.status == "HGF_EINVAL"
+    # the full (k, l) grid of a network: 8 modes at cutoff 32 (2^80 points)
+    S = hgf.System((32,) * n, [0.0] * n, [0.0] * n, [0.0] * (n * n), [0.1] * n, [0.0] * n, [0.0] * n,
+                   drive=[1.0] + [0.0] * (n - 1))
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.map_operator(S, factors=[np.eye(32)] * n)
+    assert e.value.status == "HGF_EINVAL" and "2^28" in str(e.value)
