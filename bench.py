@@ -106,13 +106,44 @@ def cpu_baseline(w, steps: int):
                               "sample": f"3 RK4 steps of the same 10 modes at cutoff 4 on one thread ({el1:.1f} s)"}}
 
 
+def golden(name: str):
+    """Stored FP64 oracle values (written by tests/golden/make_golden.py, which
+    calls only the oracle)."""
+    with open(os.path.join(ROOT, "tests", "golden", f"{name}.json")) as fh:
+        return json.load(fh)
+
+
+def ten_mode_full_horizon(hgf, torch, w, S, tune_cache=None):
+    """The 10-mode workload over its full horizon (T = 2 us, 4e4 steps) in
+    mixed precision and in FP64, each in its tuned launch shape: wall time of
+    hgf_evolve + hgf_expectation and the relative error of the expectation
+    value against the stored FP64 oracle value (a product of single-mode
+    oracle runs, exact on the diagonal sector)."""
+    ref = complex(*golden("workloads")["ten_mode"]["value"])
+    out = {"workload": "10 Kerr modes, cutoff 6, parity-weighted projector, T = 2 us, dt = 0.05 ns (4e4 steps)",
+           "oracle_value": [ref.real, ref.imag]}
+    for prec in ("mixed", "fp64"):
+        op = hgf.map_operator(S, factors=w.factors, precision=prec)
+        hgf.autotune([op], w.dt, cache=tune_cache)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hgf.evolve(op, w.t_total, w.dt)
+        J = hgf.expectation(op, w.states[0])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[prec] = {"seconds": el, "steps": op.info()["steps_done"], "rel_err_vs_oracle": abs(J - ref) / abs(ref)}
+        log(f"10-mode full horizon {prec}: {el:.1f} s, error {out[prec]['rel_err_vs_oracle']:.2e}")
+        del op
+    out["mixed_within_1e-5"] = out["mixed"]["rel_err_vs_oracle"] <= 1e-5
+    out["fp64_within_1e-10"] = out["fp64"]["rel_err_vs_oracle"] <= 1e-10
+    return out
+
+
 def time_to_tolerance(hgf, torch):
     """Wall time of the full 3-mode horizon (1e5 steps) in mixed precision and
     in FP64, each with its error against the FP64 oracle's stored value."""
     import synth
-    gold_path = os.path.join(ROOT, "tests", "golden", "three_mode.json")
-    with open(gold_path) as fh:
-        gold = json.load(fh)
+    gold = golden("three_mode")
     w = synth.three_mode_c1()
     S = hgf.define_system(w.system)
     ref = complex(*gold["values"][0])
@@ -161,43 +192,61 @@ def stiff_time_to_tolerance(hgf, torch):
     return out
 
 
-def batch_throughput(hgf, torch, steps: int):
+def batch_throughput(hgf, torch, seq_steps: int):
     """One grouped, graph-captured hgf_evolve_batch over the batch workload:
     64 systems of 6 modes at cutoff 8 plus 32 systems of 2-5 modes with
-    cutoffs 6-20 (seeded), mixed precision, dt = 0.1 ns."""
+    cutoffs 6-20 (seeded), mixed precision, dt = 0.1 ns, over the full horizon
+    T = 1 us (1e4 steps), with every member's expectation value against the
+    stored FP64 oracle value; the same members evolved one call at a time
+    over `seq_steps` steps for comparison."""
     import synth
     ws = synth.batch_c2()
     ops = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
     pts = sum(op.info()["total_points"] for op in ops)
     dt = ws[0].dt
+    import tempfile
+    tmp = tempfile.TemporaryDirectory()
+    batch_cache = os.path.join(tmp.name, "batch.txt")
     t0 = time.perf_counter()
-    hgf.autotune(ops, dt)  # grid shapes, and the grouped launches of the batch as a whole
+    hgf.autotune(ops, dt, cache=batch_cache)  # grid shapes, and the grouped launches of the batch as a whole
     tune_s = time.perf_counter() - t0
     # sequential reference: the same members evolved one hgf_evolve call at a
     # time, each with the launch shape tuned for its grid alone
-    import tempfile
     ops2 = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
-    with tempfile.TemporaryDirectory() as tmp:
-        for op in ops2:
-            hgf.autotune([op], dt, cache=os.path.join(tmp, "shapes.txt"))
-    hgf.evolve_batch(ops, [2 * dt] * len(ops), [dt] * len(ops))  # warm-up (plan, graph)
+    for op in ops2:
+        hgf.autotune([op], dt, cache=os.path.join(tmp.name, "shapes.txt"))
+    # warm-up (plan, graph) on fresh copies, so that the timed run starts at t = 0
+    warm = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws[:1]]
+    hgf.evolve_batch(warm + ops[1:], [2 * dt] * len(ops), [dt] * len(ops))
+    del warm
+    ops = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
+    hgf.autotune(ops, dt, cache=batch_cache)  # applies the shapes found above without measuring
+    steps = ws[0].n_steps
+    hgf.evolve_batch(ops, [0.0] * len(ops), [dt] * len(ops))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hgf.evolve_batch(ops, [steps * dt] * len(ops), [dt] * len(ops))
+    hgf.evolve_batch(ops, [w.t_total for w in ws], [w.dt for w in ws])
+    Js = [hgf.expectation(op, w.states[0]) for op, w in zip(ops, ws)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    refs = [complex(*m["value"]) for m in golden("workloads")["batch"]]
+    errs = [abs(J - r) / abs(r) for J, r in zip(Js, refs)]
     for op in ops2:
         hgf.evolve(op, 2 * dt, dt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for op in ops2:
-        hgf.evolve(op, steps * dt, dt)
+        hgf.evolve(op, seq_steps * dt, dt)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t1
-    return {"workload": "96 systems: 64 x (6 modes, cutoff 8) + 32 x (2-5 modes, cutoffs 6-20), mixed",
+    tmp.cleanup()
+    return {"workload": "96 systems: 64 x (6 modes, cutoff 8) + 32 x (2-5 modes, cutoffs 6-20), mixed, "
+                        "T = 1 us, dt = 0.1 ns",
             "members": len(ops), "grid_points": pts, "steps": steps,
             "value": pts * 4 * steps / el, "unit": "point-stage updates/s", "seconds": el,
-            "sequential_seconds": el_seq, "autotune_seconds": tune_s}
+            "rel_err_vs_oracle": max(errs), "within_1e-5": max(errs) <= 1e-5,
+            "sequential": {"steps": seq_steps, "seconds": el_seq, "value": pts * 4 * seq_steps / el_seq},
+            "autotune_seconds": tune_s}
 
 
 def network_timing(hgf, torch, five_only: bool = False):
@@ -280,9 +329,16 @@ def gradient_timing(hgf, torch, t_total: float):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     steps = int(round(t_total / w.dt))
-    return {"workload": f"4 Kerr modes, cutoff 16, bitstring projector, T = {t_total} us, dt = 0.1 ns",
-            "steps": steps, "params": len(g), "seconds": el, "value": val.real,
-            "max_abs_grad": float(np.max(np.abs(g)))}
+    out = {"workload": f"4 Kerr modes, cutoff 16, bitstring projector, T = {t_total} us, dt = 0.1 ns",
+           "steps": steps, "params": len(g), "seconds": el, "value": val.real,
+           "max_abs_grad": float(np.max(np.abs(g)))}
+    ref = golden("workloads")["gradient"]
+    if steps == ref["steps"]:
+        rv = complex(*ref["value"])
+        rg = np.array([complex(*x) for x in ref["grad"]])
+        out["rel_err_vs_oracle"] = {"value": abs(val - rv) / abs(rv),
+                                    "grad": float(np.max(np.abs(g - rg)) / np.max(np.abs(rg)))}
+    return out
 
 
 def main():
@@ -294,6 +350,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 and time-to-1e-5 comparisons")
+    ap.add_argument("--no-full-horizon", action="store_true",
+                    help="skip the full-horizon runs of the 10-mode workload (4e4 steps, mixed and FP64)")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
     ap.add_argument("--only", choices=["network", "network5", "gradient"], default=None,
@@ -400,6 +458,9 @@ def main():
                               "achieved_GBs": bytes_per_point_stage("fp64", real64) * pts / launch64 / 1e9}
         log("time-to-1e-5 on the 3-mode workload")
         line["time_to_1e-5"] = time_to_tolerance(hgf, torch)
+        if not args.no_full_horizon:
+            log("10-mode workload over the full horizon")
+            line["time_to_1e-5"]["ten_mode"] = ten_mode_full_horizon(hgf, torch, w, S, args.tune_cache)
         log("batched evolve")
         line["batch"] = batch_throughput(hgf, torch, 500)
         log("gradient")

@@ -42,6 +42,9 @@
  *  - HGF_REAL_GRIDS=0: diagonal-sector functions keep complex grids.
  *  - HGF_GRAD_STORE=0: hgf_grad keeps only the states of a segment and
  *    recomputes each step's stage grids in the reverse sweep (bit-identical).
+ *  - HGF_MAX_NFAST=k (1..4): the default launch shape of the tiled stage
+ *    kernel takes at most k fast (LDS) axes, so small grids also run with
+ *    slow-axis neighbour tiles (the shape large grids take).
  */
 #ifndef HGF_H
 #define HGF_H

@@ -255,7 +255,12 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
   if (c.nfast == 0) return true;
   const int rs = precision == HGF_FP64 ? 8 : 4, ts = real ? rs : 2 * rs;
   int best = 0;
-  for (int F = std::min(4, g.n); F >= 1; --F) {
+  int fmax = std::min(4, g.n);
+  if (c.nfast < 0) {
+    const char* env = std::getenv("HGF_MAX_NFAST");  // cap on the default rule
+    if (env && std::atoi(env) >= 1) fmax = std::min(fmax, std::atoi(env));
+  }
+  for (int F = fmax; F >= 1; --F) {
     if (c.nfast > 0 && F != c.nfast) continue;
     if (g.n - F > tiled_max_slow_axes()) continue;
     // padded LDS tile: (e_0 + 2) x prod_{q>=1} (e_q + 1), see k_rk4_tiled
@@ -268,7 +273,7 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
       esum += e;
       emax = std::max(emax, e);
     }
-    const int cbits = F == 4 ? 4 : 5;
+    const int cbits = tile_coord_bits(F);
     if (emax > (1 << cbits) || padded >= 65536) continue;
     // one point per lane; a tile takes at most kTileRounds rounds of lanes
     // (the kernel's prefetch registers)
@@ -281,7 +286,8 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
     }
     if (threads < 64 || threads > 512 || threads % 64 != 0) continue;
     if ((T + threads - 1) / threads > kTileRounds) continue;
-    const int64_t bytes = padded * ts + T * ts + ((T + 1) & ~1) * 4 + 2 * esum * rs + 64;
+    const int64_t bytes =
+        tiled_lds((int)padded, (int)T, (int)esum, ts, rs).bytes;
     if (bytes > 65536) continue;
     best = F;
     g.nfast = F;
@@ -340,12 +346,12 @@ static bool configure_tiles(GridArgs& g, int precision, bool real, const TileCho
 }
 
 // Per-tile records of the slow-axis terms for k_rk4_tiled (layout of
-// TileRec<NS, R>): lam_slow (R re, im), 2*NS int32 element offsets, 2*NS R
+// TileRec<NS, R>): lam_slow (FP64 re, im), 2*NS int32 element offsets, 2*NS R
 // coefficients, with the coefficient array aligned to sizeof(R).
 template <typename R>
 static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) {
   const int ns = g.n - g.nfast, nd = 2 * std::max(ns, 1);
-  size_t bytes = 2 * sizeof(R) + nd * sizeof(int32_t);
+  size_t bytes = 2 * sizeof(double) + nd * sizeof(int32_t);
   bytes = (bytes + sizeof(R) - 1) / sizeof(R) * sizeof(R);
   const size_t coef_at = bytes;
   bytes += nd * sizeof(R);
@@ -369,10 +375,10 @@ static std::vector<char> tile_records(const GridArgs& g, const SectorTables& t) 
         coef[2 * j + 1] = (R)t.beta[j][sj];
       }
     }
-    R lr = (R)lam.real(), li = (R)lam.imag();
-    std::memcpy(r, &lr, sizeof(R));
-    std::memcpy(r + sizeof(R), &li, sizeof(R));
-    std::memcpy(r + 2 * sizeof(R), off.data(), nd * sizeof(int32_t));
+    const double lr = lam.real(), li = lam.imag();
+    std::memcpy(r, &lr, sizeof(double));
+    std::memcpy(r + sizeof(double), &li, sizeof(double));
+    std::memcpy(r + 2 * sizeof(double), off.data(), nd * sizeof(int32_t));
     std::memcpy(r + coef_at, coef.data(), nd * sizeof(R));
   }
   return out;
@@ -499,13 +505,27 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
   }
   g.lam0_re = t.lam0.real();
   g.lam0_im = t.lam0.imag();
-  if (!stage_kernel_generic() && !f.full) configure_tiles(g, precision, want_real, TileChoice{});
+  // Phase slopes: within a sector Im lam_j(m) = m * slope_j (the stage
+  // kernels on complex FP32 grids form the phase from the coordinates in
+  // FP64).  Every generator this library builds has this form; a table that
+  // did not would run the generic kernel, which sums the tables in FP64.
+  bool linear = true;
+  for (int j = 0; j < t.n && !f.full; ++j) {
+    const double slope = t.ext[j] > 1 ? t.lam[j][1].imag() : 0.0;
+    g.phase_slope[j] = slope;
+    for (int m = 0; m < t.ext[j]; ++m)
+      if (std::fabs(t.lam[j][m].imag() - m * slope) > 1e-12 * std::max(1.0, std::fabs(m * slope))) linear = false;
+  }
+  g.phase_linear = linear ? 1 : 0;
+  if (!stage_kernel_generic() && !f.full && (linear || precision == HGF_FP64))
+    configure_tiles(g, precision, want_real, TileChoice{});
   f.real = g.real != 0;
-  // device tables, one block: lam (double2), beta, alpha (double), lam_f
-  // (float2), beta_f, alpha_f (float), each concatenated over the axes
+  // device tables, one block: lam (double2), beta, alpha (double), beta_f,
+  // alpha_f (float), each concatenated over the axes (the stencils sum the
+  // diagonal rate lam in FP64 in every precision)
   const int tot = off;
   std::vector<double> lam(2 * tot), beta(tot), alpha(tot);
-  std::vector<float> lamf(2 * tot), betaf(tot), alphaf(tot);
+  std::vector<float> betaf(tot), alphaf(tot);
   for (int j = 0; j < t.n; ++j)
     for (int m = 0; m < t.ext[j]; ++m) {
       const int o = g.off[j] + m;
@@ -513,27 +533,22 @@ static void fill_grid_args(Function& f, int precision, bool want_real) {
       lam[2 * o + 1] = t.lam[j][m].imag();
       beta[o] = t.beta[j][m];
       alpha[o] = t.alpha[j][m];
-      lamf[2 * o] = (float)lam[2 * o];
-      lamf[2 * o + 1] = (float)lam[2 * o + 1];
       betaf[o] = (float)beta[o];
       alphaf[o] = (float)alpha[o];
     }
-  const size_t b_lam = sizeof(double) * 2 * tot, b_d = sizeof(double) * tot;
-  const size_t b_lamf = sizeof(float) * 2 * tot, b_f = sizeof(float) * tot;
-  const size_t o_beta = b_lam, o_alpha = o_beta + b_d, o_lamf = o_alpha + b_d, o_betaf = o_lamf + b_lamf,
-               o_alphaf = o_betaf + b_f, total = o_alphaf + b_f + 64;
+  const size_t b_lam = sizeof(double) * 2 * tot, b_d = sizeof(double) * tot, b_f = sizeof(float) * tot;
+  const size_t o_beta = b_lam, o_alpha = o_beta + b_d, o_betaf = o_alpha + b_d, o_alphaf = o_betaf + b_f,
+               total = o_alphaf + b_f + 64;
   f.dtab = dmalloc(total);
   char* base = (char*)f.dtab;
   hip_check(hipMemcpy(base, lam.data(), b_lam, hipMemcpyHostToDevice), "upload tables");
   hip_check(hipMemcpy(base + o_beta, beta.data(), b_d, hipMemcpyHostToDevice), "upload tables");
   hip_check(hipMemcpy(base + o_alpha, alpha.data(), b_d, hipMemcpyHostToDevice), "upload tables");
-  hip_check(hipMemcpy(base + o_lamf, lamf.data(), b_lamf, hipMemcpyHostToDevice), "upload tables");
   hip_check(hipMemcpy(base + o_betaf, betaf.data(), b_f, hipMemcpyHostToDevice), "upload tables");
   hip_check(hipMemcpy(base + o_alphaf, alphaf.data(), b_f, hipMemcpyHostToDevice), "upload tables");
   g.lam = (const double2*)base;
   g.beta = (const double*)(base + o_beta);
   g.alpha = (const double*)(base + o_alpha);
-  g.lam_f = (const float2*)(base + o_lamf);
   g.beta_f = (const float*)(base + o_betaf);
   g.alpha_f = (const float*)(base + o_alphaf);
   g.tiles = nullptr;
@@ -1921,7 +1936,8 @@ static void retile(Function& f, int precision, const TileChoice& c) {
     g.ntiles = g.points;
     g.xblock = 0;
     g.pipe = 0;
-  } else if (!configure_tiles(g, precision, f.real, c) || (g.real != 0) != f.real) {
+  } else if ((!g.phase_linear && precision == HGF_MIXED) || !configure_tiles(g, precision, f.real, c) ||
+             (g.real != 0) != f.real) {
     fail(HGF_EINVAL, "tile configuration not feasible for this grid");
   }
   g.tiles = nullptr;

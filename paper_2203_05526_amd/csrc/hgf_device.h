@@ -100,4 +100,43 @@ __device__ __forceinline__ void stg_nt(T* base, uint32_t idx, T v) {
   nt_store((T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))), v);
 }
 
+// Diagonal term lam(m) z of the stencil, lam(m) = lam_slow(tile) + lam_fast(p).
+// Complex FP32 stage grids (the mixed form of off-diagonal sectors): the
+// phase Im lam reaches 1e4 rad/us and its parts cancel, so a phase rounded to
+// FP32 would leave a systematic error that grows with the number of steps.
+// Within a sector the phase is linear in the occupations (the cross-Kerr
+// products cancel), Im lam_j(m) = m * slope_j, so it is formed in FP64 from
+// the tile's FP64 part and the point's fast coordinates and applied as
+// hi + lo in FP32.  The damping part (Re lam, all terms of one sign) is taken
+// in the stage type, as are both parts for other element types.
+template <typename TS>
+struct DiagLam {
+  static constexpr bool split = false;
+};
+template <>
+struct DiagLam<float2> {
+  static constexpr bool split = true;
+};
+// (ar, ai) = lam z: lsr, lsi the slow part in the stage type, lsdi its phase
+// in FP64, lf the fast part (stage type), pf the fast phase in FP64 (split only)
+template <typename TS>
+__device__ __forceinline__ void diag_term(typename Real<TS>::T lsr, typename Real<TS>::T lsi, double lsdi, TS lf,
+                                          double pf, TS zc, typename Real<TS>::T& ar, typename Real<TS>::T& ai) {
+  using R = typename Real<TS>::T;
+  const R lr = lsr + re_(lf);
+  if constexpr (DiagLam<TS>::split) {
+    const double Li = lsdi + pf;
+    const R hi = (R)Li;
+    const R lo = (R)(Li - (double)hi);
+    ar = -lo * im_(zc);
+    ai = lo * re_(zc);
+    ar += lr * re_(zc) - hi * im_(zc);
+    ai += lr * im_(zc) + hi * re_(zc);
+  } else {
+    const R li = lsi + im_(lf);
+    ar = lr * re_(zc) - li * im_(zc);
+    ai = lr * im_(zc) + li * re_(zc);
+  }
+}
+
 }  // namespace hgf

@@ -126,9 +126,10 @@ struct GridArgs {
   const uint32_t* walk;     // tile index at each walk position (NULL: the identity)
   double lam0_re, lam0_im;
   const double2* lam;       // concatenated lam_j(m)
+  double phase_slope[kMaxModes];  // Im lam_j(m) = m * phase_slope[j] (linear within a sector)
+  int phase_linear;         // the tables have that form (else mixed precision runs the generic kernel)
   const double* beta;       // concatenated beta_j(m)
   const double* alpha;      // concatenated alpha_j(m) (0 at m = 0)
-  const float2* lam_f;
   const float* beta_f;
   const float* alpha_f;
   const FullTables* full;   // network operator on the full (k, l) grid, else NULL
@@ -167,6 +168,28 @@ struct FullTerm {
   double cr, ci;
 };
 constexpr int32_t kFullShift = 4, kFullUp = 8, kFullFactor = 16;
+
+// Bits per fast coordinate in the tiled kernels' per-position words (16 bits
+// hold NF coordinates): 4 for four fast axes (extents <= 16), else 5.
+__host__ __device__ constexpr int tile_coord_bits(int nf) { return nf == 4 ? 4 : 5; }
+
+// LDS carve-up of the tiled stage kernels, shared by the host (sizing) and
+// the kernels (pointers), in bytes from the start of dynamic LDS: the padded
+// tile (lds_elems stage elements of `ts` bytes), the per-position diagonal
+// rate (T stage elements, 16-byte aligned), the per-position slot and
+// coordinate words (T uint32, rounded up to an even count), and the fast
+// axes' beta and alpha tables (esum values of `rs` bytes each), plus slack.
+struct TiledLds {
+  int lam_at, info_at, btab_at, bytes;
+};
+__host__ __device__ inline TiledLds tiled_lds(int lds_elems, int T, int esum, int ts, int rs) {
+  TiledLds l;
+  l.lam_at = (lds_elems * ts + 15) & ~15;
+  l.info_at = l.lam_at + T * ts;
+  l.btab_at = l.info_at + ((T + 1) & ~1) * 4;
+  l.bytes = l.btab_at + 2 * esum * rs + 64;
+  return l;
+}
 
 // Arguments of one member of a grouped (tiled) stage launch, kept in device
 // memory: the member's grid, its buffers per stage and its step size.

@@ -49,12 +49,6 @@ __device__ __forceinline__ typename C2<R>::T load_as(const T* p, int64_t i) {
 }
 
 template <typename R>
-__device__ __forceinline__ const typename C2<R>::T* lam_table(const GridArgs& g);
-template <>
-__device__ __forceinline__ const double2* lam_table<double>(const GridArgs& g) { return g.lam; }
-template <>
-__device__ __forceinline__ const float2* lam_table<float>(const GridArgs& g) { return g.lam_f; }
-template <typename R>
 __device__ __forceinline__ const R* beta_table(const GridArgs& g);
 template <>
 __device__ __forceinline__ const double* beta_table<double>(const GridArgs& g) { return g.beta; }
@@ -107,10 +101,11 @@ template <typename R, typename TIN>
 __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TIN* __restrict__ in,
                                                      const Walker& w) {
   using CT = typename C2<R>::T;
-  const CT* lam = lam_table<R>(g);
   const R* beta = beta_table<R>(g);
   const R* alpha = alpha_table<R>(g);
-  R lr = (R)g.lam0_re, li = (R)g.lam0_im;
+  // the diagonal rate lam(m) is summed in FP64 (its phase part can reach
+  // 1e4 rad/us and cancel between lam0 and the per-axis terms)
+  double lr = g.lam0_re, li = g.lam0_im;
   CT acc;
   acc.x = 0;
   acc.y = 0;
@@ -118,7 +113,7 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
   for (int j = 0; j < kMaxModes; ++j) {
     if (j < g.n) {
       const int m = w.c[j];
-      const CT lj = lam[g.off[j] + m];
+      const double2 lj = g.lam[g.off[j] + m];
       lr += lj.x;
       li += lj.y;
       // out-of-range neighbours read the centre with a zero coefficient
@@ -132,8 +127,15 @@ __device__ __forceinline__ typename C2<R>::T apply_L(const GridArgs& g, const TI
     }
   }
   const CT c = load_as<R>(in, w.i);
-  acc.x += lr * c.x - li * c.y;
-  acc.y += lr * c.y + li * c.x;
+  // lam = hi + lo in the stencil precision (lo = 0 in FP64): the stencil
+  // arithmetic sees the rate to FP64 accuracy, so rounding it to FP32 leaves
+  // no systematic phase error that would grow with the number of steps
+  const R hr = (R)lr, hi = (R)li;
+  const R or_ = (R)(lr - (double)hr), oi = (R)(li - (double)hi);
+  acc.x += or_ * c.x - oi * c.y;
+  acc.y += or_ * c.y + oi * c.x;
+  acc.x += hr * c.x - hi * c.y;
+  acc.y += hr * c.y + hi * c.x;
   return acc;
 }
 

@@ -68,10 +68,15 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
   // ---- per-point constants in registers: LDS slot, coordinates, diagonal
   // coefficient, up-jump coefficient per axis.  Lanes past the grid's end (last round)
   // work on a copy of the last point and store nothing.
+  // Diagonal rate: complex FP32 grids hold it as hi + lo of its FP64 value
+  // (Kerr phases reach 1e4 rad/us; a rate rounded to FP32 would leave a
+  // systematic phase error growing with the steps), other types in R.
+  constexpr bool SPLIT = DiagLam<TS>::split;
   const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
   int slot[kResidentRounds];
   uint32_t cpk[kResidentRounds];  // the point's coordinates, 5 bits per axis
   R lrr[kResidentRounds], lir[kResidentRounds], bqr[kResidentRounds][NF];
+  R lro[SPLIT ? kResidentRounds : 1], lio[SPLIT ? kResidentRounds : 1];
 #pragma unroll
   for (int r = 0; r < kResidentRounds; ++r) {
     if (r < rounds) {
@@ -93,10 +98,18 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
       }
       slot[r] = off;
       cpk[r] = cp;
-      // the same rounding as the tiled kernel: per-point sum in FP64, then the
-      // stage type, then the constant part added in the stage type
-      lrr[r] = lr0 + (R)lr;
-      lir[r] = li0 + (R)li;
+      if constexpr (SPLIT) {
+        const double Lr = it->g.lam0_re + lr, Li = it->g.lam0_im + li;
+        lrr[r] = (R)Lr;
+        lir[r] = (R)Li;
+        lro[r] = (R)(Lr - (double)lrr[r]);
+        lio[r] = (R)(Li - (double)lir[r]);
+      } else {
+        // the same rounding as the tiled kernel: per-point sum in FP64, then
+        // the stage type, then the constant part added in the stage type
+        lrr[r] = lr0 + (R)lr;
+        lir[r] = li0 + (R)li;
+      }
     }
   }
   __syncthreads();  // halo zeroed before the interior is written
@@ -129,8 +142,13 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
         if (r < rounds) {
           const int lo_ = slot[r];
           const TS zc = cur[lo_];
-          R ar = lrr[r] * re_(zc) - lir[r] * im_(zc);
-          R ai = lrr[r] * im_(zc) + lir[r] * re_(zc);
+          R ar = 0, ai = 0;
+          if constexpr (SPLIT) {
+            ar = lro[r] * re_(zc) - lio[r] * im_(zc);
+            ai = lro[r] * im_(zc) + lio[r] * re_(zc);
+          }
+          ar += lrr[r] * re_(zc) - lir[r] * im_(zc);
+          ai += lrr[r] * im_(zc) + lir[r] * re_(zc);
 #pragma unroll
           for (int q = 0; q < NF; ++q) {
             const TS dn = cur[lo_ - it->g.pstride[q]];

@@ -32,12 +32,12 @@
 namespace hgf {
 
 // Per-tile record of the slow-axis terms (built on the host, read with scalar
-// loads): lam_slow = lam0 + sum_{slow j} lam_j(s_j); for each slow axis the
-// element offsets of the down and up neighbour tiles and their coefficients
-// (an out-of-range direction has offset 0 and coefficient 0).
+// loads): lam_slow = lam0 + sum_{slow j} lam_j(s_j) in FP64; for each slow
+// axis the element offsets of the down and up neighbour tiles and their
+// coefficients (an out-of-range direction has offset 0 and coefficient 0).
 template <int NS, typename R>
 struct TileRec {
-  R lam_re, lam_im;
+  double lam_re, lam_im;
   int32_t off[2 * (NS > 0 ? NS : 1)];
   R coef[2 * (NS > 0 ? NS : 1)];
 };
@@ -195,10 +195,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   extern __shared__ __align__(16) unsigned char smem[];
   const int T = (int)g.tile_points;
   const int nt = blockDim.x, tid = threadIdx.x;
+  int esum = 0;
+#pragma unroll
+  for (int q = 0; q < NF; ++q) esum += g.ext[NS + q];
+  const TiledLds L = tiled_lds(g.lds_elems, T, esum, sizeof(TS), sizeof(R));
   TS* tile = (TS*)smem;
-  TS* lamf = tile + g.lds_elems;
-  uint32_t* info = (uint32_t*)(lamf + T);
-  R* btab = (R*)(info + ((T + 1) & ~1));
+  TS* lamf = (TS*)(smem + L.lam_at);
+  uint32_t* info = (uint32_t*)(smem + L.info_at);
+  R* btab = (R*)(smem + L.btab_at);
   const double2* lamt = g.lam;
   const double* betat = g.beta;
   const double* alphat = g.alpha;
@@ -208,7 +212,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   // slots with some coordinate at 0 (and the last row of the outermost fast
   // axis) are never written and read as the zero neighbours.
   for (int i = tid; i < g.lds_elems; i += nt) tile[i] = mk_<TS>(0, 0);
-  const uint32_t cmask = (1u << g.cbits) - 1u;
+  constexpr int CB = tile_coord_bits(NF);  // equals g.cbits (the host uses the same rule)
+  constexpr uint32_t cmask = (1u << CB) - 1u;
   for (int p = tid; p < T; p += nt) {
     int rem = p;
     uint32_t off = 0, coords = 0;
@@ -220,7 +225,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
       const int c = rem % e;
       rem /= e;
       off += (uint32_t)(c + 1) * (uint32_t)g.pstride[q];
-      coords |= (uint32_t)c << (g.cbits * q);
+      coords |= (uint32_t)c << (CB * q);
       const double2 lj = lamt[g.off[j] + c];
       lr += lj.x;
       li += lj.y;
@@ -231,9 +236,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
   // per-axis coefficient tables of the fast axes: btab (beta_j(c)) and, after
   // it, atab (alpha_j(c))
   int boff[NF];
-  int esum = 0;
-#pragma unroll
-  for (int q = 0; q < NF; ++q) esum += g.ext[NS + q];
   R* atab = btab + esum;
   {
     int o = 0;
@@ -313,7 +315,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
     // slow-axis terms, uniform over the tile (scalar loads of the tile's
     // record); every neighbour load is issued unconditionally
     const TileRec<NS, R>* rec = (const TileRec<NS, R>*)g.tiles + t;
-    const R lsr = rec->lam_re, lsi = rec->lam_im;
+    const double lsdi = rec->lam_im;
+    const R lsr = (R)rec->lam_re, lsi = (R)lsdi;
     int32_t soff[2 * (NS > 0 ? NS : 1)];
     R scoef[2 * (NS > 0 ? NS : 1)];
 #pragma unroll
@@ -357,15 +360,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
         const uint32_t inf = info[p];
         const int lo_ = (int)(inf & 0xffffu);
         const TS zc = tile[lo_];
-        const TS lf = lamf[p];
-        const R lr = lsr + re_(lf), li = lsi + im_(lf);
-        R ar = lr * re_(zc) - li * im_(zc);
-        R ai = lr * im_(zc) + li * re_(zc);
+        double pf = 0.0;  // phase of the fast part in FP64 (complex FP32 grids)
+        if constexpr (DiagLam<TS>::split) {
+#pragma unroll
+          for (int q = 0; q < NF; ++q)
+            pf += (double)(int)((inf >> (16 + CB * q)) & cmask) * g.phase_slope[NS + q];
+        }
+        R ar, ai;
+        diag_term<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
           const TS dn = tile[lo_ - g.pstride[q]];
           const TS upv = tile[lo_ + g.pstride[q]];
-          const int c = (int)((inf >> (16 + g.cbits * q)) & cmask);
+          const int c = (int)((inf >> (16 + CB * q)) & cmask);
           const R bq = btab[boff[q] + c];
           const R aq = atab[boff[q] + c];
           ar += aq * re_(dn) + bq * re_(upv);
@@ -454,11 +461,15 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       if (tid == 0) atomicOr(flag, 2);
       return;
     }
-    TS* const lamf = tile + mp->g.lds_elems;
-    uint32_t* const info = (uint32_t*)(lamf + T);
-    R* const btab = (R*)(info + ((T + 1) & ~1));
-    const int cbits = mp->g.cbits;
-    const uint32_t cmask = (1u << cbits) - 1u;
+    int esum = 0;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) esum += mp->g.ext[NS + q];
+    const TiledLds L = tiled_lds(mp->g.lds_elems, T, esum, sizeof(TS), sizeof(R));
+    TS* const lamf = (TS*)(smem + L.lam_at);
+    uint32_t* const info = (uint32_t*)(smem + L.info_at);
+    R* const btab = (R*)(smem + L.btab_at);
+    constexpr int cbits = tile_coord_bits(NF);  // equals mp->g.cbits (the host uses the same rule)
+    constexpr uint32_t cmask = (1u << cbits) - 1u;
     __syncthreads();  // a previous member's tile is no longer read
     // zero halo and per-position tables.  LDS layout of the tile: fast
     // coordinate c_q sits at c_q + 1 with stride pstride[q]; the slots with
@@ -484,9 +495,6 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       info[p] = off | (coords << 16);
       lamf[p] = mk_<TS>((R)lr, (R)li);
     }
-    int esum = 0;
-#pragma unroll
-    for (int q = 0; q < NF; ++q) esum += mp->g.ext[NS + q];
     R* const atab = btab + esum;
     {
       int o = 0;
@@ -541,7 +549,8 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
       }
       // slow-axis terms, uniform over the tile (scalar loads of its record)
       const TileRec<NS, R>* rec = (const TileRec<NS, R>*)mp->g.tiles + lt;
-      const R lsr = rec->lam_re, lsi = rec->lam_im;
+      const double lsdi = rec->lam_im;
+      const R lsr = (R)rec->lam_re, lsi = (R)lsdi;
       int32_t soff[2 * (NS > 0 ? NS : 1)];
       R scoef[2 * (NS > 0 ? NS : 1)];
 #pragma unroll
@@ -563,10 +572,14 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
         const uint32_t inf = info[p];
         const int lo_ = (int)(inf & 0xffffu);
         const TS zc = tile[lo_];
-        const TS lf = lamf[p];
-        const R lr = lsr + re_(lf), li = lsi + im_(lf);
-        R ar = lr * re_(zc) - li * im_(zc);
-        R ai = lr * im_(zc) + li * re_(zc);
+        double pf = 0.0;  // phase of the fast part in FP64 (complex FP32 grids)
+        if constexpr (DiagLam<TS>::split) {
+#pragma unroll
+          for (int q = 0; q < NF; ++q)
+            pf += (double)(int)((inf >> (16 + cbits * q)) & cmask) * mp->g.phase_slope[NS + q];
+        }
+        R ar, ai;
+        diag_term<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
         int bo = 0;
 #pragma unroll
         for (int q = 0; q < NF; ++q) {

@@ -240,7 +240,7 @@ def grad_c3b(seed: int = 3, cutoff: int = 8, t_total: float = 0.02,
     """Off-diagonal companion of the gradient workload: observable
     prod_j (a_j + a_j^+), which spans 2^N occupation-difference sectors."""
     sysm, bits, alpha = seeded_system((cutoff,) * 4, seed)
-    return Workload("4 Kerr modes, cutoff 8, product of quadratures", sysm,
+    return Workload(f"4 Kerr modes, cutoff {cutoff}, product of quadratures", sysm,
                     quadrature_factors(sysm.cutoff),
                     [coherent_state(alpha)], t_total, dt, bitstring=bits)
 

@@ -104,7 +104,7 @@ def test_secular_gradient_matches_oracle_sensitivities(hgf):
     ref_grad = np.array([oracle.expectation(cutoff, sp, st) for sp in sens])
     val, g = hgf.grad(S, st, T, dt, dense=M, checkpoint_every=7)
     assert rel(val, ref_val) < FP64_TOL
-    assert np.max(np.abs(g - ref_grad)) / np.max(np.abs(ref_grad)) < 1e-9
+    assert np.max(np.abs(g - ref_grad)) / np.max(np.abs(ref_grad)) < FP64_TOL
 
 
 def test_secular_equals_lindblad_on_populations(hgf):
