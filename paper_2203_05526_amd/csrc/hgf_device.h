@@ -117,25 +117,33 @@ template <>
 struct DiagLam<float2> {
   static constexpr bool split = true;
 };
-// (ar, ai) = lam z: lsr, lsi the slow part in the stage type, lsdi its phase
-// in FP64, lf the fast part (stage type), pf the fast phase in FP64 (split only)
+// (ar, ai) += lam z: lsr, lsi the slow part in the stage type, lsdi its phase
+// in FP64, lf the fast part (stage type), pf the fast phase in FP64 (split
+// only).  The stencils add this term last, after the neighbour terms, with
+// its products fused into the accumulator: accumulated first, the large
+// diagonal product made every later neighbour addition round at its scale,
+// which left a systematic error growing with the steps.
 template <typename TS>
-__device__ __forceinline__ void diag_term(typename Real<TS>::T lsr, typename Real<TS>::T lsi, double lsdi, TS lf,
-                                          double pf, TS zc, typename Real<TS>::T& ar, typename Real<TS>::T& ai) {
+__device__ __forceinline__ void diag_add(typename Real<TS>::T lsr, typename Real<TS>::T lsi, double lsdi, TS lf,
+                                         double pf, TS zc, typename Real<TS>::T& ar, typename Real<TS>::T& ai) {
   using R = typename Real<TS>::T;
   const R lr = lsr + re_(lf);
   if constexpr (DiagLam<TS>::split) {
     const double Li = lsdi + pf;
     const R hi = (R)Li;
     const R lo = (R)(Li - (double)hi);
-    ar = -lo * im_(zc);
-    ai = lo * re_(zc);
-    ar += lr * re_(zc) - hi * im_(zc);
-    ai += lr * im_(zc) + hi * re_(zc);
+    ar -= lo * im_(zc);
+    ai += lo * re_(zc);
+    ar += lr * re_(zc);
+    ai += lr * im_(zc);
+    ar -= hi * im_(zc);
+    ai += hi * re_(zc);
   } else {
     const R li = lsi + im_(lf);
-    ar = lr * re_(zc) - li * im_(zc);
-    ai = lr * im_(zc) + li * re_(zc);
+    ar += lr * re_(zc);
+    ai += lr * im_(zc);
+    ar -= li * im_(zc);
+    ai += li * re_(zc);
   }
 }
 

@@ -143,12 +143,6 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
           const int lo_ = slot[r];
           const TS zc = cur[lo_];
           R ar = 0, ai = 0;
-          if constexpr (SPLIT) {
-            ar = lro[r] * re_(zc) - lio[r] * im_(zc);
-            ai = lro[r] * im_(zc) + lio[r] * re_(zc);
-          }
-          ar += lrr[r] * re_(zc) - lir[r] * im_(zc);
-          ai += lrr[r] * im_(zc) + lir[r] * re_(zc);
 #pragma unroll
           for (int q = 0; q < NF; ++q) {
             const TS dn = cur[lo_ - it->g.pstride[q]];
@@ -157,6 +151,16 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
             ar += aq * re_(dn) + bqr[r][q] * re_(upv);
             ai += aq * im_(dn) + bqr[r][q] * im_(upv);
           }
+          // the diagonal last (its products fused into the accumulator), as
+          // in the tiled kernels
+          if constexpr (SPLIT) {
+            ar += lro[r] * re_(zc) - lio[r] * im_(zc);
+            ai += lro[r] * im_(zc) + lio[r] * re_(zc);
+          }
+          ar += lrr[r] * re_(zc);
+          ai += lrr[r] * im_(zc);
+          ar -= lir[r] * im_(zc);
+          ai += lir[r] * re_(zc);
           if (stage == 1) {
             xr[r] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));
             orr[r] = xr[r];

@@ -366,8 +366,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
           for (int q = 0; q < NF; ++q)
             pf += (double)(int)((inf >> (16 + CB * q)) & cmask) * g.phase_slope[NS + q];
         }
-        R ar, ai;
-        diag_term<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
+        R ar = 0, ai = 0;
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
           const TS dn = tile[lo_ - g.pstride[q]];
@@ -383,6 +382,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TiledWaves<
           ar += scoef[j] * re_(sv[j].e[v]);
           ai += scoef[j] * im_(sv[j].e[v]);
         }
+        diag_add<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
         if (stage == 1) {
           o.e[v] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));
         } else if (stage == 2 || stage == 3) {
@@ -578,8 +578,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
           for (int q = 0; q < NF; ++q)
             pf += (double)(int)((inf >> (16 + cbits * q)) & cmask) * mp->g.phase_slope[NS + q];
         }
-        R ar, ai;
-        diag_term<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
+        R ar = 0, ai = 0;
         int bo = 0;
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
@@ -598,6 +597,7 @@ __global__ __launch_bounds__(512) void k_rk4_group(const MemberArgs* __restrict_
           ar += scoef[j] * re_(sv[j]);
           ai += scoef[j] * im_(sv[j]);
         }
+        diag_add<TS>(lsr, lsi, lsdi, lamf[p], pf, zc, ar, ai);
         if (pr < T) {
           const double h = mp->h;
           if (stage == 1) {
