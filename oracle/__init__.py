@@ -63,6 +63,8 @@ def _load():
                                                  ctypes.c_double, ctypes.c_int]
     lib.oracle_rhs_full.argtypes = sysargs + [dp, dp, vp, vp, ctypes.c_int]
     lib.oracle_evolve_full.argtypes = sysargs + [dp, dp, vp, ctypes.c_long, ctypes.c_double, ctypes.c_int]
+    lib.oracle_evolve_separated.argtypes = sysargs + [dp, dp, ctypes.c_int, ip, ip, vp, ctypes.c_int, vp, vp, vp,
+                                                      ctypes.c_long, ctypes.c_double, ctypes.c_int]
     lib.oracle_num_params.argtypes = [ctypes.c_int]
     lib.oracle_max_threads.argtypes = []
     _lib = lib
@@ -142,6 +144,78 @@ def evolve_full(system, A: np.ndarray, t_total: float, dt: float, nthreads: int 
     if rc:
         raise RuntimeError(f"oracle_evolve_full failed ({rc})")
     return A
+
+
+def monomials(system, A: np.ndarray, drop_tol: float = 0.0):
+    """The initial monomials of Eq. (10) for the full number-basis matrix A:
+    (p, q, g_pq(0)) for every coefficient g_{p,q} = A[p, q] / sqrt(p! q!)
+    (Eqs. (6)-(8) with o1 = a^+, o2 = a) with |g_pq| > drop_tol, p and q as
+    occupation tuples."""
+    cutoff = tuple(system.cutoff)
+    dim = int(np.prod(cutoff))
+    out = []
+    for K in range(dim):
+        k = np.unravel_index(K, cutoff)
+        for L in range(dim):
+            if A[K, L] == 0:
+                continue
+            l = np.unravel_index(L, cutoff)
+            sc = math.sqrt(float(np.prod([math.factorial(int(x)) for x in k + l])))
+            g = complex(A[K, L]) / sc
+            if abs(g) > drop_tol:
+                out.append((tuple(int(x) for x in k), tuple(int(x) for x in l), g))
+    return out
+
+
+def evolve_separated(system, monos, t_total: float, dt: float, rmode: str = "full", nthreads: int = 0):
+    """The separated form G = Gx Gy + R of Eqs. (9a)-(9c) for every monomial
+    (p, q, c) of `monos` (Gx(0) = x^p, Gy(0) = y^q, R(0) = 0), classical RK4
+    on the joint state.  Returns (gx [nmono, *cutoff], gy [nmono, *cutoff],
+    r): r is the sum over the monomials of c R, on the full (k, l) box
+    ([dim, dim], rmode "full") or on its diagonal k = l ([*cutoff], rmode "z",
+    the approximation by a function of x_j y_j)."""
+    lib = _load()
+    cutoff = tuple(system.cutoff)
+    n = len(cutoff)
+    dim = int(np.prod(cutoff))
+    nm = len(monos)
+    P = np.ascontiguousarray(np.array([m[0] for m in monos], dtype=np.int32).reshape(nm, n))
+    Q = np.ascontiguousarray(np.array([m[1] for m in monos], dtype=np.int32).reshape(nm, n))
+    C = np.ascontiguousarray(np.array([m[2] for m in monos], dtype=np.complex128))
+    gx = np.zeros((nm, dim), dtype=np.complex128)
+    gy = np.zeros((nm, dim), dtype=np.complex128)
+    for i in range(nm):
+        gx[i, np.ravel_multi_index(P[i], cutoff)] = 1.0
+        gy[i, np.ravel_multi_index(Q[i], cutoff)] = 1.0
+    rm = {"full": 0, "z": 1}[rmode]
+    r = np.zeros((dim, dim) if rm == 0 else (dim,), dtype=np.complex128)
+    args, keep = _sysargs(system)
+    rc = lib.oracle_evolve_separated(*args, *_network_args(system, keep), nm,
+                                     P.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                     Q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), C.ctypes.data, rm,
+                                     gx.ctypes.data, gy.ctypes.data, r.ctypes.data, n_steps(t_total, dt), float(dt),
+                                     nthreads)
+    if rc:
+        raise RuntimeError(f"oracle_evolve_separated failed ({rc})")
+    return gx.reshape((nm,) + cutoff), gy.reshape((nm,) + cutoff), (r if rm == 0 else r.reshape(cutoff))
+
+
+def separated_matrix(system, monos, gx, gy, r) -> np.ndarray:
+    """The full number-basis matrix of G = sum_i c_i Gx_i Gy_i + R (Eq. (11)
+    with the coefficient map of Eqs. (6)-(8)): M[k, l] = sqrt(k! l!) g(k, l)."""
+    cutoff = tuple(system.cutoff)
+    dim = int(np.prod(cutoff))
+    g = np.zeros((dim, dim), dtype=np.complex128)
+    for i, (_, _, c) in enumerate(monos):
+        g += c * np.outer(gx[i].reshape(dim), gy[i].reshape(dim))
+    r = np.asarray(r)
+    if r.shape == (dim, dim):
+        g += r
+    else:
+        g += np.diag(r.reshape(dim))
+    fac = np.array([math.sqrt(float(np.prod([math.factorial(int(x)) for x in np.unravel_index(K, cutoff)])))
+                    for K in range(dim)])
+    return g * np.outer(fac, fac)
 
 
 def _pack(system, ops: Sectors):

@@ -593,3 +593,273 @@ int oracle_evolve_sens(int n, const int *nc, const double *det, const double *ke
   free(units); free(X); free(kk); free(Y); free(acc); free(tmp);
   return 0;
 }
+
+/*
+ * ------------------------------------------------------------------------
+ * Separated form of the paper's method (Eqs. (9a)-(9c), with the network
+ * generator of Eqs. (16)-(19)): the transformed generating function of each
+ * initial monomial x^p y^q is held as G = Gx(x) Gy(y) + R(x, y) with
+ *   dGx/dt = (Kx + C) Gx,   dGy/dt = (Ky - C) Gy,
+ *   dR/dt  = (Kx + Ky + P) R + P (Gx Gy),
+ * Gx(0) = x^p, Gy(0) = y^q, R(0) = 0, and C = -(i/2)(E(p) + E(q)) (the
+ * separation constant of Eq. (20) for this Hamiltonian).  Everything is in
+ * the coefficients of the generating functions (g = <k|A|l> / sqrt(k! l!)),
+ * on the truncated box:
+ *   Kx (left multiplication by i H plus the k-half of the dissipator):
+ *     x^k  ->  [i E(k) - sum_j (out_j(k_j) / 2 + gamma_phi_j k_j^2)] x^k
+ *     drive:    i Omega_j x_j + i conj(Omega_j) d/dx_j
+ *     exchange: i J_ij (x_i d/dx_j + x_j d/dx_i)
+ *   Ky (right multiplication by -i H plus the l-half):
+ *     y^l  ->  [-i E(l) - sum_j (out_j(l_j) / 2 + gamma_phi_j l_j^2)] y^l
+ *     drive:    -i Omega_j d/dy_j - i conj(Omega_j) y_j
+ *     exchange: -i J_ij (y_j d/dy_i + y_i d/dy_j)
+ *   P (the parts that couple x and y: jumps and the dephasing cross term):
+ *     Lindblad:  gamma1_j (1 + nth_j) x_j y_j  +  gamma1_j nth_j d/dx_j d/dy_j
+ *     secular:   the same two shifts restricted to the terms with k_j = l_j,
+ *                with the per-transition rates (down gamma1 (nbar_{k-1} + 1),
+ *                up gamma1 nbar_k (k + 1)^2 on the coefficients)
+ *     dephasing: 2 gamma_phi_j k_j l_j
+ * with out_j(n) the total jump rate out of level n (truncated ladders:
+ * Lindblad gamma1 (1 + nth) n + gamma1 nth (n + 1)[n + 1 < Nc]; secular the
+ * sum of the two transition rates).  Kx + Ky + P is the full generator of
+ * the coefficients, so G follows the adjoint master equation exactly in
+ * continuous time.
+ *
+ * Classical RK4 on the joint state (Gx_i, Gy_i of every monomial i, R).
+ * R is linear with the source sum_i c_i P(Gx_i Gy_i) (c_i = g_{p_i q_i}(0)),
+ * so one R holds the sum over the monomials of c_i R_i.
+ *
+ * rmode 0: R on the whole (k, l) box.  rmode 1: R restricted to the diagonal
+ * k = l (a function of the products z_j = x_j y_j alone, the approximation
+ * the paper reports for the network); each stage's derivative is taken on
+ * the diagonal, where Kx + Ky reduces to -sum_j out_j(m_j) and P keeps its
+ * diagonal shifts, and the off-diagonal part of every term is dropped.
+ *
+ * gx, gy: [nmono * dim] in/out (row-major boxes, last mode fastest), r:
+ * [dim * dim] (rmode 0) or [dim] (rmode 1) in/out, coef: [nmono].
+ */
+static void sep_tables(const osys *s, double *outr /* [OMAXN][OMAXC] */, double *down, double *up) {
+  for (int j = 0; j < s->n; ++j) {
+    const int nc = s->nc[j];
+    for (int m = 0; m < nc; ++m) {
+      double o = 0.0, dn = 0.0, u = 0.0;
+      if (s->secular) {
+        const double *nb = s->nlev[j];
+        if (m >= 1) o += s->g1[j] * m * (nb[m - 1] + 1.0);
+        if (m + 1 < nc) o += s->g1[j] * (m + 1) * nb[m];
+        if (m >= 1) dn = s->g1[j] * (nb[m - 1] + 1.0);
+        if (m + 1 < nc) u = s->g1[j] * nb[m] * (m + 1.0) * (m + 1.0);
+      } else {
+        const double kd = s->g1[j] * (1.0 + s->nth[j]), ku = s->g1[j] * s->nth[j];
+        o = kd * m + ((m + 1 < nc) ? ku * (m + 1) : 0.0);
+        if (m >= 1) dn = kd;
+        if (m + 1 < nc) u = ku; /* times (k_j + 1)(l_j + 1) at the point */
+      }
+      outr[j * OMAXC + m] = o;
+      down[j * OMAXC + m] = dn;
+      up[j * OMAXC + m] = u;
+    }
+  }
+}
+
+static void unflat(const osys *s, long f, int *k) {
+  for (int j = s->n - 1; j >= 0; --j) {
+    k[j] = (int)(f % s->nc[j]);
+    f /= s->nc[j];
+  }
+}
+
+/* out = (Kx + c) gx (side 0) or (Ky + c) gy (side 1) on one N-mode box */
+static void sep_side(const osys *s, const double *outr, int side, cplx c, const cplx *g, cplx *out) {
+  const int n = s->n;
+  const long dim = box_size(s);
+  long stride[OMAXN];
+  stride[n - 1] = 1;
+  for (int j = n - 2; j >= 0; --j) stride[j] = stride[j + 1] * s->nc[j + 1];
+  const double sg = side == 0 ? 1.0 : -1.0;
+  for (long f = 0; f < dim; ++f) {
+    int k[OMAXN];
+    unflat(s, f, k);
+    double damp = 0.0;
+    for (int j = 0; j < n; ++j) damp += 0.5 * outr[j * OMAXC + k[j]] + s->gphi[j] * k[j] * k[j];
+    cplx r = (sg * I * energy(s, k) - damp + c) * g[f];
+    for (int j = 0; j < n; ++j) {
+      const cplx om = s->drive[j];
+      if (om == 0.0) continue;
+      const int nc = s->nc[j];
+      /* x side: i Omega x + i conj(Omega) d/dx;  y side: -i Omega d/dy - i conj(Omega) y */
+      const cplx cmul = side == 0 ? I * om : -I * conj(om);   /* multiplication by the variable */
+      const cplx cder = side == 0 ? I * conj(om) : -I * om;   /* derivative */
+      if (k[j] >= 1) r += cmul * g[f - stride[j]];
+      if (k[j] + 1 < nc) r += cder * (k[j] + 1.0) * g[f + stride[j]];
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        const double J = s->exch[i * n + j];
+        if (J == 0.0) continue;
+        /* x_i d/dx_j + x_j d/dx_i (and the same in y): v_i d/dv_j moves one
+           unit from j to i with the factor (k_j + 1) of the source */
+        cplx t = 0.0;
+        if (k[i] >= 1 && k[j] + 1 < s->nc[j]) t += (k[j] + 1.0) * g[f - stride[i] + stride[j]];
+        if (k[j] >= 1 && k[i] + 1 < s->nc[i]) t += (k[i] + 1.0) * g[f - stride[j] + stride[i]];
+        r += sg * I * J * t;
+      }
+    out[f] = r;
+  }
+}
+
+/* P applied to a full-box function S (rmode 0: every (k, l); rmode 1: only
+ * the diagonal points (m, m), written to out[m]).  S(k, l) is given by a
+ * callback-free representation: S = R (full) or the outer products of the
+ * monomials (gx_i (x) gy_i weighted by c_i), evaluated at the points needed. */
+typedef struct {
+  const cplx *R;       /* full R (may be NULL) */
+  int nmono;
+  const cplx *gx, *gy, *coef;
+  long dim;
+} sep_src;
+
+static cplx src_at(const sep_src *q, long K, long L) {
+  cplx v = q->R ? q->R[K * q->dim + L] : 0.0;
+  for (int i = 0; i < q->nmono; ++i) v += q->coef[i] * q->gx[i * q->dim + K] * q->gy[i * q->dim + L];
+  return v;
+}
+
+static cplx apply_P(const osys *s, const double *down, const double *up, const sep_src *q, long K, long L,
+                    const int *k, const int *l, const long *stride) {
+  cplx r = 0.0;
+  for (int j = 0; j < s->n; ++j) {
+    if (s->secular && k[j] != l[j]) {
+      continue;
+    }
+    if (k[j] >= 1 && l[j] >= 1) {
+      const double dn = s->secular ? down[j * OMAXC + k[j]] : down[j * OMAXC + 1];
+      r += dn * src_at(q, K - stride[j], L - stride[j]);
+    }
+    if (k[j] + 1 < s->nc[j] && l[j] + 1 < s->nc[j]) {
+      const double u = s->secular ? up[j * OMAXC + k[j]] : up[j * OMAXC + k[j]] * (k[j] + 1.0) * (l[j] + 1.0);
+      r += u * src_at(q, K + stride[j], L + stride[j]);
+    }
+  }
+  for (int j = 0; j < s->n; ++j)
+    if (s->gphi[j] != 0.0 && k[j] * l[j] != 0) r += 2.0 * s->gphi[j] * k[j] * l[j] * src_at(q, K, L);
+  return r;
+}
+
+/* derivative of R: rmode 0 on the full box, rmode 1 on the diagonal */
+static void sep_R(const osys *s, const double *outr, const double *down, const double *up, int rmode,
+                  const cplx *R, int nmono, const cplx *gx, const cplx *gy, const cplx *coef, cplx *out) {
+  const int n = s->n;
+  const long dim = box_size(s);
+  long stride[OMAXN];
+  stride[n - 1] = 1;
+  for (int j = n - 2; j >= 0; --j) stride[j] = stride[j + 1] * s->nc[j + 1];
+  if (rmode == 0) {
+    /* (Kx + Ky) R through the two one-sided maps on rows and columns, P on R + sum_i c_i gx_i gy_i */
+    cplx *col = malloc(sizeof(cplx) * dim), *tmp = malloc(sizeof(cplx) * dim);
+    for (long K = 0; K < dim; ++K) { /* Ky on each row K (a function of l) */
+      sep_side(s, outr, 1, 0.0, R + K * dim, tmp);
+      for (long L = 0; L < dim; ++L) out[K * dim + L] = tmp[L];
+    }
+    for (long L = 0; L < dim; ++L) { /* Kx on each column L (a function of k) */
+      for (long K = 0; K < dim; ++K) col[K] = R[K * dim + L];
+      sep_side(s, outr, 0, 0.0, col, tmp);
+      for (long K = 0; K < dim; ++K) out[K * dim + L] += tmp[K];
+    }
+    sep_src q = {R, nmono, gx, gy, coef, dim};
+#pragma omp parallel for schedule(static)
+    for (long f = 0; f < dim * dim; ++f) {
+      const long K = f / dim, L = f % dim;
+      int k[OMAXN], l[OMAXN];
+      unflat(s, K, k);
+      unflat(s, L, l);
+      out[f] += apply_P(s, down, up, &q, K, L, k, l, stride);
+    }
+    free(col); free(tmp);
+  } else {
+    /* diagonal: -sum_j out_j(m_j) R(m) + P (R + sum_i c_i gx_i gy_i) on (m, m); the
+       dephasing terms of Kx + Ky (-gamma_phi (k^2 + l^2)) and of P (2 gamma_phi k l)
+       cancel on the diagonal and are left out of both */
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < dim; ++m) {
+      int k[OMAXN];
+      unflat(s, m, k);
+      double o = 0.0;
+      for (int j = 0; j < n; ++j) o += outr[j * OMAXC + k[j]];
+      cplx r = -o * R[m];
+      /* P on the diagonal: its shifts stay on the diagonal (k - e_j, k - e_j) */
+      for (int j = 0; j < n; ++j) {
+        if (k[j] >= 1) {
+          const double dn = s->secular ? down[j * OMAXC + k[j]] : down[j * OMAXC + 1];
+          cplx v = R[m - stride[j]];
+          for (int i = 0; i < nmono; ++i)
+            v += coef[i] * gx[i * dim + m - stride[j]] * gy[i * dim + m - stride[j]];
+          r += dn * v;
+        }
+        if (k[j] + 1 < s->nc[j]) {
+          const double u = s->secular ? up[j * OMAXC + k[j]] : up[j * OMAXC + k[j]] * (k[j] + 1.0) * (k[j] + 1.0);
+          cplx v = R[m + stride[j]];
+          for (int i = 0; i < nmono; ++i)
+            v += coef[i] * gx[i * dim + m + stride[j]] * gy[i * dim + m + stride[j]];
+          r += u * v;
+        }
+        if (s->gphi[j] != 0.0 && k[j] != 0) {
+          cplx v = 0.0; /* the cross term acts on the source only (its R part cancelled above) */
+          for (int i = 0; i < nmono; ++i) v += coef[i] * gx[i * dim + m] * gy[i * dim + m];
+          r += 2.0 * s->gphi[j] * k[j] * k[j] * v;
+        }
+      }
+      out[m] = r;
+    }
+  }
+}
+
+int oracle_evolve_separated(int n, const int *nc, const double *det, const double *kerr, const double *chi,
+                            const double *g1, const double *gphi, const double *nth, int diss, const double *nlev,
+                            const double *drive, const double *exch, int nmono, const int *p, const int *q,
+                            const cplx *coef, int rmode, cplx *gx, cplx *gy, cplx *r, long nsteps, double h,
+                            int nthreads) {
+  osys s;
+  if (load_sys(&s, n, nc, det, kerr, chi, g1, gphi, nth, diss, nlev) || load_full(&s, drive, exch)) return -1;
+  if (rmode != 0 && rmode != 1) return -1;
+  set_threads(nthreads);
+  const long dim = box_size(&s), rlen = rmode == 0 ? dim * dim : dim;
+  const long xlen = (long)nmono * dim;
+  static double outr[OMAXN * OMAXC], down[OMAXN * OMAXC], up[OMAXN * OMAXC];
+  sep_tables(&s, outr, down, up);
+  cplx *Cs = malloc(sizeof(cplx) * (nmono > 0 ? nmono : 1));
+  for (int i = 0; i < nmono; ++i) Cs[i] = -0.5 * I * (energy(&s, p + (long)i * n) + energy(&s, q + (long)i * n));
+  /* joint state u = (gx, gy, r); RK4 with stage inputs Y, derivative kk, accumulator acc */
+  const long tot = 2 * xlen + rlen;
+  cplx *U = malloc(sizeof(cplx) * tot), *Y = malloc(sizeof(cplx) * tot), *kk = malloc(sizeof(cplx) * tot),
+       *acc = malloc(sizeof(cplx) * tot);
+  if (!U || !Y || !kk || !acc || !Cs) {
+    free(U); free(Y); free(kk); free(acc); free(Cs);
+    return -2;
+  }
+  memcpy(U, gx, sizeof(cplx) * xlen);
+  memcpy(U + xlen, gy, sizeof(cplx) * xlen);
+  memcpy(U + 2 * xlen, r, sizeof(cplx) * rlen);
+  static const double wacc[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+  static const double wnext[3] = {0.5, 0.5, 1.0};
+  for (long step = 0; step < nsteps; ++step) {
+    for (int st = 0; st < 4; ++st) {
+      const cplx *src = st == 0 ? U : Y;
+#pragma omp parallel for schedule(static)
+      for (int i = 0; i < nmono; ++i) {
+        sep_side(&s, outr, 0, Cs[i], src + (long)i * dim, kk + (long)i * dim);
+        sep_side(&s, outr, 1, -Cs[i], src + xlen + (long)i * dim, kk + xlen + (long)i * dim);
+      }
+      sep_R(&s, outr, down, up, rmode, src + 2 * xlen, nmono, src, src + xlen, coef, kk + 2 * xlen);
+      if (st == 0) axpy_into(tot, acc, U, h * wacc[0], kk);
+      else axpy_into(tot, acc, acc, h * wacc[st], kk);
+      if (st < 3) axpy_into(tot, Y, U, h * wnext[st], kk);
+      else memcpy(U, acc, sizeof(cplx) * tot);
+    }
+  }
+  memcpy(gx, U, sizeof(cplx) * xlen);
+  memcpy(gy, U + xlen, sizeof(cplx) * xlen);
+  memcpy(r, U + 2 * xlen, sizeof(cplx) * rlen);
+  free(U); free(Y); free(kk); free(acc); free(Cs);
+  return 0;
+}

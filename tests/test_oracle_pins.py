@@ -564,3 +564,76 @@ def test_network_exchange_swaps_a_coherent_field(oracle_lib):
         opT = oracle.evolve_full(s, op, T, dt)
         got = np.conj(c) @ opT @ c
         assert abs(got - want) < 1e-9 * abs(alpha), (got, want)
+
+
+# --------------------------------------------- separated form (Eqs. (9a)-(9c))
+
+def _product(factors):
+    A = np.ones((1, 1), dtype=np.complex128)
+    for f in factors:
+        A = np.kron(A, f)
+    return A
+
+
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+@pytest.mark.parametrize("cutoff,seed", [((4,), 140), ((3, 3), 141)])
+def test_separated_form_converges_to_expm(oracle_lib, cutoff, seed, dissipator):
+    """G = Gx Gy + R per initial monomial (Eq. (10)), with R on the whole
+    (k, l) box, is exact in continuous time: its RK4 result converges to
+    exp(S T) of the independently built Kronecker superoperator at fourth
+    order (error / 16 per halving of the step), for a driven, exchange-coupled
+    network with dephasing and a random operator over all (k, l)."""
+    s = network(seed, cutoff, dissipator)
+    s.gamma_phi = np.full(len(cutoff), 0.4)
+    dim = int(np.prod(cutoff))
+    rng = np.random.default_rng(seed)
+    A0 = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    monos = oracle.monomials(s, A0)
+    assert len(monos) == dim * dim
+    T = 0.3
+    ref = pinlib.expm_evolve(s, A0, T)
+    errs = []
+    for steps in (40, 80, 160):
+        gx, gy, r = oracle.evolve_separated(s, monos, T, T / steps, "full")
+        errs.append(pinlib.rel(oracle.separated_matrix(s, monos, gx, gy, r), ref))
+    assert errs[-1] < 1e-7, errs
+    for a, b in zip(errs, errs[1:]):
+        assert 10.0 < a / b < 24.0, errs
+
+
+def test_separated_form_without_dissipation_keeps_R_zero(oracle_lib):
+    """Without jumps and dephasing P = 0: R stays exactly zero and G = Gx Gy
+    (for both representations of R)."""
+    cutoff = (3, 4)
+    s = network(142, cutoff)
+    s.gamma1[:] = 0.0
+    s.gamma_phi[:] = 0.0
+    A0 = _product([oracle.adag_matrix(3).conj().T, oracle.adag_matrix(4)])
+    monos = oracle.monomials(s, A0)
+    for mode in ("full", "z"):
+        gx, gy, r = oracle.evolve_separated(s, monos, 0.2, 2.5e-4, mode)
+        assert np.max(np.abs(r)) == 0.0
+    ref = pinlib.expm_evolve(s, A0, 0.2)
+    assert pinlib.rel(oracle.separated_matrix(s, monos, gx, gy, r), ref) < 1e-9
+
+
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+def test_separated_z_grid_exact_without_drive_and_exchange(oracle_lib, dissipator):
+    """With no drive and no exchange the one-sided operators Kx, Ky are
+    diagonal, so a diagonal initial operator keeps Gx Gy diagonal in each
+    mode, the source P(Gx Gy) feeds only the diagonal, and R is a function of
+    x_j y_j alone: R on the z-grid equals R on the whole box."""
+    cutoff = (4, 3)
+    s = network(143, cutoff, dissipator)
+    s.drive = np.zeros(2, dtype=np.complex128)
+    s.exchange = np.zeros((2, 2))
+    s.gamma_phi = np.full(2, 0.5)
+    rng = np.random.default_rng(143)
+    A0 = np.diag(rng.normal(size=12) + 1j * rng.normal(size=12))
+    monos = oracle.monomials(s, A0)
+    gx, gy, r = oracle.evolve_separated(s, monos, 0.3, 1e-3, "full")
+    gx2, gy2, rz = oracle.evolve_separated(s, monos, 0.3, 1e-3, "z")
+    assert np.max(np.abs(r - np.diag(np.diag(r)))) == 0.0
+    assert np.max(np.abs(np.diag(r) - rz.reshape(-1))) < 1e-14 * np.max(np.abs(r))
+    assert pinlib.rel(oracle.separated_matrix(s, monos, gx2, gy2, rz),
+                      pinlib.expm_evolve(s, A0, 0.3)) < 1e-9
