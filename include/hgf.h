@@ -240,6 +240,24 @@ hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double ou
                            void* hip_stream);
 
 /*
+ * hgf_expectation for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, computed by the same kernels, with every device buffer of
+ * the call (weight tables, partial sums, result) taken from a static device
+ * array of 4 MiB that each GPU holds from the library's first use until the
+ * process ends.  No hipMalloc, hipFree or allocating library routine is
+ * called.  Operators whose buffers need more than 4 MiB (weight tables of
+ * sum_j extent_j complex values per function plus one partial sum per
+ * workgroup, at most 2048 per function: roughly a few hundred large functions
+ * or a few thousand small ones) are refused with HGF_EINVAL; hgf_expectation
+ * serves them.  Calls on one GPU share its array: calls that overlap in time
+ * on one GPU (several threads, or streams running concurrently) race and
+ * must be serialised by the caller.  Errors as for hgf_expectation.
+ */
+hgf_status hgf_expectation_noalloc(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2],
+                                   void* hip_stream);
+
+/*
  * Step (iii) at the operator level: the number-basis matrix elements
  * <k|A(t)|l> (Eq. (11): the generating-function coefficients g_{k,l} of the
  * evolved operator times sqrt(k! l!), with o1 = a^+, o2 = a, r = 1) for every

@@ -15,6 +15,7 @@ from .hgf import (  # noqa: F401
     evolve,
     evolve_batch,
     expectation,
+    expectation_noalloc,
     reconstruct,
     grad,
     load_library,

@@ -2422,7 +2422,13 @@ static std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_de
   return amps;
 }
 
-static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStream_t st) {
+// <psi0| A |psi0> over every function.  The device buffers of the call
+// (weight tables, per-block partial sums, their offsets and coefficients, the
+// result) are carved from `ws` (ws_bytes available; nothing is allocated) when
+// it is given, else allocated for the call.  Every buffer is written before it
+// is read, so `ws` need not be cleared.
+static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStream_t st, void* ws = nullptr,
+                           size_t ws_bytes = 0) {
   validate_state(op->sys, psi);
   const auto amps = all_amps(op->sys, psi);
   const int nf = (int)op->fn.size();
@@ -2444,19 +2450,44 @@ static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStr
       analytic += f.g0 * f.cx * f.cy * wm;
     }
   }
-  DBuf dw(wall.size() * sizeof(double2)), dpart(start[nf] * sizeof(double2)), dstart((nf + 1) * sizeof(int)),
-      dcoef(nf * sizeof(double2)), dout(sizeof(double2));
-  hip_check(hipMemcpyAsync(dw.p, wall.data(), wall.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
-  hip_check(hipMemcpyAsync(dstart.p, start.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, st), "upload");
-  hip_check(hipMemcpyAsync(dcoef.p, coef.data(), nf * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+  const size_t b_w = wall.size() * sizeof(double2), b_part = start[nf] * sizeof(double2),
+               b_start = (nf + 1) * sizeof(int), b_coef = nf * sizeof(double2), b_out = sizeof(double2);
+  double2 *dw, *dpart, *dcoef, *dout;
+  int* dstart;
+  std::vector<std::unique_ptr<DBuf>> owned;
+  if (ws) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t need = al(b_w) + al(b_part) + al(b_start) + al(b_coef) + al(b_out);
+    if (need > ws_bytes)
+      fail(HGF_EINVAL, "this expectation needs " + std::to_string(need) + " bytes of device scratch; the static "
+                       "scratch holds " + std::to_string(ws_bytes) + " (use hgf_expectation)");
+    char* p = (char*)ws;
+    dw = (double2*)p;
+    p += al(b_w);
+    dpart = (double2*)p;
+    p += al(b_part);
+    dstart = (int*)p;
+    p += al(b_start);
+    dcoef = (double2*)p;
+    p += al(b_coef);
+    dout = (double2*)p;
+  } else {
+    for (size_t b : {b_w, b_part, b_start, b_coef, b_out}) owned.emplace_back(new DBuf(b));
+    dw = owned[0]->as<double2>();
+    dpart = owned[1]->as<double2>();
+    dstart = owned[2]->as<int>();
+    dcoef = owned[3]->as<double2>();
+    dout = owned[4]->as<double2>();
+  }
+  hip_check(hipMemcpyAsync(dw, wall.data(), b_w, hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(dstart, start.data(), b_start, hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(dcoef, coef.data(), b_coef, hipMemcpyHostToDevice, st), "upload");
   for (int i = 0; i < nf; ++i)
-    launch_expect_partial(op->fn[i].ga, op->fn[i].y, true, dw.as<double2>() + woff[i],
-                          dpart.as<double2>() + start[i], st, op->fn[i].real);
-  launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), nf,
-                      make_double2(analytic.real(), analytic.imag()), dout.as<double2>(), st);
+    launch_expect_partial(op->fn[i].ga, op->fn[i].y, true, dw + woff[i], dpart + start[i], st, op->fn[i].real);
+  launch_expect_final(dpart, dstart, dcoef, nf, make_double2(analytic.real(), analytic.imag()), dout, st);
   hip_check(hipGetLastError(), "kernel launch");
   double2 r;
-  hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipMemcpyAsync(&r, dout, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
   hip_check(hipStreamSynchronize(st), "synchronize");
   return cd(r.x, r.y);
 }
@@ -2968,6 +2999,17 @@ hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double ou
     if (!op || !out_re_im) fail(HGF_EINVAL, "NULL argument");
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     const cd r = expectation_impl(op, psi, (hipStream_t)hip_stream);
+    out_re_im[0] = r.real();
+    out_re_im[1] = r.imag();
+  });
+}
+
+hgf_status hgf_expectation_noalloc(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2],
+                                   void* hip_stream) {
+  return guarded([&] {
+    if (!op || !out_re_im) fail(HGF_EINVAL, "NULL argument");
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    const cd r = expectation_impl(op, psi, (hipStream_t)hip_stream, scratch_address(), kScratchBytes);
     out_re_im[0] = r.real();
     out_re_im[1] = r.imag();
   });

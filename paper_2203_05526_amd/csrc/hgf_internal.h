@@ -17,6 +17,9 @@ constexpr int kMaxCutoff = HGF_MAX_CUTOFF;
 // Points of a tile handled by one thread of the tiled stage kernel:
 // lane groups of a tile <= kTileRounds * 512.
 constexpr int kTileRounds = 8;
+// Bytes of the static device scratch of the entry points that allocate
+// nothing (hgf_expectation_noalloc); every GPU holds one copy.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
 
 using cd = std::complex<double>;
 

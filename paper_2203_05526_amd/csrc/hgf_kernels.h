@@ -106,5 +106,8 @@ void launch_gather_levels(const GridArgs& g, const void* y, bool real, const Gat
 // device-to-device copy as a kernel (safe to record in a captured graph)
 void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st);
 void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st);
+// Device address of the current device's copy of the static scratch
+// (kScratchBytes), looked up once per device.
+void* scratch_address();
 
 }  // namespace hgf

@@ -26,7 +26,8 @@ STATUS = {0: "HGF_OK", -1: "HGF_EINVAL", -2: "HGF_ENOMEM", -3: "HGF_EDEVICE", -4
           -5: "HGF_ENONFINITE", -6: "HGF_EUNSUPPORTED", -7: "HGF_ESTATE"}
 
 EXPORTED = ["hgf_define_system", "hgf_destroy_system", "hgf_num_params", "hgf_map_operator",
-            "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_reconstruct", "hgf_grad",
+            "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_expectation_noalloc",
+            "hgf_reconstruct", "hgf_grad",
             "hgf_get_info", "hgf_get_function", "hgf_last_error", "hgf_version"]
 
 
@@ -110,6 +111,7 @@ def load_library(path: str = LIB_PATH):
     lib.hgf_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     lib.hgf_evolve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_expectation.argtypes = [vp, ctypes.POINTER(_StateDesc), _f64p, vp]
+    lib.hgf_expectation_noalloc.argtypes = [vp, ctypes.POINTER(_StateDesc), _f64p, vp]
     lib.hgf_reconstruct.argtypes = [vp, ctypes.c_int32, _f64p, vp]
     lib.hgf_grad.argtypes = [vp, ctypes.POINTER(_OperatorDesc), ctypes.POINTER(_StateDesc),
                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, _f64p, _f64p, vp]
@@ -429,6 +431,16 @@ def expectation(op: Operator, state, stream=None) -> complex:
     d, keep = _state_desc(op.system, state)
     out = np.zeros(2)
     _check(_lib.hgf_expectation(op.handle, ctypes.byref(d), out.ctypes.data_as(_f64p), _stream(stream)))
+    return complex(out[0], out[1])
+
+
+def expectation_noalloc(op: Operator, state, stream=None) -> complex:
+    """hgf_expectation_noalloc: the same value as expectation(), with every
+    device buffer taken from the library's static device scratch (no device
+    allocation; operators needing more than its 4 MiB are refused)."""
+    d, keep = _state_desc(op.system, state)
+    out = np.zeros(2)
+    _check(_lib.hgf_expectation_noalloc(op.handle, ctypes.byref(d), out.ctypes.data_as(_f64p), _stream(stream)))
     return complex(out[0], out[1])
 
 
