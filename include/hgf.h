@@ -77,8 +77,14 @@ enum {
 enum {
   HGF_MERGED = 0, /* one grid per occupation-difference sector, initial value the
                      sector's part of G(0) (Eq. (10) summed up front by linearity) */
-  HGF_SPLIT = 1   /* one function per non-negligible g_{p,q}(0): G = Gx Gy + R with
+  HGF_SPLIT = 1,  /* one function per non-negligible g_{p,q}(0): G = Gx Gy + R with
                      Gx = c_x x^p, Gy = c_y y^q, R(0) = 0 (Eqs. (9)-(10), (19)) */
+  HGF_SEPARATED = 2,      /* the separated form of Eqs. (9a)-(9c) with Gx(x) and Gy(y) as grids
+                             over the N occupations (drive and exchange shift them), one pair
+                             per non-negligible g_{p,q}(0), and R restricted to the diagonal
+                             k = l: R approximated by a function of the products x_j y_j (the
+                             approximation the paper reports for the driven network) */
+  HGF_SEPARATED_EXACT = 3 /* the same with R on the whole (k, l) box: exact in continuous time */
 };
 
 /* operator input forms */

@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libhgf.so")
 ARCH = os.environ.get("HGF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["hgf_kernels.hip", "hgf_full_tiled.hip", "hgf_tiled_c64.hip", "hgf_tiled_c128.hip", "hgf_tiled_r32.hip",
-           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_api.cpp", "hgf_tables.cpp"]
+           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_separated.hip", "hgf_api.cpp", "hgf_separated_host.cpp",
+           "hgf_tables.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -23,6 +23,7 @@
 
 #include "hgf.h"
 #include "hgf_internal.h"
+#include "hgf_host.h"
 #include "hgf_kernels.h"
 
 namespace hgf {
@@ -73,7 +74,7 @@ static hgf_status guarded(F&& f) {
 
 // ------------------------------------------------------------------ helpers
 
-static double sqrt_factorial(int n) {
+double sqrt_factorial(int n) {
   double f = 1.0;
   for (int i = 2; i <= n; ++i) f *= i;
   return std::sqrt(f);
@@ -100,7 +101,7 @@ static AllocHook g_hook;
 static uint64_t g_hook_generation = 0;
 static std::unordered_map<void*, uint64_t> g_hooked;  // block -> generation of its hook
 
-static void* dmalloc(size_t bytes) {
+void* dmalloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
   AllocHook h;
@@ -121,7 +122,7 @@ static void* dmalloc(size_t bytes) {
   return p;
 }
 
-static void dfree(void*& p) {
+void dfree(void*& p) {
   if (!p) return;
   AllocHook h;
   bool hooked = false, current = false;
@@ -145,20 +146,7 @@ static void dfree(void*& p) {
   p = nullptr;
 }
 
-// RAII device buffer for temporaries
-struct DBuf {
-  void* p = nullptr;
-  explicit DBuf(size_t bytes) { p = dmalloc(bytes); }
-  ~DBuf() { dfree(p); }
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  template <typename T>
-  T* as() const {
-    return (T*)p;
-  }
-};
-
-static int64_t check_steps(double t_total, double dt) {
+int64_t check_steps(double t_total, double dt) {
   if (!(std::isfinite(t_total) && std::isfinite(dt)) || t_total < 0 || dt <= 0)
     fail(HGF_EINVAL, "t_total must be >= 0 and dt > 0, both finite");
   const double r = t_total / dt;
@@ -610,17 +598,12 @@ static std::vector<cd> mode_g(const double* vals, int nc, int basis) {
   return g;
 }
 
-struct Coeff {
-  std::vector<int> k, l;
-  cd v;
-};
-
 // Largest total dimension of an HGF_OP_DENSE operator.
 constexpr int64_t kMaxDenseDim = 4096;
 
 // All nonzero g_{k,l}(0) of the operator, as (k, l, value).
-static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map<std::vector<int>, std::vector<cd>>& merged,
-                           std::vector<Coeff>& split, bool want_split) {
+void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map<std::vector<int>, std::vector<cd>>& merged,
+                    std::vector<Coeff>& split, bool want_split) {
   const int n = s.n;
   if (d->kind == HGF_OP_PRODUCT) {
     if (!d->values) fail(HGF_EINVAL, "operator values is NULL");
@@ -819,8 +802,6 @@ static void collect_coeffs(const System& s, const hgf_operator_desc* d, std::map
   }
 }
 
-// Largest full (k, l) grid of a network operator, in points.
-constexpr int64_t kMaxFullPoints = (int64_t)1 << 28;
 
 // Host-side size check of an operator before any device work: the grids its
 // coefficients populate must stay within kMaxOperatorPoints (per sector and in
@@ -956,7 +937,7 @@ static void setup_split(Function& f, const System& s, const Coeff& c) {
 
 
 // Generator tables of a network operator's full grid (see FullTables).
-static FullTables full_tables(const System& s) {
+FullTables full_tables(const System& s) {
   FullTables ft{};
   ft.n = s.n;
   ft.secular = s.secular;
@@ -996,7 +977,7 @@ static FullTables full_tables(const System& s) {
 // the largest diagonal entry (|E(k) - E(l)| is at most the range of E over
 // the grid, plus the damping and dephasing) plus every neighbour coefficient
 // at its largest.
-static double full_generator_bound(const FullTables& ft) {
+double full_generator_bound(const FullTables& ft) {
   double erange = 0.0, dmax = 0.0, b = 0.0;
   for (int j = 0; j < ft.n; ++j) {
     const int nc = ft.nc[j];
@@ -1387,7 +1368,7 @@ static void build_functions(hgf_operator_s* op, const hgf_operator_desc* d, bool
 
 // ------------------------------------------------------------------ stepping
 
-static void reset_flag(hgf_operator_s* op, hipStream_t st) {
+void reset_flag(hgf_operator_s* op, hipStream_t st) {
   hip_check(hipMemsetAsync(op->dflag, 0, sizeof(int), st), "reset flag");
 }
 
@@ -1762,7 +1743,7 @@ static void lawson_steps(hgf_operator_s* op, int64_t steps, double h, hipStream_
   hip_check(hipStreamSynchronize(st), "synchronize");  // the items must outlive the launches
 }
 
-static int read_flag(hgf_operator_s* op, hipStream_t st) {
+int read_flag(hgf_operator_s* op, hipStream_t st) {
   int flag = 0;
   hip_check(hipMemcpyAsync(&flag, op->dflag, sizeof(int), hipMemcpyDeviceToHost, st), "read flag");
   hip_check(hipStreamSynchronize(st), "synchronize");
@@ -1774,6 +1755,12 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
     fail(HGF_EUNSUPPORTED, "the integrating-factor scheme runs on merged-layout operators only");
   if (scheme == HGF_LAWSON_RK4 && op->sys.full)
     fail(HGF_EUNSUPPORTED, "the integrating-factor scheme needs uncoupled sectors (no drive or exchange)");
+  if (op->sep) {  // separated layout: classical RK4 on (Gx_i, Gy_i, R)
+    separated_evolve(op, steps, h, st);
+    op->steps_done += steps;
+    op->time_us += steps * h;
+    return;
+  }
   if (steps == 0) return;
   if (op->fn.empty()) {  // the zero operator stays zero
     op->steps_done += steps;
@@ -2373,7 +2360,7 @@ static std::vector<cd> mode_amps(const hgf_state_desc* psi, int j, int nc, size_
   return c;
 }
 
-static void validate_state(const System& s, const hgf_state_desc* psi) {
+void validate_state(const System& s, const hgf_state_desc* psi) {
   if (!psi) fail(HGF_EINVAL, "state is NULL");
   if (psi->kind == HGF_PSI_FOCK) {
     if (!psi->fock) fail(HGF_EINVAL, "fock occupations are NULL");
@@ -2412,7 +2399,7 @@ static std::vector<cd> sector_weights(const System& s, const Function& f, const 
   return w;
 }
 
-static std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_desc* psi) {
+std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_desc* psi) {
   std::vector<std::vector<cd>> amps(s.n);
   size_t off = 0;
   for (int j = 0; j < s.n; ++j) {
@@ -2429,6 +2416,10 @@ static std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_de
 // is read, so `ws` need not be cleared.
 static cd expectation_impl(hgf_operator_s* op, const hgf_state_desc* psi, hipStream_t st, void* ws = nullptr,
                            size_t ws_bytes = 0) {
+  if (op->sep) {
+    if (ws) fail(HGF_EUNSUPPORTED, "separated-layout operators are read through hgf_expectation");
+    return separated_expectation(op, psi, st);
+  }
   validate_state(op->sys, psi);
   const auto amps = all_amps(op->sys, psi);
   const int nf = (int)op->fn.size();
@@ -2501,6 +2492,10 @@ constexpr int64_t kMaxReconstructElems = (int64_t)1 << 24;
 // function's grid points in that box, times sqrt(k! l!), scattered into a
 // dense matrix on the device, then copied to `out`.
 static void reconstruct_impl(hgf_operator_s* op, int levels, double* out, hipStream_t st) {
+  if (op->sep) {
+    separated_reconstruct(op, levels, out, st);
+    return;
+  }
   const int n = op->sys.n;
   int64_t ln = 1;
   for (int j = 0; j < n; ++j) {
@@ -2903,7 +2898,9 @@ hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_o
   return guarded([&] {
     if (!sys || !desc || !out) fail(HGF_EINVAL, "NULL argument");
     if (desc->precision != HGF_FP64 && desc->precision != HGF_MIXED) fail(HGF_EINVAL, "unknown precision");
-    if (desc->layout != HGF_MERGED && desc->layout != HGF_SPLIT) fail(HGF_EINVAL, "unknown layout");
+    if (desc->layout != HGF_MERGED && desc->layout != HGF_SPLIT && desc->layout != HGF_SEPARATED &&
+        desc->layout != HGF_SEPARATED_EXACT)
+      fail(HGF_EINVAL, "unknown layout");
     if (desc->basis != HGF_BASIS_NUMBER && desc->basis != HGF_BASIS_NORMAL) fail(HGF_EINVAL, "unknown basis");
     if (!(desc->drop_tol >= 0)) fail(HGF_EINVAL, "drop_tol must be >= 0");
     hgf::precheck_operator_size(sys->sys, desc);
@@ -2914,7 +2911,10 @@ hgf_status hgf_map_operator(hgf_system sys, const hgf_operator_desc* desc, hgf_o
       op->layout = desc->layout;
       hip_check(hipGetDevice(&op->device), "hipGetDevice");
       op->dflag = (int*)dmalloc(sizeof(int));
-      build_functions(op, desc);
+      if (op->layout == HGF_SEPARATED || op->layout == HGF_SEPARATED_EXACT)
+        build_separated(op, desc);
+      else
+        build_functions(op, desc);
       hip_check(hipDeviceSynchronize(), "synchronize");
     } catch (...) {
       hgf_destroy_operator(op);
@@ -2928,6 +2928,7 @@ void hgf_destroy_operator(hgf_operator op) {
   if (!op) return;
   (void)hipSetDevice(op->device);
   drop_plan(op);
+  free_separated(op);
   for (auto& f : op->fn) free_function(f);
   if (op->dflag) dfree(*(void**)&op->dflag);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
@@ -3030,13 +3031,13 @@ hgf_status hgf_grad(hgf_system sys, const hgf_operator_desc* desc, const hgf_sta
 hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
   return guarded([&] {
     if (!op || !info) fail(HGF_EINVAL, "NULL argument");
-    info->n_functions = (int32_t)op->fn.size();
+    info->n_functions = op->sep ? separated_functions(op) : (int32_t)op->fn.size();
     info->precision = op->precision;
     info->layout = op->layout;
     info->n_modes = op->sys.n;
     int64_t pts = 0;
     for (auto& f : op->fn) pts += f.ga.points;
-    info->total_points = pts;
+    info->total_points = op->sep ? separated_points(op) : pts;
     info->steps_done = op->steps_done;
     info->time_us = op->time_us;
     info->fp32_underflow = op->underflow;

@@ -72,6 +72,21 @@ struct FullTables {
   double exch[kMaxFullModes][kMaxFullModes];
 };
 
+// Separated form (Eqs. (9a)-(9c)): sizes of the N-mode boxes of Gx, Gy (and
+// of R's rows and columns), and the number of monomials.
+struct SepDims {
+  int n;
+  int nmono;
+  int64_t dim;                       // prod_j Nc_j
+  int64_t stride[kMaxFullModes];     // row-major strides of the box (last mode fastest)
+};
+// One separated operator's launch arguments: dimensions and the device copy
+// of its generator tables.
+struct SepLaunch {
+  SepDims d;
+  const FullTables* ft;
+};
+
 // Coefficients of the generator restricted to one occupation-difference
 // sector d (Eq. (17) with the dissipators of Eq. (3); derivation in the
 // sector form): for grid point m,
@@ -277,6 +292,7 @@ struct Function {
 };
 
 struct StepPlan;
+struct SepState;
 
 }  // namespace hgf
 
@@ -301,4 +317,6 @@ struct hgf_operator_s {
   int graph_steps = 0;
   double graph_dt = 0.0;
   hipStream_t cap_stream = nullptr;
+  // separated layout (Eqs. (9a)-(9c)): the monomials' Gx, Gy grids and R
+  hgf::SepState* sep = nullptr;
 };

@@ -106,6 +106,22 @@ void launch_gather_levels(const GridArgs& g, const void* y, bool real, const Gat
 // device-to-device copy as a kernel (safe to record in a captured graph)
 void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st);
 void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st);
+// Separated form (Eqs. (9a)-(9c)), classical RK4 stage by stage: every
+// monomial's Gx and Gy (with +-C), the source P(sum_i c_i Gx_i Gy_i) of R
+// (rmode 1: its diagonal products; 0: the whole outer-product sum), and R
+// (rmode 1: on the diagonal k = l; 0: on the whole box); readout.
+void launch_sep_sides(const SepLaunch& L, int stage, double h, const double2* cst, double2* u, double2* acc,
+                      const double2* yin, double2* yout, int* flag, hipStream_t st);
+void launch_sep_source(const SepLaunch& L, int rmode, const double2* coef, const double2* x, double2* s,
+                       hipStream_t st);
+void launch_sep_r(const SepLaunch& L, int rmode, int stage, double h, const double2* src, double2* u,
+                  double2* acc, const double2* yin, double2* yout, int* flag, hipStream_t st);
+int sep_expect_parts(const SepDims& d);
+void launch_sep_expect(const SepLaunch& L, int rmode, const double2* wt, const double2* coef, const double2* x,
+                       const double2* r, double2* part, double2* out, hipStream_t st);
+void launch_sep_ones(int64_t n, const int64_t* idx, double2* x, hipStream_t st);
+void launch_sep_gather(const SepLaunch& L, int rmode, int levels, int64_t ln, const double* fac, const double2* coef,
+                       const double2* x, const double2* r, double2* out, hipStream_t st);
 // Device address of the current device's copy of the static scratch
 // (kScratchBytes), looked up once per device.
 void* scratch_address();

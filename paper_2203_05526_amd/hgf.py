@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgf.so")
 
 HGF_FP64, HGF_MIXED = 0, 1
-HGF_MERGED, HGF_SPLIT = 0, 1
+HGF_MERGED, HGF_SPLIT, HGF_SEPARATED, HGF_SEPARATED_EXACT = 0, 1, 2, 3
 HGF_OP_PRODUCT, HGF_OP_SPARSE, HGF_OP_DENSE = 0, 1, 2
 HGF_BASIS_NUMBER, HGF_BASIS_NORMAL = 0, 1
 HGF_PSI_FOCK, HGF_PSI_COHERENT, HGF_PSI_PRODUCT = 0, 1, 2
@@ -232,7 +232,7 @@ def define_system(system) -> System:
 # ------------------------------------------------------------------ operators
 
 _PREC = {"fp64": HGF_FP64, "mixed": HGF_MIXED}
-_LAYOUT = {"merged": HGF_MERGED, "split": HGF_SPLIT}
+_LAYOUT = {"merged": HGF_MERGED, "split": HGF_SPLIT, "separated": HGF_SEPARATED, "separated_exact": HGF_SEPARATED_EXACT}
 _BASIS = {"number": HGF_BASIS_NUMBER, "normal": HGF_BASIS_NORMAL}
 
 
