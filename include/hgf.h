@@ -301,9 +301,27 @@ typedef struct {
   int64_t fp32_underflow; /* MIXED: nonzero initial coefficients below FP32's normal range */
   int32_t error_state;    /* nonzero after HGF_ENONFINITE */
   int32_t real_functions; /* functions held as real grids (real generator and data) */
+  int64_t stored_peak;    /* with a threshold set (hgf_set_threshold): the largest number of
+                             coefficients kept after any step since it was set; else -1 */
 } hgf_operator_info;
 
 hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
+
+/*
+ * Thresholded representation of the operator (the paper's truncation of the
+ * stored representation, tuned in its network example to a fixed operator
+ * error): after every RK4 step of hgf_evolve, every stored generating-function
+ * coefficient g with |g| <= threshold is set to zero, and the number of
+ * coefficients kept is counted; hgf_get_info's stored_peak reports the
+ * largest count since the threshold was set (the stored elements a sparse
+ * store of the representation would hold at its peak).  The grids stay dense
+ * in memory.  threshold = 0 turns it off.  For FP64 network operators on the
+ * full (k, l) grid and for the separated layouts (every Gx, Gy grid and R);
+ * other operators return HGF_EUNSUPPORTED.  Steps run one launch sequence at
+ * a time (no graph) while a threshold is set.  Errors: HGF_EINVAL (negative
+ * or non-finite threshold), HGF_EUNSUPPORTED, HGF_EDEVICE.
+ */
+hgf_status hgf_set_threshold(hgf_operator op, double threshold);
 
 /*
  * Copy function `idx` to the host for inspection: sector_d [N] gets d = q - p

@@ -167,13 +167,15 @@ def monomials(system, A: np.ndarray, drop_tol: float = 0.0):
     return out
 
 
-def evolve_separated(system, monos, t_total: float, dt: float, rmode: str = "full", nthreads: int = 0):
+def evolve_separated(system, monos, t_total: float, dt: float, rmode: str = "full", nthreads: int = 0,
+                     state=None):
     """The separated form G = Gx Gy + R of Eqs. (9a)-(9c) for every monomial
     (p, q, c) of `monos` (Gx(0) = x^p, Gy(0) = y^q, R(0) = 0), classical RK4
     on the joint state.  Returns (gx [nmono, *cutoff], gy [nmono, *cutoff],
     r): r is the sum over the monomials of c R, on the full (k, l) box
     ([dim, dim], rmode "full") or on its diagonal k = l ([*cutoff], rmode "z",
-    the approximation by a function of x_j y_j)."""
+    the approximation by a function of x_j y_j).  `state` = (gx, gy, r) as
+    returned continues from that state instead of the initial monomials."""
     lib = _load()
     cutoff = tuple(system.cutoff)
     n = len(cutoff)
@@ -189,6 +191,10 @@ def evolve_separated(system, monos, t_total: float, dt: float, rmode: str = "ful
         gy[i, np.ravel_multi_index(Q[i], cutoff)] = 1.0
     rm = {"full": 0, "z": 1}[rmode]
     r = np.zeros((dim, dim) if rm == 0 else (dim,), dtype=np.complex128)
+    if state is not None:
+        gx = np.array(state[0], dtype=np.complex128).reshape(nm, dim)
+        gy = np.array(state[1], dtype=np.complex128).reshape(nm, dim)
+        r = np.array(state[2], dtype=np.complex128).reshape(r.shape)
     args, keep = _sysargs(system)
     rc = lib.oracle_evolve_separated(*args, *_network_args(system, keep), nm,
                                      P.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),

@@ -17,6 +17,7 @@ from .hgf import (  # noqa: F401
     expectation,
     expectation_noalloc,
     reconstruct,
+    set_threshold,
     grad,
     load_library,
     map_operator,

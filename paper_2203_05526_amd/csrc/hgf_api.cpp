@@ -1750,6 +1750,13 @@ int read_flag(hgf_operator_s* op, hipStream_t st) {
   return flag;
 }
 
+// Thresholded representation: drop every coefficient with |g| <= threshold
+// from the operator's full-grid functions and update the peak count.
+static void apply_threshold(hgf_operator_s* op, hipStream_t st) {
+  for (auto& f : op->fn) launch_threshold((double2*)f.y, f.ga.points, op->threshold, op->dcount, st);
+  launch_threshold_peak(op->dcount, op->dcount + 1, st);
+}
+
 static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, int scheme = HGF_RK4) {
   if (scheme == HGF_LAWSON_RK4 && op->layout != HGF_MERGED)
     fail(HGF_EUNSUPPORTED, "the integrating-factor scheme runs on merged-layout operators only");
@@ -1782,6 +1789,13 @@ static void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t
   reset_flag(op, st);
   if (scheme == HGF_LAWSON_RK4) {
     lawson_steps(op, steps, h, st);
+  } else if (op->layout == HGF_MERGED && op->threshold > 0.0) {
+    // one step at a time, the representation truncated after each
+    ensure_plan(op, h);
+    for (int64_t k = 0; k < steps; ++k) {
+      run_plan_step(*op->plan, op->dflag, st);
+      apply_threshold(op, st);
+    }
   } else if (op->layout == HGF_MERGED) {
     ensure_plan(op, h);
     run_resident(*op->plan, steps, op->dflag, st);
@@ -2929,6 +2943,7 @@ void hgf_destroy_operator(hgf_operator op) {
   (void)hipSetDevice(op->device);
   drop_plan(op);
   free_separated(op);
+  if (op->dcount) dfree(*(void**)&op->dcount);
   for (auto& f : op->fn) free_function(f);
   if (op->dflag) dfree(*(void**)&op->dflag);
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
@@ -2943,6 +2958,22 @@ hgf_status hgf_set_allocator(hgf_alloc_fn alloc, hgf_free_fn free_fn, void* user
     g_hook.free = free_fn;
     g_hook.user = user;
     g_hook.generation = alloc ? ++g_hook_generation : 0;
+  });
+}
+
+hgf_status hgf_set_threshold(hgf_operator op, double threshold) {
+  return guarded([&] {
+    if (!op) fail(HGF_EINVAL, "operator is NULL");
+    if (!std::isfinite(threshold) || threshold < 0.0) fail(HGF_EINVAL, "threshold must be finite and >= 0");
+    bool ok = op->precision == HGF_FP64 && (op->sep != nullptr || !op->fn.empty());
+    for (auto& f : op->fn) ok = ok && f.full;
+    if (!ok)
+      fail(HGF_EUNSUPPORTED, "thresholded storage applies to FP64 network operators on the full grid and to the "
+                             "separated layouts");
+    hip_check(hipSetDevice(op->device), "hipSetDevice");
+    if (!op->dcount) op->dcount = (unsigned long long*)dmalloc(2 * sizeof(unsigned long long));
+    hip_check(hipMemset(op->dcount, 0, 2 * sizeof(unsigned long long)), "clear counters");
+    op->threshold = threshold;
   });
 }
 
@@ -3045,6 +3076,13 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
     int nreal = 0;
     for (auto& f : op->fn) nreal += f.real ? 1 : 0;
     info->real_functions = nreal;
+    info->stored_peak = -1;
+    if (op->threshold > 0.0 && op->dcount) {
+      unsigned long long peak = 0;
+      hip_check(hipSetDevice(op->device), "hipSetDevice");
+      hip_check(hipMemcpy(&peak, op->dcount + 1, sizeof(peak), hipMemcpyDeviceToHost), "download");
+      info->stored_peak = (int64_t)peak;
+    }
   });
 }
 

@@ -319,4 +319,9 @@ struct hgf_operator_s {
   hipStream_t cap_stream = nullptr;
   // separated layout (Eqs. (9a)-(9c)): the monomials' Gx, Gy grids and R
   hgf::SepState* sep = nullptr;
+  // thresholded representation (hgf_set_threshold): coefficients with
+  // |g| <= threshold are dropped after every step; device counters of the
+  // survivors (count of the last step, peak since the threshold was set)
+  double threshold = 0.0;
+  unsigned long long* dcount = nullptr;  // [2]: count, peak
 };

@@ -122,6 +122,10 @@ void launch_sep_expect(const SepLaunch& L, int rmode, const double2* wt, const d
 void launch_sep_ones(int64_t n, const int64_t* idx, double2* x, hipStream_t st);
 void launch_sep_gather(const SepLaunch& L, int rmode, int levels, int64_t ln, const double* fac, const double2* coef,
                        const double2* x, const double2* r, double2* out, hipStream_t st);
+// Thresholded representation: zero every coefficient with |g| <= thr and add
+// the survivors to *count; then peak = max(peak, count) and count = 0.
+void launch_threshold(double2* g, int64_t n, double thr, unsigned long long* count, hipStream_t st);
+void launch_threshold_peak(unsigned long long* count, unsigned long long* peak, hipStream_t st);
 // Device address of the current device's copy of the static scratch
 // (kScratchBytes), looked up once per device.
 void* scratch_address();

@@ -510,6 +510,41 @@ static void full_launch_n(int stage, int precision, const GridArgs& g, const Str
                        (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
 }
 
+// ------------------------------------------------------------ thresholded representation
+// Coefficients with |g| <= thr are set to zero (the truncated representation
+// of the operator); the survivors are counted into *count.
+__global__ __launch_bounds__(256) void k_threshold(double2* __restrict__ g, int64_t n, double thr,
+                                                   unsigned long long* __restrict__ count) {
+  const double t2 = thr * thr;
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = g[i];
+    if (v.x * v.x + v.y * v.y <= t2) {
+      if (v.x != 0.0 || v.y != 0.0) g[i] = make_double2(0.0, 0.0);
+    } else {
+      ++c;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+// peak = max(peak, count); count = 0 (one thread)
+__global__ void k_threshold_peak(unsigned long long* __restrict__ count, unsigned long long* __restrict__ peak) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (*count > *peak) *peak = *count;
+    *count = 0;
+  }
+}
+
+void launch_threshold(double2* g, int64_t n, double thr, unsigned long long* count, hipStream_t st) {
+  if (n <= 0) return;
+  const int b = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_threshold, dim3(b), dim3(256), 0, st, g, n, thr, count);
+}
+void launch_threshold_peak(unsigned long long* count, unsigned long long* peak, hipStream_t st) {
+  hipLaunchKernelGGL(k_threshold_peak, dim3(1), dim3(64), 0, st, count, peak);
+}
+
 // ------------------------------------------------------------ stage-precision copy
 // The tiled RK4 stage kernel lives in hgf_tiled.h, the resident integrator in
 // hgf_resident.h.  yf = y in the stage precision (the stage-1 stencil input of

@@ -170,6 +170,11 @@ void separated_evolve(hgf_operator_s* op, int64_t steps, double h, hipStream_t s
       if (d.nmono > 0)
         launch_sep_sides(st->L, s, h, (const double2*)st->dcst, X[0], X[1], X[in_of[s]], X[out_of[s]], op->dflag,
                          strm);
+      if (s == 4 && op->threshold > 0.0) {  // thresholded representation of every grid
+        launch_threshold(X[0], 2 * (int64_t)d.nmono * d.dim, op->threshold, op->dcount, strm);
+        launch_threshold(R[0], st->rlen, op->threshold, op->dcount, strm);
+        launch_threshold_peak(op->dcount, op->dcount + 1, strm);
+      }
     }
   hip_check(hipGetLastError(), "kernel launch");
   if (read_flag(op, strm)) {

@@ -27,7 +27,7 @@ STATUS = {0: "HGF_OK", -1: "HGF_EINVAL", -2: "HGF_ENOMEM", -3: "HGF_EDEVICE", -4
 
 EXPORTED = ["hgf_define_system", "hgf_destroy_system", "hgf_num_params", "hgf_map_operator",
             "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_expectation_noalloc",
-            "hgf_reconstruct", "hgf_grad",
+            "hgf_reconstruct", "hgf_grad", "hgf_set_threshold",
             "hgf_get_info", "hgf_get_function", "hgf_last_error", "hgf_version"]
 
 
@@ -69,7 +69,8 @@ class _Info(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("n_modes", ctypes.c_int32),
                 ("total_points", ctypes.c_int64), ("steps_done", ctypes.c_int64),
                 ("time_us", ctypes.c_double), ("fp32_underflow", ctypes.c_int64),
-                ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32)]
+                ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32),
+                ("stored_peak", ctypes.c_int64)]
 
 
 class _TileConfig(ctypes.Structure):
@@ -116,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.hgf_grad.argtypes = [vp, ctypes.POINTER(_OperatorDesc), ctypes.POINTER(_StateDesc),
                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, _f64p, _f64p, vp]
     lib.hgf_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.hgf_set_threshold.argtypes = [vp, ctypes.c_double]
     lib.hgf_get_function.argtypes = [vp, ctypes.c_int32, _i32p, _i32p, _f64p, ctypes.c_int64, _f64p, vp]
     lib.hgf_get_tile_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(_TileConfig)]
     lib.hgf_set_tile_config.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(_TileConfig)]
@@ -338,6 +340,13 @@ SCHEMES = {"rk4": 0, "lawson": 1}  # HGF_RK4, HGF_LAWSON_RK4
 def evolve(op: Operator, t_total: float, dt: float, stream=None, scheme: str = "rk4") -> None:
     """hgf_evolve with scheme "rk4" (classical RK4) or "lawson" (integrating-factor RK4)."""
     _check(_lib.hgf_evolve(op.handle, float(t_total), float(dt), SCHEMES[scheme], _stream(stream)))
+
+
+def set_threshold(op: Operator, threshold: float) -> None:
+    """hgf_set_threshold: after every step, drop the coefficients with |g| <=
+    threshold (0 turns it off); op.info()["stored_peak"] reports the largest
+    number kept since."""
+    _check(_lib.hgf_set_threshold(op.handle, float(threshold)))
 
 
 def clear_error(op: Operator) -> None:
