@@ -317,6 +317,84 @@ def network_timing(hgf, torch, five_only: bool = False):
             "runs": runs, "five_modes": five}
 
 
+def network_storage(hgf, torch, max_modes: int = 4):
+    """The paper's memory comparison on the network example (Table I chain,
+    operator prod_j a_j, w_q t / pi = 10 in 100 RK4 steps, cutoff 6, FP64):
+    the conventional representation (one grid over all (k, l)) against the
+    separated form G = Gx Gy + R of Eqs. (9a)-(9c) with R approximated on the
+    diagonal k = l (the paper's approximation by a function of x_j y_j), both
+    with the thresholded representation (coefficients with |g| <= threshold
+    dropped after every step).  Per mode count and method: the operator error
+    on the three lowest levels against the paper's reference recipe (the
+    conventional method at cutoff 7 and half the step, untruncated), without
+    truncation and at the largest threshold (from a geometric sweep) whose
+    error stays within the common target max(100 ppm, 1.25 x the larger
+    untruncated error); the peak number of coefficients kept (the stored
+    elements of a sparse store) and the dense grid points; the wall time.
+    The separated form with R on the whole box (exact) is also run untruncated
+    up to three modes."""
+    import synth
+
+    def run(w, layout, thr):
+        op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="fp64", layout=layout)
+        if thr > 0:
+            hgf.set_threshold(op, thr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hgf.evolve(op, w.t_total, w.dt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        info = op.info()
+        return op, el, info
+
+    out = []
+    for n in range(1, max_modes + 1):
+        w = synth.table1_network(n, 6)
+        wr = synth.table1_network(n, 7)
+        ref_op = hgf.map_operator(hgf.define_system(wr.system), factors=wr.factors, precision="fp64")
+        hgf.evolve(ref_op, wr.t_total, wr.dt / 2)
+        Mr = hgf.reconstruct(ref_op, 3)
+        del ref_op
+
+        def eps(op):
+            M = hgf.reconstruct(op, 3)
+            return float(np.linalg.norm(M - Mr) / np.linalg.norm(Mr))
+
+        rec = {"modes": n, "cutoff": 6}
+        base = {}
+        for name, layout in (("conventional", "merged"), ("separated", "separated")):
+            op, el, info = run(w, layout, 0.0)
+            base[name] = {"eps_r_untruncated": eps(op), "dense_points": info["total_points"], "seconds": el,
+                          "functions": info["n_functions"]}
+            del op
+        if n <= 3:
+            op, el, info = run(w, "separated_exact", 0.0)
+            rec["separated_exact"] = {"eps_r_untruncated": eps(op), "dense_points": info["total_points"],
+                                      "seconds": el}
+            del op
+        target = max(1e-4, 1.25 * max(base["conventional"]["eps_r_untruncated"],
+                                      base["separated"]["eps_r_untruncated"]))
+        rec["eps_r_target"] = target
+        for name, layout in (("conventional", "merged"), ("separated", "separated")):
+            best = None
+            for k in range(0, 25):
+                thr = 10.0 ** (-1.0 - 0.5 * k)
+                op, el, info = run(w, layout, thr)
+                e = eps(op)
+                del op
+                if e <= target:
+                    best = {"threshold": thr, "eps_r": e, "stored_peak": info["stored_peak"], "seconds": el}
+                    break
+            base[name]["truncated"] = best
+            rec[name] = base[name]
+        out.append(rec)
+        log(f"network storage {n} modes: conventional {rec['conventional']['truncated']}, "
+            f"separated {rec['separated']['truncated']}")
+    return {"workload": "Table I network (chain, drive on mode 1), operator prod_j a_j, cutoff 6, "
+                        "T = 1/700 us in 100 RK4 steps, FP64; reference: conventional at cutoff 7, half step",
+            "runs": out}
+
+
 def gradient_timing(hgf, torch, t_total: float):
     """hgf_grad on the 4-mode, cutoff-16 workload (bitstring projector,
     coherent state, 22 parameters, checkpoints every 100 steps)."""
@@ -354,7 +432,7 @@ def main():
                     help="skip the full-horizon runs of the 10-mode workload (4e4 steps, mixed and FP64)")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
-    ap.add_argument("--only", choices=["network", "network5", "gradient"], default=None,
+    ap.add_argument("--only", choices=["network", "network5", "gradient", "storage"], default=None,
                     help="run one section alone and print its JSON (for profiling it): network = the Table I "
                          "network for 1 to 5 modes, network5 = its five-mode runs alone, gradient = the gradient "
                          "workload over 0.5 us (5,000 steps)")
@@ -381,6 +459,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 elementwise passes reading and writing 1 GiB")
         del a, b
+    if args.only == "storage":
+        print(json.dumps({"network_storage": network_storage(hgf, torch)}))
+        return
     if args.only in ("network", "network5"):
         print(json.dumps({"network": network_timing(hgf, torch, five_only=args.only == "network5")}))
         return
@@ -467,6 +548,8 @@ def main():
         line["gradient"] = gradient_timing(hgf, torch, 5.0)
         log("network")
         line["network"] = network_timing(hgf, torch)
+        log("network storage (thresholded, conventional vs separated)")
+        line["network"]["storage"] = network_storage(hgf, torch)
     if not args.no_cpu_baseline:
         log("cpu oracle baseline")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
