@@ -192,13 +192,17 @@ def stiff_time_to_tolerance(hgf, torch):
     return out
 
 
-def batch_throughput(hgf, torch, seq_steps: int):
+def batch_throughput(hgf, torch, seq_steps: int, steps=None, tune_cache=None):
     """One grouped, graph-captured hgf_evolve_batch over the batch workload:
     64 systems of 6 modes at cutoff 8 plus 32 systems of 2-5 modes with
     cutoffs 6-20 (seeded), mixed precision, dt = 0.1 ns, over the full horizon
     T = 1 us (1e4 steps), with every member's expectation value against the
     stored FP64 oracle value; the same members evolved one call at a time
-    over `seq_steps` steps for comparison."""
+    over `seq_steps` steps for comparison.  With `steps` set, only that many
+    steps are run (for profiling) and no error is reported.  The roofline
+    entry is the whole batch's algorithmic bytes (every member's bytes per
+    point-stage, as for the single grid, times its points, times 4 stages per
+    step) over the evolve time from HIP events on the launching stream."""
     import synth
     ws = synth.batch_c2()
     ops = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
@@ -206,13 +210,14 @@ def batch_throughput(hgf, torch, seq_steps: int):
     dt = ws[0].dt
     import tempfile
     tmp = tempfile.TemporaryDirectory()
-    batch_cache = os.path.join(tmp.name, "batch.txt")
+    batch_cache = tune_cache or os.path.join(tmp.name, "batch.txt")
     t0 = time.perf_counter()
     hgf.autotune(ops, dt, cache=batch_cache)  # grid shapes, and the grouped launches of the batch as a whole
     tune_s = time.perf_counter() - t0
     # sequential reference: the same members evolved one hgf_evolve call at a
     # time, each with the launch shape tuned for its grid alone
-    ops2 = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
+    ops2 = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed")
+            for w in (ws if seq_steps else [])]
     for op in ops2:
         hgf.autotune([op], dt, cache=os.path.join(tmp.name, "shapes.txt"))
     # warm-up (plan, graph) on fresh copies, so that the timed run starts at t = 0
@@ -221,16 +226,31 @@ def batch_throughput(hgf, torch, seq_steps: int):
     del warm
     ops = [hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed") for w in ws]
     hgf.autotune(ops, dt, cache=batch_cache)  # applies the shapes found above without measuring
-    steps = ws[0].n_steps
+    full = steps is None
+    if full:
+        steps = ws[0].n_steps
+    step_bytes = 0.0
+    for op in ops:
+        info = op.info()
+        if info["real_functions"] not in (0, info["n_functions"]):
+            raise RuntimeError("batch member with both real and complex grids")
+        step_bytes += 4 * bytes_per_point_stage("mixed", info["real_functions"] > 0) * info["total_points"]
     hgf.evolve_batch(ops, [0.0] * len(ops), [dt] * len(ops))
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    hgf.evolve_batch(ops, [w.t_total for w in ws], [w.dt for w in ws])
+    ev0.record()
+    hgf.evolve_batch(ops, [w.t_total if full else steps * w.dt for w in ws], [w.dt for w in ws])
+    ev1.record()
     Js = [hgf.expectation(op, w.states[0]) for op, w in zip(ops, ws)]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    refs = [complex(*m["value"]) for m in golden("workloads")["batch"]]
-    errs = [abs(J - r) / abs(r) for J, r in zip(Js, refs)]
+    ev_s = ev0.elapsed_time(ev1) * 1e-3
+    achieved = step_bytes * steps / ev_s / 1e9
+    errs = None
+    if full:
+        refs = [complex(*m["value"]) for m in golden("workloads")["batch"]]
+        errs = [abs(J - r) / abs(r) for J, r in zip(Js, refs)]
     for op in ops2:
         hgf.evolve(op, 2 * dt, dt)
     torch.cuda.synchronize()
@@ -238,14 +258,19 @@ def batch_throughput(hgf, torch, seq_steps: int):
     for op in ops2:
         hgf.evolve(op, seq_steps * dt, dt)
     torch.cuda.synchronize()
-    el_seq = time.perf_counter() - t1
+    el_seq = time.perf_counter() - t1 if seq_steps else None
     tmp.cleanup()
     return {"workload": "96 systems: 64 x (6 modes, cutoff 8) + 32 x (2-5 modes, cutoffs 6-20), mixed, "
                         "T = 1 us, dt = 0.1 ns",
             "members": len(ops), "grid_points": pts, "steps": steps,
             "value": pts * 4 * steps / el, "unit": "point-stage updates/s", "seconds": el,
-            "rel_err_vs_oracle": max(errs), "within_1e-5": max(errs) <= 1e-5,
-            "sequential": {"steps": seq_steps, "seconds": el_seq, "value": pts * 4 * seq_steps / el_seq},
+            "rel_err_vs_oracle": None if errs is None else max(errs),
+            "within_1e-5": None if errs is None else max(errs) <= 1e-5,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_step": step_bytes,
+                         "evolve_seconds_events": ev_s},
+            "sequential": None if not seq_steps else
+            {"steps": seq_steps, "seconds": el_seq, "value": pts * 4 * seq_steps / el_seq},
             "autotune_seconds": tune_s}
 
 
@@ -432,10 +457,11 @@ def main():
                     help="skip the full-horizon runs of the 10-mode workload (4e4 steps, mixed and FP64)")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
-    ap.add_argument("--only", choices=["network", "network5", "gradient", "storage"], default=None,
+    ap.add_argument("--only", choices=["network", "network5", "gradient", "storage", "batch"], default=None,
                     help="run one section alone and print its JSON (for profiling it): network = the Table I "
                          "network for 1 to 5 modes, network5 = its five-mode runs alone, gradient = the gradient "
-                         "workload over 0.5 us (5,000 steps)")
+                         "workload over 0.5 us (5,000 steps), storage = the conventional and separated "
+                         "network forms with thresholds, batch = the batch workload over --steps steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -459,6 +485,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 elementwise passes reading and writing 1 GiB")
         del a, b
+    if args.only == "batch":
+        print(json.dumps({"batch": batch_throughput(hgf, torch, 0, steps=args.steps, tune_cache=args.tune_cache)}))
+        return
     if args.only == "storage":
         print(json.dumps({"network_storage": network_storage(hgf, torch)}))
         return
