@@ -303,6 +303,11 @@ typedef struct {
   int32_t real_functions; /* functions held as real grids (real generator and data) */
   int64_t stored_peak;    /* with a threshold set (hgf_set_threshold): the largest number of
                              coefficients kept after any step since it was set; else -1 */
+  int32_t untiled_functions; /* merged and network layouts: functions whose RK4 stages run on the
+                                untiled grid-stride kernel because the tiled one does not take
+                                them (a tile beyond LDS, more than 12 slow axes, a buffer over
+                                2^32 bytes, or HGF_STAGE_KERNEL=generic); several times slower */
+  int32_t reserved;
 } hgf_operator_info;
 
 hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);

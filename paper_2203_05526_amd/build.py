@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libhgf.so")
 ARCH = os.environ.get("HGF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["hgf_kernels.hip", "hgf_full_tiled.hip", "hgf_tiled_c64.hip", "hgf_tiled_c128.hip", "hgf_tiled_r32.hip",
-           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_separated.hip", "hgf_api.cpp", "hgf_separated_host.cpp",
+           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_separated.hip", "hgf_api.cpp", "hgf_functions.cpp",
+           "hgf_step.cpp", "hgf_autotune.cpp", "hgf_readout.cpp", "hgf_grad.cpp", "hgf_separated_host.cpp",
            "hgf_tables.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"]
@@ -48,7 +49,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -1,0 +1,263 @@
+// Discrete-adjoint gradient of J = <psi0|A(T)|psi0> with respect to the
+// system parameters (the transposed stencil on the forward stage kernels).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "hgf.h"
+#include "hgf_internal.h"
+#include "hgf_host.h"
+#include "hgf_kernels.h"
+#include "hgf_runtime.h"
+
+namespace hgf {
+
+// ------------------------------------------------------------------ gradient
+
+// L^T of a sector's generator as tables of the same stencil form:
+// (L^T mu)(m) = lam(m) mu(m) + sum_j [alpha_j(m_j + 1) mu(m + e_j) + beta_j(m_j - 1) mu(m - e_j)],
+// i.e. alpha'_j(m) = beta_j(m - 1) (0 at m = 0) and beta'_j(m) = alpha_j(m + 1)
+// (0 at the top of the axis): transpose only, no conjugation.
+SectorTables transposed_tables(const SectorTables& t) {
+  SectorTables r = t;
+  for (int j = 0; j < t.n; ++j) {
+    const int e = t.ext[j];
+    for (int m = 0; m < e; ++m) {
+      r.alpha[j][m] = m >= 1 ? t.beta[j][m - 1] : 0.0;
+      r.beta[j][m] = m + 1 < e ? t.alpha[j][m + 1] : 0.0;
+    }
+  }
+  return r;
+}
+
+// Longest reverse segment captured as one graph (about 10 nodes per step).
+constexpr int64_t kGradGraphSteps = 512;
+// A segment keeps every step's stage grids X1, V1, V2 next to its state when
+// they fit in this many bytes (the reverse sweep then recomputes nothing);
+// otherwise, or with HGF_GRAD_STORE=0 in the environment, it keeps the states
+// only and recomputes the three stages of each step in the sweep (the same
+// numbers either way).
+constexpr int64_t kGradStoreBytes = (int64_t)2 << 30;
+
+void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
+                      double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
+  const int64_t M = check_steps(T, dt);
+  if (ce < 1) fail(HGF_EINVAL, "checkpoint_every must be >= 1");
+  if (sys.full) fail(HGF_EUNSUPPORTED, "gradients need uncoupled sectors (no drive or exchange)");
+  validate_state(sys, psi);
+  hgf_operator_s op;
+  op.sys = sys;
+  op.precision = HGF_FP64;
+  op.layout = HGF_MERGED;
+  hip_check(hipGetDevice(&op.device), "hipGetDevice");
+  hgf_operator_desc d2 = *desc;
+  d2.layout = HGF_MERGED;
+  d2.precision = HGF_FP64;
+  struct OpGuard {
+    hgf_operator_s& o;
+    ~OpGuard() {
+      for (auto& f : o.fn) free_function(f);
+      if (o.dflag) dfree(*(void**)&o.dflag);
+    }
+  } guard{op};
+  op.dflag = (int*)dmalloc(sizeof(int));
+  hipStream_t cap = nullptr;
+  hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() {
+      if (s) (void)hipStreamDestroy(s);
+    }
+  } sg{cap};
+  build_functions(&op, &d2, false);
+  check_stability(op.fn, dt);
+  const auto amps = all_amps(sys, psi);
+  const int P = num_params(sys.n);
+  std::vector<cd> grad(P, 0.0);
+  cd value = 0.0;
+  reset_flag(&op, st);
+  for (auto& f : op.fn) {
+    const int64_t pts = f.ga.points;
+    const size_t gb = pts * sizeof(double2);
+    const int64_t nseg = (M + ce - 1) / ce;
+    const int64_t seg_steps = std::min<int64_t>(ce, std::max<int64_t>(M, 1));
+    const char* store_env = std::getenv("HGF_GRAD_STORE");  // "0": keep states only
+    const bool store = 4 * seg_steps * (int64_t)gb <= kGradStoreBytes && !(store_env && std::string(store_env) == "0");
+    const int64_t per_step = store ? 4 : 1;  // grids kept per step: y (and X1, V1, V2)
+    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)(seg_steps * per_step) * gb), mu(gb), vb2(gb), vb1(gb),
+        xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
+    // the adjoint stencils run on the forward stage kernels of L^T
+    Function fa;
+    struct FreeOnExit {
+      Function& f;
+      ~FreeOnExit() { free_function(f); }
+    } fa_guard{fa};
+    fa.tab = transposed_tables(f.tab);
+    fill_grid_args(fa, HGF_FP64, false);
+    DBuf zero(gb);
+    launch_fill_zero(zero.as<double2>(), pts, st);
+    const auto w = sector_weights(sys, f, amps);
+    DBuf dw(w.size() * sizeof(double2));
+    hip_check(hipMemcpyAsync(dw.p, w.data(), w.size() * sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+    launch_fill_weights(f.ga, dw.as<double2>(), wt.as<double2>(), st);
+    // forward with checkpoints (f.y is the working state)
+    double2* ck = ckpt.as<double2>();
+    hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+    DBuf y0(gb);
+    hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
+    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, false));
+    // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
+    {
+      const int64_t full = M / ce;
+      if (full > 0) {
+        const int chunk = (int)std::min<int64_t>(ce, 64);
+        GraphHolder g(capture_steps(*fplan, op.dflag, chunk, cap));
+        for (int64_t c = 1; c <= full; ++c) {
+          int64_t done = 0;
+          for (; done + chunk <= ce; done += chunk) hip_check(hipGraphLaunch(g.e, st), "graph launch");
+          for (; done < ce; ++done) run_plan_step(*fplan, op.dflag, st);
+          hip_check(hipMemcpyAsync(ck + c * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+        }
+        hip_check(hipStreamSynchronize(st), "synchronize");
+      }
+      for (int64_t s = full * ce; s < M; ++s) run_plan_step(*fplan, op.dflag, st);
+    }
+    // value
+    {
+      std::vector<int> start = {0, expect_blocks(f.ga)};
+      cd one = 1.0;
+      DBuf dpart(start[1] * sizeof(double2)), dstart(2 * sizeof(int)), dcoef(sizeof(double2)), dout(sizeof(double2));
+      hip_check(hipMemcpyAsync(dstart.p, start.data(), 2 * sizeof(int), hipMemcpyHostToDevice, st), "upload");
+      hip_check(hipMemcpyAsync(dcoef.p, &one, sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+      launch_expect_partial(f.ga, f.y, true, dw.as<double2>(), dpart.as<double2>(), st);
+      launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), 1, make_double2(0, 0),
+                          dout.as<double2>(), st);
+      double2 r;
+      hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+      hip_check(hipStreamSynchronize(st), "synchronize");
+      value += cd(r.x, r.y);
+    }
+    // reverse sweep: mu_M = w
+    hip_check(hipMemcpyAsync(mu.p, wt.p, gb, hipMemcpyDeviceToDevice, st), "seed");
+    launch_fill_zero(Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
+    double2* seg = segbuf.as<double2>();
+    double2* Qp = Q.as<double2>();
+    // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
+    // f.y into the segment buffer (with each step's X1, V1, V2 when `store`),
+    // then sweep them in reverse.  The work of a segment depends only on L, so
+    // it is captured once per length.  The stage launches are those of the
+    // forward pass (same kernel, shape and operands), so the recomputed states
+    // equal the checkpointed trajectory bit for bit.
+    auto slot = [&](int64_t i, int k) { return seg + (i * per_step + k) * pts; };  // k: y, X1, V1, V2
+    auto segment = [&](int64_t L, hipStream_t s) {
+      for (int64_t i = 0; i < L; ++i) {
+        launch_copy2(slot(i, 0), (const double2*)f.y, pts, s);
+        if (!store) {
+          if (i + 1 < L) run_plan_step(*fplan, op.dflag, s);
+          continue;
+        }
+        stage_launch(f, HGF_FP64, 1, slot(i, 0), nullptr, slot(i, 0), nullptr, slot(i, 1), dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 2, slot(i, 1), slot(i, 1), slot(i, 0), nullptr, slot(i, 2), dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 3, slot(i, 2), slot(i, 1), slot(i, 0), nullptr, slot(i, 3), dt, op.dflag, s);
+        if (i + 1 < L)
+          stage_launch(f, HGF_FP64, 4, slot(i, 3), slot(i, 1), f.y, nullptr, nullptr, dt, op.dflag, s);
+      }
+      for (int64_t i = L - 1; i >= 0; --i) {
+        double2* yn = slot(i, 0);
+        const double2 *x1 = (const double2*)f.s1, *v1 = (const double2*)f.s2, *v2 = (const double2*)f.s3;
+        if (store) {
+          x1 = slot(i, 1);
+          v1 = slot(i, 2);
+          v2 = slot(i, 3);
+        } else {  // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
+          stage_launch(f, HGF_FP64, 1, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, s);
+          stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
+          stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
+        }
+        double2 *pm = mu.as<double2>(), *pv2 = vb2.as<double2>(), *pv1 = vb1.as<double2>(), *px = xb1.as<double2>();
+        // stage-1 form (out = h' L^T in): B1, B2 and B3's stencil part
+        stage_launch(fa, HGF_FP64, 1, pm, nullptr, pm, nullptr, pv2, 0.5 * dt, op.dflag, s);
+        stage_launch(fa, HGF_FP64, 1, pv2, nullptr, pv2, nullptr, pv1, dt / 3.0, op.dflag, s);
+        stage_launch(fa, HGF_FP64, 1, pv1, nullptr, pv1, nullptr, px, 0.25 * dt, op.dflag, s);
+        launch_adjoint_q(f.ga, pm, pv2, pv1, px, v2, v1, x1, yn, Qp, dt, s);
+        // stage-4 form (y += x1 + (h'/2) L^T in) with x1 = 0, h' = 2h: B4
+        stage_launch(fa, HGF_FP64, 4, px, zero.p, pm, nullptr, nullptr, 2.0 * dt, op.dflag, s);
+      }
+    };
+    std::map<int64_t, std::unique_ptr<GraphHolder>> seg_graphs;
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
+      hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+      if (L > kGradGraphSteps) {  // long segments run without a graph
+        segment(L, st);
+        continue;
+      }
+      auto it = seg_graphs.find(L);
+      if (it == seg_graphs.end()) {
+        hip_check(hipStreamSynchronize(st), "synchronize");
+        hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        segment(L, cap);
+        hipGraph_t graph;
+        hip_check(hipStreamEndCapture(cap, &graph), "end capture");
+        hipGraphExec_t exec;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "graph instantiate");
+        it = seg_graphs.emplace(L, std::unique_ptr<GraphHolder>(new GraphHolder(exec))).first;
+      }
+      hip_check(hipGraphLaunch(it->second->e, st), "graph launch");
+    }
+    hip_check(hipStreamSynchronize(st), "synchronize");  // graphs are destroyed with seg_graphs
+    // leave the function at its initial state
+    hip_check(hipMemcpyAsync(f.y, y0.p, gb, hipMemcpyDeviceToDevice, st), "restore");
+    // marginals of Q -> parameter derivatives
+    const int nb = marginal_bins(f.ga);
+    DBuf dbins(nb * sizeof(double2));
+    launch_marginals(f.ga, Q.as<double2>(), dbins.as<double2>(), st);
+    hip_check(hipGetLastError(), "kernel launch");
+    std::vector<cd> bins(nb);
+    hip_check(hipMemcpyAsync(bins.data(), dbins.p, nb * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    int tot_e = 0;
+    for (int j = 0; j < sys.n; ++j) tot_e += f.ga.ext[j];
+    cd S0 = 0.0;
+    for (int v = 0; v < f.ga.ext[0]; ++v) S0 += bins[v];
+    for (int p = 0; p < P; ++p) {
+      const System u = unit_system(sys, p);
+      const SectorTables tp = sector_tables(u, f.tab.d);
+      cd g = tp.lam0 * S0;
+      for (int j = 0; j < sys.n; ++j) {
+        for (int v = 0; v < f.ga.ext[j]; ++v) {
+          g += tp.lam[j][v] * bins[f.ga.off[j] + v];
+          g += tp.alpha[j][v] * bins[tot_e + f.ga.off[j] + v];
+          g += tp.beta[j][v] * bins[2 * tot_e + f.ga.off[j] + v];
+        }
+      }
+      grad[p] += g;
+    }
+  }
+  if (read_flag(&op, st)) fail(HGF_ENONFINITE, "non-finite value during the gradient sweep");
+  value_out[0] = value.real();
+  value_out[1] = value.imag();
+  for (int p = 0; p < P; ++p) {
+    grad_out[2 * p] = grad[p].real();
+    grad_out[2 * p + 1] = grad[p].imag();
+  }
+}
+
+}  // namespace hgf

@@ -70,7 +70,8 @@ class _Info(ctypes.Structure):
                 ("total_points", ctypes.c_int64), ("steps_done", ctypes.c_int64),
                 ("time_us", ctypes.c_double), ("fp32_underflow", ctypes.c_int64),
                 ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32),
-                ("stored_peak", ctypes.c_int64)]
+                ("stored_peak", ctypes.c_int64), ("untiled_functions", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _TileConfig(ctypes.Structure):

@@ -282,3 +282,25 @@ def test_resident_members_in_a_batch(hgf):
         assert max_rel_err(a, b) < 1e-6, c
         ref = oracle_number_grids(c, oracle.evolve(s, oracle.product_sectors(f), t, dt))
         assert max_rel_err(a, ref) < MIXED_TOL, c
+
+
+def test_untiled_functions_reported(hgf, monkeypatch):
+    """hgf_get_info counts the functions that run on the untiled stage kernel:
+    none on a grid the tiled kernel takes, all of them when the untiled
+    kernel is forced, and that count follows a forced shape (nfast 0)."""
+    announce("untiled functions in hgf_get_info")
+    cutoff = (4, 6, 6, 6, 6)  # one diagonal sector of 5184 points: tiled, not resident
+    s = synth.random_system(cutoff, 52)
+    rng = np.random.default_rng(52)
+    # complex diagonal entries: a complex grid (the untiled kernel takes no real grids)
+    fac = [np.diag(rng.uniform(0.5, 1.5, size=c) * np.exp(1j * rng.uniform(0, 6.3, size=c))) for c in cutoff]
+    S = hgf.define_system(s)
+    op = hgf.map_operator(S, factors=fac, precision="fp64")
+    info = op.info()
+    assert info["untiled_functions"] == 0
+    op.set_tile_config(0, 0)
+    assert op.info()["untiled_functions"] == 1
+    monkeypatch.setenv("HGF_STAGE_KERNEL", "generic")
+    op2 = hgf.map_operator(S, factors=fac, precision="fp64")
+    i2 = op2.info()
+    assert i2["untiled_functions"] == i2["n_functions"] > 0
