@@ -64,10 +64,10 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def stored_traffic(shape: dict):
+def stored_traffic(shape: dict, real: bool = True, precision: str = "mixed"):
     """HBM bytes per stage launch from committed rocprofv3 counter runs, or
     None when the kernel source changed since, or no run used this launch
-    shape."""
+    shape (with these element types)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
@@ -75,8 +75,9 @@ def stored_traffic(shape: dict):
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     want = [shape[k] for k in ("nfast", "threads", "xblock", "pipe", "wgs_per_cu", "walk_block")]
+    kind = f":{precision}:{'real' if real else 'complex'}:"
     for entry in t.get("shapes", []):
-        if [int(x) for x in entry["tune_cache_line"].split()[1:7]] == want:
+        if kind in entry["tune_cache_line"] and [int(x) for x in entry["tune_cache_line"].split()[1:7]] == want:
             return entry["traffic_bytes_per_launch"]
     return None
 
@@ -471,6 +472,8 @@ def main():
                          "network for 1 to 5 modes, network5 = its five-mode runs alone, gradient = the gradient "
                          "workload over 0.5 us (5,000 steps), storage = the conventional and separated "
                          "network forms with thresholds, batch = the batch workload over --steps steps")
+    ap.add_argument("--complex-grids", action="store_true",
+                    help="time the general complex form of the grid (real-grid form off) as the main run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -511,9 +514,14 @@ def main():
     pts = int(np.prod(w.system.cutoff))
     S = hgf.define_system(w.system)
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, real_grids=True):
         tm = time.perf_counter()
-        op = hgf.map_operator(S, factors=w.factors, precision=precision)  # step (i): host build and upload
+        if not real_grids:
+            os.environ["HGF_REAL_GRIDS"] = "0"  # the general complex form of the same grid
+        try:
+            op = hgf.map_operator(S, factors=w.factors, precision=precision)  # step (i): host build and upload
+        finally:
+            os.environ.pop("HGF_REAL_GRIDS", None)
         torch.cuda.synchronize()
         log(f"map_operator: {time.perf_counter() - tm:.3f} s")
         real = op.info()["real_functions"] == 1
@@ -537,12 +545,12 @@ def main():
         return el, launch_s, J, real, tune
 
     log(f"timing {args.steps} steps ({args.precision}) over {pts} points")
-    el, launch_s, J, real, tune = run(args.precision, args.steps, args.warmup)
+    el, launch_s, J, real, tune = run(args.precision, args.steps, args.warmup, real_grids=not args.complex_grids)
     log(f"done: {el:.3f} s, stage launch {launch_s * 1e6:.1f} us")
     value = pts * 4 * args.steps / el
     bytes_launch = bytes_per_point_stage(args.precision, real) * pts
     achieved = bytes_launch / launch_s / 1e9
-    traffic = stored_traffic(tune)
+    traffic = stored_traffic(tune, real, args.precision)
     line = {
         "metric": METRIC,
         "value": value,
@@ -575,6 +583,17 @@ def main():
         el64, launch64, J64, real64, _ = run("fp64", n64, 2)
         line["fp64_plain"] = {"value": pts * 4 * n64 / el64, "steps": n64, "real_grids": real64,
                               "achieved_GBs": bytes_per_point_stage("fp64", real64) * pts / launch64 / 1e9}
+        log("complex grid (real-grid form off)")
+        nc = max(10, args.steps // 4)
+        line["complex_grid"] = {}
+        for prec in ("mixed", "fp64"):
+            elc, launchc, Jc, realc, tunec = run(prec, nc, 2, real_grids=False)
+            bc = bytes_per_point_stage(prec, realc) * pts
+            line["complex_grid"][prec] = {
+                "value": pts * 4 * nc / elc, "steps": nc, "real_grids": realc, "avg_launch_us": launchc * 1e6,
+                "algorithmic_bytes_per_launch": bc, "achieved_GBs": bc / launchc / 1e9,
+                "frac": bc / launchc / 1e9 / HBM_PEAK_GBS, "tile_shape": tunec,
+                "rel_diff_from_real_grid_J": abs(Jc - J) / abs(J) if prec == args.precision else None}
         log("time-to-1e-5 on the 3-mode workload")
         line["time_to_1e-5"] = time_to_tolerance(hgf, torch)
         if not args.no_full_horizon:

@@ -245,8 +245,10 @@ double time_plan_steps(const std::vector<PlanItem>& items, int* flag, int steps,
 // Grouped launches: the functions of all operators that share an axis split
 // and element types run as one grouped launch per stage (a batch, or the
 // sectors of one operator).  The grouped kernel is tuned as a whole: workgroup
-// size and resident workgroups per CU, applied to every member (their numbers
-// of fast axes are kept).  The cache key names the group's composition.
+// size, resident workgroups per CU and the number of fast axes (the members'
+// own, or one more: a tile that would leave one grid too few tiles to fill
+// the chip can pay off across many members, with fewer slow-axis neighbours),
+// applied to every member.  The cache key names the group's composition.
 void tune_groups(hgf_operator* ops, int n, double h, const std::string& dev,
                         std::map<std::string, TuneEntry>& cache, std::set<std::string>& fresh, int flags,
                         bool& measured, int* flag, hipStream_t st) {
@@ -289,27 +291,28 @@ void tune_groups(hgf_operator* ops, int n, double h, const std::string& dev,
       continue;
     }
     if (flags & HGF_TUNE_CACHED_ONLY) continue;
-    // candidates: workgroup sizes every member can use, full occupancy or one
-    // to three workgroups per CU fewer
+    // candidates: the members' fast axes or one more, workgroup sizes every
+    // member can use, all resident workgroups per CU or a cap
     std::vector<TileChoice> cands;
-    for (int th = 64; th <= 512; th += 64)
-      for (int w : {0, 1, 2, 3, 4, 6}) {
-        TileChoice c;
-        c.nfast = nfast;
-        c.threads = th;
-        c.xblock = 0;
-        c.pipe = 0;
-        c.wgs_per_cu = w;
-        bool ok = true;
-        for (auto& m : mem) {
-          GridArgs g = m.second->ga;
-          if (!configure_tiles(g, prec, m.second->real, c)) {
-            ok = false;
-            break;
+    for (int nf = nfast; nf <= nfast + 1; ++nf)
+      for (int th = 64; th <= 512; th += 64)
+        for (int w : {0, 1, 2, 3, 4, 6}) {
+          TileChoice c;
+          c.nfast = nf;
+          c.threads = th;
+          c.xblock = 0;
+          c.pipe = 0;
+          c.wgs_per_cu = w;
+          bool ok = true;
+          for (auto& m : mem) {
+            GridArgs g = m.second->ga;
+            if (!configure_tiles(g, prec, m.second->real, c)) {
+              ok = false;
+              break;
+            }
           }
+          if (ok) cands.push_back(c);
         }
-        if (ok) cands.push_back(c);
-      }
     if (cands.empty()) continue;
     std::vector<PlanItem> items;
     for (auto& m : mem) items.push_back({m.second, prec, h});

@@ -30,3 +30,4 @@ def test_stored_traffic_matches_the_stage_kernel_source():
     traffic = bench.stored_traffic(tuned)
     assert traffic is not None and traffic > t["algorithmic_bytes_per_launch"]
     assert bench.stored_traffic(dict(tuned, threads=128)) is None  # a shape without counter runs
+    assert bench.stored_traffic(tuned, real=False) is None  # the complex form has counters of its own
