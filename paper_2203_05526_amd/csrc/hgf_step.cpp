@@ -218,11 +218,78 @@ void ensure_plan(hgf_operator_s* op, double h) {
 }
 
 
+// Streams a capture forks onto (one per grouped launch beyond the first),
+// per host thread and device (so that captures on several threads never
+// share one), created with the default priority and kept until the process
+// ends.
+static hipStream_t branch_stream(int dev, size_t i) {
+  static thread_local std::map<int, std::vector<hipStream_t>> pool;
+  std::vector<hipStream_t>& v = pool[dev];
+  while (v.size() <= i) {
+    hipStream_t s;
+    hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
+    v.push_back(s);
+  }
+  return v[i];
+}
+
+// HGF_GRAPH_BRANCHES=0 captures every launch in one chain.
+static bool graph_branches() {
+  const char* env = std::getenv("HGF_GRAPH_BRANCHES");
+  return !(env && std::string(env) == "0");
+}
+
+// `chunk` steps of the plan as one graph.  The grouped launches are
+// independent of each other (different functions), so with several groups
+// each group's chain of stages is captured on its own branch (forked from and
+// joined back to `cap`): a group too small to fill the chip then runs beside
+// the others instead of after them.  Within a branch the stages keep their
+// order; results do not depend on the branching.
 hipGraphExec_t capture_steps(const StepPlan& plan, int* flag, int chunk, hipStream_t cap) {
   hipGraph_t graph;
+  const size_t ng = plan.groups.size();
+  const bool fork = ng > 1 && graph_branches();
+  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[g]: join of group g's branch
+  auto drop_events = [&] {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  };
+  int dev = 0;
+  if (fork) hip_check(hipGetDevice(&dev), "hipGetDevice");
   hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
-  for (int s = 0; s < chunk; ++s) run_plan_step(plan, flag, cap);
-  hip_check(hipStreamEndCapture(cap, &graph), "end capture");
+  try {
+    if (!fork) {
+      for (int s = 0; s < chunk; ++s) run_plan_step(plan, flag, cap);
+    } else {
+      for (size_t g = 0; g < ng; ++g) {
+        hipEvent_t e;
+        hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        ev.push_back(e);
+      }
+      hip_check(hipEventRecord(ev[0], cap), "fork");
+      for (size_t g = 1; g < ng; ++g) {
+        hipStream_t b = branch_stream(dev, g - 1);
+        hip_check(hipStreamWaitEvent(b, ev[0], 0), "fork");
+        for (int s = 0; s < chunk; ++s)
+          for (int stage = 1; stage <= 4; ++stage) launch_group(plan.groups[g], stage, flag, b);
+        hip_check(hipEventRecord(ev[g], b), "join");
+      }
+      for (int s = 0; s < chunk; ++s)
+        for (int stage = 1; stage <= 4; ++stage) {
+          launch_group(plan.groups[0], stage, flag, cap);
+          for (const PlanItem& it : plan.generic) generic_stage(it, stage, flag, cap);
+        }
+      for (size_t g = 1; g < ng; ++g) hip_check(hipStreamWaitEvent(cap, ev[g], 0), "join");
+    }
+  } catch (...) {
+    hipGraph_t partial;
+    if (hipStreamEndCapture(cap, &partial) == hipSuccess) (void)hipGraphDestroy(partial);
+    drop_events();
+    throw;
+  }
+  const hipError_t ec = hipStreamEndCapture(cap, &graph);
+  drop_events();
+  hip_check(ec, "end capture");
   hipGraphExec_t exec;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
