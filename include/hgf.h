@@ -223,7 +223,8 @@ hgf_status hgf_evolve(hgf_operator op, double t_total_us, double dt_us, int32_t 
  * Batched form of hgf_evolve: every member advances by its own t_total/dt
  * (arrays of n), all members' RK stages issued as one grouped launch per
  * stage and captured in a HIP graph.  Members must be distinct handles on the
- * same device with the layout HGF_MERGED.  Errors as for hgf_evolve; on
+ * same device with the layout HGF_MERGED.  Errors as for hgf_evolve, and
+ * HGF_EUNSUPPORTED for a member with a threshold (hgf_set_threshold); on
  * error no member has been advanced.
  */
 hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_us,
@@ -239,7 +240,8 @@ typedef struct {
 /*
  * Step (iii): out_re_im = <psi0| A(t) |psi0> for a product state, summed over
  * every function with FP64 accumulation (Eq. (11) contracted with psi0; in
- * split mode the separable part c_x c_y x^p y^q is added analytically).
+ * split mode the separable part c_x c_y x^p y^q is added analytically; in the
+ * separated layouts sum_i g_i <Gx_i> <Gy_i> + <R>).
  * Errors: HGF_EINVAL, HGF_EDEVICE.  Synchronises hip_stream.
  */
 hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2],
@@ -258,7 +260,8 @@ hgf_status hgf_expectation(hgf_operator op, const hgf_state_desc* psi, double ou
  * or a few thousand small ones) are refused with HGF_EINVAL; hgf_expectation
  * serves them.  Calls on one GPU share its array: calls that overlap in time
  * on one GPU (several threads, or streams running concurrently) race and
- * must be serialised by the caller.  Errors as for hgf_expectation.
+ * must be serialised by the caller.  Errors as for hgf_expectation, and
+ * HGF_EUNSUPPORTED for the separated layouts (read through hgf_expectation).
  */
 hgf_status hgf_expectation_noalloc(hgf_operator op, const hgf_state_desc* psi, double out_re_im[2],
                                    void* hip_stream);

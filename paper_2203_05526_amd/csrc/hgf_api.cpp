@@ -383,6 +383,8 @@ hgf_status hgf_evolve_batch(hgf_operator* ops, int32_t n, const double* t_total_
       if (!ops[i]) fail(HGF_EINVAL, "NULL operator in batch");
       if (ops[i]->error_state) fail(HGF_ESTATE, "operator in batch is in an error state");
       if (ops[i]->layout != HGF_MERGED) fail(HGF_EINVAL, "batched evolve needs the merged layout");
+      if (ops[i]->threshold > 0.0)
+        fail(HGF_EUNSUPPORTED, "an operator with a threshold is evolved with hgf_evolve, not in a batch");
       for (int k = 0; k < i; ++k)
         if (ops[k] == ops[i]) fail(HGF_EINVAL, "batch members must be distinct");
       steps[i] = check_steps(t_total_us[i], dt_us[i]);

@@ -90,7 +90,8 @@ def test_threshold_separated_matches_truncated_oracle(hgf):
 
 def test_threshold_switches(hgf):
     """Threshold 0 turns the truncation off (the same result as never set);
-    negative thresholds are refused; sector operators are not truncated."""
+    negative thresholds are refused; a batch refuses a truncated member;
+    sector operators are not truncated."""
     w = synth.table1_network(2, 4)
     S = hgf.define_system(w.system)
     a = hgf.map_operator(S, factors=w.factors)
@@ -104,6 +105,10 @@ def test_threshold_switches(hgf):
     with pytest.raises(hgf.HgfError) as e:
         hgf.set_threshold(a, -1.0)
     assert e.value.status == "HGF_EINVAL"
+    hgf.set_threshold(b, 1e-6)
+    with pytest.raises(hgf.HgfError) as e:  # truncation runs step by step in hgf_evolve only
+        hgf.evolve_batch([a, b], [w.t_total] * 2, [w.dt] * 2)
+    assert e.value.status == "HGF_EUNSUPPORTED"
     s = synth.random_system((3, 3), 1)
     c = hgf.map_operator(hgf.define_system(s), factors=[np.eye(3), np.eye(3)])
     with pytest.raises(hgf.HgfError) as e:
