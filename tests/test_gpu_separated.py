@@ -115,3 +115,57 @@ def test_separated_layout_rules(hgf):
     hgf.evolve(b, w.t_total / 2, w.dt)
     assert np.array_equal(hgf.reconstruct(a, 5), hgf.reconstruct(b, 5))
     assert a.info()["steps_done"] == 100
+
+
+@pytest.mark.parametrize("layout", ["separated", "separated_exact"])
+def test_ragged_three_modes_sparse_operator_with_drop_tol(hgf, layout):
+    """Three modes of unequal cutoffs (3, 4, 5) in a driven exchange chain
+    under the Lindblad dissipator at finite temperature, a sparse random
+    operator, and drop_tol keeping part of its monomials (the same ones on
+    both sides: the threshold sits in a wide gap of the |g_{p,q}(0)|)."""
+    cutoff = (3, 4, 5)
+    s = synth.random_system(cutoff, 402, scale=2.0, n_th=0.15)
+    s.gamma_phi = np.array([0.2, 0.5, 0.3])
+    s.drive = np.array([0.0, 1.2 + 0.4j, -0.6j])
+    s.exchange = np.array([[0.0, 1.7, 0.0], [1.7, 0.0, -2.2], [0.0, -2.2, 0.0]])
+    ks, ls, vals = synth.random_sparse_operator(cutoff, 40, 402)
+    dim = int(np.prod(cutoff))
+    A0 = np.zeros((dim, dim), dtype=np.complex128)
+    for k, l, v in zip(ks, ls, vals):
+        A0[np.ravel_multi_index(k, cutoff), np.ravel_multi_index(l, cutoff)] += v
+    g = np.sort(np.array([abs(m[2]) for m in oracle.monomials(s, A0)]))
+    gaps = g[1:] / g[:-1]
+    idx = np.arange(len(gaps))
+    i = int(np.argmax(np.where((idx >= len(g) // 3) & (idx < 2 * len(g) // 3), gaps, 0.0)))
+    assert gaps[i] > 1.01
+    drop = float(np.sqrt(g[i] * g[i + 1]))
+    monos = oracle.monomials(s, A0, drop_tol=drop)
+    assert 0 < len(monos) < len(g)
+    announce(f"separated {layout}: ragged 3 modes, {len(monos)} of {len(g)} monomials")
+    op = hgf.map_operator(hgf.define_system(s), sparse=(ks, ls, vals), layout=layout, drop_tol=drop)
+    assert op.info()["n_functions"] == 2 * len(monos) + 1
+    T, dt = 0.1, 1e-3
+    hgf.evolve(op, T, dt)
+    gx, gy, r = oracle.evolve_separated(s, monos, T, dt, "z" if layout == "separated" else "full")
+    ref = oracle.separated_matrix(s, monos, gx, gy, r)
+    assert _matrix_err(hgf.reconstruct(op, 3), ref[np.ix_(*[_levels(cutoff, 3)] * 2)]) < FP64_TOL
+    st = synth.coherent_state([0.4, 0.7 - 0.3j, 0.5j])
+    amps = oracle.state_amplitudes(cutoff, st)
+    c = np.kron(np.kron(amps[0], amps[1]), amps[2])
+    assert rel(hgf.expectation(op, st), np.conj(c) @ ref @ c) < FP64_TOL
+
+
+def test_separated_zero_operator_and_noalloc_refusal(hgf):
+    """With every coefficient below drop_tol there is no monomial: R stays
+    zero; the allocation-free expectation refuses the separated layouts."""
+    w = synth.table1_network(2, 4)
+    S = hgf.define_system(w.system)
+    op = hgf.map_operator(S, factors=w.factors, layout="separated", drop_tol=1e9)
+    assert op.info()["n_functions"] == 1
+    hgf.evolve(op, w.t_total, w.dt)
+    assert np.all(hgf.reconstruct(op, 4) == 0)
+    assert hgf.expectation(op, w.states[0]) == 0
+    op2 = hgf.map_operator(S, factors=w.factors, layout="separated")
+    with pytest.raises(hgf.HgfError) as e:
+        hgf.expectation_noalloc(op2, w.states[0])
+    assert e.value.status == "HGF_EUNSUPPORTED"
