@@ -326,8 +326,9 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
  * in memory.  threshold = 0 turns it off.  For FP64 network operators on the
  * full (k, l) grid and for the separated layouts (every Gx, Gy grid and R);
  * other operators return HGF_EUNSUPPORTED.  Steps run one launch sequence at
- * a time (no graph) while a threshold is set.  Errors: HGF_EINVAL (negative
- * or non-finite threshold), HGF_EUNSUPPORTED, HGF_EDEVICE.
+ * a time (no graph) while a threshold is set.  The call synchronises the
+ * device (it resets the counters).  Errors: HGF_EINVAL (negative or
+ * non-finite threshold), HGF_EUNSUPPORTED, HGF_EDEVICE.
  */
 hgf_status hgf_set_threshold(hgf_operator op, double threshold);
 

@@ -345,11 +345,13 @@ hgf_status hgf_set_threshold(hgf_operator op, double threshold) {
     if (!op) fail(HGF_EINVAL, "operator is NULL");
     if (!std::isfinite(threshold) || threshold < 0.0) fail(HGF_EINVAL, "threshold must be finite and >= 0");
     bool ok = op->precision == HGF_FP64 && (op->sep != nullptr || !op->fn.empty());
-    for (auto& f : op->fn) ok = ok && f.full;
+    for (auto& f : op->fn) ok = ok && f.full && !f.real;  // complex128 grids
     if (!ok)
       fail(HGF_EUNSUPPORTED, "thresholded storage applies to FP64 network operators on the full grid and to the "
                              "separated layouts");
     hip_check(hipSetDevice(op->device), "hipSetDevice");
+    // work still in flight on any stream may be adding to the counters
+    hip_check(hipDeviceSynchronize(), "synchronize");
     if (!op->dcount) op->dcount = (unsigned long long*)dmalloc(2 * sizeof(unsigned long long));
     hip_check(hipMemset(op->dcount, 0, 2 * sizeof(unsigned long long)), "clear counters");
     op->threshold = threshold;
