@@ -356,7 +356,9 @@ def network_storage(hgf, torch, max_modes: int = 4):
     truncation and at the largest threshold (from a geometric sweep) whose
     error stays within the common target max(100 ppm, 1.25 x the larger
     untruncated error); the peak number of coefficients kept (the stored
-    elements of a sparse store) and the dense grid points; the wall time.
+    elements of a sparse store) and the dense grid points, and the same at
+    the granularity of tiles (the stage kernel's tile on the full grid, one
+    grid of a monomial in the separated form); the wall time.
     The separated form with R on the whole box (exact) is also run untruncated
     up to three modes, and the separated form at cutoff 5 (untruncated, and
     thresholded where its untruncated error meets the target)."""
@@ -409,7 +411,9 @@ def network_storage(hgf, torch, max_modes: int = 4):
                 e = eps(op)
                 del op
                 if e <= target:
-                    return {"threshold": thr, "eps_r": e, "stored_peak": info["stored_peak"], "seconds": el}
+                    return {"threshold": thr, "eps_r": e, "stored_peak": info["stored_peak"], "seconds": el,
+                            "stored_tiles_peak": info["stored_tiles_peak"], "tile_points": info["tile_points"],
+                            "tiles": info["total_points"] // max(1, info["tile_points"])}
             return None
 
         for name, layout in (("conventional", "merged"), ("separated", "separated")):

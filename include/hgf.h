@@ -311,6 +311,12 @@ typedef struct {
                                 them (a tile beyond LDS, more than 12 slow axes, a buffer over
                                 2^32 bytes, or HGF_STAGE_KERNEL=generic); several times slower */
   int32_t reserved;
+  int64_t stored_tiles_peak; /* with a threshold set: the largest number of tiles (runs of tile_points
+                                consecutive coefficients) holding a kept coefficient after any step,
+                                the units a sparse store would skip whole; else -1 */
+  int64_t tile_points;       /* network operators: the stage kernel's tile on the full grid (the (k, l)
+                                block of the two fastest modes, the whole grid below three modes);
+                                separated layouts: one grid of prod_j Nc_j points; else 0 */
 } hgf_operator_info;
 
 hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
@@ -322,7 +328,8 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info);
  * coefficient g with |g| <= threshold is set to zero, and the number of
  * coefficients kept is counted; hgf_get_info's stored_peak reports the
  * largest count since the threshold was set (the stored elements a sparse
- * store of the representation would hold at its peak).  The grids stay dense
+ * store of the representation would hold at its peak), and stored_tiles_peak
+ * the same for tiles of tile_points coefficients.  The grids stay dense
  * in memory.  threshold = 0 turns it off.  For FP64 network operators on the
  * full (k, l) grid and for the separated layouts (every Gx, Gy grid and R);
  * other operators return HGF_EUNSUPPORTED.  Steps run one launch sequence at

@@ -352,8 +352,8 @@ hgf_status hgf_set_threshold(hgf_operator op, double threshold) {
     hip_check(hipSetDevice(op->device), "hipSetDevice");
     // work still in flight on any stream may be adding to the counters
     hip_check(hipDeviceSynchronize(), "synchronize");
-    if (!op->dcount) op->dcount = (unsigned long long*)dmalloc(2 * sizeof(unsigned long long));
-    hip_check(hipMemset(op->dcount, 0, 2 * sizeof(unsigned long long)), "clear counters");
+    if (!op->dcount) op->dcount = (unsigned long long*)dmalloc(4 * sizeof(unsigned long long));
+    hip_check(hipMemset(op->dcount, 0, 4 * sizeof(unsigned long long)), "clear counters");
     op->threshold = threshold;
   });
 }
@@ -465,11 +465,16 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
     info->untiled_functions = untiled;
     info->reserved = 0;
     info->stored_peak = -1;
+    info->stored_tiles_peak = -1;
+    info->tile_points = op->sep ? separated_tile_points(op) : (op->fn.size() == 1 && op->fn[0].full)
+                                                                   ? full_tile_points(op->fn[0])
+                                                                   : 0;
     if (op->threshold > 0.0 && op->dcount) {
-      unsigned long long peak = 0;
+      unsigned long long c[4] = {};
       hip_check(hipSetDevice(op->device), "hipSetDevice");
-      hip_check(hipMemcpy(&peak, op->dcount + 1, sizeof(peak), hipMemcpyDeviceToHost), "download");
-      info->stored_peak = (int64_t)peak;
+      hip_check(hipMemcpy(c, op->dcount, sizeof(c), hipMemcpyDeviceToHost), "download");
+      info->stored_peak = (int64_t)c[1];
+      info->stored_tiles_peak = (int64_t)c[3];
     }
   });
 }

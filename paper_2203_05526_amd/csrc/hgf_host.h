@@ -67,6 +67,7 @@ void separated_evolve(hgf_operator_s* op, int64_t steps, double h, hipStream_t s
 cd separated_expectation(hgf_operator_s* op, const hgf_state_desc* psi, hipStream_t st);
 void separated_reconstruct(hgf_operator_s* op, int levels, double* out, hipStream_t st);
 int64_t separated_points(const hgf_operator_s* op);
+int64_t separated_tile_points(const hgf_operator_s* op);
 int separated_functions(const hgf_operator_s* op);
 
 }  // namespace hgf

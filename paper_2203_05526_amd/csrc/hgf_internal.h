@@ -323,5 +323,5 @@ struct hgf_operator_s {
   // |g| <= threshold are dropped after every step; device counters of the
   // survivors (count of the last step, peak since the threshold was set)
   double threshold = 0.0;
-  unsigned long long* dcount = nullptr;  // [2]: count, peak
+  unsigned long long* dcount = nullptr;  // [4]: count, peak, tile count, tile peak
 };

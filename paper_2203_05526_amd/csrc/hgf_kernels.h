@@ -126,8 +126,14 @@ void launch_sep_gather(const SepLaunch& L, int rmode, int levels, int64_t ln, co
                        const double2* x, const double2* r, double2* out, hipStream_t st);
 // Thresholded representation: zero every coefficient with |g| <= thr and add
 // the survivors to *count; then peak = max(peak, count) and count = 0.
-void launch_threshold(double2* g, int64_t n, double thr, unsigned long long* count, hipStream_t st);
-void launch_threshold_peak(unsigned long long* count, unsigned long long* peak, hipStream_t st);
+// Thresholded representation: zero |g| <= thr in g[0, n) and add the kept
+// count to counters[0]; with tile > 0 (n a multiple of it) also add the
+// number of tiles of `tile` points that keep a coefficient to counters[2].
+// launch_threshold_peak folds counters[0] into the peak counters[1] and
+// counters[2] into counters[3], and clears the counts.
+void launch_threshold(double2* g, int64_t n, double thr, int64_t tile, unsigned long long* counters,
+                      hipStream_t st);
+void launch_threshold_peak(unsigned long long* counters, hipStream_t st);
 // Device address of the current device's copy of the static scratch
 // (kScratchBytes), looked up once per device.
 void* scratch_address();

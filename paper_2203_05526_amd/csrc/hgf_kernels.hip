@@ -528,21 +528,44 @@ __global__ __launch_bounds__(256) void k_threshold(double2* __restrict__ g, int6
   for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
-// peak = max(peak, count); count = 0 (one thread)
-__global__ void k_threshold_peak(unsigned long long* __restrict__ count, unsigned long long* __restrict__ peak) {
+// tiles (runs of `tile` consecutive points) that hold a nonzero coefficient:
+// one workgroup per tile at a time, one atomic add per such tile
+__global__ __launch_bounds__(256) void k_threshold_tiles(const double2* __restrict__ g, int64_t ntiles, int64_t tile,
+                                                         unsigned long long* __restrict__ count) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {  // uniform across the workgroup
+    int any = 0;
+    for (int64_t i = threadIdx.x; i < tile; i += blockDim.x) {
+      const double2 v = g[t * tile + i];
+      any |= (v.x != 0.0 || v.y != 0.0) ? 1 : 0;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0 && any) atomicAdd(count, 1ull);
+  }
+}
+// counters [count, peak, tile count, tile peak]: each peak = max(peak, count),
+// count = 0 (one thread)
+__global__ void k_threshold_peak(unsigned long long* __restrict__ c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (*count > *peak) *peak = *count;
-    *count = 0;
+    for (int k = 0; k < 4; k += 2) {
+      if (c[k] > c[k + 1]) c[k + 1] = c[k];
+      c[k] = 0;
+    }
   }
 }
 
-void launch_threshold(double2* g, int64_t n, double thr, unsigned long long* count, hipStream_t st) {
+void launch_threshold(double2* g, int64_t n, double thr, int64_t tile, unsigned long long* counters,
+                      hipStream_t st) {
   if (n <= 0) return;
   const int b = (int)std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_threshold, dim3(b), dim3(256), 0, st, g, n, thr, count);
+  hipLaunchKernelGGL(k_threshold, dim3(b), dim3(256), 0, st, g, n, thr, counters);
+  if (tile > 0) {
+    const int64_t nt = n / tile;
+    hipLaunchKernelGGL(k_threshold_tiles, dim3((unsigned)std::min<int64_t>(nt, 4096)), dim3(256), 0, st,
+                       (const double2*)g, nt, tile, counters + 2);
+  }
 }
-void launch_threshold_peak(unsigned long long* count, unsigned long long* peak, hipStream_t st) {
-  hipLaunchKernelGGL(k_threshold_peak, dim3(1), dim3(64), 0, st, count, peak);
+void launch_threshold_peak(unsigned long long* counters, hipStream_t st) {
+  hipLaunchKernelGGL(k_threshold_peak, dim3(1), dim3(64), 0, st, counters);
 }
 
 // ------------------------------------------------------------ stage-precision copy

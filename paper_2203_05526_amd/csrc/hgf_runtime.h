@@ -124,6 +124,7 @@ void ensure_graph(hgf_operator_s* op, double h, int chunk);
 void split_step(hgf_operator_s* op, Function& f, double h, hipStream_t st);
 void ensure_lawson_tables(Function& f, double h, hipStream_t st);
 void lawson_steps(hgf_operator_s* op, int64_t steps, double h, hipStream_t st);
+int64_t full_tile_points(const Function& f);
 void apply_threshold(hgf_operator_s* op, hipStream_t st);
 void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, int scheme = HGF_RK4);
 void batch_impl(hgf_operator* ops, int n, const std::vector<int64_t>& steps, const double* dt, hipStream_t st);

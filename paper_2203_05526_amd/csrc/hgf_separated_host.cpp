@@ -141,6 +141,8 @@ int64_t separated_points(const hgf_operator_s* op) {
 
 int separated_functions(const hgf_operator_s* op) { return 2 * op->sep->L.d.nmono + 1; }
 
+int64_t separated_tile_points(const hgf_operator_s* op) { return op->sep->L.d.dim; }
+
 void separated_evolve(hgf_operator_s* op, int64_t steps, double h, hipStream_t strm) {
   SepState* st = op->sep;
   const SepDims& d = st->L.d;
@@ -176,9 +178,10 @@ void separated_evolve(hgf_operator_s* op, int64_t steps, double h, hipStream_t s
         launch_sep_sides(st->L, s, h, (const double2*)st->dcst, X[0], X[1], X[in_of[s]], X[out_of[s]], op->dflag,
                          strm);
       if (s == 4 && op->threshold > 0.0) {  // thresholded representation of every grid
-        launch_threshold(X[0], 2 * (int64_t)d.nmono * d.dim, op->threshold, op->dcount, strm);
-        launch_threshold(R[0], st->rlen, op->threshold, op->dcount, strm);
-        launch_threshold_peak(op->dcount, op->dcount + 1, strm);
+        // tiles: one grid of D points (each Gx_i, Gy_i; R per row of D)
+        launch_threshold(X[0], 2 * (int64_t)d.nmono * d.dim, op->threshold, d.dim, op->dcount, strm);
+        launch_threshold(R[0], st->rlen, op->threshold, d.dim, op->dcount, strm);
+        launch_threshold_peak(op->dcount, strm);
       }
     }
   hip_check(hipGetLastError(), "kernel launch");

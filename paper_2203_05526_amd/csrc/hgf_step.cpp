@@ -449,9 +449,18 @@ int read_flag(hgf_operator_s* op, hipStream_t st) {
 
 // Thresholded representation: drop every coefficient with |g| <= threshold
 // from the operator's full-grid functions and update the peak count.
+// Tile of a network operator's full grid: the (k, l) block of the last two
+// positions (the stage kernel's tile), or the whole grid below three modes.
+int64_t full_tile_points(const Function& f) {
+  int64_t t = 1;
+  for (int a = std::max(0, f.ga.n - 4); a < f.ga.n; ++a) t *= f.ga.ext[a];
+  return t;
+}
+
 void apply_threshold(hgf_operator_s* op, hipStream_t st) {
-  for (auto& f : op->fn) launch_threshold((double2*)f.y, f.ga.points, op->threshold, op->dcount, st);
-  launch_threshold_peak(op->dcount, op->dcount + 1, st);
+  for (auto& f : op->fn)
+    launch_threshold((double2*)f.y, f.ga.points, op->threshold, full_tile_points(f), op->dcount, st);
+  launch_threshold_peak(op->dcount, st);
 }
 
 void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, int scheme) {

@@ -71,7 +71,8 @@ class _Info(ctypes.Structure):
                 ("time_us", ctypes.c_double), ("fp32_underflow", ctypes.c_int64),
                 ("error_state", ctypes.c_int32), ("real_functions", ctypes.c_int32),
                 ("stored_peak", ctypes.c_int64), ("untiled_functions", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("stored_tiles_peak", ctypes.c_int64),
+                ("tile_points", ctypes.c_int64)]
 
 
 class _TileConfig(ctypes.Structure):
