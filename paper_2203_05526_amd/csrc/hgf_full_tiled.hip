@@ -78,17 +78,30 @@ __device__ __forceinline__ void full_point(const HGF_CONST FullTables* __restric
   // in-tile strides of k_P, l_P, k_Q, l_Q
   const uint32_t slq = 1, skq = (uint32_t)ncQ, slp = (uint32_t)(ncQ * ncQ), skp = slp * (uint32_t)ncP;
 
-  // diagonal: slow part from the record, fast part here (FP64, then the
-  // stencil precision, as in the untiled kernel)
-  const double dr = rec->lam_re + tb.dk[0][kp] + tb.dk[0][lp] + tb.dk[1][kq] + tb.dk[1][lq] -
-                    ft->gphi[P] * (double)((kp - lp) * (kp - lp)) - ft->gphi[Q] * (double)((kq - lq) * (kq - lq));
-  const double ed = rec->lam_im + tb.e[0][kp] - tb.e[0][lp] + tb.e[1][kq] - tb.e[1][lq] +
-                    ft->chi[P][Q] * (double)(kp * kq - lp * lq) + rec->ck[0] * kp - rec->cl[0] * lp +
-                    rec->ck[1] * kq - rec->cl[1] * lq;
-  const TS c = tile[p];
-  const R lr = (R)dr, li = (R)ed;
-  ar = lr * re_(c) - li * im_(c);
-  ai = lr * im_(c) + li * re_(c);
+  // diagonal: slow part from the record, fast part here, in FP64 (formed
+  // where it is applied, so that nothing stays live across the neighbour
+  // terms).  In FP64 it is applied first; in mixed precision last, with the
+  // phase rate split into an FP32 high part and the FP32 rounding of the
+  // remainder, as in the untiled kernel
+  auto diag = [&](double& dr, double& ed) {
+    dr = rec->lam_re + tb.dk[0][kp] + tb.dk[0][lp] + tb.dk[1][kq] + tb.dk[1][lq] -
+         ft->gphi[P] * (double)((kp - lp) * (kp - lp)) - ft->gphi[Q] * (double)((kq - lq) * (kq - lq));
+    ed = rec->lam_im + tb.e[0][kp] - tb.e[0][lp] + tb.e[1][kq] - tb.e[1][lq] +
+         ft->chi[P][Q] * (double)(kp * kq - lp * lq) + rec->ck[0] * kp - rec->cl[0] * lp + rec->ck[1] * kq -
+         rec->cl[1] * lq;
+  };
+  constexpr bool kLast = sizeof(R) == 4;
+  if constexpr (!kLast) {
+    double dr, ed;
+    diag(dr, ed);
+    const TS c = tile[p];
+    const R lr = (R)dr, li = (R)ed;
+    ar = lr * re_(c) - li * im_(c);
+    ai = lr * im_(c) + li * re_(c);
+  } else {
+    ar = 0;
+    ai = 0;
+  }
 
   // jumps of the fast modes: g(k - e, l - e) and g(k + e, l + e) (secular:
   // only where k = l, per-level coefficients)
@@ -163,13 +176,25 @@ __device__ __forceinline__ void full_point(const HGF_CONST FullTables* __restric
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc_cplx(ar, ai, cr[q], ci[q], v[q]);
   }
+  if constexpr (kLast) {
+    double dr, ed;
+    diag(dr, ed);
+    const TS c = tile[p];
+    const R lr = (R)dr, hi = (R)ed, lo = (R)(ed - (double)hi);
+    ar -= lo * im_(c);
+    ai += lo * re_(c);
+    ar += lr * re_(c);
+    ai += lr * im_(c);
+    ar -= hi * im_(c);
+    ai += hi * re_(c);
+  }
 }
 
 // TS: stage-grid element (double2 FP64, float2 mixed); R its real type.  The
-// FP64 form is held to 128 VGPRs (4 waves per SIMD).
+// FP64 form is held to 128 VGPRs (4 waves per SIMD), the mixed form to 80 (6).
 template <typename TS>
 struct FullWaves {
-  static constexpr int value = sizeof(TS) == 16 ? 4 : 1;
+  static constexpr int value = sizeof(TS) == 16 ? 4 : 6;
 };
 template <typename TS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FullWaves<TS>::value))) void k_full_tiled(

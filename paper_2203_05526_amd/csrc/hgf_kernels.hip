@@ -203,9 +203,17 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
       el += ft->chi[i][j] * (double)(w.c[2 * i + 1] * lj);
     }
   }
+  // the diagonal: in FP64 first; in mixed precision after the neighbour
+  // terms, with the phase rate split into FP32 high and low parts (its
+  // rounding would otherwise bias every stage alike)
+  constexpr bool kLast = sizeof(R) == 4;
   const CT c = load_as<R>(in, i0);
-  const R lr = (R)dr, li = (R)(ek - el);
-  R ar = lr * c.x - li * c.y, ai = lr * c.y + li * c.x;
+  R ar = 0, ai = 0;
+  if constexpr (!kLast) {
+    const R lr = (R)dr, li = (R)(ek - el);
+    ar = lr * c.x - li * c.y;
+    ai = lr * c.y + li * c.x;
+  }
   // neighbour loops not unrolled: unrolled, their loads are all issued up
   // front and the registers they hold cost more occupancy than they save
 #pragma unroll 1
@@ -290,6 +298,16 @@ __device__ __forceinline__ typename C2<R>::T apply_L_full(const GridArgs& g, con
       ar -= J * ti;
       ai += J * tr;
     }
+  if constexpr (kLast) {
+    const double ed = ek - el;
+    const R lr = (R)dr, hi = (R)ed, lo = (R)(ed - (double)hi);
+    ar -= lo * c.y;
+    ai += lo * c.x;
+    ar += lr * c.x;
+    ai += lr * c.y;
+    ar -= hi * c.y;
+    ai += hi * c.x;
+  }
   CT out;
   out.x = ar;
   out.y = ai;
