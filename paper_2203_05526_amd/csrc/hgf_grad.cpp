@@ -158,32 +158,34 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     double2* seg = segbuf.as<double2>();
     double2* Qp = Q.as<double2>();
     // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
-    // f.y into the segment buffer (with each step's X1, V1, V2 when `store`),
-    // then sweep them in reverse.  The work of a segment depends only on L, so
-    // it is captured once per length.  The stage launches are those of the
-    // forward pass (same kernel, shape and operands), so the recomputed states
-    // equal the checkpointed trajectory bit for bit.
-    auto slot = [&](int64_t i, int k) { return seg + (i * per_step + k) * pts; };  // k: y, X1, V1, V2
-    auto segment = [&](int64_t L, hipStream_t s) {
+    // f.y into a segment buffer (with each step's X1, V1, V2 when `store`),
+    // then sweep them in reverse.  The work of a segment depends only on L
+    // (and the buffer), so it is captured once per length.  The stage launches
+    // are those of the forward pass (same kernel, shape and operands), so the
+    // recomputed states equal the checkpointed trajectory bit for bit.
+    auto slot = [&](double2* seg, int64_t i, int k) { return seg + (i * per_step + k) * pts; };  // k: y, X1, V1, V2
+    auto recompute = [&](double2* seg, int64_t L, hipStream_t s) {
       for (int64_t i = 0; i < L; ++i) {
-        launch_copy2(slot(i, 0), (const double2*)f.y, pts, s);
+        launch_copy2(slot(seg, i, 0), (const double2*)f.y, pts, s);
         if (!store) {
           if (i + 1 < L) run_plan_step(*fplan, op.dflag, s);
           continue;
         }
-        stage_launch(f, HGF_FP64, 1, slot(i, 0), nullptr, slot(i, 0), nullptr, slot(i, 1), dt, op.dflag, s);
-        stage_launch(f, HGF_FP64, 2, slot(i, 1), slot(i, 1), slot(i, 0), nullptr, slot(i, 2), dt, op.dflag, s);
-        stage_launch(f, HGF_FP64, 3, slot(i, 2), slot(i, 1), slot(i, 0), nullptr, slot(i, 3), dt, op.dflag, s);
-        if (i + 1 < L)
-          stage_launch(f, HGF_FP64, 4, slot(i, 3), slot(i, 1), f.y, nullptr, nullptr, dt, op.dflag, s);
+        double2 *y_ = slot(seg, i, 0), *x1_ = slot(seg, i, 1), *v1_ = slot(seg, i, 2), *v2_ = slot(seg, i, 3);
+        stage_launch(f, HGF_FP64, 1, y_, nullptr, y_, nullptr, x1_, dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 2, x1_, x1_, y_, nullptr, v1_, dt, op.dflag, s);
+        stage_launch(f, HGF_FP64, 3, v1_, x1_, y_, nullptr, v2_, dt, op.dflag, s);
+        if (i + 1 < L) stage_launch(f, HGF_FP64, 4, v2_, x1_, f.y, nullptr, nullptr, dt, op.dflag, s);
       }
+    };
+    auto reverse = [&](double2* seg, int64_t L, hipStream_t s) {
       for (int64_t i = L - 1; i >= 0; --i) {
-        double2* yn = slot(i, 0);
+        double2* yn = slot(seg, i, 0);
         const double2 *x1 = (const double2*)f.s1, *v1 = (const double2*)f.s2, *v2 = (const double2*)f.s3;
         if (store) {
-          x1 = slot(i, 1);
-          v1 = slot(i, 2);
-          v2 = slot(i, 3);
+          x1 = slot(seg, i, 1);
+          v1 = slot(seg, i, 2);
+          v2 = slot(seg, i, 3);
         } else {  // forward stage grids X1, V1, V2 of this step (FP64: s1, s2, s3)
           stage_launch(f, HGF_FP64, 1, yn, nullptr, yn, nullptr, f.s1, dt, op.dflag, s);
           stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
@@ -199,28 +201,85 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
         stage_launch(fa, HGF_FP64, 4, px, zero.p, pm, nullptr, nullptr, 2.0 * dt, op.dflag, s);
       }
     };
-    std::map<int64_t, std::unique_ptr<GraphHolder>> seg_graphs;
-    for (int64_t c = nseg - 1; c >= 0; --c) {
-      const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
-      hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
-      if (L > kGradGraphSteps) {  // long segments run without a graph
-        segment(L, st);
-        continue;
-      }
-      auto it = seg_graphs.find(L);
+    // graphs by (part, length, buffer): part 0 = recompute and reverse of one
+    // segment, 1 = recompute alone, 2 = reverse alone
+    std::map<std::vector<int64_t>, std::unique_ptr<GraphHolder>> seg_graphs;
+    auto graph_of = [&](int part, int64_t L, int b, double2* sb) -> hipGraphExec_t {
+      const std::vector<int64_t> key = {part, L, b};
+      auto it = seg_graphs.find(key);
       if (it == seg_graphs.end()) {
-        hip_check(hipStreamSynchronize(st), "synchronize");
         hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
-        segment(L, cap);
+        try {
+          if (part != 2) recompute(sb, L, cap);
+          if (part != 1) reverse(sb, L, cap);
+        } catch (...) {
+          hipGraph_t partial;
+          if (hipStreamEndCapture(cap, &partial) == hipSuccess) (void)hipGraphDestroy(partial);
+          throw;
+        }
         hipGraph_t graph;
         hip_check(hipStreamEndCapture(cap, &graph), "end capture");
         hipGraphExec_t exec;
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         hip_check(e, "graph instantiate");
-        it = seg_graphs.emplace(L, std::unique_ptr<GraphHolder>(new GraphHolder(exec))).first;
+        it = seg_graphs.emplace(key, std::unique_ptr<GraphHolder>(new GraphHolder(exec))).first;
       }
-      hip_check(hipGraphLaunch(it->second->e, st), "graph launch");
+      return it->second->e;
+    };
+    // With stored stages the recompute of segment c - 1 touches only f.y and
+    // its own segment buffer, and the reverse sweep of segment c only the
+    // adjoint buffers and the other segment buffer: the two run side by side
+    // on two streams (each launch of this small grid leaves most of the chip
+    // idle), alternating between two segment buffers.  HGF_GRAD_OVERLAP=0
+    // runs them one after the other.
+    const char* ov_env = std::getenv("HGF_GRAD_OVERLAP");
+    const bool overlap = store && nseg > 1 && ce <= kGradGraphSteps && !(ov_env && std::string(ov_env) == "0");
+    if (!overlap) {
+      for (int64_t c = nseg - 1; c >= 0; --c) {
+        const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
+        hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+        if (L > kGradGraphSteps) {  // long segments run without a graph
+          recompute(seg, L, st);
+          reverse(seg, L, st);
+          continue;
+        }
+        hip_check(hipGraphLaunch(graph_of(0, L, 0, seg), st), "graph launch");
+      }
+    } else {
+      DBuf segbuf2((size_t)(seg_steps * per_step) * gb);
+      double2* bufs[2] = {seg, segbuf2.as<double2>()};
+      hipStream_t sb = nullptr;
+      hip_check(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking), "stream");
+      StreamGuard sbg{sb};
+      struct Events {
+        hipEvent_t e[5] = {};
+        ~Events() {
+          for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } ev;  // 0, 1: recompute into buffer b done; 2, 3: reverse of buffer b done; 4: start
+      for (hipEvent_t& x : ev.e) hip_check(hipEventCreateWithFlags(&x, hipEventDisableTiming), "event");
+      hip_check(hipEventRecord(ev.e[4], st), "record");
+      hip_check(hipStreamWaitEvent(sb, ev.e[4], 0), "wait");
+      auto len = [&](int64_t c) { return std::min<int64_t>(ce, M - c * ce); };
+      auto launch_recompute = [&](int64_t c) {
+        const int b = (int)(c & 1);
+        if (c + 2 <= nseg - 1) hip_check(hipStreamWaitEvent(sb, ev.e[2 + b], 0), "wait");  // buffer free
+        hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, sb), "restore");
+        hip_check(hipGraphLaunch(graph_of(1, len(c), b, bufs[b]), sb), "graph launch");
+        hip_check(hipEventRecord(ev.e[b], sb), "record");
+      };
+      launch_recompute(nseg - 1);
+      for (int64_t c = nseg - 1; c >= 0; --c) {
+        const int b = (int)(c & 1);
+        hip_check(hipStreamWaitEvent(st, ev.e[b], 0), "wait");
+        hip_check(hipGraphLaunch(graph_of(2, len(c), b, bufs[b]), st), "graph launch");
+        hip_check(hipEventRecord(ev.e[2 + b], st), "record");
+        if (c >= 1) launch_recompute(c - 1);
+      }
+      hip_check(hipStreamSynchronize(sb), "synchronize");
+      hip_check(hipStreamSynchronize(st), "synchronize");
     }
     hip_check(hipStreamSynchronize(st), "synchronize");  // graphs are destroyed with seg_graphs
     // leave the function at its initial state

@@ -432,8 +432,10 @@ def test_gradient_matches_oracle_sensitivities(hgf):
 def test_gradient_stored_and_recomputed_stages_agree(hgf, monkeypatch):
     """The reverse sweep reads each step's stage grids stored by the segment's
     forward recompute, or recomputes them from the step's state
-    (HGF_GRAD_STORE=0): the same kernels on the same operands, so the value
-    and the gradient agree bit for bit."""
+    (HGF_GRAD_STORE=0); with stored stages the recompute of the next segment
+    runs beside the sweep (two segment buffers) unless HGF_GRAD_OVERLAP=0: the
+    same kernels on the same operands, so the value and the gradient agree
+    bit for bit (six segments, the last one shorter)."""
     cutoff = (5, 4, 6)
     announce("gradient stored vs recomputed stages")
     s = synth.random_system(cutoff, 19, scale=2.0, n_th=0.1)
@@ -441,14 +443,16 @@ def test_gradient_stored_and_recomputed_stages_agree(hgf, monkeypatch):
     st = synth.coherent_state([0.6 + 0.2j, 0.9, -0.4j])
     S = hgf.define_system(s)
     out = []
-    for env in (None, "0"):
-        if env is None:
-            monkeypatch.delenv("HGF_GRAD_STORE", raising=False)
-        else:
-            monkeypatch.setenv("HGF_GRAD_STORE", env)
+    for store, overlap in ((None, None), ("0", None), (None, "0")):
+        for name, val in (("HGF_GRAD_STORE", store), ("HGF_GRAD_OVERLAP", overlap)):
+            if val is None:
+                monkeypatch.delenv(name, raising=False)
+            else:
+                monkeypatch.setenv(name, val)
         out.append(hgf.grad(S, st, 0.05, 1e-3, sparse=_sparse_from_dense(cutoff, M), checkpoint_every=9))
-    assert out[0][0] == out[1][0]
-    assert np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert out[0][0] == o[0]
+        assert np.array_equal(out[0][1], o[1])
 
 
 # ----------------------------------------------------------------- kernel variants
