@@ -1,5 +1,5 @@
 // Declarations shared by the host runtime modules (hgf_api.cpp, hgf_functions.cpp,
-// hgf_step.cpp, hgf_autotune.cpp, hgf_readout.cpp, hgf_grad.cpp).
+// hgf_network.cpp, hgf_step.cpp, hgf_autotune.cpp, hgf_readout.cpp, hgf_grad.cpp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,7 +82,7 @@ struct TuneEntry {
 // element set, a real mixed grid with its stage grids, take over 100 GB).
 constexpr int64_t kMaxOperatorPoints = (int64_t)1 << 32;
 
-// ---- hgf_functions.cpp: functions of an operator, tile configuration, network grids
+// ---- hgf_functions.cpp: functions of an operator, tile configuration
 bool stage_kernel_generic();
 bool configure_tiles(GridArgs& g, int precision, bool real, const TileChoice& c);
 std::vector<uint32_t> walk_order(const GridArgs& g);
@@ -99,13 +99,15 @@ void precheck_operator_size(const System& s, const hgf_operator_desc* d);
 void upload_state(Function& f, const std::vector<cd>& grid, int precision);
 double energy(const System& s, const int* k);
 void setup_split(Function& f, const System& s, const Coeff& c);
+void build_functions(hgf_operator_s* op, const hgf_operator_desc* d, bool allow_real = true);
+
+// ---- hgf_network.cpp: network operators on the full (k, l) grid
 std::vector<char> full_tile_records(const GridArgs& g, const FullTables& ft, int& rec_bytes);
 bool configure_full_tiles(Function& f, const FullTables& ft, int precision, const TileChoice& c);
 void drop_full_tiles(Function& f);
 void full_mode_order(const System& s, int* perm);
 System permute_modes(const System& s, const int* perm);
 void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d);
-void build_functions(hgf_operator_s* op, const hgf_operator_desc* d, bool allow_real = true);
 
 // ---- hgf_step.cpp: launch plans, graphs, RK4 stepping, batches
 MemberArgs member_args(const PlanItem& it);
