@@ -1,9 +1,9 @@
 // C-ABI entry points of the library: argument validation, the error state,
 // device memory (hipMalloc or the caller's allocator hook) and the checks
 // shared by the host modules.  The work behind the entry points lives in
-// hgf_functions.cpp and hgf_network.cpp (step (i): operator -> functions), hgf_step.cpp (step
-// (ii): RK4 stepping), hgf_readout.cpp (step (iii)), hgf_autotune.cpp,
-// hgf_grad.cpp and hgf_separated_host.cpp.
+// hgf_functions.cpp and hgf_network.cpp (step (i): operator -> functions),
+// hgf_step.cpp (step (ii): RK4 stepping), hgf_readout.cpp (step (iii)),
+// hgf_autotune.cpp, hgf_grad.cpp and hgf_separated_host.cpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
