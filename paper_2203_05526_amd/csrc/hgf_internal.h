@@ -80,11 +80,21 @@ struct SepDims {
   int64_t dim;                       // prod_j Nc_j
   int64_t stride[kMaxFullModes];     // row-major strides of the box (last mode fastest)
 };
-// One separated operator's launch arguments: dimensions and the device copy
-// of its generator tables.
+// Per point of the N-mode box of a separated operator, precomputed on the
+// host: the occupations (5 bits per mode), sum_j dk_j(k_j),
+// sum_j gamma_phi_j k_j^2 and the energy E(k) with the cross-Kerr products.
+struct SepPoint {
+  uint64_t coords;
+  double dks;
+  double g2;
+  double energy;
+};
+// One separated operator's launch arguments: dimensions, the device copy of
+// its generator tables and its per-point table.
 struct SepLaunch {
   SepDims d;
   const FullTables* ft;
+  const SepPoint* pt;
 };
 
 // Coefficients of the generator restricted to one occupation-difference

@@ -57,28 +57,14 @@ __device__ __forceinline__ uint64_t pack_coords(const HGF_CONST FullTables* ft, 
 }
 __device__ __forceinline__ int coord(uint64_t p, int j) { return (int)((p >> (5 * j)) & 31u); }
 
-__device__ __forceinline__ double energy(const HGF_CONST FullTables* ft, uint64_t p) {
-  double e = 0.0;
-  for (int j = 0; j < ft->n; ++j) {
-    const int kj = coord(p, j);
-    e += ft->e[j][kj];
-    for (int i = 0; i < j; ++i) e += ft->chi[i][j] * (double)(coord(p, i) * kj);
-  }
-  return e;
-}
-
-// one-sided operator (side 0: Kx; 1: Ky) at flat index f of grid `in`
+// one-sided operator (side 0: Kx; 1: Ky) at flat index f of grid `in`; the
+// point's occupations, damping and energy come from the per-point table
 __device__ __forceinline__ double2 side_op(const HGF_CONST FullTables* ft, const SepDims& d, int side,
-                                           const double2* __restrict__ in, int64_t f) {
-  const uint64_t p = pack_coords(ft, f);
+                                           const SepPoint& q, const double2* __restrict__ in, int64_t f) {
+  const uint64_t p = q.coords;
   const double sg = side == 0 ? 1.0 : -1.0;
-  double damp = 0.0;
-  for (int j = 0; j < ft->n; ++j) {
-    const int kj = coord(p, j);
-    damp += ft->dk[j][kj] - ft->gphi[j] * (double)(kj * kj);
-  }
   const double2 c = in[f];
-  double2 r = c_addi(c_scale(damp, c), sg * energy(ft, p), c);
+  double2 r = c_addi(c_scale(q.dks - q.g2, c), sg * q.energy, c);
   for (int j = 0; j < ft->n; ++j) {
     const double orr = ft->drive_re[j], oi = ft->drive_im[j];
     if (orr == 0.0 && oi == 0.0) continue;
@@ -125,7 +111,8 @@ __device__ __forceinline__ void rk4_update(int stage, double h, double2 k, doubl
 
 // ---- Gx and Gy of every monomial: blockIdx.y is the grid (gx_i for i < M,
 // gy_{i - M} otherwise), with its separation constant +C_i or -C_i
-__global__ __launch_bounds__(256) void k_sep_sides(const FullTables* __restrict__ ftg, SepDims d, int stage,
+__global__ __launch_bounds__(256) void k_sep_sides(const FullTables* __restrict__ ftg,
+                                                   const SepPoint* __restrict__ pt, SepDims d, int stage,
                                                    double h, const double2* __restrict__ cst, double2* __restrict__ u,
                                                    double2* __restrict__ acc, const double2* __restrict__ yin,
                                                    double2* __restrict__ yout, int* __restrict__ flag) {
@@ -137,7 +124,7 @@ __global__ __launch_bounds__(256) void k_sep_sides(const FullTables* __restrict_
   int bad = 0;
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < d.dim; f += (int64_t)gridDim.x * blockDim.x) {
     const double2* in = (stage == 1 ? u : yin) + base;
-    double2 k = side_op(ft, d, side, in, f);
+    double2 k = side_op(ft, d, side, pt[f], in, f);
     k = c_add(k, c_mul(cg, in[f]));
     rk4_update(stage, h, k, u + base, acc + base, yout + base, f, bad);
   }
@@ -197,7 +184,8 @@ __global__ __launch_bounds__(256) void k_sep_souter(SepDims d, const double2* __
 // ---- R on the diagonal: derivative (Kx + Ky + P) R + P S restricted to
 // k = l (the drive and exchange shifts leave the diagonal and are dropped;
 // the dephasing terms of Kx + Ky and P cancel on R there)
-__global__ __launch_bounds__(256) void k_sep_rz(const FullTables* __restrict__ ftg, SepDims d, int stage, double h,
+__global__ __launch_bounds__(256) void k_sep_rz(const FullTables* __restrict__ ftg, const SepPoint* __restrict__ pt,
+                                                SepDims d, int stage, double h,
                                                 const double2* __restrict__ src, double2* __restrict__ u,
                                                 double2* __restrict__ acc, const double2* __restrict__ yin,
                                                 double2* __restrict__ yout, int* __restrict__ flag) {
@@ -205,10 +193,8 @@ __global__ __launch_bounds__(256) void k_sep_rz(const FullTables* __restrict__ f
   const double2* in = stage == 1 ? u : yin;
   int bad = 0;
   for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < d.dim; m += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t p = pack_coords(ft, m);
-    double out = 0.0;
-    for (int j = 0; j < ft->n; ++j) out += 2.0 * ft->dk[j][coord(p, j)];
-    double2 k = c_scale(out, in[m]);
+    const uint64_t p = pt[m].coords;
+    double2 k = c_scale(2.0 * pt[m].dks, in[m]);
     for (int j = 0; j < ft->n; ++j) {
       const int mj = coord(p, j), nc = ft->nc[j];
       const int64_t s = d.stride[j];
@@ -225,7 +211,8 @@ __global__ __launch_bounds__(256) void k_sep_rz(const FullTables* __restrict__ f
 }
 
 // ---- R on the whole (k, l) box: the full generator on R plus P on S
-__global__ __launch_bounds__(256) void k_sep_rfull(const FullTables* __restrict__ ftg, SepDims d, int stage,
+__global__ __launch_bounds__(256) void k_sep_rfull(const FullTables* __restrict__ ftg, const SepPoint* __restrict__ pt,
+                                                   SepDims d, int stage,
                                                    double h, const double2* __restrict__ src,
                                                    double2* __restrict__ u, double2* __restrict__ acc,
                                                    const double2* __restrict__ yin, double2* __restrict__ yout,
@@ -236,13 +223,13 @@ __global__ __launch_bounds__(256) void k_sep_rfull(const FullTables* __restrict_
   int bad = 0;
   for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < tot; f += (int64_t)gridDim.x * blockDim.x) {
     const int64_t K = f / D, L = f - K * D;
-    const uint64_t pk = pack_coords(ft, K), pl = pack_coords(ft, L);
+    const uint64_t pk = pt[K].coords, pl = pt[L].coords;
     double dr = 0.0;
     for (int j = 0; j < ft->n; ++j) {
       const int kj = coord(pk, j), lj = coord(pl, j);
       dr += ft->dk[j][kj] + ft->dk[j][lj] - ft->gphi[j] * (double)((kj - lj) * (kj - lj));
     }
-    double2 k = c_addi(c_scale(dr, in[f]), energy(ft, pk) - energy(ft, pl), in[f]);
+    double2 k = c_addi(c_scale(dr, in[f]), pt[K].energy - pt[L].energy, in[f]);
     for (int j = 0; j < ft->n; ++j) {
       const int kj = coord(pk, j), lj = coord(pl, j), nc = ft->nc[j];
       const int64_t s = d.stride[j];
@@ -397,7 +384,7 @@ void launch_sep_ones(int64_t n, const int64_t* idx, double2* x, hipStream_t st) 
 void launch_sep_sides(const SepLaunch& L, int stage, double h, const double2* cst, double2* u, double2* acc,
                       const double2* yin, double2* yout, int* flag, hipStream_t st) {
   const int bx = (int)std::min<int64_t>((L.d.dim + 255) / 256, 64);
-  hipLaunchKernelGGL(k_sep_sides, dim3(bx, 2 * L.d.nmono), dim3(256), 0, st, L.ft, L.d, stage, h, cst, u, acc, yin,
+  hipLaunchKernelGGL(k_sep_sides, dim3(bx, 2 * L.d.nmono), dim3(256), 0, st, L.ft, L.pt, L.d, stage, h, cst, u, acc, yin,
                      yout, flag);
 }
 // monomials per partial sum of the diagonal source (the partial planes stay
@@ -426,9 +413,9 @@ void launch_sep_r(const SepLaunch& L, int rmode, int stage, double h, const doub
   const int64_t tot = rmode == 1 ? L.d.dim : L.d.dim * L.d.dim;
   const int b = (int)std::min<int64_t>((tot + 255) / 256, 4096);
   if (rmode == 1)
-    hipLaunchKernelGGL(k_sep_rz, dim3(b), dim3(256), 0, st, L.ft, L.d, stage, h, src, u, acc, yin, yout, flag);
+    hipLaunchKernelGGL(k_sep_rz, dim3(b), dim3(256), 0, st, L.ft, L.pt, L.d, stage, h, src, u, acc, yin, yout, flag);
   else
-    hipLaunchKernelGGL(k_sep_rfull, dim3(b), dim3(256), 0, st, L.ft, L.d, stage, h, src, u, acc, yin, yout, flag);
+    hipLaunchKernelGGL(k_sep_rfull, dim3(b), dim3(256), 0, st, L.ft, L.pt, L.d, stage, h, src, u, acc, yin, yout, flag);
 }
 int sep_expect_parts(const SepDims& d) { return 2 * d.nmono + 64; }
 void launch_sep_expect(const SepLaunch& L, int rmode, const double2* wt, const double2* coef, const double2* x,

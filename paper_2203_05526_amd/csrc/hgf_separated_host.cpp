@@ -26,6 +26,7 @@ struct SepState {
   void* dft = nullptr;    // FullTables
   void* dcst = nullptr;   // +C_i (x side), then -C_i (y side): 2M complex
   void* dcoef = nullptr;  // g_i: M complex
+  void* dpt = nullptr;    // per-point table of the N-mode box (SepPoint)
   void* x[4] = {};        // u, acc, ya, yb of the 2M grids (each 2M D complex)
   void* r[4] = {};        // u, acc, ya, yb of R (D or D^2 complex)
   void* src = nullptr;    // the source P-operand sum_i g_i Gx_i Gy_i (diagonal or whole box)
@@ -71,6 +72,31 @@ void build_separated(hgf_operator_s* op, const hgf_operator_desc* desc) {
   st->dft = dmalloc(sizeof(FullTables));
   hip_check(hipMemcpy(st->dft, &ft, sizeof(FullTables), hipMemcpyHostToDevice), "upload tables");
   st->L.ft = (const FullTables*)st->dft;
+  // per-point table of the N-mode box: occupations, damping and dephasing
+  // sums, energy (in the order the stencils would form them)
+  {
+    std::vector<SepPoint> pts((size_t)d.dim);
+    std::vector<int> k(s.n, 0);
+    for (int64_t f = 0; f < d.dim; ++f) {
+      int64_t r = f;
+      for (int j = s.n - 1; j >= 0; --j) {
+        k[j] = (int)(r % s.nc[j]);
+        r /= s.nc[j];
+      }
+      SepPoint q{};
+      for (int j = 0; j < s.n; ++j) {
+        q.coords |= (uint64_t)k[j] << (5 * j);
+        q.dks += ft.dk[j][k[j]];
+        q.g2 += ft.gphi[j] * (double)(k[j] * k[j]);
+        q.energy += ft.e[j][k[j]];
+        for (int i = 0; i < j; ++i) q.energy += ft.chi[i][j] * (double)(k[i] * k[j]);
+      }
+      pts[(size_t)f] = q;
+    }
+    st->dpt = dmalloc(pts.size() * sizeof(SepPoint));
+    hip_check(hipMemcpy(st->dpt, pts.data(), pts.size() * sizeof(SepPoint), hipMemcpyHostToDevice), "upload");
+    st->L.pt = (const SepPoint*)st->dpt;
+  }
   // separation constants and coefficients
   auto energy = [&](const std::vector<int>& k) {
     double e = 0.0;
@@ -130,6 +156,7 @@ void free_separated(hgf_operator_s* op) {
   dfree(st->dft);
   dfree(st->dcst);
   dfree(st->dcoef);
+  dfree(st->dpt);
   delete st;
   op->sep = nullptr;
 }
