@@ -112,10 +112,8 @@ void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, h
 // (rmode 1: on the diagonal k = l; 0: on the whole box); readout.
 void launch_sep_sides(const SepLaunch& L, int stage, double h, const double2* cst, double2* u, double2* acc,
                       const double2* yin, double2* yout, int* flag, hipStream_t st);
-// work: sep_source_work(d, rmode) complex elements of device scratch
-int64_t sep_source_work(const SepDims& d, int rmode);
 void launch_sep_source(const SepLaunch& L, int rmode, const double2* coef, const double2* x, double2* s,
-                       double2* work, hipStream_t st);
+                       hipStream_t st);
 void launch_sep_r(const SepLaunch& L, int rmode, int stage, double h, const double2* src, double2* u,
                   double2* acc, const double2* yin, double2* yout, int* flag, hipStream_t st);
 int sep_expect_parts(const SepDims& d);

@@ -133,25 +133,26 @@ __global__ __launch_bounds__(256) void k_sep_sides(const FullTables* __restrict_
 
 // ---- source of the diagonal R: S(m) = sum_i c_i Gx_i(m) Gy_i(m) at the stage
 // inputs (the diagonal of sum_i c_i Gx_i Gy_i).  The grids are small (D
-// points) and the monomials many, so the sum is split over the monomials:
-// block (bx, p) sums monomials [p slice, (p + 1) slice) for 64 points into a
-// partial plane, and a second pass adds the planes in order (deterministic).
-__global__ __launch_bounds__(64) void k_sep_sdiag_part(SepDims d, int slice, const double2* __restrict__ coef,
-                                                       const double2* __restrict__ x, double2* __restrict__ part) {
-  const int64_t m = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (m >= d.dim) return;
-  const int i0 = (int)blockIdx.y * slice, i1 = min(d.nmono, i0 + slice);
+// points) and the monomials many, so a workgroup of 16 wavefronts takes 64
+// points: wavefront w sums monomials w, w + 16, ... in order, and the 16
+// partial sums are added in wavefront order (deterministic).
+constexpr int kSdiagWaves = 16;
+__global__ __launch_bounds__(64 * kSdiagWaves) void k_sep_sdiag(SepDims d, const double2* __restrict__ coef,
+                                                                const double2* __restrict__ x,
+                                                                double2* __restrict__ s) {
+  __shared__ double2 part[kSdiagWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t m = (int64_t)blockIdx.x * 64 + lane;
   double2 a = make_double2(0.0, 0.0);
-  for (int i = i0; i < i1; ++i)
-    a = c_add(a, c_mul(coef[i], c_mul(x[(int64_t)i * d.dim + m], x[(int64_t)(d.nmono + i) * d.dim + m])));
-  part[(int64_t)blockIdx.y * d.dim + m] = a;
-}
-__global__ __launch_bounds__(256) void k_sep_sdiag_sum(SepDims d, int np, const double2* __restrict__ part,
-                                                       double2* __restrict__ s) {
-  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < d.dim; m += (int64_t)gridDim.x * blockDim.x) {
-    double2 a = make_double2(0.0, 0.0);
-    for (int p = 0; p < np; ++p) a = c_add(a, part[(int64_t)p * d.dim + m]);
-    s[m] = a;
+  if (m < d.dim)
+    for (int i = w; i < d.nmono; i += kSdiagWaves)
+      a = c_add(a, c_mul(coef[i], c_mul(x[(int64_t)i * d.dim + m], x[(int64_t)(d.nmono + i) * d.dim + m])));
+  part[w][lane] = a;
+  __syncthreads();
+  if (w == 0 && m < d.dim) {
+    double2 t = part[0][lane];
+    for (int q = 1; q < kSdiagWaves; ++q) t = c_add(t, part[q][lane]);
+    s[m] = t;
   }
 }
 
@@ -387,22 +388,11 @@ void launch_sep_sides(const SepLaunch& L, int stage, double h, const double2* cs
   hipLaunchKernelGGL(k_sep_sides, dim3(bx, 2 * L.d.nmono), dim3(256), 0, st, L.ft, L.pt, L.d, stage, h, cst, u, acc, yin,
                      yout, flag);
 }
-// monomials per partial sum of the diagonal source (the partial planes stay
-// within the 65535 blocks of gridDim.y)
-static int sdiag_slice(const SepDims& d) { return std::max(16, (d.nmono + 65534) / 65535); }
-int64_t sep_source_work(const SepDims& d, int rmode) {
-  if (rmode != 1 || d.nmono == 0) return 0;
-  const int slice = sdiag_slice(d);
-  return (int64_t)((d.nmono + slice - 1) / slice) * d.dim;
-}
 void launch_sep_source(const SepLaunch& L, int rmode, const double2* coef, const double2* x, double2* s,
-                       double2* work, hipStream_t st) {
+                       hipStream_t st) {
   if (rmode == 1) {
-    const int slice = sdiag_slice(L.d), np = (L.d.nmono + slice - 1) / slice;
-    hipLaunchKernelGGL(k_sep_sdiag_part, dim3((unsigned)((L.d.dim + 63) / 64), np), dim3(64), 0, st, L.d, slice,
-                       coef, x, work);
-    const int b = (int)std::min<int64_t>((L.d.dim + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_sep_sdiag_sum, dim3(b), dim3(256), 0, st, L.d, np, (const double2*)work, s);
+    hipLaunchKernelGGL(k_sep_sdiag, dim3((unsigned)((L.d.dim + 63) / 64)), dim3(64 * kSdiagWaves), 0, st, L.d, coef,
+                       x, s);
   } else {
     const int nb = (int)((L.d.dim + 15) / 16);
     hipLaunchKernelGGL(k_sep_souter, dim3(nb, nb), dim3(256), 0, st, L.d, coef, x, s);

@@ -30,7 +30,6 @@ struct SepState {
   void* x[4] = {};        // u, acc, ya, yb of the 2M grids (each 2M D complex)
   void* r[4] = {};        // u, acc, ya, yb of R (D or D^2 complex)
   void* src = nullptr;    // the source P-operand sum_i g_i Gx_i Gy_i (diagonal or whole box)
-  void* swork = nullptr;  // partial sums of the diagonal source
   void* xbak = nullptr;   // state copies for recovery after a non-finite result
   void* rbak = nullptr;
   double bound = 0.0;
@@ -129,8 +128,6 @@ void build_separated(hgf_operator_s* op, const hgf_operator_desc* desc) {
     st->r[b] = dmalloc(rb);
   }
   st->src = dmalloc(rb);
-  const int64_t sw = sep_source_work(d, st->rmode);
-  if (sw > 0) st->swork = dmalloc((size_t)sw * sizeof(double2));
   hip_check(hipMemset(st->x[0], 0, xb), "clear");
   hip_check(hipMemset(st->r[0], 0, rb), "clear");
   if (!ones.empty()) {
@@ -150,7 +147,6 @@ void free_separated(hgf_operator_s* op) {
     dfree(st->r[b]);
   }
   dfree(st->src);
-  dfree(st->swork);
   dfree(st->xbak);
   dfree(st->rbak);
   dfree(st->dft);
@@ -197,7 +193,7 @@ void separated_evolve(hgf_operator_s* op, int64_t steps, double h, hipStream_t s
   for (int64_t k = 0; k < steps; ++k)
     for (int s = 1; s <= 4; ++s) {
       if (d.nmono > 0) launch_sep_source(st->L, st->rmode, (const double2*)st->dcoef, X[in_of[s]], (double2*)st->src,
-                                          (double2*)st->swork, strm);
+                                          strm);
       else hip_check(hipMemsetAsync(st->src, 0, rb, strm), "clear");
       launch_sep_r(st->L, st->rmode, s, h, (const double2*)st->src, R[0], R[1], R[in_of[s]], R[out_of[s]], op->dflag,
                    strm);
