@@ -239,47 +239,56 @@ static bool graph_branches() {
   return !(env && std::string(env) == "0");
 }
 
-// `chunk` steps of the plan as one graph.  The grouped launches are
-// independent of each other (different functions), so with several groups
-// each group's chain of stages is captured on its own branch (forked from and
-// joined back to `cap`): a group too small to fill the chip then runs beside
-// the others instead of after them.  Within a branch the stages keep their
-// order; results do not depend on the branching.
+// `chunk` steps of the plan as one graph.  The plan's chains of launches
+// (each grouped launch, each function on the untiled kernels) are
+// independent of each other (different functions), so with several chains
+// they are spread over up to kGraphBranches branches of the graph (forked
+// from and joined back to `cap`; chain c on branch c mod branches): a chain
+// too small to fill the chip then runs beside the others instead of after
+// them.  Within a branch the stages keep their order; results do not depend
+// on the branching.
+constexpr size_t kGraphBranches = 8;
 hipGraphExec_t capture_steps(const StepPlan& plan, int* flag, int chunk, hipStream_t cap) {
   hipGraph_t graph;
-  const size_t ng = plan.groups.size();
-  const bool fork = ng > 1 && graph_branches();
-  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[g]: join of group g's branch
+  const size_t ng = plan.groups.size(), nchain = ng + plan.generic.size();
+  const size_t nb = graph_branches() ? std::min(nchain, kGraphBranches) : 1;
+  auto launch_chain = [&](size_t c, int stage, hipStream_t s) {
+    if (c < ng)
+      launch_group(plan.groups[c], stage, flag, s);
+    else
+      generic_stage(plan.generic[c - ng], stage, flag, s);
+  };
+  auto branch_steps = [&](size_t b, hipStream_t s) {
+    for (int k = 0; k < chunk; ++k)
+      for (int stage = 1; stage <= 4; ++stage)
+        for (size_t c = b; c < nchain; c += nb) launch_chain(c, stage, s);
+  };
+  std::vector<hipEvent_t> ev;  // ev[0]: fork; ev[b]: join of branch b
   auto drop_events = [&] {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     ev.clear();
   };
   int dev = 0;
-  if (fork) hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (nb > 1) hip_check(hipGetDevice(&dev), "hipGetDevice");
   hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
   try {
-    if (!fork) {
-      for (int s = 0; s < chunk; ++s) run_plan_step(plan, flag, cap);
+    if (nb <= 1) {
+      for (int k = 0; k < chunk; ++k) run_plan_step(plan, flag, cap);
     } else {
-      for (size_t g = 0; g < ng; ++g) {
+      for (size_t b = 0; b < nb; ++b) {
         hipEvent_t e;
         hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
         ev.push_back(e);
       }
       hip_check(hipEventRecord(ev[0], cap), "fork");
-      for (size_t g = 1; g < ng; ++g) {
-        hipStream_t b = branch_stream(dev, g - 1);
-        hip_check(hipStreamWaitEvent(b, ev[0], 0), "fork");
-        for (int s = 0; s < chunk; ++s)
-          for (int stage = 1; stage <= 4; ++stage) launch_group(plan.groups[g], stage, flag, b);
-        hip_check(hipEventRecord(ev[g], b), "join");
+      for (size_t b = 1; b < nb; ++b) {
+        hipStream_t bs = branch_stream(dev, b - 1);
+        hip_check(hipStreamWaitEvent(bs, ev[0], 0), "fork");
+        branch_steps(b, bs);
+        hip_check(hipEventRecord(ev[b], bs), "join");
       }
-      for (int s = 0; s < chunk; ++s)
-        for (int stage = 1; stage <= 4; ++stage) {
-          launch_group(plan.groups[0], stage, flag, cap);
-          for (const PlanItem& it : plan.generic) generic_stage(it, stage, flag, cap);
-        }
-      for (size_t g = 1; g < ng; ++g) hip_check(hipStreamWaitEvent(cap, ev[g], 0), "join");
+      branch_steps(0, cap);
+      for (size_t b = 1; b < nb; ++b) hip_check(hipStreamWaitEvent(cap, ev[b], 0), "join");
     }
   } catch (...) {
     hipGraph_t partial;
