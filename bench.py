@@ -302,7 +302,8 @@ def network_timing(hgf, torch, five_only: bool = False):
         el = timed(op, w)
         rec = {"modes": n, "cutoff": 6, "grid_points": pts, "steps": w.n_steps, "seconds": el,
                "value": pts * 4 * w.n_steps / el, "unit": "point-stage updates/s",
-               "kernel": "tiled" if op.tile_config(0)["nfast"] else "untiled"}
+               "kernel": ("tiled" if op.tile_config(0)["nfast"] else
+                          "resident" if op.tile_config(0)["resident"] else "untiled")}
         if n <= 4:
             wr = synth.table1_network(n, 7)
             ref = hgf.map_operator(hgf.define_system(wr.system), factors=wr.factors, precision="fp64")

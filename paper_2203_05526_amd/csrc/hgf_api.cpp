@@ -461,7 +461,7 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
     info->real_functions = nreal;
     int untiled = 0;
     if (op->layout == HGF_MERGED)
-      for (auto& f : op->fn) untiled += (f.full ? f.ga.fblocks == 0 : (f.ga.blocks == 0 && !f.resident)) ? 1 : 0;
+      for (auto& f : op->fn) untiled += ((f.full ? f.ga.fblocks == 0 : f.ga.blocks == 0) && !f.resident) ? 1 : 0;
     info->untiled_functions = untiled;
     info->reserved = 0;
     info->stored_peak = -1;
@@ -488,7 +488,8 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
       const bool ft = f.ga.fblocks > 0;
       *out = hgf_tile_config{};
       out->nfast = ft ? 4 : 0;
-      out->threads = ft ? f.ga.fthreads : 0;
+      out->threads = ft ? f.ga.fthreads : f.resident ? f.res_threads : 0;
+      out->resident = f.resident ? 1 : 0;
       out->wgs_per_cu = ft ? f.ga.fwgs : 0;
       out->walk_block = ft ? f.ga.fwblock : 0;
       out->blocks = ft ? f.ga.fblocks : 0;
@@ -527,13 +528,23 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
     hip_check(hipDeviceSynchronize(), "synchronize");  // no launch may still read the old records
     Function& f = op->fn[idx];
     if (f.full) {
-      if (cfg->xblock != 0 || cfg->pipe != 0 || cfg->resident != 0 || (cfg->nfast != 0 && cfg->nfast != 4))
-        fail(HGF_EINVAL, "a network operator takes nfast 0 (untiled) or 4 (tiles of its last two modes), "
-                         "without xblock, pipe or the resident form");
+      if (cfg->xblock != 0 || cfg->pipe != 0 || (cfg->nfast != 0 && cfg->nfast != 4) ||
+          (cfg->resident && cfg->nfast != 0))
+        fail(HGF_EINVAL, "a network operator takes nfast 0 (untiled, or with resident 1 the resident form) or 4 "
+                         "(tiles of its last two modes), without xblock or pipe");
+      if (cfg->resident) {
+        Function probe;
+        probe.full = true;
+        probe.ga = f.ga;
+        if (!full_resident_eligible(probe, op->precision))
+          fail(HGF_EINVAL, "the resident form of a network operator needs its grid twice within 64 KB of LDS "
+                           "and at most three modes");
+      }
       if (cfg->nfast == 0)
         drop_full_tiles(f);
       else if (!configure_full_tiles(f, f.fhost.at(0), op->precision, c))
         fail(HGF_EINVAL, "tile configuration not feasible for this network grid");
+      f.resident = cfg->resident && full_resident_eligible(f, op->precision);
       drop_plan(op);
       return;
     }

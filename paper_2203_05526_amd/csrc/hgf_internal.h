@@ -238,6 +238,7 @@ struct ResidentItem {
   GridArgs g;
   void* y;   // state
   void* yf;  // stage-precision copy of y (mixed) or NULL
+  void* x1;  // network operators: X1 of the current step (the function's stage grid)
   int steps;
   double h;
 };
@@ -247,8 +248,9 @@ struct ResidentItem {
 struct ResidentLaunch {
   const ResidentItem* items;  // device array
   int count;
-  int nfast, threads, lds_bytes;
+  int nfast, threads, lds_bytes;  // network operators (full = 1): nfast is the number of modes
   int real, precision;
+  int full;
 };
 
 // One grouped launch: members sharing the axis split and element types.

@@ -528,6 +528,96 @@ static void full_launch_n(int stage, int precision, const GridArgs& g, const Str
                        (const float2*)x1, (double2*)y, (float2*)yf, (float2*)out, h, flag);
 }
 
+// ------------------------------------------------------------ resident network operators
+// A network operator whose whole (k, l) grid fits twice in one workgroup's LDS
+// is integrated for all the steps of a call in one launch, one workgroup per
+// function: the stencil input of the current stage lives in LDS (two copies
+// used in turn, one barrier per stage), the stencil is the untiled kernel's
+// (apply_L_full on the LDS copy) with the same Horner arithmetic, and the
+// state y and X1 stay in the function's own buffers (a few tens of KB, held
+// in cache).  Each lane owns the points tid, tid + blockDim, ... in every
+// stage, so its reads of y and X1 follow its own writes.
+template <int N, typename TS, typename RS>
+__global__ __launch_bounds__(1024) void k_full_resident(const ResidentItem* __restrict__ items,
+                                                      int* __restrict__ flag) {
+  using CT = typename C2<RS>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ResidentItem& it = items[blockIdx.x];
+  const GridArgs& g = it.g;
+  const int T = (int)g.points;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  TS* buf0 = (TS*)smem;
+  TS* buf1 = buf0 + T;
+  double2* __restrict__ y = (double2*)it.y;
+  TS* __restrict__ x1 = (TS*)it.x1;
+  const double h = it.h;
+  for (int p = tid; p < T; p += nt) buf0[p] = from_d2<TS>(y[p]);
+  const TS* cur = buf0;
+  TS* nxt = buf1;
+  int bad = 0;
+  for (int s = 0; s < it.steps; ++s) {
+#pragma unroll 1
+    for (int stage = 1; stage <= 4; ++stage) {
+      __syncthreads();  // `cur` holds this stage's stencil input
+      for (int p = tid; p < T; p += nt) {
+        Walker w;
+        w.i = p;
+        int rem = p;
+#pragma unroll
+        for (int j = 2 * N - 1; j >= 0; --j) {
+          const int e = g.ext[j];
+          w.c[j] = rem % e;
+          rem /= e;
+        }
+        const CT lv = apply_L_full<N, RS>(g, cur, w);
+        if (stage == 1) {
+          const TS xv = from_d2<TS>(make_double2(h * (double)lv.x, h * (double)lv.y));
+          x1[p] = xv;
+          nxt[p] = xv;
+        } else if (stage == 2 || stage == 3) {
+          const double c = (stage == 2) ? 0.25 * h : h / 3.0;
+          const double2 base = to_d2(x1[p]);
+          nxt[p] = from_d2<TS>(make_double2(base.x + c * (double)lv.x, base.y + c * (double)lv.y));
+        } else {
+          const double c = 0.5 * h;
+          const double2 base = to_d2(x1[p]);
+          double2 yv = y[p];
+          yv.x += base.x + c * (double)lv.x;
+          yv.y += base.y + c * (double)lv.y;
+          bad |= !(isfinite(yv.x) && isfinite(yv.y));
+          y[p] = yv;
+          nxt[p] = from_d2<TS>(yv);
+        }
+      }
+      const TS* t = cur;
+      cur = nxt;
+      nxt = const_cast<TS*>(t);
+    }
+  }
+  // the stage-precision copy of y (mixed): `cur` holds it after the last step
+  TS* __restrict__ yf = (TS*)it.yf;
+  if (yf && it.steps > 0)
+    for (int p = tid; p < T; p += nt) yf[p] = cur[p];
+  if (bad) atomicOr(flag, 1);
+}
+
+template <int N>
+static void full_resident_n(const ResidentLaunch& rl, int* flag, hipStream_t st) {
+  dim3 gr(rl.count), bl(rl.threads);
+  if (rl.precision == HGF_FP64)
+    hipLaunchKernelGGL((k_full_resident<N, double2, double>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+  else
+    hipLaunchKernelGGL((k_full_resident<N, float2, float>), gr, bl, rl.lds_bytes, st, rl.items, flag);
+}
+
+static void launch_full_resident(const ResidentLaunch& rl, int* flag, hipStream_t st) {
+  switch (rl.nfast) {
+    case 1: full_resident_n<1>(rl, flag, st); break;
+    case 2: full_resident_n<2>(rl, flag, st); break;
+    default: full_resident_n<3>(rl, flag, st); break;
+  }
+}
+
 // ------------------------------------------------------------ thresholded representation
 // Coefficients with |g| <= thr are set to zero (the truncated representation
 // of the operator); the survivors are counted into *count.
@@ -978,6 +1068,10 @@ void launch_resident_r64(const ResidentLaunch&, int*, hipStream_t);
 int resident_max_points() { return 4 * 1024; }
 
 void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st) {
+  if (rl.full) {
+    launch_full_resident(rl, flag, st);
+    return;
+  }
   if (rl.real)
     (rl.precision == HGF_FP64 ? launch_resident_r64 : launch_resident_r32)(rl, flag, st);
   else

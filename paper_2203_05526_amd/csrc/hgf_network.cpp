@@ -399,8 +399,23 @@ void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d) {
   hip_check(hipMemcpy(f.ftab, &ft, sizeof(FullTables), hipMemcpyHostToDevice), "upload tables");
   fill_grid_args(f, op->precision, false);
   if (!stage_kernel_generic()) configure_full_tiles(f, ft, op->precision, TileChoice{});
+  // small untiled grids: the resident integrator (HGF_RESIDENT=0 turns it off)
+  const char* env = std::getenv("HGF_RESIDENT");
+  if (!stage_kernel_generic() && f.ga.fblocks == 0 && !(env && std::string(env) == "0"))
+    f.resident = full_resident_eligible(f, op->precision);
   alloc_function_buffers(f, op->precision);
   upload_state(f, grid, op->precision);
+}
+
+// A network operator runs on the resident integrator when its whole grid fits
+// twice in 64 KB of LDS (in the stage precision) and it has at most three
+// modes (the kernel's instantiations).
+bool full_resident_eligible(Function& f, int precision) {
+  const int64_t T = f.ga.points, ts = precision == HGF_FP64 ? 16 : 8;
+  if (!f.full || f.ga.n / 2 > 3 || 2 * T * ts > 65536) return false;
+  f.res_lds_bytes = (int)(2 * T * ts);
+  f.res_threads = (int)std::min<int64_t>(1024, (T + 63) / 64 * 64);
+  return true;
 }
 
 }  // namespace hgf

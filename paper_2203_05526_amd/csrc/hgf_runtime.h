@@ -108,6 +108,7 @@ void drop_full_tiles(Function& f);
 void full_mode_order(const System& s, int* perm);
 System permute_modes(const System& s, const int* perm);
 void build_full_function(hgf_operator_s* op, const hgf_operator_desc* d);
+bool full_resident_eligible(Function& f, int precision);
 
 // ---- hgf_step.cpp: launch plans, graphs, RK4 stepping, batches
 MemberArgs member_args(const PlanItem& it);

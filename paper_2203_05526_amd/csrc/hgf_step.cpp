@@ -61,7 +61,7 @@ StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resident) {
   for (const PlanItem& it : items) {
     const GridArgs& g = it.f->ga;
     if (allow_resident && it.f->resident)
-      res_key[{g.nfast, g.real, it.precision}].push_back(it);
+      res_key[{it.f->full ? g.n / 2 : g.nfast, g.real, it.precision, it.f->full ? 1 : 0}].push_back(it);
     else if (g.blocks > 0)
       by_key[{g.nfast, g.n - g.nfast, g.real, it.precision}].push_back(it);
     else
@@ -107,12 +107,14 @@ StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resident) {
     rl.nfast = kv.first[0];
     rl.real = kv.first[1];
     rl.precision = kv.first[2];
+    rl.full = kv.first[3];
     std::vector<ResidentItem> host;
     for (const PlanItem& it : kv.second) {
       ResidentItem ri{};
       ri.g = it.f->ga;
       ri.y = it.f->y;
       ri.yf = it.precision == HGF_MIXED ? it.f->yf : nullptr;
+      ri.x1 = it.f->s1;
       ri.steps = 0;
       ri.h = it.h;
       host.push_back(ri);
@@ -508,6 +510,7 @@ void evolve_impl(hgf_operator_s* op, int64_t steps, double h, hipStream_t st, in
     // one step at a time, the representation truncated after each
     ensure_plan(op, h);
     for (int64_t k = 0; k < steps; ++k) {
+      run_resident(*op->plan, 1, op->dflag, st);
       run_plan_step(*op->plan, op->dflag, st);
       apply_threshold(op, st);
     }
