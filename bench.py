@@ -362,7 +362,9 @@ def network_storage(hgf, torch, max_modes: int = 4):
     grid of a monomial in the separated form); the wall time.
     The separated form with R on the whole box (exact) is also run untruncated
     up to three modes, and the separated form at cutoff 5 (untruncated, and
-    thresholded where its untruncated error meets the target)."""
+    thresholded where its untruncated error meets the target).  For one and
+    two modes also the running peak against the simulated time (the paper's
+    figure of stored elements against w_q t / pi)."""
     import synth
 
     def run(w, layout, thr):
@@ -427,6 +429,21 @@ def network_storage(hgf, torch, max_modes: int = 4):
         del op
         rec["separated_cutoff5"] = {"eps_r_untruncated": e5, "dense_points": info["total_points"], "seconds": el,
                                     "truncated": sweep(w5, "separated") if e5 <= target else None}
+        if n <= 2:  # the running peak against the simulated time (w_q t / pi = 1 .. 10), at the chosen thresholds
+            rec["peak_vs_time"] = {}
+            for name, layout in (("conventional", "merged"), ("separated", "separated")):
+                best = rec[name]["truncated"]
+                if best is None:
+                    continue
+                op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="fp64",
+                                      layout=layout)
+                hgf.set_threshold(op, best["threshold"])
+                peaks = []
+                for _ in range(10):
+                    hgf.evolve(op, w.t_total / 10, w.dt)
+                    peaks.append(op.info()["stored_peak"])
+                rec["peak_vs_time"][name] = {"wq_t_over_pi": list(range(1, 11)), "stored_peak": peaks}
+                del op
         out.append(rec)
         log(f"network storage {n} modes: conventional {rec['conventional']['truncated']}, "
             f"separated {rec['separated']['truncated']}, separated at cutoff 5 {rec['separated_cutoff5']}")
