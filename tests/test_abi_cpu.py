@@ -87,6 +87,13 @@ def test_null_arguments_are_rejected(hgf):
     assert lib.hgf_autotune(None, 1, 1e-3, None, 0, None) == -1
     assert lib.hgf_reconstruct(None, 3, None, None) == -1
     assert b"NULL" in lib.hgf_last_error()
+    assert lib.hgf_set_threshold(None, 1e-6) == -1
+    assert lib.hgf_get_info(None, None) == -1
+    two = (ctypes.c_double * 2)()
+    assert lib.hgf_expectation_noalloc(None, None, two, None) == -1
+    assert lib.hgf_expectation(None, None, two, None) == -1
+    assert lib.hgf_evolve_batch(None, 1, None, None, None) == -1
+    assert b"bad batch arguments" in lib.hgf_last_error()
 
 
 def test_allocator_hook_arguments(hgf):
