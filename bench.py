@@ -573,6 +573,9 @@ def main():
     bytes_launch = bytes_per_point_stage(args.precision, real) * pts
     achieved = bytes_launch / launch_s / 1e9
     traffic = stored_traffic(tune, real, args.precision)
+    # the same operands streamed once per point with no neighbour reads
+    ceil_us = hgf.stream_ceiling(args.precision, real, pts, 10)
+    ceil_s = sum(ceil_us) / 4 * 1e-6
     line = {
         "metric": METRIC,
         "value": value,
@@ -596,7 +599,12 @@ def main():
                      "kernel": STAGE_KERNEL, "avg_launch_us": launch_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      # the counted HBM bytes per launch over the launch time
-                     "traffic_GBps": None if traffic is None else traffic / launch_s / 1e9},
+                     "traffic_GBps": None if traffic is None else traffic / launch_s / 1e9,
+                     # streaming ceiling: the stage operands read and written once per point
+                     # (hgf_stream_ceiling), per stage and averaged; the kernel's time over it
+                     "stream_ceiling": {"us_per_stage": ceil_us, "avg_launch_us": ceil_s * 1e6,
+                                        "GBps": bytes_launch / ceil_s / 1e9,
+                                        "kernel_time_over_ceiling": launch_s / ceil_s}},
         "expectation": [J.real, J.imag],
     }
     if not args.no_extras:

@@ -450,6 +450,21 @@ typedef void* (*hgf_alloc_fn)(size_t bytes, int32_t device, void* user);
 typedef void (*hgf_free_fn)(void* ptr, int32_t device, void* user);
 hgf_status hgf_set_allocator(hgf_alloc_fn alloc, hgf_free_fn free_fn, void* user);
 
+/*
+ * Measurement helper (no part of the method): the streaming ceiling of the RK4
+ * stage kernel.  On `points` points of fresh buffers, each Horner stage's
+ * operands (the stencil input at the point itself, X1, the state y, the stage
+ * output, the stage-precision copy of y) are read and written once per point
+ * with the stage kernel's access policies and no neighbour reads; us_out[4]
+ * receives the average microseconds per launch of stages 1..4 over `reps`
+ * launches each.  precision: HGF_FP64 or HGF_MIXED; real: 1 for real grids.
+ * Allocates and frees its buffers (about 6 x points x 16 bytes at most).
+ * Errors: HGF_EINVAL (points or reps < 1, buffers beyond 2^32 bytes),
+ * HGF_ENOMEM, HGF_EDEVICE.  Synchronises hip_stream.
+ */
+hgf_status hgf_stream_ceiling(int32_t precision, int32_t real, int64_t points, int32_t reps, double us_out[4],
+                              void* hip_stream);
+
 /* Thread-local message describing the last error of this thread ("" if none). */
 const char* hgf_last_error(void);
 

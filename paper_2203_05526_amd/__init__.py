@@ -18,6 +18,7 @@ from .hgf import (  # noqa: F401
     expectation_noalloc,
     reconstruct,
     set_threshold,
+    stream_ceiling,
     grad,
     load_library,
     map_operator,

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libhgf.so")
 ARCH = os.environ.get("HGF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["hgf_kernels.hip", "hgf_full_tiled.hip", "hgf_tiled_c64.hip", "hgf_tiled_c128.hip", "hgf_tiled_r32.hip",
-           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_separated.hip", "hgf_api.cpp", "hgf_functions.cpp", "hgf_network.cpp",
+           "hgf_tiled_r64.hip", "hgf_scratch.hip", "hgf_stream.hip", "hgf_separated.hip", "hgf_api.cpp", "hgf_functions.cpp", "hgf_network.cpp",
            "hgf_step.cpp", "hgf_autotune.cpp", "hgf_readout.cpp", "hgf_grad.cpp", "hgf_separated_host.cpp",
            "hgf_tables.cpp"]
 

@@ -479,6 +479,15 @@ hgf_status hgf_get_info(hgf_operator op, hgf_operator_info* info) {
   });
 }
 
+hgf_status hgf_stream_ceiling(int32_t precision, int32_t real, int64_t points, int32_t reps, double us_out[4],
+                              void* hip_stream) {
+  return guarded([&] {
+    if (!us_out) fail(HGF_EINVAL, "NULL argument");
+    if (precision != HGF_FP64 && precision != HGF_MIXED) fail(HGF_EINVAL, "unknown precision");
+    stream_ceiling(precision, real != 0, points, reps, us_out, (hipStream_t)hip_stream);
+  });
+}
+
 hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* out) {
   return guarded([&] {
     if (!op || !out) fail(HGF_EINVAL, "NULL argument");

@@ -59,6 +59,10 @@ std::vector<std::vector<cd>> all_amps(const System& s, const hgf_state_desc* psi
 void reset_flag(hgf_operator_s* op, hipStream_t st);
 int read_flag(hgf_operator_s* op, hipStream_t st);
 
+// streaming ceiling of the stage kernel's operand mix (hgf_stream.hip):
+// microseconds per launch of each of the four Horner stages into us[4]
+void stream_ceiling(int precision, bool real, int64_t points, int reps, double* us, hipStream_t st);
+
 // ---- separated layout (Eqs. (9a)-(9c)), hgf_separated_host.cpp
 struct SepState;
 void build_separated(hgf_operator_s* op, const hgf_operator_desc* d);

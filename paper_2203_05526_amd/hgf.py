@@ -27,7 +27,7 @@ STATUS = {0: "HGF_OK", -1: "HGF_EINVAL", -2: "HGF_ENOMEM", -3: "HGF_EDEVICE", -4
 
 EXPORTED = ["hgf_define_system", "hgf_destroy_system", "hgf_num_params", "hgf_map_operator",
             "hgf_destroy_operator", "hgf_evolve", "hgf_evolve_batch", "hgf_expectation", "hgf_expectation_noalloc",
-            "hgf_reconstruct", "hgf_grad", "hgf_set_threshold",
+            "hgf_reconstruct", "hgf_grad", "hgf_set_threshold", "hgf_stream_ceiling",
             "hgf_get_info", "hgf_get_function", "hgf_last_error", "hgf_version"]
 
 
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH):
     lib.hgf_last_error.argtypes = []
     lib.hgf_version.restype = ctypes.c_char_p
     lib.hgf_version.argtypes = []
+    lib.hgf_stream_ceiling.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_double), vp]
     for name in EXPORTED:
         if not hasattr(lib, name):
             raise RuntimeError(f"libhgf.so does not export {name}")
@@ -481,6 +483,16 @@ def grad(system: System, state, t_total: float, dt: float, factors=None, sparse=
 
 def version() -> str:
     return load_library().hgf_version().decode()
+
+
+def stream_ceiling(precision: str, real: bool, points: int, reps: int = 10, stream=None) -> List[float]:
+    """hgf_stream_ceiling: microseconds per launch of each Horner stage when its
+    operands are streamed once per point with no neighbour reads (the stage
+    kernel's streaming ceiling; a measurement helper)."""
+    us = (ctypes.c_double * 4)()
+    _check(_lib.hgf_stream_ceiling(_PREC[precision], 1 if real else 0, int(points), int(reps), us,
+                                   _stream(stream)))
+    return [us[i] for i in range(4)]
 
 
 def param_names(n: int) -> List[str]:

@@ -304,3 +304,16 @@ def test_untiled_functions_reported(hgf, monkeypatch):
     op2 = hgf.map_operator(S, factors=fac, precision="fp64")
     i2 = op2.info()
     assert i2["untiled_functions"] == i2["n_functions"] > 0
+
+
+def test_stream_ceiling_helper(hgf):
+    """The streaming-ceiling helper times the four stages on fresh buffers and
+    refuses empty or over-large sizes."""
+    announce("stream ceiling helper")
+    us = hgf.stream_ceiling("mixed", True, 1 << 20, 3)
+    assert len(us) == 4 and all(u > 0 for u in us)
+    assert us[3] >= us[0] * 0.8  # stage 4 moves the most bytes
+    for args in (("fp64", False, 0, 3), ("mixed", True, 1 << 20, 0), ("fp64", False, 1 << 29, 1)):
+        with pytest.raises(hgf.HgfError) as e:
+            hgf.stream_ceiling(*args)
+        assert e.value.status == "HGF_EINVAL"
