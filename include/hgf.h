@@ -458,7 +458,7 @@ hgf_status hgf_set_allocator(hgf_alloc_fn alloc, hgf_free_fn free_fn, void* user
  * with the stage kernel's access policies and no neighbour reads; us_out[4]
  * receives the average microseconds per launch of stages 1..4 over `reps`
  * launches each.  precision: HGF_FP64 or HGF_MIXED; real: 1 for real grids.
- * Allocates and frees its buffers (about 6 x points x 16 bytes at most).
+ * Allocates and frees its buffers (5 x points x 16 bytes at most).
  * Errors: HGF_EINVAL (points or reps < 1, buffers beyond 2^32 bytes),
  * HGF_ENOMEM, HGF_EDEVICE.  Synchronises hip_stream.
  */
