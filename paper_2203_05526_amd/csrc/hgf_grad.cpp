@@ -48,10 +48,11 @@ SectorTables transposed_tables(const SectorTables& t) {
 // Longest reverse segment captured as one graph (about 10 nodes per step).
 constexpr int64_t kGradGraphSteps = 512;
 // A segment keeps every step's stage grids X1, V1, V2 next to its state when
-// they fit in this many bytes (the reverse sweep then recomputes nothing);
-// otherwise, or with HGF_GRAD_STORE=0 in the environment, it keeps the states
-// only and recomputes the three stages of each step in the sweep (the same
-// numbers either way).
+// they fit in this many bytes (the reverse sweep then recomputes nothing, and
+// keeps each step's adjoint grids, as many bytes again, for the segment's
+// parameter products); otherwise, or with HGF_GRAD_STORE=0 in the
+// environment, it keeps the states only and recomputes the three stages of
+// each step in the sweep (the same numbers either way).
 constexpr int64_t kGradStoreBytes = (int64_t)2 << 30;
 
 void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
@@ -99,8 +100,12 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     const char* store_env = std::getenv("HGF_GRAD_STORE");  // "0": keep states only
     const bool store = 4 * seg_steps * (int64_t)gb <= kGradStoreBytes && !(store_env && std::string(store_env) == "0");
     const int64_t per_step = store ? 4 : 1;  // grids kept per step: y (and X1, V1, V2)
-    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)(seg_steps * per_step) * gb), mu(gb), vb2(gb), vb1(gb),
-        xb1(gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
+    // adjoint grids: mu, and a set of Vb2, Vb1, Xb1 and a copy of mu per
+    // step of a segment (with stored stages: the parameter products then run
+    // once per segment) or one set
+    const int64_t adj_sets = store ? seg_steps : 1;
+    DBuf ckpt((size_t)(nseg + 1) * gb), segbuf((size_t)(seg_steps * per_step) * gb), mu(gb),
+        adj((size_t)(4 * adj_sets) * gb), Q((size_t)(1 + 2 * sys.n) * gb), wt(gb);
     // the adjoint stencils run on the forward stage kernels of L^T
     Function fa;
     struct FreeOnExit {
@@ -178,6 +183,10 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
         if (i + 1 < L) stage_launch(f, HGF_FP64, 4, v2_, x1_, f.y, nullptr, nullptr, dt, op.dflag, s);
       }
     };
+    // With stored stages the parameter products of the whole segment run after
+    // its sweep in one launch per four modes (k_adjoint_q_seg: the same sums in
+    // the same order as step by step, with one pass over Q); otherwise after
+    // each step (k_adjoint_q).
     auto reverse = [&](double2* seg, int64_t L, hipStream_t s) {
       for (int64_t i = L - 1; i >= 0; --i) {
         double2* yn = slot(seg, i, 0);
@@ -191,15 +200,18 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
           stage_launch(f, HGF_FP64, 2, f.s1, f.s1, yn, nullptr, f.s2, dt, op.dflag, s);
           stage_launch(f, HGF_FP64, 3, f.s2, f.s1, yn, nullptr, f.s3, dt, op.dflag, s);
         }
-        double2 *pm = mu.as<double2>(), *pv2 = vb2.as<double2>(), *pv1 = vb1.as<double2>(), *px = xb1.as<double2>();
+        double2* set = adj.as<double2>() + (store ? i : 0) * 4 * pts;
+        double2 *pm = mu.as<double2>(), *pv2 = set, *pv1 = set + pts, *px = set + 2 * pts, *pmc = set + 3 * pts;
         // stage-1 form (out = h' L^T in): B1, B2 and B3's stencil part
         stage_launch(fa, HGF_FP64, 1, pm, nullptr, pm, nullptr, pv2, 0.5 * dt, op.dflag, s);
         stage_launch(fa, HGF_FP64, 1, pv2, nullptr, pv2, nullptr, pv1, dt / 3.0, op.dflag, s);
         stage_launch(fa, HGF_FP64, 1, pv1, nullptr, pv1, nullptr, px, 0.25 * dt, op.dflag, s);
-        launch_adjoint_q(f.ga, pm, pv2, pv1, px, v2, v1, x1, yn, Qp, dt, s);
+        launch_adjoint_x(pts, pm, pv2, pv1, px, pmc, s);
+        if (!store) launch_adjoint_q(f.ga, pmc, pv2, pv1, px, v2, v1, x1, yn, Qp, dt, s);
         // stage-4 form (y += x1 + (h'/2) L^T in) with x1 = 0, h' = 2h: B4
         stage_launch(fa, HGF_FP64, 4, px, zero.p, pm, nullptr, nullptr, 2.0 * dt, op.dflag, s);
       }
+      if (store) launch_adjoint_q_segment(f.ga, adj.as<double2>(), seg, (int)L, Qp, dt, s);
     };
     // graphs by (part, length, buffer): part 0 = recompute and reverse of one
     // segment, 1 = recompute alone, 2 = reverse alone

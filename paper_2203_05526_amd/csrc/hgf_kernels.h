@@ -78,10 +78,18 @@ void launch_expect_partial(const GridArgs& g, const void* grid, bool grid_fp64, 
                            double2* partial, hipStream_t st, bool real = false);
 void launch_expect_final(const double2* partial, const int* start, const double2* coef, int nfun,
                          double2 analytic, double2* out, hipStream_t st);
-// parameter products of a reverse step (completes Xb1 in place first)
+// completes Xb1 of a reverse step in place and copies mu into mu_copy
+void launch_adjoint_x(int64_t n, const double2* mu, const double2* vb2, const double2* vb1, double2* xb1,
+                      double2* mu_copy, hipStream_t st);
+// parameter products of a reverse step (Xb1 complete)
 void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, const double2* vb1,
-                      double2* xb1, const double2* v2, const double2* v1, const double2* x1,
+                      const double2* xb1, const double2* v2, const double2* v1, const double2* x1,
                       const double2* y, double2* Q, double h, hipStream_t st);
+// parameter products of a reverse segment of L steps: step i's adjoint set
+// (Vb2, Vb1, Xb1, mu) at adj + 4 i points, its grids (y, X1, V1, V2) at
+// fwd + 4 i points
+void launch_adjoint_q_segment(const GridArgs& g, const double2* adj, const double2* fwd, int L, double2* Q, double h,
+                              hipStream_t st);
 int marginal_bins(const GridArgs& g);
 void launch_marginals(const GridArgs& g, const double2* Q, double2* bins, hipStream_t st);
 void launch_fill_zero(double2* p, int64_t n, hipStream_t st);

@@ -873,17 +873,40 @@ __global__ __launch_bounds__(kRedThreads) void k_expect_final(const double2* __r
 // Q is laid out as (1 + 2N) consecutive planes of `points` complex values.
 // L^T is a stencil of the same form as L (transposed per-level tables), so
 // the stencils of B1..B4 run on the forward stage kernels; B3's stencil
-// leaves (h/4) L^T Vb1 in Xb1 and k_adjoint_q adds mu + Vb2 + Vb1 to it.
+// leaves (h/4) L^T Vb1 in Xb1 and k_adjoint_x adds mu + Vb2 + Vb1 to it.
+
+// Completes Xb1 = (h/4) L^T Vb1 + (mu + (Vb2 + Vb1)) in place after B3's
+// stencil, and keeps a copy of mu for the parameter products (B4 then updates
+// mu in place while k_adjoint_q reads the copy).
+__global__ __launch_bounds__(256) void k_adjoint_x(int64_t n, const double2* __restrict__ mu,
+                                                   const double2* __restrict__ vb2,
+                                                   const double2* __restrict__ vb1, double2* __restrict__ xb1,
+                                                   double2* __restrict__ mu_copy) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 mv = mu[i];
+    xb1[i] = cadd(xb1[i], cadd(mv, cadd(vb2[i], vb1[i])));
+    mu_copy[i] = mv;
+  }
+}
+
+// q + a1 v2 + a2 v1 + a3 x1 + a4 y, added in that order (one step's products
+// for one plane of Q; both product kernels use it, so they agree bit for bit).
+__device__ __forceinline__ double2 q_step(double2 q, double2 a1, double2 a2, double2 a3, double2 a4, double2 v2,
+                                          double2 v1, double2 x1, double2 y) {
+  q = cadd(q, cmul(a1, v2));
+  q = cadd(q, cmul(a2, v1));
+  q = cadd(q, cmul(a3, x1));
+  return cadd(q, cmul(a4, y));
+}
 
 // Parameter products of one reverse step, in the order the four stages would
-// add them: Q += (h/2) mu (x) V2, (h/3) Vb2 (x) V1, (h/4) Vb1 (x) X1, h Xb1 (x) y.
-// Runs after B3's stencil and before B4 (which overwrites mu); first completes
-// Xb1 = (h/4) L^T Vb1 + (mu + (Vb2 + Vb1)) in place.  One read-modify-write of
-// the 1 + 2N planes per step instead of one per stage.
+// add them: Q += (h/2) mu (x) V2, (h/3) Vb2 (x) V1, (h/4) Vb1 (x) X1, h Xb1 (x) y,
+// with Xb1 complete (k_adjoint_x).  One read-modify-write of the 1 + 2N planes
+// per step instead of one per stage.
 __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, const double2* __restrict__ mu,
                                                    const double2* __restrict__ vb2,
                                                    const double2* __restrict__ vb1,
-                                                   double2* __restrict__ xb1,
+                                                   const double2* __restrict__ xb1,
                                                    const double2* __restrict__ v2, const double2* __restrict__ v1,
                                                    const double2* __restrict__ x1, const double2* __restrict__ y,
                                                    double2* __restrict__ Q, double h) {
@@ -893,19 +916,9 @@ __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, 
   walker_init(w, g, i0);
   const int64_t P = g.points;
   while (w.i < g.points) {
-    const double2 mv = mu[w.i], b2 = vb2[w.i], b1 = vb1[w.i];
-    const double2 xb = cadd(xb1[w.i], cadd(mv, cadd(b2, b1)));
-    xb1[w.i] = xb;
-    const double2 a1 = cscale(0.5 * h, mv), a2 = cscale(h / 3.0, b2);
-    const double2 a3 = cscale(0.25 * h, b1), a4 = cscale(h, xb);
-    {
-      double2 q = Q[w.i];
-      q = cadd(q, cmul(a1, v2[w.i]));
-      q = cadd(q, cmul(a2, v1[w.i]));
-      q = cadd(q, cmul(a3, x1[w.i]));
-      q = cadd(q, cmul(a4, y[w.i]));
-      Q[w.i] = q;
-    }
+    const double2 a1 = cscale(0.5 * h, mu[w.i]), a2 = cscale(h / 3.0, vb2[w.i]);
+    const double2 a3 = cscale(0.25 * h, vb1[w.i]), a4 = cscale(h, xb1[w.i]);
+    Q[w.i] = q_step(Q[w.i], a1, a2, a3, a4, v2[w.i], v1[w.i], x1[w.i], y[w.i]);
 #pragma unroll
     for (int j = 0; j < kMaxModes; ++j) {
       if (j < g.n) {
@@ -913,24 +926,74 @@ __global__ __launch_bounds__(256) void k_adjoint_q(GridArgs g, StrideDigits sd, 
         if (m >= 1) {
           const int64_t k = w.i - g.stride[j];
           double2& qr = Q[(1 + j) * P + w.i];
-          double2 q = qr;
-          q = cadd(q, cmul(a1, v2[k]));
-          q = cadd(q, cmul(a2, v1[k]));
-          q = cadd(q, cmul(a3, x1[k]));
-          q = cadd(q, cmul(a4, y[k]));
-          qr = q;
+          qr = q_step(qr, a1, a2, a3, a4, v2[k], v1[k], x1[k], y[k]);
         }
         if (m + 1 < g.ext[j]) {
           const int64_t k = w.i + g.stride[j];
           double2& qr = Q[(1 + g.n + j) * P + w.i];
-          double2 q = qr;
-          q = cadd(q, cmul(a1, v2[k]));
-          q = cadd(q, cmul(a2, v1[k]));
-          q = cadd(q, cmul(a3, x1[k]));
-          q = cadd(q, cmul(a4, y[k]));
-          qr = q;
+          qr = q_step(qr, a1, a2, a3, a4, v2[k], v1[k], x1[k], y[k]);
         }
       }
+    }
+    walker_step(w, g, sd);
+  }
+}
+
+// Parameter products of a whole reverse segment of L steps: per point, the
+// steps L-1 down to 0 in turn with the partial sums in registers, that is,
+// the additions of k_adjoint_q step after step in the same order, and one
+// read-modify-write of Q per segment.  Step i's adjoint set is at
+// adj + 4 i P (Vb2, Vb1, Xb1 complete, mu) and its forward grids at
+// fwd + 4 i P (y, X1, V1, V2).  One launch covers the planes of modes
+// J0 .. J0+3 (and Q0 for J0 = 0).
+template <int J0>
+__global__ __launch_bounds__(256) void k_adjoint_q_seg(GridArgs g, StrideDigits sd, const double2* __restrict__ adj,
+                                                       const double2* __restrict__ fwd, int L,
+                                                       double2* __restrict__ Q, double h) {
+  constexpr int kJ = 4;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= g.points) return;
+  Walker w;
+  walker_init(w, g, i0);
+  const int64_t P = g.points;
+  while (w.i < g.points) {
+    double2 q0 = make_double2(0.0, 0.0), qd[kJ], qu[kJ];
+    bool hd[kJ], hu[kJ];
+    int64_t sj[kJ];
+    if (J0 == 0) q0 = Q[w.i];
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int j = J0 + jj;
+      hd[jj] = j < g.n && w.c[j] >= 1;
+      hu[jj] = j < g.n && w.c[j] + 1 < g.ext[j];
+      sj[jj] = j < g.n ? g.stride[j] : 0;
+      qd[jj] = hd[jj] ? Q[(1 + j) * P + w.i] : make_double2(0.0, 0.0);
+      qu[jj] = hu[jj] ? Q[(1 + g.n + j) * P + w.i] : make_double2(0.0, 0.0);
+    }
+    for (int i = L - 1; i >= 0; --i) {
+      const double2* a = adj + (int64_t)i * 4 * P;
+      const double2* f = fwd + (int64_t)i * 4 * P;
+      const double2 a1 = cscale(0.5 * h, a[3 * P + w.i]), a2 = cscale(h / 3.0, a[w.i]);
+      const double2 a3 = cscale(0.25 * h, a[P + w.i]), a4 = cscale(h, a[2 * P + w.i]);
+      if (J0 == 0) q0 = q_step(q0, a1, a2, a3, a4, f[3 * P + w.i], f[2 * P + w.i], f[P + w.i], f[w.i]);
+#pragma unroll
+      for (int jj = 0; jj < kJ; ++jj) {
+        if (hd[jj]) {
+          const int64_t k = w.i - sj[jj];
+          qd[jj] = q_step(qd[jj], a1, a2, a3, a4, f[3 * P + k], f[2 * P + k], f[P + k], f[k]);
+        }
+        if (hu[jj]) {
+          const int64_t k = w.i + sj[jj];
+          qu[jj] = q_step(qu[jj], a1, a2, a3, a4, f[3 * P + k], f[2 * P + k], f[P + k], f[k]);
+        }
+      }
+    }
+    if (J0 == 0) Q[w.i] = q0;
+#pragma unroll
+    for (int jj = 0; jj < kJ; ++jj) {
+      const int j = J0 + jj;
+      if (hd[jj]) Q[(1 + j) * P + w.i] = qd[jj];
+      if (hu[jj]) Q[(1 + g.n + j) * P + w.i] = qu[jj];
     }
     walker_step(w, g, sd);
   }
@@ -1232,13 +1295,35 @@ void launch_expect_final(const double2* partial, const int* start, const double2
   hipLaunchKernelGGL(k_expect_final, dim3(1), dim3(kRedThreads), 0, st, partial, start, coef, nfun, analytic, out);
 }
 
+void launch_adjoint_x(int64_t n, const double2* mu, const double2* vb2, const double2* vb1, double2* xb1,
+                      double2* mu_copy, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_adjoint_x, dim3(blocks), dim3(256), 0, st, n, mu, vb2, vb1, xb1, mu_copy);
+}
+
 void launch_adjoint_q(const GridArgs& g, const double2* mu, const double2* vb2, const double2* vb1,
-                      double2* xb1, const double2* v2, const double2* v1, const double2* x1,
+                      const double2* xb1, const double2* v2, const double2* v1, const double2* x1,
                       const double2* y, double2* Q, double h, hipStream_t st) {
   const LaunchShape ls = shape_for(g, kStageBlocks);
   const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
   hipLaunchKernelGGL(k_adjoint_q, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, mu, vb2, vb1, xb1, v2, v1, x1, y,
                      Q, h);
+}
+
+void launch_adjoint_q_segment(const GridArgs& g, const double2* adj, const double2* fwd, int L, double2* Q, double h,
+                              hipStream_t st) {
+  static_assert(kMaxModes <= 16, "mode chunks of k_adjoint_q_seg cover 16 modes");
+  if (L <= 0) return;
+  const LaunchShape ls = shape_for(g, kStageBlocks);
+  const StrideDigits sd = digits_for(g, (int64_t)ls.blocks * ls.threads);
+  hipLaunchKernelGGL(k_adjoint_q_seg<0>, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, adj, fwd, L, Q, h);
+  if (g.n > 4)
+    hipLaunchKernelGGL(k_adjoint_q_seg<4>, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, adj, fwd, L, Q, h);
+  if (g.n > 8)
+    hipLaunchKernelGGL(k_adjoint_q_seg<8>, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, adj, fwd, L, Q, h);
+  if (g.n > 12)
+    hipLaunchKernelGGL(k_adjoint_q_seg<12>, dim3(ls.blocks), dim3(ls.threads), 0, st, g, sd, adj, fwd, L, Q, h);
 }
 
 int marginal_bins(const GridArgs& g) {
