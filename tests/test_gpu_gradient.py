@@ -142,6 +142,53 @@ def test_gradient_workload_factorises(hgf):
     assert np.max(np.abs(g[zeros])) <= 1e-14 * np.max(np.abs(g))
 
 
+def test_gradient_thirteen_modes_products(hgf, monkeypatch):
+    """13 modes at cutoff 2 with a bitstring projector (one 8,192-point
+    sector): the parameter products run once per segment in chunks of four
+    modes (0-3, 4-7, 8-11, 12), and step by step in one pass when the stages
+    are not stored (HGF_GRAD_STORE=0); both give the same bits, and the
+    gamma1 partials match factorised single-mode oracle sensitivities while
+    the other 117 partials (K, chi, Delta, gamma_phi) are zero on the
+    diagonal sector."""
+    n = 13
+    cutoff = (2,) * n
+    announce("gradient, 13 modes, segment products vs per step vs factorised oracle")
+    s = synth.random_system(cutoff, 341, scale=2.0, n_th=0.3)
+    rng = np.random.default_rng(341)
+    bits = rng.integers(0, 2, size=n)
+    fac = synth.projector_factors(cutoff, bits)
+    alpha = rng.uniform(0.2, 0.8, size=n) * np.exp(1j * rng.uniform(0, 2 * np.pi, size=n))
+    st = synth.coherent_state(list(alpha))
+    T, dt = 0.05, 1e-3
+    S = hgf.define_system(s)
+    out = []
+    for store in (None, "0"):
+        if store is None:
+            monkeypatch.delenv("HGF_GRAD_STORE", raising=False)
+        else:
+            monkeypatch.setenv("HGF_GRAD_STORE", store)
+        out.append(hgf.grad(S, st, T, dt, factors=fac, checkpoint_every=7))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
+    val, g = out[0]
+    Js, dg = [], []
+    for j in range(n):
+        fin, sens = oracle.evolve_sens(_single_mode(s, j), oracle.product_sectors([fac[j]]), T, dt, nthreads=1)
+        c = ("coherent", [alpha[j]])
+        Js.append(oracle.expectation((2,), fin, c))
+        dg.append(oracle.expectation((2,), sens[2], c))  # single-mode parameters: K, Delta, gamma1, gamma_phi
+    P = n + n * (n - 1) // 2 + 3 * n
+    assert len(g) == P
+    ref = np.zeros(P, dtype=np.complex128)
+    gam = slice(n + n * (n - 1) // 2 + n, n + n * (n - 1) // 2 + 2 * n)
+    ref[gam] = [dg[j] * np.prod([Js[i] for i in range(n) if i != j]) for j in range(n)]
+    assert rel(val, np.prod(Js)) < FP64_TOL
+    assert grad_err(g[gam], ref[gam]) < FP64_TOL, grad_err(g[gam], ref[gam])
+    zeros = np.ones(P, dtype=bool)
+    zeros[gam] = False
+    assert np.max(np.abs(g[zeros])) <= 1e-14 * np.max(np.abs(g))
+
+
 def test_gradient_matches_central_differences(hgf):
     """dJ/dtheta from the reverse sweep against central differences of the
     forward evolve (FP64), h_i = 1e-6 max(|theta_i|, 1), on the slow-axis
