@@ -253,14 +253,10 @@ bool resident_eligible(Function& f, int threads) {
   if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
   const int max_threads = f.precision_fp64 ? 512 : 1024;  // the kernel's workgroup limit
   if (g.tile_points > (int64_t)resident_max_points() * max_threads / 1024) return false;
-  // two padded copies of the grid and the down-jump tables in LDS
+  // two padded copies of the grid in LDS
   const int rs = f.precision_fp64 ? 8 : 4, es = (f.ga.real ? 1 : 2) * rs;
-  int esum = 0;
-  for (int j = 0; j < g.n; ++j) esum += g.ext[j];
   if (g.n > 4) return false;
-  for (int j = 0; j < g.n; ++j)
-    if (g.ext[j] > 32) return false;  // 5-bit coordinates
-  const int64_t lds = 2 * (int64_t)g.lds_elems * es + (int64_t)esum * rs;
+  const int64_t lds = 2 * (int64_t)g.lds_elems * es;
   if (lds > 65536) return false;
   f.res_lds_bytes = (int)lds;
   if (threads > 0) {

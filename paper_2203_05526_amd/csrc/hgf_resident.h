@@ -52,21 +52,8 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
   TS* const buf0 = (TS*)smem;
   TS* const buf1 = buf0 + E;
   for (int i = tid; i < 2 * E; i += nt) buf0[i] = mk_<TS>(0, 0);
-  // down-jump coefficients alpha_q(c) of every axis, after the two copies
-  R* const atab = (R*)(buf1 + E);
-  int aoff[NF];
-  {
-    int o = 0;
-#pragma unroll
-    for (int q = 0; q < NF; ++q) {
-      aoff[q] = o;
-      for (int c = tid; c < it->g.ext[q]; c += nt) atab[o + c] = (R)it->g.alpha[it->g.off[q] + c];
-      o += it->g.ext[q];
-    }
-  }
-
-  // ---- per-point constants in registers: LDS slot, coordinates, diagonal
-  // coefficient, up-jump coefficient per axis.  Lanes past the grid's end (last round)
+  // ---- per-point constants in registers: LDS slot, diagonal coefficient,
+  // down- and up-jump coefficients per axis.  Lanes past the grid's end (last round)
   // work on a copy of the last point and store nothing.
   // Diagonal rate: complex FP32 grids hold it as hi + lo of its FP64 value
   // (Kerr phases reach 1e4 rad/us; a rate rounded to FP32 would leave a
@@ -74,15 +61,13 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
   constexpr bool SPLIT = DiagLam<TS>::split;
   const R lr0 = (R)it->g.lam0_re, li0 = (R)it->g.lam0_im;
   int slot[kResidentRounds];
-  uint32_t cpk[kResidentRounds];  // the point's coordinates, 5 bits per axis
-  R lrr[kResidentRounds], lir[kResidentRounds], bqr[kResidentRounds][NF];
+  R lrr[kResidentRounds], lir[kResidentRounds], bqr[kResidentRounds][NF], aqr[kResidentRounds][NF];
   R lro[SPLIT ? kResidentRounds : 1], lio[SPLIT ? kResidentRounds : 1];
 #pragma unroll
   for (int r = 0; r < kResidentRounds; ++r) {
     if (r < rounds) {
       int rem = min(tid + r * nt, T - 1);
       int off = 0;
-      uint32_t cp = 0;
       double lr = 0.0, li = 0.0;
 #pragma unroll
       for (int q = NF - 1; q >= 0; --q) {
@@ -94,10 +79,9 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
         lr += lj.x;
         li += lj.y;
         bqr[r][q] = (R)it->g.beta[it->g.off[q] + c];
-        cp |= (uint32_t)c << (5 * q);
+        aqr[r][q] = (R)it->g.alpha[it->g.off[q] + c];
       }
       slot[r] = off;
-      cpk[r] = cp;
       if constexpr (SPLIT) {
         const double Lr = it->g.lam0_re + lr, Li = it->g.lam0_im + li;
         lrr[r] = (R)Lr;
@@ -129,6 +113,8 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
     }
   }
   const double h = it->h;
+  const R c2 = (R)(0.25 * h), c3 = (R)(h / 3.0);
+  const double c4 = 0.5 * h;
   const int steps = it->steps;
   int bad = 0;
   const TS* cur = buf0;
@@ -141,13 +127,13 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
       for (int r = 0; r < kResidentRounds; ++r) {
         if (r < rounds) {
           const int lo_ = slot[r];
-          const TS zc = cur[lo_];
+          const TS zc = orr[r];  // this lane's stencil input (what it wrote into `cur`)
           R ar = 0, ai = 0;
 #pragma unroll
           for (int q = 0; q < NF; ++q) {
             const TS dn = cur[lo_ - it->g.pstride[q]];
             const TS upv = cur[lo_ + it->g.pstride[q]];
-            const R aq = atab[aoff[q] + (int)((cpk[r] >> (5 * q)) & 31u)];
+            const R aq = aqr[r][q];
             ar += aq * re_(dn) + bqr[r][q] * re_(upv);
             ai += aq * im_(dn) + bqr[r][q] * im_(upv);
           }
@@ -165,10 +151,10 @@ __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(con
             xr[r] = mk_<TS>((R)(h * (double)ar), (R)(h * (double)ai));
             orr[r] = xr[r];
           } else if (stage == 2 || stage == 3) {
-            const R c = (R)(stage == 2 ? 0.25 * h : h / 3.0);
+            const R c = stage == 2 ? c2 : c3;
             orr[r] = mk_<TS>(re_(xr[r]) + c * ar, im_(xr[r]) + c * ai);
           } else {
-            const double c = 0.5 * h;
+            const double c = c4;
             const double nr = re_(yr[r]) + (double)re_(xr[r]) + c * (double)ar;
             const double ni = Real<TS>::cplx ? im_(yr[r]) + (double)im_(xr[r]) + c * (double)ai : 0.0;
             bad |= (tid + r * nt < T) && !(isfinite(nr) && isfinite(ni));
