@@ -369,10 +369,13 @@ typedef struct {
                           current round computes */
   int32_t wgs_per_cu;  /* resident workgroups per CU in the persistent grid; 0 = as many as
                           fit (fewer narrow the band of tiles each XCD works on) */
-  int32_t resident;    /* 1 = the whole grid is one tile and one workgroup integrates it on
-                          chip through all the steps of a call (state in registers, stage
-                          grids in LDS); 0 = one launch per RK4 stage.  Set by default
-                          where the grid allows it */
+  int32_t resident;    /* 1 = one workgroup integrates the whole grid on chip through all
+                          the steps of a call (state in registers, stage grids in LDS): at
+                          most 4 axes and 4096 points (2048 in FP64), two padded copies of
+                          the grid within 160 KB; 0 = one launch per RK4 stage.  Set by
+                          default where the grid allows it (not under
+                          HGF_STAGE_KERNEL=generic or an HGF_MAX_NFAST below the axis
+                          count); the other fields keep the stage kernels' shape */
   int32_t walk_block;  /* order in which the persistent grid walks the tiles: 0 = row-major
                           over the slow axes; B >= 2 = blocks of B along every slow axis,
                           row-major inside a block and across blocks (neighbour tiles along
@@ -390,11 +393,14 @@ hgf_status hgf_get_tile_config(hgf_operator op, int32_t idx, hgf_tile_config* ou
  * wgs_per_cu, resident, walk_block).
  * On a network operator's full (k, l) grid nfast is 0 (untiled kernel) or 4
  * (tiles of the last two modes' (k, l) block, the four fastest axes), with
- * threads, wgs_per_cu and walk_block; xblock, pipe and resident must be 0.
+ * threads, wgs_per_cu and walk_block, or nfast 0 with resident 1 (the
+ * resident form of a network grid twice within 64 KB of LDS, at most three
+ * modes); xblock and pipe must be 0.
  * hgf_autotune leaves network operators alone.
  * Errors: HGF_EINVAL when the shape does not fit the grid (LDS, lane rounds,
  * register budget), asks a real grid for the untiled kernel, or asks for the
- * resident form where the grid is not a single tile of at most 4096 points;
+ * resident form where the grid does not fit it (above; on a sector grid
+ * nfast >= 1 must also name a feasible stage-kernel shape, kept beside it);
  * HGF_EUNSUPPORTED for split-layout functions (classical kernel only).  The
  * function is unchanged on error.
  */

@@ -37,6 +37,13 @@ bool stage_kernel_generic() {
   return env && std::string(env) == "generic";
 }
 
+// HGF_MAX_NFAST below the axis count asks small grids to run the tiled kernel
+// with slow axes, so it also keeps them off the resident form by default.
+static bool nfast_capped_below(int n) {
+  const char* env = std::getenv("HGF_MAX_NFAST");
+  return env && std::atoi(env) >= 1 && std::atoi(env) < n;
+}
+
 
 // Configure the tiled stage kernel for grid g.  Default rule: the largest
 // number nfast <= 4 of trailing axes whose padded tile and tables fit in 64 KB
@@ -243,32 +250,52 @@ void* upload_tile_records(GridArgs& g, const SectorTables& t, int precision) {
 
 void build_tile_records(Function& f, int precision) { f.ttab = upload_tile_records(f.ga, f.tab, precision); }
 
-// A function runs on the resident kernel when its tiled configuration is a
-// single tile holding every axis (then one workgroup does a stage's work in any
-// case) and the tile fits the resident kernel's lane rounds.  `threads` > 0
-// asks for that workgroup size (a multiple of 64 that covers the grid in the
+// A function runs on the resident kernel when it has at most four axes, its
+// points fit the kernel's lane rounds (4096 in mixed precision, 2048 in FP64)
+// and two padded copies of the whole grid (the tiled kernel's layout with
+// every axis in the tile) fit in the CU's LDS; its layout is kept in f.rga,
+// beside the stage kernels' (f.ga), which other calls use.  `threads` > 0 asks
+// for that workgroup size (a multiple of 64 that covers the grid in the
 // kernel's lane rounds), else the fewest rounds with lanes spread evenly.
 bool resident_eligible(Function& f, int threads) {
   const GridArgs& g = f.ga;
-  if (f.split || g.blocks == 0 || g.nfast != g.n || g.ntiles != 1) return false;
+  if (f.split || f.full || g.n > 4) return false;
   const int max_threads = f.precision_fp64 ? 512 : 1024;  // the kernel's workgroup limit
-  if (g.tile_points > (int64_t)resident_max_points() * max_threads / 1024) return false;
-  // two padded copies of the grid in LDS
-  const int rs = f.precision_fp64 ? 8 : 4, es = (f.ga.real ? 1 : 2) * rs;
-  if (g.n > 4) return false;
-  const int64_t lds = 2 * (int64_t)g.lds_elems * es;
-  if (lds > 65536) return false;
+  if (g.points > (int64_t)resident_max_points() * max_threads / 1024) return false;
+  GridArgs r = g;
+  int64_t padded = 1, pst = 1;
+  for (int q = 0; q < g.n; ++q) padded *= q == 0 ? g.ext[q] + 2 : g.ext[q] + 1;
+  for (int q = g.n - 1; q >= 0; --q) {
+    r.pstride[q] = (int)pst;
+    pst *= g.ext[q] + 1;
+  }
+  r.nfast = g.n;
+  r.tile_points = g.points;
+  r.ntiles = 1;
+  r.lds_elems = (int)padded;
+  const int rs = f.precision_fp64 ? 8 : 4, es = (g.real ? 1 : 2) * rs;
+  const int64_t lds = 2 * padded * es;
+  if (lds > kResidentLdsMax) return false;
+  // (the kernels' limit goes to the maximum at once, so that it never drops
+  // below what another resident function of the same types needs)
+  if (lds > 65536 &&
+      resident_allow_lds(g.real != 0, f.precision_fp64 ? HGF_FP64 : HGF_MIXED, kResidentLdsMax) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (threads > 0 &&
+      (threads % 64 != 0 || threads > max_threads ||
+       (g.points + threads - 1) / threads * (int64_t)1024 > (int64_t)resident_max_points()))
+    return false;
+  f.rga = r;
   f.res_lds_bytes = (int)lds;
   if (threads > 0) {
-    if (threads % 64 != 0 || threads > max_threads ||
-        (g.tile_points + threads - 1) / threads * (int64_t)1024 > (int64_t)resident_max_points())
-      return false;
     f.res_threads = threads;
     return true;
   }
   // lanes: enough for the fewest rounds, spread evenly over them
-  const int64_t rounds = (g.tile_points + max_threads - 1) / max_threads;
-  const int64_t per = (g.tile_points + rounds - 1) / rounds;
+  const int64_t rounds = (g.points + max_threads - 1) / max_threads;
+  const int64_t per = (g.points + rounds - 1) / rounds;
   f.res_threads = (int)std::min<int64_t>(max_threads, std::max<int64_t>(64, (per + 63) / 64 * 64));
   return true;
 }
@@ -346,7 +373,7 @@ void fill_grid_args(Function& f, int precision, bool want_real) {
   g.tiles = nullptr;
   g.full = (const FullTables*)f.ftab;
   if (g.blocks > 0) build_tile_records(f, precision);
-  f.resident = resident_eligible(f);
+  f.resident = !stage_kernel_generic() && !nfast_capped_below(g.n) && resident_eligible(f);
   const char* env = std::getenv("HGF_RESIDENT");
   if (env && std::string(env) == "0") f.resident = false;
 }

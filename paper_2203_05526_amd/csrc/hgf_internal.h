@@ -289,6 +289,7 @@ struct Function {
   bool resident = false;  // integrated on chip by the resident kernel
   int res_threads = 0;    // workgroup size of the resident kernel
   int res_lds_bytes = 0;  // its LDS (two padded copies of the grid)
+  GridArgs rga{};         // the resident kernel's layout (ga with every axis in LDS)
   bool precision_fp64 = false;
   // integrating-factor scheme: per-axis factors exp(lam_j(m) h/2) on the
   // device (concatenated like lam), exp(lam0 h/2), and the h they are for

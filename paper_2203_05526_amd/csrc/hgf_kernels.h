@@ -70,6 +70,11 @@ int tiled_max_lane_groups();
 void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st);
 // resident (on-chip, many-step) integrator; grids of at most this many points
 int resident_max_points();
+// LDS a resident workgroup may take: the CU's 160 KB on gfx950
+constexpr int kResidentLdsMax = 160 * 1024;
+// set the resident kernels' dynamic-LDS limit (for a function's element
+// types) to `bytes`; a host call, made outside graph capture
+hipError_t resident_allow_lds(bool real, int precision, int bytes);
 void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st);
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
                       double h, const PointSources& src, int* flag, hipStream_t st);

@@ -1128,7 +1128,16 @@ void launch_resident_c64(const ResidentLaunch&, int*, hipStream_t);
 void launch_resident_c128(const ResidentLaunch&, int*, hipStream_t);
 void launch_resident_r32(const ResidentLaunch&, int*, hipStream_t);
 void launch_resident_r64(const ResidentLaunch&, int*, hipStream_t);
+hipError_t resident_allow_lds_c64(int);
+hipError_t resident_allow_lds_c128(int);
+hipError_t resident_allow_lds_r32(int);
+hipError_t resident_allow_lds_r64(int);
 int resident_max_points() { return 4 * 1024; }
+
+hipError_t resident_allow_lds(bool real, int precision, int bytes) {
+  if (real) return (precision == HGF_FP64 ? resident_allow_lds_r64 : resident_allow_lds_r32)(bytes);
+  return (precision == HGF_FP64 ? resident_allow_lds_c128 : resident_allow_lds_c64)(bytes);
+}
 
 void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st) {
   if (rl.full) {

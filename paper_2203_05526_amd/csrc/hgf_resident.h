@@ -1,10 +1,11 @@
 // Resident RK4 integrator for grids that fit in one workgroup's LDS.
 //
-// When every axis of a function is a fast axis of the tiled stage kernel (the
-// whole grid is a single tile), one workgroup does all the work of a stage
-// launch anyway.  The resident form keeps that workgroup's grid on chip for
-// many RK4 steps: the stencil input of the current stage lives in LDS (the
-// padded zero-halo layout of the tiled kernel, two copies used in turn), and
+// A grid of up to four axes and a few thousand points is too small to fill
+// more than a few CUs with one launch per RK4 stage, and each such launch
+// costs microseconds of latency.  The resident form keeps the grid on one
+// workgroup's chip for many RK4 steps: the stencil input of the current stage
+// lives in LDS (the padded zero-halo layout of the tiled kernel with every
+// axis in the tile, two copies used in turn), and
 // each lane keeps its points' state y, X1 and per-point coefficients in
 // registers.  A stage is: read the neighbours from one LDS copy, compute the
 // stage value (the same delta-Horner arithmetic as the tiled kernel), write
@@ -204,9 +205,24 @@ static void resident_launch_all(const ResidentLaunch& rl, int* flag, hipStream_t
   }
 }
 
+// A resident workgroup may use up to the CU's whole LDS (160 KB on gfx950);
+// dynamic LDS beyond 64 KB needs each kernel's limit raised first, a host
+// call made when a function is made resident (never under graph capture).
+template <typename TS, typename TY>
+static hipError_t resident_allow_lds_all(int bytes) {
+  const void* fns[4] = {(const void*)k_rk4_resident<1, TS, TY>, (const void*)k_rk4_resident<2, TS, TY>,
+                        (const void*)k_rk4_resident<3, TS, TY>, (const void*)k_rk4_resident<4, TS, TY>};
+  for (const void* fn : fns) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 #define HGF_RESIDENT_INSTANTIATE(TS, TY, SUFFIX)                                    \
   void launch_resident_##SUFFIX(const ResidentLaunch& rl, int* flag, hipStream_t st) { \
     resident_launch_all<TS, TY>(rl, flag, st);                                      \
-  }
+  }                                                                                 \
+  hipError_t resident_allow_lds_##SUFFIX(int bytes) { return resident_allow_lds_all<TS, TY>(bytes); }
 
 }  // namespace hgf

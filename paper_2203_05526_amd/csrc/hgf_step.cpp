@@ -61,7 +61,7 @@ StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resident) {
   for (const PlanItem& it : items) {
     const GridArgs& g = it.f->ga;
     if (allow_resident && it.f->resident)
-      res_key[{it.f->full ? g.n / 2 : g.nfast, g.real, it.precision, it.f->full ? 1 : 0}].push_back(it);
+      res_key[{it.f->full ? g.n / 2 : g.n, g.real, it.precision, it.f->full ? 1 : 0}].push_back(it);
     else if (g.blocks > 0)
       by_key[{g.nfast, g.n - g.nfast, g.real, it.precision}].push_back(it);
     else
@@ -111,7 +111,7 @@ StepPlan* build_plan(const std::vector<PlanItem>& items, bool allow_resident) {
     std::vector<ResidentItem> host;
     for (const PlanItem& it : kv.second) {
       ResidentItem ri{};
-      ri.g = it.f->ga;
+      ri.g = it.f->full ? it.f->ga : it.f->rga;
       ri.y = it.f->y;
       ri.yf = it.precision == HGF_MIXED ? it.f->yf : nullptr;
       ri.x1 = it.f->s1;

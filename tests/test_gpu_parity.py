@@ -532,16 +532,18 @@ def test_large_tile_random_diagonal_operator(hgf, precision):
 
 # ----------------------------------------------------------------- large phases in mixed precision
 
-@pytest.mark.parametrize("kernel", ["grouped", "tiled", "generic", "resident"])
+@pytest.mark.parametrize("kernel", ["grouped", "tiled", "generic", "resident", "resident8"])
 def test_mixed_precision_off_diagonal_phases(hgf, monkeypatch, kernel):
     """Product of quadratures on 4 Kerr modes (16 off-diagonal sectors, Kerr
     phases up to ~1.5e4 rad/us), T = 0.02 us with classical RK4 at dt = 1 ps
     (2e4 steps): the mixed form forms the diagonal rate's phase in FP64
     (hi + lo in the FP32 stencil), so it stays within 1e-5 of the FP64
     oracle's stored value on every stage kernel.  Cutoff 8 (sectors of 7^4
-    points): one grouped launch of the 16 sectors by default (three fast axes
-    in LDS), the tiled kernel with two slow axes (at most two fast axes), the
-    generic kernel; cutoff 6 (5^4 points): the resident integrator."""
+    points): the resident integrator by default (the two padded copies take
+    73,728 B of LDS, beyond 64 KB), one grouped launch of the 16 sectors
+    without it (three fast axes in LDS), the tiled kernel with two slow axes
+    (at most two fast axes), the generic kernel; cutoff 6 (5^4 points): the
+    resident integrator."""
     import json
     cutoff = 6 if kernel == "resident" else 8
     with open(os.path.join(GOLDEN, "quadratures6.json" if cutoff == 6 else "quadratures.json")) as fh:
@@ -550,11 +552,13 @@ def test_mixed_precision_off_diagonal_phases(hgf, monkeypatch, kernel):
         monkeypatch.setenv("HGF_MAX_NFAST", "2")
     elif kernel == "generic":
         monkeypatch.setenv("HGF_STAGE_KERNEL", "generic")
+    elif kernel == "grouped":
+        monkeypatch.setenv("HGF_RESIDENT", "0")
     w = synth.grad_c3b(cutoff=cutoff)
     announce(f"off-diagonal phases, mixed, {kernel}")
     op = hgf.map_operator(hgf.define_system(w.system), factors=w.factors, precision="mixed")
     cfg = op.tile_config(0)
-    if kernel == "resident":
+    if kernel in ("resident", "resident8"):
         assert cfg["resident"] == 1
     elif kernel == "grouped":
         assert cfg["resident"] == 0 and cfg["nfast"] >= 3 and cfg["blocks"] > 0
