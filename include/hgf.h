@@ -362,7 +362,7 @@ typedef struct {
   int32_t nfast;       /* trailing axes staged in LDS; 0 = untiled (generic) kernel */
   int32_t threads;     /* workgroup size: multiple of 64 in [64, 512] (the resident form: up to
                           1024 in mixed precision, 512 in FP64, covering the grid in at most 4
-                          lane rounds); 0 = default rule */
+                          lane rounds, 5 on complex FP64 grids); 0 = default rule */
   int32_t xblock;      /* tile order over the 8 XCDs: 0 = contiguous eighths of the grid,
                           B > 0 = interleaved blocks of B consecutive tiles */
   int32_t pipe;        /* 1 = neighbour loads of the next lane round issued before the
@@ -371,7 +371,7 @@ typedef struct {
                           fit (fewer narrow the band of tiles each XCD works on) */
   int32_t resident;    /* 1 = one workgroup integrates the whole grid on chip through all
                           the steps of a call (state in registers, stage grids in LDS): at
-                          most 4 axes and 4096 points (2048 in FP64), two padded copies of
+                          most 4 axes and 4096 points (FP64: 2048 real, 2560 complex), two padded copies of
                           the grid within 160 KB; 0 = one launch per RK4 stage.  Set by
                           default where the grid allows it (not under
                           HGF_STAGE_KERNEL=generic or an HGF_MAX_NFAST below the axis

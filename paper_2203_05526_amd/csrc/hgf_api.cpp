@@ -567,9 +567,9 @@ hgf_status hgf_set_tile_config(hgf_operator op, int32_t idx, const hgf_tile_conf
       probe.ga = f.ga;
       if (c.nfast == 0 || !configure_tiles(probe.ga, op->precision, f.real, c) ||
           !resident_eligible(probe, cfg->threads))
-        fail(HGF_EINVAL, "the resident form needs a grid of at most 4 axes and 4096 points (2048 in FP64) "
-                         "whose two padded copies fit in 160 KB of LDS (and threads, if set, a multiple of 64 "
-                         "covering it in at most 4 lane rounds)");
+        fail(HGF_EINVAL, "the resident form needs a grid of at most 4 axes and 4096 points (FP64: 2048 real, "
+                         "2560 complex) whose two padded copies fit in 160 KB of LDS (and threads, if set, a "
+                         "multiple of 64 covering it in at most 4 lane rounds, 5 on complex FP64 grids)");
     }
     retile(f, op->precision, c);
     f.resident = cfg->resident && resident_eligible(f, cfg->threads);

@@ -251,7 +251,8 @@ void* upload_tile_records(GridArgs& g, const SectorTables& t, int precision) {
 void build_tile_records(Function& f, int precision) { f.ttab = upload_tile_records(f.ga, f.tab, precision); }
 
 // A function runs on the resident kernel when it has at most four axes, its
-// points fit the kernel's lane rounds (4096 in mixed precision, 2048 in FP64)
+// points fit the kernel's lane rounds (4096 in mixed precision, 2048 on real
+// and 2560 on complex FP64 grids)
 // and two padded copies of the whole grid (the tiled kernel's layout with
 // every axis in the tile) fit in the CU's LDS; its layout is kept in f.rga,
 // beside the stage kernels' (f.ga), which other calls use.  `threads` > 0 asks
@@ -261,7 +262,8 @@ bool resident_eligible(Function& f, int threads) {
   const GridArgs& g = f.ga;
   if (f.split || f.full || g.n > 4) return false;
   const int max_threads = f.precision_fp64 ? 512 : 1024;  // the kernel's workgroup limit
-  if (g.points > (int64_t)resident_max_points() * max_threads / 1024) return false;
+  const int max_rounds = resident_max_rounds(f.precision_fp64, g.real != 0);
+  if (g.points > (int64_t)max_rounds * max_threads) return false;
   GridArgs r = g;
   int64_t padded = 1, pst = 1;
   for (int q = 0; q < g.n; ++q) padded *= q == 0 ? g.ext[q] + 2 : g.ext[q] + 1;
@@ -285,7 +287,7 @@ bool resident_eligible(Function& f, int threads) {
   }
   if (threads > 0 &&
       (threads % 64 != 0 || threads > max_threads ||
-       (g.points + threads - 1) / threads * (int64_t)1024 > (int64_t)resident_max_points()))
+       (g.points + threads - 1) / threads > max_rounds))
     return false;
   f.rga = r;
   f.res_lds_bytes = (int)lds;

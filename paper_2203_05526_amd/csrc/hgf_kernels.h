@@ -69,7 +69,8 @@ int tiled_max_slow_axes();
 int tiled_max_lane_groups();
 void launch_group(const GroupLaunch& gl, int stage, int* flag, hipStream_t st);
 // resident (on-chip, many-step) integrator; grids of at most this many points
-int resident_max_points();
+// lane rounds of the resident kernel's workgroup (1024 lanes, 512 in FP64)
+int resident_max_rounds(bool fp64, bool real);
 // LDS a resident workgroup may take: the CU's 160 KB on gfx950
 constexpr int kResidentLdsMax = 160 * 1024;
 // set the resident kernels' dynamic-LDS limit (for a function's element

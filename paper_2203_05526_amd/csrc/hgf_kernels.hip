@@ -1132,7 +1132,7 @@ hipError_t resident_allow_lds_c64(int);
 hipError_t resident_allow_lds_c128(int);
 hipError_t resident_allow_lds_r32(int);
 hipError_t resident_allow_lds_r64(int);
-int resident_max_points() { return 4 * 1024; }
+int resident_max_rounds(bool fp64, bool real) { return fp64 && !real ? 5 : 4; }
 
 hipError_t resident_allow_lds(bool real, int precision, int bytes) {
   if (real) return (precision == HGF_FP64 ? resident_allow_lds_r64 : resident_allow_lds_r32)(bytes);

@@ -23,20 +23,28 @@
 
 namespace hgf {
 
-// Lane rounds per workgroup of the resident kernel: a grid of at most
-// kResidentRounds * (1024 lanes, 512 in FP64) points.
-constexpr int kResidentRounds = 4;
-
 // Workgroup size limit: FP64 grids need more registers per lane.
 template <typename TS>
 struct ResidentThreads {
   static constexpr int value = sizeof(typename Real<TS>::T) == 8 ? 512 : 1024;
 };
 
+// Lane rounds per workgroup (each lane keeps one point per round in
+// registers): a grid of at most 4 x 1024 points in mixed precision, 4 x 512
+// on real FP64 grids and 5 x 512 on complex FP64 grids, where the
+// workgroup's 8 waves leave 256 registers a lane (a fifth round on real FP64
+// grids slowed the four-round case: 4.3 against 3.5 us per step on 1728
+// points).
+template <typename TS>
+struct ResidentRounds {
+  static constexpr int value = sizeof(typename Real<TS>::T) == 8 && Real<TS>::cplx ? 5 : 4;
+};
+
 template <int NF, typename TS, typename TY>
 __global__ __launch_bounds__(ResidentThreads<TS>::value) void k_rk4_resident(const ResidentItem* __restrict__ items,
                                                                              int* __restrict__ flag) {
   using R = typename Real<TS>::T;
+  constexpr int kResidentRounds = ResidentRounds<TS>::value;
   extern __shared__ __align__(16) unsigned char smem[];
   const ResidentItem* __restrict__ it = items + blockIdx.x;
   const int T = (int)it->g.tile_points;

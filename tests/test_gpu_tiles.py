@@ -233,9 +233,9 @@ def test_resident_integrator_matches_stage_launches(hgf, precision):
 def test_resident_workgroup_sizes(hgf, precision):
     """The resident integrator's workgroup size, set through
     hgf_set_tile_config: every size that covers the 3-mode grid (1,728
-    points) in at most four lane rounds gives the same result bit for bit
-    (each point's arithmetic does not depend on it); other sizes are
-    rejected and leave the function as it was."""
+    points) in at most four lane rounds gives the same result
+    bit for bit (each point's arithmetic does not depend on it); other sizes
+    are rejected and leave the function as it was."""
     w = synth.three_mode_c1()
     S = hgf.define_system(w.system)
     announce(f"resident workgroup sizes {precision}")
