@@ -275,6 +275,8 @@ bool resident_eligible(Function& f, int threads) {
   r.tile_points = g.points;
   r.ntiles = 1;
   r.lds_elems = (int)padded;
+  r.tiles = nullptr;  // the stage kernels' records (replaced by a later retile) are not its
+  r.walk = nullptr;
   const int rs = f.precision_fp64 ? 8 : 4, es = (g.real ? 1 : 2) * rs;
   const int64_t lds = 2 * padded * es;
   if (lds > kResidentLdsMax) return false;
