@@ -280,6 +280,37 @@ def batch_throughput(hgf, torch, seq_steps: int, steps=None, tune_cache=None):
             "autotune_seconds": tune_s}
 
 
+def axis_count_comparison(hgf, torch):
+    """The stage kernel (mixed, real diagonal sector, autotuned shape) on grids
+    of tens of millions of points with 10, 8, 7 and 5 axes: 6^10, 9^8, 13^7
+    and 32^5.  With more axes more of them are slow (outside the LDS tile),
+    and more neighbour tiles must be reused from one XCD's L2; the algorithmic
+    bandwidth (14 B per point-stage) over the stage time from HIP events."""
+    import synth
+    out = []
+    for cut in ((6,) * 10, (9,) * 8, (13,) * 7, (32,) * 5):
+        s, _, _ = synth.seeded_system(cut, 4, alpha_range=(0.3, 1.0))
+        op = hgf.map_operator(hgf.define_system(s), factors=synth.parity_factors(cut), precision="mixed")
+        pts = op.info()["total_points"]
+        dt = 5e-5
+        hgf.autotune([op], dt)
+        cfg = op.tile_config(0)
+        hgf.evolve(op, 2 * dt, dt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = 50
+        e0.record()
+        hgf.evolve(op, n * dt, dt)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / (4 * n)
+        gbs = bytes_per_point_stage("mixed", True) * pts / us / 1e3
+        out.append({"grid": "x".join(map(str, cut)), "points": pts, "slow_axes": len(cut) - cfg["nfast"],
+                    "tile_shape": cfg, "us_per_stage": us, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS})
+        del op
+    return out
+
+
 def network_timing(hgf, torch, five_only: bool = False):
     """The driven, exchange-coupled network of the paper's example (Table I
     parameters, secular dissipator at zero temperature, observable prod_j a_j,
@@ -494,11 +525,12 @@ def main():
                     help="skip the full-horizon runs of the 10-mode workload (4e4 steps, mixed and FP64)")
     ap.add_argument("--tune-cache", default=None,
                     help="launch-shape cache file: shapes found there are applied without measuring")
-    ap.add_argument("--only", choices=["network", "network5", "gradient", "storage", "batch"], default=None,
+    ap.add_argument("--only", choices=["network", "network5", "gradient", "storage", "batch", "axes"], default=None,
                     help="run one section alone and print its JSON (for profiling it): network = the Table I "
                          "network for 1 to 5 modes, network5 = its five-mode runs alone, gradient = the gradient "
                          "workload over 0.5 us (5,000 steps), storage = the conventional and separated "
-                         "network forms with thresholds, batch = the batch workload over --steps steps")
+                         "network forms with thresholds, batch = the batch workload over --steps steps, "
+                         "axes = the stage kernel on grids of 10, 8, 7 and 5 axes")
     ap.add_argument("--complex-grids", action="store_true",
                     help="time the general complex form of the grid (real-grid form off) as the main run")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -524,6 +556,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 elementwise passes reading and writing 1 GiB")
         del a, b
+    if args.only == "axes":
+        print(json.dumps({"axis_count": axis_count_comparison(hgf, torch)}))
+        return
     if args.only == "batch":
         print(json.dumps({"batch": batch_throughput(hgf, torch, 0, steps=args.steps, tune_cache=args.tune_cache)}))
         return
