@@ -44,7 +44,8 @@
  *    recomputes each step's stage grids in the reverse sweep (bit-identical).
  *  - HGF_MAX_NFAST=k (1..4): the default launch shape of the tiled stage
  *    kernel takes at most k fast (LDS) axes, so small grids also run with
- *    slow-axis neighbour tiles (the shape large grids take).
+ *    slow-axis neighbour tiles (the shape large grids take); grids of more
+ *    than k axes then also stay off the resident integrator by default.
  */
 #ifndef HGF_H
 #define HGF_H
