@@ -187,6 +187,35 @@ def test_autotune_cache_and_results(hgf, tmp_path):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_integrator_large_sectors(hgf, monkeypatch, precision):
+    """Sectors of 7^4 points (product of quadratures on 4 modes at cutoff 8):
+    more points than one tile of the stage kernel, so they run on the
+    resident integrator by their own layout, with two padded copies of
+    73,728 B (mixed) or 147,456 B (FP64, five lane rounds of 512 lanes) of
+    LDS; equal to the grouped stage launches (to rounding) and the oracle."""
+    announce(f"resident 7^4 sectors {precision}")
+    w = synth.grad_c3b()
+    S = hgf.define_system(w.system)
+    T = 200 * w.dt
+    ops = {}
+    for res in ("1", "0"):
+        monkeypatch.setenv("HGF_RESIDENT", res)
+        op = hgf.map_operator(S, factors=w.factors, precision=precision)
+        nf = op.info()["n_functions"]
+        assert nf == 16
+        cfgs = [op.tile_config(i) for i in range(nf)]
+        assert all(c["resident"] == (res == "1") and c["tile_points"] < 2401 for c in cfgs)
+        hgf.evolve(op, T, w.dt)
+        ops[res] = op
+    monkeypatch.delenv("HGF_RESIDENT")
+    cutoff = w.system.cutoff
+    a, b = gpu_number_grids(ops["1"], cutoff), gpu_number_grids(ops["0"], cutoff)
+    assert max_rel_err(a, b) < (1e-13 if precision == "fp64" else 1e-6)
+    ref = oracle_number_grids(cutoff, oracle.evolve(w.system, oracle.product_sectors(w.factors), T, w.dt))
+    assert max_rel_err(a, ref) < (FP64_TOL if precision == "fp64" else MIXED_TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_resident_integrator_matches_stage_launches(hgf, precision):
     """Grids that are one tile are integrated on chip by one workgroup through
     all steps of a call.  The result equals the per-stage launches (to
