@@ -288,6 +288,11 @@ hgf_status hgf_reconstruct(hgf_operator op, int32_t levels, double* out, void* h
  * checkpoints taken every `checkpoint_every` steps, in FP64 and merged layout
  * (desc->precision and desc->layout are ignored).  value_out receives J,
  * grad_out 2*hgf_num_params doubles (complex dJ/dtheta; real for Hermitian A).
+ * Device memory per sector of P points (16 P bytes a grid): the checkpoints
+ * (T / (checkpoint_every dt) + 1 grids) and, when a segment's states and
+ * stage grids fit in 2 GiB, two segment buffers of 4 checkpoint_every grids
+ * and the segment's adjoint grids (4 checkpoint_every more); else one
+ * buffer of checkpoint_every states (the stages are then recomputed).
  * Errors: HGF_EINVAL, HGF_EUNSTABLE, HGF_ENOMEM, HGF_EDEVICE, HGF_ENONFINITE.
  */
 hgf_status hgf_grad(hgf_system sys, const hgf_operator_desc* desc, const hgf_state_desc* psi,
