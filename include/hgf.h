@@ -292,8 +292,7 @@ hgf_status hgf_reconstruct(hgf_operator op, int32_t levels, double* out, void* h
  * (T / (checkpoint_every dt) + 1 grids) and, when a segment's states and
  * stage grids fit in 2 GiB, one segment buffer of 4 checkpoint_every grids
  * (two when there are several segments: the next is recomputed beside the
- * sweep)
- * and the segment's adjoint grids (4 checkpoint_every more); else one
+ * sweep) and the segment's adjoint grids (4 checkpoint_every more); else one
  * buffer of checkpoint_every states (the stages are then recomputed).
  * Errors: HGF_EINVAL, HGF_EUNSTABLE, HGF_ENOMEM, HGF_EDEVICE, HGF_ENONFINITE.
  */
