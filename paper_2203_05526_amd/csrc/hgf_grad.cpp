@@ -125,9 +125,28 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
     DBuf y0(gb);
     hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
-    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, false));
-    // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
-    {
+    // Small sectors (at most four axes and 1024 points, the generator and its
+    // transpose both on the resident integrator's layout) run the gradient on
+    // chip: the forward pass and each segment's recompute on the resident
+    // integrator (the recompute recording every step's y, X1, V1, V2), each
+    // segment's reverse sweep with its products in one launch
+    // (k_adjoint_resident).  Other sectors, and all with HGF_RESIDENT=0, run
+    // the stage launches below.
+    bool on_chip = store && f.resident && fa.resident && f.ga.n <= 4 && pts <= 2 * 512 &&
+                   f.res_threads == fa.res_threads && f.res_lds_bytes == fa.res_lds_bytes;
+    if (on_chip && f.res_lds_bytes > 65536 && grad_resident_allow_lds(kResidentLdsMax) != hipSuccess) {
+      (void)hipGetLastError();
+      on_chip = false;
+    }
+    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, on_chip));
+    if (on_chip) {  // forward on chip, a checkpoint after every `ce` steps
+      const int64_t full = M / ce;
+      for (int64_t c = 1; c <= full; ++c) {
+        run_resident(*fplan, ce, op.dflag, st);
+        hip_check(hipMemcpyAsync(ck + c * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+      }
+      run_resident(*fplan, M - full * ce, op.dflag, st);
+    } else {  // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
       const int64_t full = M / ce;
       if (full > 0) {
         const int chunk = (int)std::min<int64_t>(ce, 64);
@@ -162,6 +181,39 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     launch_fill_zero(Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
     double2* seg = segbuf.as<double2>();
     double2* Qp = Q.as<double2>();
+    if (on_chip) {
+      // one recording launch and one reverse launch per segment; the items for
+      // a full segment and for the last one (shorter when ce does not divide M)
+      const int64_t rest = M - (nseg - 1) * ce;
+      ResidentItem ri[2] = {};
+      AdjointResidentItem ai[2] = {};
+      for (int k = 0; k < 2; ++k) {
+        ri[k].g = f.rga;
+        ri[k].y = f.y;
+        ri[k].x1 = f.s1;
+        ri[k].steps = (int)(k == 0 ? seg_steps : rest);
+        ri[k].h = dt;
+        ri[k].rec = seg;
+        ai[k].g = fa.rga;
+        ai[k].mu = mu.p;
+        ai[k].seg = seg;
+        ai[k].Q = Qp;
+        ai[k].steps = ri[k].steps;
+        ai[k].h = dt;
+      }
+      DBuf dri(sizeof ri), dai(sizeof ai);
+      hip_check(hipMemcpy(dri.p, ri, sizeof ri, hipMemcpyHostToDevice), "upload items");
+      hip_check(hipMemcpy(dai.p, ai, sizeof ai, hipMemcpyHostToDevice), "upload items");
+      for (int64_t c = nseg - 1; c >= 0; --c) {
+        const int k = c == nseg - 1 ? 1 : 0;
+        hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
+        launch_grad_record(dri.as<ResidentItem>() + k, 1, f.ga.n, f.res_threads, f.res_lds_bytes, op.dflag, st);
+        launch_grad_reverse(dai.as<AdjointResidentItem>() + k, 1, f.ga.n, fa.res_threads, fa.res_lds_bytes,
+                            op.dflag, st);
+      }
+      hip_check(hipGetLastError(), "kernel launch");
+      hip_check(hipStreamSynchronize(st), "synchronize");  // the items are freed on leaving this block
+    }
     // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
     // f.y into a segment buffer (with each step's X1, V1, V2 when `store`),
     // then sweep them in reverse.  The work of a segment depends only on L
@@ -247,7 +299,9 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     // runs them one after the other.
     const char* ov_env = std::getenv("HGF_GRAD_OVERLAP");
     const bool overlap = store && nseg > 1 && ce <= kGradGraphSteps && !(ov_env && std::string(ov_env) == "0");
-    if (!overlap) {
+    if (on_chip) {
+      // done above
+    } else if (!overlap) {
       for (int64_t c = nseg - 1; c >= 0; --c) {
         const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
         hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");

@@ -241,6 +241,20 @@ struct ResidentItem {
   void* x1;  // network operators: X1 of the current step (the function's stage grid)
   int steps;
   double h;
+  void* rec;  // complex FP64 only, or NULL: step s's y, X1, V1, V2 written at rec + 4 s P (the gradient's records)
+};
+
+// One function's reverse sweep over a segment of the discrete adjoint, on chip
+// (complex FP64): the transposed generator's layout and tables, the adjoint
+// state, the segment's forward records (step i's y, X1, V1, V2 at
+// seg + 4 i P) and the accumulator planes (1 + 2N planes of P points).
+struct AdjointResidentItem {
+  GridArgs g;
+  void* mu;
+  const void* seg;
+  void* Q;
+  int steps;
+  double h;
 };
 
 // One resident launch: one workgroup per item, items sharing the number of

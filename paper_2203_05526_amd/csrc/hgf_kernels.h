@@ -76,6 +76,15 @@ constexpr int kResidentLdsMax = 160 * 1024;
 // set the resident kernels' dynamic-LDS limit (for a function's element
 // types) to `bytes`; a host call, made outside graph capture
 hipError_t resident_allow_lds(bool real, int precision, int bytes);
+// the gradient's on-chip segment kernels (complex FP64; csrc/hgf_resident.h):
+// the recording forward integrator (items' rec set) and the reverse sweep,
+// `count` items of `nf` axes, one workgroup of `threads` lanes and `lds` bytes
+// each; grad_resident_allow_lds raises their dynamic-LDS limit (host call)
+hipError_t grad_resident_allow_lds(int bytes);
+void launch_grad_record(const ResidentItem* items, int count, int nf, int threads, int lds, int* flag,
+                        hipStream_t st);
+void launch_grad_reverse(const AdjointResidentItem* items, int count, int nf, int threads, int lds, int* flag,
+                         hipStream_t st);
 void launch_resident(const ResidentLaunch& rl, int* flag, hipStream_t st);
 void launch_classical(int stage, int precision, const GridArgs& g, const void* in, void* y, void* acc, void* next,
                       double h, const PointSources& src, int* flag, hipStream_t st);

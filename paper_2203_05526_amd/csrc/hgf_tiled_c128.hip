@@ -5,4 +5,5 @@
 namespace hgf {
 HGF_TILED_INSTANTIATE(double2, double2, c128)
 HGF_RESIDENT_INSTANTIATE(double2, double2, c128)
+HGF_ADJOINT_RESIDENT_DEFINE()
 }  // namespace hgf

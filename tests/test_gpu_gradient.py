@@ -142,6 +142,38 @@ def test_gradient_workload_factorises(hgf):
     assert np.max(np.abs(g[zeros])) <= 1e-14 * np.max(np.abs(g))
 
 
+@pytest.mark.parametrize("dissipator", ["lindblad", "secular"])
+@pytest.mark.parametrize("cutoff,ce", [((5, 5, 5, 5), 7), ((9, 3, 7), 100), ((16,), 13), ((32, 32), 9)])
+def test_gradient_on_chip_matches_launches_and_oracle(hgf, monkeypatch, dissipator, cutoff, ce):
+    """Sectors of at most four axes and 1024 points run the whole gradient on
+    chip (the resident integrator for the forward pass and each segment's
+    recompute, one launch for each segment's reverse sweep and products);
+    it agrees with the stage-launch path (HGF_RESIDENT=0) to rounding and
+    with the oracle's forward sensitivities at 1e-10."""
+    announce(f"gradient on chip {cutoff} ce={ce} {dissipator}")
+    s = synth.random_system(cutoff, 351, scale=2.0, n_th=0.2)
+    if dissipator == "secular":
+        rng = np.random.default_rng(351)
+        s.dissipator = "secular"
+        s.n_th_levels = rng.uniform(0.0, 0.6, size=sum(c - 1 for c in cutoff))
+    fac = tridiagonal_factors(cutoff, 351) if max(cutoff) <= 16 else \
+        [np.diag(np.random.default_rng(352 + j).normal(size=c)) + 0j for j, c in enumerate(cutoff)]
+    st = synth.coherent_state([0.5 + 0.2j, 0.7, -0.3j, 0.4][:len(cutoff)])
+    T, dt = 0.03, 1e-3
+    S = hgf.define_system(s)
+    out = {}
+    for res in ("1", "0"):
+        monkeypatch.setenv("HGF_RESIDENT", res)
+        out[res] = hgf.grad(S, st, T, dt, factors=fac, checkpoint_every=ce)
+    monkeypatch.delenv("HGF_RESIDENT")
+    assert rel(out["1"][0], out["0"][0]) < 1e-12
+    assert grad_err(out["1"][1], out["0"][1]) < 1e-12
+    if np.prod(cutoff) <= 1024 and max(cutoff) <= 16:
+        ref_val, ref_grad = oracle_value_and_grad(s, oracle.product_sectors(fac), T, dt, st)
+        assert rel(out["1"][0], ref_val) < FP64_TOL
+        assert grad_err(out["1"][1], ref_grad) < FP64_TOL
+
+
 def test_gradient_thirteen_modes_products(hgf, monkeypatch):
     """13 modes at cutoff 2 with a bitstring projector (one 8,192-point
     sector): the parameter products run once per segment in chunks of four

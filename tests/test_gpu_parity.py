@@ -435,9 +435,11 @@ def test_gradient_stored_and_recomputed_stages_agree(hgf, monkeypatch):
     (HGF_GRAD_STORE=0); with stored stages the recompute of the next segment
     runs beside the sweep (two segment buffers) unless HGF_GRAD_OVERLAP=0: the
     same kernels on the same operands, so the value and the gradient agree
-    bit for bit (six segments, the last one shorter)."""
+    bit for bit (six segments, the last one shorter), on the stage-launch
+    path."""
     cutoff = (5, 4, 6)
     announce("gradient stored vs recomputed stages")
+    monkeypatch.setenv("HGF_RESIDENT", "0")  # the stage-launch path (small sectors otherwise run on chip)
     s = synth.random_system(cutoff, 19, scale=2.0, n_th=0.1)
     M = _dense_random_operator(cutoff, 19, hermitian=True)
     st = synth.coherent_state([0.6 + 0.2j, 0.9, -0.4j])
