@@ -55,6 +55,167 @@ constexpr int64_t kGradGraphSteps = 512;
 // each step in the sweep (the same numbers either way).
 constexpr int64_t kGradStoreBytes = (int64_t)2 << 30;
 
+// J's part from one sector: its grid contracted with the weights `dw`.
+static cd sector_value(const Function& f, const double2* dw, hipStream_t st) {
+  std::vector<int> start = {0, expect_blocks(f.ga)};
+  cd one = 1.0;
+  DBuf dpart(start[1] * sizeof(double2)), dstart(2 * sizeof(int)), dcoef(sizeof(double2)), dout(sizeof(double2));
+  hip_check(hipMemcpyAsync(dstart.p, start.data(), 2 * sizeof(int), hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(dcoef.p, &one, sizeof(double2), hipMemcpyHostToDevice, st), "upload");
+  launch_expect_partial(f.ga, f.y, true, dw, dpart.as<double2>(), st);
+  launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), 1, make_double2(0, 0),
+                      dout.as<double2>(), st);
+  double2 r;
+  hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  return cd(r.x, r.y);
+}
+
+// Parameter derivatives from one sector's accumulator planes Q: the marginals
+// of Q against the derivative tables of every parameter (unit systems).
+static void sector_grad(const System& sys, const Function& f, const double2* Q, std::vector<cd>& grad,
+                        hipStream_t st) {
+  const int nb = marginal_bins(f.ga);
+  DBuf dbins(nb * sizeof(double2));
+  launch_marginals(f.ga, Q, dbins.as<double2>(), st);
+  hip_check(hipGetLastError(), "kernel launch");
+  std::vector<cd> bins(nb);
+  hip_check(hipMemcpyAsync(bins.data(), dbins.p, nb * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "synchronize");
+  int tot_e = 0;
+  for (int j = 0; j < sys.n; ++j) tot_e += f.ga.ext[j];
+  cd S0 = 0.0;
+  for (int v = 0; v < f.ga.ext[0]; ++v) S0 += bins[v];
+  for (size_t p = 0; p < grad.size(); ++p) {
+    const System u = unit_system(sys, (int)p);
+    const SectorTables tp = sector_tables(u, f.tab.d);
+    cd g = tp.lam0 * S0;
+    for (int j = 0; j < sys.n; ++j) {
+      for (int v = 0; v < f.ga.ext[j]; ++v) {
+        g += tp.lam[j][v] * bins[f.ga.off[j] + v];
+        g += tp.alpha[j][v] * bins[tot_e + f.ga.off[j] + v];
+        g += tp.beta[j][v] * bins[2 * tot_e + f.ga.off[j] + v];
+      }
+    }
+    grad[p] += g;
+  }
+}
+
+// Small sectors (at most four axes and 1024 points, the generator and its
+// transpose both on the resident integrator's layout) run the gradient on chip
+// and together, one workgroup per sector in every launch: the forward pass
+// with its checkpoints on the resident integrator; per segment, from the last,
+// one launch of the resident integrator that also records every step's y, X1,
+// V1, V2 (the same arithmetic as the plain form) and one launch of
+// k_adjoint_resident (the reverse sweep with its parameter products).  `fas`
+// are the sectors' transposed functions.
+static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, std::vector<Function>& fas,
+                         const std::vector<std::vector<cd>>& ws, int64_t M, int ce, double dt, cd& value,
+                         std::vector<cd>& grad, int* dflag, hipStream_t st) {
+  const size_t K = fs.size();
+  if (K == 0) return;
+  const int64_t nseg = (M + ce - 1) / ce;
+  const int64_t seg_steps = std::min<int64_t>(ce, std::max<int64_t>(M, 1));
+  const int64_t rest = M - (nseg - 1) * ce;  // steps of the last segment
+  struct Sector {
+    DBuf ckpt, seg, mu, Q, wt, y0, dw;
+    Sector(int64_t pts, int64_t nseg, int64_t seg_steps, int n, size_t nw)
+        : ckpt((size_t)(nseg + 1) * pts * sizeof(double2)),
+          seg((size_t)(4 * seg_steps) * pts * sizeof(double2)),
+          mu(pts * sizeof(double2)),
+          Q((size_t)(1 + 2 * n) * pts * sizeof(double2)),
+          wt(pts * sizeof(double2)),
+          y0(pts * sizeof(double2)),
+          dw(nw * sizeof(double2)) {}
+  };
+  std::vector<std::unique_ptr<Sector>> sec;
+  int threads = 0, athreads = 0, lds = 0, alds = 0;
+  for (size_t k = 0; k < K; ++k) {
+    Function& f = *fs[k];
+    const int64_t pts = f.ga.points;
+    const size_t gb = pts * sizeof(double2);
+    sec.emplace_back(new Sector(pts, nseg, seg_steps, sys.n, ws[k].size()));
+    Sector& x = *sec.back();
+    hip_check(hipMemcpyAsync(x.dw.p, ws[k].data(), ws[k].size() * sizeof(double2), hipMemcpyHostToDevice, st),
+              "upload");
+    launch_fill_weights(f.ga, x.dw.as<double2>(), x.wt.as<double2>(), st);
+    hip_check(hipMemcpyAsync(x.ckpt.p, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
+    hip_check(hipMemcpyAsync(x.y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
+    threads = std::max(threads, f.res_threads);
+    athreads = std::max(athreads, fas[k].res_threads);
+    lds = std::max(lds, f.res_lds_bytes);
+    alds = std::max(alds, fas[k].res_lds_bytes);
+  }
+  if (std::max(lds, alds) > 65536) hip_check(grad_resident_allow_lds(kResidentLdsMax), "LDS limit");
+  // forward, a checkpoint of every sector after every `ce` steps
+  std::vector<PlanItem> items;
+  for (Function* f : fs) items.push_back(PlanItem{f, HGF_FP64, dt});
+  std::unique_ptr<StepPlan> plan(build_plan(items, true));
+  const int64_t full = M / ce;
+  for (int64_t c = 1; c <= full; ++c) {
+    run_resident(*plan, ce, dflag, st);
+    for (size_t k = 0; k < K; ++k) {
+      const int64_t pts = fs[k]->ga.points;
+      hip_check(hipMemcpyAsync(sec[k]->ckpt.as<double2>() + c * pts, fs[k]->y, pts * sizeof(double2),
+                               hipMemcpyDeviceToDevice, st),
+                "checkpoint");
+    }
+  }
+  run_resident(*plan, M - full * ce, dflag, st);
+  for (size_t k = 0; k < K; ++k) value += sector_value(*fs[k], sec[k]->dw.as<double2>(), st);
+  // reverse sweep: mu_M = w; items for a full segment and for the last one
+  std::vector<ResidentItem> ri(2 * K);
+  std::vector<AdjointResidentItem> ai(2 * K);
+  for (size_t k = 0; k < K; ++k) {
+    Function& f = *fs[k];
+    Sector& x = *sec[k];
+    const int64_t pts = f.ga.points;
+    hip_check(hipMemcpyAsync(x.mu.p, x.wt.p, pts * sizeof(double2), hipMemcpyDeviceToDevice, st), "seed");
+    launch_fill_zero(x.Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
+    for (int l = 0; l < 2; ++l) {
+      ResidentItem& r = ri[l * K + k];
+      r = ResidentItem{};
+      r.g = f.rga;
+      r.y = f.y;
+      r.x1 = f.s1;
+      r.steps = (int)(l == 0 ? seg_steps : rest);
+      r.h = dt;
+      r.rec = x.seg.p;
+      AdjointResidentItem& a = ai[l * K + k];
+      a = AdjointResidentItem{};
+      a.g = fas[k].rga;
+      a.mu = x.mu.p;
+      a.seg = x.seg.p;
+      a.Q = x.Q.p;
+      a.steps = r.steps;
+      a.h = dt;
+    }
+  }
+  DBuf dri(ri.size() * sizeof(ResidentItem)), dai(ai.size() * sizeof(AdjointResidentItem));
+  hip_check(hipMemcpy(dri.p, ri.data(), ri.size() * sizeof(ResidentItem), hipMemcpyHostToDevice), "upload items");
+  hip_check(hipMemcpy(dai.p, ai.data(), ai.size() * sizeof(AdjointResidentItem), hipMemcpyHostToDevice),
+            "upload items");
+  const int n = fs[0]->ga.n;
+  for (int64_t c = nseg - 1; c >= 0; --c) {
+    const size_t l = c == nseg - 1 ? 1 : 0;
+    for (size_t k = 0; k < K; ++k) {
+      const int64_t pts = fs[k]->ga.points;
+      hip_check(hipMemcpyAsync(fs[k]->y, sec[k]->ckpt.as<double2>() + c * pts, pts * sizeof(double2),
+                               hipMemcpyDeviceToDevice, st),
+                "restore");
+    }
+    launch_grad_record(dri.as<ResidentItem>() + l * K, (int)K, n, threads, lds, dflag, st);
+    launch_grad_reverse(dai.as<AdjointResidentItem>() + l * K, (int)K, n, athreads, alds, dflag, st);
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+  for (size_t k = 0; k < K; ++k) {
+    const int64_t pts = fs[k]->ga.points;
+    hip_check(hipMemcpyAsync(fs[k]->y, sec[k]->y0.p, pts * sizeof(double2), hipMemcpyDeviceToDevice, st),
+              "restore");
+    sector_grad(sys, *fs[k], sec[k]->Q.as<double2>(), grad, st);
+  }
+}
+
 void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state_desc* psi, double T,
                       double dt, int ce, double* value_out, double* grad_out, hipStream_t st) {
   const int64_t M = check_steps(T, dt);
@@ -92,7 +253,39 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
   std::vector<cd> grad(P, 0.0);
   cd value = 0.0;
   reset_flag(&op, st);
+  // sectors small enough for the gradient on chip (HGF_RESIDENT=0 or
+  // HGF_GRAD_STORE=0 keep every sector on the stage launches)
+  std::vector<Function*> chip;
+  std::vector<Function> chip_t;  // their transposed functions
+  std::vector<std::vector<cd>> chip_w;
+  {
+    const char* store_env = std::getenv("HGF_GRAD_STORE");
+    const bool no_store = store_env && std::string(store_env) == "0";
+    chip_t.reserve(op.fn.size());
+    for (auto& f : op.fn) {
+      if (no_store || !f.resident || f.ga.n > 4 || f.ga.points > 2 * 512) continue;
+      chip_t.emplace_back();
+      Function& fa = chip_t.back();
+      fa.tab = transposed_tables(f.tab);
+      fill_grid_args(fa, HGF_FP64, false);
+      if (!fa.resident || fa.res_threads != f.res_threads || fa.res_lds_bytes != f.res_lds_bytes) {
+        free_function(fa);
+        chip_t.pop_back();
+        continue;
+      }
+      chip.push_back(&f);
+      chip_w.push_back(sector_weights(sys, f, amps));
+    }
+  }
+  struct FreeChip {
+    std::vector<Function>& v;
+    ~FreeChip() {
+      for (auto& f : v) free_function(f);
+    }
+  } chip_guard{chip_t};
+  grad_on_chip(sys, chip, chip_t, chip_w, M, ce, dt, value, grad, op.dflag, st);
   for (auto& f : op.fn) {
+    if (std::find(chip.begin(), chip.end(), &f) != chip.end()) continue;
     const int64_t pts = f.ga.points;
     const size_t gb = pts * sizeof(double2);
     const int64_t nseg = (M + ce - 1) / ce;
@@ -125,28 +318,9 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     hip_check(hipMemcpyAsync(ck, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
     DBuf y0(gb);
     hip_check(hipMemcpyAsync(y0.p, f.y, gb, hipMemcpyDeviceToDevice, st), "copy");
-    // Small sectors (at most four axes and 1024 points, the generator and its
-    // transpose both on the resident integrator's layout) run the gradient on
-    // chip: the forward pass and each segment's recompute on the resident
-    // integrator (the recompute recording every step's y, X1, V1, V2), each
-    // segment's reverse sweep with its products in one launch
-    // (k_adjoint_resident).  Other sectors, and all with HGF_RESIDENT=0, run
-    // the stage launches below.
-    bool on_chip = store && f.resident && fa.resident && f.ga.n <= 4 && pts <= 2 * 512 &&
-                   f.res_threads == fa.res_threads && f.res_lds_bytes == fa.res_lds_bytes;
-    if (on_chip && f.res_lds_bytes > 65536 && grad_resident_allow_lds(kResidentLdsMax) != hipSuccess) {
-      (void)hipGetLastError();
-      on_chip = false;
-    }
-    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, on_chip));
-    if (on_chip) {  // forward on chip, a checkpoint after every `ce` steps
-      const int64_t full = M / ce;
-      for (int64_t c = 1; c <= full; ++c) {
-        run_resident(*fplan, ce, op.dflag, st);
-        hip_check(hipMemcpyAsync(ck + c * pts, f.y, gb, hipMemcpyDeviceToDevice, st), "checkpoint");
-      }
-      run_resident(*fplan, M - full * ce, op.dflag, st);
-    } else {  // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
+    std::unique_ptr<StepPlan> fplan(build_plan({PlanItem{&f, HGF_FP64, dt}}, false));
+    // forward: graphs of up to 64 steps, a checkpoint after every `ce` steps
+    {
       const int64_t full = M / ce;
       if (full > 0) {
         const int chunk = (int)std::min<int64_t>(ce, 64);
@@ -161,59 +335,12 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
       }
       for (int64_t s = full * ce; s < M; ++s) run_plan_step(*fplan, op.dflag, st);
     }
-    // value
-    {
-      std::vector<int> start = {0, expect_blocks(f.ga)};
-      cd one = 1.0;
-      DBuf dpart(start[1] * sizeof(double2)), dstart(2 * sizeof(int)), dcoef(sizeof(double2)), dout(sizeof(double2));
-      hip_check(hipMemcpyAsync(dstart.p, start.data(), 2 * sizeof(int), hipMemcpyHostToDevice, st), "upload");
-      hip_check(hipMemcpyAsync(dcoef.p, &one, sizeof(double2), hipMemcpyHostToDevice, st), "upload");
-      launch_expect_partial(f.ga, f.y, true, dw.as<double2>(), dpart.as<double2>(), st);
-      launch_expect_final(dpart.as<double2>(), dstart.as<int>(), dcoef.as<double2>(), 1, make_double2(0, 0),
-                          dout.as<double2>(), st);
-      double2 r;
-      hip_check(hipMemcpyAsync(&r, dout.p, sizeof(double2), hipMemcpyDeviceToHost, st), "download");
-      hip_check(hipStreamSynchronize(st), "synchronize");
-      value += cd(r.x, r.y);
-    }
+    value += sector_value(f, dw.as<double2>(), st);
     // reverse sweep: mu_M = w
     hip_check(hipMemcpyAsync(mu.p, wt.p, gb, hipMemcpyDeviceToDevice, st), "seed");
     launch_fill_zero(Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
     double2* seg = segbuf.as<double2>();
     double2* Qp = Q.as<double2>();
-    if (on_chip) {
-      // one recording launch and one reverse launch per segment; the items for
-      // a full segment and for the last one (shorter when ce does not divide M)
-      const int64_t rest = M - (nseg - 1) * ce;
-      ResidentItem ri[2] = {};
-      AdjointResidentItem ai[2] = {};
-      for (int k = 0; k < 2; ++k) {
-        ri[k].g = f.rga;
-        ri[k].y = f.y;
-        ri[k].x1 = f.s1;
-        ri[k].steps = (int)(k == 0 ? seg_steps : rest);
-        ri[k].h = dt;
-        ri[k].rec = seg;
-        ai[k].g = fa.rga;
-        ai[k].mu = mu.p;
-        ai[k].seg = seg;
-        ai[k].Q = Qp;
-        ai[k].steps = ri[k].steps;
-        ai[k].h = dt;
-      }
-      DBuf dri(sizeof ri), dai(sizeof ai);
-      hip_check(hipMemcpy(dri.p, ri, sizeof ri, hipMemcpyHostToDevice), "upload items");
-      hip_check(hipMemcpy(dai.p, ai, sizeof ai, hipMemcpyHostToDevice), "upload items");
-      for (int64_t c = nseg - 1; c >= 0; --c) {
-        const int k = c == nseg - 1 ? 1 : 0;
-        hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
-        launch_grad_record(dri.as<ResidentItem>() + k, 1, f.ga.n, f.res_threads, f.res_lds_bytes, op.dflag, st);
-        launch_grad_reverse(dai.as<AdjointResidentItem>() + k, 1, f.ga.n, fa.res_threads, fa.res_lds_bytes,
-                            op.dflag, st);
-      }
-      hip_check(hipGetLastError(), "kernel launch");
-      hip_check(hipStreamSynchronize(st), "synchronize");  // the items are freed on leaving this block
-    }
     // One segment of L steps: recompute y_{s0} .. y_{s0+L-1} from the state in
     // f.y into a segment buffer (with each step's X1, V1, V2 when `store`),
     // then sweep them in reverse.  The work of a segment depends only on L
@@ -299,9 +426,7 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     // runs them one after the other.
     const char* ov_env = std::getenv("HGF_GRAD_OVERLAP");
     const bool overlap = store && nseg > 1 && ce <= kGradGraphSteps && !(ov_env && std::string(ov_env) == "0");
-    if (on_chip) {
-      // done above
-    } else if (!overlap) {
+    if (!overlap) {
       for (int64_t c = nseg - 1; c >= 0; --c) {
         const int64_t s0 = c * ce, L = std::min<int64_t>(ce, M - s0);
         hip_check(hipMemcpyAsync(f.y, ck + c * pts, gb, hipMemcpyDeviceToDevice, st), "restore");
@@ -350,31 +475,7 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
     hip_check(hipStreamSynchronize(st), "synchronize");  // graphs are destroyed with seg_graphs
     // leave the function at its initial state
     hip_check(hipMemcpyAsync(f.y, y0.p, gb, hipMemcpyDeviceToDevice, st), "restore");
-    // marginals of Q -> parameter derivatives
-    const int nb = marginal_bins(f.ga);
-    DBuf dbins(nb * sizeof(double2));
-    launch_marginals(f.ga, Q.as<double2>(), dbins.as<double2>(), st);
-    hip_check(hipGetLastError(), "kernel launch");
-    std::vector<cd> bins(nb);
-    hip_check(hipMemcpyAsync(bins.data(), dbins.p, nb * sizeof(double2), hipMemcpyDeviceToHost, st), "download");
-    hip_check(hipStreamSynchronize(st), "synchronize");
-    int tot_e = 0;
-    for (int j = 0; j < sys.n; ++j) tot_e += f.ga.ext[j];
-    cd S0 = 0.0;
-    for (int v = 0; v < f.ga.ext[0]; ++v) S0 += bins[v];
-    for (int p = 0; p < P; ++p) {
-      const System u = unit_system(sys, p);
-      const SectorTables tp = sector_tables(u, f.tab.d);
-      cd g = tp.lam0 * S0;
-      for (int j = 0; j < sys.n; ++j) {
-        for (int v = 0; v < f.ga.ext[j]; ++v) {
-          g += tp.lam[j][v] * bins[f.ga.off[j] + v];
-          g += tp.alpha[j][v] * bins[tot_e + f.ga.off[j] + v];
-          g += tp.beta[j][v] * bins[2 * tot_e + f.ga.off[j] + v];
-        }
-      }
-      grad[p] += g;
-    }
+    sector_grad(sys, f, Q.as<double2>(), grad, st);
   }
   if (read_flag(&op, st)) fail(HGF_ENONFINITE, "non-finite value during the gradient sweep");
   value_out[0] = value.real();
