@@ -512,6 +512,44 @@ def gradient_timing(hgf, torch, t_total: float):
     return out
 
 
+def small_gradient_timing(hgf, torch):
+    """hgf_grad on a small off-diagonal workload (4 Kerr modes, cutoff 5,
+    product of quadratures: 16 sectors of 256 points; T = 0.02 us, dt = 0.01
+    ns, 2,000 steps, checkpoints every 100): on chip (every sector within the
+    resident integrator's size) and on the stage launches (HGF_RESIDENT=0),
+    each with its errors against the stored oracle value and sensitivities."""
+    import synth
+    w = synth.grad_c3b(cutoff=5, t_total=0.02, dt=1e-5)
+    ref = golden("small_gradient")
+    rv = complex(*ref["value"])
+    rg = np.array([complex(*x) for x in ref["grad"]])
+    S = hgf.define_system(w.system)
+    out = {"workload": f"{w.name}, 16 sectors of 256 points, T = 0.02 us, dt = 0.01 ns", "steps": w.n_steps,
+           "params": len(rg)}
+    prev = os.environ.get("HGF_RESIDENT")
+    try:
+        for name, res in (("on_chip", None), ("stage_launches", "0")):
+            if res is None:
+                os.environ.pop("HGF_RESIDENT", None)
+            else:
+                os.environ["HGF_RESIDENT"] = res
+            hgf.grad(S, w.states[0], 10 * w.dt, w.dt, factors=w.factors, checkpoint_every=100)  # loads the kernels
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            val, g = hgf.grad(S, w.states[0], w.t_total, w.dt, factors=w.factors, checkpoint_every=100)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[name] = {"seconds": el, "us_per_step": el / w.n_steps * 1e6,
+                         "rel_err_vs_oracle": {"value": abs(val - rv) / abs(rv),
+                                               "grad": float(np.max(np.abs(g - rg)) / np.max(np.abs(rg)))}}
+    finally:
+        if prev is None:
+            os.environ.pop("HGF_RESIDENT", None)
+        else:
+            os.environ["HGF_RESIDENT"] = prev
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,7 +608,8 @@ def main():
         return
     if args.only == "gradient":
         gradient_timing(hgf, torch, 0.01)  # first call: loads the kernels, captures the graphs
-        print(json.dumps({"gradient": gradient_timing(hgf, torch, 0.5)}))
+        print(json.dumps({"gradient": gradient_timing(hgf, torch, 0.5),
+                          "gradient_small": small_gradient_timing(hgf, torch)}))
         return
     w = synth.large_c4()
     pts = int(np.prod(w.system.cutoff))
@@ -675,6 +714,7 @@ def main():
         line["batch"] = batch_throughput(hgf, torch, 500)
         log("gradient")
         line["gradient"] = gradient_timing(hgf, torch, 5.0)
+        line["gradient_small"] = small_gradient_timing(hgf, torch)
         log("network")
         line["network"] = network_timing(hgf, torch)
         log("network storage (thresholded, conventional vs separated)")

@@ -106,8 +106,22 @@ def workloads():
     return {"ten_mode": ten, "batch": batch, "gradient": grad, "oracle_seconds": time.time() - t0}
 
 
+def small_gradient():
+    """The gradient of a small off-diagonal workload (4 Kerr modes, cutoff 5,
+    product of quadratures: 16 sectors of 4^4 points), T = 0.02 us at
+    dt = 1e-5 us (2,000 steps): J and the oracle's forward sensitivities in
+    the library's parameter order."""
+    w = synth.grad_c3b(cutoff=5, t_total=0.02, dt=1e-5)
+    t0 = time.time()
+    fin, sens = oracle.evolve_sens(w.system, oracle.product_sectors(w.factors), w.t_total, w.dt)
+    J = oracle.expectation(w.system.cutoff, fin, w.states[0])
+    dJ = [oracle.expectation(w.system.cutoff, sp, w.states[0]) for sp in sens]
+    return {"workload": w.name, "seed": 3, "t_total": w.t_total, "dt": w.dt, "steps": w.n_steps,
+            "value": [J.real, J.imag], "grad": [[x.real, x.imag] for x in dJ], "oracle_seconds": time.time() - t0}
+
+
 WRITERS = {"three_mode": three_mode, "quadratures": quadratures, "quadratures6": lambda: quadratures(6),
-           "workloads": workloads}
+           "workloads": workloads, "small_gradient": small_gradient}
 
 if __name__ == "__main__":
     for name in sys.argv[1:] or WRITERS:

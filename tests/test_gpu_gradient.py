@@ -174,6 +174,23 @@ def test_gradient_on_chip_matches_launches_and_oracle(hgf, monkeypatch, dissipat
         assert grad_err(out["1"][1], ref_grad) < FP64_TOL
 
 
+def test_small_gradient_workload_matches_stored_oracle(hgf):
+    """The small off-diagonal gradient workload of the benchmark (4 Kerr
+    modes, cutoff 5, product of quadratures, 2,000 steps, on chip) against
+    the oracle's value and sensitivities stored by tests/golden/make_golden.py."""
+    import json
+    import os
+    announce("small gradient workload vs stored oracle")
+    w = synth.grad_c3b(cutoff=5, t_total=0.02, dt=1e-5)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "small_gradient.json")) as fh:
+        ref = json.load(fh)
+    assert ref["steps"] == w.n_steps
+    val, g = hgf.grad(hgf.define_system(w.system), w.states[0], w.t_total, w.dt, factors=w.factors,
+                      checkpoint_every=100)
+    assert rel(val, complex(*ref["value"])) < FP64_TOL
+    assert grad_err(g, np.array([complex(*x) for x in ref["grad"]])) < FP64_TOL
+
+
 def test_gradient_thirteen_modes_products(hgf, monkeypatch):
     """13 modes at cutoff 2 with a bitstring projector (one 8,192-point
     sector): the parameter products run once per segment in chunks of four
