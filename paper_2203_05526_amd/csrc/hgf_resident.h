@@ -5,15 +5,17 @@
 // costs microseconds of latency.  The resident form keeps the grid on one
 // workgroup's chip for many RK4 steps: the stencil input of the current stage
 // lives in LDS (the padded zero-halo layout of the tiled kernel with every
-// axis in the tile, two copies used in turn), and
-// each lane keeps its points' state y, X1 and per-point coefficients in
-// registers.  A stage is: read the neighbours from one LDS copy, compute the
-// stage value (the same delta-Horner arithmetic as the tiled kernel), write
-// it into the other copy, barrier.  HBM is touched only to load y at the
-// start and store y (and its stage-precision copy) at the end.
+// axis in the tile, two copies used in turn), and each lane keeps its points'
+// state y, X1 and per-point coefficients in registers.  A stage is: read the
+// neighbours from one LDS copy, compute the stage value (the same
+// delta-Horner arithmetic as the tiled kernel), write it into the other copy,
+// barrier.  HBM is touched only to load y at the start and store y (and its
+// stage-precision copy) at the end.
 //
 // One launch covers a list of such functions, one workgroup each (all the
-// small sectors of an operator, or the small members of a batch).
+// small sectors of an operator, or the small members of a batch).  The same
+// file holds the gradient's on-chip kernels for such sectors: a recording
+// form of the integrator and the reverse sweep of the discrete adjoint.
 #pragma once
 
 #include <hip/hip_runtime.h>
