@@ -117,11 +117,18 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
   const int64_t nseg = (M + ce - 1) / ce;
   const int64_t seg_steps = std::min<int64_t>(ce, std::max<int64_t>(M, 1));
   const int64_t rest = M - (nseg - 1) * ce;  // steps of the last segment
+  // With several segments the recompute of segment c - 1 runs beside the
+  // reverse sweep of segment c (two streams, two record buffers per sector,
+  // as on the stage launches); HGF_GRAD_OVERLAP=0 runs them in sequence
+  // (the same results).
+  const char* ov_env = std::getenv("HGF_GRAD_OVERLAP");
+  const bool overlap = nseg > 1 && !(ov_env && std::string(ov_env) == "0");
+  const int nbuf = overlap ? 2 : 1;
   struct Sector {
     DBuf ckpt, seg, mu, Q, wt, y0, dw;
-    Sector(int64_t pts, int64_t nseg, int64_t seg_steps, int n, size_t nw)
+    Sector(int64_t pts, int64_t nseg, int64_t seg_steps, int n, size_t nw, int nbuf)
         : ckpt((size_t)(nseg + 1) * pts * sizeof(double2)),
-          seg((size_t)(4 * seg_steps) * pts * sizeof(double2)),
+          seg((size_t)(4 * seg_steps * nbuf) * pts * sizeof(double2)),
           mu(pts * sizeof(double2)),
           Q((size_t)(1 + 2 * n) * pts * sizeof(double2)),
           wt(pts * sizeof(double2)),
@@ -134,7 +141,7 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
     Function& f = *fs[k];
     const int64_t pts = f.ga.points;
     const size_t gb = pts * sizeof(double2);
-    sec.emplace_back(new Sector(pts, nseg, seg_steps, sys.n, ws[k].size()));
+    sec.emplace_back(new Sector(pts, nseg, seg_steps, sys.n, ws[k].size(), nbuf));
     Sector& x = *sec.back();
     hip_check(hipMemcpyAsync(x.dw.p, ws[k].data(), ws[k].size() * sizeof(double2), hipMemcpyHostToDevice, st),
               "upload");
@@ -163,49 +170,91 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
   }
   run_resident(*plan, M - full * ce, dflag, st);
   for (size_t k = 0; k < K; ++k) value += sector_value(*fs[k], sec[k]->dw.as<double2>(), st);
-  // reverse sweep: mu_M = w; items for a full segment and for the last one
-  std::vector<ResidentItem> ri(2 * K);
-  std::vector<AdjointResidentItem> ai(2 * K);
+  // reverse sweep: mu_M = w; items per record buffer b, for a full segment
+  // (l = 0) and for the last one (l = 1), at [(2 b + l) K + k]
+  std::vector<ResidentItem> ri(4 * K);
+  std::vector<AdjointResidentItem> ai(4 * K);
   for (size_t k = 0; k < K; ++k) {
     Function& f = *fs[k];
     Sector& x = *sec[k];
     const int64_t pts = f.ga.points;
     hip_check(hipMemcpyAsync(x.mu.p, x.wt.p, pts * sizeof(double2), hipMemcpyDeviceToDevice, st), "seed");
     launch_fill_zero(x.Q.as<double2>(), (int64_t)(1 + 2 * sys.n) * pts, st);
-    for (int l = 0; l < 2; ++l) {
-      ResidentItem& r = ri[l * K + k];
-      r = ResidentItem{};
-      r.g = f.rga;
-      r.y = f.y;
-      r.x1 = f.s1;
-      r.steps = (int)(l == 0 ? seg_steps : rest);
-      r.h = dt;
-      r.rec = x.seg.p;
-      AdjointResidentItem& a = ai[l * K + k];
-      a = AdjointResidentItem{};
-      a.g = fas[k].rga;
-      a.mu = x.mu.p;
-      a.seg = x.seg.p;
-      a.Q = x.Q.p;
-      a.steps = r.steps;
-      a.h = dt;
-    }
+    for (int b = 0; b < 2; ++b)
+      for (int l = 0; l < 2; ++l) {
+        double2* buf = x.seg.as<double2>() + (b < nbuf ? b : 0) * 4 * seg_steps * pts;
+        ResidentItem& r = ri[(2 * b + l) * K + k];
+        r = ResidentItem{};
+        r.g = f.rga;
+        r.y = f.y;
+        r.x1 = f.s1;
+        r.steps = (int)(l == 0 ? seg_steps : rest);
+        r.h = dt;
+        r.rec = buf;
+        AdjointResidentItem& a = ai[(2 * b + l) * K + k];
+        a = AdjointResidentItem{};
+        a.g = fas[k].rga;
+        a.mu = x.mu.p;
+        a.seg = buf;
+        a.Q = x.Q.p;
+        a.steps = r.steps;
+        a.h = dt;
+      }
   }
   DBuf dri(ri.size() * sizeof(ResidentItem)), dai(ai.size() * sizeof(AdjointResidentItem));
   hip_check(hipMemcpy(dri.p, ri.data(), ri.size() * sizeof(ResidentItem), hipMemcpyHostToDevice), "upload items");
   hip_check(hipMemcpy(dai.p, ai.data(), ai.size() * sizeof(AdjointResidentItem), hipMemcpyHostToDevice),
             "upload items");
   const int n = fs[0]->ga.n;
-  for (int64_t c = nseg - 1; c >= 0; --c) {
-    const size_t l = c == nseg - 1 ? 1 : 0;
+  auto item_at = [&](int64_t c) { return (size_t)(2 * (overlap ? (c & 1) : 0) + (c == nseg - 1 ? 1 : 0)) * K; };
+  // restore every sector's state to checkpoint c and record segment c
+  auto record = [&](int64_t c, hipStream_t s) {
     for (size_t k = 0; k < K; ++k) {
       const int64_t pts = fs[k]->ga.points;
       hip_check(hipMemcpyAsync(fs[k]->y, sec[k]->ckpt.as<double2>() + c * pts, pts * sizeof(double2),
-                               hipMemcpyDeviceToDevice, st),
+                               hipMemcpyDeviceToDevice, s),
                 "restore");
     }
-    launch_grad_record(dri.as<ResidentItem>() + l * K, (int)K, n, threads, lds, dflag, st);
-    launch_grad_reverse(dai.as<AdjointResidentItem>() + l * K, (int)K, n, athreads, alds, dflag, st);
+    launch_grad_record(dri.as<ResidentItem>() + item_at(c), (int)K, n, threads, lds, dflag, s);
+  };
+  auto sweep = [&](int64_t c, hipStream_t s) {
+    launch_grad_reverse(dai.as<AdjointResidentItem>() + item_at(c), (int)K, n, athreads, alds, dflag, s);
+  };
+  if (!overlap) {
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      record(c, st);
+      sweep(c, st);
+    }
+  } else {
+    hipStream_t sb = nullptr;
+    hip_check(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking), "stream");
+    struct Guard {
+      hipStream_t s;
+      hipEvent_t e[5] = {};
+      ~Guard() {
+        for (hipEvent_t x : e)
+          if (x) (void)hipEventDestroy(x);
+        if (s) (void)hipStreamDestroy(s);
+      }
+    } gd{sb};  // events 0, 1: record into buffer b done; 2, 3: sweep of buffer b done; 4: start
+    for (hipEvent_t& x : gd.e) hip_check(hipEventCreateWithFlags(&x, hipEventDisableTiming), "event");
+    hip_check(hipEventRecord(gd.e[4], st), "record");
+    hip_check(hipStreamWaitEvent(sb, gd.e[4], 0), "wait");
+    auto record_on_sb = [&](int64_t c) {
+      const int b = (int)(c & 1);
+      if (c + 2 <= nseg - 1) hip_check(hipStreamWaitEvent(sb, gd.e[2 + b], 0), "wait");  // buffer b free
+      record(c, sb);
+      hip_check(hipEventRecord(gd.e[b], sb), "record");
+    };
+    record_on_sb(nseg - 1);
+    for (int64_t c = nseg - 1; c >= 0; --c) {
+      const int b = (int)(c & 1);
+      hip_check(hipStreamWaitEvent(st, gd.e[b], 0), "wait");
+      sweep(c, st);
+      hip_check(hipEventRecord(gd.e[2 + b], st), "record");
+      if (c >= 1) record_on_sb(c - 1);
+    }
+    hip_check(hipStreamSynchronize(sb), "synchronize");
   }
   hip_check(hipGetLastError(), "kernel launch");
   for (size_t k = 0; k < K; ++k) {

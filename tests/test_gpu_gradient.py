@@ -147,9 +147,10 @@ def test_gradient_workload_factorises(hgf):
 def test_gradient_on_chip_matches_launches_and_oracle(hgf, monkeypatch, dissipator, cutoff, ce):
     """Sectors of at most four axes and 1024 points run the whole gradient on
     chip (the resident integrator for the forward pass and each segment's
-    recompute, one launch for each segment's reverse sweep and products);
-    it agrees with the stage-launch path (HGF_RESIDENT=0) to rounding and
-    with the oracle's forward sensitivities at 1e-10."""
+    recompute, one launch for each segment's reverse sweep and products,
+    the next recompute beside each sweep); it agrees with the same run in
+    sequence bit for bit, with the stage-launch path (HGF_RESIDENT=0) to
+    rounding and with the oracle's forward sensitivities at 1e-10."""
     announce(f"gradient on chip {cutoff} ce={ce} {dissipator}")
     s = synth.random_system(cutoff, 351, scale=2.0, n_th=0.2)
     if dissipator == "secular":
@@ -166,6 +167,11 @@ def test_gradient_on_chip_matches_launches_and_oracle(hgf, monkeypatch, dissipat
         monkeypatch.setenv("HGF_RESIDENT", res)
         out[res] = hgf.grad(S, st, T, dt, factors=fac, checkpoint_every=ce)
     monkeypatch.delenv("HGF_RESIDENT")
+    # the next segment's recompute beside the sweep, or in sequence: the same bits
+    monkeypatch.setenv("HGF_GRAD_OVERLAP", "0")
+    seq = hgf.grad(S, st, T, dt, factors=fac, checkpoint_every=ce)
+    monkeypatch.delenv("HGF_GRAD_OVERLAP")
+    assert seq[0] == out["1"][0] and np.array_equal(seq[1], out["1"][1])
     assert rel(out["1"][0], out["0"][0]) < 1e-12
     assert grad_err(out["1"][1], out["0"][1]) < 1e-12
     if np.prod(cutoff) <= 1024 and max(cutoff) <= 16:
