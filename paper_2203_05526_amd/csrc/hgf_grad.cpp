@@ -228,15 +228,19 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
   } else {
     hipStream_t sb = nullptr;
     hip_check(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking), "stream");
+    // (on every exit, error paths included, both streams are drained before
+    // the events recorded on them and the second stream are destroyed)
     struct Guard {
-      hipStream_t s;
+      hipStream_t s, main;
       hipEvent_t e[5] = {};
       ~Guard() {
+        if (s) (void)hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(main);
         for (hipEvent_t x : e)
           if (x) (void)hipEventDestroy(x);
         if (s) (void)hipStreamDestroy(s);
       }
-    } gd{sb};  // events 0, 1: record into buffer b done; 2, 3: sweep of buffer b done; 4: start
+    } gd{sb, st};  // events 0, 1: record into buffer b done; 2, 3: sweep of buffer b done; 4: start
     for (hipEvent_t& x : gd.e) hip_check(hipEventCreateWithFlags(&x, hipEventDisableTiming), "event");
     hip_check(hipEventRecord(gd.e[4], st), "record");
     hip_check(hipStreamWaitEvent(sb, gd.e[4], 0), "wait");
@@ -254,7 +258,10 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
       hip_check(hipEventRecord(gd.e[2 + b], st), "record");
       if (c >= 1) record_on_sb(c - 1);
     }
+    // both streams drained before the events (recorded on both) and the
+    // second stream are destroyed
     hip_check(hipStreamSynchronize(sb), "synchronize");
+    hip_check(hipStreamSynchronize(st), "synchronize");
   }
   hip_check(hipGetLastError(), "kernel launch");
   for (size_t k = 0; k < K; ++k) {
@@ -493,12 +500,15 @@ void grad_impl(const System& sys, const hgf_operator_desc* desc, const hgf_state
       hip_check(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking), "stream");
       StreamGuard sbg{sb};
       struct Events {
+        hipStream_t a, b;
         hipEvent_t e[5] = {};
-        ~Events() {
+        ~Events() {  // both streams drained first (error paths included)
+          (void)hipStreamSynchronize(a);
+          (void)hipStreamSynchronize(b);
           for (hipEvent_t x : e)
             if (x) (void)hipEventDestroy(x);
         }
-      } ev;  // 0, 1: recompute into buffer b done; 2, 3: reverse of buffer b done; 4: start
+      } ev{sb, st};  // 0, 1: recompute into buffer b done; 2, 3: reverse of buffer b done; 4: start
       for (hipEvent_t& x : ev.e) hip_check(hipEventCreateWithFlags(&x, hipEventDisableTiming), "event");
       hip_check(hipEventRecord(ev.e[4], st), "record");
       hip_check(hipStreamWaitEvent(sb, ev.e[4], 0), "wait");
