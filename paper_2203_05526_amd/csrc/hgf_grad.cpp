@@ -154,6 +154,16 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
     alds = std::max(alds, fas[k].res_lds_bytes);
   }
   if (std::max(lds, alds) > 65536) hip_check(grad_resident_allow_lds(kResidentLdsMax), "LDS limit");
+  // every sector's state and checkpoints, for the batched checkpoint copies
+  std::vector<CheckpointItem> cki(K);
+  int64_t max_pts = 0;
+  for (size_t k = 0; k < K; ++k) {
+    cki[k] = CheckpointItem{(double2*)fs[k]->y, sec[k]->ckpt.as<double2>(), fs[k]->ga.points};
+    max_pts = std::max(max_pts, fs[k]->ga.points);
+  }
+  DBuf dcki(K * sizeof(CheckpointItem));
+  hip_check(hipMemcpy(dcki.p, cki.data(), K * sizeof(CheckpointItem), hipMemcpyHostToDevice), "upload items");
+  const CheckpointItem* ckp = dcki.as<CheckpointItem>();
   // forward, a checkpoint of every sector after every `ce` steps
   std::vector<PlanItem> items;
   for (Function* f : fs) items.push_back(PlanItem{f, HGF_FP64, dt});
@@ -161,12 +171,7 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
   const int64_t full = M / ce;
   for (int64_t c = 1; c <= full; ++c) {
     run_resident(*plan, ce, dflag, st);
-    for (size_t k = 0; k < K; ++k) {
-      const int64_t pts = fs[k]->ga.points;
-      hip_check(hipMemcpyAsync(sec[k]->ckpt.as<double2>() + c * pts, fs[k]->y, pts * sizeof(double2),
-                               hipMemcpyDeviceToDevice, st),
-                "checkpoint");
-    }
+    launch_checkpoint_batch(ckp, (int)K, max_pts, c, true, st);
   }
   run_resident(*plan, M - full * ce, dflag, st);
   for (size_t k = 0; k < K; ++k) value += sector_value(*fs[k], sec[k]->dw.as<double2>(), st);
@@ -209,12 +214,7 @@ static void grad_on_chip(const System& sys, const std::vector<Function*>& fs, st
   auto item_at = [&](int64_t c) { return (size_t)(2 * (overlap ? (c & 1) : 0) + (c == nseg - 1 ? 1 : 0)) * K; };
   // restore every sector's state to checkpoint c and record segment c
   auto record = [&](int64_t c, hipStream_t s) {
-    for (size_t k = 0; k < K; ++k) {
-      const int64_t pts = fs[k]->ga.points;
-      hip_check(hipMemcpyAsync(fs[k]->y, sec[k]->ckpt.as<double2>() + c * pts, pts * sizeof(double2),
-                               hipMemcpyDeviceToDevice, s),
-                "restore");
-    }
+    launch_checkpoint_batch(ckp, (int)K, max_pts, c, false, s);
     launch_grad_record(dri.as<ResidentItem>() + item_at(c), (int)K, n, threads, lds, dflag, s);
   };
   auto sweep = [&](int64_t c, hipStream_t s) {

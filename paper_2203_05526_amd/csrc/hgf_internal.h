@@ -244,6 +244,14 @@ struct ResidentItem {
   void* rec;  // complex FP64 only, or NULL: step s's y, X1, V1, V2 written at rec + 4 s P (the gradient's records)
 };
 
+// One grid of a batched checkpoint copy: the state y and the checkpoint array
+// (checkpoint c of `points` complex values at ckpt + c points).
+struct CheckpointItem {
+  double2* y;
+  double2* ckpt;
+  int64_t points;
+};
+
 // One function's reverse sweep over a segment of the discrete adjoint, on chip
 // (complex FP64): the transposed generator's layout and tables, the adjoint
 // state, the segment's forward records (step i's y, X1, V1, V2 at

@@ -128,6 +128,10 @@ void launch_gather_levels(const GridArgs& g, const void* y, bool real, const Gat
                           double2* out, hipStream_t st);
 // device-to-device copy as a kernel (safe to record in a captured graph)
 void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st);
+// checkpoint c of `count` grids in one launch: states into it (to_ckpt) or
+// restored from it; max_points: the largest grid
+void launch_checkpoint_batch(const CheckpointItem* items, int count, int64_t max_points, int64_t c, bool to_ckpt,
+                             hipStream_t st);
 void launch_fill_weights(const GridArgs& g, const double2* wtab, double2* out, hipStream_t st);
 // Separated form (Eqs. (9a)-(9c)), classical RK4 stage by stage: every
 // monomial's Gx and Gy (with +-C), the source P(sum_i c_i Gx_i Gy_i) of R

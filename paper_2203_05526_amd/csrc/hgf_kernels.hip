@@ -1061,6 +1061,17 @@ __global__ void k_gather_levels(GridArgs g, const double* __restrict__ y, int re
   }
 }
 
+// Checkpoint c of every item: to_ckpt copies each state into it, else each
+// state is restored from it.  blockIdx.y is the item.
+__global__ void k_checkpoint_batch(const CheckpointItem* __restrict__ items, int64_t c, int to_ckpt) {
+  const CheckpointItem it = items[blockIdx.y];
+  double2* ck = it.ckpt + c * it.points;
+  double2* dst = to_ckpt ? ck : it.y;
+  const double2* src = to_ckpt ? it.y : ck;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < it.points; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void k_copy2(double2* __restrict__ dst, const double2* __restrict__ src, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -1358,6 +1369,15 @@ void launch_fill_zero(double2* p, int64_t n, hipStream_t st) {
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, p, n);
+}
+
+void launch_checkpoint_batch(const CheckpointItem* items, int count, int64_t max_points, int64_t c, bool to_ckpt,
+                             hipStream_t st) {
+  const int bx = (int)std::max<int64_t>(1, std::min<int64_t>((max_points + 255) / 256, 64));
+  for (int first = 0; first < count; first += 65535) {  // the grid's y extent per launch
+    const int n = std::min(65535, count - first);
+    hipLaunchKernelGGL(k_checkpoint_batch, dim3(bx, n), dim3(256), 0, st, items + first, c, to_ckpt ? 1 : 0);
+  }
 }
 
 void launch_copy2(double2* dst, const double2* src, int64_t n, hipStream_t st) {
